@@ -1,0 +1,342 @@
+"""Pins of the oracle's multigrid, DD and FGMRES parts."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from oracle import discretisation as disc
+from oracle import multigrid as mg
+from oracle import dd as ddm
+from oracle import krylov
+
+
+def _hetero(n, seed=0, abl=2):
+    rng = np.random.default_rng(seed)
+    shape = tuple(reversed(n))
+    mu = rng.uniform(0.5, 2.0, shape)
+    lam = mu * rng.uniform(0.5, 8.0, shape)
+    rho = rng.uniform(0.7, 1.5, shape)
+    gam = disc.abl_gamma(n, [abl] * len(n), 1.0) + 0.01
+    return lam, mu, rho, gam
+
+
+def _positions(dims):
+    d = len(dims)
+    grids = np.meshgrid(*[np.arange(v) for v in dims], indexing="ij")
+    return [g.transpose(tuple(reversed(range(d)))).reshape(-1) for g in grids]
+
+
+@pytest.mark.parametrize("n", [(16, 12), (8, 8, 12)])
+def test_prolongation_reproduces_linear_fields(n):
+    """Bilinear staggered interpolation reproduces any linear field at fine points
+    whose interpolation stencil stays inside the coarse grid (section 3)."""
+    d = len(n)
+    nc = tuple(v // 2 for v in n)
+    P = mg.prolongation(n)
+    coef = np.array([0.3, -0.7, 0.45][:d])
+    xs = []
+    fine_pos, fine_ok = [], []
+    for k in range(d + 1):
+        cd = disc.face_dims(nc, k) if k < d else nc
+        fd = disc.face_dims(n, k) if k < d else n
+        cp, fp = _positions(cd), _positions(fd)
+        # physical coordinates in fine-cell units (coarse cell = 2 fine cells)
+        cx = [2.0 * (cp[a] + 1) if a == k else 2.0 * (cp[a] + 0.5) for a in range(d)]
+        fx = [(fp[a] + 1.0) if a == k else (fp[a] + 0.5) for a in range(d)]
+        xs.append(sum(coef[a] * cx[a] for a in range(d)) + 1.0)
+        ok = np.ones(fp[0].shape, dtype=bool)
+        for a in range(d):
+            if k == d:
+                continue          # piecewise-constant pressure: checked separately
+            if a == k:
+                ok &= (fx[a] >= 2.0) & (fx[a] <= n[a] - 2.0)
+            else:
+                ok &= (fx[a] >= 1.0) & (fx[a] <= n[a] - 1.0)
+        fine_pos.append(sum(coef[a] * fx[a] for a in range(d)) + 1.0)
+        fine_ok.append(ok)
+    y = P @ np.concatenate(xs)
+    off = disc.offsets(n)
+    for k in range(d):
+        seg = y[off[k]:off[k + 1]]
+        assert np.max(np.abs(seg[fine_ok[k]] - fine_pos[k][fine_ok[k]])) < 1e-13
+    # pressure: each fine cell takes the value of its coarse parent
+    pc = np.arange(int(np.prod(nc)), dtype=float)
+    Pp = P[off[d]:, disc.offsets(nc)[d]:]
+    fp = _positions(n)
+    parent = np.zeros(fp[0].shape, dtype=np.int64)
+    stride = 1
+    for a in range(d):
+        parent += (fp[a] // 2) * stride
+        stride *= nc[a]
+    assert np.array_equal(Pp @ pc, parent.astype(float))
+
+
+def test_prolongation_interior_rows_sum_to_one():
+    n = (16, 16)
+    P = mg.prolongation(n)
+    rs = np.asarray(P.sum(axis=1)).reshape(-1)
+    off = disc.offsets(n)
+    u0 = rs[off[0]:off[1]].reshape(16, 15)
+    assert np.allclose(u0[1:-1, 1:-1], 1.0)
+    assert np.allclose(rs[off[2]:], 1.0)
+
+
+@pytest.mark.parametrize("n", [(16, 16), (8, 8, 8)])
+def test_galerkin_footprint_and_symmetry(n):
+    """Coarse Galerkin operators (eq. (9)) stay complex symmetric; the u_k-u_k stencil
+    spans 3 normal x 5 tangential points, u_k-p 2 x 3 cells, p-p is diagonal and
+    distinct displacement components never couple directly."""
+    d = len(n)
+    lam, mu, rho, gam = _hetero(n, 1)
+    A = disc.assemble(n, 1.0, 0.7, lam, mu, rho, gam, 0.5)
+    H = mg.Hierarchy(A, n, 3, [0.75, 0.5])
+    for l in (1, 2):
+        Ac = H.A[l]
+        nl = H.n[l]
+        assert abs(Ac - Ac.T).max() < 1e-13 * abs(Ac).max()
+        off = disc.offsets(nl)
+        C = sp.coo_matrix(Ac)
+        blk = np.searchsorted(off, C.row, side="right") - 1
+        bcol = np.searchsorted(off, C.col, side="right") - 1
+        nz = np.abs(C.data) > 1e-14 * abs(Ac).max()
+        for k in range(d):
+            sel = nz & (blk == k)
+            assert not np.any((bcol[sel] != k) & (bcol[sel] != d))
+        assert not np.any(nz & (blk == d) & (bcol == d) & (C.row != C.col))
+        # footprint of one interior u_0 face
+        mid = tuple(v // 2 for v in nl)
+        r = disc.unknown_index(nl, 0, mid)
+        row = Ac[r].tocoo()
+        for c, v in zip(row.col, row.data):
+            if abs(v) < 1e-14 * abs(Ac).max():
+                continue
+            kb = np.searchsorted(off, c, side="right") - 1
+            local = c - off[kb]
+            dims = disc.face_dims(nl, kb) if kb < d else nl
+            pos = []
+            for a in range(d):
+                pos.append(local % dims[a])
+                local //= dims[a]
+            if kb == 0:
+                dn = (pos[0] + 1) - mid[0]
+                assert abs(dn) <= 1
+                assert all(abs(pos[a] - mid[a]) <= 2 for a in range(1, d))
+            else:
+                assert kb == d
+                assert pos[0] - mid[0] in (-1, 0)
+                assert all(abs(pos[a] - mid[a]) <= 1 for a in range(1, d))
+
+
+def test_economic_block_is_the_matrix_B_of_section5():
+    """For an interior cell of a homogeneous grid the economic local matrix is B of
+    section 5.2: s00 on the u diagonal, +-1/h couplings to p, -1/(lam+mu) on p."""
+    n = (8, 8)
+    h, lam, mu, rho, omega, gam = 1.0, 7.0, 1.2, 0.8, 0.9, 0.35
+    shape = tuple(reversed(n))
+    A = disc.assemble(n, h, omega, np.full(shape, lam), np.full(shape, mu), np.full(shape, rho),
+                      np.full(shape, gam))
+    B, dofs, colour = mg.vanka_blocks(A, n, economic=True)
+    s00 = 4 * mu / h ** 2 - rho * omega ** 2 * (1 - 1j * gam)
+    sp_, sm = 1 / h, -1 / h          # s_{1/2} and s_{-1/2}
+    paper_B = np.array([
+        [s00, 0, 0, 0, sp_],
+        [0, s00, 0, 0, sm],
+        [0, 0, s00, 0, sp_],
+        [0, 0, 0, s00, sm],
+        [-sm, -sp_, -sm, -sp_, -1 / (lam + mu)]], dtype=complex)
+    cell = 3 * 8 + 4
+    assert np.max(np.abs(B[cell] - paper_B)) < 1e-12
+    Bf, _, _ = mg.vanka_blocks(A, n, economic=False)
+    assert abs(Bf[cell][0, 1] + mu / h ** 2) < 1e-12 and abs(Bf[cell][2, 3] + mu / h ** 2) < 1e-12
+
+
+def test_red_black_cells_share_no_unknown():
+    for n in [(8, 6), (4, 6, 4)]:
+        dofs, colour = mg.cell_dofs(n)
+        for c in (0, 1):
+            d = dofs[colour == c]
+            d = d[d >= 0]
+            assert len(np.unique(d)) == d.size
+
+
+@pytest.mark.parametrize("economic", [False, True])
+def test_vanka_fixed_point(economic):
+    n = (12, 10)
+    lam, mu, rho, gam = _hetero(n, 2)
+    A = disc.assemble(n, 1.0, 0.8, lam, mu, rho, gam, 0.5)
+    rng = np.random.default_rng(0)
+    e = rng.standard_normal(A.shape[0]) + 1j * rng.standard_normal(A.shape[0])
+    b = A @ e
+    B, dofs, colour = mg.vanka_blocks(A, n, economic)
+    for c in (0, 1):
+        e2 = mg.vanka_half_sweep(A, B, dofs, colour, c, b, e, 0.75)
+        assert np.max(np.abs(e2 - e)) < 1e-12 * np.max(np.abs(e))
+
+
+def test_full_vanka_solves_isolated_blocks_exactly():
+    """Undamped full Vanka on a red cell makes that cell's residual vanish."""
+    n = (8, 8)
+    lam, mu, rho, gam = _hetero(n, 3)
+    A = disc.assemble(n, 1.0, 0.8, lam, mu, rho, gam, 0.5)
+    rng = np.random.default_rng(4)
+    b = rng.standard_normal(A.shape[0]) + 1j * rng.standard_normal(A.shape[0])
+    B, dofs, colour = mg.vanka_blocks(A, n, False)
+    e = mg.vanka_half_sweep(A, B, dofs, colour, 0, b, np.zeros(A.shape[0], complex), 1.0)
+    r = b - A @ e
+    cell = 2 * 8 + 2          # red interior cell; its block sees only its own update
+    d = dofs[cell]
+    # residual of the cell's unknowns w.r.t. the block only (neighbours' updates excluded)
+    own = np.zeros(A.shape[0], complex)
+    own[d[d >= 0]] = e[d[d >= 0]]
+    rb = b[d] - (A @ own)[d]
+    assert np.max(np.abs(rb)) < 1e-12 * np.max(np.abs(b))
+
+
+def test_one_level_cycle_is_exact_solve():
+    n = (8, 8)
+    lam, mu, rho, gam = _hetero(n, 5)
+    A = disc.assemble(n, 1.0, 0.8, lam, mu, rho, gam, 0.5)
+    H = mg.Hierarchy(A, n, 1, [])
+    rng = np.random.default_rng(6)
+    b = rng.standard_normal(A.shape[0]) + 1j * rng.standard_normal(A.shape[0])
+    x = H.cycle(b)
+    assert np.linalg.norm(A @ x - b) < 1e-12 * np.linalg.norm(b)
+
+
+def test_two_level_without_smoothing_is_coarse_correction():
+    n = (16, 16)
+    lam, mu, rho, gam = _hetero(n, 6)
+    A = disc.assemble(n, 1.0, 0.8, lam, mu, rho, gam, 0.5)
+    H = mg.Hierarchy(A, n, 2, [0.75], nu1=0, nu2=0)
+    rng = np.random.default_rng(7)
+    b = rng.standard_normal(A.shape[0]) + 1j * rng.standard_normal(A.shape[0])
+    P = H.P[0]
+    Ac = (P.T @ A @ P).toarray()
+    expect = P @ np.linalg.solve(Ac, P.T @ b)
+    assert np.linalg.norm(H.cycle(b) - expect) < 1e-11 * np.linalg.norm(expect)
+
+
+@pytest.mark.parametrize("cycle", [1, 2])
+def test_cycle_is_linear(cycle):
+    n = (16, 16)
+    lam, mu, rho, gam = _hetero(n, 8)
+    A = disc.assemble(n, 1.0, 0.8, lam, mu, rho, gam, 0.5)
+    H = mg.Hierarchy(A, n, 3, [0.75, 0.5], cycle=cycle)
+    rng = np.random.default_rng(9)
+    b1 = rng.standard_normal(A.shape[0]) + 1j * rng.standard_normal(A.shape[0])
+    b2 = rng.standard_normal(A.shape[0]) + 1j * rng.standard_normal(A.shape[0])
+    a = 0.3 - 1.7j
+    lhs = H.cycle(b1 + a * b2)
+    rhs = H.cycle(b1) + a * H.cycle(b2)
+    assert np.linalg.norm(lhs - rhs) < 1e-12 * np.linalg.norm(rhs)
+
+
+def test_fgmres_minimal_residual_property():
+    """With a fixed linear preconditioner M, the k-th FGMRES iterate minimises
+    |b - A x| over x in M K_k(A M, b); checked against an explicit dense least squares."""
+    rng = np.random.default_rng(11)
+    N = 30
+    A = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N)) + 6 * np.eye(N)
+    Mi = np.diag(1.0 / np.diag(A))
+    b = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    for k in (1, 3, 6):
+        _, st = krylov.fgmres(lambda v: A @ v, lambda v: Mi @ v, b, tol=1e-300, restart=k, maxit=k)
+        AM = A @ Mi
+        K = np.stack([np.linalg.matrix_power(AM, i) @ b for i in range(k)], axis=1)
+        c, *_ = np.linalg.lstsq(AM @ K, b, rcond=None)
+        best = np.linalg.norm(b - AM @ K @ c) / np.linalg.norm(b)
+        assert abs(st["rel_res_true"] - best) < 1e-10
+
+
+def test_fgmres_finite_termination_and_exact_preconditioner():
+    rng = np.random.default_rng(12)
+    N = 12
+    A = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N)) + 3 * np.eye(N)
+    b = rng.standard_normal(N) + 0j
+    x, st = krylov.fgmres(lambda v: A @ v, lambda v: v, b, tol=1e-13, restart=N, maxit=N)
+    assert st["iters"] <= N and st["rel_res_true"] < 1e-11
+    Ainv = np.linalg.inv(A)
+    x, st = krylov.fgmres(lambda v: A @ v, lambda v: Ainv @ v, b, tol=1e-12, restart=5, maxit=5)
+    assert st["iters"] == 1 and st["rel_res_true"] < 1e-12
+
+
+def test_mg_preconditioned_fgmres_reaches_true_residual():
+    n = (32, 32)
+    lam, mu, rho, gam = _hetero(n, 13, abl=6)
+    pbA = disc.assemble(n, 1.0, 0.5, lam, mu, rho, gam, 0.0)
+    As = disc.assemble(n, 1.0, 0.5, lam, mu, rho, gam, 0.5)
+    H = mg.Hierarchy(As, n, 3, [0.75, 0.5])
+    b = disc.point_source_vector(n, [(0, (16, 4), 1.0)])
+    x, st = krylov.fgmres(lambda v: pbA @ v, H.cycle, b, tol=1e-8, restart=5, maxit=200)
+    assert st["converged"] and st["rel_res_true"] <= 1e-8
+    xd = spla.spsolve(pbA.tocsc(), b)
+    assert np.linalg.norm(x - xd) < 1e-5 * np.linalg.norm(xd)
+
+
+# ------------------------------------------------------------------------------ DD
+def _dd_problem(n, seed=14):
+    lam, mu, rho, gam = _hetero(n, seed, abl=4)
+    pb = disc.Problem.__new__(disc.Problem)
+    pb.n = tuple(n); pb.dim = len(n); pb.shift = 0.5; pb.omega = 0.6
+    pb.lam, pb.mu, pb.rho, pb.gamma_hat = lam, mu, rho, gam
+    return pb
+
+
+def test_single_subdomain_dd_equals_multigrid():
+    n = (16, 16)
+    pb = _dd_problem(n)
+    P = ddm.DDPreconditioner(pb, (1, 1), 0, 0, 3, [0.75, 0.5])
+    H = mg.Hierarchy(pb.matrix(shifted=True), n, 3, [0.75, 0.5])
+    rng = np.random.default_rng(1)
+    v = rng.standard_normal(pb.size) + 1j * rng.standard_normal(pb.size)
+    assert np.linalg.norm(P.apply(v) - H.cycle(v)) < 1e-13 * np.linalg.norm(H.cycle(v))
+
+
+@pytest.mark.parametrize("n,parts", [((32, 16), (2, 2)), ((16, 16, 16), (2, 2, 2))])
+def test_dd_overlap_weights_partition_unity(n, parts):
+    subs = ddm.make_subdomains(n, parts, 4, 2)
+    cnt = np.zeros(disc.n_unknowns(n))
+    for s in subs:
+        m = ddm.local_to_global(n, s)
+        cnt[m[m >= 0]] += 1
+        assert len(np.unique(m[m >= 0])) == np.count_nonzero(m >= 0)
+    assert cnt.min() >= 1
+    assert cnt.max() == 2 ** len(n)
+
+
+def test_dd_local_operator_restricts_global_operator():
+    """Away from the padding, the local shifted matrix equals the global one on the
+    unknowns of the extent (the medium is copied, the layer only lives in the padding)."""
+    n = (24, 16)
+    pb = _dd_problem(n, 15)
+    P = ddm.DDPreconditioner(pb, (2, 1), 4, 2, 2, [0.75])
+    Ag = pb.matrix(shifted=True)
+    sub, m = P.subs[0], P.maps[0]
+    Al = P.hier[0].A[0]
+    inside = np.nonzero(m >= 0)[0]
+    # rows of local unknowns at least 2 cells away from the subdomain's interior side
+    X = _positions(disc.face_dims(sub.nloc, 0))
+    keep = []
+    off = disc.offsets(sub.nloc)
+    for li in inside:
+        k = np.searchsorted(off, li, side="right") - 1
+        dims = disc.face_dims(sub.nloc, k) if k < 2 else sub.nloc
+        local = li - off[k]
+        x = local % dims[0]
+        if x + sub.origin[0] <= sub.hi[0] - 3:
+            keep.append(li)
+    keep = np.array(keep)
+    sub_l = Al[keep][:, inside].toarray()
+    sub_g = Ag[m[keep]][:, m[inside]].toarray()
+    assert np.max(np.abs(sub_l - sub_g)) < 1e-14 * np.max(np.abs(sub_g))
+
+
+@pytest.mark.parametrize("colours", [1, 4])
+def test_dd_mg_fgmres_converges(colours):
+    n = (32, 32)
+    pb = _dd_problem(n, 16)
+    P = ddm.DDPreconditioner(pb, (2, 2), 4, 4, 2, [0.75], colours=colours)
+    A = pb.matrix()
+    b = disc.point_source_vector(n, [(0, (10, 5), 1.0), (1, (20, 20), 0.5j)])
+    x, st = krylov.fgmres(lambda v: A @ v, P.apply, b, tol=1e-8, restart=5, maxit=300)
+    assert st["converged"] and st["rel_res_true"] <= 1e-8

@@ -1,0 +1,184 @@
+"""Named workload configurations.
+
+Each configuration fixes a grid, a seeded medium, a frequency rule, the
+absorbing layer, the point sources and the solver settings.  Sources are listed
+as (component, position, amplitude): component k in 0..dim-1 is the displacement
+u_{k+1} on faces normal to axis k, and position is given in face/cell
+coordinates (x, y[, z]) where the normal coordinate is the face index
+1..n_k-1 (face i sits between cells i-1 and i).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Callable, List, Tuple
+
+import numpy as np
+
+from . import media as M
+
+Source = Tuple[int, Tuple[int, ...], complex]
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    description: str
+    dim: int
+    n: Tuple[int, ...]
+    h: float
+    media_fn: Callable[[], dict]
+    ppw: float                      # cells per minimum shear wavelength
+    abl_cells: Tuple[int, ...]
+    abl_max: float = 1.0
+    atten0: float = 0.01 * math.pi  # constant attenuation gamma_0 [1/s]
+    shift: float = 0.5
+    levels: int = 3
+    cycle: int = 1                  # 1 = V, 2 = W
+    nu1: int = 1
+    nu2: int = 1
+    vanka: int = 1                  # 1 = full, 0 = economic
+    damping: Tuple[float, ...] = (0.75, 0.5, 0.25)
+    precond_bits: int = 64
+    restart: int = 5
+    tol: float = 1e-6
+    maxit: int = 400
+    dd_parts: Tuple[int, ...] = (1, 1, 1)
+    dd_overlap: int = 0
+    dd_pad: int = 0
+    dd_colors: int = 1
+    sources_fn: Callable[["Workload"], List[Source]] = None
+
+    _media_cache: dict = dataclasses.field(default=None, repr=False)
+
+    def media(self) -> dict:
+        if self._media_cache is None:
+            self._media_cache = self.media_fn()
+        return self._media_cache
+
+    @property
+    def omega(self) -> float:
+        vs_min = float(self.media()["vs"].min())
+        return M.shear_frequency(vs_min, self.h, self.ppw)
+
+    def sources(self) -> List[Source]:
+        return self.sources_fn(self)
+
+    @property
+    def nrhs(self) -> int:
+        return len(self.sources())
+
+
+def _src_centre(w: Workload) -> List[Source]:
+    return [(0, tuple(v // 2 for v in w.n), 1.0 + 0j)]
+
+
+def _src_top_single(w: Workload) -> List[Source]:
+    # x-force on the u1 face in the middle of the top, 5 cells deep
+    if w.dim == 2:
+        return [(0, (w.n[0] // 2, 5), 1.0 + 0j)]
+    return [(0, (w.n[0] // 2, w.n[1] // 2, 5), 1.0 + 0j)]
+
+
+def _src_line(count: int, spacing: int, first: int, depth: int, seed: int):
+    def fn(w: Workload) -> List[Source]:
+        rng = np.random.default_rng(seed)
+        phases = rng.uniform(0.0, 2.0 * np.pi, size=count)
+        out = []
+        for s in range(count):
+            i = first + spacing * s
+            out.append((0, (i, depth), complex(np.exp(1j * phases[s]))))
+        return out
+    return fn
+
+
+def _src_lattice(per_axis: int, spacing: int, first: int, depth: int, seed: int):
+    def fn(w: Workload) -> List[Source]:
+        rng = np.random.default_rng(seed)
+        phases = rng.uniform(0.0, 2.0 * np.pi, size=per_axis * per_axis)
+        out = []
+        for b in range(per_axis):
+            for a in range(per_axis):
+                s = b * per_axis + a
+                out.append((0, (first + spacing * a, first + spacing * b, depth),
+                            complex(np.exp(1j * phases[s]))))
+        return out
+    return fn
+
+
+def _scaled_line(count: int, depth: int, seed: int):
+    """count x-forces equally spaced along x at the given depth."""
+    def fn(w: Workload) -> List[Source]:
+        spacing = w.n[0] // count
+        return _src_line(count, spacing, spacing // 2, depth, seed)(w)
+    return fn
+
+
+CONFIGS = {}
+
+
+def _add(w: Workload):
+    CONFIGS[w.name] = w
+
+
+_add(Workload(
+    name="c1_homog64",
+    description="2D 64x64 homogeneous (Vp 2000, Vs 2000/sqrt3, rho 1000), h=10 m, "
+                "10 cells per shear wavelength, 10-cell absorbing layer, unit x-force at the centre",
+    dim=2, n=(64, 64), h=10.0, media_fn=lambda: M.homogeneous_media((64, 64)), ppw=10.0,
+    abl_cells=(10, 10), shift=0.5, levels=3, damping=(0.75, 0.5), tol=1e-8,
+    sources_fn=_src_centre))
+
+_add(Workload(
+    name="c2_hetero512_fp64",
+    description="2D 512x512 heterogeneous (Vp GRF 1500-4500, Poisson 0.25-0.45, Gardner rho), "
+                "h=10 m, 10 cells per minimum shear wavelength, shift 0.5, 20-cell layer, one source, "
+                "FP64 FGMRES(5) + FP64 V(1,1)",
+    dim=2, n=(512, 512), h=10.0, media_fn=lambda: M.heterogeneous_2d_media((512, 512)), ppw=10.0,
+    abl_cells=(20, 20), shift=0.5, levels=6, damping=(0.75, 0.5, 0.5, 0.5, 0.5),
+    precond_bits=64, sources_fn=_src_top_single))
+
+_add(Workload(
+    name="c3_hetero512_batch32_fp32",
+    description="as c2, 32 x-forces at depth 5 (x = 8 + 16 s, seeded phases), complex64 V-cycle "
+                "inside FP64 FGMRES with FP64 coarsest solve",
+    dim=2, n=(512, 512), h=10.0, media_fn=lambda: M.heterogeneous_2d_media((512, 512)), ppw=10.0,
+    abl_cells=(20, 20), shift=0.5, levels=6, damping=(0.75, 0.5, 0.5, 0.5, 0.5),
+    precond_bits=32, sources_fn=_src_line(32, 16, 8, 5, seed=3)))
+
+_add(Workload(
+    name="c4_layered128_dd8_batch16_fp32",
+    description="3D 128^3 layered (8 layers, Vp 1500-4500, 5% perturbation, Poisson 0.30-0.45), "
+                "h=10 m, 8 cells per minimum shear wavelength, 12-cell layer, 2x2x2 overlapping "
+                "subdomains (overlap 4, padding 6), 16 sources, complex64 DD-MG preconditioner",
+    dim=3, n=(128, 128, 128), h=10.0, media_fn=lambda: M.layered_3d_media((128, 128, 128)),
+    ppw=8.0, abl_cells=(12, 12, 12), shift=0.4, levels=4, damping=(0.5, 0.5, 0.2),
+    precond_bits=32, dd_parts=(2, 2, 2), dd_overlap=4, dd_pad=6, dd_colors=1,
+    sources_fn=_src_lattice(4, 32, 16, 5, seed=7)))
+
+# Reduced-size relatives used where the oracle has to factorise the full operator.
+_add(Workload(
+    name="c2s_hetero128_fp64",
+    description="c2 media generator at 128x128 (parity size)",
+    dim=2, n=(128, 128), h=10.0, media_fn=lambda: M.heterogeneous_2d_media((128, 128)), ppw=10.0,
+    abl_cells=(20, 20), shift=0.5, levels=4, damping=(0.75, 0.5, 0.5), precond_bits=64,
+    sources_fn=_src_top_single))
+
+_add(Workload(
+    name="c3s_hetero128_batch8_fp32",
+    description="c3 at 128x128 with 8 sources (parity size)",
+    dim=2, n=(128, 128), h=10.0, media_fn=lambda: M.heterogeneous_2d_media((128, 128)), ppw=10.0,
+    abl_cells=(20, 20), shift=0.5, levels=4, damping=(0.75, 0.5, 0.5), precond_bits=32,
+    sources_fn=_scaled_line(8, 5, seed=3)))
+
+_add(Workload(
+    name="c4s_layered32_dd8_batch4_fp32",
+    description="c4 generator at 32^3 with 2x2x2 subdomains and 4 sources (parity size)",
+    dim=3, n=(32, 32, 32), h=10.0, media_fn=lambda: M.layered_3d_media((32, 32, 32)),
+    ppw=8.0, abl_cells=(6, 6, 6), shift=0.4, levels=3, damping=(0.5, 0.5),
+    precond_bits=32, dd_parts=(2, 2, 2), dd_overlap=4, dd_pad=4, dd_colors=1,
+    sources_fn=_src_lattice(2, 16, 8, 5, seed=7)))
+
+
+def get_config(name: str) -> Workload:
+    return CONFIGS[name]
