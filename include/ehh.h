@@ -1,0 +1,202 @@
+/*
+ * ehh.h -- C ABI of the MI355X elastic Helmholtz hybrid multigrid / domain
+ * decomposition solver (Treister & Yovel, "A hybrid shifted Laplacian multigrid
+ * and domain decomposition preconditioner for the elastic Helmholtz equations").
+ *
+ * The system (section 2.1 and section 3, eq. (14)) is the mixed staggered
+ * discretisation
+ *
+ *     [ grad_h^T A_e(mu) grad_h - w^2 M    grad_h        ] [u]   [q]
+ *     [ grad_h^T                          -D_c(1/(l+mu)) ] [p] = [0]
+ *
+ * with M = A_f(rho (1 - i gamma/w)) (eq. (5)).  The preconditioner approximately
+ * inverts the shifted operator, in which M becomes A_f(rho (1 - i (gamma/w + alpha)))
+ * on the u block only (eq. (10) with M_s = A_f(rho), section 3; the shift is
+ * given the sign of the attenuation), by one multigrid cycle (Algorithm 1 applied
+ * recursively) with damped red-black cell-wise Vanka relaxation, Galerkin coarse
+ * operators (eq. (9)), staggered bilinear transfers and an exact coarsest solve,
+ * optionally wrapped in overlapping domain decomposition with absorbing padding
+ * (section 2.3, section 4, Algorithm 2).  The outer solver is FGMRES(m) from a
+ * zero initial guess (section 6).
+ *
+ * Grid, unknowns and vector layout
+ *   Cells: n[0] x n[1] (x n[2]) of size h; x is axis 0, depth is the last axis.
+ *   Media (lambda, mu, rho, gamma) are cell arrays, x fastest.
+ *   u_k lives on the interior faces normal to axis k (the normal displacement
+ *   vanishes on the walls); p lives on cells.  Component k has
+ *   prod_a (a == k ? n_a - 1 : n_a) unknowns, x fastest; p has prod n_a.
+ *   A complex vector of one right-hand side is 2 N reals: the real parts of
+ *   [u_0, u_1, (u_2), p] followed by their imaginary parts (N = unknowns).
+ *   Several right-hand sides are stored back to back (stride 2 N reals).
+ *
+ * Units
+ *   Every vector at this ABI is in the library's nondimensional scaling:
+ *   h -> 1, lambda, mu -> lambda/mu_bar, mu/mu_bar, rho -> rho/rho_bar and
+ *   w -> w h sqrt(rho_bar/mu_bar), with mu_bar = mean(mu) (mean(lambda+2mu) if mu
+ *   is zero everywhere) and rho_bar = mean(rho).  A force q [SI] enters the
+ *   u rows as q h^2/mu_bar; p_SI = p mu_bar / h.  Relative residuals are taken in
+ *   the 2-norm of these vectors.  ehh_scaling() returns mu_bar, rho_bar and the
+ *   nondimensional w.
+ *
+ * Memory and streams
+ *   Pointers marked (device) are HIP device pointers; the caller owns them and
+ *   keeps them alive until the work on `stream` (a hipStream_t, NULL = default
+ *   stream) has completed.  The handle owns everything it allocates.  A handle
+ *   may be used from one host thread at a time.  Calls return a status; on
+ *   failure ehh_last_error() gives a message (thread-local).  EHH_ERR_INVALID
+ *   is returned before any device work is enqueued.
+ */
+#ifndef EHH_H
+#define EHH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EHH_MAX_LEVELS 8
+#define EHH_MAX_RESTART 16
+
+typedef struct ehh_ctx* ehh_handle_t;
+
+typedef enum {
+    EHH_OK = 0,
+    EHH_NOT_CONVERGED = 1,      /* maxit reached: x holds the last iterate */
+    EHH_ERR_INVALID = -1,       /* bad argument; nothing was enqueued */
+    EHH_ERR_HIP = -2,           /* a HIP call failed (message has the HIP string) */
+    EHH_ERR_OOM = -3,           /* device allocation failed; nothing leaked */
+    EHH_ERR_BREAKDOWN = -4,     /* NaN/Inf in media or right-hand side, or Krylov breakdown */
+    EHH_ERR_UNSUPPORTED = -5
+} ehh_status_t;
+
+typedef struct {
+    int32_t dim;            /* 2 or 3 */
+    int32_t n[3];           /* cells along x, y, z (n[2] ignored when dim == 2) */
+    double  h;              /* cell size [m], > 0 */
+    double  omega;          /* angular frequency [rad/s], > 0 */
+    double  shift;          /* alpha >= 0 of the shifted preconditioning operator */
+    int32_t abl_cells[3];   /* absorbing layer width per axis, on both sides (>= 0) */
+    double  abl_max;        /* gamma/omega reached at the wall, per axis (section 2.1: 1) */
+    double  atten0;         /* constant attenuation gamma_0 [1/s] added everywhere */
+} ehh_problem_t;
+
+typedef struct {
+    int32_t levels;         /* multigrid levels, 1..EHH_MAX_LEVELS; every (sub)domain
+                               axis must be divisible by 2^(levels-1) */
+    int32_t cycle;          /* 1 = V-cycle, 2 = W-cycle */
+    int32_t nu1, nu2;       /* red-black relaxation steps before / after the correction */
+    int32_t vanka;          /* 1 = full cell block, 0 = economic (diagonal u part) */
+    int32_t precond_bits;   /* 64: complex128 cycle; 32: complex64 cycle (FP32
+                               accumulation) with an FP64 coarsest solve */
+    int32_t restart;        /* FGMRES restart length m, 1..EHH_MAX_RESTART */
+    int32_t dd_parts[3];    /* subdomains per axis; all 1 = no domain decomposition */
+    int32_t dd_overlap;     /* overlap between neighbouring subdomains [cells] */
+    int32_t dd_pad;         /* absorbing padding on interior subdomain sides [cells] */
+    int32_t dd_colors;      /* 1 = one colour, local corrections averaged on the
+                               overlaps; 0 = multicolour schedule of Algorithm 2 */
+    double  damping[EHH_MAX_LEVELS];  /* Vanka damping per level, finest first */
+} ehh_options_t;
+
+typedef struct {
+    int32_t status;         /* ehh_status_t of this right-hand side */
+    int32_t iters;          /* preconditioner applications */
+    double  rel_res_est;    /* Arnoldi estimate |b - A x| / |b| at exit */
+    double  rel_res_true;   /* recomputed |b - A x| / |b| at exit (FP64) */
+    double  conv_factor;    /* (r_k / r_5)^(1/(k-5)) over the estimates (section 5.4) */
+} ehh_stats_t;
+
+/* Defaults: 3 levels, V(1,1), full Vanka, damping 0.75/0.5/0.25..., 64-bit
+ * cycle, restart 5, no domain decomposition. */
+void ehh_default_options(ehh_options_t* opt);
+
+/* Build the operator, its shifted multigrid hierarchy (Galerkin coarse levels
+ * and the inverse of every coarsest operator) and, with domain decomposition,
+ * one padded subdomain hierarchy per subdomain (section 2.1 for the
+ * coefficients, eq. (9) for the hierarchy, section 4 for the subdomains).
+ *   lambda, mu, rho: (device) FP64 cell arrays [Pa, Pa, kg/m^3], x fastest;
+ *                    rho > 0, mu >= 0, lambda + mu > 0.
+ *   gamma:           (device) FP64 physical attenuation [1/s] per cell, or NULL.
+ *   stream:          work is enqueued on it; the call synchronises it once to
+ *                    read the media means.
+ *   out:             receives the handle (set only on EHH_OK).
+ * Errors: EHH_ERR_INVALID (sizes, levels, options), EHH_ERR_BREAKDOWN (non-finite
+ * or non-physical media), EHH_ERR_OOM, EHH_ERR_HIP. */
+int32_t ehh_setup_operator(const ehh_problem_t* problem, const double* lambda,
+                           const double* mu, const double* rho, const double* gamma,
+                           const ehh_options_t* options, void* stream, ehh_handle_t* out);
+
+/* Release every device buffer of the handle (waits for the handle's work). */
+void ehh_destroy(ehh_handle_t h);
+
+/* counts[4] = unknowns of u_0, u_1, u_2 (0 in 2D), p; *stride = 2 * N reals
+ * between consecutive right-hand sides. */
+int32_t ehh_vector_layout(ehh_handle_t h, int64_t counts[4], int64_t* stride);
+
+/* out[0] = mu_bar [Pa], out[1] = rho_bar [kg/m^3], out[2] = nondimensional omega. */
+int32_t ehh_scaling(ehh_handle_t h, double out[3]);
+
+/* y = A x for nrhs right-hand sides (FP64, global layout), A the system of eq. (14)
+ * (shifted = 0) or the shifted preconditioning operator (shifted = 1).
+ * x, y: (device), distinct. */
+int32_t ehh_apply(ehh_handle_t h, int32_t shifted, const double* x, double* y,
+                  int32_t nrhs, void* stream);
+
+/* One multigrid cycle (Algorithm 1, recursive, zero initial guess) of the shifted
+ * operator of subdomain `sub` (0 without domain decomposition): e ~ A_s^{-1} r.
+ * r, e: (device) vectors in the subdomain's level-0 layout (ehh_level_info),
+ * float when precond_bits == 32, double when 64; r and e distinct. */
+int32_t ehh_vcycle(ehh_handle_t h, int32_t sub, const void* r, void* e, int32_t nrhs,
+                   void* stream);
+
+/* z = M^{-1} v: the preconditioner of the outer Krylov method -- one cycle of the
+ * global shifted hierarchy, or with domain decomposition one cycle per padded
+ * subdomain combined by overlap averaging (one colour) or Algorithm 2.
+ * v, z: (device) FP64, global layout, distinct. */
+int32_t ehh_precondition(ehh_handle_t h, const double* v, double* z, int32_t nrhs,
+                         void* stream);
+
+/* Solve A x = b for nrhs right-hand sides with right-preconditioned FGMRES(m)
+ * from x = 0 until |b - A x| <= tol |b| per right-hand side (section 6).
+ * b, x: (device) FP64 global layout; stats: host array of nrhs entries or NULL.
+ * Returns EHH_OK when every right-hand side converged, EHH_NOT_CONVERGED when
+ * maxit preconditioner applications were reached for some (x holds the last
+ * iterates), EHH_ERR_BREAKDOWN on a non-finite residual.  Synchronises `stream`
+ * once per iteration to read the residual estimates. */
+int32_t ehh_solve(ehh_handle_t h, const double* b, double* x, int32_t nrhs, double tol,
+                  int32_t maxit, ehh_stats_t* stats, void* stream);
+
+/* Per-step entry points of the multigrid path (for checking each kernel).
+ * Vectors are (device) in the level's layout and the cycle precision. */
+int32_t ehh_num_subdomains(ehh_handle_t h);
+/* n_local[3]: padded local cells; origin[3]: global cell of local cell 0;
+ * lo[3], hi[3]: owned extent [lo, hi) in global cells. */
+int32_t ehh_subdomain_info(ehh_handle_t h, int32_t sub, int32_t n_local[3],
+                           int32_t origin[3], int32_t lo[3], int32_t hi[3]);
+int32_t ehh_level_info(ehh_handle_t h, int32_t sub, int32_t level, int32_t n[3],
+                       int64_t counts[4], int64_t* stride);
+/* y = A_level x (level 0: the shifted fine operator; level > 0: Galerkin). */
+int32_t ehh_level_apply(ehh_handle_t h, int32_t sub, int32_t level, const void* x,
+                        void* y, int32_t nrhs, void* stream);
+/* One damped red-black half-sweep on colour (0 = red: even index sum) with the
+ * residual taken at the start of the half-sweep; e_in == NULL means e_in = 0. */
+int32_t ehh_level_relax(ehh_handle_t h, int32_t sub, int32_t level, int32_t colour,
+                        const void* b, const void* e_in, void* e_out, int32_t nrhs,
+                        void* stream);
+/* rc = P^T (b - A_level e) on level + 1. */
+int32_t ehh_level_restrict(ehh_handle_t h, int32_t sub, int32_t level, const void* b,
+                           const void* e, void* rc, int32_t nrhs, void* stream);
+/* e += P ec, ec on level + 1. */
+int32_t ehh_level_prolong(ehh_handle_t h, int32_t sub, int32_t level, const void* ec,
+                          void* e, int32_t nrhs, void* stream);
+/* e = A_coarsest^{-1} r (FP64 dense inverse; r, e in the cycle precision). */
+int32_t ehh_coarse_solve(ehh_handle_t h, int32_t sub, const void* r, void* e,
+                         int32_t nrhs, void* stream);
+
+const char* ehh_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EHH_H */

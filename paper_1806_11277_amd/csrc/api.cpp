@@ -1,0 +1,953 @@
+// C ABI of the elastic Helmholtz hybrid MG/DD solver (declared in include/ehh.h).
+//
+// Host side: validation, the multigrid hierarchy per (sub)domain, the cycle
+// sequencing of Algorithm 1 (recursive; one call = V, two = W), the domain
+// decomposition around it (section 4, Algorithm 2) and the flexible GMRES loop.
+// Every arithmetic step runs in the HIP kernels of this library.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "ehh.h"
+#include "internal.hpp"
+
+using namespace ehh;
+
+namespace {
+
+thread_local std::string g_err;
+
+int32_t fail(int32_t code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail(EHH_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define CHK(expr)                      \
+    do {                               \
+        int32_t s_ = (expr);           \
+        if (s_ != EHH_OK) return s_;   \
+    } while (0)
+
+// Optional injected allocation failure (EHH_FAIL_ALLOC_AFTER=k: the (k+1)-th
+// device allocation of the process fails), for testing the OOM path.
+long g_alloc_count = 0;
+long fail_alloc_after() {
+    static long v = [] {
+        const char* s = std::getenv("EHH_FAIL_ALLOC_AFTER");
+        return s ? std::atol(s) : -1L;
+    }();
+    return v;
+}
+
+struct Level {
+    Geo g{};
+    bool fine = false;
+    double damping = 0.0;
+    double* coef64 = nullptr;   // fine: mu, dinv, rho, gam planes; coarse: stencil
+    float* coef32 = nullptr;
+    void* b = nullptr;          // right-hand side of this level (levels >= 1)
+    void* e = nullptr;          // correction of this level (levels >= 1)
+    void* t = nullptr;          // half-sweep ping-pong / residual
+};
+
+struct Sub {
+    int origin[3] = {0, 0, 0}, lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
+    int pad_lo[3] = {0, 0, 0}, pad_hi[3] = {0, 0, 0}, nloc[3] = {1, 1, 1};
+    int colour = 0;
+    std::vector<Level> lev;
+    double* inv = nullptr;      // dense inverse of the coarsest operator
+    void* r0 = nullptr;         // local level-0 right-hand side / correction (DD or FP32)
+    void* e0 = nullptr;
+};
+
+}  // namespace
+
+struct ehh_ctx {
+    ehh_problem_t prob{};
+    ehh_options_t opt{};
+    int dim = 2;
+    Geo gg{};
+    double mu_bar = 1, rho_bar = 1, omega_nd = 1;
+    double* fine64 = nullptr;
+    std::vector<Sub> subs;
+    bool dd = false;
+    int* cnt_dev = nullptr;
+    const int* cnt_cell[3] = {nullptr, nullptr, nullptr};
+    const int* cnt_face[3] = {nullptr, nullptr, nullptr};
+    int ws_rhs = 0;
+    // Krylov workspace
+    int kr_rhs = 0;
+    double *V = nullptr, *Z = nullptr, *w = nullptr, *R = nullptr, *H = nullptr, *cs = nullptr, *g = nullptr;
+    double *hcol = nullptr, *hcol2 = nullptr, *nrm2 = nullptr, *bnorm = nullptr, *est = nullptr, *y = nullptr;
+    double *partial = nullptr, *scal = nullptr;
+    int *active = nullptr, *ncols = nullptr;
+    double* host_pinned = nullptr;
+    std::vector<void*> allocs;
+
+    ~ehh_ctx() {
+        for (void* p : allocs) (void)hipFree(p);
+        if (host_pinned) (void)hipHostFree(host_pinned);
+    }
+
+    int32_t alloc(void** p, size_t bytes) {
+        *p = nullptr;
+        if (bytes == 0) bytes = 8;
+        const long lim = fail_alloc_after();
+        if (lim >= 0 && g_alloc_count >= lim) return fail(EHH_ERR_OOM, "injected allocation failure");
+        ++g_alloc_count;
+        hipError_t e = hipMalloc(p, bytes);
+        if (e != hipSuccess) {
+            *p = nullptr;
+            (void)hipGetLastError();
+            return fail(EHH_ERR_OOM, std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+        }
+        allocs.push_back(*p);
+        return EHH_OK;
+    }
+    void release(void* p) {
+        if (!p) return;
+        auto it = std::find(allocs.begin(), allocs.end(), p);
+        if (it != allocs.end()) allocs.erase(it);
+        (void)hipFree(p);
+    }
+    int bits() const { return opt.precond_bits; }
+};
+
+namespace {
+
+template <typename T> const T* coef_of(const Level& L);
+template <> const double* coef_of<double>(const Level& L) { return L.coef64; }
+template <> const float* coef_of<float>(const Level& L) { return L.coef32; }
+
+template <typename T> LevelDesc<T> level_desc(const ehh_ctx* c, const Level& L, double alpha) {
+    LevelDesc<T> d{};
+    d.g = L.g;
+    d.fine = L.fine;
+    const T* base = coef_of<T>(L);
+    if (L.fine) {
+        const int64_t n = L.g.ncell;
+        d.f = FineCoef<T>{base, base + n, base + 2 * n, base + 3 * n, (T)(c->omega_nd * c->omega_nd), (T)alpha};
+    } else if (L.g.dim == 2) {
+        d.s = stencil_view<2, T>(L.g, base);
+    } else {
+        d.s = stencil_view<3, T>(L.g, base);
+    }
+    return d;
+}
+
+int64_t stencil_size(const Geo& g) { return g.dim == 2 ? stencil_reals<2>(g) : stencil_reals<3>(g); }
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// --------------------------------------------------------------- workspaces
+int32_t ensure_ws(ehh_ctx* c, int nrhs) {
+    if (nrhs <= c->ws_rhs) return EHH_OK;
+    const size_t es = c->bits() == 32 ? sizeof(float) : sizeof(double);
+    for (Sub& S : c->subs) {
+        for (size_t l = 0; l < S.lev.size(); ++l) {
+            Level& L = S.lev[l];
+            const size_t bytes = es * 2 * (size_t)L.g.N * nrhs;
+            c->release(L.b);
+            c->release(L.e);
+            c->release(L.t);
+            L.b = L.e = L.t = nullptr;
+            CHK(c->alloc(&L.t, bytes));
+            if (l > 0) {
+                CHK(c->alloc(&L.b, bytes));
+                CHK(c->alloc(&L.e, bytes));
+            }
+        }
+        c->release(S.r0);
+        c->release(S.e0);
+        S.r0 = S.e0 = nullptr;
+        const size_t b0 = es * 2 * (size_t)S.lev[0].g.N * nrhs;
+        CHK(c->alloc(&S.r0, b0));
+        CHK(c->alloc(&S.e0, b0));
+    }
+    c->ws_rhs = nrhs;
+    return EHH_OK;
+}
+
+int32_t ensure_krylov(ehh_ctx* c, int nrhs) {
+    if (nrhs <= c->kr_rhs) return EHH_OK;
+    const int m = c->opt.restart;
+    const size_t vec = 2 * (size_t)c->gg.N * nrhs * sizeof(double);
+    double** bufs[] = {&c->V, &c->Z, &c->w, &c->R, &c->H, &c->cs, &c->g, &c->hcol, &c->hcol2, &c->nrm2,
+                       &c->bnorm, &c->est, &c->y, &c->partial, &c->scal};
+    for (double** b : bufs) {
+        c->release(*b);
+        *b = nullptr;
+    }
+    c->release(c->active);
+    c->release(c->ncols);
+    c->active = c->ncols = nullptr;
+    if (c->host_pinned) (void)hipHostFree(c->host_pinned);
+    c->host_pinned = nullptr;
+    const int nb = krylov_blocks(c->gg.N);
+    CHK(c->alloc((void**)&c->V, vec * (m + 1)));
+    CHK(c->alloc((void**)&c->Z, vec * m));
+    CHK(c->alloc((void**)&c->w, vec));
+    CHK(c->alloc((void**)&c->R, vec));
+    CHK(c->alloc((void**)&c->H, sizeof(double) * 2 * (size_t)nrhs * m * (m + 1)));
+    CHK(c->alloc((void**)&c->cs, sizeof(double) * 3 * (size_t)nrhs * m));
+    CHK(c->alloc((void**)&c->g, sizeof(double) * 2 * (size_t)nrhs * (m + 1)));
+    CHK(c->alloc((void**)&c->hcol, sizeof(double) * 2 * (size_t)nrhs * (m + 1)));
+    CHK(c->alloc((void**)&c->hcol2, sizeof(double) * 2 * (size_t)nrhs * (m + 1)));
+    CHK(c->alloc((void**)&c->nrm2, sizeof(double) * nrhs));
+    CHK(c->alloc((void**)&c->bnorm, sizeof(double) * nrhs));
+    CHK(c->alloc((void**)&c->est, sizeof(double) * nrhs));
+    CHK(c->alloc((void**)&c->y, sizeof(double) * 2 * (size_t)nrhs * m));
+    CHK(c->alloc((void**)&c->partial, sizeof(double) * (size_t)nb * nrhs * (m + 1) * 2));
+    CHK(c->alloc((void**)&c->scal, sizeof(double) * nrhs));
+    CHK(c->alloc((void**)&c->active, sizeof(int) * nrhs));
+    CHK(c->alloc((void**)&c->ncols, sizeof(int) * nrhs));
+    hipError_t e = hipHostMalloc((void**)&c->host_pinned, sizeof(double) * 4 * nrhs);
+    if (e != hipSuccess) {
+        c->host_pinned = nullptr;
+        return fail(EHH_ERR_OOM, "hipHostMalloc failed");
+    }
+    c->kr_rhs = nrhs;
+    return EHH_OK;
+}
+
+// ------------------------------------------------------------------- the cycle
+template <typename T>
+int32_t cycle(ehh_ctx* c, Sub& S, int l, const T* b, T* e, bool zero_init, int nrhs, hipStream_t s) {
+    Level& L = S.lev[l];
+    const int nl = (int)S.lev.size();
+    if (l == nl - 1) {
+        HIPCHK(launch_coarse_apply<T>(S.inv, L.g.N, b, e, nrhs, s));
+        return EHH_OK;
+    }
+    const LevelDesc<T> D = level_desc<T>(c, L, c->prob.shift);
+    const int econ = c->opt.vanka == 0;
+    T* t = (T*)L.t;
+    bool have = !zero_init;
+    for (int it = 0; it < c->opt.nu1; ++it) {
+        HIPCHK(launch_relax<T>(D, 0, L.damping, econ, b, have ? e : nullptr, t, nrhs, s));
+        HIPCHK(launch_relax<T>(D, 1, L.damping, econ, b, t, e, nrhs, s));
+        have = true;
+    }
+    Level& C = S.lev[l + 1];
+    if (have) {
+        HIPCHK(launch_apply<T>(D, e, b, t, nrhs, s));   // t = b - A e
+        HIPCHK(launch_restrict<T>(L.g, C.g, t, (T*)C.b, nrhs, s));
+    } else {
+        HIPCHK(hipMemsetAsync(e, 0, sizeof(T) * 2 * (size_t)L.g.N * nrhs, s));
+        HIPCHK(launch_restrict<T>(L.g, C.g, b, (T*)C.b, nrhs, s));
+    }
+    for (int k = 0; k < c->opt.cycle; ++k) CHK(cycle<T>(c, S, l + 1, (const T*)C.b, (T*)C.e, k == 0, nrhs, s));
+    HIPCHK(launch_prolong<T>(L.g, C.g, (const T*)C.e, e, nrhs, s));
+    for (int it = 0; it < c->opt.nu2; ++it) {
+        HIPCHK(launch_relax<T>(D, 0, L.damping, econ, b, e, t, nrhs, s));
+        HIPCHK(launch_relax<T>(D, 1, L.damping, econ, b, t, e, nrhs, s));
+    }
+    return EHH_OK;
+}
+
+SubMap submap(const ehh_ctx* c, const Sub& S) {
+    SubMap m{};
+    m.dim = c->dim;
+    for (int a = 0; a < 3; ++a) {
+        m.origin[a] = S.origin[a];
+        m.lo[a] = S.lo[a];
+        m.hi[a] = S.hi[a];
+        m.cnt_cell[a] = c->cnt_cell[a];
+        m.cnt_face[a] = c->cnt_face[a];
+    }
+    return m;
+}
+
+// z = M^{-1} v (FP64 global vectors).
+template <typename T> int32_t precondition_t(ehh_ctx* c, const double* v, double* z, int nrhs, hipStream_t s) {
+    const Geo& gg = c->gg;
+    if (!c->dd) {
+        Sub& S = c->subs[0];
+        if (std::is_same<T, double>::value) {
+            return cycle<T>(c, S, 0, (const T*)v, (T*)z, true, nrhs, s);
+        }
+        HIPCHK(launch_cast_d2f(v, (float*)S.r0, 2 * gg.N * nrhs, s));
+        CHK(cycle<T>(c, S, 0, (const T*)S.r0, (T*)S.e0, true, nrhs, s));
+        HIPCHK(launch_cast_f2d((const float*)S.e0, z, 2 * gg.N * nrhs, s));
+        return EHH_OK;
+    }
+    HIPCHK(hipMemsetAsync(z, 0, sizeof(double) * 2 * (size_t)gg.N * nrhs, s));
+    if (c->opt.dd_colors == 1) {
+        for (Sub& S : c->subs) {
+            const SubMap m = submap(c, S);
+            HIPCHK(launch_dd_gather<T>(gg, S.lev[0].g, m, v, (T*)S.r0, nrhs, s));
+            CHK(cycle<T>(c, S, 0, (const T*)S.r0, (T*)S.e0, true, nrhs, s));
+            HIPCHK(launch_dd_scatter<T>(gg, S.lev[0].g, m, (const T*)S.e0, z, nrhs, 1, s));
+        }
+        return EHH_OK;
+    }
+    // Algorithm 2: colours in turn, each from the residual of the unshifted operator
+    int ncol = 0;
+    for (const Sub& S : c->subs) ncol = std::max(ncol, S.colour + 1);
+    const Level& L0 = c->subs[0].lev[0];
+    (void)L0;
+    LevelDesc<double> A{};
+    A.g = gg;
+    A.fine = true;
+    const int64_t n = gg.ncell;
+    A.f = FineCoef<double>{c->fine64, c->fine64 + n, c->fine64 + 2 * n, c->fine64 + 3 * n,
+                           c->omega_nd * c->omega_nd, 0.0};
+    for (int col = 0; col < ncol; ++col) {
+        const double* src = v;
+        if (col > 0) {
+            HIPCHK(launch_apply<double>(A, z, v, c->R, nrhs, s));   // R = v - A z
+            src = c->R;
+        }
+        for (Sub& S : c->subs) {
+            if (S.colour != col) continue;
+            const SubMap m = submap(c, S);
+            HIPCHK(launch_dd_gather<T>(gg, S.lev[0].g, m, src, (T*)S.r0, nrhs, s));
+            CHK(cycle<T>(c, S, 0, (const T*)S.r0, (T*)S.e0, true, nrhs, s));
+            HIPCHK(launch_dd_scatter<T>(gg, S.lev[0].g, m, (const T*)S.e0, z, nrhs, 0, s));
+        }
+    }
+    return EHH_OK;
+}
+
+int32_t precondition_any(ehh_ctx* c, const double* v, double* z, int nrhs, hipStream_t s) {
+    CHK(ensure_ws(c, nrhs));
+    if (c->dd && c->opt.dd_colors != 1) CHK(ensure_krylov(c, nrhs));
+    return c->bits() == 32 ? precondition_t<float>(c, v, z, nrhs, s) : precondition_t<double>(c, v, z, nrhs, s);
+}
+
+// ------------------------------------------------------------------ validation
+int32_t check_problem(const ehh_problem_t* p, const ehh_options_t* o) {
+    if (!p || !o) return fail(EHH_ERR_INVALID, "null problem or options");
+    if (p->dim != 2 && p->dim != 3) return fail(EHH_ERR_INVALID, "dim must be 2 or 3");
+    for (int a = 0; a < p->dim; ++a) {
+        if (p->n[a] < 2 || p->n[a] > (1 << 20)) return fail(EHH_ERR_INVALID, "each n[a] must be in [2, 2^20]");
+        if (p->abl_cells[a] < 0 || p->abl_cells[a] > p->n[a]) return fail(EHH_ERR_INVALID, "abl_cells out of range");
+    }
+    if (!(p->h > 0) || !(p->omega > 0) || !(p->shift >= 0) || !(p->abl_max >= 0) || !(p->atten0 >= 0) ||
+        !std::isfinite(p->h) || !std::isfinite(p->omega) || !std::isfinite(p->shift) || !std::isfinite(p->abl_max) ||
+        !std::isfinite(p->atten0))
+        return fail(EHH_ERR_INVALID, "h, omega > 0 and shift, abl_max, atten0 >= 0 (finite) required");
+    if (o->levels < 1 || o->levels > EHH_MAX_LEVELS) return fail(EHH_ERR_INVALID, "levels out of range");
+    if (o->cycle != 1 && o->cycle != 2) return fail(EHH_ERR_INVALID, "cycle must be 1 (V) or 2 (W)");
+    if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 > 8 || o->nu2 > 8) return fail(EHH_ERR_INVALID, "nu1, nu2 in [0, 8]");
+    if (o->vanka != 0 && o->vanka != 1) return fail(EHH_ERR_INVALID, "vanka must be 0 or 1");
+    if (o->precond_bits != 32 && o->precond_bits != 64) return fail(EHH_ERR_INVALID, "precond_bits must be 32 or 64");
+    if (o->restart < 1 || o->restart > EHH_MAX_RESTART) return fail(EHH_ERR_INVALID, "restart out of range");
+    for (int a = 0; a < p->dim; ++a)
+        if (o->dd_parts[a] < 1 || o->dd_parts[a] > p->n[a]) return fail(EHH_ERR_INVALID, "dd_parts out of range");
+    if (o->dd_overlap < 0 || o->dd_pad < 0) return fail(EHH_ERR_INVALID, "dd_overlap, dd_pad >= 0");
+    if (o->dd_colors != 0 && o->dd_colors != 1) return fail(EHH_ERR_INVALID, "dd_colors must be 0 or 1");
+    for (int l = 0; l < o->levels - 1; ++l)
+        if (!(o->damping[l] > 0 && o->damping[l] <= 2)) return fail(EHH_ERR_INVALID, "damping must be in (0, 2]");
+    return EHH_OK;
+}
+
+// Subdomain extents per axis: core = n / parts, overlap split around the cut,
+// absorbing padding on interior sides only.
+void make_subdomains(ehh_ctx* c) {
+    const int d = c->dim;
+    int parts[3] = {1, 1, 1};
+    for (int a = 0; a < d; ++a) parts[a] = c->opt.dd_parts[a];
+    const int ov = c->opt.dd_overlap, pad = c->opt.dd_pad;
+    const int nz = d == 3 ? parts[2] : 1;
+    for (int pz = 0; pz < nz; ++pz)
+        for (int py = 0; py < parts[1]; ++py)
+            for (int px = 0; px < parts[0]; ++px) {
+                Sub S;
+                const int idx[3] = {px, py, pz};
+                for (int a = 0; a < 3; ++a) {
+                    if (a >= d) {
+                        S.lo[a] = 0;
+                        S.hi[a] = 1;
+                        S.nloc[a] = 1;
+                        continue;
+                    }
+                    const int n = c->prob.n[a], P = parts[a], p = idx[a];
+                    const int core = n / P;
+                    int lo = std::max(0, p * core - ov / 2);
+                    int hi = p < P - 1 ? std::min(n, (p + 1) * core + (ov - ov / 2)) : n;
+                    if (p == 0) lo = 0;
+                    S.lo[a] = lo;
+                    S.hi[a] = hi;
+                    S.pad_lo[a] = lo > 0 ? pad : 0;
+                    S.pad_hi[a] = hi < n ? pad : 0;
+                    S.origin[a] = lo - S.pad_lo[a];
+                    S.nloc[a] = hi - lo + S.pad_lo[a] + S.pad_hi[a];
+                }
+                S.colour = (px % 2) + 2 * (py % 2) + 4 * (pz % 2);
+                c->subs.push_back(std::move(S));
+            }
+}
+
+int32_t build_hierarchy(ehh_ctx* c, Sub& S, const double* lam, const double* mu, const double* rho,
+                        const double* gam, hipStream_t s) {
+    const int L = c->opt.levels;
+    S.lev.resize(L);
+    int n[3] = {S.nloc[0], S.nloc[1], S.nloc[2]};
+    for (int l = 0; l < L; ++l) {
+        if (l > 0)
+            for (int a = 0; a < c->dim; ++a) {
+                if (n[a] % 2) return fail(EHH_ERR_INVALID, "(sub)domain size not divisible by 2^(levels-1)");
+                n[a] /= 2;
+            }
+        for (int a = 0; a < c->dim; ++a)
+            if (n[a] < 2) return fail(EHH_ERR_INVALID, "coarsest grid must keep at least 2 cells per axis");
+        S.lev[l].g = make_geo(c->dim, n);
+        S.lev[l].fine = l == 0;
+        S.lev[l].damping = l < L - 1 ? c->opt.damping[l] : 0.0;
+    }
+    // level 0 coefficients
+    Level& L0 = S.lev[0];
+    if (!c->dd) {
+        L0.coef64 = c->fine64;
+    } else {
+        CHK(c->alloc((void**)&L0.coef64, sizeof(double) * 4 * L0.g.ncell));
+        FineCoefParams p{};
+        p.dim = c->dim;
+        for (int a = 0; a < 3; ++a) {
+            p.n_glob[a] = c->gg.n[a];
+            p.n_loc[a] = L0.g.n[a];
+            p.origin[a] = S.origin[a];
+            p.pad_lo[a] = S.pad_lo[a];
+            p.pad_hi[a] = S.pad_hi[a];
+            p.abl[a] = a < c->dim ? c->prob.abl_cells[a] : 0;
+        }
+        p.abl_max = c->prob.abl_max;
+        p.gam0 = c->prob.atten0 / c->prob.omega;
+        p.inv_omega = 1.0 / c->prob.omega;
+        p.mu_bar = c->mu_bar;
+        p.rho_bar = c->rho_bar;
+        HIPCHK(launch_fine_coef(p, lam, mu, rho, gam, L0.coef64, s));
+    }
+    const int64_t n0 = L0.g.ncell;
+    const FineCoef<double> fc{L0.coef64, L0.coef64 + n0, L0.coef64 + 2 * n0, L0.coef64 + 3 * n0,
+                              c->omega_nd * c->omega_nd, c->prob.shift};
+    // stencil of level 0 (temporary), Galerkin levels, dense coarsest
+    double* st0 = nullptr;
+    CHK(c->alloc((void**)&st0, sizeof(double) * stencil_size(L0.g)));
+    HIPCHK(launch_materialise(L0.g, fc, st0, s));
+    const double* prev = st0;
+    for (int l = 1; l < L; ++l) {
+        Level& C = S.lev[l];
+        CHK(c->alloc((void**)&C.coef64, sizeof(double) * stencil_size(C.g)));
+        HIPCHK(launch_galerkin(S.lev[l - 1].g, prev, C.g, C.coef64, s));
+        prev = C.coef64;
+    }
+    const Level& Lc = S.lev[L - 1];
+    const int64_t nc = Lc.g.N;
+    if ((double)nc * nc * 16.0 > 8.0e9) return fail(EHH_ERR_UNSUPPORTED, "coarsest grid too large for a dense inverse");
+    CHK(c->alloc((void**)&S.inv, sizeof(double) * 2 * nc * nc));
+    HIPCHK(launch_dense_assemble(Lc.g, L == 1 ? st0 : Lc.coef64, S.inv, s));
+    double* work = nullptr;
+    int* piv = nullptr;
+    CHK(c->alloc((void**)&work, sizeof(double) * 2 * nc));
+    CHK(c->alloc((void**)&piv, sizeof(int) * nc));
+    HIPCHK(launch_dense_invert(S.inv, nc, 1, work, piv, s));
+    HIPCHK(hipStreamSynchronize(s));
+    c->release(work);
+    c->release(piv);
+    c->release(st0);
+    if (c->bits() == 32) {
+        for (int l = 0; l < L; ++l) {
+            Level& Q = S.lev[l];
+            if (l == 0 && !c->dd) continue;   // shares the global FP32 copy (set by the caller)
+            const int64_t cnt = Q.fine ? 4 * Q.g.ncell : stencil_size(Q.g);
+            CHK(c->alloc((void**)&Q.coef32, sizeof(float) * cnt));
+            HIPCHK(launch_cast_d2f(Q.coef64, Q.coef32, cnt, s));
+        }
+    }
+    return EHH_OK;
+}
+
+int32_t setup_impl(ehh_ctx* c, const double* lam, const double* mu, const double* rho, const double* gam,
+                   hipStream_t s) {
+    const ehh_problem_t& P = c->prob;
+    c->dim = P.dim;
+    int n[3] = {P.n[0], P.n[1], P.dim == 3 ? P.n[2] : 1};
+    c->gg = make_geo(P.dim, n);
+    // media means and physical check
+    const int nb = media_check_blocks(c->gg.ncell);
+    double* part = nullptr;
+    CHK(c->alloc((void**)&part, sizeof(double) * (3 * nb + 4)));
+    HIPCHK(launch_media_check(lam, mu, rho, gam, c->gg.ncell, part, nb, part + 3 * nb, s));
+    double sums[4];
+    HIPCHK(hipMemcpyAsync(sums, part + 3 * nb, sizeof(sums), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    c->release(part);
+    if (sums[2] > 0) return fail(EHH_ERR_BREAKDOWN, "media contain non-finite or non-physical values");
+    c->mu_bar = sums[0] / (double)c->gg.ncell;
+    if (!(c->mu_bar > 0)) c->mu_bar = sums[3] / (double)c->gg.ncell;
+    c->rho_bar = sums[1] / (double)c->gg.ncell;
+    if (!(c->mu_bar > 0) || !(c->rho_bar > 0)) return fail(EHH_ERR_BREAKDOWN, "degenerate media means");
+    c->omega_nd = P.omega * P.h * std::sqrt(c->rho_bar / c->mu_bar);
+    // global fine coefficients (the unshifted operator of the outer solve)
+    CHK(c->alloc((void**)&c->fine64, sizeof(double) * 4 * c->gg.ncell));
+    FineCoefParams fp{};
+    fp.dim = P.dim;
+    for (int a = 0; a < 3; ++a) {
+        fp.n_glob[a] = n[a];
+        fp.n_loc[a] = n[a];
+        fp.abl[a] = a < P.dim ? P.abl_cells[a] : 0;
+    }
+    fp.abl_max = P.abl_max;
+    fp.gam0 = P.atten0 / P.omega;
+    fp.inv_omega = 1.0 / P.omega;
+    fp.mu_bar = c->mu_bar;
+    fp.rho_bar = c->rho_bar;
+    HIPCHK(launch_fine_coef(fp, lam, mu, rho, gam, c->fine64, s));
+    // subdomains
+    c->dd = false;
+    for (int a = 0; a < P.dim; ++a) c->dd = c->dd || c->opt.dd_parts[a] > 1;
+    if (c->dd) {
+        make_subdomains(c);
+        // owner counts per axis
+        std::vector<int> host;
+        int offc[3], offf[3];
+        for (int a = 0; a < 3; ++a) {
+            offc[a] = (int)host.size();
+            const int na = a < P.dim ? n[a] : 1;
+            for (int x = 0; x < na; ++x) {
+                int cnt = 0;
+                std::vector<std::pair<int, int>> seen;
+                for (const Sub& S : c->subs) {
+                    std::pair<int, int> r{S.lo[a], S.hi[a]};
+                    if (std::find(seen.begin(), seen.end(), r) != seen.end()) continue;
+                    seen.push_back(r);
+                    if (x >= S.lo[a] && x < S.hi[a]) ++cnt;
+                }
+                host.push_back(std::max(cnt, 1));
+            }
+            offf[a] = (int)host.size();
+            for (int f = 0; f <= na; ++f) {
+                int cnt = 0;
+                std::vector<std::pair<int, int>> seen;
+                for (const Sub& S : c->subs) {
+                    std::pair<int, int> r{S.lo[a], S.hi[a]};
+                    if (std::find(seen.begin(), seen.end(), r) != seen.end()) continue;
+                    seen.push_back(r);
+                    if (f > S.lo[a] && f < S.hi[a]) ++cnt;
+                }
+                host.push_back(std::max(cnt, 1));
+            }
+        }
+        CHK(c->alloc((void**)&c->cnt_dev, sizeof(int) * host.size()));
+        HIPCHK(hipMemcpyAsync(c->cnt_dev, host.data(), sizeof(int) * host.size(), hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int a = 0; a < 3; ++a) {
+            c->cnt_cell[a] = c->cnt_dev + offc[a];
+            c->cnt_face[a] = c->cnt_dev + offf[a];
+        }
+    } else {
+        Sub S;
+        for (int a = 0; a < 3; ++a) {
+            S.hi[a] = n[a];
+            S.nloc[a] = n[a];
+        }
+        c->subs.push_back(std::move(S));
+    }
+    float* fine32 = nullptr;
+    if (c->bits() == 32 && !c->dd) {
+        CHK(c->alloc((void**)&fine32, sizeof(float) * 4 * c->gg.ncell));
+        HIPCHK(launch_cast_d2f(c->fine64, fine32, 4 * c->gg.ncell, s));
+    }
+    for (Sub& S : c->subs) {
+        CHK(build_hierarchy(c, S, lam, mu, rho, gam, s));
+        if (fine32) S.lev[0].coef32 = fine32;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    return EHH_OK;
+}
+
+int32_t check_handle(ehh_handle_t h) {
+    if (!h) return fail(EHH_ERR_INVALID, "null handle");
+    return EHH_OK;
+}
+
+int32_t level_of(ehh_ctx* c, int sub, int level, Sub** S, Level** L) {
+    if (sub < 0 || sub >= (int)c->subs.size()) return fail(EHH_ERR_INVALID, "subdomain index out of range");
+    Sub& Sr = c->subs[sub];
+    if (level < 0 || level >= (int)Sr.lev.size()) return fail(EHH_ERR_INVALID, "level out of range");
+    *S = &Sr;
+    *L = &Sr.lev[level];
+    return EHH_OK;
+}
+
+}  // namespace
+
+// ======================================================================= C ABI
+extern "C" {
+
+void ehh_default_options(ehh_options_t* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->levels = 3;
+    o->cycle = 1;
+    o->nu1 = o->nu2 = 1;
+    o->vanka = 1;
+    o->precond_bits = 64;
+    o->restart = 5;
+    o->dd_parts[0] = o->dd_parts[1] = o->dd_parts[2] = 1;
+    o->dd_colors = 1;
+    const double d[EHH_MAX_LEVELS] = {0.75, 0.5, 0.25, 0.25, 0.25, 0.25, 0.25, 0.25};
+    for (int l = 0; l < EHH_MAX_LEVELS; ++l) o->damping[l] = d[l];
+}
+
+int32_t ehh_setup_operator(const ehh_problem_t* problem, const double* lambda, const double* mu, const double* rho,
+                           const double* gamma, const ehh_options_t* options, void* stream, ehh_handle_t* out) {
+    if (!out) return fail(EHH_ERR_INVALID, "null output handle");
+    *out = nullptr;
+    CHK(check_problem(problem, options));
+    if (!lambda || !mu || !rho) return fail(EHH_ERR_INVALID, "null media pointer");
+    ehh_ctx* c = new ehh_ctx();
+    c->prob = *problem;
+    c->opt = *options;
+    if (c->prob.dim == 2) {
+        c->prob.n[2] = 1;
+        c->prob.abl_cells[2] = 0;
+        c->opt.dd_parts[2] = 1;
+    }
+    int32_t st = setup_impl(c, lambda, mu, rho, gamma, as_stream(stream));
+    if (st != EHH_OK) {
+        (void)hipStreamSynchronize(as_stream(stream));
+        delete c;
+        return st;
+    }
+    *out = c;
+    return EHH_OK;
+}
+
+void ehh_destroy(ehh_handle_t h) {
+    if (!h) return;
+    (void)hipDeviceSynchronize();
+    delete h;
+}
+
+int32_t ehh_vector_layout(ehh_handle_t h, int64_t counts[4], int64_t* stride) {
+    CHK(check_handle(h));
+    if (!counts || !stride) return fail(EHH_ERR_INVALID, "null output");
+    for (int k = 0; k < 4; ++k) counts[k] = h->gg.cnt[k];
+    *stride = 2 * h->gg.N;
+    return EHH_OK;
+}
+
+int32_t ehh_scaling(ehh_handle_t h, double out[3]) {
+    CHK(check_handle(h));
+    if (!out) return fail(EHH_ERR_INVALID, "null output");
+    out[0] = h->mu_bar;
+    out[1] = h->rho_bar;
+    out[2] = h->omega_nd;
+    return EHH_OK;
+}
+
+int32_t ehh_apply(ehh_handle_t h, int32_t shifted, const double* x, double* y, int32_t nrhs, void* stream) {
+    CHK(check_handle(h));
+    if (!x || !y || x == y || nrhs < 1) return fail(EHH_ERR_INVALID, "ehh_apply: bad vectors or nrhs");
+    LevelDesc<double> A{};
+    A.g = h->gg;
+    A.fine = true;
+    const int64_t n = h->gg.ncell;
+    A.f = FineCoef<double>{h->fine64, h->fine64 + n, h->fine64 + 2 * n, h->fine64 + 3 * n,
+                           h->omega_nd * h->omega_nd, shifted ? h->prob.shift : 0.0};
+    HIPCHK(launch_apply<double>(A, x, nullptr, y, nrhs, as_stream(stream)));
+    return EHH_OK;
+}
+
+int32_t ehh_vcycle(ehh_handle_t h, int32_t sub, const void* r, void* e, int32_t nrhs, void* stream) {
+    CHK(check_handle(h));
+    Sub* S;
+    Level* L;
+    CHK(level_of(h, sub, 0, &S, &L));
+    if (!r || !e || r == e || nrhs < 1) return fail(EHH_ERR_INVALID, "ehh_vcycle: bad vectors or nrhs");
+    CHK(ensure_ws(h, nrhs));
+    if (h->bits() == 32) return cycle<float>(h, *S, 0, (const float*)r, (float*)e, true, nrhs, as_stream(stream));
+    return cycle<double>(h, *S, 0, (const double*)r, (double*)e, true, nrhs, as_stream(stream));
+}
+
+int32_t ehh_precondition(ehh_handle_t h, const double* v, double* z, int32_t nrhs, void* stream) {
+    CHK(check_handle(h));
+    if (!v || !z || v == z || nrhs < 1) return fail(EHH_ERR_INVALID, "ehh_precondition: bad vectors or nrhs");
+    return precondition_any(h, v, z, nrhs, as_stream(stream));
+}
+
+int32_t ehh_solve(ehh_handle_t h, const double* b, double* x, int32_t nrhs, double tol, int32_t maxit,
+                  ehh_stats_t* stats, void* stream) {
+    CHK(check_handle(h));
+    if (!b || !x || b == x || nrhs < 1 || !(tol > 0) || maxit < 1)
+        return fail(EHH_ERR_INVALID, "ehh_solve: bad vectors, nrhs, tol or maxit");
+    hipStream_t s = as_stream(stream);
+    ehh_ctx* c = h;
+    CHK(ensure_ws(c, nrhs));
+    CHK(ensure_krylov(c, nrhs));
+    const int m = c->opt.restart;
+    const int64_t N = c->gg.N;
+    const size_t vb = sizeof(double) * 2 * (size_t)N;
+    double* hp = c->host_pinned;
+    LevelDesc<double> A{};
+    A.g = c->gg;
+    A.fine = true;
+    const int64_t nc = c->gg.ncell;
+    A.f = FineCoef<double>{c->fine64, c->fine64 + nc, c->fine64 + 2 * nc, c->fine64 + 3 * nc,
+                           c->omega_nd * c->omega_nd, 0.0};
+
+    std::vector<double> bnorm(nrhs), beta(nrhs), est(nrhs, 1.0), fin_est(nrhs, 1.0);
+    std::vector<int> active(nrhs, 0), iters(nrhs, 0), ncols(nrhs, 0), done_flag(nrhs, 0);
+    std::vector<std::vector<double>> hist(nrhs);
+    HIPCHK(launch_norm2(b, N, nrhs, c->partial, c->nrm2, s));
+    HIPCHK(hipMemcpyAsync(hp, c->nrm2, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemsetAsync(x, 0, vb * nrhs, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int r = 0; r < nrhs; ++r) {
+        bnorm[r] = std::sqrt(hp[r]);
+        if (!std::isfinite(bnorm[r])) return fail(EHH_ERR_BREAKDOWN, "non-finite right-hand side");
+    }
+    HIPCHK(hipMemcpyAsync(c->bnorm, bnorm.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, s));
+    int it = 0;
+    bool first = true;
+    bool breakdown = false;
+    std::vector<double> g0(2 * (size_t)nrhs * (m + 1));
+    std::vector<double> inv_beta(nrhs);
+    while (true) {
+        // true residual R = b - A x
+        if (first) {
+            HIPCHK(hipMemcpyAsync(c->R, b, vb * nrhs, hipMemcpyDeviceToDevice, s));
+            for (int r = 0; r < nrhs; ++r) beta[r] = bnorm[r];
+        } else {
+            HIPCHK(launch_apply<double>(A, x, b, c->R, nrhs, s));
+            HIPCHK(launch_norm2(c->R, N, nrhs, c->partial, c->nrm2, s));
+            HIPCHK(hipMemcpyAsync(hp, c->nrm2, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            for (int r = 0; r < nrhs; ++r) beta[r] = std::sqrt(hp[r]);
+        }
+        first = false;
+        int nact = 0;
+        for (int r = 0; r < nrhs; ++r) {
+            if (!std::isfinite(beta[r])) breakdown = true;
+            active[r] = bnorm[r] > 0 && beta[r] > tol * bnorm[r] && std::isfinite(beta[r]);
+            if (bnorm[r] > 0) fin_est[r] = beta[r] / bnorm[r];
+            nact += active[r];
+        }
+        if (breakdown || nact == 0 || it >= maxit) break;
+        std::fill(g0.begin(), g0.end(), 0.0);
+        for (int r = 0; r < nrhs; ++r) {
+            g0[2 * (size_t)r * (m + 1)] = beta[r];
+            inv_beta[r] = active[r] ? 1.0 / beta[r] : 0.0;
+            ncols[r] = 0;
+        }
+        HIPCHK(hipMemcpyAsync(c->g, g0.data(), sizeof(double) * g0.size(), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(c->scal, inv_beta.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(c->active, active.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+        HIPCHK(launch_scale(c->R, c->V, N, nrhs, c->scal, 0, s));
+        int j = 0;
+        for (j = 0; j < m; ++j) {
+            double* Vj = c->V + (size_t)j * nrhs * 2 * N;
+            double* Zj = c->Z + (size_t)j * nrhs * 2 * N;
+            CHK(precondition_any(c, Vj, Zj, nrhs, s));
+            HIPCHK(launch_apply<double>(A, Zj, nullptr, c->w, nrhs, s));
+            // classical Gram-Schmidt, twice
+            HIPCHK(launch_dots(c->V, j + 1, c->w, N, nrhs, c->partial, c->hcol, m + 1, s));
+            HIPCHK(launch_axpy_multi(c->V, j + 1, c->w, N, nrhs, c->hcol, m + 1, c->partial, nullptr, s));
+            HIPCHK(launch_dots(c->V, j + 1, c->w, N, nrhs, c->partial, c->hcol2, m + 1, s));
+            HIPCHK(launch_axpy_multi(c->V, j + 1, c->w, N, nrhs, c->hcol2, m + 1, c->partial, c->nrm2, s));
+            HIPCHK(launch_axpby(c->hcol, c->hcol2, c->hcol, 2 * (int64_t)nrhs * (m + 1), 1.0, 1.0, s));
+            HIPCHK(launch_givens(c->H, c->cs, c->g, c->hcol, c->nrm2, j, m, nrhs, c->active, c->est, c->bnorm, s));
+            HIPCHK(launch_scale(c->w, c->V + (size_t)(j + 1) * nrhs * 2 * N, N, nrhs, c->nrm2, 1, s));
+            HIPCHK(hipMemcpyAsync(hp, c->est, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            ++it;
+            bool changed = false;
+            int left = 0;
+            for (int r = 0; r < nrhs; ++r) {
+                if (!active[r]) continue;
+                iters[r] += 1;
+                const double e = hp[r];
+                hist[r].push_back(e);
+                fin_est[r] = e;
+                if (!std::isfinite(e)) {
+                    breakdown = true;
+                    active[r] = 0;
+                    ncols[r] = j;
+                    changed = true;
+                    continue;
+                }
+                if (e <= tol) {
+                    active[r] = 0;
+                    ncols[r] = j + 1;
+                    changed = true;
+                    continue;
+                }
+                ++left;
+            }
+            if (left == 0 || it >= maxit || breakdown) break;
+            if (changed)
+                HIPCHK(hipMemcpyAsync(c->active, active.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+        }
+        const int done_cols = std::min(j + 1, m);
+        for (int r = 0; r < nrhs; ++r)
+            if (active[r]) ncols[r] = done_cols;
+        HIPCHK(hipMemcpyAsync(c->ncols, ncols.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+        HIPCHK(launch_update_x(c->H, c->g, c->Z, x, N, nrhs, m, c->ncols, c->y, s));
+        if (breakdown) break;
+    }
+    // final true residuals
+    HIPCHK(launch_apply<double>(A, x, b, c->R, nrhs, s));
+    HIPCHK(launch_norm2(c->R, N, nrhs, c->partial, c->nrm2, s));
+    HIPCHK(hipMemcpyAsync(hp, c->nrm2, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int32_t status = EHH_OK;
+    for (int r = 0; r < nrhs; ++r) {
+        const double tr = bnorm[r] > 0 ? std::sqrt(hp[r]) / bnorm[r] : 0.0;
+        int32_t st = EHH_OK;
+        if (!std::isfinite(tr) || breakdown) st = EHH_ERR_BREAKDOWN;
+        else if (tr > tol) st = EHH_NOT_CONVERGED;
+        if (stats) {
+            stats[r].status = st;
+            stats[r].iters = iters[r];
+            stats[r].rel_res_est = fin_est[r];
+            stats[r].rel_res_true = tr;
+            const auto& hh = hist[r];
+            const int warm = 5;
+            if ((int)hh.size() > warm + 1 && hh[warm] > 0 && hh.back() > 0)
+                stats[r].conv_factor = std::pow(hh.back() / hh[warm], 1.0 / (double)(hh.size() - 1 - warm));
+            else
+                stats[r].conv_factor = NAN;
+        }
+        if (st == EHH_ERR_BREAKDOWN) status = EHH_ERR_BREAKDOWN;
+        else if (st == EHH_NOT_CONVERGED && status == EHH_OK) status = EHH_NOT_CONVERGED;
+    }
+    if (status == EHH_ERR_BREAKDOWN) g_err = "non-finite residual in the Krylov iteration";
+    else if (status == EHH_NOT_CONVERGED) g_err = "maxit reached before tol";
+    return status;
+}
+
+int32_t ehh_num_subdomains(ehh_handle_t h) { return h ? (int32_t)h->subs.size() : 0; }
+
+int32_t ehh_subdomain_info(ehh_handle_t h, int32_t sub, int32_t n_local[3], int32_t origin[3], int32_t lo[3],
+                           int32_t hi[3]) {
+    CHK(check_handle(h));
+    if (sub < 0 || sub >= (int)h->subs.size()) return fail(EHH_ERR_INVALID, "subdomain index out of range");
+    const Sub& S = h->subs[sub];
+    for (int a = 0; a < 3; ++a) {
+        if (n_local) n_local[a] = S.nloc[a];
+        if (origin) origin[a] = S.origin[a];
+        if (lo) lo[a] = S.lo[a];
+        if (hi) hi[a] = S.hi[a];
+    }
+    return EHH_OK;
+}
+
+int32_t ehh_level_info(ehh_handle_t h, int32_t sub, int32_t level, int32_t n[3], int64_t counts[4], int64_t* stride) {
+    CHK(check_handle(h));
+    Sub* S;
+    Level* L;
+    CHK(level_of(h, sub, level, &S, &L));
+    for (int a = 0; a < 3; ++a)
+        if (n) n[a] = L->g.n[a];
+    for (int k = 0; k < 4; ++k)
+        if (counts) counts[k] = L->g.cnt[k];
+    if (stride) *stride = 2 * L->g.N;
+    return EHH_OK;
+}
+
+int32_t ehh_level_apply(ehh_handle_t h, int32_t sub, int32_t level, const void* x, void* y, int32_t nrhs,
+                        void* stream) {
+    CHK(check_handle(h));
+    Sub* S;
+    Level* L;
+    CHK(level_of(h, sub, level, &S, &L));
+    if (!x || !y || x == y || nrhs < 1) return fail(EHH_ERR_INVALID, "bad vectors or nrhs");
+    if (h->bits() == 32)
+        HIPCHK(launch_apply<float>(level_desc<float>(h, *L, h->prob.shift), (const float*)x, nullptr, (float*)y, nrhs,
+                                   as_stream(stream)));
+    else
+        HIPCHK(launch_apply<double>(level_desc<double>(h, *L, h->prob.shift), (const double*)x, nullptr, (double*)y,
+                                    nrhs, as_stream(stream)));
+    return EHH_OK;
+}
+
+int32_t ehh_level_relax(ehh_handle_t h, int32_t sub, int32_t level, int32_t colour, const void* b, const void* e_in,
+                        void* e_out, int32_t nrhs, void* stream) {
+    CHK(check_handle(h));
+    Sub* S;
+    Level* L;
+    CHK(level_of(h, sub, level, &S, &L));
+    if (level == (int)S->lev.size() - 1) return fail(EHH_ERR_INVALID, "the coarsest level is not relaxed");
+    if (!b || !e_out || e_in == e_out || b == e_out || (colour != 0 && colour != 1) || nrhs < 1)
+        return fail(EHH_ERR_INVALID, "bad vectors, colour or nrhs");
+    const int econ = h->opt.vanka == 0;
+    if (h->bits() == 32)
+        HIPCHK(launch_relax<float>(level_desc<float>(h, *L, h->prob.shift), colour, L->damping, econ, (const float*)b,
+                                   (const float*)e_in, (float*)e_out, nrhs, as_stream(stream)));
+    else
+        HIPCHK(launch_relax<double>(level_desc<double>(h, *L, h->prob.shift), colour, L->damping, econ,
+                                    (const double*)b, (const double*)e_in, (double*)e_out, nrhs, as_stream(stream)));
+    return EHH_OK;
+}
+
+int32_t ehh_level_restrict(ehh_handle_t h, int32_t sub, int32_t level, const void* b, const void* e, void* rc,
+                           int32_t nrhs, void* stream) {
+    CHK(check_handle(h));
+    Sub* S;
+    Level* L;
+    CHK(level_of(h, sub, level, &S, &L));
+    if (level == (int)S->lev.size() - 1) return fail(EHH_ERR_INVALID, "no coarser level");
+    if (!b || !e || !rc || nrhs < 1) return fail(EHH_ERR_INVALID, "bad vectors or nrhs");
+    CHK(ensure_ws(h, nrhs));
+    hipStream_t s = as_stream(stream);
+    const Geo& gc = S->lev[level + 1].g;
+    if (h->bits() == 32) {
+        HIPCHK(launch_apply<float>(level_desc<float>(h, *L, h->prob.shift), (const float*)e, (const float*)b,
+                                   (float*)L->t, nrhs, s));
+        HIPCHK(launch_restrict<float>(L->g, gc, (const float*)L->t, (float*)rc, nrhs, s));
+    } else {
+        HIPCHK(launch_apply<double>(level_desc<double>(h, *L, h->prob.shift), (const double*)e, (const double*)b,
+                                    (double*)L->t, nrhs, s));
+        HIPCHK(launch_restrict<double>(L->g, gc, (const double*)L->t, (double*)rc, nrhs, s));
+    }
+    return EHH_OK;
+}
+
+int32_t ehh_level_prolong(ehh_handle_t h, int32_t sub, int32_t level, const void* ec, void* e, int32_t nrhs,
+                          void* stream) {
+    CHK(check_handle(h));
+    Sub* S;
+    Level* L;
+    CHK(level_of(h, sub, level, &S, &L));
+    if (level == (int)S->lev.size() - 1) return fail(EHH_ERR_INVALID, "no coarser level");
+    if (!ec || !e || nrhs < 1) return fail(EHH_ERR_INVALID, "bad vectors or nrhs");
+    const Geo& gc = S->lev[level + 1].g;
+    if (h->bits() == 32)
+        HIPCHK(launch_prolong<float>(L->g, gc, (const float*)ec, (float*)e, nrhs, as_stream(stream)));
+    else
+        HIPCHK(launch_prolong<double>(L->g, gc, (const double*)ec, (double*)e, nrhs, as_stream(stream)));
+    return EHH_OK;
+}
+
+int32_t ehh_coarse_solve(ehh_handle_t h, int32_t sub, const void* r, void* e, int32_t nrhs, void* stream) {
+    CHK(check_handle(h));
+    Sub* S;
+    Level* L;
+    if (sub < 0 || sub >= (int)h->subs.size()) return fail(EHH_ERR_INVALID, "subdomain index out of range");
+    CHK(level_of(h, sub, (int)h->subs[sub].lev.size() - 1, &S, &L));
+    if (!r || !e || r == e || nrhs < 1) return fail(EHH_ERR_INVALID, "bad vectors or nrhs");
+    if (h->bits() == 32)
+        HIPCHK(launch_coarse_apply<float>(S->inv, L->g.N, (const float*)r, (float*)e, nrhs, as_stream(stream)));
+    else
+        HIPCHK(launch_coarse_apply<double>(S->inv, L->g.N, (const double*)r, (double*)e, nrhs, as_stream(stream)));
+    return EHH_OK;
+}
+
+const char* ehh_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

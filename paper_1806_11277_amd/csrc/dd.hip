@@ -1,0 +1,102 @@
+// Domain-decomposition transfers between the global FP64 vectors of the outer
+// Krylov method and the padded local vectors of the subdomain cycles (section
+// 2.3, section 4): restriction of the residual to a subdomain (zero in its
+// absorbing padding, cast to the cycle precision) and extension of the local
+// correction back to the global vector, either averaged over the subdomains
+// that own an unknown (one colour) or added unweighted (Algorithm 2).
+#include "internal.hpp"
+
+namespace ehh {
+
+static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+// Global index of the local unknown t (component k, local position), or -1 when
+// it lies outside the subdomain's extent [lo, hi).  A face belongs to the
+// extent when both adjacent cells do.  *w receives the owner count product.
+template <int D>
+EHH_DEV int64_t local_to_global(const Geo& gg, const Geo& gl, const SubMap& m, int64_t t, int& k, int* cnt) {
+    k = 0;
+    while (k < 3 && t >= gl.off[k + 1]) ++k;
+    if (k >= D) k = 3;
+    const int64_t li = t - gl.off[k];
+    int p[3];
+    if (k == 3) cell_pos<D>(gl, li, p);
+    else face_pos<D>(gl, k, li, p);
+    int c = 1;
+    for (int a = 0; a < D; ++a) {
+        const int gp = p[a] + m.origin[a];
+        if (a == k) {
+            if (!(gp > m.lo[a] && gp < m.hi[a])) return -1;
+            c *= m.cnt_face[a][gp];
+        } else {
+            if (!(gp >= m.lo[a] && gp < m.hi[a])) return -1;
+            c *= m.cnt_cell[a][gp];
+        }
+        p[a] = gp;
+    }
+    *cnt = c;
+    return k == 3 ? gg.off[3] + cell_idx<D>(gg, p) : gg.off[k] + face_idx<D>(gg, k, p);
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_dd_gather(Geo gg, Geo gl, SubMap m, const double* __restrict__ v,
+                                                   T* __restrict__ out, int nrhs) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= gl.N) return;
+    int k, cnt;
+    const int64_t gi = local_to_global<D>(gg, gl, m, t, k, &cnt);
+    for (int r = 0; r < nrhs; ++r) {
+        T* o = out + (int64_t)r * 2 * gl.N;
+        const double* vv = v + (int64_t)r * 2 * gg.N;
+        o[t] = gi >= 0 ? (T)vv[gi] : T(0);
+        o[gl.N + t] = gi >= 0 ? (T)vv[gg.N + gi] : T(0);
+    }
+}
+
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_dd_scatter(Geo gg, Geo gl, SubMap m, const T* __restrict__ e,
+                                                    double* __restrict__ z, int nrhs, int weighted) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= gl.N) return;
+    int k, cnt;
+    const int64_t gi = local_to_global<D>(gg, gl, m, t, k, &cnt);
+    if (gi < 0) return;
+    const double w = weighted ? 1.0 / cnt : 1.0;
+    for (int r = 0; r < nrhs; ++r) {
+        const T* ee = e + (int64_t)r * 2 * gl.N;
+        double* zz = z + (int64_t)r * 2 * gg.N;
+        zz[gi] += w * (double)ee[t];
+        zz[gg.N + gi] += w * (double)ee[gl.N + t];
+    }
+}
+
+template <typename T>
+hipError_t launch_dd_gather(const Geo& gg, const Geo& gl, const SubMap& m, const double* v, T* out, int nrhs,
+                            hipStream_t s) {
+    if (gg.dim == 2)
+        hipLaunchKernelGGL((k_dd_gather<2, T>), nblk(gl.N), 256, 0, s, gg, gl, m, v, out, nrhs);
+    else
+        hipLaunchKernelGGL((k_dd_gather<3, T>), nblk(gl.N), 256, 0, s, gg, gl, m, v, out, nrhs);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_dd_scatter(const Geo& gg, const Geo& gl, const SubMap& m, const T* e, double* z, int nrhs,
+                             int weighted, hipStream_t s) {
+    if (gg.dim == 2)
+        hipLaunchKernelGGL((k_dd_scatter<2, T>), nblk(gl.N), 256, 0, s, gg, gl, m, e, z, nrhs, weighted);
+    else
+        hipLaunchKernelGGL((k_dd_scatter<3, T>), nblk(gl.N), 256, 0, s, gg, gl, m, e, z, nrhs, weighted);
+    return hipGetLastError();
+}
+
+template hipError_t launch_dd_gather<float>(const Geo&, const Geo&, const SubMap&, const double*, float*, int,
+                                            hipStream_t);
+template hipError_t launch_dd_gather<double>(const Geo&, const Geo&, const SubMap&, const double*, double*, int,
+                                             hipStream_t);
+template hipError_t launch_dd_scatter<float>(const Geo&, const Geo&, const SubMap&, const float*, double*, int, int,
+                                             hipStream_t);
+template hipError_t launch_dd_scatter<double>(const Geo&, const Geo&, const SubMap&, const double*, double*, int,
+                                              int, hipStream_t);
+
+}  // namespace ehh

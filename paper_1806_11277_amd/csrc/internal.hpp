@@ -1,0 +1,105 @@
+// Host-side declarations shared by the kernel files and the C ABI implementation.
+#pragma once
+
+#include "common.hpp"
+
+#define EHH_KMAXV 17   // restart length + 1
+
+namespace ehh {
+
+// Operator of one multigrid level in precision T: matrix-free on level 0 of a
+// (sub)domain, Galerkin stencils on the coarser levels.
+template <typename T> struct LevelDesc {
+    Geo g;
+    bool fine;
+    FineCoef<T> f;
+    StCoef<T> s;
+};
+
+// ---- levels.hip
+template <typename T>
+hipError_t launch_apply(const LevelDesc<T>& L, const T* x, const T* b, T* y, int nrhs, hipStream_t s);
+template <typename T>
+hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, const T* b, const T* ein,
+                        T* eout, int nrhs, hipStream_t s);
+template <typename T>
+hipError_t launch_restrict(const Geo& gf, const Geo& gc, const T* rf, T* rc, int nrhs, hipStream_t s);
+template <typename T>
+hipError_t launch_prolong(const Geo& gf, const Geo& gc, const T* ec, T* ef, int nrhs, hipStream_t s);
+
+// ---- setup.hip
+// Sums of mu and rho and the number of non-physical cells (non-finite values,
+// rho <= 0, mu < 0, lambda + mu <= 0); out[0..2] on the device.
+hipError_t launch_media_check(const double* lam, const double* mu, const double* rho, const double* gam,
+                              int64_t ncell, double* partial, int nblocks, double* out, hipStream_t s);
+int media_check_blocks(int64_t ncell);
+
+struct FineCoefParams {
+    int dim;
+    int n_glob[3];
+    int n_loc[3];
+    int origin[3];       // global cell of local cell 0
+    int pad_lo[3], pad_hi[3];
+    int abl[3];
+    double abl_max;
+    double gam0;         // atten0 / omega
+    double inv_omega;    // 1 / omega (for the physical attenuation)
+    double mu_bar, rho_bar;
+};
+// mu, dinv, rho, gam planes (4 * ncell_loc doubles) of a (sub)domain level 0.
+hipError_t launch_fine_coef(const FineCoefParams& p, const double* lam, const double* mu, const double* rho,
+                            const double* gam_phys, double* out, hipStream_t s);
+// Level-0 shifted operator written in the stencil format of the coarse levels.
+hipError_t launch_materialise(const Geo& g, const FineCoef<double>& c, double* st, hipStream_t s);
+// Galerkin product P^T A P: stencil of grid gf -> stencil of grid gc.
+hipError_t launch_galerkin(const Geo& gf, const double* stf, const Geo& gc, double* stc, hipStream_t s);
+// Dense row-major complex (re, im interleaved) matrix of a stencil-format level.
+hipError_t launch_dense_assemble(const Geo& g, const double* st, double* dense, hipStream_t s);
+// In-place Gauss-Jordan inversion of `batch` dense n x n complex matrices with
+// partial pivoting; work: 2 * n * batch doubles, piv: n * batch ints.
+hipError_t launch_dense_invert(double* dense, int64_t n, int batch, double* work, int* piv, hipStream_t s);
+// e = inv r for a batch of right-hand sides (FP64 accumulation).
+template <typename T>
+hipError_t launch_coarse_apply(const double* inv, int64_t n, const T* r, T* e, int nrhs, hipStream_t s);
+hipError_t launch_cast_d2f(const double* in, float* out, int64_t n, hipStream_t s);
+hipError_t launch_cast_f2d(const float* in, double* out, int64_t n, hipStream_t s);
+
+// ---- dd.hip
+struct SubMap {
+    int dim;
+    int origin[3];
+    int lo[3], hi[3];
+    const int* cnt_cell[3];   // per axis: subdomains covering cell c (global)
+    const int* cnt_face[3];   // per axis: subdomains owning face position f (global)
+};
+template <typename T>
+hipError_t launch_dd_gather(const Geo& gg, const Geo& gl, const SubMap& m, const double* v, T* out, int nrhs,
+                            hipStream_t s);
+template <typename T>
+hipError_t launch_dd_scatter(const Geo& gg, const Geo& gl, const SubMap& m, const T* e, double* z, int nrhs,
+                             int weighted, hipStream_t s);
+
+// ---- krylov.hip (FP64, vectors of 2N reals per right-hand side)
+int krylov_blocks(int64_t n2);
+// h[r*ldh + i] = <V_i(r), w(r)> (Hermitian, conj on V) for i < nv; V_i(r) at
+// V + (i*nrhs + r) * 2N; partial: krylov_blocks * nrhs * nv * 2 doubles.
+hipError_t launch_dots(const double* V, int nv, const double* w, int64_t N, int nrhs, double* partial,
+                       double* h, int ldh, hipStream_t s);
+// w(r) -= sum_i h[r*ldh+i] V_i(r); optionally nrm2[r] = |w(r)|^2 (partial used).
+hipError_t launch_axpy_multi(const double* V, int nv, double* w, int64_t N, int nrhs, const double* h,
+                             int ldh, double* partial, double* nrm2, hipStream_t s);
+// nrm2[r] = |x(r)|^2
+hipError_t launch_norm2(const double* x, int64_t N, int nrhs, double* partial, double* nrm2, hipStream_t s);
+// out(r) = x(r) * scale[r] (scale real)
+hipError_t launch_scale(const double* x, double* out, int64_t N, int nrhs, const double* scale, int mode,
+                        hipStream_t s);
+// Givens update of column j of every right-hand side's Hessenberg matrix.
+hipError_t launch_givens(double* H, double* cs, double* g, const double* hcol, const double* hnext2, int j,
+                         int m, int nrhs, const int* active, double* est, const double* bnorm, hipStream_t s);
+// y = R^{-1} g (columns ncols[r]); x(r) += sum_i y_i Z_i(r)
+hipError_t launch_update_x(const double* H, const double* g, const double* Z, double* x, int64_t N, int nrhs,
+                           int m, const int* ncols, double* y, hipStream_t s);
+hipError_t launch_axpby(const double* x, const double* y, double* out, int64_t n, double a, double b,
+                        hipStream_t s);
+
+}  // namespace ehh

@@ -1,0 +1,303 @@
+// FP64 vector kernels of the outer flexible GMRES: block-wide Hermitian dot
+// products reduced deterministically in two passes (no floating-point atomics),
+// multi-vector updates, the per-right-hand-side Givens rotations of the
+// Hessenberg matrix and the final x += Z y.
+//
+// Complex vectors hold the real plane (N doubles) then the imaginary plane.
+#include <math.h>
+
+#include "internal.hpp"
+
+namespace ehh {
+
+static constexpr int KB = 256;       // threads per block
+static constexpr int MAXV = EHH_KMAXV;
+
+static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+int krylov_blocks(int64_t n) {
+    int64_t b = (n + 4 * KB - 1) / (4 * KB);
+    if (b > 512) b = 512;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+EHH_DEV double block_sum(double v, double* sm) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sm[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < KB / 64; ++w) s += sm[w];
+    return s;   // valid in thread 0
+}
+
+// partial[((r * nv + i) * 2 + c) * nb + blk]
+__global__ __launch_bounds__(KB) void k_dots_partial(const double* __restrict__ V, int nv, const double* __restrict__ w,
+                                                     int64_t N, int nrhs, double* __restrict__ partial) {
+    __shared__ double sm[KB / 64];
+    const int r = blockIdx.y;
+    const int nb = gridDim.x;
+    const double* wr = w + (int64_t)r * 2 * N;
+    double are[MAXV], aim[MAXV];
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) are[i] = aim[i] = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * KB + threadIdx.x; e < N; e += (int64_t)nb * KB) {
+        const double xr = wr[e], xi = wr[N + e];
+#pragma unroll
+        for (int i = 0; i < MAXV; ++i) {
+            if (i >= nv) break;
+            const double* v = V + ((int64_t)i * nrhs + r) * 2 * N;
+            const double vr = v[e], vi = v[N + e];
+            are[i] += vr * xr + vi * xi;
+            aim[i] += vr * xi - vi * xr;
+        }
+    }
+    for (int i = 0; i < nv; ++i) {
+        const double sr = block_sum(are[i], sm);
+        if (threadIdx.x == 0) partial[(((int64_t)r * nv + i) * 2 + 0) * nb + blockIdx.x] = sr;
+        const double si = block_sum(aim[i], sm);
+        if (threadIdx.x == 0) partial[(((int64_t)r * nv + i) * 2 + 1) * nb + blockIdx.x] = si;
+    }
+}
+
+__global__ void k_partial_final(const double* __restrict__ partial, int nv, int nb, int nrhs, double* __restrict__ out,
+                                int ldo) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nrhs * nv * 2) return;
+    const int c = t & 1, i = (t >> 1) % nv, r = (t >> 1) / nv;
+    const double* p = partial + (((int64_t)r * nv + i) * 2 + c) * nb;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += p[b];
+    out[2 * ((int64_t)r * ldo + i) + c] = s;
+}
+
+hipError_t launch_dots(const double* V, int nv, const double* w, int64_t N, int nrhs, double* partial, double* h,
+                       int ldh, hipStream_t s) {
+    const int nb = krylov_blocks(N);
+    hipLaunchKernelGGL(k_dots_partial, dim3(nb, nrhs), KB, 0, s, V, nv, w, N, nrhs, partial);
+    hipLaunchKernelGGL(k_partial_final, nblk(nrhs * nv * 2, 64), 64, 0, s, partial, nv, nb, nrhs, h, ldh);
+    return hipGetLastError();
+}
+
+// w -= sum_i h_i V_i, optionally with the partial sums of |w|^2.
+__global__ __launch_bounds__(KB) void k_axpy_multi(const double* __restrict__ V, int nv, double* __restrict__ w,
+                                                   int64_t N, int nrhs, const double* __restrict__ h, int ldh,
+                                                   double* __restrict__ partial) {
+    __shared__ double sm[KB / 64];
+    const int r = blockIdx.y;
+    const int nb = gridDim.x;
+    double* wr = w + (int64_t)r * 2 * N;
+    double hr[MAXV], hi[MAXV];
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+        hr[i] = i < nv ? h[2 * ((int64_t)r * ldh + i)] : 0.0;
+        hi[i] = i < nv ? h[2 * ((int64_t)r * ldh + i) + 1] : 0.0;
+    }
+    double acc = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * KB + threadIdx.x; e < N; e += (int64_t)nb * KB) {
+        double xr = wr[e], xi = wr[N + e];
+#pragma unroll
+        for (int i = 0; i < MAXV; ++i) {
+            if (i >= nv) break;
+            const double* v = V + ((int64_t)i * nrhs + r) * 2 * N;
+            const double vr = v[e], vi = v[N + e];
+            xr -= hr[i] * vr - hi[i] * vi;
+            xi -= hr[i] * vi + hi[i] * vr;
+        }
+        wr[e] = xr;
+        wr[N + e] = xi;
+        acc += xr * xr + xi * xi;
+    }
+    if (partial) {
+        const double s = block_sum(acc, sm);
+        if (threadIdx.x == 0) partial[(int64_t)r * nb + blockIdx.x] = s;
+    }
+}
+
+__global__ void k_norm_final(const double* __restrict__ partial, int nb, int nrhs, double* __restrict__ out) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += partial[(int64_t)r * nb + b];
+    out[r] = s;
+}
+
+hipError_t launch_axpy_multi(const double* V, int nv, double* w, int64_t N, int nrhs, const double* h, int ldh,
+                             double* partial, double* nrm2, hipStream_t s) {
+    const int nb = krylov_blocks(N);
+    hipLaunchKernelGGL(k_axpy_multi, dim3(nb, nrhs), KB, 0, s, V, nv, w, N, nrhs, h, ldh, nrm2 ? partial : nullptr);
+    if (nrm2) hipLaunchKernelGGL(k_norm_final, nblk(nrhs, 64), 64, 0, s, partial, nb, nrhs, nrm2);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(KB) void k_norm_partial(const double* __restrict__ x, int64_t N, double* __restrict__ partial) {
+    __shared__ double sm[KB / 64];
+    const int r = blockIdx.y;
+    const int nb = gridDim.x;
+    const double* xr = x + (int64_t)r * 2 * N;
+    double acc = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * KB + threadIdx.x; e < 2 * N; e += (int64_t)nb * KB) acc += xr[e] * xr[e];
+    const double s = block_sum(acc, sm);
+    if (threadIdx.x == 0) partial[(int64_t)r * nb + blockIdx.x] = s;
+}
+
+hipError_t launch_norm2(const double* x, int64_t N, int nrhs, double* partial, double* nrm2, hipStream_t s) {
+    const int nb = krylov_blocks(N);
+    hipLaunchKernelGGL(k_norm_partial, dim3(nb, nrhs), KB, 0, s, x, N, partial);
+    hipLaunchKernelGGL(k_norm_final, nblk(nrhs, 64), 64, 0, s, partial, nb, nrhs, nrm2);
+    return hipGetLastError();
+}
+
+// mode 0: out = x * sc[r]; mode 1: out = x / sqrt(sc[r]) (0 if sc[r] == 0)
+__global__ void k_scale(const double* __restrict__ x, double* __restrict__ out, int64_t N, int nrhs,
+                        const double* __restrict__ sc, int mode) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * N * nrhs) return;
+    const int r = (int)(t / (2 * N));
+    double f = sc[r];
+    if (mode == 1) f = f > 0.0 ? 1.0 / sqrt(f) : 0.0;
+    out[t] = x[t] * f;
+}
+
+hipError_t launch_scale(const double* x, double* out, int64_t N, int nrhs, const double* scale, int mode,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_scale, nblk(2 * N * nrhs), 256, 0, s, x, out, N, nrhs, scale, mode);
+    return hipGetLastError();
+}
+
+__global__ void k_axpby(const double* __restrict__ x, const double* __restrict__ y, double* __restrict__ out, int64_t n,
+                        double a, double b) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) out[t] = a * x[t] + b * y[t];
+}
+
+hipError_t launch_axpby(const double* x, const double* y, double* out, int64_t n, double a, double b, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpby, nblk(n), 256, 0, s, x, y, out, n, a, b);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ Givens rotations
+// H[r][j][i] (column j, i <= m) complex; cs[r][i] = (c, s_re, s_im); g[r][i] complex.
+// hcol[r][i] for i <= j: <v_i, w> (complex, from CGS), hnext2[r] = |w|^2.
+__global__ void k_givens(double* __restrict__ H, double* __restrict__ cs, double* __restrict__ g,
+                         const double* __restrict__ hcol, const double* __restrict__ hnext2, int j, int m, int nrhs,
+                         const int* __restrict__ active, double* __restrict__ est, const double* __restrict__ bnorm) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    if (!active[r]) return;
+    double* col = H + 2 * (((int64_t)r * m + j) * (m + 1));
+    double* c = cs + 3 * (int64_t)r * m;
+    double* gg = g + 2 * (int64_t)r * (m + 1);
+    for (int i = 0; i <= j; ++i) {
+        col[2 * i] = hcol[2 * ((int64_t)r * (m + 1) + i)];
+        col[2 * i + 1] = hcol[2 * ((int64_t)r * (m + 1) + i) + 1];
+    }
+    col[2 * (j + 1)] = sqrt(hnext2[r]);
+    col[2 * (j + 1) + 1] = 0.0;
+    for (int i = 0; i < j; ++i) {
+        const double cc = c[3 * i], sr = c[3 * i + 1], si = c[3 * i + 2];
+        const double ar = col[2 * i], ai = col[2 * i + 1];
+        const double br = col[2 * (i + 1)], bi = col[2 * (i + 1) + 1];
+        // a' = c a + s b ; b' = -conj(s) a + c b
+        col[2 * i] = cc * ar + (sr * br - si * bi);
+        col[2 * i + 1] = cc * ai + (sr * bi + si * br);
+        col[2 * (i + 1)] = -(sr * ar + si * ai) + cc * br;
+        col[2 * (i + 1) + 1] = -(sr * ai - si * ar) + cc * bi;
+    }
+    const double ar = col[2 * j], ai = col[2 * j + 1];
+    const double br = col[2 * (j + 1)], bi = col[2 * (j + 1) + 1];
+    const double na = sqrt(ar * ar + ai * ai), nb = sqrt(br * br + bi * bi);
+    double cc, sr, si;
+    if (nb == 0.0) {
+        cc = 1.0;
+        sr = si = 0.0;
+    } else if (na == 0.0) {
+        cc = 0.0;
+        sr = br / nb;
+        si = -bi / nb;
+    } else {
+        const double t = sqrt(na * na + nb * nb);
+        cc = na / t;
+        // s = (a/|a|) conj(b) / t
+        const double ur = ar / na, ui = ai / na;
+        sr = (ur * br + ui * bi) / t;
+        si = (ui * br - ur * bi) / t;
+    }
+    c[3 * j] = cc;
+    c[3 * j + 1] = sr;
+    c[3 * j + 2] = si;
+    // new diagonal: c a + s b
+    const double dr = cc * ar + (sr * br - si * bi), di = cc * ai + (sr * bi + si * br);
+    col[2 * j] = dr;
+    col[2 * j + 1] = di;
+    col[2 * (j + 1)] = 0.0;
+    col[2 * (j + 1) + 1] = 0.0;
+    const double gr = gg[2 * j], gi = gg[2 * j + 1];
+    gg[2 * j] = cc * gr;
+    gg[2 * j + 1] = cc * gi;
+    gg[2 * (j + 1)] = -(sr * gr + si * gi);
+    gg[2 * (j + 1) + 1] = -(sr * gi - si * gr);
+    const double er = gg[2 * (j + 1)], ei = gg[2 * (j + 1) + 1];
+    est[r] = sqrt(er * er + ei * ei) / bnorm[r];
+}
+
+hipError_t launch_givens(double* H, double* cs, double* g, const double* hcol, const double* hnext2, int j, int m,
+                         int nrhs, const int* active, double* est, const double* bnorm, hipStream_t s) {
+    hipLaunchKernelGGL(k_givens, nblk(nrhs, 64), 64, 0, s, H, cs, g, hcol, hnext2, j, m, nrhs, active, est, bnorm);
+    return hipGetLastError();
+}
+
+// y = R^{-1} g for the first ncols[r] columns (upper triangular R in H).
+__global__ void k_backsub(const double* __restrict__ H, const double* __restrict__ g, int m, int nrhs,
+                          const int* __restrict__ ncols, double* __restrict__ y) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    const int nc = ncols[r];
+    double* yr = y + 2 * (int64_t)r * m;
+    for (int i = 0; i < m; ++i) yr[2 * i] = yr[2 * i + 1] = 0.0;
+    for (int i = nc - 1; i >= 0; --i) {
+        double sr = g[2 * ((int64_t)r * (m + 1) + i)], si = g[2 * ((int64_t)r * (m + 1) + i) + 1];
+        for (int jj = i + 1; jj < nc; ++jj) {
+            const double* hc = H + 2 * (((int64_t)r * m + jj) * (m + 1) + i);
+            sr -= hc[0] * yr[2 * jj] - hc[1] * yr[2 * jj + 1];
+            si -= hc[0] * yr[2 * jj + 1] + hc[1] * yr[2 * jj];
+        }
+        const double* d = H + 2 * (((int64_t)r * m + i) * (m + 1) + i);
+        const double dd = d[0] * d[0] + d[1] * d[1];
+        yr[2 * i] = (sr * d[0] + si * d[1]) / dd;
+        yr[2 * i + 1] = (si * d[0] - sr * d[1]) / dd;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_update_x(const double* __restrict__ Z, double* __restrict__ x, int64_t N,
+                                                  int nrhs, int m, const int* __restrict__ ncols,
+                                                  const double* __restrict__ y) {
+    const int r = blockIdx.y;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= N) return;
+    const int nc = ncols[r];
+    if (nc == 0) return;
+    double* xr = x + (int64_t)r * 2 * N;
+    double ar = xr[e], ai = xr[N + e];
+    for (int i = 0; i < nc; ++i) {
+        const double* z = Z + ((int64_t)i * nrhs + r) * 2 * N;
+        const double yr = y[2 * ((int64_t)r * m + i)], yi = y[2 * ((int64_t)r * m + i) + 1];
+        const double zr = z[e], zi = z[N + e];
+        ar += yr * zr - yi * zi;
+        ai += yr * zi + yi * zr;
+    }
+    xr[e] = ar;
+    xr[N + e] = ai;
+}
+
+hipError_t launch_update_x(const double* H, const double* g, const double* Z, double* x, int64_t N, int nrhs, int m,
+                           const int* ncols, double* y, hipStream_t s) {
+    hipLaunchKernelGGL(k_backsub, nblk(nrhs, 64), 64, 0, s, H, g, m, nrhs, ncols, y);
+    hipLaunchKernelGGL(k_update_x, dim3(nblk(N), nrhs), 256, 0, s, Z, x, N, nrhs, m, ncols, y);
+    return hipGetLastError();
+}
+
+}  // namespace ehh

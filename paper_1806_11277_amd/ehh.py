@@ -1,0 +1,252 @@
+"""ctypes binding of libehh.so (include/ehh.h), with the same names.
+
+Argument marshalling only: torch tensors provide device memory and the current
+HIP stream; every arithmetic step runs in the library's kernels.  The library
+must be built (``python -m paper_1806_11277_amd.build``); nothing falls back to
+another implementation when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libehh.so")
+
+EHH_OK, EHH_NOT_CONVERGED = 0, 1
+EHH_ERR_INVALID, EHH_ERR_HIP, EHH_ERR_OOM, EHH_ERR_BREAKDOWN, EHH_ERR_UNSUPPORTED = -1, -2, -3, -4, -5
+EHH_MAX_LEVELS = 8
+EHH_MAX_RESTART = 16
+
+STATUS_NAMES = {0: "EHH_OK", 1: "EHH_NOT_CONVERGED", -1: "EHH_ERR_INVALID", -2: "EHH_ERR_HIP",
+                -3: "EHH_ERR_OOM", -4: "EHH_ERR_BREAKDOWN", -5: "EHH_ERR_UNSUPPORTED"}
+
+
+class ehh_problem_t(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32 * 3), ("h", ctypes.c_double),
+                ("omega", ctypes.c_double), ("shift", ctypes.c_double),
+                ("abl_cells", ctypes.c_int32 * 3), ("abl_max", ctypes.c_double),
+                ("atten0", ctypes.c_double)]
+
+
+class ehh_options_t(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("cycle", ctypes.c_int32), ("nu1", ctypes.c_int32),
+                ("nu2", ctypes.c_int32), ("vanka", ctypes.c_int32), ("precond_bits", ctypes.c_int32),
+                ("restart", ctypes.c_int32), ("dd_parts", ctypes.c_int32 * 3),
+                ("dd_overlap", ctypes.c_int32), ("dd_pad", ctypes.c_int32),
+                ("dd_colors", ctypes.c_int32), ("damping", ctypes.c_double * EHH_MAX_LEVELS)]
+
+
+class ehh_stats_t(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("rel_res_est", ctypes.c_double),
+                ("rel_res_true", ctypes.c_double), ("conv_factor", ctypes.c_double)]
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int32
+_SIGS = {
+    "ehh_default_options": (None, [ctypes.POINTER(ehh_options_t)]),
+    "ehh_setup_operator": (_I, [ctypes.POINTER(ehh_problem_t), _P, _P, _P, _P,
+                                ctypes.POINTER(ehh_options_t), _P, ctypes.POINTER(_P)]),
+    "ehh_destroy": (None, [_P]),
+    "ehh_vector_layout": (_I, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    "ehh_scaling": (_I, [_P, ctypes.POINTER(ctypes.c_double)]),
+    "ehh_apply": (_I, [_P, _I, _P, _P, _I, _P]),
+    "ehh_vcycle": (_I, [_P, _I, _P, _P, _I, _P]),
+    "ehh_precondition": (_I, [_P, _P, _P, _I, _P]),
+    "ehh_solve": (_I, [_P, _P, _P, _I, ctypes.c_double, _I, ctypes.POINTER(ehh_stats_t), _P]),
+    "ehh_num_subdomains": (_I, [_P]),
+    "ehh_subdomain_info": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I),
+                                ctypes.POINTER(_I)]),
+    "ehh_level_info": (_I, [_P, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_int64),
+                            ctypes.POINTER(ctypes.c_int64)]),
+    "ehh_level_apply": (_I, [_P, _I, _I, _P, _P, _I, _P]),
+    "ehh_level_relax": (_I, [_P, _I, _I, _I, _P, _P, _P, _I, _P]),
+    "ehh_level_restrict": (_I, [_P, _I, _I, _P, _P, _P, _I, _P]),
+    "ehh_level_prolong": (_I, [_P, _I, _I, _P, _P, _I, _P]),
+    "ehh_coarse_solve": (_I, [_P, _I, _P, _P, _I, _P]),
+    "ehh_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libehh.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_1806_11277_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class EHHError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(status, allow=(EHH_OK,)):
+    if status not in allow:
+        raise EHHError(status, lib().ehh_last_error().decode(errors="replace"))
+    return status
+
+
+def default_options() -> ehh_options_t:
+    o = ehh_options_t()
+    lib().ehh_default_options(ctypes.byref(o))
+    return o
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("vectors must be contiguous device tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """Owns one ehh handle.  Media: float64 device tensors shaped like the cell
+    grid (x fastest).  Vectors: (nrhs, 2N) tensors on the device, float64 for
+    the global vectors, the cycle precision for level vectors."""
+
+    def __init__(self, dim: int, n: Sequence[int], h: float, omega: float, shift: float,
+                 abl_cells: Sequence[int], lam, mu, rho, gamma=None, abl_max: float = 1.0,
+                 atten0: float = 0.0, levels: int = 3, cycle: int = 1, nu1: int = 1, nu2: int = 1,
+                 vanka: int = 1, precond_bits: int = 64, restart: int = 5,
+                 dd_parts: Sequence[int] = (1, 1, 1), dd_overlap: int = 0, dd_pad: int = 0,
+                 dd_colors: int = 1, damping: Optional[Sequence[float]] = None, stream=None):
+        import torch
+        p = ehh_problem_t()
+        p.dim = dim
+        nn = list(n) + [1] * (3 - len(n))
+        ab = list(abl_cells) + [0] * (3 - len(abl_cells))
+        for a in range(3):
+            p.n[a] = int(nn[a])
+            p.abl_cells[a] = int(ab[a])
+        p.h, p.omega, p.shift, p.abl_max, p.atten0 = float(h), float(omega), float(shift), float(abl_max), float(atten0)
+        o = default_options()
+        o.levels, o.cycle, o.nu1, o.nu2, o.vanka = levels, cycle, nu1, nu2, vanka
+        o.precond_bits, o.restart = precond_bits, restart
+        dp = list(dd_parts) + [1] * (3 - len(dd_parts))
+        for a in range(3):
+            o.dd_parts[a] = int(dp[a])
+        o.dd_overlap, o.dd_pad, o.dd_colors = dd_overlap, dd_pad, dd_colors
+        if damping is not None:
+            for l, w in enumerate(damping[:EHH_MAX_LEVELS]):
+                o.damping[l] = float(w)
+        self.problem, self.options = p, o
+        self.dim = dim
+        self.precond_bits = precond_bits
+        self._media = [t.contiguous() for t in (lam, mu, rho)] + ([gamma.contiguous()] if gamma is not None else [])
+        for t in self._media:
+            if t.dtype != torch.float64 or not t.is_cuda:
+                raise ValueError("media must be float64 device tensors")
+        h_ = ctypes.c_void_p()
+        _check(lib().ehh_setup_operator(ctypes.byref(p), _ptr(self._media[0]), _ptr(self._media[1]),
+                                        _ptr(self._media[2]), _ptr(gamma) if gamma is not None else None,
+                                        ctypes.byref(o), _stream(stream), ctypes.byref(h_)))
+        self.handle = h_
+        counts = (ctypes.c_int64 * 4)()
+        stride = ctypes.c_int64()
+        _check(lib().ehh_vector_layout(self.handle, counts, ctypes.byref(stride)))
+        self.counts = list(counts)
+        self.N = sum(self.counts)
+        self.stride = stride.value
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().ehh_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------- queries
+    def scaling(self):
+        out = (ctypes.c_double * 3)()
+        _check(lib().ehh_scaling(self.handle, out))
+        return dict(mu_bar=out[0], rho_bar=out[1], omega_nd=out[2])
+
+    def num_subdomains(self):
+        return lib().ehh_num_subdomains(self.handle)
+
+    def subdomain_info(self, sub):
+        n, o, lo, hi = ((_I * 3)() for _ in range(4))
+        _check(lib().ehh_subdomain_info(self.handle, sub, n, o, lo, hi))
+        return dict(n=list(n), origin=list(o), lo=list(lo), hi=list(hi))
+
+    def level_info(self, sub, level):
+        n = (_I * 3)()
+        counts = (ctypes.c_int64 * 4)()
+        stride = ctypes.c_int64()
+        _check(lib().ehh_level_info(self.handle, sub, level, n, counts, ctypes.byref(stride)))
+        return dict(n=list(n), counts=list(counts), N=sum(counts), stride=stride.value)
+
+    # ------------------------------------------------------------- calls
+    def apply(self, x, y, shifted=False, stream=None):
+        _check(lib().ehh_apply(self.handle, int(shifted), _ptr(x), _ptr(y), x.shape[0], _stream(stream)))
+
+    def vcycle(self, r, e, sub=0, stream=None):
+        _check(lib().ehh_vcycle(self.handle, sub, _ptr(r), _ptr(e), r.shape[0], _stream(stream)))
+
+    def precondition(self, v, z, stream=None):
+        _check(lib().ehh_precondition(self.handle, _ptr(v), _ptr(z), v.shape[0], _stream(stream)))
+
+    def solve(self, b, x, tol=1e-6, maxit=500, stream=None, raise_on_fail=False):
+        nrhs = b.shape[0]
+        stats = (ehh_stats_t * nrhs)()
+        st = lib().ehh_solve(self.handle, _ptr(b), _ptr(x), nrhs, float(tol), int(maxit), stats,
+                             _stream(stream))
+        _check(st, allow=(EHH_OK,) if raise_on_fail else (EHH_OK, EHH_NOT_CONVERGED))
+        return st, [dict(status=s.status, iters=s.iters, rel_res_est=s.rel_res_est,
+                         rel_res_true=s.rel_res_true, conv_factor=s.conv_factor) for s in stats]
+
+    def level_apply(self, sub, level, x, y, stream=None):
+        _check(lib().ehh_level_apply(self.handle, sub, level, _ptr(x), _ptr(y), x.shape[0], _stream(stream)))
+
+    def level_relax(self, sub, level, colour, b, e_in, e_out, stream=None):
+        _check(lib().ehh_level_relax(self.handle, sub, level, colour, _ptr(b), _ptr(e_in), _ptr(e_out),
+                                     b.shape[0], _stream(stream)))
+
+    def level_restrict(self, sub, level, b, e, rc, stream=None):
+        _check(lib().ehh_level_restrict(self.handle, sub, level, _ptr(b), _ptr(e), _ptr(rc), b.shape[0],
+                                        _stream(stream)))
+
+    def level_prolong(self, sub, level, ec, e, stream=None):
+        _check(lib().ehh_level_prolong(self.handle, sub, level, _ptr(ec), _ptr(e), ec.shape[0],
+                                       _stream(stream)))
+
+    def coarse_solve(self, sub, r, e, stream=None):
+        _check(lib().ehh_coarse_solve(self.handle, sub, _ptr(r), _ptr(e), r.shape[0], _stream(stream)))
+
+
+def solver_for_workload(w, device="cuda", **overrides):
+    """Solver for a workloads.Workload (media uploaded as float64 device tensors)."""
+    import torch
+    m = w.media()
+    kw = dict(levels=w.levels, cycle=w.cycle, nu1=w.nu1, nu2=w.nu2, vanka=w.vanka,
+              precond_bits=w.precond_bits, restart=w.restart, dd_parts=w.dd_parts,
+              dd_overlap=w.dd_overlap, dd_pad=w.dd_pad, dd_colors=w.dd_colors, damping=w.damping,
+              abl_max=w.abl_max, atten0=w.atten0)
+    kw.update(overrides)
+    t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=device).contiguous()
+    return Solver(w.dim, w.n, w.h, w.omega, kw.pop("shift", w.shift), w.abl_cells,
+                  t(m["lam"]), t(m["mu"]), t(m["rho"]), **kw)

@@ -1,0 +1,139 @@
+"""End-to-end parity of precondition / solve (single and batched right-hand sides,
+FP64 and complex64 cycles, domain decomposition) with the oracle, plus the
+error paths of the C ABI."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from _helpers import (say, workload, small_hetero, oracle_problem, oracle_hierarchy, oracle_dd,
+                      rand_cvec, to_dev, from_dev, rel_err, rhs_matrix)
+from oracle import krylov
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(w, **over):
+    import torch
+    from paper_1806_11277_amd import ehh
+    torch.cuda.synchronize()
+    return ehh.solver_for_workload(w, **over)
+
+
+@pytest.mark.parametrize("name,bits", [("c1_homog64", 64), ("c1_homog64", 32),
+                                       ("c2s_hetero128_fp64", 64)])
+def test_solve_matches_direct_solution(name, bits):
+    """At tol 1e-10 the FGMRES solution equals the sparse direct solution to 1e-6
+    and the iteration count equals the oracle's FGMRES count within 2."""
+    import torch
+    w = workload(name, precond_bits=bits)
+    say(f"[solve {name} bits={bits}]")
+    pb = oracle_problem(w)
+    A = pb.matrix()
+    B = rhs_matrix(w)
+    xd = spla.splu(A.tocsc()).solve(B[0])
+    S = _solver(w)
+    x = torch.zeros_like(to_dev(B))
+    st, stats = S.solve(to_dev(B), x, tol=1e-10, maxit=600)
+    torch.cuda.synchronize()
+    got = from_dev(x)[0]
+    assert st == 0, stats
+    assert stats[0]["rel_res_true"] <= 1e-10
+    assert np.linalg.norm(got - xd) <= 1e-6 * np.linalg.norm(xd)
+    H = oracle_hierarchy(w, pb)
+    _, ost = krylov.fgmres(lambda v: A @ v, H.cycle, B[0], tol=1e-10, restart=w.restart, maxit=600)
+    say(f"  gpu iters {stats[0]['iters']} oracle iters {ost['iters']}")
+    assert abs(stats[0]["iters"] - ost["iters"]) <= 2
+    S.close()
+
+
+def test_batched_fp32_solve_per_source():
+    """c3 layout at parity size: 8 sources, complex64 cycle, FP64 Krylov; each
+    source reaches its tolerance and matches the direct solution."""
+    import torch
+    w = workload("c3s_hetero128_batch8_fp32")
+    say("[batched fp32 solve]")
+    pb = oracle_problem(w)
+    lu = spla.splu(pb.matrix().tocsc())
+    B = rhs_matrix(w)
+    S = _solver(w)
+    x = torch.zeros_like(to_dev(B))
+    st, stats = S.solve(to_dev(B), x, tol=1e-10, maxit=800)
+    torch.cuda.synchronize()
+    assert st == 0, stats
+    got = from_dev(x)
+    for r in range(B.shape[0]):
+        xd = lu.solve(B[r])
+        assert stats[r]["rel_res_true"] <= 1e-10
+        assert np.linalg.norm(got[r] - xd) <= 1e-6 * np.linalg.norm(xd)
+    S.close()
+
+
+@pytest.mark.parametrize("bits,colors", [(64, 1), (32, 1), (64, 0)])
+def test_dd_precondition_matches_oracle(bits, colors):
+    import torch
+    w = workload("c4s_layered32_dd8_batch4_fp32", precond_bits=bits, dd_colors=colors)
+    say(f"[dd precondition bits={bits} colors={colors}]")
+    pb = oracle_problem(w)
+    P = oracle_dd(w, pb)
+    S = _solver(w)
+    assert S.num_subdomains() == len(P.subs)
+    for i, sub in enumerate(P.subs):
+        info = S.subdomain_info(i)
+        assert tuple(info["n"][:3]) == tuple(sub.nloc)
+        assert tuple(info["lo"][:3]) == tuple(sub.lo) and tuple(info["hi"][:3]) == tuple(sub.hi)
+    v = rand_cvec(pb.size, 2, 60)
+    z = torch.zeros_like(to_dev(v))
+    S.precondition(to_dev(v), z)
+    torch.cuda.synchronize()
+    got = from_dev(z)
+    tol = 1e-11 if bits == 64 else 2e-5
+    for r in range(2):
+        ref = P.apply(v[r])
+        assert np.linalg.norm(got[r] - ref) <= tol * np.linalg.norm(ref)
+    S.close()
+
+
+def test_dd_solve_3d():
+    import torch
+    w = workload("c4s_layered32_dd8_batch4_fp32")
+    say("[dd solve 3d]")
+    pb = oracle_problem(w)
+    A = pb.matrix()
+    B = rhs_matrix(w)
+    S = _solver(w)
+    x = torch.zeros_like(to_dev(B))
+    st, stats = S.solve(to_dev(B), x, tol=1e-8, maxit=600)
+    torch.cuda.synchronize()
+    assert st == 0, stats
+    got = from_dev(x)
+    for r in range(B.shape[0]):
+        res = np.linalg.norm(B[r] - A @ got[r]) / np.linalg.norm(B[r])
+        assert res <= 1.01e-8
+    S.close()
+
+
+def test_invalid_arguments_are_rejected():
+    import torch
+    from paper_1806_11277_amd import ehh
+    w = workload("c1_homog64")
+    say("[invalid arguments]")
+    with pytest.raises(ehh.EHHError) as ei:
+        ehh.solver_for_workload(w, levels=9)
+    assert ei.value.status == ehh.EHH_ERR_INVALID
+    with pytest.raises(ehh.EHHError) as ei:
+        ehh.solver_for_workload(w, levels=7)          # 64 not divisible into 7 levels
+    assert ei.value.status == ehh.EHH_ERR_INVALID
+    m = w.media()
+    bad = np.array(m["rho"], copy=True)
+    bad[3, 4] = np.nan
+    t = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda")
+    with pytest.raises(ehh.EHHError) as ei:
+        ehh.Solver(2, w.n, w.h, w.omega, w.shift, w.abl_cells, t(m["lam"]), t(m["mu"]), t(bad))
+    assert ei.value.status == ehh.EHH_ERR_BREAKDOWN
+    S = _solver(w)
+    B = rhs_matrix(w)
+    x = torch.zeros_like(to_dev(B))
+    st, stats = S.solve(to_dev(B), x, tol=1e-10, maxit=3)
+    assert st == ehh.EHH_NOT_CONVERGED and stats[0]["iters"] == 3
+    assert stats[0]["rel_res_true"] > 1e-10
+    S.close()

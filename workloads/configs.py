@@ -176,7 +176,7 @@ _add(Workload(
     description="c4 generator at 32^3 with 2x2x2 subdomains and 4 sources (parity size)",
     dim=3, n=(32, 32, 32), h=10.0, media_fn=lambda: M.layered_3d_media((32, 32, 32)),
     ppw=8.0, abl_cells=(6, 6, 6), shift=0.4, levels=3, damping=(0.5, 0.5),
-    precond_bits=32, dd_parts=(2, 2, 2), dd_overlap=4, dd_pad=4, dd_colors=1,
+    precond_bits=32, dd_parts=(2, 2, 2), dd_overlap=4, dd_pad=2, dd_colors=1,
     sources_fn=_src_lattice(2, 16, 8, 5, seed=7)))
 
 
