@@ -1,0 +1,221 @@
+"""Benchmark of the elastic Helmholtz hot path on one MI355X.
+
+One step = one pass of the whole path on one batch of synthetic input that is
+already resident in HBM: operator setup (coefficients, Galerkin hierarchy,
+coarsest inverse) + the preconditioned FGMRES solve of every right-hand side to
+relative residual 1e-6 + release.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0   # MI355X HBM3E
+
+
+def rhs_tensor(S, w):
+    import torch
+    nrhs = len(w.sources())
+    B = np.zeros((nrhs, 2 * S.N))
+    # unknown index of a face/cell in the library layout (x fastest per component)
+    n = list(w.n) + [1] * (3 - len(w.n))
+    offs = np.concatenate([[0], np.cumsum(S.counts)])
+    for r, (comp, pos, amp) in enumerate(w.sources()):
+        dims = [n[a] - (1 if a == comp else 0) for a in range(3)]
+        c = [pos[a] - (1 if a == comp else 0) for a in range(len(pos))] + [0] * (3 - len(pos))
+        idx = offs[comp] + c[0] + dims[0] * (c[1] + dims[1] * c[2])
+        B[r, idx] += amp.real
+        B[r, S.N + idx] += amp.imag
+    return torch.as_tensor(B, device="cuda")
+
+
+def relax_bytes_per_launch(S, level_info, bits, nrhs, fine=True):
+    """Algorithmic HBM bytes of one half-sweep launch on a level: b, e_in and e_out
+    (every unknown, complex) per right-hand side plus the level coefficients once."""
+    w = 8 if bits == 32 else 16
+    vec = 3 * level_info["N"] * w * nrhs
+    ncell = int(np.prod(level_info["n"]))
+    coef = (4 * ncell * (4 if bits == 32 else 8)) if fine else None
+    return vec + coef
+
+
+def run_gpu(w, steps, warmup, tol):
+    import torch
+    from paper_1806_11277_amd import ehh
+    m = w.media()
+    dev = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda").contiguous()
+    lam, mu, rho = dev(m["lam"]), dev(m["mu"]), dev(m["rho"])
+    opts = dict(levels=w.levels, cycle=w.cycle, nu1=w.nu1, nu2=w.nu2, vanka=w.vanka,
+                precond_bits=w.precond_bits, restart=w.restart, dd_parts=w.dd_parts,
+                dd_overlap=w.dd_overlap, dd_pad=w.dd_pad, dd_colors=w.dd_colors, damping=w.damping,
+                abl_max=w.abl_max, atten0=w.atten0)
+
+    def make():
+        return ehh.Solver(w.dim, w.n, w.h, w.omega, w.shift, w.abl_cells, lam, mu, rho, **opts)
+
+    S0 = make()
+    B = rhs_tensor(S0, w)
+    X = torch.zeros_like(B)
+    S0.close()
+    torch.cuda.synchronize()
+    results = []
+
+    def step():
+        t0 = time.perf_counter()
+        S = make()
+        t1 = time.perf_counter()
+        st, stats = S.solve(B, X, tol=tol, maxit=w.maxit)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        S.close()
+        results.append((t1 - t0, t2 - t1, st, stats))
+        print(f"[bench] step: setup {1e3 * (t1 - t0):.1f} ms, solve {1e3 * (t2 - t1):.1f} ms, "
+              f"iters {[s_['iters'] for s_ in stats][:4]}", file=sys.stderr, flush=True)
+
+    for _ in range(warmup):
+        step()
+    results.clear()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    return total, results, B, X
+
+
+def kernel_roofline(w, reps=50):
+    """Average duration of the finest-level half-sweep (HIP events on the stream
+    the library launches on) and its algorithmic bytes."""
+    import torch
+    from paper_1806_11277_amd import ehh
+    S = ehh.solver_for_workload(w)
+    nrhs = len(w.sources())
+    info = S.level_info(0, 0)
+    dt = torch.float32 if w.precond_bits == 32 else torch.float64
+    b = torch.randn((nrhs, 2 * info["N"]), dtype=dt, device="cuda")
+    e_in = torch.randn_like(b)
+    e_out = torch.zeros_like(b)
+    for _ in range(5):
+        S.level_relax(0, 0, 0, b, e_in, e_out)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(reps):
+        S.level_relax(0, 0, 0, b, e_in, e_out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    avg_s = ev0.elapsed_time(ev1) / reps / 1e3
+    nbytes = relax_bytes_per_launch(S, info, w.precond_bits, nrhs)
+    S.close()
+    return avg_s, nbytes
+
+
+def cpu_baseline(w, gpu_iters, budget_s=20.0):
+    """The oracle as it stands (numpy/scipy, FP64) on this host: hierarchy setup
+    plus as many FGMRES iterations as fit in the budget, scaled to a full solve
+    with the GPU's iteration count."""
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        limiter = None
+    from oracle import discretisation as disc, multigrid as mg
+    m = w.media()
+    t0 = time.perf_counter()
+    pb = disc.Problem(w.n, w.h, w.omega, m["lam"], m["mu"], m["rho"], w.abl_cells, w.abl_max,
+                      w.atten0, shift=w.shift)
+    A = pb.matrix()
+    H = mg.build_hierarchy(pb, w.levels, list(w.damping), economic=(w.vanka == 0), cycle=w.cycle,
+                           nu1=w.nu1, nu2=w.nu2)
+    t_setup = time.perf_counter() - t0
+    b = disc.point_source_vector(w.n, w.sources()[:1])
+    v = b / np.linalg.norm(b)
+    k = 0
+    t1 = time.perf_counter()
+    while time.perf_counter() - t1 < budget_s:
+        z = H.cycle(v)
+        wv = A @ z
+        v = wv / np.linalg.norm(wv)
+        k += 1
+    t_iter = (time.perf_counter() - t1) / k
+    t_solve = t_setup + gpu_iters * t_iter
+    if limiter is not None:
+        limiter.unregister()
+    return dict(value=1.0 / t_solve, unit="solves/s", cores=1, kind="oracle",
+                sample=f"oracle setup ({t_setup:.1f} s) + {k} preconditioned FGMRES iterations "
+                       f"({t_iter:.2f} s each) of {w.name}, one right-hand side, scaled to "
+                       f"{gpu_iters} iterations")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2_hetero512_fp64")
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-roofline", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the solver runs all subdomains and right-hand sides "
+              "on a single device; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from workloads import get_config
+    w = get_config(a.config)
+    print(f"[bench] {w.name}: n={w.n} nrhs={len(w.sources())} levels={w.levels} cycle={w.cycle} "
+          f"bits={w.precond_bits}", file=sys.stderr, flush=True)
+    total, res, B, X = run_gpu(w, a.steps, a.warmup, a.tol)
+    setup_ms = 1e3 * float(np.mean([r[0] for r in res]))
+    solve_ms = 1e3 * float(np.mean([r[1] for r in res]))
+    stats = res[-1][3]
+    iters = [s["iters"] for s in stats]
+    nrhs = len(stats)
+    ms_per_step = 1e3 * total / a.steps
+    out = {
+        "metric": "preconditioned solves/sec at rel. residual 1e-6; V-cycle HBM GB/s vs peak",
+        "value": nrhs * a.steps / total,
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if w.precond_bits == 64 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "grid": list(w.n), "unknowns": int(B.shape[1] // 2),
+                   "nrhs": nrhs, "levels": w.levels, "cycle": "V" if w.cycle == 1 else "W",
+                   "nu": [w.nu1, w.nu2], "vanka": "full" if w.vanka else "economic",
+                   "shift": w.shift, "precond_bits": w.precond_bits, "restart": w.restart,
+                   "dd_parts": list(w.dd_parts[:w.dim]), "tol": a.tol},
+        "setup_ms": setup_ms, "solve_ms": solve_ms,
+        "iters": iters if nrhs <= 4 else [min(iters), max(iters)],
+        "rel_res_true_max": max(s["rel_res_true"] for s in stats),
+        "status": res[-1][2],
+    }
+    if not a.no_roofline:
+        avg_s, nbytes = kernel_roofline(w)
+        achieved = nbytes / avg_s / 1e9
+        out["roofline"] = {"bound": "hbm", "kernel": "k_relax (finest level, one colour)",
+                           "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                           "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                           "bytes_per_launch": nbytes, "avg_launch_us": avg_s * 1e6}
+    if not a.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, int(np.median(iters)))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

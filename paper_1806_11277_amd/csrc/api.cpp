@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -43,6 +45,29 @@ int32_t fail(int32_t code, const std::string& msg) {
 // Optional injected allocation failure (EHH_FAIL_ALLOC_AFTER=k: the (k+1)-th
 // device allocation of the process fails), for testing the OOM path.
 long g_alloc_count = 0;
+
+// EHH_LOG=1 prints the setup phases with their durations to stderr.
+bool log_enabled() {
+    static bool v = [] {
+        const char* s = std::getenv("EHH_LOG");
+        return s && std::atoi(s) != 0;
+    }();
+    return v;
+}
+struct PhaseLog {
+    hipStream_t s;
+    std::chrono::steady_clock::time_point t0;
+    explicit PhaseLog(hipStream_t st) : s(st), t0(std::chrono::steady_clock::now()) {}
+    void mark(const char* what) {
+        if (!log_enabled()) return;
+        (void)hipStreamSynchronize(s);
+        const auto t1 = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[ehh] %-40s %9.2f ms\n", what,
+                     std::chrono::duration<double, std::milli>(t1 - t0).count());
+        std::fflush(stderr);
+        t0 = t1;
+    }
+};
 long fail_alloc_after() {
     static long v = [] {
         const char* s = std::getenv("EHH_FAIL_ALLOC_AFTER");
@@ -95,10 +120,22 @@ struct ehh_ctx {
     int *active = nullptr, *ncols = nullptr;
     double* host_pinned = nullptr;
     std::vector<void*> allocs;
+    // one captured graph per Arnoldi step j for the current batch size
+    int graph_rhs = 0;
+    std::vector<hipGraphExec_t> graphs;
+    hipStream_t cap_stream = nullptr;
 
     ~ehh_ctx() {
+        clear_graphs();
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (void* p : allocs) (void)hipFree(p);
         if (host_pinned) (void)hipHostFree(host_pinned);
+    }
+    void clear_graphs() {
+        for (hipGraphExec_t e : graphs)
+            if (e) (void)hipGraphExecDestroy(e);
+        graphs.clear();
+        graph_rhs = 0;
     }
 
     int32_t alloc(void** p, size_t bytes) {
@@ -154,6 +191,7 @@ hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 // --------------------------------------------------------------- workspaces
 int32_t ensure_ws(ehh_ctx* c, int nrhs) {
     if (nrhs <= c->ws_rhs) return EHH_OK;
+    c->clear_graphs();
     const size_t es = c->bits() == 32 ? sizeof(float) : sizeof(double);
     for (Sub& S : c->subs) {
         for (size_t l = 0; l < S.lev.size(); ++l) {
@@ -182,6 +220,7 @@ int32_t ensure_ws(ehh_ctx* c, int nrhs) {
 
 int32_t ensure_krylov(ehh_ctx* c, int nrhs) {
     if (nrhs <= c->kr_rhs) return EHH_OK;
+    c->clear_graphs();
     const int m = c->opt.restart;
     const size_t vec = 2 * (size_t)c->gg.N * nrhs * sizeof(double);
     double** bufs[] = {&c->V, &c->Z, &c->w, &c->R, &c->H, &c->cs, &c->g, &c->hcol, &c->hcol2, &c->nrm2,
@@ -245,10 +284,13 @@ int32_t cycle(ehh_ctx* c, Sub& S, int l, const T* b, T* e, bool zero_init, int n
         HIPCHK(launch_apply<T>(D, e, b, t, nrhs, s));   // t = b - A e
         HIPCHK(launch_restrict<T>(L.g, C.g, t, (T*)C.b, nrhs, s));
     } else {
-        HIPCHK(hipMemsetAsync(e, 0, sizeof(T) * 2 * (size_t)L.g.N * nrhs, s));
+        HIPCHK(launch_zero(e, sizeof(T) * 2 * (size_t)L.g.N * nrhs, s));
         HIPCHK(launch_restrict<T>(L.g, C.g, b, (T*)C.b, nrhs, s));
     }
-    for (int k = 0; k < c->opt.cycle; ++k) CHK(cycle<T>(c, S, l + 1, (const T*)C.b, (T*)C.e, k == 0, nrhs, s));
+    // gamma_c recursive calls (V: 1, W: 2); the coarsest solve is exact, so a second
+    // call there with the same right-hand side would repeat the same result.
+    const int ncall = (l + 1 == nl - 1) ? 1 : c->opt.cycle;
+    for (int k = 0; k < ncall; ++k) CHK(cycle<T>(c, S, l + 1, (const T*)C.b, (T*)C.e, k == 0, nrhs, s));
     HIPCHK(launch_prolong<T>(L.g, C.g, (const T*)C.e, e, nrhs, s));
     for (int it = 0; it < c->opt.nu2; ++it) {
         HIPCHK(launch_relax<T>(D, 0, L.damping, econ, b, e, t, nrhs, s));
@@ -283,7 +325,7 @@ template <typename T> int32_t precondition_t(ehh_ctx* c, const double* v, double
         HIPCHK(launch_cast_f2d((const float*)S.e0, z, 2 * gg.N * nrhs, s));
         return EHH_OK;
     }
-    HIPCHK(hipMemsetAsync(z, 0, sizeof(double) * 2 * (size_t)gg.N * nrhs, s));
+    HIPCHK(launch_zero(z, sizeof(double) * 2 * (size_t)gg.N * nrhs, s));
     if (c->opt.dd_colors == 1) {
         for (Sub& S : c->subs) {
             const SubMap m = submap(c, S);
@@ -431,6 +473,7 @@ int32_t build_hierarchy(ehh_ctx* c, Sub& S, const double* lam, const double* mu,
         p.rho_bar = c->rho_bar;
         HIPCHK(launch_fine_coef(p, lam, mu, rho, gam, L0.coef64, s));
     }
+    PhaseLog lg(s);
     const int64_t n0 = L0.g.ncell;
     const FineCoef<double> fc{L0.coef64, L0.coef64 + n0, L0.coef64 + 2 * n0, L0.coef64 + 3 * n0,
                               c->omega_nd * c->omega_nd, c->prob.shift};
@@ -444,6 +487,7 @@ int32_t build_hierarchy(ehh_ctx* c, Sub& S, const double* lam, const double* mu,
         CHK(c->alloc((void**)&C.coef64, sizeof(double) * stencil_size(C.g)));
         HIPCHK(launch_galerkin(S.lev[l - 1].g, prev, C.g, C.coef64, s));
         prev = C.coef64;
+        lg.mark("galerkin level");
     }
     const Level& Lc = S.lev[L - 1];
     const int64_t nc = Lc.g.N;
@@ -454,8 +498,10 @@ int32_t build_hierarchy(ehh_ctx* c, Sub& S, const double* lam, const double* mu,
     int* piv = nullptr;
     CHK(c->alloc((void**)&work, sizeof(double) * 2 * nc));
     CHK(c->alloc((void**)&piv, sizeof(int) * nc));
+    lg.mark("dense assemble");
     HIPCHK(launch_dense_invert(S.inv, nc, 1, work, piv, s));
     HIPCHK(hipStreamSynchronize(s));
+    lg.mark("dense invert");
     c->release(work);
     c->release(piv);
     c->release(st0);
@@ -584,6 +630,63 @@ int32_t level_of(ehh_ctx* c, int sub, int level, Sub** S, Level** L) {
     return EHH_OK;
 }
 
+// One Arnoldi step j of flexible GMRES for every right-hand side, enqueued
+// without any host synchronisation (so that it can be captured in a graph):
+// Z_j = M^{-1} V_j, w = A Z_j, two classical Gram-Schmidt passes, |w|, the
+// Givens rotation and the residual estimate, V_{j+1} = w / |w|.
+int32_t enqueue_iter(ehh_ctx* c, const LevelDesc<double>& A, int j, int nrhs, hipStream_t s) {
+    const int m = c->opt.restart;
+    const int64_t N = c->gg.N;
+    double* Vj = c->V + (size_t)j * nrhs * 2 * N;
+    double* Zj = c->Z + (size_t)j * nrhs * 2 * N;
+    CHK(precondition_any(c, Vj, Zj, nrhs, s));
+    HIPCHK(launch_apply<double>(A, Zj, nullptr, c->w, nrhs, s));
+    HIPCHK(launch_dots(c->V, j + 1, c->w, N, nrhs, c->partial, c->hcol, m + 1, s));
+    HIPCHK(launch_axpy_multi(c->V, j + 1, c->w, N, nrhs, c->hcol, m + 1, c->partial, nullptr, s));
+    HIPCHK(launch_dots(c->V, j + 1, c->w, N, nrhs, c->partial, c->hcol2, m + 1, s));
+    HIPCHK(launch_axpy_multi(c->V, j + 1, c->w, N, nrhs, c->hcol2, m + 1, c->partial, c->nrm2, s));
+    HIPCHK(launch_axpby(c->hcol, c->hcol2, c->hcol, 2 * (int64_t)nrhs * (m + 1), 1.0, 1.0, s));
+    HIPCHK(launch_givens(c->H, c->cs, c->g, c->hcol, c->nrm2, j, m, nrhs, c->active, c->est, c->bnorm, s));
+    HIPCHK(launch_scale(c->w, c->V + (size_t)(j + 1) * nrhs * 2 * N, N, nrhs, c->nrm2, 1, s));
+    return EHH_OK;
+}
+
+bool graphs_enabled() {
+    const char* v = std::getenv("EHH_GRAPHS");
+    return !(v && std::atoi(v) == 0);
+}
+
+// Capture the m Arnoldi steps of the current batch size into executable graphs.
+int32_t build_graphs(ehh_ctx* c, const LevelDesc<double>& A, int nrhs) {
+    c->clear_graphs();
+    if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    for (int j = 0; j < c->opt.restart; ++j) {
+        HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        const int32_t st = enqueue_iter(c, A, j, nrhs, c->cap_stream);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+        if (st != EHH_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            c->clear_graphs();
+            return st;
+        }
+        if (e != hipSuccess) {
+            c->clear_graphs();
+            return fail(EHH_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        }
+        hipGraphExec_t ex = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            c->clear_graphs();
+            return fail(EHH_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+        }
+        c->graphs.push_back(ex);
+    }
+    c->graph_rhs = nrhs;
+    return EHH_OK;
+}
+
 }  // namespace
 
 // ======================================================================= C ABI
@@ -701,6 +804,8 @@ int32_t ehh_solve(ehh_handle_t h, const double* b, double* x, int32_t nrhs, doub
     A.f = FineCoef<double>{c->fine64, c->fine64 + nc, c->fine64 + 2 * nc, c->fine64 + 3 * nc,
                            c->omega_nd * c->omega_nd, 0.0};
 
+    const bool use_graphs = graphs_enabled();
+    if (use_graphs && c->graph_rhs != nrhs) CHK(build_graphs(c, A, nrhs));
     std::vector<double> bnorm(nrhs), beta(nrhs), est(nrhs, 1.0), fin_est(nrhs, 1.0);
     std::vector<int> active(nrhs, 0), iters(nrhs, 0), ncols(nrhs, 0), done_flag(nrhs, 0);
     std::vector<std::vector<double>> hist(nrhs);
@@ -751,18 +856,10 @@ int32_t ehh_solve(ehh_handle_t h, const double* b, double* x, int32_t nrhs, doub
         HIPCHK(launch_scale(c->R, c->V, N, nrhs, c->scal, 0, s));
         int j = 0;
         for (j = 0; j < m; ++j) {
-            double* Vj = c->V + (size_t)j * nrhs * 2 * N;
-            double* Zj = c->Z + (size_t)j * nrhs * 2 * N;
-            CHK(precondition_any(c, Vj, Zj, nrhs, s));
-            HIPCHK(launch_apply<double>(A, Zj, nullptr, c->w, nrhs, s));
-            // classical Gram-Schmidt, twice
-            HIPCHK(launch_dots(c->V, j + 1, c->w, N, nrhs, c->partial, c->hcol, m + 1, s));
-            HIPCHK(launch_axpy_multi(c->V, j + 1, c->w, N, nrhs, c->hcol, m + 1, c->partial, nullptr, s));
-            HIPCHK(launch_dots(c->V, j + 1, c->w, N, nrhs, c->partial, c->hcol2, m + 1, s));
-            HIPCHK(launch_axpy_multi(c->V, j + 1, c->w, N, nrhs, c->hcol2, m + 1, c->partial, c->nrm2, s));
-            HIPCHK(launch_axpby(c->hcol, c->hcol2, c->hcol, 2 * (int64_t)nrhs * (m + 1), 1.0, 1.0, s));
-            HIPCHK(launch_givens(c->H, c->cs, c->g, c->hcol, c->nrm2, j, m, nrhs, c->active, c->est, c->bnorm, s));
-            HIPCHK(launch_scale(c->w, c->V + (size_t)(j + 1) * nrhs * 2 * N, N, nrhs, c->nrm2, 1, s));
+            if (use_graphs)
+                HIPCHK(hipGraphLaunch(c->graphs[j], s));
+            else
+                CHK(enqueue_iter(c, A, j, nrhs, s));
             HIPCHK(hipMemcpyAsync(hp, c->est, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
             ++it;
@@ -788,6 +885,13 @@ int32_t ehh_solve(ehh_handle_t h, const double* b, double* x, int32_t nrhs, doub
                     continue;
                 }
                 ++left;
+            }
+            if (log_enabled() && it % 10 == 0) {
+                double worst = 0.0;
+                for (int r = 0; r < nrhs; ++r)
+                    if (active[r]) worst = std::max(worst, hp[r]);
+                std::fprintf(stderr, "[ehh] iteration %d: %d active, worst estimate %.3e\n", it, left, worst);
+                std::fflush(stderr);
             }
             if (left == 0 || it >= maxit || breakdown) break;
             if (changed)

@@ -62,6 +62,7 @@ hipError_t launch_dense_invert(double* dense, int64_t n, int batch, double* work
 template <typename T>
 hipError_t launch_coarse_apply(const double* inv, int64_t n, const T* r, T* e, int nrhs, hipStream_t s);
 hipError_t launch_cast_d2f(const double* in, float* out, int64_t n, hipStream_t s);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);   // bytes multiple of 4
 hipError_t launch_cast_f2d(const float* in, double* out, int64_t n, hipStream_t s);
 
 // ---- dd.hip

@@ -48,37 +48,49 @@ __global__ __launch_bounds__(KB) void k_dots_partial(const double* __restrict__ 
         const double xr = wr[e], xi = wr[N + e];
 #pragma unroll
         for (int i = 0; i < MAXV; ++i) {
-            if (i >= nv) break;
-            const double* v = V + ((int64_t)i * nrhs + r) * 2 * N;
-            const double vr = v[e], vi = v[N + e];
-            are[i] += vr * xr + vi * xi;
-            aim[i] += vr * xi - vi * xr;
+            if (i < nv) {
+                const double* v = V + ((int64_t)i * nrhs + r) * 2 * N;
+                const double vr = v[e], vi = v[N + e];
+                are[i] += vr * xr + vi * xi;
+                aim[i] += vr * xi - vi * xr;
+            }
         }
     }
-    for (int i = 0; i < nv; ++i) {
-        const double sr = block_sum(are[i], sm);
-        if (threadIdx.x == 0) partial[(((int64_t)r * nv + i) * 2 + 0) * nb + blockIdx.x] = sr;
-        const double si = block_sum(aim[i], sm);
-        if (threadIdx.x == 0) partial[(((int64_t)r * nv + i) * 2 + 1) * nb + blockIdx.x] = si;
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+        if (i < nv) {
+            const double sr = block_sum(are[i], sm);
+            if (threadIdx.x == 0) partial[(((int64_t)r * nv + i) * 2 + 0) * nb + blockIdx.x] = sr;
+            const double si = block_sum(aim[i], sm);
+            if (threadIdx.x == 0) partial[(((int64_t)r * nv + i) * 2 + 1) * nb + blockIdx.x] = si;
+        }
     }
 }
 
-__global__ void k_partial_final(const double* __restrict__ partial, int nv, int nb, int nrhs, double* __restrict__ out,
-                                int ldo) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+// One 64-wide wavefront per output: lanes stride over the block partials, then a
+// fixed butterfly (deterministic order).
+EHH_DEV double wave_sum(const double* p, int nb) {
+    const int lane = threadIdx.x & 63;
+    double s = 0.0;
+    for (int b = lane; b < nb; b += 64) s += p[b];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    return s;
+}
+
+__global__ __launch_bounds__(256) void k_partial_final(const double* __restrict__ partial, int nv, int nb, int nrhs,
+                                                       double* __restrict__ out, int ldo) {
+    const int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (t >= nrhs * nv * 2) return;
     const int c = t & 1, i = (t >> 1) % nv, r = (t >> 1) / nv;
-    const double* p = partial + (((int64_t)r * nv + i) * 2 + c) * nb;
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += p[b];
-    out[2 * ((int64_t)r * ldo + i) + c] = s;
+    const double s = wave_sum(partial + (((int64_t)r * nv + i) * 2 + c) * nb, nb);
+    if ((threadIdx.x & 63) == 0) out[2 * ((int64_t)r * ldo + i) + c] = s;
 }
 
 hipError_t launch_dots(const double* V, int nv, const double* w, int64_t N, int nrhs, double* partial, double* h,
                        int ldh, hipStream_t s) {
     const int nb = krylov_blocks(N);
     hipLaunchKernelGGL(k_dots_partial, dim3(nb, nrhs), KB, 0, s, V, nv, w, N, nrhs, partial);
-    hipLaunchKernelGGL(k_partial_final, nblk(nrhs * nv * 2, 64), 64, 0, s, partial, nv, nb, nrhs, h, ldh);
+    hipLaunchKernelGGL(k_partial_final, nblk((int64_t)nrhs * nv * 2 * 64), 256, 0, s, partial, nv, nb, nrhs, h, ldh);
     return hipGetLastError();
 }
 
@@ -101,11 +113,12 @@ __global__ __launch_bounds__(KB) void k_axpy_multi(const double* __restrict__ V,
         double xr = wr[e], xi = wr[N + e];
 #pragma unroll
         for (int i = 0; i < MAXV; ++i) {
-            if (i >= nv) break;
-            const double* v = V + ((int64_t)i * nrhs + r) * 2 * N;
-            const double vr = v[e], vi = v[N + e];
-            xr -= hr[i] * vr - hi[i] * vi;
-            xi -= hr[i] * vi + hi[i] * vr;
+            if (i < nv) {
+                const double* v = V + ((int64_t)i * nrhs + r) * 2 * N;
+                const double vr = v[e], vi = v[N + e];
+                xr -= hr[i] * vr - hi[i] * vi;
+                xi -= hr[i] * vi + hi[i] * vr;
+            }
         }
         wr[e] = xr;
         wr[N + e] = xi;
@@ -117,19 +130,19 @@ __global__ __launch_bounds__(KB) void k_axpy_multi(const double* __restrict__ V,
     }
 }
 
-__global__ void k_norm_final(const double* __restrict__ partial, int nb, int nrhs, double* __restrict__ out) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_norm_final(const double* __restrict__ partial, int nb, int nrhs,
+                                                    double* __restrict__ out) {
+    const int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (r >= nrhs) return;
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += partial[(int64_t)r * nb + b];
-    out[r] = s;
+    const double s = wave_sum(partial + (int64_t)r * nb, nb);
+    if ((threadIdx.x & 63) == 0) out[r] = s;
 }
 
 hipError_t launch_axpy_multi(const double* V, int nv, double* w, int64_t N, int nrhs, const double* h, int ldh,
                              double* partial, double* nrm2, hipStream_t s) {
     const int nb = krylov_blocks(N);
     hipLaunchKernelGGL(k_axpy_multi, dim3(nb, nrhs), KB, 0, s, V, nv, w, N, nrhs, h, ldh, nrm2 ? partial : nullptr);
-    if (nrm2) hipLaunchKernelGGL(k_norm_final, nblk(nrhs, 64), 64, 0, s, partial, nb, nrhs, nrm2);
+    if (nrm2) hipLaunchKernelGGL(k_norm_final, nblk((int64_t)nrhs * 64), 256, 0, s, partial, nb, nrhs, nrm2);
     return hipGetLastError();
 }
 
@@ -147,7 +160,7 @@ __global__ __launch_bounds__(KB) void k_norm_partial(const double* __restrict__ 
 hipError_t launch_norm2(const double* x, int64_t N, int nrhs, double* partial, double* nrm2, hipStream_t s) {
     const int nb = krylov_blocks(N);
     hipLaunchKernelGGL(k_norm_partial, dim3(nb, nrhs), KB, 0, s, x, N, partial);
-    hipLaunchKernelGGL(k_norm_final, nblk(nrhs, 64), 64, 0, s, partial, nb, nrhs, nrm2);
+    hipLaunchKernelGGL(k_norm_final, nblk((int64_t)nrhs * 64), 256, 0, s, partial, nb, nrhs, nrm2);
     return hipGetLastError();
 }
 

@@ -10,41 +10,29 @@
 namespace ehh {
 
 // --------------------------------------------------------------- y = A x, r = b - A x
-// One thread per cell; the cell owns its low face of every component (if that
-// face is interior) and its pressure.
+// One thread per unknown (row): short independent load chains, so that small
+// coarse levels are not bound by the latency of one long serial row loop.
 template <int D, typename T, class Op>
 __global__ __launch_bounds__(256) void k_apply(Op op, const T* __restrict__ x, const T* __restrict__ b,
                                                T* __restrict__ y, int nrhs, int64_t stride) {
     const Geo& g = op.g;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= g.ncell) return;
-    int c[3];
-    cell_pos<D>(g, t, c);
+    if (t >= g.N) return;
+    int k = 0;
+    while (k < 3 && t >= g.off[k + 1]) ++k;
+    const int64_t li = t - g.off[k];
+    int p[3];
+    if (k == 3) cell_pos<D>(g, li, p);
+    else face_pos<D>(g, k, li, p);
     for (int r = 0; r < nrhs; ++r) {
         const CVec<T> xv{x + r * stride, g.N};
-        const Vec<T> yv{y + r * stride, g.N};
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            if (c[k] < 1) continue;
-            const int64_t i = g.off[k] + face_idx<D>(g, k, c);
-            cx<T> v = op.row_u(k, c, xv);
-            if (b) {
-                const CVec<T> bv{b + r * stride, g.N};
-                v = bv.ld(i) - v;
-            }
-            yv.st(i, v);
-        }
-        const int64_t ip = g.off[3] + cell_idx<D>(g, c);
-        cx<T> v = op.row_p(c, xv);
-        if (b) {
-            const CVec<T> bv{b + r * stride, g.N};
-            v = bv.ld(ip) - v;
-        }
-        yv.st(ip, v);
+        cx<T> v = k == 3 ? op.row_p(p, xv) : op.row_u(k, p, xv);
+        if (b) v = CVec<T>{b + r * stride, g.N}.ld(t) - v;
+        Vec<T>{y + r * stride, g.N}.st(t, v);
     }
 }
 
-// ------------------------------------------------------------ red-black Vanka half-sweep
+// ------------------------------------------- red-black Vanka half-sweep, finest level
 // One thread per pair of cells along x: the cell of the swept colour is relaxed
 // (its 2D+1 unknowns: both faces of every component and the pressure), the other
 // cell only has its pressure carried over.  Every face belongs to exactly one cell
@@ -54,7 +42,7 @@ __global__ __launch_bounds__(256) void k_apply(Op op, const T* __restrict__ x, c
 // the block: one 2x2 complex system per displacement component (diagonal only in
 // the economic variant) and the scalar Schur complement on the pressure.
 template <int D, typename T, class Op>
-__global__ __launch_bounds__(256) void k_relax(Op op, int colour, T w, int econ,
+__global__ __launch_bounds__(256) void k_relax_pair(Op op, int colour, T w, int econ,
                                                const T* __restrict__ b, const T* __restrict__ ein,
                                                T* __restrict__ eout, int nrhs, int64_t stride) {
     const Geo& g = op.g;
@@ -136,6 +124,276 @@ __global__ __launch_bounds__(256) void k_relax(Op op, int colour, T w, int econ,
         }
         ov.st(ipr, (ein ? ev.ld(ipr) : zero) + w * dp);
         ov.st(ipb, ein ? ev.ld(ipb) : zero);
+    }
+}
+
+// ------------------------------------------------------------ red-black Vanka half-sweep
+// Eight lanes of a wavefront per relaxed cell: lane j < 2D+1 evaluates row j of
+// the cell block (row 2k / 2k+1 = low / high face of component k, row 2D = the
+// pressure), the lane of row 0 gathers the residuals with wave shuffles, solves
+// the block in closed form (one 2x2 complex system per displacement component,
+// diagonal only in the economic variant, and the scalar Schur complement on the
+// pressure) and hands each lane its correction; lane 2D+1 carries the pressure
+// of the other cell of the pair over.  Cells of one colour share no unknown and
+// every face belongs to exactly one of them, so e_out is written once per
+// unknown; the residual is taken from e_in (the state at the start of the
+// half-sweep).
+template <int D, typename T, class Op>
+__global__ __launch_bounds__(256) void k_relax(Op op, int colour, T w, int econ,
+                                               const T* __restrict__ b, const T* __restrict__ ein,
+                                               T* __restrict__ eout, int nrhs, int64_t stride) {
+    constexpr int R = 2 * D + 1;
+    const Geo& g = op.g;
+    const int hp = g.n[0] >> 1;
+    const int64_t npair = (int64_t)hp * g.n[1] * g.n[2];
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = gt >> 3;            // pair (red cell) index
+    const int row = (int)(gt & 7);
+    const int lane = threadIdx.x & 63;
+    const int base = lane & ~7;
+    const bool live = t < npair;
+    const int64_t tt = live ? t : 0;
+    const int px = (int)(tt % hp);
+    const int64_t rest = tt / hp;
+    const int yy = (int)(rest % g.n[1]);
+    const int zz = (int)(rest / g.n[1]);
+    const int par = (colour + yy + zz) & 1;
+    const int cr[3] = {2 * px + par, yy, zz};
+    const int cb[3] = {2 * px + 1 - par, yy, zz};
+    // the unknown of this lane's row
+    const int k = row < 2 * D ? (row >> 1) : 3;
+    int p[3] = {cr[0], cr[1], cr[2]};
+    bool ok = live && row < R;
+    if (k < 3) {
+        p[k] += row & 1;
+        ok = ok && p[k] >= 1 && p[k] <= g.n[k] - 1;
+    }
+    const int64_t idx = !ok ? 0 : (k == 3 ? g.off[3] + cell_idx<D>(g, p) : g.off[k] + face_idx<D>(g, k, p));
+    const bool carry = live && row == R;
+    const int64_t ipb = g.off[3] + cell_idx<D>(g, cb);
+
+    // block factorisation (lane of row 0)
+    cx<T> i00[D], i01[D], i11[D], zlo[D], zhi[D];
+    T glo[D], ghi[D];
+    cx<T> iS = mk<T>(T(0), T(0));
+    if (row == 0 && live) {
+        cx<T> S = mk<T>(op.pdiag(cr), T(0));
+#pragma unroll
+        for (int kk = 0; kk < D; ++kk) {
+            const bool lok = cr[kk] >= 1, hok = cr[kk] + 1 <= g.n[kk] - 1;
+            cx<T> all, ahh, alh;
+            op.block(cr, kk, all, ahh, alh, glo[kk], ghi[kk], lok, hok);
+            if (econ) alh = mk<T>(T(0), T(0));
+            const cx<T> idet = cinv(all * ahh - alh * alh);
+            i00[kk] = ahh * idet;
+            i11[kk] = all * idet;
+            i01[kk] = mk<T>(T(0), T(0)) - alh * idet;
+            zlo[kk] = glo[kk] * i00[kk] + ghi[kk] * i01[kk];
+            zhi[kk] = glo[kk] * i01[kk] + ghi[kk] * i11[kk];
+            S = S - (glo[kk] * zlo[kk] + ghi[kk] * zhi[kk]);
+        }
+        iS = cinv(S);
+    }
+
+    for (int r = 0; r < nrhs; ++r) {
+        const CVec<T> bv{b + r * stride, g.N};
+        const CVec<T> ev{ein ? ein + r * stride : nullptr, g.N};
+        const Vec<T> ov{eout + r * stride, g.N};
+        cx<T> res = mk<T>(T(0), T(0));
+        if (ok) {
+            res = bv.ld(idx);
+            if (ein) res = res - (k == 3 ? op.row_p(p, ev) : op.row_u(k, p, ev));
+        }
+        // gather the block residual in the lane of row 0
+        cx<T> rr[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            rr[j].re = __shfl(res.re, base + j, 64);
+            rr[j].im = __shfl(res.im, base + j, 64);
+        }
+        cx<T> d[R];
+        if (row == 0) {
+            cx<T> acc = rr[2 * D];
+            cx<T> ylo[D], yhi[D];
+#pragma unroll
+            for (int kk = 0; kk < D; ++kk) {
+                ylo[kk] = i00[kk] * rr[2 * kk] + i01[kk] * rr[2 * kk + 1];
+                yhi[kk] = i01[kk] * rr[2 * kk] + i11[kk] * rr[2 * kk + 1];
+                acc = acc - (glo[kk] * ylo[kk] + ghi[kk] * yhi[kk]);
+            }
+            const cx<T> dp = acc * iS;
+#pragma unroll
+            for (int kk = 0; kk < D; ++kk) {
+                d[2 * kk] = ylo[kk] - zlo[kk] * dp;
+                d[2 * kk + 1] = yhi[kk] - zhi[kk] * dp;
+            }
+            d[2 * D] = dp;
+        }
+        // hand every lane its correction
+        cx<T> mine = mk<T>(T(0), T(0));
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const T vr = __shfl(d[j].re, base, 64);
+            const T vi = __shfl(d[j].im, base, 64);
+            if (row == j) mine = mk<T>(vr, vi);
+        }
+        if (ok) ov.st(idx, (ein ? ev.ld(idx) : mk<T>(T(0), T(0))) + w * mine);
+        if (carry) ov.st(ipb, ein ? ev.ld(ipb) : mk<T>(T(0), T(0)));
+    }
+}
+
+// ------------------------------------------------ plan-based apply and half-sweep
+// The row plan (indices and coefficients) is built once per row and reused for
+// every right-hand side, so a batch streams only the vectors.
+template <int D, typename T, class Op>
+__global__ __launch_bounds__(256) void k_apply_plan(Op op, const T* __restrict__ x, const T* __restrict__ b,
+                                                    T* __restrict__ y, int nrhs, int64_t stride) {
+    const Geo& g = op.g;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= g.N) return;
+    int k = 0;
+    while (k < 3 && t >= g.off[k + 1]) ++k;
+    const int64_t li = t - g.off[k];
+    int p[3];
+    Plan<T, Op::NT> P;
+    if (k == 3) {
+        cell_pos<D>(g, li, p);
+        op.plan_p(p, P);
+    } else {
+        face_pos<D>(g, k, li, p);
+        op.plan_u(k, p, P);
+    }
+    for (int r = 0; r < nrhs; ++r) {
+        cx<T> v = P.dot(CVec<T>{x + r * stride, g.N});
+        if (b) v = CVec<T>{b + r * stride, g.N}.ld(t) - v;
+        Vec<T>{y + r * stride, g.N}.st(t, v);
+    }
+}
+
+// Eight lanes per relaxed cell as in k_relax, each lane holding the plan of its
+// block row; the block itself (diagonals, the coupling of the two faces of a
+// component, the couplings to the cell pressure) is read off the lanes' plans.
+template <int D, typename T, class Op>
+__global__ __launch_bounds__(256) void k_relax_plan(Op op, int colour, T w, int econ,
+                                                    const T* __restrict__ b, const T* __restrict__ ein,
+                                                    T* __restrict__ eout, int nrhs, int64_t stride) {
+    constexpr int R = 2 * D + 1;
+    const Geo& g = op.g;
+    const int hp = g.n[0] >> 1;
+    const int64_t npair = (int64_t)hp * g.n[1] * g.n[2];
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = gt >> 3;
+    const int row = (int)(gt & 7);
+    const int lane = threadIdx.x & 63;
+    const int base = lane & ~7;
+    const bool live = t < npair;
+    const int64_t tt = live ? t : 0;
+    const int px = (int)(tt % hp);
+    const int64_t rest = tt / hp;
+    const int yy = (int)(rest % g.n[1]);
+    const int zz = (int)(rest / g.n[1]);
+    const int par = (colour + yy + zz) & 1;
+    const int cr[3] = {2 * px + par, yy, zz};
+    const int cb[3] = {2 * px + 1 - par, yy, zz};
+    const int k = row < 2 * D ? (row >> 1) : 3;
+    int p[3] = {cr[0], cr[1], cr[2]};
+    bool ok = live && row < R;
+    if (k < 3) {
+        p[k] += row & 1;
+        ok = ok && p[k] >= 1 && p[k] <= g.n[k] - 1;
+    }
+    Plan<T, Op::NT> P;
+    int64_t idx = 0;
+    if (ok) {
+        if (k == 3) {
+            op.plan_p(p, P);
+            idx = g.off[3] + cell_idx<D>(g, p);
+        } else {
+            op.plan_u(k, p, P);
+            idx = g.off[k] + face_idx<D>(g, k, p);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < Op::NT; ++j) P.set(j, 0, T(0), T(0));
+    }
+    const bool carry = live && row == R;
+    const int64_t ipb = g.off[3] + cell_idx<D>(g, cb);
+    // this row's block entries
+    // the diagonal sits at T_SELF in a u row and at term 0 in the pressure row
+    const T dre = ok ? (k == 3 ? P.re[0] : P.re[Op::T_SELF]) : T(1);
+    const T dim = ok ? (k == 3 ? P.im[0] : P.im[Op::T_SELF]) : T(0);
+    const bool lowrow = row < 2 * D && (row & 1) == 0;
+    const T cre = (ok && lowrow && !econ) ? P.re[Op::T_NHI] : T(0);
+    const T cim = (ok && lowrow && !econ) ? P.im[Op::T_NHI] : T(0);
+    const T gg = (ok && row < 2 * D) ? (lowrow ? P.re[Op::T_PHI] : P.re[Op::T_PLO]) : T(0);
+    cx<T> i00[D], i01[D], i11[D], zlo[D], zhi[D];
+    T glo[D], ghi[D];
+    cx<T> S;
+    {
+        const T pd = __shfl(dre, base + 2 * D, 64);
+        S = mk<T>(pd, T(0));
+#pragma unroll
+        for (int kk = 0; kk < D; ++kk) {
+            const cx<T> all = mk<T>(__shfl(dre, base + 2 * kk, 64), __shfl(dim, base + 2 * kk, 64));
+            const cx<T> ahh = mk<T>(__shfl(dre, base + 2 * kk + 1, 64), __shfl(dim, base + 2 * kk + 1, 64));
+            const cx<T> alh = mk<T>(__shfl(cre, base + 2 * kk, 64), __shfl(cim, base + 2 * kk, 64));
+            glo[kk] = __shfl(gg, base + 2 * kk, 64);
+            ghi[kk] = __shfl(gg, base + 2 * kk + 1, 64);
+            if (row == 0) {
+                const cx<T> idet = cinv(all * ahh - alh * alh);
+                i00[kk] = ahh * idet;
+                i11[kk] = all * idet;
+                i01[kk] = mk<T>(T(0), T(0)) - alh * idet;
+                zlo[kk] = glo[kk] * i00[kk] + ghi[kk] * i01[kk];
+                zhi[kk] = glo[kk] * i01[kk] + ghi[kk] * i11[kk];
+                S = S - (glo[kk] * zlo[kk] + ghi[kk] * zhi[kk]);
+            }
+        }
+    }
+    const cx<T> iS = row == 0 ? cinv(S) : mk<T>(T(0), T(0));
+
+    for (int r = 0; r < nrhs; ++r) {
+        const CVec<T> bv{b + r * stride, g.N};
+        const CVec<T> ev{ein ? ein + r * stride : nullptr, g.N};
+        const Vec<T> ov{eout + r * stride, g.N};
+        cx<T> res = mk<T>(T(0), T(0));
+        if (ok) {
+            res = bv.ld(idx);
+            if (ein) res = res - P.dot(ev);
+        }
+        cx<T> rr[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            rr[j].re = __shfl(res.re, base + j, 64);
+            rr[j].im = __shfl(res.im, base + j, 64);
+        }
+        cx<T> d[R];
+        if (row == 0) {
+            cx<T> acc = rr[2 * D];
+            cx<T> ylo[D], yhi[D];
+#pragma unroll
+            for (int kk = 0; kk < D; ++kk) {
+                ylo[kk] = i00[kk] * rr[2 * kk] + i01[kk] * rr[2 * kk + 1];
+                yhi[kk] = i01[kk] * rr[2 * kk] + i11[kk] * rr[2 * kk + 1];
+                acc = acc - (glo[kk] * ylo[kk] + ghi[kk] * yhi[kk]);
+            }
+            const cx<T> dp = acc * iS;
+#pragma unroll
+            for (int kk = 0; kk < D; ++kk) {
+                d[2 * kk] = ylo[kk] - zlo[kk] * dp;
+                d[2 * kk + 1] = yhi[kk] - zhi[kk] * dp;
+            }
+            d[2 * D] = dp;
+        }
+        cx<T> mine = mk<T>(T(0), T(0));
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const T vr = __shfl(d[j].re, base, 64);
+            const T vi = __shfl(d[j].im, base, 64);
+            if (row == j) mine = mk<T>(vr, vi);
+        }
+        if (ok) ov.st(idx, (ein ? ev.ld(idx) : mk<T>(T(0), T(0))) + w * mine);
+        if (carry) ov.st(ipb, ein ? ev.ld(ipb) : mk<T>(T(0), T(0)));
     }
 }
 
@@ -300,15 +558,15 @@ static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b -
 template <typename T>
 hipError_t launch_apply(const LevelDesc<T>& L, const T* x, const T* b, T* y, int nrhs, hipStream_t s) {
     const int64_t stride = 2 * L.g.N;
-    const unsigned gb = nblk(L.g.ncell);
+    const unsigned gb = nblk(L.g.N);
     if (L.g.dim == 2) {
         if (L.fine)
-            hipLaunchKernelGGL((k_apply<2, T, FineOp<2, T>>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, x, b, y, nrhs, stride);
+            hipLaunchKernelGGL((k_apply_plan<2, T, FineOp<2, T>>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, x, b, y, nrhs, stride);
         else
-            hipLaunchKernelGGL((k_apply<2, T, StOp<2, T>>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, x, b, y, nrhs, stride);
+            hipLaunchKernelGGL((k_apply_plan<2, T, StOp<2, T>>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, x, b, y, nrhs, stride);
     } else {
         if (L.fine)
-            hipLaunchKernelGGL((k_apply<3, T, FineOp<3, T>>), gb, 256, 0, s, FineOp<3, T>{L.g, L.f}, x, b, y, nrhs, stride);
+            hipLaunchKernelGGL((k_apply_plan<3, T, FineOp<3, T>>), gb, 256, 0, s, FineOp<3, T>{L.g, L.f}, x, b, y, nrhs, stride);
         else
             hipLaunchKernelGGL((k_apply<3, T, StOp<3, T>>), gb, 256, 0, s, StOp<3, T>{L.g, L.s}, x, b, y, nrhs, stride);
     }
@@ -320,16 +578,16 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
                         T* eout, int nrhs, hipStream_t s) {
     const int64_t stride = 2 * L.g.N;
     const int64_t npair = (int64_t)(L.g.n[0] / 2) * L.g.n[1] * L.g.n[2];
-    const unsigned gb = nblk(npair);
+    const unsigned gb = nblk(npair * 8);
     const T tw = (T)w;
     if (L.g.dim == 2) {
         if (L.fine)
-            hipLaunchKernelGGL((k_relax<2, T, FineOp<2, T>>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride);
+            hipLaunchKernelGGL((k_relax_plan<2, T, FineOp<2, T>>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride);
         else
-            hipLaunchKernelGGL((k_relax<2, T, StOp<2, T>>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride);
+            hipLaunchKernelGGL((k_relax_plan<2, T, StOp<2, T>>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride);
     } else {
         if (L.fine)
-            hipLaunchKernelGGL((k_relax<3, T, FineOp<3, T>>), gb, 256, 0, s, FineOp<3, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride);
+            hipLaunchKernelGGL((k_relax_plan<3, T, FineOp<3, T>>), gb, 256, 0, s, FineOp<3, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride);
         else
             hipLaunchKernelGGL((k_relax<3, T, StOp<3, T>>), gb, 256, 0, s, StOp<3, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride);
     }

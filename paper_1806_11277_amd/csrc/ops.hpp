@@ -15,6 +15,29 @@
 
 namespace ehh {
 
+// A matrix row as (index, coefficient) terms, built once per row and then
+// applied to every right-hand side: terms beyond the row's support point at a
+// valid index with a zero coefficient.
+template <typename T, int NT> struct Plan {
+    int32_t ix[NT];
+    T re[NT], im[NT];
+    EHH_DEV void set(int j, int64_t i, T a, T b) {
+        ix[j] = (int32_t)i;
+        re[j] = a;
+        im[j] = b;
+    }
+    EHH_DEV cx<T> dot(const CVec<T>& e) const {
+        T ar = T(0), ai = T(0);
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const cx<T> v = e.ld(ix[j]);
+            ar += re[j] * v.re - im[j] * v.im;
+            ai += re[j] * v.im + im[j] * v.re;
+        }
+        return mk<T>(ar, ai);
+    }
+};
+
 template <int D, typename T> struct FineOp {
     Geo g;
     FineCoef<T> c;
@@ -22,24 +45,22 @@ template <int D, typename T> struct FineOp {
     EHH_DEV T mu_c(const int* q) const { return c.mu[cell_idx<D>(g, q)]; }
 
     // Mean of mu over the existing cells touching the edge of component k that
-    // lies at node position m along tangential axis t.
+    // lies at node position m along tangential axis t (rows m-1 and m along t;
+    // a row beyond the wall is read clamped and left out of the mean).
     EHH_DEV T mu_edge(int k, const int* p, int t, int m) const {
         int q[3] = {p[0], p[1], p[2]};
+        const bool lo = m - 1 >= 0, hi = m < g.n[t];
         T s = T(0);
-        int cntc = 0;
 #pragma unroll
         for (int dk = -1; dk <= 0; ++dk) {
-#pragma unroll
-            for (int dt = -1; dt <= 0; ++dt) {
-                q[k] = p[k] + dk;
-                q[t] = m + dt;
-                if (q[t] >= 0 && q[t] < g.n[t]) {
-                    s += mu_c(q);
-                    ++cntc;
-                }
-            }
+            q[k] = p[k] + dk;
+            q[t] = lo ? m - 1 : m;
+            const T a = mu_c(q);
+            q[t] = hi ? m : m - 1;
+            const T b = mu_c(q);
+            s += (lo ? a : T(0)) + (hi ? b : T(0));
         }
-        return s / T(cntc);
+        return s / T(2 * ((int)lo + (int)hi));
     }
 
     EHH_DEV cx<T> diag_u(int k, const int* p) const {
@@ -59,37 +80,36 @@ template <int D, typename T> struct FineOp {
         return mk<T>(w - c.om2 * mre, -c.om2 * mim);
     }
 
-    // (A e) at the face p of component k.
+    // (A e) at the face p of component k (branch-free: absent neighbours are read
+    // at the face itself and weighted by zero).
     EHH_DEV cx<T> row_u(int k, const int* p, const CVec<T>& e) const {
-        cx<T> acc = diag_u(k, p) * e.ld(g.off[k] + face_idx<D>(g, k, p));
-        int q[3] = {p[0], p[1], p[2]};
-        // normal neighbours couple through the cells above/below the face
-        if (p[k] + 1 <= g.n[k] - 1) {
+        const int64_t self = g.off[k] + face_idx<D>(g, k, p);
+        cx<T> acc = diag_u(k, p) * e.ld(self);
+        int ql[3] = {p[0], p[1], p[2]};
+        ql[k] -= 1;
+        {
+            int q[3] = {p[0], p[1], p[2]};
+            const bool okh = p[k] + 1 <= g.n[k] - 1, okl = p[k] - 1 >= 1;
             q[k] = p[k] + 1;
-            acc = acc - mu_c(p) * e.ld(g.off[k] + face_idx<D>(g, k, q));
-        }
-        if (p[k] - 1 >= 1) {
+            const int64_t ih = okh ? g.off[k] + face_idx<D>(g, k, q) : self;
             q[k] = p[k] - 1;
-            int ql[3] = {p[0], p[1], p[2]};
-            ql[k] -= 1;
-            acc = acc - mu_c(ql) * e.ld(g.off[k] + face_idx<D>(g, k, q));
+            const int64_t il = okl ? g.off[k] + face_idx<D>(g, k, q) : self;
+            const T wh = okh ? mu_c(p) : T(0), wl = okl ? mu_c(ql) : T(0);
+            acc = acc - wh * e.ld(ih) - wl * e.ld(il);
         }
-        q[k] = p[k];
 #pragma unroll
         for (int tt = 0; tt < D - 1; ++tt) {
             const int t = tt == 0 ? tang1<D>(k) : tang2<D>(k);
-            if (p[t] + 1 < g.n[t]) {
-                q[t] = p[t] + 1;
-                acc = acc - mu_edge(k, p, t, p[t] + 1) * e.ld(g.off[k] + face_idx<D>(g, k, q));
-            }
-            if (p[t] - 1 >= 0) {
-                q[t] = p[t] - 1;
-                acc = acc - mu_edge(k, p, t, p[t]) * e.ld(g.off[k] + face_idx<D>(g, k, q));
-            }
-            q[t] = p[t];
+            int q[3] = {p[0], p[1], p[2]};
+            const bool okh = p[t] + 1 < g.n[t], okl = p[t] - 1 >= 0;
+            q[t] = p[t] + 1;
+            const int64_t ih = okh ? g.off[k] + face_idx<D>(g, k, q) : self;
+            q[t] = p[t] - 1;
+            const int64_t il = okl ? g.off[k] + face_idx<D>(g, k, q) : self;
+            const T wh = okh ? mu_edge(k, p, t, p[t] + 1) : T(0);
+            const T wl = okl ? mu_edge(k, p, t, p[t]) : T(0);
+            acc = acc - wh * e.ld(ih) - wl * e.ld(il);
         }
-        int ql[3] = {p[0], p[1], p[2]};
-        ql[k] -= 1;
         acc = acc + e.ld(g.off[3] + cell_idx<D>(g, p)) - e.ld(g.off[3] + cell_idx<D>(g, ql));
         return acc;
     }
@@ -98,20 +118,66 @@ template <int D, typename T> struct FineOp {
     EHH_DEV cx<T> row_p(const int* cc, const CVec<T>& e) const {
         const int64_t ic = cell_idx<D>(g, cc);
         cx<T> acc = (-c.dinv[ic]) * e.ld(g.off[3] + ic);
-        int q[3] = {cc[0], cc[1], cc[2]};
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            if (cc[k] + 1 <= g.n[k] - 1) {
-                q[k] = cc[k] + 1;
-                acc = acc - e.ld(g.off[k] + face_idx<D>(g, k, q));
-            }
-            if (cc[k] >= 1) {
-                q[k] = cc[k];
-                acc = acc + e.ld(g.off[k] + face_idx<D>(g, k, q));
-            }
+            int q[3] = {cc[0], cc[1], cc[2]};
+            const bool okh = cc[k] + 1 <= g.n[k] - 1, okl = cc[k] >= 1;
+            q[k] = cc[k] + 1;
+            const int64_t ih = g.off[k] + (okh ? face_idx<D>(g, k, q) : 0);
             q[k] = cc[k];
+            const int64_t il = g.off[k] + (okl ? face_idx<D>(g, k, q) : 0);
+            const cx<T> vh = e.ld(ih), vl = e.ld(il);
+            acc = acc - (okh ? T(1) : T(0)) * vh + (okl ? T(1) : T(0)) * vl;
         }
         return acc;
+    }
+
+
+    // Row plans: u row = self, normal high/low, tangential high/low per axis,
+    // then the pressures of the cells above and below the face.
+    static constexpr int NT = 2 * D + 3;
+    static constexpr int T_SELF = 0, T_NHI = 1, T_PHI = NT - 2, T_PLO = NT - 1;
+    EHH_DEV void plan_u(int k, const int* p, Plan<T, NT>& P) const {
+        const int64_t self = g.off[k] + face_idx<D>(g, k, p);
+        const cx<T> dg = diag_u(k, p);
+        P.set(0, self, dg.re, dg.im);
+        int ql[3] = {p[0], p[1], p[2]};
+        ql[k] -= 1;
+        {
+            int q[3] = {p[0], p[1], p[2]};
+            const bool okh = p[k] + 1 <= g.n[k] - 1, okl = p[k] - 1 >= 1;
+            q[k] = p[k] + 1;
+            P.set(1, okh ? g.off[k] + face_idx<D>(g, k, q) : self, okh ? -mu_c(p) : T(0), T(0));
+            q[k] = p[k] - 1;
+            P.set(2, okl ? g.off[k] + face_idx<D>(g, k, q) : self, okl ? -mu_c(ql) : T(0), T(0));
+        }
+#pragma unroll
+        for (int tt = 0; tt < D - 1; ++tt) {
+            const int t = tt == 0 ? tang1<D>(k) : tang2<D>(k);
+            int q[3] = {p[0], p[1], p[2]};
+            const bool okh = p[t] + 1 < g.n[t], okl = p[t] - 1 >= 0;
+            q[t] = p[t] + 1;
+            P.set(3 + 2 * tt, okh ? g.off[k] + face_idx<D>(g, k, q) : self, okh ? -mu_edge(k, p, t, p[t] + 1) : T(0), T(0));
+            q[t] = p[t] - 1;
+            P.set(4 + 2 * tt, okl ? g.off[k] + face_idx<D>(g, k, q) : self, okl ? -mu_edge(k, p, t, p[t]) : T(0), T(0));
+        }
+        P.set(T_PHI, g.off[3] + cell_idx<D>(g, p), T(1), T(0));
+        P.set(T_PLO, g.off[3] + cell_idx<D>(g, ql), T(-1), T(0));
+    }
+    EHH_DEV void plan_p(const int* cc, Plan<T, NT>& P) const {
+        const int64_t self = g.off[3] + cell_idx<D>(g, cc);
+        P.set(0, self, -c.dinv[cell_idx<D>(g, cc)], T(0));
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            int q[3] = {cc[0], cc[1], cc[2]};
+            const bool okh = cc[k] + 1 <= g.n[k] - 1, okl = cc[k] >= 1;
+            q[k] = cc[k] + 1;
+            P.set(1 + 2 * k, okh ? g.off[k] + face_idx<D>(g, k, q) : self, okh ? T(-1) : T(0), T(0));
+            q[k] = cc[k];
+            P.set(2 + 2 * k, okl ? g.off[k] + face_idx<D>(g, k, q) : self, okl ? T(1) : T(0), T(0));
+        }
+#pragma unroll
+        for (int j = 2 * D + 1; j < NT; ++j) P.set(j, self, T(0), T(0));
     }
 
     // Block entries of the cell: u_k low/high diagonals, their coupling, the
@@ -139,47 +205,54 @@ template <int D, typename T> struct StOp {
     }
     EHH_DEV T up(int k, int64_t fidx, int q) const { return c.up[k][(int64_t)q * g.cnt[k] + fidx]; }
 
+    // Branch-free evaluation: absent neighbours are read at a clamped (valid)
+    // address and weighted by zero, so every load of the row can be in flight
+    // at once instead of one guarded load after another.
     EHH_DEV cx<T> row_u(int k, const int* p, const CVec<T>& e) const {
         constexpr int CF = St<D>::CF;
         const int t1 = tang1<D>(k), t2 = tang2<D>(k);
         const int64_t fi = face_idx<D>(g, k, p);
-        cx<T> acc = mk<T>(T(0), T(0));
-        int q[3];
+        T are = T(0), aim = T(0);
 #pragma unroll
         for (int F = 0; F < St<D>::NF; ++F) {
             int dn, d1, d2;
             full_offset<D>(F, dn, d1, d2);
-            q[0] = p[0];
-            q[1] = p[1];
-            q[2] = p[2];
+            int q[3] = {p[0], p[1], p[2]};
             q[k] += dn;
             q[t1] += d1;
             if (D == 3) q[t2] += d2;
-            if (!face_ok<D>(g, k, q)) continue;
-            const int64_t qi = face_idx<D>(g, k, q);
+            const bool ok = face_ok<D>(g, k, q);
+            const int64_t qi = ok ? face_idx<D>(g, k, q) : fi;
             const cx<T> a = F >= CF ? uu(k, fi, F - CF) : uu(k, qi, CF - F);
-            acc = acc + a * e.ld(g.off[k] + qi);
+            const cx<T> v = e.ld(g.off[k] + qi);
+            const T sre = ok ? a.re : T(0), sim = ok ? a.im : T(0);
+            are += sre * v.re - sim * v.im;
+            aim += sre * v.im + sim * v.re;
         }
+        const int64_t pc = g.off[3] + cell_idx<D>(g, p);
 #pragma unroll
         for (int qq = 0; qq < St<D>::NUP; ++qq) {
             int side, e1, e2;
             up_decode<D>(qq, side, e1, e2);
-            q[0] = p[0];
-            q[1] = p[1];
-            q[2] = p[2];
+            int q[3] = {p[0], p[1], p[2]};
             q[k] += side - 1;
             q[t1] += e1;
             if (D == 3) q[t2] += e2;
-            if (!cell_ok<D>(g, q)) continue;
-            acc = acc + up(k, fi, qq) * e.ld(g.off[3] + cell_idx<D>(g, q));
+            const bool ok = cell_ok<D>(g, q);
+            const int64_t ci = ok ? g.off[3] + cell_idx<D>(g, q) : pc;
+            const T c = ok ? up(k, fi, qq) : T(0);
+            const cx<T> v = e.ld(ci);
+            are += c * v.re;
+            aim += c * v.im;
         }
-        return acc;
+        return mk<T>(are, aim);
     }
 
     EHH_DEV cx<T> row_p(const int* cc, const CVec<T>& e) const {
         const int64_t ic = cell_idx<D>(g, cc);
-        cx<T> acc = c.pp[ic] * e.ld(g.off[3] + ic);
-        int q[3];
+        const cx<T> vp = e.ld(g.off[3] + ic);
+        const T d = c.pp[ic];
+        T are = d * vp.re, aim = d * vp.im;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             const int t1 = tang1<D>(k), t2 = tang2<D>(k);
@@ -187,18 +260,82 @@ template <int D, typename T> struct StOp {
             for (int qq = 0; qq < St<D>::NUP; ++qq) {
                 int side, e1, e2;
                 up_decode<D>(qq, side, e1, e2);
-                q[0] = cc[0];
-                q[1] = cc[1];
-                q[2] = cc[2];
+                int q[3] = {cc[0], cc[1], cc[2]};
                 q[k] += 1 - side;
                 q[t1] -= e1;
                 if (D == 3) q[t2] -= e2;
-                if (!face_ok<D>(g, k, q)) continue;
-                const int64_t qi = face_idx<D>(g, k, q);
-                acc = acc + up(k, qi, qq) * e.ld(g.off[k] + qi);
+                const bool ok = face_ok<D>(g, k, q);
+                const int64_t qi = ok ? face_idx<D>(g, k, q) : 0;
+                const T cf = ok ? up(k, qi, qq) : T(0);
+                const cx<T> v = e.ld(g.off[k] + qi);
+                are += cf * v.re;
+                aim += cf * v.im;
             }
         }
-        return acc;
+        return mk<T>(are, aim);
+    }
+
+
+    // Row plans (used for D == 2, where a whole row fits in registers): u row =
+    // the NF u-u offsets in full-offset order, then the NUP u-p entries; p row =
+    // the pressure itself, then the u-p entries of the faces around the cell.
+    static constexpr int NT = St<D>::NF + St<D>::NUP;
+    static constexpr int T_SELF = St<D>::CF, T_NHI = St<D>::CF + 1;
+    static constexpr int T_PHI = St<D>::NF + (D == 2 ? 1 + 2 : 1 + 2 * 4), T_PLO = St<D>::NF + (D == 2 ? 2 : 2 * 4);
+    EHH_DEV void plan_u(int k, const int* p, Plan<T, NT>& P) const {
+        constexpr int CF = St<D>::CF;
+        const int t1 = tang1<D>(k), t2 = tang2<D>(k);
+        const int64_t fi = face_idx<D>(g, k, p);
+        const int64_t self = g.off[k] + fi;
+#pragma unroll
+        for (int F = 0; F < St<D>::NF; ++F) {
+            int dn, d1, d2;
+            full_offset<D>(F, dn, d1, d2);
+            int q[3] = {p[0], p[1], p[2]};
+            q[k] += dn;
+            q[t1] += d1;
+            if (D == 3) q[t2] += d2;
+            const bool ok = face_ok<D>(g, k, q);
+            const int64_t qi = ok ? face_idx<D>(g, k, q) : fi;
+            const cx<T> a = F >= CF ? uu(k, fi, F - CF) : uu(k, qi, CF - F);
+            P.set(F, g.off[k] + qi, ok ? a.re : T(0), ok ? a.im : T(0));
+        }
+        const int64_t pc = g.off[3] + cell_idx<D>(g, p);
+#pragma unroll
+        for (int qq = 0; qq < St<D>::NUP; ++qq) {
+            int side, e1, e2;
+            up_decode<D>(qq, side, e1, e2);
+            int q[3] = {p[0], p[1], p[2]};
+            q[k] += side - 1;
+            q[t1] += e1;
+            if (D == 3) q[t2] += e2;
+            const bool ok = cell_ok<D>(g, q);
+            P.set(St<D>::NF + qq, ok ? g.off[3] + cell_idx<D>(g, q) : pc, ok ? up(k, fi, qq) : T(0), T(0));
+        }
+    }
+    EHH_DEV void plan_p(const int* cc, Plan<T, NT>& P) const {
+        const int64_t ic = cell_idx<D>(g, cc);
+        const int64_t self = g.off[3] + ic;
+        P.set(0, self, c.pp[ic], T(0));
+        int j = 1;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const int t1 = tang1<D>(k), t2 = tang2<D>(k);
+#pragma unroll
+            for (int qq = 0; qq < St<D>::NUP; ++qq) {
+                int side, e1, e2;
+                up_decode<D>(qq, side, e1, e2);
+                int q[3] = {cc[0], cc[1], cc[2]};
+                q[k] += 1 - side;
+                q[t1] -= e1;
+                if (D == 3) q[t2] -= e2;
+                const bool ok = face_ok<D>(g, k, q);
+                const int64_t qi = ok ? face_idx<D>(g, k, q) : 0;
+                P.set(j++, ok ? g.off[k] + qi : self, ok ? up(k, qi, qq) : T(0), T(0));
+            }
+        }
+#pragma unroll
+        for (int jj = 1 + D * St<D>::NUP; jj < NT; ++jj) P.set(jj, self, T(0), T(0));
     }
 
     EHH_DEV void block(const int* cc, int k, cx<T>& all, cx<T>& ahh, cx<T>& alh, T& glo, T& ghi,

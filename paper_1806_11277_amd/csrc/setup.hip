@@ -575,6 +575,17 @@ hipError_t launch_coarse_apply(const double* inv, int64_t n, const T* r, T* e, i
 template hipError_t launch_coarse_apply<float>(const double*, int64_t, const float*, float*, int, hipStream_t);
 template hipError_t launch_coarse_apply<double>(const double*, int64_t, const double*, double*, int, hipStream_t);
 
+__global__ void k_zero_words(uint32_t* __restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+// Zero fill by a kernel (not a memset node, so it may sit inside a captured graph).
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+    const int64_t n = (int64_t)(bytes / 4);
+    hipLaunchKernelGGL(k_zero_words, nblk(n), 256, 0, s, (uint32_t*)p, n);
+    return hipGetLastError();
+}
+
 __global__ void k_cast_d2f(const double* __restrict__ in, float* __restrict__ out, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = (float)in[i];

@@ -137,3 +137,25 @@ def test_invalid_arguments_are_rejected():
     assert st == ehh.EHH_NOT_CONVERGED and stats[0]["iters"] == 3
     assert stats[0]["rel_res_true"] > 1e-10
     S.close()
+
+
+def test_graph_replay_matches_eager_launches():
+    """The captured Arnoldi-step graphs, replayed many times with host work in
+    between, give bit-identical iterates to eager launches."""
+    import os
+    import torch
+    w = workload("c3s_hetero128_batch8_fp32")
+    say("[graph vs eager]")
+    B = rhs_matrix(w)
+    S = _solver(w)
+    xs = []
+    for mode in ("0", "1", "1"):
+        os.environ["EHH_GRAPHS"] = mode
+        x = torch.zeros_like(to_dev(B))
+        st, stats = S.solve(to_dev(B), x, tol=1e-8, maxit=400)
+        torch.cuda.synchronize()
+        assert st == 0
+        xs.append(x.cpu().numpy())
+    os.environ.pop("EHH_GRAPHS", None)
+    assert np.array_equal(xs[0], xs[1]) and np.array_equal(xs[1], xs[2])
+    S.close()

@@ -135,7 +135,7 @@ _add(Workload(
                 "h=10 m, 10 cells per minimum shear wavelength, shift 0.5, 20-cell layer, one source, "
                 "FP64 FGMRES(5) + FP64 V(1,1)",
     dim=2, n=(512, 512), h=10.0, media_fn=lambda: M.heterogeneous_2d_media((512, 512)), ppw=10.0,
-    abl_cells=(20, 20), shift=0.5, levels=6, damping=(0.75, 0.5, 0.5, 0.5, 0.5),
+    abl_cells=(20, 20), shift=0.5, levels=6, cycle=2, damping=(0.75, 0.5, 0.5, 0.5, 0.5),
     precond_bits=64, sources_fn=_src_top_single))
 
 _add(Workload(
@@ -143,7 +143,7 @@ _add(Workload(
     description="as c2, 32 x-forces at depth 5 (x = 8 + 16 s, seeded phases), complex64 V-cycle "
                 "inside FP64 FGMRES with FP64 coarsest solve",
     dim=2, n=(512, 512), h=10.0, media_fn=lambda: M.heterogeneous_2d_media((512, 512)), ppw=10.0,
-    abl_cells=(20, 20), shift=0.5, levels=6, damping=(0.75, 0.5, 0.5, 0.5, 0.5),
+    abl_cells=(20, 20), shift=0.5, levels=6, cycle=2, damping=(0.75, 0.5, 0.5, 0.5, 0.5),
     precond_bits=32, sources_fn=_src_line(32, 16, 8, 5, seed=3)))
 
 _add(Workload(
