@@ -39,13 +39,19 @@ def rhs_tensor(S, w):
     return torch.as_tensor(B, device="cuda")
 
 
-def relax_bytes_per_launch(S, level_info, bits, nrhs, fine=True):
-    """Algorithmic HBM bytes of one half-sweep launch on a level: b, e_in and e_out
-    (every unknown, complex) per right-hand side plus the level coefficients once."""
-    w = 8 if bits == 32 else 16
-    vec = 3 * level_info["N"] * w * nrhs
-    ncell = int(np.prod(level_info["n"]))
-    coef = (4 * ncell * (4 if bits == 32 else 8)) if fine else None
+def level_bytes(info, bits, nrhs, fine, dim):
+    """Algorithmic HBM bytes of one half-sweep launch on a level: b and e_in read,
+    e_out written (every unknown, complex, per right-hand side) plus the level's
+    operator coefficients read once (finest: mu, 1/(lambda+mu), rho, gamma per
+    cell; coarser: the stored Galerkin stencil)."""
+    es = 4 if bits == 32 else 8
+    vec = 3 * info["N"] * 2 * es * nrhs
+    ncell = int(np.prod(info["n"][:dim]))
+    if fine:
+        coef = 4 * ncell * es
+    else:
+        nuu, nup = (8, 6) if dim == 2 else (38, 18)
+        coef = (sum(info["counts"][:dim]) * (2 * nuu + nup) + ncell) * es
     return vec + coef
 
 
@@ -94,32 +100,47 @@ def run_gpu(w, steps, warmup, tol):
     return total, results, B, X
 
 
-def kernel_roofline(w, reps=50):
-    """Average duration of the finest-level half-sweep (HIP events on the stream
-    the library launches on) and its algorithmic bytes."""
+def kernel_roofline(w, reps=30):
+    """The dominant kernel is the red-black Vanka half-sweep.  Every level's
+    half-sweep is timed with HIP events on the stream the library launches on,
+    and the levels are weighted by their launch count in one cycle (V: 4 per
+    level; W: 4 * 2^l on level l)."""
     import torch
     from paper_1806_11277_amd import ehh
     S = ehh.solver_for_workload(w)
     nrhs = len(w.sources())
-    info = S.level_info(0, 0)
     dt = torch.float32 if w.precond_bits == 32 else torch.float64
-    b = torch.randn((nrhs, 2 * info["N"]), dtype=dt, device="cuda")
-    e_in = torch.randn_like(b)
-    e_out = torch.zeros_like(b)
-    for _ in range(5):
-        S.level_relax(0, 0, 0, b, e_in, e_out)
     stream = torch.cuda.current_stream()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(reps):
-        S.level_relax(0, 0, 0, b, e_in, e_out)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    avg_s = ev0.elapsed_time(ev1) / reps / 1e3
-    nbytes = relax_bytes_per_launch(S, info, w.precond_bits, nrhs)
+    rows = []
+    tot_b = tot_t = 0.0
+    for l in range(w.levels - 1):
+        info = S.level_info(0, l)
+        b = torch.randn((nrhs, 2 * info["N"]), dtype=dt, device="cuda")
+        e_in = torch.randn_like(b)
+        e_out = torch.zeros_like(b)
+        for _ in range(3):
+            S.level_relax(0, l, 0, b, e_in, e_out)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(reps):
+            S.level_relax(0, l, 0, b, e_in, e_out)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        t = ev0.elapsed_time(ev1) / reps / 1e3
+        nb = level_bytes(info, w.precond_bits, nrhs, l == 0, w.dim)
+        launches = 4 * (2 ** l if w.cycle == 2 else 1)
+        rows.append(dict(level=l, n=info["n"][:w.dim], bytes=nb, us=t * 1e6, gbs=nb / t / 1e9,
+                         launches_per_cycle=launches))
+        tot_b += launches * nb
+        tot_t += launches * t
+        del b, e_in, e_out
     S.close()
-    return avg_s, nbytes
+    achieved = tot_b / tot_t / 1e9
+    return dict(bound="hbm", kernel="k_relax_plan (red-black Vanka half-sweep, all levels, "
+                                    "launch-weighted)",
+                achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s", frac=achieved / PEAK_HBM_GBS,
+                traffic=None, bytes_per_cycle=tot_b, us_per_cycle=tot_t * 1e6, levels=rows)
 
 
 def cpu_baseline(w, gpu_iters, budget_s=20.0):
@@ -168,6 +189,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--batched", default="c3_hetero512_batch32_fp32",
+                    help="batched companion workload reported in the same line ('' to skip)")
+    ap.add_argument("--batched-steps", type=int, default=2)
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the solver runs all subdomains and right-hand sides "
@@ -205,12 +229,23 @@ def main():
         "status": res[-1][2],
     }
     if not a.no_roofline:
-        avg_s, nbytes = kernel_roofline(w)
-        achieved = nbytes / avg_s / 1e9
-        out["roofline"] = {"bound": "hbm", "kernel": "k_relax (finest level, one colour)",
-                           "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                           "frac": achieved / PEAK_HBM_GBS, "traffic": None,
-                           "bytes_per_launch": nbytes, "avg_launch_us": avg_s * 1e6}
+        print("[bench] roofline of the dominant kernel", file=sys.stderr, flush=True)
+        out["roofline"] = kernel_roofline(w)
+    if a.batched:
+        wb = get_config(a.batched)
+        print(f"[bench] batched companion {wb.name}", file=sys.stderr, flush=True)
+        tb, rb, Bb, _ = run_gpu(wb, a.batched_steps, 1, a.tol)
+        sb = rb[-1][3]
+        itb = [s_["iters"] for s_ in sb]
+        vb = len(sb) * a.batched_steps / tb
+        out["batched"] = {"workload": wb.name, "nrhs": len(sb), "value": vb, "unit": "solves/s",
+                          "ms_per_step": 1e3 * tb / a.batched_steps,
+                          "dtype": "f32 cycle + f64 Krylov/coarsest",
+                          "iters_min_max": [min(itb), max(itb)],
+                          "rel_res_true_max": max(s_["rel_res_true"] for s_ in sb),
+                          "speedup_vs_plain_fp64_single_source": vb / out["value"]}
+        if not a.no_roofline:
+            out["batched"]["roofline"] = kernel_roofline(wb)
     if not a.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, int(np.median(iters)))

@@ -338,8 +338,6 @@ template <typename T> int32_t precondition_t(ehh_ctx* c, const double* v, double
     // Algorithm 2: colours in turn, each from the residual of the unshifted operator
     int ncol = 0;
     for (const Sub& S : c->subs) ncol = std::max(ncol, S.colour + 1);
-    const Level& L0 = c->subs[0].lev[0];
-    (void)L0;
     LevelDesc<double> A{};
     A.g = gg;
     A.fine = true;
@@ -347,15 +345,19 @@ template <typename T> int32_t precondition_t(ehh_ctx* c, const double* v, double
     A.f = FineCoef<double>{c->fine64, c->fine64 + n, c->fine64 + 2 * n, c->fine64 + 3 * n,
                            c->omega_nd * c->omega_nd, 0.0};
     for (int col = 0; col < ncol; ++col) {
-        const double* src = v;
-        if (col > 0) {
-            HIPCHK(launch_apply<double>(A, z, v, c->R, nrhs, s));   // R = v - A z
-            src = c->R;
+        // every subdomain of the colour takes its residual before any of them
+        // adds its correction (the subdomains of one colour are handled together)
+        for (Sub& S : c->subs) {
+            if (S.colour != col) continue;
+            const SubMap m = submap(c, S);
+            if (col == 0)   // z = 0: the local residual is v itself
+                HIPCHK(launch_dd_gather<T>(gg, S.lev[0].g, m, v, (T*)S.r0, nrhs, s));
+            else            // local residual of the unshifted operator on the extent only
+                HIPCHK(launch_dd_gather_res<T>(gg, S.lev[0].g, m, A.f, v, z, (T*)S.r0, nrhs, s));
         }
         for (Sub& S : c->subs) {
             if (S.colour != col) continue;
             const SubMap m = submap(c, S);
-            HIPCHK(launch_dd_gather<T>(gg, S.lev[0].g, m, src, (T*)S.r0, nrhs, s));
             CHK(cycle<T>(c, S, 0, (const T*)S.r0, (T*)S.e0, true, nrhs, s));
             HIPCHK(launch_dd_scatter<T>(gg, S.lev[0].g, m, (const T*)S.e0, z, nrhs, 0, s));
         }
@@ -365,7 +367,6 @@ template <typename T> int32_t precondition_t(ehh_ctx* c, const double* v, double
 
 int32_t precondition_any(ehh_ctx* c, const double* v, double* z, int nrhs, hipStream_t s) {
     CHK(ensure_ws(c, nrhs));
-    if (c->dd && c->opt.dd_colors != 1) CHK(ensure_krylov(c, nrhs));
     return c->bits() == 32 ? precondition_t<float>(c, v, z, nrhs, s) : precondition_t<double>(c, v, z, nrhs, s);
 }
 

@@ -5,6 +5,7 @@
 // correction back to the global vector, either averaged over the subdomains
 // that own an unknown (one colour) or added unweighted (Algorithm 2).
 #include "internal.hpp"
+#include "ops.hpp"
 
 namespace ehh {
 
@@ -98,5 +99,51 @@ template hipError_t launch_dd_scatter<float>(const Geo&, const Geo&, const SubMa
                                              hipStream_t);
 template hipError_t launch_dd_scatter<double>(const Geo&, const Geo&, const SubMap&, const double*, double*, int,
                                               int, hipStream_t);
+
+// Algorithm 2, step 1: the local residual r_i = q_i - (A u)_{Omega_i} of the
+// global (unshifted) operator, evaluated only at the unknowns of the
+// subdomain's extent and written straight into its padded local vector.
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_dd_gather_res(Geo gg, Geo gl, SubMap m, FineCoef<double> A,
+                                                       const double* __restrict__ v, const double* __restrict__ z,
+                                                       T* __restrict__ out, int nrhs) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= gl.N) return;
+    int k, cnt;
+    const int64_t gi = local_to_global<D>(gg, gl, m, t, k, &cnt);
+    int p[3] = {0, 0, 0};
+    if (gi >= 0) {
+        if (k == 3) cell_pos<D>(gg, gi - gg.off[3], p);
+        else face_pos<D>(gg, k, gi - gg.off[k], p);
+    }
+    const FineOp<D, double> op{gg, A};
+    for (int r = 0; r < nrhs; ++r) {
+        T* o = out + (int64_t)r * 2 * gl.N;
+        if (gi < 0) {
+            o[t] = T(0);
+            o[gl.N + t] = T(0);
+            continue;
+        }
+        const CVec<double> zv{z + (int64_t)r * 2 * gg.N, gg.N};
+        const double* vv = v + (int64_t)r * 2 * gg.N;
+        const cx<double> az = k == 3 ? op.row_p(p, zv) : op.row_u(k, p, zv);
+        o[t] = (T)(vv[gi] - az.re);
+        o[gl.N + t] = (T)(vv[gg.N + gi] - az.im);
+    }
+}
+
+template <typename T>
+hipError_t launch_dd_gather_res(const Geo& gg, const Geo& gl, const SubMap& m, const FineCoef<double>& A,
+                                const double* v, const double* z, T* out, int nrhs, hipStream_t s) {
+    if (gg.dim == 2)
+        hipLaunchKernelGGL((k_dd_gather_res<2, T>), nblk(gl.N), 256, 0, s, gg, gl, m, A, v, z, out, nrhs);
+    else
+        hipLaunchKernelGGL((k_dd_gather_res<3, T>), nblk(gl.N), 256, 0, s, gg, gl, m, A, v, z, out, nrhs);
+    return hipGetLastError();
+}
+template hipError_t launch_dd_gather_res<float>(const Geo&, const Geo&, const SubMap&, const FineCoef<double>&,
+                                                const double*, const double*, float*, int, hipStream_t);
+template hipError_t launch_dd_gather_res<double>(const Geo&, const Geo&, const SubMap&, const FineCoef<double>&,
+                                                 const double*, const double*, double*, int, hipStream_t);
 
 }  // namespace ehh

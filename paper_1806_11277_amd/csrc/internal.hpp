@@ -77,6 +77,9 @@ template <typename T>
 hipError_t launch_dd_gather(const Geo& gg, const Geo& gl, const SubMap& m, const double* v, T* out, int nrhs,
                             hipStream_t s);
 template <typename T>
+hipError_t launch_dd_gather_res(const Geo& gg, const Geo& gl, const SubMap& m, const FineCoef<double>& A,
+                                const double* v, const double* z, T* out, int nrhs, hipStream_t s);
+template <typename T>
 hipError_t launch_dd_scatter(const Geo& gg, const Geo& gl, const SubMap& m, const T* e, double* z, int nrhs,
                              int weighted, hipStream_t s);
 

@@ -14,7 +14,15 @@ namespace ehh {
 // coarse levels are not bound by the latency of one long serial row loop.
 template <int D, typename T, class Op>
 __global__ __launch_bounds__(256) void k_apply(Op op, const T* __restrict__ x, const T* __restrict__ b,
-                                               T* __restrict__ y, int nrhs, int64_t stride) {
+                                               T* __restrict__ y, int nrhs, int64_t stride, int rpb) {
+    // right-hand sides [blockIdx.y * rpb, ...) of this grid row
+    {
+        const int rb0 = blockIdx.y * rpb;
+        x += rb0 * stride;
+        if (b) b += rb0 * stride;
+        y += rb0 * stride;
+        nrhs = nrhs - rb0 < rpb ? nrhs - rb0 : rpb;
+    }
     const Geo& g = op.g;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= g.N) return;
@@ -24,106 +32,22 @@ __global__ __launch_bounds__(256) void k_apply(Op op, const T* __restrict__ x, c
     int p[3];
     if (k == 3) cell_pos<D>(g, li, p);
     else face_pos<D>(g, k, li, p);
-    for (int r = 0; r < nrhs; ++r) {
-        const CVec<T> xv{x + r * stride, g.N};
-        cx<T> v = k == 3 ? op.row_p(p, xv) : op.row_u(k, p, xv);
-        if (b) v = CVec<T>{b + r * stride, g.N}.ld(t) - v;
-        Vec<T>{y + r * stride, g.N}.st(t, v);
-    }
-}
-
-// ------------------------------------------- red-black Vanka half-sweep, finest level
-// One thread per pair of cells along x: the cell of the swept colour is relaxed
-// (its 2D+1 unknowns: both faces of every component and the pressure), the other
-// cell only has its pressure carried over.  Every face belongs to exactly one cell
-// of each colour, so the pairs together write each unknown once.  The residual of
-// the cell's unknowns is taken from e_in (the state at the start of the
-// half-sweep); the update e_out = e_in + w B_K^{-1} r_K uses the closed form of
-// the block: one 2x2 complex system per displacement component (diagonal only in
-// the economic variant) and the scalar Schur complement on the pressure.
-template <int D, typename T, class Op>
-__global__ __launch_bounds__(256) void k_relax_pair(Op op, int colour, T w, int econ,
-                                               const T* __restrict__ b, const T* __restrict__ ein,
-                                               T* __restrict__ eout, int nrhs, int64_t stride) {
-    const Geo& g = op.g;
-    const int hp = g.n[0] >> 1;
-    const int64_t npair = (int64_t)hp * g.n[1] * g.n[2];
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= npair) return;
-    const int px = (int)(t % hp);
-    const int64_t rest = t / hp;
-    const int yy = (int)(rest % g.n[1]);
-    const int zz = (int)(rest / g.n[1]);
-    const int par = (colour + yy + zz) & 1;
-    int cr[3] = {2 * px + par, yy, zz};
-    int cb[3] = {2 * px + 1 - par, yy, zz};
-
-    cx<T> i00[D], i01[D], i11[D], zlo[D], zhi[D];
-    T glo[D], ghi[D];
-    bool lok[D], hok[D];
-    int64_t ilo[D], ihi[D];
-    cx<T> S = mk<T>(op.pdiag(cr), T(0));
+    constexpr int RB = sizeof(T) == 4 ? 4 : 2;
+    for (int r0 = 0; r0 < nrhs; r0 += RB) {
+        CVec<T> xv[RB];
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-        lok[k] = cr[k] >= 1;
-        hok[k] = cr[k] + 1 <= g.n[k] - 1;
-        cx<T> all, ahh, alh;
-        op.block(cr, k, all, ahh, alh, glo[k], ghi[k], lok[k], hok[k]);
-        if (econ) alh = mk<T>(T(0), T(0));
-        const cx<T> idet = cinv(all * ahh - alh * alh);
-        i00[k] = ahh * idet;
-        i11[k] = all * idet;
-        i01[k] = mk<T>(T(0), T(0)) - alh * idet;
-        zlo[k] = glo[k] * i00[k] + ghi[k] * i01[k];
-        zhi[k] = glo[k] * i01[k] + ghi[k] * i11[k];
-        S = S - (glo[k] * zlo[k] + ghi[k] * zhi[k]);
-        int q[3] = {cr[0], cr[1], cr[2]};
-        ilo[k] = lok[k] ? g.off[k] + face_idx<D>(g, k, q) : 0;
-        q[k] += 1;
-        ihi[k] = hok[k] ? g.off[k] + face_idx<D>(g, k, q) : 0;
-    }
-    const cx<T> iS = cinv(S);
-    const int64_t ipr = g.off[3] + cell_idx<D>(g, cr);
-    const int64_t ipb = g.off[3] + cell_idx<D>(g, cb);
-    const cx<T> zero = mk<T>(T(0), T(0));
-
-    for (int r = 0; r < nrhs; ++r) {
-        const CVec<T> bv{b + r * stride, g.N};
-        const Vec<T> ov{eout + r * stride, g.N};
-        const CVec<T> ev{ein ? ein + r * stride : nullptr, g.N};
-        cx<T> rlo[D], rhi[D];
+        for (int q = 0; q < RB; ++q) xv[q] = CVec<T>{x + (r0 + q < nrhs ? r0 + q : r0) * stride, g.N};
+        cx<T> v[RB];
+        if (k == 3) op.template row_p_rb<RB>(p, xv, v);
+        else op.template row_u_rb<RB>(k, p, xv, v);
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-            int q[3] = {cr[0], cr[1], cr[2]};
-            rlo[k] = zero;
-            rhi[k] = zero;
-            if (lok[k]) rlo[k] = ein ? bv.ld(ilo[k]) - op.row_u(k, q, ev) : bv.ld(ilo[k]);
-            q[k] += 1;
-            if (hok[k]) rhi[k] = ein ? bv.ld(ihi[k]) - op.row_u(k, q, ev) : bv.ld(ihi[k]);
+        for (int q = 0; q < RB; ++q) {
+            const int r = r0 + q;
+            if (r >= nrhs) break;
+            cx<T> o = v[q];
+            if (b) o = CVec<T>{b + r * stride, g.N}.ld(t) - o;
+            Vec<T>{y + r * stride, g.N}.st(t, o);
         }
-        const cx<T> rp = ein ? bv.ld(ipr) - op.row_p(cr, ev) : bv.ld(ipr);
-        cx<T> ylo[D], yhi[D];
-        cx<T> acc = rp;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            ylo[k] = i00[k] * rlo[k] + i01[k] * rhi[k];
-            yhi[k] = i01[k] * rlo[k] + i11[k] * rhi[k];
-            acc = acc - (glo[k] * ylo[k] + ghi[k] * yhi[k]);
-        }
-        const cx<T> dp = acc * iS;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            if (lok[k]) {
-                const cx<T> d = ylo[k] - zlo[k] * dp;
-                ov.st(ilo[k], (ein ? ev.ld(ilo[k]) : zero) + w * d);
-            }
-            if (hok[k]) {
-                const cx<T> d = yhi[k] - zhi[k] * dp;
-                ov.st(ihi[k], (ein ? ev.ld(ihi[k]) : zero) + w * d);
-            }
-        }
-        ov.st(ipr, (ein ? ev.ld(ipr) : zero) + w * dp);
-        ov.st(ipb, ein ? ev.ld(ipb) : zero);
     }
 }
 
@@ -141,7 +65,14 @@ __global__ __launch_bounds__(256) void k_relax_pair(Op op, int colour, T w, int 
 template <int D, typename T, class Op>
 __global__ __launch_bounds__(256) void k_relax(Op op, int colour, T w, int econ,
                                                const T* __restrict__ b, const T* __restrict__ ein,
-                                               T* __restrict__ eout, int nrhs, int64_t stride) {
+                                               T* __restrict__ eout, int nrhs, int64_t stride, int rpb) {
+    {
+        const int rb0 = blockIdx.y * rpb;
+        b += rb0 * stride;
+        if (ein) ein += rb0 * stride;
+        eout += rb0 * stride;
+        nrhs = nrhs - rb0 < rpb ? nrhs - rb0 : rpb;
+    }
     constexpr int R = 2 * D + 1;
     const Geo& g = op.g;
     const int hp = g.n[0] >> 1;
@@ -195,15 +126,33 @@ __global__ __launch_bounds__(256) void k_relax(Op op, int colour, T w, int econ,
         iS = cinv(S);
     }
 
-    for (int r = 0; r < nrhs; ++r) {
-        const CVec<T> bv{b + r * stride, g.N};
+    constexpr int RB = sizeof(T) == 4 ? 4 : 2;
+    for (int r0 = 0; r0 < nrhs; r0 += RB) {
+    cx<T> resb[RB];
+    {
+        CVec<T> evb[RB];
+#pragma unroll
+        for (int q = 0; q < RB; ++q)
+            evb[q] = CVec<T>{ein ? ein + (r0 + q < nrhs ? r0 + q : r0) * stride : nullptr, g.N};
+#pragma unroll
+        for (int q = 0; q < RB; ++q) resb[q] = mk<T>(T(0), T(0));
+        if (ok && ein) {
+            if (k == 3) op.template row_p_rb<RB>(p, evb, resb);
+            else op.template row_u_rb<RB>(k, p, evb, resb);
+        }
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const int r = r0 + q < nrhs ? r0 + q : r0;
+            resb[q] = ok ? CVec<T>{b + r * stride, g.N}.ld(idx) - resb[q] : mk<T>(T(0), T(0));
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+        const int r = r0 + q;
+        if (r >= nrhs) break;
         const CVec<T> ev{ein ? ein + r * stride : nullptr, g.N};
         const Vec<T> ov{eout + r * stride, g.N};
-        cx<T> res = mk<T>(T(0), T(0));
-        if (ok) {
-            res = bv.ld(idx);
-            if (ein) res = res - (k == 3 ? op.row_p(p, ev) : op.row_u(k, p, ev));
-        }
+        const cx<T> res = resb[q];
         // gather the block residual in the lane of row 0
         cx<T> rr[R];
 #pragma unroll
@@ -240,6 +189,7 @@ __global__ __launch_bounds__(256) void k_relax(Op op, int colour, T w, int econ,
         if (ok) ov.st(idx, (ein ? ev.ld(idx) : mk<T>(T(0), T(0))) + w * mine);
         if (carry) ov.st(ipb, ein ? ev.ld(ipb) : mk<T>(T(0), T(0)));
     }
+    }
 }
 
 // ------------------------------------------------ plan-based apply and half-sweep
@@ -247,7 +197,15 @@ __global__ __launch_bounds__(256) void k_relax(Op op, int colour, T w, int econ,
 // every right-hand side, so a batch streams only the vectors.
 template <int D, typename T, class Op>
 __global__ __launch_bounds__(256) void k_apply_plan(Op op, const T* __restrict__ x, const T* __restrict__ b,
-                                                    T* __restrict__ y, int nrhs, int64_t stride) {
+                                                    T* __restrict__ y, int nrhs, int64_t stride, int rpb) {
+    // right-hand sides [blockIdx.y * rpb, ...) of this grid row
+    {
+        const int rb0 = blockIdx.y * rpb;
+        x += rb0 * stride;
+        if (b) b += rb0 * stride;
+        y += rb0 * stride;
+        nrhs = nrhs - rb0 < rpb ? nrhs - rb0 : rpb;
+    }
     const Geo& g = op.g;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= g.N) return;
@@ -263,7 +221,20 @@ __global__ __launch_bounds__(256) void k_apply_plan(Op op, const T* __restrict__
         face_pos<D>(g, k, li, p);
         op.plan_u(k, p, P);
     }
-    for (int r = 0; r < nrhs; ++r) {
+    // blocks of RB right-hand sides keep RB independent load streams in flight
+    constexpr int RB = sizeof(T) == 4 ? 4 : 2;
+    int r = 0;
+    for (; r + RB <= nrhs; r += RB) {
+        cx<T> v[RB];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) v[q] = P.dot(CVec<T>{x + (r + q) * stride, g.N});
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            if (b) v[q] = CVec<T>{b + (r + q) * stride, g.N}.ld(t) - v[q];
+            Vec<T>{y + (r + q) * stride, g.N}.st(t, v[q]);
+        }
+    }
+    for (; r < nrhs; ++r) {
         cx<T> v = P.dot(CVec<T>{x + r * stride, g.N});
         if (b) v = CVec<T>{b + r * stride, g.N}.ld(t) - v;
         Vec<T>{y + r * stride, g.N}.st(t, v);
@@ -276,7 +247,14 @@ __global__ __launch_bounds__(256) void k_apply_plan(Op op, const T* __restrict__
 template <int D, typename T, class Op>
 __global__ __launch_bounds__(256) void k_relax_plan(Op op, int colour, T w, int econ,
                                                     const T* __restrict__ b, const T* __restrict__ ein,
-                                                    T* __restrict__ eout, int nrhs, int64_t stride) {
+                                                    T* __restrict__ eout, int nrhs, int64_t stride, int rpb) {
+    {
+        const int rb0 = blockIdx.y * rpb;
+        b += rb0 * stride;
+        if (ein) ein += rb0 * stride;
+        eout += rb0 * stride;
+        nrhs = nrhs - rb0 < rpb ? nrhs - rb0 : rpb;
+    }
     constexpr int R = 2 * D + 1;
     const Geo& g = op.g;
     const int hp = g.n[0] >> 1;
@@ -352,15 +330,26 @@ __global__ __launch_bounds__(256) void k_relax_plan(Op op, int colour, T w, int 
     }
     const cx<T> iS = row == 0 ? cinv(S) : mk<T>(T(0), T(0));
 
-    for (int r = 0; r < nrhs; ++r) {
-        const CVec<T> bv{b + r * stride, g.N};
+    constexpr int RB = sizeof(T) == 4 ? 4 : 2;
+    for (int r0 = 0; r0 < nrhs; r0 += RB) {
+    // residual rows of a block of right-hand sides (independent load streams)
+    cx<T> resb[RB];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+        resb[q] = mk<T>(T(0), T(0));
+        const int r = r0 + q;
+        if (ok && r < nrhs) {
+            resb[q] = CVec<T>{b + r * stride, g.N}.ld(idx);
+            if (ein) resb[q] = resb[q] - P.dot(CVec<T>{ein + r * stride, g.N});
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+        const int r = r0 + q;
+        if (r >= nrhs) break;
         const CVec<T> ev{ein ? ein + r * stride : nullptr, g.N};
         const Vec<T> ov{eout + r * stride, g.N};
-        cx<T> res = mk<T>(T(0), T(0));
-        if (ok) {
-            res = bv.ld(idx);
-            if (ein) res = res - P.dot(ev);
-        }
+        const cx<T> res = resb[q];
         cx<T> rr[R];
 #pragma unroll
         for (int j = 0; j < R; ++j) {
@@ -395,6 +384,7 @@ __global__ __launch_bounds__(256) void k_relax_plan(Op op, int colour, T w, int 
         if (ok) ov.st(idx, (ein ? ev.ld(idx) : mk<T>(T(0), T(0))) + w * mine);
         if (carry) ov.st(ipb, ein ? ev.ld(ipb) : mk<T>(T(0), T(0)));
     }
+    }
 }
 
 // --------------------------------------------------------------------- transfers
@@ -413,6 +403,10 @@ __global__ __launch_bounds__(256) void k_restrict(Geo gf, Geo gc, const T* __res
     if (k >= D) k = 3;
     const int64_t li = t - gc.off[k];
     const int64_t sf = 2 * gf.N, sc = 2 * gc.N;
+    const int r0 = blockIdx.y;   // one right-hand side per grid row
+    rf += r0 * sf;
+    rc += r0 * sc;
+    nrhs = 1;
     if (k == 3) {
         int C[3];
         cell_pos<D>(gc, li, C);
@@ -475,6 +469,10 @@ __global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const T* __rest
     if (k >= D) k = 3;
     const int64_t li = t - gf.off[k];
     const int64_t sf = 2 * gf.N, sc = 2 * gc.N;
+    const int r0 = blockIdx.y;   // one right-hand side per grid row
+    ef += r0 * sf;
+    ec += r0 * sc;
+    nrhs = 1;
     if (k == 3) {
         int c[3];
         cell_pos<D>(gf, li, c);
@@ -555,20 +553,35 @@ __global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const T* __rest
 // ------------------------------------------------------------------------ launchers
 static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
+// Right-hand sides per grid row: a level whose rows fill fewer than ~2048
+// wavefronts gets its batch split over grid rows (the coefficients of a small
+// level stay in cache, so re-reading them per group costs little).
+static inline int rhs_per_block(int64_t waves, int nrhs, int rb) {
+    const int64_t target = 2048;
+    int64_t groups = waves >= target ? 1 : (target + waves - 1) / waves;
+    const int64_t maxg = (nrhs + rb - 1) / rb;
+    if (groups > maxg) groups = maxg;
+    if (groups < 1) groups = 1;
+    int rpb = (int)((nrhs + groups - 1) / groups);
+    rpb = ((rpb + rb - 1) / rb) * rb;
+    return rpb < 1 ? 1 : rpb;
+}
+
 template <typename T>
 hipError_t launch_apply(const LevelDesc<T>& L, const T* x, const T* b, T* y, int nrhs, hipStream_t s) {
     const int64_t stride = 2 * L.g.N;
-    const unsigned gb = nblk(L.g.N);
+    const int rpb = rhs_per_block((L.g.N + 63) / 64, nrhs, sizeof(T) == 4 ? 4 : 2);
+    const dim3 gb(nblk(L.g.N), (nrhs + rpb - 1) / rpb);
     if (L.g.dim == 2) {
         if (L.fine)
-            hipLaunchKernelGGL((k_apply_plan<2, T, FineOp<2, T>>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, x, b, y, nrhs, stride);
+            hipLaunchKernelGGL((k_apply_plan<2, T, FineOp<2, T>>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, x, b, y, nrhs, stride, rpb);
         else
-            hipLaunchKernelGGL((k_apply_plan<2, T, StOp<2, T>>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, x, b, y, nrhs, stride);
+            hipLaunchKernelGGL((k_apply_plan<2, T, StOp<2, T>>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, x, b, y, nrhs, stride, rpb);
     } else {
         if (L.fine)
-            hipLaunchKernelGGL((k_apply_plan<3, T, FineOp<3, T>>), gb, 256, 0, s, FineOp<3, T>{L.g, L.f}, x, b, y, nrhs, stride);
+            hipLaunchKernelGGL((k_apply_plan<3, T, FineOp<3, T>>), gb, 256, 0, s, FineOp<3, T>{L.g, L.f}, x, b, y, nrhs, stride, rpb);
         else
-            hipLaunchKernelGGL((k_apply<3, T, StOp<3, T>>), gb, 256, 0, s, StOp<3, T>{L.g, L.s}, x, b, y, nrhs, stride);
+            hipLaunchKernelGGL((k_apply<3, T, StOp<3, T>>), gb, 256, 0, s, StOp<3, T>{L.g, L.s}, x, b, y, nrhs, stride, rpb);
     }
     return hipGetLastError();
 }
@@ -578,18 +591,19 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
                         T* eout, int nrhs, hipStream_t s) {
     const int64_t stride = 2 * L.g.N;
     const int64_t npair = (int64_t)(L.g.n[0] / 2) * L.g.n[1] * L.g.n[2];
-    const unsigned gb = nblk(npair * 8);
+    const int rpb = rhs_per_block((npair * 8 + 63) / 64, nrhs, sizeof(T) == 4 ? 4 : 2);
+    const dim3 gb(nblk(npair * 8), (nrhs + rpb - 1) / rpb);
     const T tw = (T)w;
     if (L.g.dim == 2) {
         if (L.fine)
-            hipLaunchKernelGGL((k_relax_plan<2, T, FineOp<2, T>>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride);
+            hipLaunchKernelGGL((k_relax_plan<2, T, FineOp<2, T>>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb);
         else
-            hipLaunchKernelGGL((k_relax_plan<2, T, StOp<2, T>>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride);
+            hipLaunchKernelGGL((k_relax_plan<2, T, StOp<2, T>>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb);
     } else {
         if (L.fine)
-            hipLaunchKernelGGL((k_relax_plan<3, T, FineOp<3, T>>), gb, 256, 0, s, FineOp<3, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride);
+            hipLaunchKernelGGL((k_relax_plan<3, T, FineOp<3, T>>), gb, 256, 0, s, FineOp<3, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb);
         else
-            hipLaunchKernelGGL((k_relax<3, T, StOp<3, T>>), gb, 256, 0, s, StOp<3, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride);
+            hipLaunchKernelGGL((k_relax<3, T, StOp<3, T>>), gb, 256, 0, s, StOp<3, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb);
     }
     return hipGetLastError();
 }
@@ -597,18 +611,18 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
 template <typename T>
 hipError_t launch_restrict(const Geo& gf, const Geo& gc, const T* rf, T* rc, int nrhs, hipStream_t s) {
     if (gf.dim == 2)
-        hipLaunchKernelGGL((k_restrict<2, T>), nblk(gc.N), 256, 0, s, gf, gc, rf, rc, nrhs);
+        hipLaunchKernelGGL((k_restrict<2, T>), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc, nrhs);
     else
-        hipLaunchKernelGGL((k_restrict<3, T>), nblk(gc.N), 256, 0, s, gf, gc, rf, rc, nrhs);
+        hipLaunchKernelGGL((k_restrict<3, T>), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc, nrhs);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_prolong(const Geo& gf, const Geo& gc, const T* ec, T* ef, int nrhs, hipStream_t s) {
     if (gf.dim == 2)
-        hipLaunchKernelGGL((k_prolong<2, T>), nblk(gf.N), 256, 0, s, gf, gc, ec, ef, nrhs);
+        hipLaunchKernelGGL((k_prolong<2, T>), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef, nrhs);
     else
-        hipLaunchKernelGGL((k_prolong<3, T>), nblk(gf.N), 256, 0, s, gf, gc, ec, ef, nrhs);
+        hipLaunchKernelGGL((k_prolong<3, T>), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef, nrhs);
     return hipGetLastError();
 }
 

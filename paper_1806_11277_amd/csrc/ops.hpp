@@ -276,6 +276,70 @@ template <int D, typename T> struct StOp {
     }
 
 
+    // Rows for a block of RB right-hand sides: each coefficient is read once and
+    // applied to all RB vectors (used where a whole row plan does not fit in
+    // registers, i.e. the 3D Galerkin levels).
+    template <int RB>
+    EHH_DEV void row_u_rb(int k, const int* p, const CVec<T>* ev, cx<T>* out) const {
+        constexpr int CF = St<D>::CF;
+        const int t1 = tang1<D>(k), t2 = tang2<D>(k);
+        const int64_t fi = face_idx<D>(g, k, p);
+#pragma unroll
+        for (int q = 0; q < RB; ++q) out[q] = mk<T>(T(0), T(0));
+        for (int F = 0; F < St<D>::NF; ++F) {
+            int dn, d1, d2;
+            full_offset<D>(F, dn, d1, d2);
+            int q3[3] = {p[0], p[1], p[2]};
+            q3[k] += dn;
+            q3[t1] += d1;
+            if (D == 3) q3[t2] += d2;
+            const bool ok = face_ok<D>(g, k, q3);
+            const int64_t qi = ok ? face_idx<D>(g, k, q3) : fi;
+            const cx<T> a0 = F >= CF ? uu(k, fi, F - CF) : uu(k, qi, CF - F);
+            const cx<T> a = ok ? a0 : mk<T>(T(0), T(0));
+            const int64_t ix = g.off[k] + qi;
+#pragma unroll
+            for (int q = 0; q < RB; ++q) out[q] = out[q] + a * ev[q].ld(ix);
+        }
+        const int64_t pc = g.off[3] + cell_idx<D>(g, p);
+        for (int qq = 0; qq < St<D>::NUP; ++qq) {
+            int side, e1, e2;
+            up_decode<D>(qq, side, e1, e2);
+            int q3[3] = {p[0], p[1], p[2]};
+            q3[k] += side - 1;
+            q3[t1] += e1;
+            if (D == 3) q3[t2] += e2;
+            const bool ok = cell_ok<D>(g, q3);
+            const int64_t ci = ok ? g.off[3] + cell_idx<D>(g, q3) : pc;
+            const T c0 = ok ? up(k, fi, qq) : T(0);
+#pragma unroll
+            for (int q = 0; q < RB; ++q) out[q] = out[q] + c0 * ev[q].ld(ci);
+        }
+    }
+    template <int RB>
+    EHH_DEV void row_p_rb(const int* cc, const CVec<T>* ev, cx<T>* out) const {
+        const int64_t ic = cell_idx<D>(g, cc);
+        const T d = c.pp[ic];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) out[q] = d * ev[q].ld(g.off[3] + ic);
+        for (int k = 0; k < D; ++k) {
+            const int t1 = tang1<D>(k), t2 = tang2<D>(k);
+            for (int qq = 0; qq < St<D>::NUP; ++qq) {
+                int side, e1, e2;
+                up_decode<D>(qq, side, e1, e2);
+                int q3[3] = {cc[0], cc[1], cc[2]};
+                q3[k] += 1 - side;
+                q3[t1] -= e1;
+                if (D == 3) q3[t2] -= e2;
+                const bool ok = face_ok<D>(g, k, q3);
+                const int64_t qi = ok ? face_idx<D>(g, k, q3) : 0;
+                const T cf = ok ? up(k, qi, qq) : T(0);
+#pragma unroll
+                for (int q = 0; q < RB; ++q) out[q] = out[q] + cf * ev[q].ld(g.off[k] + qi);
+            }
+        }
+    }
+
     // Row plans (used for D == 2, where a whole row fits in registers): u row =
     // the NF u-u offsets in full-offset order, then the NUP u-p entries; p row =
     // the pressure itself, then the u-p entries of the faces around the cell.

@@ -530,46 +530,52 @@ hipError_t launch_dense_invert(double* dense, int64_t n, int batch, double* work
 }
 
 // ------------------------------------------------------------------ coarse apply
-// One 64-wide wavefront per row: lanes stride over the columns, FP64
-// accumulation, a batch of up to 8 right-hand sides per pass over the row.
+// One 64-wide wavefront per (row, group of up to 4 right-hand sides): lanes stride
+// over the columns with FP64 accumulation and a butterfly reduction.  The grid
+// spans rows x right-hand-side groups so that a batch fills the chip.
 template <typename T>
 __global__ __launch_bounds__(256) void k_coarse_apply(const double* __restrict__ inv, int64_t n, const T* __restrict__ r,
                                                       T* __restrict__ e, int nrhs) {
+    constexpr int RG = 4;
     const int lane = threadIdx.x & 63;
     const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (row >= n) return;
+    const int r0 = blockIdx.y * RG;
+    const int nr = nrhs - r0 < RG ? nrhs - r0 : RG;
     const double* R = inv + 2 * row * n;
-    for (int r0 = 0; r0 < nrhs; r0 += 8) {
-        const int nr = nrhs - r0 < 8 ? nrhs - r0 : 8;
-        double ar[8], ai[8];
-        for (int q = 0; q < 8; ++q) ar[q] = ai[q] = 0.0;
-        for (int64_t j = lane; j < n; j += 64) {
-            const double mr = R[2 * j], mi = R[2 * j + 1];
-            for (int q = 0; q < nr; ++q) {
+    double ar[RG], ai[RG];
+#pragma unroll
+    for (int q = 0; q < RG; ++q) ar[q] = ai[q] = 0.0;
+    for (int64_t j = lane; j < n; j += 64) {
+        const double mr = R[2 * j], mi = R[2 * j + 1];
+#pragma unroll
+        for (int q = 0; q < RG; ++q) {
+            if (q < nr) {
                 const T* rv = r + (int64_t)(r0 + q) * 2 * n;
                 const double vr = (double)rv[j], vi = (double)rv[n + j];
                 ar[q] += mr * vr - mi * vi;
                 ai[q] += mr * vi + mi * vr;
             }
         }
-        for (int q = 0; q < nr; ++q) {
-            double sr = ar[q], si = ai[q];
-            for (int o = 32; o > 0; o >>= 1) {
-                sr += __shfl_xor(sr, o, 64);
-                si += __shfl_xor(si, o, 64);
-            }
-            if (lane == 0) {
-                T* ev = e + (int64_t)(r0 + q) * 2 * n;
-                ev[row] = (T)sr;
-                ev[n + row] = (T)si;
-            }
+    }
+#pragma unroll
+    for (int q = 0; q < RG; ++q) {
+        double sr = ar[q], si = ai[q];
+        for (int o = 32; o > 0; o >>= 1) {
+            sr += __shfl_xor(sr, o, 64);
+            si += __shfl_xor(si, o, 64);
+        }
+        if (lane == 0 && q < nr) {
+            T* ev = e + (int64_t)(r0 + q) * 2 * n;
+            ev[row] = (T)sr;
+            ev[n + row] = (T)si;
         }
     }
 }
 
 template <typename T>
 hipError_t launch_coarse_apply(const double* inv, int64_t n, const T* r, T* e, int nrhs, hipStream_t s) {
-    hipLaunchKernelGGL((k_coarse_apply<T>), nblk(n * 64), 256, 0, s, inv, n, r, e, nrhs);
+    hipLaunchKernelGGL((k_coarse_apply<T>), dim3(nblk(n * 64), (nrhs + 3) / 4), 256, 0, s, inv, n, r, e, nrhs);
     return hipGetLastError();
 }
 template hipError_t launch_coarse_apply<float>(const double*, int64_t, const float*, float*, int, hipStream_t);

@@ -159,3 +159,25 @@ def test_graph_replay_matches_eager_launches():
     os.environ.pop("EHH_GRAPHS", None)
     assert np.array_equal(xs[0], xs[1]) and np.array_equal(xs[1], xs[2])
     S.close()
+
+
+@pytest.mark.parametrize("colors", [0, 1])
+def test_dd_2d_several_subdomains_per_colour(colors):
+    """4 x 2 subdomains: with the multicolour schedule two subdomains share each
+    colour and must both start from the residual before that colour's corrections."""
+    import torch
+    w = small_hetero((64, 32), "dd2d", levels=2, damping=(0.75,), dd_parts=(4, 2, 1),
+                     dd_overlap=4, dd_pad=4, dd_colors=colors, precond_bits=64)
+    say(f"[dd 2d 4x2 colors={colors}]")
+    pb = oracle_problem(w)
+    P = oracle_dd(w, pb)
+    S = _solver(w)
+    v = rand_cvec(pb.size, 2, 61)
+    z = torch.zeros_like(to_dev(v))
+    S.precondition(to_dev(v), z)
+    torch.cuda.synchronize()
+    got = from_dev(z)
+    for r in range(2):
+        ref = P.apply(v[r])
+        assert np.linalg.norm(got[r] - ref) <= 1e-11 * np.linalg.norm(ref)
+    S.close()

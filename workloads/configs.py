@@ -150,10 +150,11 @@ _add(Workload(
     name="c4_layered128_dd8_batch16_fp32",
     description="3D 128^3 layered (8 layers, Vp 1500-4500, 5% perturbation, Poisson 0.30-0.45), "
                 "h=10 m, 8 cells per minimum shear wavelength, 12-cell layer, 2x2x2 overlapping "
-                "subdomains (overlap 4, padding 6), 16 sources, complex64 DD-MG preconditioner",
+                "subdomains (overlap 4, padding 6, multicolour schedule), 16 sources, shift 0.6, "
+                "complex64 DD-MG V(1,1) preconditioner",
     dim=3, n=(128, 128, 128), h=10.0, media_fn=lambda: M.layered_3d_media((128, 128, 128)),
-    ppw=8.0, abl_cells=(12, 12, 12), shift=0.4, levels=4, damping=(0.5, 0.5, 0.2),
-    precond_bits=32, dd_parts=(2, 2, 2), dd_overlap=4, dd_pad=6, dd_colors=1,
+    ppw=8.0, abl_cells=(12, 12, 12), shift=0.6, levels=4, damping=(0.5, 0.5, 0.2),
+    precond_bits=32, dd_parts=(2, 2, 2), dd_overlap=4, dd_pad=6, dd_colors=0, maxit=500,
     sources_fn=_src_lattice(4, 32, 16, 5, seed=7)))
 
 # Reduced-size relatives used where the oracle has to factorise the full operator.
