@@ -192,6 +192,8 @@ def main():
     ap.add_argument("--batched", default="c3_hetero512_batch32_fp32",
                     help="batched companion workload reported in the same line ('' to skip)")
     ap.add_argument("--batched-steps", type=int, default=2)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for traffic counters)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the solver runs all subdomains and right-hand sides "
@@ -199,6 +201,13 @@ def main():
         sys.exit(2)
     import torch
     from workloads import get_config
+    if a.calibrate_copy:
+        src = torch.ones(256 * 2 ** 20 // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = get_config(a.config)
     print(f"[bench] {w.name}: n={w.n} nrhs={len(w.sources())} levels={w.levels} cycle={w.cycle} "
           f"bits={w.precond_bits}", file=sys.stderr, flush=True)

@@ -4,6 +4,8 @@
 // Every kernel loops over the right-hand sides inside the thread so that the
 // operator coefficients (and the Vanka block factorisation) are read and
 // formed once per cell for the whole batch.
+#include <cstdlib>
+
 #include "internal.hpp"
 #include "ops.hpp"
 
@@ -12,7 +14,7 @@ namespace ehh {
 // --------------------------------------------------------------- y = A x, r = b - A x
 // One thread per unknown (row): short independent load chains, so that small
 // coarse levels are not bound by the latency of one long serial row loop.
-template <int D, typename T, class Op>
+template <int D, typename T, class Op, int RB>
 __global__ __launch_bounds__(256) void k_apply(Op op, const T* __restrict__ x, const T* __restrict__ b,
                                                T* __restrict__ y, int nrhs, int64_t stride, int rpb) {
     // right-hand sides [blockIdx.y * rpb, ...) of this grid row
@@ -32,7 +34,6 @@ __global__ __launch_bounds__(256) void k_apply(Op op, const T* __restrict__ x, c
     int p[3];
     if (k == 3) cell_pos<D>(g, li, p);
     else face_pos<D>(g, k, li, p);
-    constexpr int RB = sizeof(T) == 4 ? 4 : 2;
     for (int r0 = 0; r0 < nrhs; r0 += RB) {
         CVec<T> xv[RB];
 #pragma unroll
@@ -62,7 +63,7 @@ __global__ __launch_bounds__(256) void k_apply(Op op, const T* __restrict__ x, c
 // every face belongs to exactly one of them, so e_out is written once per
 // unknown; the residual is taken from e_in (the state at the start of the
 // half-sweep).
-template <int D, typename T, class Op>
+template <int D, typename T, class Op, int RB>
 __global__ __launch_bounds__(256) void k_relax(Op op, int colour, T w, int econ,
                                                const T* __restrict__ b, const T* __restrict__ ein,
                                                T* __restrict__ eout, int nrhs, int64_t stride, int rpb) {
@@ -77,11 +78,13 @@ __global__ __launch_bounds__(256) void k_relax(Op op, int colour, T w, int econ,
     const Geo& g = op.g;
     const int hp = g.n[0] >> 1;
     const int64_t npair = (int64_t)hp * g.n[1] * g.n[2];
-    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t t = gt >> 3;            // pair (red cell) index
-    const int row = (int)(gt & 7);
+    // lane = 8 * row + cell: the eight cells of a wavefront are consecutive, so a
+    // load of one row term by the eight lanes of a row touches neighbouring cells
     const int lane = threadIdx.x & 63;
-    const int base = lane & ~7;
+    const int row = lane >> 3;
+    const int cig = lane & 7;
+    const int64_t t = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 8 + cig;
+    const int base = cig;   // lane of row 0 of this cell
     const bool live = t < npair;
     const int64_t tt = live ? t : 0;
     const int px = (int)(tt % hp);
@@ -126,7 +129,6 @@ __global__ __launch_bounds__(256) void k_relax(Op op, int colour, T w, int econ,
         iS = cinv(S);
     }
 
-    constexpr int RB = sizeof(T) == 4 ? 4 : 2;
     for (int r0 = 0; r0 < nrhs; r0 += RB) {
     cx<T> resb[RB];
     {
@@ -157,8 +159,8 @@ __global__ __launch_bounds__(256) void k_relax(Op op, int colour, T w, int econ,
         cx<T> rr[R];
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-            rr[j].re = __shfl(res.re, base + j, 64);
-            rr[j].im = __shfl(res.im, base + j, 64);
+            rr[j].re = __shfl(res.re, base + 8 * j, 64);
+            rr[j].im = __shfl(res.im, base + 8 * j, 64);
         }
         cx<T> d[R];
         if (row == 0) {
@@ -195,7 +197,7 @@ __global__ __launch_bounds__(256) void k_relax(Op op, int colour, T w, int econ,
 // ------------------------------------------------ plan-based apply and half-sweep
 // The row plan (indices and coefficients) is built once per row and reused for
 // every right-hand side, so a batch streams only the vectors.
-template <int D, typename T, class Op>
+template <int D, typename T, class Op, int RB>
 __global__ __launch_bounds__(256) void k_apply_plan(Op op, const T* __restrict__ x, const T* __restrict__ b,
                                                     T* __restrict__ y, int nrhs, int64_t stride, int rpb) {
     // right-hand sides [blockIdx.y * rpb, ...) of this grid row
@@ -222,7 +224,6 @@ __global__ __launch_bounds__(256) void k_apply_plan(Op op, const T* __restrict__
         op.plan_u(k, p, P);
     }
     // blocks of RB right-hand sides keep RB independent load streams in flight
-    constexpr int RB = sizeof(T) == 4 ? 4 : 2;
     int r = 0;
     for (; r + RB <= nrhs; r += RB) {
         cx<T> v[RB];
@@ -244,7 +245,7 @@ __global__ __launch_bounds__(256) void k_apply_plan(Op op, const T* __restrict__
 // Eight lanes per relaxed cell as in k_relax, each lane holding the plan of its
 // block row; the block itself (diagonals, the coupling of the two faces of a
 // component, the couplings to the cell pressure) is read off the lanes' plans.
-template <int D, typename T, class Op>
+template <int D, typename T, class Op, int RB>
 __global__ __launch_bounds__(256) void k_relax_plan(Op op, int colour, T w, int econ,
                                                     const T* __restrict__ b, const T* __restrict__ ein,
                                                     T* __restrict__ eout, int nrhs, int64_t stride, int rpb) {
@@ -259,11 +260,13 @@ __global__ __launch_bounds__(256) void k_relax_plan(Op op, int colour, T w, int 
     const Geo& g = op.g;
     const int hp = g.n[0] >> 1;
     const int64_t npair = (int64_t)hp * g.n[1] * g.n[2];
-    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t t = gt >> 3;
-    const int row = (int)(gt & 7);
+    // lane = 8 * row + cell: the eight cells of a wavefront are consecutive, so a
+    // load of one row term by the eight lanes of a row touches neighbouring cells
     const int lane = threadIdx.x & 63;
-    const int base = lane & ~7;
+    const int row = lane >> 3;
+    const int cig = lane & 7;
+    const int64_t t = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 8 + cig;
+    const int base = cig;   // lane of row 0 of this cell
     const bool live = t < npair;
     const int64_t tt = live ? t : 0;
     const int px = (int)(tt % hp);
@@ -308,15 +311,15 @@ __global__ __launch_bounds__(256) void k_relax_plan(Op op, int colour, T w, int 
     T glo[D], ghi[D];
     cx<T> S;
     {
-        const T pd = __shfl(dre, base + 2 * D, 64);
+        const T pd = __shfl(dre, base + 8 * (2 * D), 64);
         S = mk<T>(pd, T(0));
 #pragma unroll
         for (int kk = 0; kk < D; ++kk) {
-            const cx<T> all = mk<T>(__shfl(dre, base + 2 * kk, 64), __shfl(dim, base + 2 * kk, 64));
-            const cx<T> ahh = mk<T>(__shfl(dre, base + 2 * kk + 1, 64), __shfl(dim, base + 2 * kk + 1, 64));
-            const cx<T> alh = mk<T>(__shfl(cre, base + 2 * kk, 64), __shfl(cim, base + 2 * kk, 64));
-            glo[kk] = __shfl(gg, base + 2 * kk, 64);
-            ghi[kk] = __shfl(gg, base + 2 * kk + 1, 64);
+            const cx<T> all = mk<T>(__shfl(dre, base + 8 * (2 * kk), 64), __shfl(dim, base + 8 * (2 * kk), 64));
+            const cx<T> ahh = mk<T>(__shfl(dre, base + 8 * (2 * kk + 1), 64), __shfl(dim, base + 8 * (2 * kk + 1), 64));
+            const cx<T> alh = mk<T>(__shfl(cre, base + 8 * (2 * kk), 64), __shfl(cim, base + 8 * (2 * kk), 64));
+            glo[kk] = __shfl(gg, base + 8 * (2 * kk), 64);
+            ghi[kk] = __shfl(gg, base + 8 * (2 * kk + 1), 64);
             if (row == 0) {
                 const cx<T> idet = cinv(all * ahh - alh * alh);
                 i00[kk] = ahh * idet;
@@ -330,7 +333,6 @@ __global__ __launch_bounds__(256) void k_relax_plan(Op op, int colour, T w, int 
     }
     const cx<T> iS = row == 0 ? cinv(S) : mk<T>(T(0), T(0));
 
-    constexpr int RB = sizeof(T) == 4 ? 4 : 2;
     for (int r0 = 0; r0 < nrhs; r0 += RB) {
     // residual rows of a block of right-hand sides (independent load streams)
     cx<T> resb[RB];
@@ -353,8 +355,8 @@ __global__ __launch_bounds__(256) void k_relax_plan(Op op, int colour, T w, int 
         cx<T> rr[R];
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-            rr[j].re = __shfl(res.re, base + j, 64);
-            rr[j].im = __shfl(res.im, base + j, 64);
+            rr[j].re = __shfl(res.re, base + 8 * j, 64);
+            rr[j].im = __shfl(res.im, base + 8 * j, 64);
         }
         cx<T> d[R];
         if (row == 0) {
@@ -553,11 +555,15 @@ __global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const T* __rest
 // ------------------------------------------------------------------------ launchers
 static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
-// Right-hand sides per grid row: a level whose rows fill fewer than ~2048
-// wavefronts gets its batch split over grid rows (the coefficients of a small
-// level stay in cache, so re-reading them per group costs little).
+// Right-hand sides per grid row: a level whose rows fill fewer than a target
+// number of wavefronts gets its batch split over grid rows (the coefficients of a
+// small level stay in cache, so re-reading them per group costs little).
+static inline int env_int(const char* name, int dflt) {
+    const char* v = std::getenv(name);
+    return v ? std::atoi(v) : dflt;
+}
 static inline int rhs_per_block(int64_t waves, int nrhs, int rb) {
-    const int64_t target = 2048;
+    static const int64_t target = env_int("EHH_WAVES", 2048);
     int64_t groups = waves >= target ? 1 : (target + waves - 1) / waves;
     const int64_t maxg = (nrhs + rb - 1) / rb;
     if (groups > maxg) groups = maxg;
@@ -566,22 +572,52 @@ static inline int rhs_per_block(int64_t waves, int nrhs, int rb) {
     rpb = ((rpb + rb - 1) / rb) * rb;
     return rpb < 1 ? 1 : rpb;
 }
+// Right-hand sides evaluated together per row.  Measured on MI355X: one per row
+// is fastest for the row-plan kernels (fewer registers, more wavefronts in
+// flight outweigh the extra independent loads); the 3D Galerkin rows (93 terms)
+// share each coefficient load across a block of right-hand sides.
+template <typename T> static inline int rhs_block() {
+    static const int v = env_int(sizeof(T) == 4 ? "EHH_RB32" : "EHH_RB64", 1);
+    return v == 1 || v == 2 || v == 4 ? v : 1;
+}
+template <typename T> static inline int rhs_block_3d_stencil() {
+    static const int v = env_int("EHH_RB3D", sizeof(T) == 4 ? 4 : 2);
+    return v == 1 || v == 2 || v == 4 ? v : 2;
+}
+
+#define EHH_RB_DISPATCH(RBV, CALL) \
+    do {                           \
+        if ((RBV) == 1) {          \
+            constexpr int RB = 1;  \
+            CALL;                  \
+        } else if ((RBV) == 2) {   \
+            constexpr int RB = 2;  \
+            CALL;                  \
+        } else {                   \
+            constexpr int RB = 4;  \
+            CALL;                  \
+        }                          \
+    } while (0)
 
 template <typename T>
 hipError_t launch_apply(const LevelDesc<T>& L, const T* x, const T* b, T* y, int nrhs, hipStream_t s) {
     const int64_t stride = 2 * L.g.N;
-    const int rpb = rhs_per_block((L.g.N + 63) / 64, nrhs, sizeof(T) == 4 ? 4 : 2);
+    const int rb = rhs_block<T>();
+    const int rpb = rhs_per_block((L.g.N + 63) / 64, nrhs, rb);
     const dim3 gb(nblk(L.g.N), (nrhs + rpb - 1) / rpb);
+    const int rb3 = rhs_block_3d_stencil<T>();
+    const int rpb3 = rhs_per_block((L.g.N + 63) / 64, nrhs, rb3);
+    const dim3 gb3(nblk(L.g.N), (nrhs + rpb3 - 1) / rpb3);
     if (L.g.dim == 2) {
         if (L.fine)
-            hipLaunchKernelGGL((k_apply_plan<2, T, FineOp<2, T>>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, x, b, y, nrhs, stride, rpb);
+            EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_apply_plan<2, T, FineOp<2, T>, RB>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, x, b, y, nrhs, stride, rpb));
         else
-            hipLaunchKernelGGL((k_apply_plan<2, T, StOp<2, T>>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, x, b, y, nrhs, stride, rpb);
+            EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_apply_plan<2, T, StOp<2, T>, RB>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, x, b, y, nrhs, stride, rpb));
     } else {
         if (L.fine)
-            hipLaunchKernelGGL((k_apply_plan<3, T, FineOp<3, T>>), gb, 256, 0, s, FineOp<3, T>{L.g, L.f}, x, b, y, nrhs, stride, rpb);
+            EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_apply_plan<3, T, FineOp<3, T>, RB>), gb, 256, 0, s, FineOp<3, T>{L.g, L.f}, x, b, y, nrhs, stride, rpb));
         else
-            hipLaunchKernelGGL((k_apply<3, T, StOp<3, T>>), gb, 256, 0, s, StOp<3, T>{L.g, L.s}, x, b, y, nrhs, stride, rpb);
+            EHH_RB_DISPATCH(rb3, hipLaunchKernelGGL((k_apply<3, T, StOp<3, T>, RB>), gb3, 256, 0, s, StOp<3, T>{L.g, L.s}, x, b, y, nrhs, stride, rpb3));
     }
     return hipGetLastError();
 }
@@ -591,19 +627,23 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
                         T* eout, int nrhs, hipStream_t s) {
     const int64_t stride = 2 * L.g.N;
     const int64_t npair = (int64_t)(L.g.n[0] / 2) * L.g.n[1] * L.g.n[2];
-    const int rpb = rhs_per_block((npair * 8 + 63) / 64, nrhs, sizeof(T) == 4 ? 4 : 2);
+    const int rb = rhs_block<T>();
+    const int rpb = rhs_per_block((npair * 8 + 63) / 64, nrhs, rb);
     const dim3 gb(nblk(npair * 8), (nrhs + rpb - 1) / rpb);
+    const int rb3 = rhs_block_3d_stencil<T>();
+    const int rpb3 = rhs_per_block((npair * 8 + 63) / 64, nrhs, rb3);
+    const dim3 gb3(nblk(npair * 8), (nrhs + rpb3 - 1) / rpb3);
     const T tw = (T)w;
     if (L.g.dim == 2) {
         if (L.fine)
-            hipLaunchKernelGGL((k_relax_plan<2, T, FineOp<2, T>>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb);
+            EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_relax_plan<2, T, FineOp<2, T>, RB>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb));
         else
-            hipLaunchKernelGGL((k_relax_plan<2, T, StOp<2, T>>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb);
+            EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_relax_plan<2, T, StOp<2, T>, RB>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb));
     } else {
         if (L.fine)
-            hipLaunchKernelGGL((k_relax_plan<3, T, FineOp<3, T>>), gb, 256, 0, s, FineOp<3, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb);
+            EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_relax_plan<3, T, FineOp<3, T>, RB>), gb, 256, 0, s, FineOp<3, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb));
         else
-            hipLaunchKernelGGL((k_relax<3, T, StOp<3, T>>), gb, 256, 0, s, StOp<3, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb);
+            EHH_RB_DISPATCH(rb3, hipLaunchKernelGGL((k_relax<3, T, StOp<3, T>, RB>), gb3, 256, 0, s, StOp<3, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb3));
     }
     return hipGetLastError();
 }

@@ -1,0 +1,111 @@
+"""Parity at the benchmark sizes, in the configuration bench.py times.
+
+c2 and c3 (512^2): one whole preconditioner cycle is compared element by element
+with the oracle's cycle, and a solve's true residual is recomputed by the oracle.
+c4 (128^3, 8 padded subdomains): the oracle's hierarchy is too large for a CPU
+test, so the solve is checked through properties that hold at any size: the
+residual recomputed by the oracle's sparse operator and the mirror of the
+library's own residual report."""
+import numpy as np
+import pytest
+
+from _helpers import say, workload, oracle_problem, oracle_hierarchy, rand_cvec, to_dev, from_dev, rhs_matrix
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(w, **over):
+    import torch
+    from paper_1806_11277_amd import ehh
+    torch.cuda.synchronize()
+    return ehh.solver_for_workload(w, **over)
+
+
+@pytest.fixture(scope="module")
+def c2_oracle():
+    w = workload("c2_hetero512_fp64")
+    say("[c2 full size: oracle problem and hierarchy]")
+    pb = oracle_problem(w)
+    H = oracle_hierarchy(w, pb)
+    return w, pb, H
+
+
+def test_c2_cycle_matches_oracle(c2_oracle):
+    import torch
+    w, pb, H = c2_oracle
+    say("[c2 full-size W-cycle, FP64]")
+    S = _solver(w)
+    r = rand_cvec(pb.size, 1, 70)
+    e = torch.zeros_like(to_dev(r))
+    S.vcycle(to_dev(r), e)
+    torch.cuda.synchronize()
+    got = from_dev(e)[0]
+    ref = H.cycle(r[0])
+    assert np.linalg.norm(got - ref) <= 1e-10 * np.linalg.norm(ref)
+    S.close()
+
+
+def test_c3_cycle_matches_oracle(c2_oracle):
+    """The complex64 cycle of c3 (same medium and hierarchy as c2) on 32
+    right-hand sides; two are compared with the FP64 oracle cycle."""
+    import torch
+    w2, pb, H = c2_oracle
+    w = workload("c3_hetero512_batch32_fp32")
+    say("[c3 full-size W-cycle, complex64, 32 right-hand sides]")
+    S = _solver(w)
+    r = rand_cvec(pb.size, 32, 71)
+    e = torch.zeros((32, 2 * pb.size), dtype=torch.float32, device="cuda")
+    S.vcycle(to_dev(r, torch.float32), e)
+    torch.cuda.synchronize()
+    got = from_dev(e)
+    for q in (0, 31):
+        ref = H.cycle(r[q])
+        assert np.linalg.norm(got[q] - ref) <= 2e-5 * np.linalg.norm(ref)
+    S.close()
+
+
+def test_c2_solve_true_residual(c2_oracle):
+    import torch
+    w, pb, H = c2_oracle
+    say("[c2 full-size solve, residual recomputed by the oracle]")
+    A = pb.matrix()
+    B = rhs_matrix(w)
+    S = _solver(w)
+    x = torch.zeros_like(to_dev(B))
+    st, stats = S.solve(to_dev(B), x, tol=1e-6, maxit=400)
+    torch.cuda.synchronize()
+    assert st == 0
+    got = from_dev(x)[0]
+    res = np.linalg.norm(B[0] - A @ got) / np.linalg.norm(B[0])
+    say(f"  iters {stats[0]['iters']} library residual {stats[0]['rel_res_true']:.3e} oracle residual {res:.3e}")
+    assert res <= 1e-6
+    assert abs(res - stats[0]["rel_res_true"]) <= 1e-9
+    S.close()
+
+
+def test_c4_solve_true_residual():
+    """128^3, 2 x 2 x 2 padded subdomains, complex64 DD-MG preconditioner with the
+    multicolour schedule; two of the 16 sources, residual recomputed by the
+    oracle's sparse operator."""
+    import dataclasses
+    import torch
+    w = workload("c4_layered128_dd8_batch16_fp32")
+    srcs = w.sources()[:2]
+    w = dataclasses.replace(w, sources_fn=lambda w_, s=srcs: s)
+    w._media_cache = None
+    say("[c4 full-size solve (2 sources)]")
+    S = _solver(w)
+    B = rhs_matrix(w)
+    x = torch.zeros_like(to_dev(B))
+    st, stats = S.solve(to_dev(B), x, tol=1e-6, maxit=500)
+    torch.cuda.synchronize()
+    assert st == 0, stats
+    got = from_dev(x)
+    S.close()
+    say("  oracle assembly of the 128^3 operator")
+    A = oracle_problem(w).matrix()
+    for r in range(2):
+        res = np.linalg.norm(B[r] - A @ got[r]) / np.linalg.norm(B[r])
+        say(f"  source {r}: iters {stats[r]['iters']} library {stats[r]['rel_res_true']:.3e} oracle {res:.3e}")
+        assert res <= 1e-6
+        assert abs(res - stats[r]["rel_res_true"]) <= 1e-9
