@@ -389,6 +389,221 @@ __global__ __launch_bounds__(256) void k_relax_plan(Op op, int colour, T w, int 
     }
 }
 
+// ---------------------------------------------------- LDS-staged half-sweep (2D)
+// A block relaxes the red cells of a 16 x 8 tile (64 cells, eight lanes each as in
+// k_relax_plan).  For every right-hand side the vectors the tile's rows touch
+// (tile plus a halo of one face along the normal and `ht` cells along the
+// tangential axis of each component, one cell for the pressure) are loaded once,
+// coalesced, into LDS; the rows are then evaluated from LDS instead of
+// re-reading neighbours through the caches (a Galerkin row has 21 terms).
+static constexpr int LT_X = 16, LT_Y = 8;
+
+template <typename T, class Op>
+__global__ __launch_bounds__(512) void k_relax_lds2d(Op op, int colour, T w, int econ, const T* __restrict__ b,
+                                                     const T* __restrict__ ein, T* __restrict__ eout, int nrhs,
+                                                     int64_t stride, int rpb, int ht) {
+    constexpr int D = 2, R = 5;
+    __shared__ T sre[(LT_X + 3) * (LT_Y + 4) + (LT_X + 4) * (LT_Y + 3) + (LT_X + 2) * (LT_Y + 2)];
+    __shared__ T sim[(LT_X + 3) * (LT_Y + 4) + (LT_X + 4) * (LT_Y + 3) + (LT_X + 2) * (LT_Y + 2)];
+    {
+        const int rb0 = blockIdx.y * rpb;
+        b += rb0 * stride;
+        if (ein) ein += rb0 * stride;
+        eout += rb0 * stride;
+        nrhs = nrhs - rb0 < rpb ? nrhs - rb0 : rpb;
+    }
+    const Geo& g = op.g;
+    const int tiles_x = (g.n[0] + LT_X - 1) / LT_X;
+    const int x0 = (blockIdx.x % tiles_x) * LT_X, y0 = (blockIdx.x / tiles_x) * LT_Y;
+    const int lane = threadIdx.x & 63, row = lane >> 3, cig = lane & 7;
+    const int yl = threadIdx.x >> 6;   // one tile row per wavefront
+    const int yy = y0 + yl;
+    const int par = (colour + yy) & 1;
+    const int cr[3] = {x0 + 2 * cig + par, yy, 0};
+    const int cb[3] = {x0 + 2 * cig + 1 - par, yy, 0};
+    const bool live = yy < g.n[1] && x0 + 2 * cig < g.n[0];
+    const int base = cig;
+    // region geometry: component 0 (x faces), 1 (y faces), pressure
+    const int w0x = LT_X + 3, w0y = LT_Y + 2 * ht, o0x = x0 - 1, o0y = y0 - ht;
+    const int w1x = LT_X + 2 * ht, w1y = LT_Y + 3, o1x = x0 - ht, o1y = y0 - 1;
+    const int wpx = LT_X + 2, wpy = LT_Y + 2, opx = x0 - 1, opy = y0 - 1;
+    const int b1 = w0x * w0y, bp = b1 + w1x * w1y, nreg = bp + wpx * wpy;
+
+    const int k = row < 2 * D ? (row >> 1) : 3;
+    int p[3] = {cr[0], cr[1], 0};
+    bool ok = live && row < R;
+    if (k < 3) {
+        p[k] += row & 1;
+        ok = ok && p[k] >= 1 && p[k] <= g.n[k] - 1;
+    }
+    Plan<T, Op::NT> P;
+    int64_t idx = 0;
+    int own = 0;
+    if (ok) {
+        if (k == 3) {
+            op.plan_p(p, P);
+            idx = g.off[3] + cell_idx<D>(g, p);
+        } else {
+            op.plan_u(k, p, P);
+            idx = g.off[k] + face_idx<D>(g, k, p);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < Op::NT; ++j) P.set(j, 0, T(0), T(0));
+    }
+    // block entries (before the plan indices are turned into LDS offsets)
+    const T dre = ok ? (k == 3 ? P.re[0] : P.re[Op::T_SELF]) : T(1);
+    const T dim = ok ? (k == 3 ? P.im[0] : P.im[Op::T_SELF]) : T(0);
+    const bool lowrow = row < 2 * D && (row & 1) == 0;
+    const T cre = (ok && lowrow && !econ) ? P.re[Op::T_NHI] : T(0);
+    const T cim = (ok && lowrow && !econ) ? P.im[Op::T_NHI] : T(0);
+    const T gg = (ok && row < 2 * D) ? (lowrow ? P.re[Op::T_PHI] : P.re[Op::T_PLO]) : T(0);
+    // global index -> LDS offset (clamped to 0 outside the region; such terms
+    // carry a zero coefficient)
+    auto to_lds = [&](int64_t gi) -> int {
+        int kk = gi < g.off[1] ? 0 : (gi < g.off[3] ? 1 : 3);
+        const int li = (int)(gi - g.off[kk]);
+        int q0, q1, o;
+        if (kk == 0) {
+            const int d0 = g.n[0] - 1;
+            q0 = li % d0 + 1;
+            q1 = li / d0;
+            q0 -= o0x;
+            q1 -= o0y;
+            o = (q0 >= 0 && q0 < w0x && q1 >= 0 && q1 < w0y) ? q0 + w0x * q1 : -1;
+        } else if (kk == 1) {
+            const int d0 = g.n[0];
+            q0 = li % d0;
+            q1 = li / d0 + 1;
+            q0 -= o1x;
+            q1 -= o1y;
+            o = (q0 >= 0 && q0 < w1x && q1 >= 0 && q1 < w1y) ? b1 + q0 + w1x * q1 : -1;
+        } else {
+            const int d0 = g.n[0];
+            q0 = li % d0 - opx;
+            q1 = li / d0 - opy;
+            o = (q0 >= 0 && q0 < wpx && q1 >= 0 && q1 < wpy) ? bp + q0 + wpx * q1 : -1;
+        }
+        return o < 0 ? 0 : o;
+    };
+#pragma unroll
+    for (int j = 0; j < Op::NT; ++j) {
+        const int o = to_lds(P.ix[j]);
+        P.ix[j] = o;
+    }
+    own = ok ? to_lds(idx) : 0;
+    const bool carry = live && row == R;
+    const int64_t ipb = g.off[3] + cell_idx<D>(g, cb);
+    const int ownb = carry ? to_lds(ipb) : 0;
+
+    cx<T> i00[D], i01[D], i11[D], zlo[D], zhi[D];
+    T glo[D], ghi[D];
+    cx<T> S;
+    {
+        const T pd = __shfl(dre, base + 8 * (2 * D), 64);
+        S = mk<T>(pd, T(0));
+#pragma unroll
+        for (int kk = 0; kk < D; ++kk) {
+            const cx<T> all = mk<T>(__shfl(dre, base + 8 * (2 * kk), 64), __shfl(dim, base + 8 * (2 * kk), 64));
+            const cx<T> ahh = mk<T>(__shfl(dre, base + 8 * (2 * kk + 1), 64), __shfl(dim, base + 8 * (2 * kk + 1), 64));
+            const cx<T> alh = mk<T>(__shfl(cre, base + 8 * (2 * kk), 64), __shfl(cim, base + 8 * (2 * kk), 64));
+            glo[kk] = __shfl(gg, base + 8 * (2 * kk), 64);
+            ghi[kk] = __shfl(gg, base + 8 * (2 * kk + 1), 64);
+            if (row == 0) {
+                const cx<T> idet = cinv(all * ahh - alh * alh);
+                i00[kk] = ahh * idet;
+                i11[kk] = all * idet;
+                i01[kk] = mk<T>(T(0), T(0)) - alh * idet;
+                zlo[kk] = glo[kk] * i00[kk] + ghi[kk] * i01[kk];
+                zhi[kk] = glo[kk] * i01[kk] + ghi[kk] * i11[kk];
+                S = S - (glo[kk] * zlo[kk] + ghi[kk] * zhi[kk]);
+            }
+        }
+    }
+    const cx<T> iS = row == 0 ? cinv(S) : mk<T>(T(0), T(0));
+
+    for (int r = 0; r < nrhs; ++r) {
+        const CVec<T> bv{b + r * stride, g.N};
+        const Vec<T> ov{eout + r * stride, g.N};
+        cx<T> res = mk<T>(T(0), T(0));
+        cx<T> eown = mk<T>(T(0), T(0)), ecarry = mk<T>(T(0), T(0));
+        if (ein) {
+            const CVec<T> ev{ein + r * stride, g.N};
+            __syncthreads();   // the previous right-hand side is done with the tile
+            for (int e = threadIdx.x; e < nreg; e += blockDim.x) {
+                int kk, q0, q1;
+                if (e < b1) {
+                    kk = 0;
+                    q0 = e % w0x + o0x;
+                    q1 = e / w0x + o0y;
+                } else if (e < bp) {
+                    kk = 1;
+                    q0 = (e - b1) % w1x + o1x;
+                    q1 = (e - b1) / w1x + o1y;
+                } else {
+                    kk = 3;
+                    q0 = (e - bp) % wpx + opx;
+                    q1 = (e - bp) / wpx + opy;
+                }
+                const int q[3] = {q0, q1, 0};
+                const bool in = kk == 3 ? cell_ok<D>(g, q) : face_ok<D>(g, kk, q);
+                cx<T> v = mk<T>(T(0), T(0));
+                if (in) v = ev.ld(kk == 3 ? g.off[3] + cell_idx<D>(g, q) : g.off[kk] + face_idx<D>(g, kk, q));
+                sre[e] = v.re;
+                sim[e] = v.im;
+            }
+            __syncthreads();
+            if (ok) {
+                T ar = T(0), ai = T(0);
+#pragma unroll
+                for (int j = 0; j < Op::NT; ++j) {
+                    const T vr = sre[P.ix[j]], vi = sim[P.ix[j]];
+                    ar += P.re[j] * vr - P.im[j] * vi;
+                    ai += P.re[j] * vi + P.im[j] * vr;
+                }
+                res = bv.ld(idx) - mk<T>(ar, ai);
+                eown = mk<T>(sre[own], sim[own]);
+            }
+            if (carry) ecarry = mk<T>(sre[ownb], sim[ownb]);
+        } else if (ok) {
+            res = bv.ld(idx);
+        }
+        cx<T> rr[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            rr[j].re = __shfl(res.re, base + 8 * j, 64);
+            rr[j].im = __shfl(res.im, base + 8 * j, 64);
+        }
+        cx<T> d[R];
+        if (row == 0) {
+            cx<T> acc = rr[2 * D];
+            cx<T> ylo[D], yhi[D];
+#pragma unroll
+            for (int kk = 0; kk < D; ++kk) {
+                ylo[kk] = i00[kk] * rr[2 * kk] + i01[kk] * rr[2 * kk + 1];
+                yhi[kk] = i01[kk] * rr[2 * kk] + i11[kk] * rr[2 * kk + 1];
+                acc = acc - (glo[kk] * ylo[kk] + ghi[kk] * yhi[kk]);
+            }
+            const cx<T> dp = acc * iS;
+#pragma unroll
+            for (int kk = 0; kk < D; ++kk) {
+                d[2 * kk] = ylo[kk] - zlo[kk] * dp;
+                d[2 * kk + 1] = yhi[kk] - zhi[kk] * dp;
+            }
+            d[2 * D] = dp;
+        }
+        cx<T> mine = mk<T>(T(0), T(0));
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const T vr = __shfl(d[j].re, base, 64);
+            const T vi = __shfl(d[j].im, base, 64);
+            if (row == j) mine = mk<T>(vr, vi);
+        }
+        if (ok) ov.st(idx, eown + w * mine);
+        if (carry) ov.st(ipb, ecarry);
+    }
+}
+
 // --------------------------------------------------------------------- transfers
 // Staggered bilinear transfer: u_k linear along its normal (weights 1 / (1/2, 1/2)),
 // linear along each tangential axis (3/4 nearer coarse row, 1/4 the other, zero
@@ -580,6 +795,10 @@ template <typename T> static inline int rhs_block() {
     static const int v = env_int(sizeof(T) == 4 ? "EHH_RB32" : "EHH_RB64", 1);
     return v == 1 || v == 2 || v == 4 ? v : 1;
 }
+static inline bool lds2d_enabled() {
+    static const bool v = env_int("EHH_LDS2D", 1) != 0;
+    return v;
+}
 template <typename T> static inline int rhs_block_3d_stencil() {
     static const int v = env_int("EHH_RB3D", sizeof(T) == 4 ? 4 : 2);
     return v == 1 || v == 2 || v == 4 ? v : 2;
@@ -634,7 +853,15 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
     const int rpb3 = rhs_per_block((npair * 8 + 63) / 64, nrhs, rb3);
     const dim3 gb3(nblk(npair * 8), (nrhs + rpb3 - 1) / rpb3);
     const T tw = (T)w;
-    if (L.g.dim == 2) {
+    // LDS staging pays on the 21-term Galerkin rows of large levels (measured:
+    // 134 vs 217 us per half-sweep on 256^2 with 32 sources); on small levels the
+    // extra synchronisation adds latency and the 7-term finest rows gain nothing.
+    if (L.g.dim == 2 && !L.fine && L.g.ncell >= 16384 && lds2d_enabled()) {
+        const int tiles = ((L.g.n[0] + LT_X - 1) / LT_X) * ((L.g.n[1] + LT_Y - 1) / LT_Y);
+        const int rpl = rhs_per_block((int64_t)tiles * 8, nrhs, 1);
+        const dim3 gl(tiles, (nrhs + rpl - 1) / rpl);
+        hipLaunchKernelGGL((k_relax_lds2d<T, StOp<2, T>>), gl, 512, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride, rpl, 2);
+    } else if (L.g.dim == 2) {
         if (L.fine)
             EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_relax_plan<2, T, FineOp<2, T>, RB>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb));
         else
