@@ -180,14 +180,19 @@ def total_gamma(n, omega_si, abl_cells, abl_max, atten0, gamma_phys=None):
     return g
 
 
-def nondimensionalise(h, omega, lam, mu, rho):
+def nondimensionalise(h, omega, lam, mu, rho, mu_bar=None, rho_bar=None):
     """Scale to h = 1, mean(mu) = 1, mean(rho) = 1.  Returns a dict with the
     nondimensional media and omega*h*sqrt(rho_bar/mu_bar).  If mu vanishes
-    everywhere, mean(lambda + 2 mu) is the stiffness scale."""
-    mu_bar = float(np.mean(mu))
-    if mu_bar <= 0.0:
-        mu_bar = float(np.mean(lam + 2.0 * mu))
-    rho_bar = float(np.mean(rho))
+    everywhere, mean(lambda + 2 mu) is the stiffness scale.  Units given by the
+    caller (mu_bar, rho_bar > 0) replace the means, so that vectors keep their
+    units while the media change (gradients at fixed units)."""
+    if mu_bar is None or mu_bar <= 0.0:
+        mu_bar = float(np.mean(mu))
+        if mu_bar <= 0.0:
+            mu_bar = float(np.mean(lam + 2.0 * mu))
+    if rho_bar is None or rho_bar <= 0.0:
+        rho_bar = float(np.mean(rho))
+    mu_bar, rho_bar = float(mu_bar), float(rho_bar)
     return dict(h=1.0, omega=omega * h * math.sqrt(rho_bar / mu_bar),
                 lam=np.asarray(lam) / mu_bar, mu=np.asarray(mu) / mu_bar,
                 rho=np.asarray(rho) / rho_bar, mu_bar=mu_bar, rho_bar=rho_bar)
@@ -270,14 +275,14 @@ class Problem:
     h = 1, mean mu = 1, mean rho = 1 (the residual norm is taken in these units)."""
 
     def __init__(self, n, h, omega, lam, mu, rho, abl_cells, abl_max=1.0, atten0=0.0,
-                 gamma_phys=None, shift=0.0):
+                 gamma_phys=None, shift=0.0, mu_bar=None, rho_bar=None):
         self.n = tuple(int(v) for v in n)
         self.dim = len(self.n)
         self.h_si = float(h)
         self.omega_si = float(omega)
         self.shift = float(shift)
         self.gamma_hat = total_gamma(self.n, omega, abl_cells, abl_max, atten0, gamma_phys)
-        nd = nondimensionalise(h, omega, lam, mu, rho)
+        nd = nondimensionalise(h, omega, lam, mu, rho, mu_bar, rho_bar)
         self.nd = nd
         self.omega = nd["omega"]
         self.lam, self.mu, self.rho = nd["lam"], nd["mu"], nd["rho"]
