@@ -79,6 +79,9 @@ typedef struct {
     int32_t abl_cells[3];   /* absorbing layer width per axis, on both sides (>= 0) */
     double  abl_max;        /* gamma/omega reached at the wall, per axis (section 2.1: 1) */
     double  atten0;         /* constant attenuation gamma_0 [1/s] added everywhere */
+    double  mu_bar;         /* stiffness unit [Pa] of the nondimensional scaling; 0 = mean(mu) */
+    double  rho_bar;        /* density unit [kg/m^3]; 0 = mean(rho).  Fix both to keep the
+                               units of the vectors unchanged across model updates. */
 } ehh_problem_t;
 
 typedef struct {
@@ -165,6 +168,29 @@ int32_t ehh_precondition(ehh_handle_t h, const double* v, double* z, int32_t nrh
  * once per iteration to read the residual estimates. */
 int32_t ehh_solve(ehh_handle_t h, const double* b, double* x, int32_t nrhs, double tol,
                   int32_t maxit, ehh_stats_t* stats, void* stream);
+
+/* Solve the adjoint system A^H y = g.  A of eq. (14) is complex symmetric
+ * (A^T = A), so A^H = conj(A): the call solves A conj(y) = conj(g) with the same
+ * preconditioned FGMRES and conjugates the result.  g, y: (device) FP64 global
+ * layout, distinct.  Stats and returns as ehh_solve (the residual norms of the
+ * conjugated system equal those of the adjoint one). */
+int32_t ehh_solve_adjoint(ehh_handle_t h, const double* g, double* y, int32_t nrhs, double tol,
+                          int32_t maxit, ehh_stats_t* stats, void* stream);
+
+/* Derivatives of a real misfit L(x_1..x_nrhs) with respect to the cell media,
+ * by the adjoint-state method (section 1 motivates the solver by full-waveform
+ * inversion): with A x_r = b_r and A^H y_r = dL/dx_r (the real-layout gradient
+ * read as a complex vector), dL/dm_c = -Re sum_r y_r^H (dA/dm_c) x_r for
+ * m = lambda, mu, rho at every cell c, A the unshifted operator of eq. (14).
+ * Derivatives are per SI unit (Pa, kg/m^3) at the handle's fixed scaling
+ * mu_bar, rho_bar (attenuation and omega held fixed).
+ *   y, x: (device) FP64 global layout, nrhs vectors each.
+ *   grad_lambda, grad_mu, grad_rho: (device) FP64 cell arrays, x fastest,
+ *   distinct; overwritten (accumulate = 0) or added to (accumulate = 1).
+ * Deterministic: each cell sums its right-hand sides in a fixed order. */
+int32_t ehh_media_gradient(ehh_handle_t h, const double* y, const double* x, int32_t nrhs,
+                           double* grad_lambda, double* grad_mu, double* grad_rho,
+                           int32_t accumulate, void* stream);
 
 /* Per-step entry points of the multigrid path (for checking each kernel).
  * Vectors are (device) in the level's layout and the cycle precision. */

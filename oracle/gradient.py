@@ -54,27 +54,32 @@ def media_gradient(n, omega, lam, mu, rho, gamma_hat, y, x, mu_bar=1.0, rho_bar=
     dinv = 1.0 / (lam + mu)
     y = np.atleast_2d(y)
     x = np.atleast_2d(x)
+    # Laplacian of u_k: sum_a G_a^T diag(W_a mu) G_a (see laplacian_block);
+    # mass of u_k: diag(Af (rho (1 - i gamma))) with Af the two-cell face mean
+    lap_ops = []
+    mass_ops = []
+    for k in range(d):
+        for a in range(d):
+            if a == k:
+                Gk = D.kron_axes([D._d_face_to_cell(n[b], 1.0) if b == k else D._eye(n[b]) for b in range(d)])
+                Wk = sp.identity(lam.size)
+            else:
+                Gk = D.kron_axes([D._d_cell_to_node(n[b], 1.0) if b == a else
+                                  (D._eye(n[b] - 1) if b == k else D._eye(n[b])) for b in range(d)])
+                Wk = D.kron_axes([D._avg_cell_to_node(n[b]) if b == a else
+                                  (D._avg_cell_to_face(n[b]) if b == k else D._eye(n[b])) for b in range(d)])
+            lap_ops.append((k, Gk, Wk))
+        mass_ops.append(D.kron_axes([D._avg_cell_to_face(n[b]) if b == k else D._eye(n[b]) for b in range(d)]))
     g_pd = np.zeros(lam.size)       # Re sum conj(y_p) x_p
     g_lap = np.zeros(lam.size)      # d/dmu of Re y^H (grad^T A_e(mu) grad) x
     s_mass = np.zeros(lam.size, dtype=np.complex128)   # sum over faces of conj(y) x, per cell
     for yr, xr in zip(y, x):
         yb, xb = _blocks(n, yr), _blocks(n, xr)
         g_pd += np.real(np.conj(yb[d]) * xb[d])
+        for k, Gk, Wk in lap_ops:
+            g_lap += Wk.T @ np.real(np.conj(Gk @ yb[k]) * (Gk @ xb[k]))
         for k in range(d):
-            # Laplacian of u_k: sum_a G_a^T diag(W_a mu) G_a (see laplacian_block)
-            for a in range(d):
-                if a == k:
-                    G = D.kron_axes([D._d_face_to_cell(n[b], 1.0) if b == k else D._eye(n[b]) for b in range(d)])
-                    W = sp.identity(lam.size)
-                else:
-                    G = D.kron_axes([D._d_cell_to_node(n[b], 1.0) if b == a else
-                                     (D._eye(n[b] - 1) if b == k else D._eye(n[b])) for b in range(d)])
-                    W = D.kron_axes([D._avg_cell_to_node(n[b]) if b == a else
-                                     (D._avg_cell_to_face(n[b]) if b == k else D._eye(n[b])) for b in range(d)])
-                g_lap += W.T @ np.real(np.conj(G @ yb[k]) * (G @ xb[k]))
-            # mass of u_k: diag(Af (rho (1 - i gamma))) with Af the two-cell face mean
-            Af = D.kron_axes([D._avg_cell_to_face(n[b]) if b == k else D._eye(n[b]) for b in range(d)])
-            s_mass += Af.T @ (np.conj(yb[k]) * xb[k])
+            s_mass += mass_ops[k].T @ (np.conj(yb[k]) * xb[k])
     # dA/dlambda_c = dA/dmu_c (pressure row) = +dinv^2 at (p_c, p_c)
     d_lam = -(dinv * dinv * g_pd) / mu_bar
     d_mu = -(dinv * dinv * g_pd + g_lap) / mu_bar

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libehh.so")
 
-SOURCES = ["levels.hip", "setup.hip", "krylov.hip", "dd.hip", "api.cpp"]
+SOURCES = ["levels.hip", "setup.hip", "krylov.hip", "dd.hip", "gradient.hip", "api.cpp"]
 ARCH = os.environ.get("EHH_OFFLOAD_ARCH", "gfx950")
 
 

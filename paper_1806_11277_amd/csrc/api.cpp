@@ -119,6 +119,9 @@ struct ehh_ctx {
     double *partial = nullptr, *scal = nullptr;
     int *active = nullptr, *ncols = nullptr;
     double* host_pinned = nullptr;
+    // conjugated right-hand sides of the adjoint solve
+    int adj_rhs = 0;
+    double* adjb = nullptr;
     std::vector<void*> allocs;
     // one captured graph per Arnoldi step j for the current batch size
     int graph_rhs = 0;
@@ -382,6 +385,8 @@ int32_t check_problem(const ehh_problem_t* p, const ehh_options_t* o) {
         !std::isfinite(p->h) || !std::isfinite(p->omega) || !std::isfinite(p->shift) || !std::isfinite(p->abl_max) ||
         !std::isfinite(p->atten0))
         return fail(EHH_ERR_INVALID, "h, omega > 0 and shift, abl_max, atten0 >= 0 (finite) required");
+    if (!(p->mu_bar >= 0) || !(p->rho_bar >= 0) || !std::isfinite(p->mu_bar) || !std::isfinite(p->rho_bar))
+        return fail(EHH_ERR_INVALID, "mu_bar, rho_bar must be finite and >= 0 (0 = media means)");
     if (o->levels < 1 || o->levels > EHH_MAX_LEVELS) return fail(EHH_ERR_INVALID, "levels out of range");
     if (o->cycle != 1 && o->cycle != 2) return fail(EHH_ERR_INVALID, "cycle must be 1 (V) or 2 (W)");
     if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 > 8 || o->nu2 > 8) return fail(EHH_ERR_INVALID, "nu1, nu2 in [0, 8]");
@@ -537,6 +542,8 @@ int32_t setup_impl(ehh_ctx* c, const double* lam, const double* mu, const double
     c->mu_bar = sums[0] / (double)c->gg.ncell;
     if (!(c->mu_bar > 0)) c->mu_bar = sums[3] / (double)c->gg.ncell;
     c->rho_bar = sums[1] / (double)c->gg.ncell;
+    if (P.mu_bar > 0) c->mu_bar = P.mu_bar;      // caller-fixed units (e.g. across model updates)
+    if (P.rho_bar > 0) c->rho_bar = P.rho_bar;
     if (!(c->mu_bar > 0) || !(c->rho_bar > 0)) return fail(EHH_ERR_BREAKDOWN, "degenerate media means");
     c->omega_nd = P.omega * P.h * std::sqrt(c->rho_bar / c->mu_bar);
     // global fine coefficients (the unshifted operator of the outer solve)
@@ -934,6 +941,39 @@ int32_t ehh_solve(ehh_handle_t h, const double* b, double* x, int32_t nrhs, doub
     if (status == EHH_ERR_BREAKDOWN) g_err = "non-finite residual in the Krylov iteration";
     else if (status == EHH_NOT_CONVERGED) g_err = "maxit reached before tol";
     return status;
+}
+
+int32_t ehh_solve_adjoint(ehh_handle_t h, const double* g, double* y, int32_t nrhs, double tol, int32_t maxit,
+                          ehh_stats_t* stats, void* stream) {
+    CHK(check_handle(h));
+    if (!g || !y || g == y || nrhs < 1 || !(tol > 0) || maxit < 1)
+        return fail(EHH_ERR_INVALID, "ehh_solve_adjoint: bad vectors, nrhs, tol or maxit");
+    hipStream_t s = as_stream(stream);
+    ehh_ctx* c = h;
+    if (nrhs > c->adj_rhs) {
+        c->release(c->adjb);
+        c->adjb = nullptr;
+        c->adj_rhs = 0;
+        CHK(c->alloc((void**)&c->adjb, sizeof(double) * 2 * (size_t)c->gg.N * nrhs));
+        c->adj_rhs = nrhs;
+    }
+    // A^H = conj(A) because A^T = A: A^H y = g  <=>  A conj(y) = conj(g)
+    HIPCHK(launch_conj(g, c->adjb, c->gg.N, nrhs, s));
+    const int32_t st = ehh_solve(h, c->adjb, y, nrhs, tol, maxit, stats, stream);
+    if (st == EHH_OK || st == EHH_NOT_CONVERGED || st == EHH_ERR_BREAKDOWN)
+        HIPCHK(launch_conj(y, y, c->gg.N, nrhs, s));
+    return st;
+}
+
+int32_t ehh_media_gradient(ehh_handle_t h, const double* y, const double* x, int32_t nrhs, double* grad_lambda,
+                           double* grad_mu, double* grad_rho, int32_t accumulate, void* stream) {
+    CHK(check_handle(h));
+    if (!y || !x || nrhs < 1 || !grad_lambda || !grad_mu || !grad_rho || grad_lambda == grad_mu ||
+        grad_mu == grad_rho || grad_lambda == grad_rho || (accumulate != 0 && accumulate != 1))
+        return fail(EHH_ERR_INVALID, "ehh_media_gradient: bad vectors, nrhs or accumulate flag");
+    HIPCHK(launch_media_gradient(h->gg, h->fine64, h->omega_nd * h->omega_nd, y, x, nrhs, h->mu_bar, h->rho_bar,
+                                 grad_lambda, grad_mu, grad_rho, accumulate, as_stream(stream)));
+    return EHH_OK;
 }
 
 int32_t ehh_num_subdomains(ehh_handle_t h) { return h ? (int32_t)h->subs.size() : 0; }

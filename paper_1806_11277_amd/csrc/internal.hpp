@@ -103,7 +103,17 @@ hipError_t launch_givens(double* H, double* cs, double* g, const double* hcol, c
 // y = R^{-1} g (columns ncols[r]); x(r) += sum_i y_i Z_i(r)
 hipError_t launch_update_x(const double* H, const double* g, const double* Z, double* x, int64_t N, int nrhs,
                            int m, const int* ncols, double* y, hipStream_t s);
+
 hipError_t launch_axpby(const double* x, const double* y, double* out, int64_t n, double a, double b,
                         hipStream_t s);
+
+// ---- gradient.hip
+// y = conj(x) for nrhs vectors of the global layout (x == y allowed).
+hipError_t launch_conj(const double* x, double* y, int64_t N, int nrhs, hipStream_t s);
+// Per cell: dL/d{lambda, mu, rho} = -Re sum_r y_r^H (dA/dm) x_r in SI units
+// (fine = mu, dinv, rho, gamma planes of the global operator).
+hipError_t launch_media_gradient(const Geo& g, const double* fine, double om2, const double* y, const double* x,
+                                 int nrhs, double mu_bar, double rho_bar, double* gl, double* gm, double* gr,
+                                 int accumulate, hipStream_t s);
 
 }  // namespace ehh

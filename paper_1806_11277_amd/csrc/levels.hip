@@ -853,10 +853,11 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
     const int rpb3 = rhs_per_block((npair * 8 + 63) / 64, nrhs, rb3);
     const dim3 gb3(nblk(npair * 8), (nrhs + rpb3 - 1) / rpb3);
     const T tw = (T)w;
-    // LDS staging pays on the 21-term Galerkin rows of large levels (measured:
-    // 134 vs 217 us per half-sweep on 256^2 with 32 sources); on small levels the
-    // extra synchronisation adds latency and the 7-term finest rows gain nothing.
-    if (L.g.dim == 2 && !L.fine && L.g.ncell >= 16384 && lds2d_enabled()) {
+    // LDS staging pays on the 21-term Galerkin rows of large levels (measured on
+    // 256^2: 133 vs 217 us per half-sweep with 32 sources, 55 vs 62 us with one);
+    // at 128^2 and below the block-wide synchronisation costs more than it saves
+    // (24 vs 13 us with one source), and the 7-term finest rows gain nothing.
+    if (L.g.dim == 2 && !L.fine && L.g.ncell >= 65536 && lds2d_enabled()) {
         const int tiles = ((L.g.n[0] + LT_X - 1) / LT_X) * ((L.g.n[1] + LT_Y - 1) / LT_Y);
         const int rpl = rhs_per_block((int64_t)tiles * 8, nrhs, 1);
         const dim3 gl(tiles, (nrhs + rpl - 1) / rpl);

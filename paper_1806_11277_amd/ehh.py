@@ -27,7 +27,7 @@ class ehh_problem_t(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32 * 3), ("h", ctypes.c_double),
                 ("omega", ctypes.c_double), ("shift", ctypes.c_double),
                 ("abl_cells", ctypes.c_int32 * 3), ("abl_max", ctypes.c_double),
-                ("atten0", ctypes.c_double)]
+                ("atten0", ctypes.c_double), ("mu_bar", ctypes.c_double), ("rho_bar", ctypes.c_double)]
 
 
 class ehh_options_t(ctypes.Structure):
@@ -56,6 +56,8 @@ _SIGS = {
     "ehh_vcycle": (_I, [_P, _I, _P, _P, _I, _P]),
     "ehh_precondition": (_I, [_P, _P, _P, _I, _P]),
     "ehh_solve": (_I, [_P, _P, _P, _I, ctypes.c_double, _I, ctypes.POINTER(ehh_stats_t), _P]),
+    "ehh_solve_adjoint": (_I, [_P, _P, _P, _I, ctypes.c_double, _I, ctypes.POINTER(ehh_stats_t), _P]),
+    "ehh_media_gradient": (_I, [_P, _P, _P, _I, _P, _P, _P, _I, _P]),
     "ehh_num_subdomains": (_I, [_P]),
     "ehh_subdomain_info": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I),
                                 ctypes.POINTER(_I)]),
@@ -129,7 +131,8 @@ class Solver:
                  atten0: float = 0.0, levels: int = 3, cycle: int = 1, nu1: int = 1, nu2: int = 1,
                  vanka: int = 1, precond_bits: int = 64, restart: int = 5,
                  dd_parts: Sequence[int] = (1, 1, 1), dd_overlap: int = 0, dd_pad: int = 0,
-                 dd_colors: int = 1, damping: Optional[Sequence[float]] = None, stream=None):
+                 dd_colors: int = 1, damping: Optional[Sequence[float]] = None,
+                 mu_bar: float = 0.0, rho_bar: float = 0.0, stream=None):
         import torch
         p = ehh_problem_t()
         p.dim = dim
@@ -139,6 +142,7 @@ class Solver:
             p.n[a] = int(nn[a])
             p.abl_cells[a] = int(ab[a])
         p.h, p.omega, p.shift, p.abl_max, p.atten0 = float(h), float(omega), float(shift), float(abl_max), float(atten0)
+        p.mu_bar, p.rho_bar = float(mu_bar), float(rho_bar)
         o = default_options()
         o.levels, o.cycle, o.nu1, o.nu2, o.vanka = levels, cycle, nu1, nu2, vanka
         o.precond_bits, o.restart = precond_bits, restart
@@ -218,6 +222,19 @@ class Solver:
         _check(st, allow=(EHH_OK,) if raise_on_fail else (EHH_OK, EHH_NOT_CONVERGED))
         return st, [dict(status=s.status, iters=s.iters, rel_res_est=s.rel_res_est,
                          rel_res_true=s.rel_res_true, conv_factor=s.conv_factor) for s in stats]
+
+    def solve_adjoint(self, g, y, tol=1e-6, maxit=500, stream=None, raise_on_fail=False):
+        nrhs = g.shape[0]
+        stats = (ehh_stats_t * nrhs)()
+        st = lib().ehh_solve_adjoint(self.handle, _ptr(g), _ptr(y), nrhs, float(tol), int(maxit), stats,
+                                     _stream(stream))
+        _check(st, allow=(EHH_OK,) if raise_on_fail else (EHH_OK, EHH_NOT_CONVERGED))
+        return st, [dict(status=s.status, iters=s.iters, rel_res_est=s.rel_res_est,
+                         rel_res_true=s.rel_res_true, conv_factor=s.conv_factor) for s in stats]
+
+    def media_gradient(self, y, x, grad_lambda, grad_mu, grad_rho, accumulate=False, stream=None):
+        _check(lib().ehh_media_gradient(self.handle, _ptr(y), _ptr(x), x.shape[0], _ptr(grad_lambda),
+                                        _ptr(grad_mu), _ptr(grad_rho), int(bool(accumulate)), _stream(stream)))
 
     def level_apply(self, sub, level, x, y, stream=None):
         _check(lib().ehh_level_apply(self.handle, sub, level, _ptr(x), _ptr(y), x.shape[0], _stream(stream)))

@@ -36,9 +36,31 @@ def test_binding_covers_the_header():
     assert sorted(ehh._SIGS) == _declared()
 
 
-def test_struct_layouts_match_header_sizes():
+def test_struct_layouts_match_the_c_compiler(tmp_path):
+    """Every field offset and struct size of the ctypes mirrors equals what gcc
+    computes from include/ehh.h."""
     import ctypes
+    import shutil
+    import subprocess
     from paper_1806_11277_amd import ehh
-    # int32 dim, n[3], double h, omega, shift, int32 abl[3], double abl_max, atten0
-    assert ctypes.sizeof(ehh.ehh_problem_t) == 72
-    assert ctypes.sizeof(ehh.ehh_stats_t) == 8 + 24
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    structs = [ehh.ehh_problem_t, ehh.ehh_options_t, ehh.ehh_stats_t]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ehh.h"', 'int main(void) {']
+    expect = []
+    for S in structs:
+        nm = S.__name__
+        lines.append(f'printf("%zu\\n", sizeof({nm}));')
+        expect.append(ctypes.sizeof(S))
+        for f, _ in S._fields_:
+            lines.append(f'printf("%zu\\n", offsetof({nm}, {f}));')
+            expect.append(getattr(S, f).offset)
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    assert got == expect

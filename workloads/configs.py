@@ -48,6 +48,8 @@ class Workload:
     dd_pad: int = 0
     dd_colors: int = 1
     sources_fn: Callable[["Workload"], List[Source]] = None
+    receivers_fn: Callable[["Workload"], List[Tuple[int, Tuple[int, ...]]]] = None
+    true_media_fn: Callable[[], dict] = None
 
     _media_cache: dict = dataclasses.field(default=None, repr=False)
 
@@ -179,6 +181,52 @@ _add(Workload(
     ppw=8.0, abl_cells=(6, 6, 6), shift=0.4, levels=3, damping=(0.5, 0.5),
     precond_bits=32, dd_parts=(2, 2, 2), dd_overlap=4, dd_pad=2, dd_colors=1,
     sources_fn=_src_lattice(2, 16, 8, 5, seed=7)))
+
+
+def _rec_line(count: int, spacing: int, first: int, depth: int):
+    def fn(w: Workload):
+        return [(0, (first + spacing * r, depth)) for r in range(count)]
+    return fn
+
+
+def unknown_offset(w: Workload, comp: int, pos) -> int:
+    """Position of an unknown in one right-hand side's vector: component blocks
+    [u_0, u_1, (u_2), p] in turn, each x fastest; u_k has n_k - 1 interior faces
+    along its axis (pos[k] = 1..n_k - 1)."""
+    dims = []
+    for k in range(w.dim + 1):
+        dims.append([w.n[a] - 1 if a == k else w.n[a] for a in range(w.dim)])
+    off = sum(int(np.prod(dims[k])) for k in range(comp))
+    d = dims[comp]
+    q = [pos[a] - 1 if a == comp else pos[a] for a in range(w.dim)]
+    idx = 0
+    for a in reversed(range(w.dim)):
+        idx = idx * d[a] + q[a]
+    return off + idx
+
+
+def receiver_offsets(w: Workload) -> np.ndarray:
+    return np.array([unknown_offset(w, c, p) for c, p in w.receivers_fn(w)], dtype=np.int64)
+
+
+_add(Workload(
+    name="c5_fwi256_batch16",
+    description="differentiable 2D solve: the c2 media generator at 256x256 (background model) "
+                "and the same with a +10% Gaussian anomaly in mu (true model), 16 x-forces at depth "
+                "5 (x = 8 + 16 s, seeded phases), 128 receivers of u_1 at depth 3 (x = 1 + 2 r), "
+                "least-squares data misfit",
+    dim=2, n=(256, 256), h=10.0, media_fn=lambda: M.heterogeneous_2d_media((256, 256)), ppw=10.0,
+    abl_cells=(20, 20), shift=0.5, levels=5, cycle=2, damping=(0.75, 0.5, 0.5, 0.5),
+    precond_bits=32, tol=1e-10, maxit=600, sources_fn=_src_line(16, 16, 8, 5, seed=8),
+    receivers_fn=_rec_line(128, 2, 1, 3), true_media_fn=lambda: M.fwi_true_media((256, 256))))
+
+_add(Workload(
+    name="c5s_fwi64_batch4",
+    description="c5 at 64x64 with 4 sources and 32 receivers (parity size)",
+    dim=2, n=(64, 64), h=10.0, media_fn=lambda: M.heterogeneous_2d_media((64, 64), corr_vp=5.0, corr_nu=16.0),
+    ppw=10.0, abl_cells=(8, 8), shift=0.5, levels=3, cycle=2, damping=(0.75, 0.5), precond_bits=64,
+    tol=1e-12, maxit=600, sources_fn=_src_line(4, 16, 8, 5, seed=8), receivers_fn=_rec_line(32, 2, 1, 3),
+    true_media_fn=lambda: M.fwi_true_media((64, 64), corr_vp=5.0, corr_nu=16.0)))
 
 
 def get_config(name: str) -> Workload:

@@ -91,3 +91,25 @@ def layered_3d_media(n, n_layers=8, seed_layers=4, seed_pert=5, seed_nu=6,
     rho = gardner_density(vp)
     lam, mu = lame_from_velocities(vp, vs, rho)
     return dict(lam=lam, mu=mu, rho=rho, vp=vp, vs=vs)
+
+
+def gaussian_anomaly(shape, centre, width: float, amplitude: float) -> np.ndarray:
+    """1 + amplitude * exp(-|x - centre|^2 / (2 width^2)) on the cell grid; centre
+    is given in cell coordinates (x, y[, z]), shape as the media arrays."""
+    grids = np.meshgrid(*[np.arange(v) + 0.5 for v in shape], indexing="ij")
+    r2 = np.zeros(shape)
+    for ax, g in enumerate(grids):
+        r2 = r2 + (g - centre[len(shape) - 1 - ax]) ** 2
+    return 1.0 + amplitude * np.exp(-r2 / (2.0 * width * width))
+
+
+def fwi_true_media(n, amplitude=0.10, **kw):
+    """The 2D heterogeneous medium with a smooth Gaussian anomaly in mu (the
+    'true' model of an inversion test); lambda and rho are unchanged."""
+    m = heterogeneous_2d_media(n, **kw)
+    shape = tuple(reversed(n))
+    bump = gaussian_anomaly(shape, (n[0] / 2.0, 0.4 * n[1]), n[0] / 16.0, amplitude)
+    out = dict(m)
+    out["mu"] = m["mu"] * bump
+    out["vs"] = np.sqrt(out["mu"] / m["rho"])
+    return out
