@@ -61,7 +61,7 @@ def run_gpu(w, steps, warmup, tol):
     m = w.media()
     dev = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda").contiguous()
     lam, mu, rho = dev(m["lam"]), dev(m["mu"]), dev(m["rho"])
-    opts = dict(levels=w.levels, cycle=w.cycle, nu1=w.nu1, nu2=w.nu2, vanka=w.vanka,
+    opts = dict(levels=w.levels, cycle=w.cycle, cycle_level=w.cycle_level, nu1=w.nu1, nu2=w.nu2, vanka=w.vanka,
                 precond_bits=w.precond_bits, restart=w.restart, dd_parts=w.dd_parts,
                 dd_overlap=w.dd_overlap, dd_pad=w.dd_pad, dd_colors=w.dd_colors, damping=w.damping,
                 abl_max=w.abl_max, atten0=w.atten0)
@@ -100,11 +100,22 @@ def run_gpu(w, steps, warmup, tol):
     return total, results, B, X
 
 
+def visits_per_cycle(w):
+    """Visits of each non-coarsest level in one cycle: a level makes `cycle`
+    recursive calls from cycle_level on (one call above it and into the
+    coarsest level, whose exact solve a second call would only repeat)."""
+    v = [1]
+    for l in range(w.levels - 2):
+        calls = 1 if (l + 1 == w.levels - 1 or l < w.cycle_level) else w.cycle
+        v.append(v[-1] * calls)
+    return v
+
+
 def kernel_roofline(w, reps=30):
     """The dominant kernel is the red-black Vanka half-sweep.  Every level's
     half-sweep is timed with HIP events on the stream the library launches on,
-    and the levels are weighted by their launch count in one cycle (V: 4 per
-    level; W: 4 * 2^l on level l)."""
+    and the levels are weighted by their launch count in one cycle
+    (2 (nu1 + nu2) half-sweeps per visit)."""
     import torch
     from paper_1806_11277_amd import ehh
     S = ehh.solver_for_workload(w)
@@ -129,7 +140,7 @@ def kernel_roofline(w, reps=30):
         torch.cuda.synchronize()
         t = ev0.elapsed_time(ev1) / reps / 1e3
         nb = level_bytes(info, w.precond_bits, nrhs, l == 0, w.dim)
-        launches = 4 * (2 ** l if w.cycle == 2 else 1)
+        launches = 2 * (w.nu1 + w.nu2) * visits_per_cycle(w)[l]
         rows.append(dict(level=l, n=info["n"][:w.dim], bytes=nb, us=t * 1e6, gbs=nb / t / 1e9,
                          launches_per_cycle=launches))
         tot_b += launches * nb
@@ -159,7 +170,7 @@ def cpu_baseline(w, gpu_iters, budget_s=20.0):
                       w.atten0, shift=w.shift)
     A = pb.matrix()
     H = mg.build_hierarchy(pb, w.levels, list(w.damping), economic=(w.vanka == 0), cycle=w.cycle,
-                           nu1=w.nu1, nu2=w.nu2)
+                           nu1=w.nu1, nu2=w.nu2, cycle_level=w.cycle_level)
     t_setup = time.perf_counter() - t0
     b = disc.point_source_vector(w.n, w.sources()[:1])
     v = b / np.linalg.norm(b)
@@ -229,6 +240,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "grid": list(w.n), "unknowns": int(B.shape[1] // 2),
                    "nrhs": nrhs, "levels": w.levels, "cycle": "V" if w.cycle == 1 else "W",
+                   "cycle_level": w.cycle_level,
                    "nu": [w.nu1, w.nu2], "vanka": "full" if w.vanka else "economic",
                    "shift": w.shift, "precond_bits": w.precond_bits, "restart": w.restart,
                    "dd_parts": list(w.dd_parts[:w.dim]), "tol": a.tol},

@@ -87,7 +87,10 @@ typedef struct {
 typedef struct {
     int32_t levels;         /* multigrid levels, 1..EHH_MAX_LEVELS; every (sub)domain
                                axis must be divisible by 2^(levels-1) */
-    int32_t cycle;          /* 1 = V-cycle, 2 = W-cycle */
+    int32_t cycle;          /* recursive calls per coarse-grid correction: 1 = V, 2 = W */
+    int32_t cycle_level;    /* levels >= cycle_level make `cycle` calls, the finer ones a
+                               single call (0: every level; e.g. 1 = V on the finest
+                               level, W below) */
     int32_t nu1, nu2;       /* red-black relaxation steps before / after the correction */
     int32_t vanka;          /* 1 = full cell block, 0 = economic (diagonal u part) */
     int32_t precond_bits;   /* 64: complex128 cycle; 32: complex64 cycle (FP32
@@ -109,7 +112,7 @@ typedef struct {
     double  conv_factor;    /* (r_k / r_5)^(1/(k-5)) over the estimates (section 5.4) */
 } ehh_stats_t;
 
-/* Defaults: 3 levels, V(1,1), full Vanka, damping 0.75/0.5/0.25..., 64-bit
+/* Defaults: 3 levels, V(1,1) (cycle_level 0), full Vanka, damping 0.75/0.5/0.25..., 64-bit
  * cycle, restart 5, no domain decomposition. */
 void ehh_default_options(ehh_options_t* opt);
 

@@ -163,7 +163,7 @@ class Hierarchy:
     """Galerkin hierarchy of a shifted operator A0 on grid n."""
 
     def __init__(self, A0, n, levels, damping: Sequence[float], economic=False,
-                 cycle=1, nu1=1, nu2=1):
+                 cycle=1, nu1=1, nu2=1, cycle_level=0):
         self.n = [tuple(n)]
         self.A = [sp.csr_matrix(A0)]
         self.P = []
@@ -179,6 +179,7 @@ class Hierarchy:
         self.damping = list(damping)
         self.economic = economic
         self.cycle_index = cycle
+        self.cycle_level = cycle_level
         self.nu1, self.nu2 = nu1, nu2
         self.blocks = []
         for l in range(levels - 1):
@@ -199,7 +200,7 @@ class Hierarchy:
             e = self.relax(l, b, e, 1)
         rc = self.P[l].T @ (b - self.A[l] @ e)
         ec = None
-        for _ in range(self.cycle_index):
+        for _ in range(self.cycle_index if l >= self.cycle_level else 1):
             ec = self.cycle(rc, l + 1, ec)
         e = e + self.P[l] @ ec
         for _ in range(self.nu2):
@@ -209,6 +210,6 @@ class Hierarchy:
 
 
 def build_hierarchy(problem: disc.Problem, levels, damping, economic=False, cycle=1,
-                    nu1=1, nu2=1):
+                    nu1=1, nu2=1, cycle_level=0):
     return Hierarchy(problem.matrix(shifted=True), problem.n, levels, damping,
-                     economic, cycle, nu1, nu2)
+                     economic, cycle, nu1, nu2, cycle_level)

@@ -41,7 +41,7 @@ class SolveSpec:
 
 
 def spec_for_workload(w, mu_bar=0.0, rho_bar=0.0, tol=None, maxit=None, **solver_over) -> SolveSpec:
-    kw = dict(levels=w.levels, cycle=w.cycle, nu1=w.nu1, nu2=w.nu2, vanka=w.vanka,
+    kw = dict(levels=w.levels, cycle=w.cycle, cycle_level=w.cycle_level, nu1=w.nu1, nu2=w.nu2, vanka=w.vanka,
               precond_bits=w.precond_bits, restart=w.restart, dd_parts=w.dd_parts,
               dd_overlap=w.dd_overlap, dd_pad=w.dd_pad, dd_colors=w.dd_colors, damping=w.damping)
     kw.update(solver_over)

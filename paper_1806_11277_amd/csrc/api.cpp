@@ -292,7 +292,7 @@ int32_t cycle(ehh_ctx* c, Sub& S, int l, const T* b, T* e, bool zero_init, int n
     }
     // gamma_c recursive calls (V: 1, W: 2); the coarsest solve is exact, so a second
     // call there with the same right-hand side would repeat the same result.
-    const int ncall = (l + 1 == nl - 1) ? 1 : c->opt.cycle;
+    const int ncall = (l + 1 == nl - 1 || l < c->opt.cycle_level) ? 1 : c->opt.cycle;
     for (int k = 0; k < ncall; ++k) CHK(cycle<T>(c, S, l + 1, (const T*)C.b, (T*)C.e, k == 0, nrhs, s));
     HIPCHK(launch_prolong<T>(L.g, C.g, (const T*)C.e, e, nrhs, s));
     for (int it = 0; it < c->opt.nu2; ++it) {
@@ -389,6 +389,7 @@ int32_t check_problem(const ehh_problem_t* p, const ehh_options_t* o) {
         return fail(EHH_ERR_INVALID, "mu_bar, rho_bar must be finite and >= 0 (0 = media means)");
     if (o->levels < 1 || o->levels > EHH_MAX_LEVELS) return fail(EHH_ERR_INVALID, "levels out of range");
     if (o->cycle != 1 && o->cycle != 2) return fail(EHH_ERR_INVALID, "cycle must be 1 (V) or 2 (W)");
+    if (o->cycle_level < 0 || o->cycle_level >= EHH_MAX_LEVELS) return fail(EHH_ERR_INVALID, "cycle_level out of range");
     if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 > 8 || o->nu2 > 8) return fail(EHH_ERR_INVALID, "nu1, nu2 in [0, 8]");
     if (o->vanka != 0 && o->vanka != 1) return fail(EHH_ERR_INVALID, "vanka must be 0 or 1");
     if (o->precond_bits != 32 && o->precond_bits != 64) return fail(EHH_ERR_INVALID, "precond_bits must be 32 or 64");
@@ -500,15 +501,34 @@ int32_t build_hierarchy(ehh_ctx* c, Sub& S, const double* lam, const double* mu,
     if ((double)nc * nc * 16.0 > 8.0e9) return fail(EHH_ERR_UNSUPPORTED, "coarsest grid too large for a dense inverse");
     CHK(c->alloc((void**)&S.inv, sizeof(double) * 2 * nc * nc));
     HIPCHK(launch_dense_assemble(Lc.g, L == 1 ? st0 : Lc.coef64, S.inv, s));
-    double* work = nullptr;
     int* piv = nullptr;
-    CHK(c->alloc((void**)&work, sizeof(double) * 2 * nc));
-    CHK(c->alloc((void**)&piv, sizeof(int) * nc));
+    CHK(c->alloc((void**)&piv, sizeof(int) * (nc + 1)));
     lg.mark("dense assemble");
-    HIPCHK(launch_dense_invert(S.inv, nc, 1, work, piv, s));
+    HIPCHK(launch_dense_invert(S.inv, nc, piv, piv + nc, s));
+    std::vector<int> hp(nc + 1);
+    HIPCHK(hipMemcpyAsync(hp.data(), piv, sizeof(int) * (nc + 1), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     lg.mark("dense invert");
-    c->release(work);
+    if (hp[nc]) {
+        c->release(piv);
+        return fail(EHH_ERR_BREAKDOWN, "singular coarsest operator");
+    }
+    // A^{-1} = (Pi A)^{-1} Pi: column q[k] of A^{-1} is column k of the result,
+    // with q the row order after the interchanges.
+    {
+        std::vector<int> q(nc), qinv(nc);
+        for (int64_t k = 0; k < nc; ++k) q[k] = (int)k;
+        for (int64_t k = 0; k < nc; ++k) std::swap(q[k], q[hp[k]]);
+        for (int64_t k = 0; k < nc; ++k) qinv[q[k]] = (int)k;
+        HIPCHK(hipMemcpyAsync(piv, qinv.data(), sizeof(int) * nc, hipMemcpyHostToDevice, s));
+        double* inv = nullptr;
+        CHK(c->alloc((void**)&inv, sizeof(double) * 2 * nc * nc));
+        HIPCHK(launch_permute_columns(S.inv, inv, nc, piv, s));
+        HIPCHK(hipStreamSynchronize(s));
+        c->release(S.inv);
+        S.inv = inv;
+        lg.mark("column permutation");
+    }
     c->release(piv);
     c->release(st0);
     if (c->bits() == 32) {

@@ -55,9 +55,13 @@ hipError_t launch_materialise(const Geo& g, const FineCoef<double>& c, double* s
 hipError_t launch_galerkin(const Geo& gf, const double* stf, const Geo& gc, double* stc, hipStream_t s);
 // Dense row-major complex (re, im interleaved) matrix of a stencil-format level.
 hipError_t launch_dense_assemble(const Geo& g, const double* st, double* dense, hipStream_t s);
-// In-place Gauss-Jordan inversion of `batch` dense n x n complex matrices with
-// partial pivoting; work: 2 * n * batch doubles, piv: n * batch ints.
-hipError_t launch_dense_invert(double* dense, int64_t n, int batch, double* work, int* piv, hipStream_t s);
+// In-place blocked Gauss-Jordan inversion of a dense n x n complex matrix,
+// pivoting inside 64 x 64 diagonal blocks: leaves (Pi A)^{-1}, with the row
+// interchanges in piv[0..n) (row k swapped with row piv[k], in order) and
+// *flag = 1 on a zero pivot.
+hipError_t launch_dense_invert(double* dense, int64_t n, int* piv, int* flag, hipStream_t s);
+// out[i][j] = X[i][qinv[j]] (n x n complex, out-of-place).
+hipError_t launch_permute_columns(const double* X, double* out, int64_t n, const int* qinv, hipStream_t s);
 // e = inv r for a batch of right-hand sides (FP64 accumulation).
 template <typename T>
 hipError_t launch_coarse_apply(const double* inv, int64_t n, const T* r, T* e, int nrhs, hipStream_t s);

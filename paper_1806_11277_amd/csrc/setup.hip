@@ -411,121 +411,257 @@ hipError_t launch_dense_assemble(const Geo& g, const double* st, double* dense, 
     return hipGetLastError();
 }
 
-// Gauss-Jordan step k, part 1 (one block per matrix): choose the pivot row of
-// column k among rows >= k, swap it into row k, scale row k by 1/pivot with the
-// pivot position replaced by 1 first (so that column k accumulates the inverse),
-// and save column k (the elimination factors) before zeroing it.
-__global__ __launch_bounds__(1024) void k_gj_pivot(double* __restrict__ Ab, int64_t n, int64_t k,
-                                                   double* __restrict__ workb, int* __restrict__ pivb) {
-    double* A = Ab + (int64_t)blockIdx.y * 2 * n * n;
-    double* f = workb + (int64_t)blockIdx.y * 2 * n;
-    int* piv = pivb + (int64_t)blockIdx.y * n;
-    __shared__ double bv[1024];
-    __shared__ int bi[1024];
-    double best = -1.0;
-    int bidx = (int)k;
-    for (int64_t i = k + threadIdx.x; i < n; i += blockDim.x) {
-        const double re = A[2 * (i * n + k)], im = A[2 * (i * n + k) + 1];
-        const double m = re * re + im * im;
-        if (m > best) {
-            best = m;
-            bidx = (int)i;
-        }
+// ------------------------------------------------------------------ dense inverse
+// Blocked Gauss-Jordan inversion of an n x n complex matrix (row-major, re/im
+// interleaved), in place, for the exact coarsest solve of the multigrid cycle.
+// Panels of GJ_NB indices K are swept in turn: W = A[K,K]^{-1} by Gauss-Jordan
+// with partial pivoting inside the block (one workgroup, in LDS), the block's
+// row interchanges applied to the rest of those rows, then
+//      A[K,J] <- W A[K,J],  A[I,J] <- A[I,J] - A[I,K] A[K,J],
+//      A[I,K] <- -A[I,K] W,  A[K,K] <- W   (I, J outside K),
+// the block form of the scalar Gauss-Jordan step, as 64 x 64 output tiles with
+// 16-deep k chunks staged in LDS.  Pivot rows are sought inside the diagonal
+// block only: for the shifted Galerkin operators every leading principal
+// submatrix in the [u; p] ordering is nonsingular (the displacement block has
+// a positive-definite imaginary part, omega^2 (gamma + alpha) times a mass
+// matrix, and the pressure Schur complement stays definite), so elimination in
+// this order needs no interchange for existence; the in-block search guards
+// against small pivots.  The result is (Pi A)^{-1} for the accumulated row
+// interchanges Pi; the caller undoes Pi as a column permutation
+// (launch_permute_columns).
+constexpr int GJ_NB = 64;
+
+__device__ inline void cmul_acc(double& cr, double& ci, double ar, double ai, double br, double bi) {
+    cr = fma(ar, br, fma(-ai, bi, cr));
+    ci = fma(ar, bi, fma(ai, br, ci));
+}
+
+// Apply the block's row interchanges (in order) to the columns outside K (the
+// block itself already holds the inverse of its interchanged rows).
+__global__ __launch_bounds__(256) void k_swap_rows(double* __restrict__ A, int64_t n, int64_t k0, int kb,
+                                                   const int* __restrict__ piv) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n || (j >= k0 && j < k0 + kb)) return;
+    for (int c = 0; c < kb; ++c) {
+        const int64_t p = piv[k0 + c];
+        const int64_t k = k0 + c;
+        if (p == k) continue;
+        const double ar = A[2 * (k * n + j)], ai = A[2 * (k * n + j) + 1];
+        A[2 * (k * n + j)] = A[2 * (p * n + j)];
+        A[2 * (k * n + j) + 1] = A[2 * (p * n + j) + 1];
+        A[2 * (p * n + j)] = ar;
+        A[2 * (p * n + j) + 1] = ai;
     }
-    bv[threadIdx.x] = best;
-    bi[threadIdx.x] = bidx;
+}
+
+// A[K,K] <- (Pi_K A[K,K])^{-1} by Gauss-Jordan with partial pivoting inside the
+// block (one workgroup, the block in LDS); piv[k0 + k] = row swapped with k0 + k.
+__global__ __launch_bounds__(256) void k_diag_inverse(double* __restrict__ A, int64_t n, int64_t k0, int kb,
+                                                      int* __restrict__ piv, int* __restrict__ flag) {
+    __shared__ double W[GJ_NB * GJ_NB * 2];
+    __shared__ double fc[GJ_NB * 2], rr[GJ_NB * 2];
+    __shared__ int prow;
+    const int t = threadIdx.x;
+    for (int e = t; e < kb * kb; e += blockDim.x) {
+        const int i = e / kb, j = e % kb;
+        W[2 * (i * GJ_NB + j)] = A[2 * ((k0 + i) * n + k0 + j)];
+        W[2 * (i * GJ_NB + j) + 1] = A[2 * ((k0 + i) * n + k0 + j) + 1];
+    }
     __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            const double o = bv[threadIdx.x + w];
-            const int oi = bi[threadIdx.x + w];
-            if (o > bv[threadIdx.x] || (o == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
-                bv[threadIdx.x] = o;
-                bi[threadIdx.x] = oi;
+    for (int k = 0; k < kb; ++k) {
+        if (t < 64) {   // pivot search by the first wavefront: largest modulus, lowest row on ties
+            double m = -1.0;
+            int idx = k;
+            if (t >= k && t < kb) {
+                const double xr = W[2 * (t * GJ_NB + k)], xi = W[2 * (t * GJ_NB + k) + 1];
+                m = xr * xr + xi * xi;
+                idx = t;
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                const double om = __shfl_xor(m, o, 64);
+                const int oi = __shfl_xor(idx, o, 64);
+                if (om > m || (om == m && oi < idx)) {
+                    m = om;
+                    idx = oi;
+                }
+            }
+            if (t == 0) {
+                prow = idx;
+                piv[k0 + k] = (int)(k0 + idx);
+            }
+        }
+        __syncthreads();
+        const int p = prow;
+        if (p != k && t < kb) {
+            const double ar = W[2 * (k * GJ_NB + t)], ai = W[2 * (k * GJ_NB + t) + 1];
+            W[2 * (k * GJ_NB + t)] = W[2 * (p * GJ_NB + t)];
+            W[2 * (k * GJ_NB + t) + 1] = W[2 * (p * GJ_NB + t) + 1];
+            W[2 * (p * GJ_NB + t)] = ar;
+            W[2 * (p * GJ_NB + t) + 1] = ai;
+        }
+        __syncthreads();
+        const double pr = W[2 * (k * GJ_NB + k)], pi = W[2 * (k * GJ_NB + k) + 1];
+        const double dd = pr * pr + pi * pi;
+        if (t == 0 && !(dd > 0.0)) *flag = 1;
+        const double ir = pr / dd, ii = -pi / dd;
+        if (t < kb) {
+            fc[2 * t] = W[2 * (t * GJ_NB + k)];
+            fc[2 * t + 1] = W[2 * (t * GJ_NB + k) + 1];
+            if (t == k) {
+                rr[2 * t] = ir;
+                rr[2 * t + 1] = ii;
+            } else {
+                const double ar = W[2 * (k * GJ_NB + t)], ai = W[2 * (k * GJ_NB + t) + 1];
+                rr[2 * t] = ar * ir - ai * ii;
+                rr[2 * t + 1] = ar * ii + ai * ir;
+            }
+        }
+        __syncthreads();
+        for (int e = t; e < kb * kb; e += blockDim.x) {
+            const int i = e / kb, j = e % kb;
+            double* w = W + 2 * (i * GJ_NB + j);
+            if (i == k) {
+                w[0] = rr[2 * j];
+                w[1] = rr[2 * j + 1];
+            } else if (j == k) {
+                const double fr = fc[2 * i], fi = fc[2 * i + 1];
+                w[0] = -(fr * ir - fi * ii);
+                w[1] = -(fr * ii + fi * ir);
+            } else {
+                const double fr = fc[2 * i], fi = fc[2 * i + 1];
+                const double br = rr[2 * j], bi = rr[2 * j + 1];
+                w[0] -= fr * br - fi * bi;
+                w[1] -= fr * bi + fi * br;
             }
         }
         __syncthreads();
     }
-    const int p = bi[0];
-    if (threadIdx.x == 0) piv[k] = p;
-    if (p != k) {
-        for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
-            const double ar = A[2 * (k * n + j)], ai = A[2 * (k * n + j) + 1];
-            A[2 * (k * n + j)] = A[2 * (p * n + j)];
-            A[2 * (k * n + j) + 1] = A[2 * (p * n + j) + 1];
-            A[2 * (p * n + j)] = ar;
-            A[2 * (p * n + j) + 1] = ai;
-        }
-    }
-    __syncthreads();
-    const double pr = A[2 * (k * n + k)], pi = A[2 * (k * n + k) + 1];
-    const double dd = pr * pr + pi * pi;
-    const double ir = pr / dd, ii = -pi / dd;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        A[2 * (k * n + k)] = 1.0;
-        A[2 * (k * n + k) + 1] = 0.0;
-    }
-    __syncthreads();
-    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
-        const double ar = A[2 * (k * n + j)], ai = A[2 * (k * n + j) + 1];
-        A[2 * (k * n + j)] = ar * ir - ai * ii;
-        A[2 * (k * n + j) + 1] = ar * ii + ai * ir;
-    }
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-        if (i == k) {
-            f[2 * i] = 0.0;
-            f[2 * i + 1] = 0.0;
-            continue;
-        }
-        f[2 * i] = A[2 * (i * n + k)];
-        f[2 * i + 1] = A[2 * (i * n + k) + 1];
-        A[2 * (i * n + k)] = 0.0;
-        A[2 * (i * n + k) + 1] = 0.0;
+    for (int e = t; e < kb * kb; e += blockDim.x) {
+        const int i = e / kb, j = e % kb;
+        A[2 * ((k0 + i) * n + k0 + j)] = W[2 * (i * GJ_NB + j)];
+        A[2 * ((k0 + i) * n + k0 + j) + 1] = W[2 * (i * GJ_NB + j) + 1];
     }
 }
 
-// Part 2: A[i][j] -= f[i] * A[k][j] for i != k (column k included: it receives
-// -f[i]/pivot).
-__global__ __launch_bounds__(256) void k_gj_elim(double* __restrict__ Ab, int64_t n, int64_t k,
-                                                 const double* __restrict__ workb) {
-    double* A = Ab + (int64_t)blockIdx.z * 2 * n * n;
-    const double* f = workb + (int64_t)blockIdx.z * 2 * n;
+// C[i][j] = (beta_one ? C[i][j] : 0) + alpha sum_k A[i][k] B[k][j] on one 64 x 64
+// output tile (complex, interleaved, row-major; leading dimensions in complex
+// elements).  Rows in [rh_lo, rh_hi) and columns in [ch_lo, ch_hi) of C are left
+// untouched.  All reads of a tile's operands finish before its writes, so C may
+// alias the operand that only this tile reads.
+__global__ __launch_bounds__(256) void k_zgemm_tile(double* C, int64_t ldc, const double* A, int64_t lda,
+                                                    const double* B, int64_t ldb, int64_t m, int64_t ncol, int kdim,
+                                                    double alpha, int beta_one, int64_t rh_lo, int64_t rh_hi,
+                                                    int64_t ch_lo, int64_t ch_hi) {
+    const int64_t row0 = (int64_t)blockIdx.y * 64, col0 = (int64_t)blockIdx.x * 64;
+    if ((row0 >= rh_lo && row0 + 64 <= rh_hi) || (col0 >= ch_lo && col0 + 64 <= ch_hi)) return;
+    __shared__ double As[16][65 * 2];
+    __shared__ double Bs[16][64 * 2];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    double cr[4][4], ci[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cr[i][j] = ci[i][j] = 0.0;
+    for (int k0 = 0; k0 < kdim; k0 += 16) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            const int r = e >> 4, kk = e & 15;
+            const int64_t gr = row0 + r;
+            const int gk = k0 + kk;
+            double vr = 0.0, vi = 0.0;
+            if (gr < m && gk < kdim) {
+                vr = A[2 * (gr * lda + gk)];
+                vi = A[2 * (gr * lda + gk) + 1];
+            }
+            As[kk][2 * r] = vr;
+            As[kk][2 * r + 1] = vi;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            const int kk = e >> 6, cc = e & 63;
+            const int gk = k0 + kk;
+            const int64_t gc = col0 + cc;
+            double vr = 0.0, vi = 0.0;
+            if (gk < kdim && gc < ncol) {
+                vr = B[2 * ((int64_t)gk * ldb + gc)];
+                vi = B[2 * ((int64_t)gk * ldb + gc) + 1];
+            }
+            Bs[kk][2 * cc] = vr;
+            Bs[kk][2 * cc + 1] = vi;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < 16; ++kk) {
+            double ar[4], ai[4], br[4], bi[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                ar[i] = As[kk][2 * (ty + 16 * i)];
+                ai[i] = As[kk][2 * (ty + 16 * i) + 1];
+                br[i] = Bs[kk][2 * (tx + 16 * i)];
+                bi[i] = Bs[kk][2 * (tx + 16 * i) + 1];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) cmul_acc(cr[i][j], ci[i][j], ar[i], ai[i], br[j], bi[j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t r = row0 + ty + 16 * i;
+        if (r >= m || (r >= rh_lo && r < rh_hi)) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t cidx = col0 + tx + 16 * j;
+            if (cidx >= ncol || (cidx >= ch_lo && cidx < ch_hi)) continue;
+            double* o = C + 2 * (r * ldc + cidx);
+            const double o0 = beta_one ? o[0] : 0.0, o1 = beta_one ? o[1] : 0.0;
+            o[0] = o0 + alpha * cr[i][j];
+            o[1] = o1 + alpha * ci[i][j];
+        }
+    }
+}
+
+// out[i][j] = X[i][qinv[j]] (the column permutation that turns (Pi A)^{-1} into A^{-1}).
+__global__ __launch_bounds__(256) void k_permute_columns(const double* __restrict__ X, double* __restrict__ out,
+                                                         int64_t n, const int* __restrict__ qinv) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t i0 = (int64_t)blockIdx.y * 16;
+    const int64_t i = blockIdx.y;
     if (j >= n) return;
-    const double kr = A[2 * (k * n + j)], ki = A[2 * (k * n + j) + 1];
-    for (int64_t i = i0; i < i0 + 16 && i < n; ++i) {
-        if (i == k) continue;
-        const double fr = f[2 * i], fi = f[2 * i + 1];
-        A[2 * (i * n + j)] -= fr * kr - fi * ki;
-        A[2 * (i * n + j) + 1] -= fr * ki + fi * kr;
-    }
+    const int64_t src = qinv[j];
+    out[2 * (i * n + j)] = X[2 * (i * n + src)];
+    out[2 * (i * n + j) + 1] = X[2 * (i * n + src) + 1];
 }
 
-// Undo the row interchanges as column interchanges, last step first.
-__global__ __launch_bounds__(256) void k_gj_unpivot(double* __restrict__ Ab, int64_t n, const int* __restrict__ pivb) {
-    double* A = Ab + (int64_t)blockIdx.y * 2 * n * n;
-    const int* piv = pivb + (int64_t)blockIdx.y * n;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    for (int64_t k = n - 1; k >= 0; --k) {
-        const int64_t p = piv[k];
-        if (p == k) continue;
-        const double ar = A[2 * (i * n + k)], ai = A[2 * (i * n + k) + 1];
-        A[2 * (i * n + k)] = A[2 * (i * n + p)];
-        A[2 * (i * n + k) + 1] = A[2 * (i * n + p) + 1];
-        A[2 * (i * n + p)] = ar;
-        A[2 * (i * n + p) + 1] = ai;
+hipError_t launch_dense_invert(double* A, int64_t n, int* piv, int* flag, hipStream_t s) {
+    hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), s);
+    if (e != hipSuccess) return e;
+    for (int64_t k0 = 0; k0 < n; k0 += GJ_NB) {
+        const int kb = (int)std::min<int64_t>(GJ_NB, n - k0);
+        hipLaunchKernelGGL(k_diag_inverse, 1, 256, 0, s, A, n, k0, kb, piv, flag);
+        hipLaunchKernelGGL(k_swap_rows, nblk(n), 256, 0, s, A, n, k0, kb, piv);
+        double* AK = A + 2 * k0 * n;           // rows K
+        double* AKK = AK + 2 * k0;             // the inverted block W
+        double* ACK = A + 2 * k0;              // columns K
+        const unsigned tiles = (unsigned)((n + 63) / 64);
+        // A[K,J] <- W A[K,J]
+        hipLaunchKernelGGL(k_zgemm_tile, dim3(tiles, 1), 256, 0, s, AK, n, AKK, n, AK, n, (int64_t)kb, n, kb, 1.0, 0,
+                           (int64_t)0, (int64_t)0, k0, k0 + kb);
+        // A[I,J] <- A[I,J] - A[I,K] A[K,J]
+        hipLaunchKernelGGL(k_zgemm_tile, dim3(tiles, tiles), 256, 0, s, A, n, ACK, n, AK, n, n, n, kb, -1.0, 1, k0,
+                           k0 + kb, k0, k0 + kb);
+        // A[I,K] <- -A[I,K] W
+        hipLaunchKernelGGL(k_zgemm_tile, dim3(1, tiles), 256, 0, s, ACK, n, ACK, n, AKK, n, n, (int64_t)kb, kb, -1.0,
+                           0, k0, k0 + kb, (int64_t)0, (int64_t)0);
     }
+    return hipGetLastError();
 }
 
-hipError_t launch_dense_invert(double* dense, int64_t n, int batch, double* work, int* piv, hipStream_t s) {
-    for (int64_t k = 0; k < n; ++k) {
-        hipLaunchKernelGGL(k_gj_pivot, dim3(1, batch), 1024, 0, s, dense, n, k, work, piv);
-        hipLaunchKernelGGL(k_gj_elim, dim3(nblk(n), (unsigned)((n + 15) / 16), batch), 256, 0, s, dense, n, k, work);
-    }
-    hipLaunchKernelGGL(k_gj_unpivot, dim3(nblk(n), batch), 256, 0, s, dense, n, piv);
+hipError_t launch_permute_columns(const double* X, double* out, int64_t n, const int* qinv, hipStream_t s) {
+    hipLaunchKernelGGL(k_permute_columns, dim3(nblk(n), (unsigned)n), 256, 0, s, X, out, n, qinv);
     return hipGetLastError();
 }
 
@@ -573,9 +709,87 @@ __global__ __launch_bounds__(256) void k_coarse_apply(const double* __restrict__
     }
 }
 
+// Many right-hand sides: a workgroup owns 512/W rows and W right-hand sides and
+// walks the columns in chunks of 64, staging the rows' chunk of the inverse and
+// the vectors' chunk (as FP64) in LDS, so that the matrix is read from HBM once
+// per W right-hand sides instead of once per 4.  Thread: one right-hand side,
+// two rows; the row values are LDS broadcasts within a wavefront.
+template <typename T, int W>
+__global__ __launch_bounds__(256) void k_coarse_apply_multi(const double* __restrict__ inv, int64_t n,
+                                                            const T* __restrict__ r, T* __restrict__ e, int nrhs) {
+    constexpr int ROWS = 512 / W;
+    constexpr int KC = 64;
+    __shared__ double Ms[ROWS][KC * 2];
+    __shared__ double Xs[KC][W * 2];
+    const int t = threadIdx.x;
+    const int q = t % W, rg = t / W;
+    const int64_t i0 = (int64_t)blockIdx.x * ROWS;
+    const int q0 = blockIdx.y * W;
+    double a0r = 0.0, a0i = 0.0, a1r = 0.0, a1i = 0.0;
+    for (int64_t j0 = 0; j0 < n; j0 += KC) {
+        for (int el = t; el < ROWS * KC; el += 256) {
+            const int rr = el / KC, cc = el % KC;
+            const int64_t gi = i0 + rr, gj = j0 + cc;
+            double vr = 0.0, vi = 0.0;
+            if (gi < n && gj < n) {
+                vr = inv[2 * (gi * n + gj)];
+                vi = inv[2 * (gi * n + gj) + 1];
+            }
+            Ms[rr][2 * cc] = vr;
+            Ms[rr][2 * cc + 1] = vi;
+        }
+        for (int el = t; el < KC * W; el += 256) {
+            const int kk = el % KC, qq = el / KC;
+            const int64_t gj = j0 + kk;
+            double vr = 0.0, vi = 0.0;
+            if (gj < n && q0 + qq < nrhs) {
+                const T* rv = r + (int64_t)(q0 + qq) * 2 * n;
+                vr = (double)rv[gj];
+                vi = (double)rv[n + gj];
+            }
+            Xs[kk][2 * qq] = vr;
+            Xs[kk][2 * qq + 1] = vi;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int kk = 0; kk < KC; ++kk) {
+            const double xr = Xs[kk][2 * q], xi = Xs[kk][2 * q + 1];
+            const double m0r = Ms[2 * rg][2 * kk], m0i = Ms[2 * rg][2 * kk + 1];
+            const double m1r = Ms[2 * rg + 1][2 * kk], m1i = Ms[2 * rg + 1][2 * kk + 1];
+            a0r = fma(m0r, xr, fma(-m0i, xi, a0r));
+            a0i = fma(m0r, xi, fma(m0i, xr, a0i));
+            a1r = fma(m1r, xr, fma(-m1i, xi, a1r));
+            a1i = fma(m1r, xi, fma(m1i, xr, a1i));
+        }
+        __syncthreads();
+    }
+    if (q0 + q >= nrhs) return;
+    T* ev = e + (int64_t)(q0 + q) * 2 * n;
+    const int64_t g0 = i0 + 2 * rg;
+    if (g0 < n) {
+        ev[g0] = (T)a0r;
+        ev[n + g0] = (T)a0i;
+    }
+    if (g0 + 1 < n) {
+        ev[g0 + 1] = (T)a1r;
+        ev[n + g0 + 1] = (T)a1i;
+    }
+}
+
 template <typename T>
 hipError_t launch_coarse_apply(const double* inv, int64_t n, const T* r, T* e, int nrhs, hipStream_t s) {
-    hipLaunchKernelGGL((k_coarse_apply<T>), dim3(nblk(n * 64), (nrhs + 3) / 4), 256, 0, s, inv, n, r, e, nrhs);
+    if (nrhs <= 4) {
+        hipLaunchKernelGGL((k_coarse_apply<T>), dim3(nblk(n * 64), (nrhs + 3) / 4), 256, 0, s, inv, n, r, e, nrhs);
+    } else if (nrhs <= 8) {
+        hipLaunchKernelGGL((k_coarse_apply_multi<T, 8>), dim3((unsigned)((n + 63) / 64), 1), 256, 0, s, inv, n, r,
+                           e, nrhs);
+    } else if (nrhs <= 16) {
+        hipLaunchKernelGGL((k_coarse_apply_multi<T, 16>), dim3((unsigned)((n + 31) / 32), 1), 256, 0, s, inv, n, r,
+                           e, nrhs);
+    } else {
+        hipLaunchKernelGGL((k_coarse_apply_multi<T, 32>), dim3((unsigned)((n + 15) / 16), (nrhs + 31) / 32), 256, 0,
+                           s, inv, n, r, e, nrhs);
+    }
     return hipGetLastError();
 }
 template hipError_t launch_coarse_apply<float>(const double*, int64_t, const float*, float*, int, hipStream_t);

@@ -31,7 +31,8 @@ class ehh_problem_t(ctypes.Structure):
 
 
 class ehh_options_t(ctypes.Structure):
-    _fields_ = [("levels", ctypes.c_int32), ("cycle", ctypes.c_int32), ("nu1", ctypes.c_int32),
+    _fields_ = [("levels", ctypes.c_int32), ("cycle", ctypes.c_int32), ("cycle_level", ctypes.c_int32),
+                ("nu1", ctypes.c_int32),
                 ("nu2", ctypes.c_int32), ("vanka", ctypes.c_int32), ("precond_bits", ctypes.c_int32),
                 ("restart", ctypes.c_int32), ("dd_parts", ctypes.c_int32 * 3),
                 ("dd_overlap", ctypes.c_int32), ("dd_pad", ctypes.c_int32),
@@ -128,7 +129,8 @@ class Solver:
 
     def __init__(self, dim: int, n: Sequence[int], h: float, omega: float, shift: float,
                  abl_cells: Sequence[int], lam, mu, rho, gamma=None, abl_max: float = 1.0,
-                 atten0: float = 0.0, levels: int = 3, cycle: int = 1, nu1: int = 1, nu2: int = 1,
+                 atten0: float = 0.0, levels: int = 3, cycle: int = 1, cycle_level: int = 0,
+                 nu1: int = 1, nu2: int = 1,
                  vanka: int = 1, precond_bits: int = 64, restart: int = 5,
                  dd_parts: Sequence[int] = (1, 1, 1), dd_overlap: int = 0, dd_pad: int = 0,
                  dd_colors: int = 1, damping: Optional[Sequence[float]] = None,
@@ -144,7 +146,7 @@ class Solver:
         p.h, p.omega, p.shift, p.abl_max, p.atten0 = float(h), float(omega), float(shift), float(abl_max), float(atten0)
         p.mu_bar, p.rho_bar = float(mu_bar), float(rho_bar)
         o = default_options()
-        o.levels, o.cycle, o.nu1, o.nu2, o.vanka = levels, cycle, nu1, nu2, vanka
+        o.levels, o.cycle, o.cycle_level, o.nu1, o.nu2, o.vanka = levels, cycle, cycle_level, nu1, nu2, vanka
         o.precond_bits, o.restart = precond_bits, restart
         dp = list(dd_parts) + [1] * (3 - len(dd_parts))
         for a in range(3):
@@ -259,7 +261,7 @@ def solver_for_workload(w, device="cuda", **overrides):
     """Solver for a workloads.Workload (media uploaded as float64 device tensors)."""
     import torch
     m = w.media()
-    kw = dict(levels=w.levels, cycle=w.cycle, nu1=w.nu1, nu2=w.nu2, vanka=w.vanka,
+    kw = dict(levels=w.levels, cycle=w.cycle, cycle_level=w.cycle_level, nu1=w.nu1, nu2=w.nu2, vanka=w.vanka,
               precond_bits=w.precond_bits, restart=w.restart, dd_parts=w.dd_parts,
               dd_overlap=w.dd_overlap, dd_pad=w.dd_pad, dd_colors=w.dd_colors, damping=w.damping,
               abl_max=w.abl_max, atten0=w.atten0)

@@ -45,7 +45,7 @@ def oracle_problem(w):
 def oracle_hierarchy(w, pb=None):
     pb = pb or oracle_problem(w)
     return mg.build_hierarchy(pb, w.levels, list(w.damping), economic=(w.vanka == 0), cycle=w.cycle,
-                              nu1=w.nu1, nu2=w.nu2)
+                              nu1=w.nu1, nu2=w.nu2, cycle_level=w.cycle_level)
 
 
 def oracle_dd(w, pb=None):

@@ -9,8 +9,8 @@ pytestmark = pytest.mark.gpu
 
 CASES = {
     "c1": lambda **o: workload("c1_homog64", **o),
-    "het2d": lambda **o: small_hetero((48, 40), "het2d", levels=3, damping=(0.75, 0.5), **o),
-    "het3d": lambda **o: small_hetero((12, 8, 16), "het3d", levels=3, damping=(0.5, 0.5), **o),
+    "het2d": lambda **o: small_hetero((48, 40), "het2d", **{"levels": 3, "damping": (0.75, 0.5), **o}),
+    "het3d": lambda **o: small_hetero((12, 8, 16), "het3d", **{"levels": 3, "damping": (0.5, 0.5), **o}),
 }
 
 
@@ -114,12 +114,16 @@ def test_restrict_prolong_coarse(case):
         assert rel_err(from_dev(out)[r], H.coarse_lu.solve(r_[r])) < 1e-10
 
 
-@pytest.mark.parametrize("bits,cycle,vanka", [(64, 1, 1), (64, 2, 1), (64, 1, 0), (32, 1, 1)])
+@pytest.mark.parametrize("bits,cycle,vanka,cycle_level", [(64, 1, 1, 0), (64, 2, 1, 0), (64, 1, 0, 0),
+                                                          (32, 1, 1, 0), (64, 2, 1, 1)])
 @pytest.mark.parametrize("name", sorted(CASES))
-def test_vcycle(name, bits, cycle, vanka):
+def test_vcycle(name, bits, cycle, vanka, cycle_level):
     import torch
-    w = CASES[name](precond_bits=bits, cycle=cycle, vanka=vanka)
-    say(f"[vcycle {name} bits={bits} cycle={cycle} vanka={vanka}]")
+    w = CASES[name](precond_bits=bits, cycle=cycle, vanka=vanka, cycle_level=cycle_level)
+    if cycle_level and name != "het3d":     # four levels, so that level 1 makes two calls
+        w = CASES[name](precond_bits=bits, cycle=cycle, vanka=vanka, cycle_level=cycle_level, levels=4,
+                        damping=(0.75, 0.5, 0.5))
+    say(f"[vcycle {name} bits={bits} cycle={cycle} vanka={vanka} cycle_level={cycle_level} levels={w.levels}]")
     H = oracle_hierarchy(w)
     S = _solver(w)
     N = H.A[0].shape[0]
@@ -133,4 +137,53 @@ def test_vcycle(name, bits, cycle, vanka):
     for q in range(3):
         ref = H.cycle(r[q])
         assert np.linalg.norm(got[q] - ref) <= tol * np.linalg.norm(ref)
+    S.close()
+
+
+@pytest.mark.parametrize("nrhs", [1, 6, 12, 32])
+@pytest.mark.parametrize("bits", [64, 32])
+def test_coarse_solve_widths(bits, nrhs):
+    """Coarsest solve of the 2D case (338 unknowns: five full 64-column panels of
+    the blocked inverse and a ragged one) for every right-hand-side width of the
+    coarse apply; FP64 inverse, vectors in the cycle precision."""
+    import torch
+    w = CASES["het2d"](precond_bits=bits)
+    say(f"[coarse widths bits={bits} nrhs={nrhs}]")
+    H = oracle_hierarchy(w)
+    S = _solver(w)
+    Nc = H.A[-1].shape[0]
+    r_ = rand_cvec(Nc, nrhs, 44)
+    dt = torch.float32 if bits == 32 else torch.float64
+    out = torch.full((nrhs, 2 * Nc), float("nan"), dtype=dt, device="cuda")
+    S.coarse_solve(0, to_dev(r_, dt), out)
+    torch.cuda.synchronize()
+    got = from_dev(out)
+    tol = 1e-10 if bits == 64 else 1e-5
+    rin = from_dev(to_dev(r_, dt))       # the inputs as rounded to the cycle precision
+    for r in range(nrhs):
+        ref = H.coarse_lu.solve(rin[r])
+        assert np.linalg.norm(got[r] - ref) <= tol * np.linalg.norm(ref)
+    S.close()
+
+
+@pytest.mark.parametrize("nrhs", [1, 32])
+def test_dense_inverse_of_the_whole_grid(nrhs):
+    """One level: the cycle is the exact solve of the shifted operator, so the
+    blocked inverse of the 12,160-unknown 64^2 system (190 panels) applied to
+    random vectors must match the sparse LU of the oracle."""
+    import torch
+    import scipy.sparse.linalg as spla
+    w = workload("c1_homog64", levels=1, precond_bits=64)
+    say(f"[dense inverse 64^2 nrhs={nrhs}]")
+    pb = oracle_problem(w)
+    lu = spla.splu(pb.matrix(shifted=True).tocsc())
+    S = _solver(w)
+    r_ = rand_cvec(pb.size, nrhs, 45)
+    e = torch.zeros((nrhs, 2 * pb.size), dtype=torch.float64, device="cuda")
+    S.vcycle(to_dev(r_), e)
+    torch.cuda.synchronize()
+    got = from_dev(e)
+    for r in range(nrhs):
+        ref = lu.solve(r_[r])
+        assert np.linalg.norm(got[r] - ref) <= 1e-10 * np.linalg.norm(ref)
     S.close()

@@ -35,6 +35,7 @@ class Workload:
     shift: float = 0.5
     levels: int = 3
     cycle: int = 1                  # 1 = V, 2 = W
+    cycle_level: int = 0            # levels >= this use `cycle` calls, finer ones one call
     nu1: int = 1
     nu2: int = 1
     vanka: int = 1                  # 1 = full, 0 = economic
@@ -135,17 +136,18 @@ _add(Workload(
     name="c2_hetero512_fp64",
     description="2D 512x512 heterogeneous (Vp GRF 1500-4500, Poisson 0.25-0.45, Gardner rho), "
                 "h=10 m, 10 cells per minimum shear wavelength, shift 0.5, 20-cell layer, one source, "
-                "FP64 FGMRES(5) + FP64 V(1,1)",
+                "FP64 FGMRES(5) + FP64 (1,1) cycle on 5 levels: V on the finest level, W below, exact "
+                "solve of the 32^2 level",
     dim=2, n=(512, 512), h=10.0, media_fn=lambda: M.heterogeneous_2d_media((512, 512)), ppw=10.0,
-    abl_cells=(20, 20), shift=0.5, levels=6, cycle=2, damping=(0.75, 0.5, 0.5, 0.5, 0.5),
+    abl_cells=(20, 20), shift=0.5, levels=5, cycle=2, cycle_level=1, damping=(0.75, 0.5, 0.5, 0.5),
     precond_bits=64, sources_fn=_src_top_single))
 
 _add(Workload(
     name="c3_hetero512_batch32_fp32",
-    description="as c2, 32 x-forces at depth 5 (x = 8 + 16 s, seeded phases), complex64 V-cycle "
+    description="as c2, 32 x-forces at depth 5 (x = 8 + 16 s, seeded phases), complex64 cycle "
                 "inside FP64 FGMRES with FP64 coarsest solve",
     dim=2, n=(512, 512), h=10.0, media_fn=lambda: M.heterogeneous_2d_media((512, 512)), ppw=10.0,
-    abl_cells=(20, 20), shift=0.5, levels=6, cycle=2, damping=(0.75, 0.5, 0.5, 0.5, 0.5),
+    abl_cells=(20, 20), shift=0.5, levels=5, cycle=2, cycle_level=1, damping=(0.75, 0.5, 0.5, 0.5),
     precond_bits=32, sources_fn=_src_line(32, 16, 8, 5, seed=3)))
 
 _add(Workload(
