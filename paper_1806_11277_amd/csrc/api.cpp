@@ -112,6 +112,7 @@ struct ehh_ctx {
     const int* cnt_cell[3] = {nullptr, nullptr, nullptr};
     const int* cnt_face[3] = {nullptr, nullptr, nullptr};
     int ws_rhs = 0;
+    double* coarse_ws = nullptr;   // partial sums of the split coarse apply
     // Krylov workspace
     int kr_rhs = 0;
     double *V = nullptr, *Z = nullptr, *w = nullptr, *R = nullptr, *H = nullptr, *cs = nullptr, *g = nullptr;
@@ -217,6 +218,13 @@ int32_t ensure_ws(ehh_ctx* c, int nrhs) {
         CHK(c->alloc(&S.r0, b0));
         CHK(c->alloc(&S.e0, b0));
     }
+    // the split depends on the batch size: cover every batch up to nrhs
+    size_t cw = 0;
+    for (const Sub& S : c->subs)
+        for (int q = 1; q <= nrhs; ++q) cw = std::max(cw, coarse_ws_doubles(S.lev.back().g.N, q));
+    c->release(c->coarse_ws);
+    c->coarse_ws = nullptr;
+    if (cw) CHK(c->alloc((void**)&c->coarse_ws, sizeof(double) * cw));
     c->ws_rhs = nrhs;
     return EHH_OK;
 }
@@ -270,7 +278,7 @@ int32_t cycle(ehh_ctx* c, Sub& S, int l, const T* b, T* e, bool zero_init, int n
     Level& L = S.lev[l];
     const int nl = (int)S.lev.size();
     if (l == nl - 1) {
-        HIPCHK(launch_coarse_apply<T>(S.inv, L.g.N, b, e, nrhs, s));
+        HIPCHK(launch_coarse_apply<T>(S.inv, L.g.N, b, e, nrhs, c->coarse_ws, s));
         return EHH_OK;
     }
     const LevelDesc<T> D = level_desc<T>(c, L, c->prob.shift);
@@ -316,14 +324,17 @@ SubMap submap(const ehh_ctx* c, const Sub& S) {
 }
 
 // z = M^{-1} v (FP64 global vectors).
-template <typename T> int32_t precondition_t(ehh_ctx* c, const double* v, double* z, int nrhs, hipStream_t s) {
+// v_in_r0: the complex64 copy of v is already in the cycle's input buffer
+// (written by the scaling that produced v).
+template <typename T>
+int32_t precondition_t(ehh_ctx* c, const double* v, double* z, int nrhs, hipStream_t s, bool v_in_r0) {
     const Geo& gg = c->gg;
     if (!c->dd) {
         Sub& S = c->subs[0];
         if (std::is_same<T, double>::value) {
             return cycle<T>(c, S, 0, (const T*)v, (T*)z, true, nrhs, s);
         }
-        HIPCHK(launch_cast_d2f(v, (float*)S.r0, 2 * gg.N * nrhs, s));
+        if (!v_in_r0) HIPCHK(launch_cast_d2f(v, (float*)S.r0, 2 * gg.N * nrhs, s));
         CHK(cycle<T>(c, S, 0, (const T*)S.r0, (T*)S.e0, true, nrhs, s));
         HIPCHK(launch_cast_f2d((const float*)S.e0, z, 2 * gg.N * nrhs, s));
         return EHH_OK;
@@ -368,10 +379,15 @@ template <typename T> int32_t precondition_t(ehh_ctx* c, const double* v, double
     return EHH_OK;
 }
 
-int32_t precondition_any(ehh_ctx* c, const double* v, double* z, int nrhs, hipStream_t s) {
+int32_t precondition_any(ehh_ctx* c, const double* v, double* z, int nrhs, hipStream_t s, bool v_in_r0 = false) {
     CHK(ensure_ws(c, nrhs));
-    return c->bits() == 32 ? precondition_t<float>(c, v, z, nrhs, s) : precondition_t<double>(c, v, z, nrhs, s);
+    return c->bits() == 32 ? precondition_t<float>(c, v, z, nrhs, s, v_in_r0)
+                           : precondition_t<double>(c, v, z, nrhs, s, false);
 }
+
+// FP32 copy of the Krylov vector for the complex64 cycle, written by the
+// scaling kernel (global preconditioner only; with subdomains the gather casts).
+float* krylov_copy32(ehh_ctx* c) { return (c->bits() == 32 && !c->dd) ? (float*)c->subs[0].r0 : nullptr; }
 
 // ------------------------------------------------------------------ validation
 int32_t check_problem(const ehh_problem_t* p, const ehh_options_t* o) {
@@ -667,15 +683,16 @@ int32_t enqueue_iter(ehh_ctx* c, const LevelDesc<double>& A, int j, int nrhs, hi
     const int64_t N = c->gg.N;
     double* Vj = c->V + (size_t)j * nrhs * 2 * N;
     double* Zj = c->Z + (size_t)j * nrhs * 2 * N;
-    CHK(precondition_any(c, Vj, Zj, nrhs, s));
+    float* v32 = krylov_copy32(c);
+    CHK(precondition_any(c, Vj, Zj, nrhs, s, v32 != nullptr));
     HIPCHK(launch_apply<double>(A, Zj, nullptr, c->w, nrhs, s));
+    // CGS2: h1 = V^H w; w -= V h1 and h2 = V^H w (one sweep); w -= V h2 with |w|^2
     HIPCHK(launch_dots(c->V, j + 1, c->w, N, nrhs, c->partial, c->hcol, m + 1, s));
-    HIPCHK(launch_axpy_multi(c->V, j + 1, c->w, N, nrhs, c->hcol, m + 1, c->partial, nullptr, s));
-    HIPCHK(launch_dots(c->V, j + 1, c->w, N, nrhs, c->partial, c->hcol2, m + 1, s));
+    HIPCHK(launch_axpy_dots(c->V, j + 1, c->w, N, nrhs, c->hcol, m + 1, c->partial, c->hcol2, m + 1, s));
     HIPCHK(launch_axpy_multi(c->V, j + 1, c->w, N, nrhs, c->hcol2, m + 1, c->partial, c->nrm2, s));
     HIPCHK(launch_axpby(c->hcol, c->hcol2, c->hcol, 2 * (int64_t)nrhs * (m + 1), 1.0, 1.0, s));
     HIPCHK(launch_givens(c->H, c->cs, c->g, c->hcol, c->nrm2, j, m, nrhs, c->active, c->est, c->bnorm, s));
-    HIPCHK(launch_scale(c->w, c->V + (size_t)(j + 1) * nrhs * 2 * N, N, nrhs, c->nrm2, 1, s));
+    HIPCHK(launch_scale(c->w, c->V + (size_t)(j + 1) * nrhs * 2 * N, N, nrhs, c->nrm2, 1, s, v32));
     return EHH_OK;
 }
 
@@ -881,7 +898,7 @@ int32_t ehh_solve(ehh_handle_t h, const double* b, double* x, int32_t nrhs, doub
         HIPCHK(hipMemcpyAsync(c->g, g0.data(), sizeof(double) * g0.size(), hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(c->scal, inv_beta.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(c->active, active.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
-        HIPCHK(launch_scale(c->R, c->V, N, nrhs, c->scal, 0, s));
+        HIPCHK(launch_scale(c->R, c->V, N, nrhs, c->scal, 0, s, krylov_copy32(c)));
         int j = 0;
         for (j = 0; j < m; ++j) {
             if (use_graphs)
@@ -1106,10 +1123,13 @@ int32_t ehh_coarse_solve(ehh_handle_t h, int32_t sub, const void* r, void* e, in
     if (sub < 0 || sub >= (int)h->subs.size()) return fail(EHH_ERR_INVALID, "subdomain index out of range");
     CHK(level_of(h, sub, (int)h->subs[sub].lev.size() - 1, &S, &L));
     if (!r || !e || r == e || nrhs < 1) return fail(EHH_ERR_INVALID, "bad vectors or nrhs");
+    CHK(ensure_ws(h, nrhs));   // sizes the coarse-apply workspace for nrhs
     if (h->bits() == 32)
-        HIPCHK(launch_coarse_apply<float>(S->inv, L->g.N, (const float*)r, (float*)e, nrhs, as_stream(stream)));
+        HIPCHK(launch_coarse_apply<float>(S->inv, L->g.N, (const float*)r, (float*)e, nrhs, h->coarse_ws,
+                                          as_stream(stream)));
     else
-        HIPCHK(launch_coarse_apply<double>(S->inv, L->g.N, (const double*)r, (double*)e, nrhs, as_stream(stream)));
+        HIPCHK(launch_coarse_apply<double>(S->inv, L->g.N, (const double*)r, (double*)e, nrhs, h->coarse_ws,
+                                           as_stream(stream)));
     return EHH_OK;
 }
 

@@ -64,7 +64,10 @@ hipError_t launch_dense_invert(double* dense, int64_t n, int* piv, int* flag, hi
 hipError_t launch_permute_columns(const double* X, double* out, int64_t n, const int* qinv, hipStream_t s);
 // e = inv r for a batch of right-hand sides (FP64 accumulation).
 template <typename T>
-hipError_t launch_coarse_apply(const double* inv, int64_t n, const T* r, T* e, int nrhs, hipStream_t s);
+hipError_t launch_coarse_apply(const double* inv, int64_t n, const T* r, T* e, int nrhs, double* ws, hipStream_t s);
+// Column segments of the coarse apply and the FP64 workspace they need (0: none).
+int coarse_ksplit(int64_t n, int nrhs);
+size_t coarse_ws_doubles(int64_t n, int nrhs);
 hipError_t launch_cast_d2f(const double* in, float* out, int64_t n, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);   // bytes multiple of 4
 hipError_t launch_cast_f2d(const float* in, double* out, int64_t n, hipStream_t s);
@@ -98,9 +101,13 @@ hipError_t launch_axpy_multi(const double* V, int nv, double* w, int64_t N, int 
                              int ldh, double* partial, double* nrm2, hipStream_t s);
 // nrm2[r] = |x(r)|^2
 hipError_t launch_norm2(const double* x, int64_t N, int nrhs, double* partial, double* nrm2, hipStream_t s);
-// out(r) = x(r) * scale[r] (scale real)
+// out(r) = x(r) * scale[r] (scale real; mode 1: 1/sqrt(scale[r])); out32, if
+// not null, receives an FP32 copy.
 hipError_t launch_scale(const double* x, double* out, int64_t N, int nrhs, const double* scale, int mode,
-                        hipStream_t s);
+                        hipStream_t s, float* out32 = nullptr);
+// w -= sum_i h_i V_i, then hout = <V_i, w> for the updated w (one sweep).
+hipError_t launch_axpy_dots(const double* V, int nv, double* w, int64_t N, int nrhs, const double* h, int ldh,
+                            double* partial, double* hout, int ldo, hipStream_t s);
 // Givens update of column j of every right-hand side's Hessenberg matrix.
 hipError_t launch_givens(double* H, double* cs, double* g, const double* hcol, const double* hnext2, int j,
                          int m, int nrhs, const int* active, double* est, const double* bnorm, hipStream_t s);

@@ -130,6 +130,65 @@ __global__ __launch_bounds__(KB) void k_axpy_multi(const double* __restrict__ V,
     }
 }
 
+// Classical Gram-Schmidt, first pass and second projection in one sweep:
+// w <- w - sum_i h_i V_i, then the partial sums of <V_i, w> for the updated w,
+// with each V_i element loaded once for both.
+__global__ __launch_bounds__(KB) void k_axpy_dots(const double* __restrict__ V, int nv, double* __restrict__ w,
+                                                  int64_t N, int nrhs, const double* __restrict__ h, int ldh,
+                                                  double* __restrict__ partial) {
+    __shared__ double sm[KB / 64];
+    const int r = blockIdx.y;
+    const int nb = gridDim.x;
+    double* wr = w + (int64_t)r * 2 * N;
+    double hr[MAXV], hi[MAXV], are[MAXV], aim[MAXV];
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+        hr[i] = i < nv ? h[2 * ((int64_t)r * ldh + i)] : 0.0;
+        hi[i] = i < nv ? h[2 * ((int64_t)r * ldh + i) + 1] : 0.0;
+        are[i] = aim[i] = 0.0;
+    }
+    for (int64_t e = (int64_t)blockIdx.x * KB + threadIdx.x; e < N; e += (int64_t)nb * KB) {
+        double xr = wr[e], xi = wr[N + e];
+        double vr[MAXV], vi[MAXV];
+#pragma unroll
+        for (int i = 0; i < MAXV; ++i) {
+            if (i < nv) {
+                const double* v = V + ((int64_t)i * nrhs + r) * 2 * N;
+                vr[i] = v[e];
+                vi[i] = v[N + e];
+                xr -= hr[i] * vr[i] - hi[i] * vi[i];
+                xi -= hr[i] * vi[i] + hi[i] * vr[i];
+            }
+        }
+        wr[e] = xr;
+        wr[N + e] = xi;
+#pragma unroll
+        for (int i = 0; i < MAXV; ++i) {
+            if (i < nv) {
+                are[i] += vr[i] * xr + vi[i] * xi;
+                aim[i] += vr[i] * xi - vi[i] * xr;
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+        if (i < nv) {
+            const double sr = block_sum(are[i], sm);
+            if (threadIdx.x == 0) partial[(((int64_t)r * nv + i) * 2 + 0) * nb + blockIdx.x] = sr;
+            const double si = block_sum(aim[i], sm);
+            if (threadIdx.x == 0) partial[(((int64_t)r * nv + i) * 2 + 1) * nb + blockIdx.x] = si;
+        }
+    }
+}
+
+hipError_t launch_axpy_dots(const double* V, int nv, double* w, int64_t N, int nrhs, const double* h, int ldh,
+                            double* partial, double* hout, int ldo, hipStream_t s) {
+    const int nb = krylov_blocks(N);
+    hipLaunchKernelGGL(k_axpy_dots, dim3(nb, nrhs), KB, 0, s, V, nv, w, N, nrhs, h, ldh, partial);
+    hipLaunchKernelGGL(k_partial_final, nblk((int64_t)nrhs * nv * 2 * 64), 256, 0, s, partial, nv, nb, nrhs, hout, ldo);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void k_norm_final(const double* __restrict__ partial, int nb, int nrhs,
                                                     double* __restrict__ out) {
     const int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -165,19 +224,23 @@ hipError_t launch_norm2(const double* x, int64_t N, int nrhs, double* partial, d
 }
 
 // mode 0: out = x * sc[r]; mode 1: out = x / sqrt(sc[r]) (0 if sc[r] == 0)
+// (out32, when given, receives the same values in FP32: the input of a
+// complex64 preconditioner cycle, written in the same pass.)
 __global__ void k_scale(const double* __restrict__ x, double* __restrict__ out, int64_t N, int nrhs,
-                        const double* __restrict__ sc, int mode) {
+                        const double* __restrict__ sc, int mode, float* __restrict__ out32) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 2 * N * nrhs) return;
     const int r = (int)(t / (2 * N));
     double f = sc[r];
     if (mode == 1) f = f > 0.0 ? 1.0 / sqrt(f) : 0.0;
-    out[t] = x[t] * f;
+    const double v = x[t] * f;
+    out[t] = v;
+    if (out32) out32[t] = (float)v;
 }
 
 hipError_t launch_scale(const double* x, double* out, int64_t N, int nrhs, const double* scale, int mode,
-                        hipStream_t s) {
-    hipLaunchKernelGGL(k_scale, nblk(2 * N * nrhs), 256, 0, s, x, out, N, nrhs, scale, mode);
+                        hipStream_t s, float* out32) {
+    hipLaunchKernelGGL(k_scale, nblk(2 * N * nrhs), 256, 0, s, x, out, N, nrhs, scale, mode, out32);
     return hipGetLastError();
 }
 

@@ -389,6 +389,175 @@ __global__ __launch_bounds__(256) void k_relax_plan(Op op, int colour, T w, int 
     }
 }
 
+// Raw buffer access: a scalar resource descriptor (base, size in bytes) plus a
+// 32-bit byte offset per lane, so that a kernel keeps one VGPR per address.
+// Reads past the descriptor's size return zero.
+typedef uint32_t ehh_u2 __attribute__((ext_vector_type(2)));
+template <typename T> struct Buf;
+template <> struct Buf<float> {
+    __amdgpu_buffer_rsrc_t r;
+    EHH_DEV Buf(const void* p, uint32_t bytes)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000)) {}
+    EHH_DEV float ld(uint32_t off) const { return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0)); }
+    EHH_DEV void st(uint32_t off, float v) const {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
+    }
+};
+template <> struct Buf<double> {
+    __amdgpu_buffer_rsrc_t r;
+    EHH_DEV Buf(const void* p, uint32_t bytes)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000)) {}
+    EHH_DEV double ld(uint32_t off) const {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    }
+    EHH_DEV void st(uint32_t off, double v) const {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(ehh_u2, v), r, off, 0, 0);
+    }
+};
+
+// ------------------------------------------- one thread per cell (2D finest level)
+// The finest level's rows have few terms (self, two normal and two tangential
+// neighbours, two pressures; the off-diagonal weights are real), so one thread
+// owns one cell of the colour: it builds the cell's 5 x 5 block inverse once
+// (per component a 2 x 2 inverse, then the Schur complement on the pressure) and
+// then, for each of its right-hand sides, loads the 21 values of e_in its five
+// rows touch plus b, and writes the corrected unknowns.  Consecutive threads own
+// consecutive cells of the colour along x, so every load of a wavefront covers
+// 128 consecutive cells and the other colour's half of each line is used by the
+// neighbour loads of the same wavefront.  The thread also copies the pressure
+// of the other cell of its x-pair (not relaxed in this half-sweep).
+template <typename T>
+__global__ __launch_bounds__(256) void k_relax_cell2d(FineOp<2, T> op, int colour, T w, int econ,
+                                                      const T* __restrict__ b, const T* __restrict__ ein,
+                                                      T* __restrict__ eout, int nrhs, int64_t stride, int rpb) {
+    const Geo& g = op.g;
+    const int n0 = g.n[0], n1 = g.n[1];
+    const int hp = n0 >> 1;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)hp * n1) return;
+    const int r_begin = blockIdx.y * rpb;
+    const int r_end = r_begin + rpb < nrhs ? r_begin + rpb : nrhs;
+    const int px = (int)(t % hp), y = (int)(t / hp);
+    const int par = (colour + y) & 1;
+    const int x = 2 * px + par;          // the relaxed cell
+    const int xo = 2 * px + 1 - par;     // the other cell of the pair
+    // unknown indices (clamped to a valid unknown where a neighbour is absent)
+    const int64_t o0 = g.off[0], o1 = g.off[1], op3 = g.off[3];
+    const int d0 = n0 - 1;                // u_0 faces per row
+    auto iu0 = [&](int fx, int yy) { return o0 + (int64_t)yy * d0 + (fx - 1); };
+    auto iu1 = [&](int xx, int fy) { return o1 + (int64_t)(fy - 1) * n0 + xx; };
+    auto ip = [&](int xx, int yy) { return op3 + (int64_t)yy * n0 + xx; };
+    // the four faces of the cell and their existence
+    const bool vl = x >= 1, vr = x + 1 <= n0 - 1, vb = y >= 1, vt = y + 1 <= n1 - 1;
+    const int pl[3] = {x, y, 0}, pr[3] = {x + 1, y, 0}, pb[3] = {x, y, 0}, pt[3] = {x, y + 1, 0};
+    // row coefficients: diagonal (complex) and the real neighbour weights (0 when absent)
+    const cx<T> one = mk<T>(T(1), T(0));
+    const cx<T> dl = vl ? op.diag_u(0, pl) : one, dr = vr ? op.diag_u(0, pr) : one;
+    const cx<T> db = vb ? op.diag_u(1, pb) : one, dt = vt ? op.diag_u(1, pt) : one;
+    const int cc[3] = {x, y, 0};
+    const T mu_k = op.mu_c(cc);
+    // left face u0(x): normal lo u0(x-1) [cell x-1], tangential u0(x, y +- 1)
+    const bool l_nlo = vl && x - 1 >= 1;
+    int cq[3] = {x - 1, y, 0};
+    const T wl_nlo = l_nlo ? -op.mu_c(cq) : T(0);
+    const T wl_thi = (vl && y + 1 < n1) ? -op.mu_edge(0, pl, 1, y + 1) : T(0);
+    const T wl_tlo = (vl && y - 1 >= 0) ? -op.mu_edge(0, pl, 1, y) : T(0);
+    // right face u0(x+1): normal hi u0(x+2) [cell x+1], tangential u0(x+1, y +- 1)
+    const bool r_nhi = vr && x + 2 <= n0 - 1;
+    cq[0] = x + 1;
+    const T wr_nhi = r_nhi ? -op.mu_c(cq) : T(0);
+    const T wr_thi = (vr && y + 1 < n1) ? -op.mu_edge(0, pr, 1, y + 1) : T(0);
+    const T wr_tlo = (vr && y - 1 >= 0) ? -op.mu_edge(0, pr, 1, y) : T(0);
+    // bottom face u1(y): normal lo u1(y-1) [cell y-1], tangential u1(x +- 1, y)
+    const bool b_nlo = vb && y - 1 >= 1;
+    cq[0] = x;
+    cq[1] = y - 1;
+    const T wb_nlo = b_nlo ? -op.mu_c(cq) : T(0);
+    const T wb_thi = (vb && x + 1 < n0) ? -op.mu_edge(1, pb, 0, x + 1) : T(0);
+    const T wb_tlo = (vb && x - 1 >= 0) ? -op.mu_edge(1, pb, 0, x) : T(0);
+    // top face u1(y+1): normal hi u1(y+2) [cell y+1], tangential u1(x +- 1, y+1)
+    const bool t_nhi = vt && y + 2 <= n1 - 1;
+    cq[1] = y + 1;
+    const T wt_nhi = t_nhi ? -op.mu_c(cq) : T(0);
+    const T wt_thi = (vt && x + 1 < n0) ? -op.mu_edge(1, pt, 0, x + 1) : T(0);
+    const T wt_tlo = (vt && x - 1 >= 0) ? -op.mu_edge(1, pt, 0, x) : T(0);
+    // in-block coupling of the two faces of a component (through mu of the cell)
+    const T c0 = (vl && vr) ? -mu_k : T(0), c1 = (vb && vt) ? -mu_k : T(0);
+    const T pdiag = -op.c.dinv[cell_idx<2>(g, cc)];
+    // block inverse: per component [[d_lo, c], [c, d_hi]]^{-1}; g = (+1, -1) on present faces
+    const T gl0 = vl ? T(1) : T(0), gh0 = vr ? T(-1) : T(0), gl1 = vb ? T(1) : T(0), gh1 = vt ? T(-1) : T(0);
+    const T cu0 = econ ? T(0) : c0, cu1 = econ ? T(0) : c1;
+    const cx<T> id0 = cinv(dl * dr - mk<T>(cu0 * cu0, T(0)));
+    const cx<T> id1 = cinv(db * dt - mk<T>(cu1 * cu1, T(0)));
+    const cx<T> a00 = dr * id0, a11 = dl * id0, a01 = (-cu0) * id0;   // inverse of component 0
+    const cx<T> b00 = dt * id1, b11 = db * id1, b01 = (-cu1) * id1;   // inverse of component 1
+    const cx<T> z0l = gl0 * a00 + gh0 * a01, z0h = gl0 * a01 + gh0 * a11;
+    const cx<T> z1l = gl1 * b00 + gh1 * b01, z1h = gl1 * b01 + gh1 * b11;
+    const cx<T> iS = cinv(mk<T>(pdiag, T(0)) - (gl0 * z0l + gh0 * z0h + gl1 * z1l + gh1 * z1h));
+    // 32-bit byte offsets within one right-hand side's vector for buffer access
+    // (the launcher checks that a vector stays below 4 GiB); absent neighbours
+    // are read at the face itself (their weight is zero)
+    using U = uint32_t;
+    constexpr U E = (U)sizeof(T);
+    const U kl = E * (U)iu0(vl ? x : 1, y), kr = E * (U)iu0(vr ? x + 1 : 1, y);
+    const U kb = E * (U)iu1(x, vb ? y : 1), kt = E * (U)iu1(x, vt ? y + 1 : 1);
+    const U kp = E * (U)ip(x, y), kpo = E * (U)ip(xo, y);
+    const U ud0 = E * (U)d0, un0 = E * (U)n0;
+    const U sl_n = l_nlo ? 0u - E : 0u, sr_n = r_nhi ? E : 0u;
+    const U sl_th = wl_thi != T(0) ? ud0 : 0u, sl_tl = wl_tlo != T(0) ? 0u - ud0 : 0u;
+    const U sr_th = wr_thi != T(0) ? ud0 : 0u, sr_tl = wr_tlo != T(0) ? 0u - ud0 : 0u;
+    const U sb_n = b_nlo ? 0u - un0 : 0u, st_n = t_nhi ? un0 : 0u;
+    const U sb_th = wb_thi != T(0) ? E : 0u, sb_tl = wb_tlo != T(0) ? 0u - E : 0u;
+    const U st_th = wt_thi != T(0) ? E : 0u, st_tl = wt_tlo != T(0) ? 0u - E : 0u;
+    const U sp_l = vl ? 0u - E : 0u, sp_r = vr ? E : 0u, sp_b = vb ? 0u - un0 : 0u, sp_t = vt ? un0 : 0u;
+    const U NB = E * (U)g.N;   // bytes of one plane (real or imaginary parts)
+    const U VB = 2 * NB;       // bytes of one right-hand side's vector
+    for (int r = r_begin; r < r_end; ++r) {
+        const Buf<T> bb(b + (int64_t)r * stride, VB);
+        const Buf<T> eo(eout + (int64_t)r * stride, VB);
+        auto ldb = [&](U i) { return mk<T>(bb.ld(i), bb.ld(NB + i)); };
+        cx<T> rl = vl ? ldb(kl) : mk<T>(T(0), T(0)), rr = vr ? ldb(kr) : mk<T>(T(0), T(0));
+        cx<T> rb_ = vb ? ldb(kb) : mk<T>(T(0), T(0)), rt = vt ? ldb(kt) : mk<T>(T(0), T(0));
+        cx<T> rp = ldb(kp);
+        cx<T> el = mk<T>(T(0), T(0)), ere = el, eb = el, et = el, ep = el, epo = el;
+        if (ein) {
+            const Buf<T> ei(ein + (int64_t)r * stride, VB);
+            auto ld = [&](U i) { return mk<T>(ei.ld(i), ei.ld(NB + i)); };
+            el = ld(kl);
+            ere = ld(kr);
+            eb = ld(kb);
+            et = ld(kt);
+            ep = ld(kp);
+            epo = ld(kpo);
+            const cx<T> pl_ = ld(kp + sp_l), pr_ = ld(kp + sp_r), pb_ = ld(kp + sp_b), pt_ = ld(kp + sp_t);
+            // residuals of the five rows: r = b - A e
+            rl = rl - (dl * el + c0 * ere + wl_nlo * ld(kl + sl_n) + wl_thi * ld(kl + sl_th) + wl_tlo * ld(kl + sl_tl) +
+                       gl0 * (ep - pl_));
+            rr = rr - (dr * ere + c0 * el + wr_nhi * ld(kr + sr_n) + wr_thi * ld(kr + sr_th) + wr_tlo * ld(kr + sr_tl) +
+                       (-gh0) * (pr_ - ep));
+            rb_ = rb_ - (db * eb + c1 * et + wb_nlo * ld(kb + sb_n) + wb_thi * ld(kb + sb_th) + wb_tlo * ld(kb + sb_tl) +
+                         gl1 * (ep - pb_));
+            rt = rt - (dt * et + c1 * eb + wt_nhi * ld(kt + st_n) + wt_thi * ld(kt + st_th) + wt_tlo * ld(kt + st_tl) +
+                       (-gh1) * (pt_ - ep));
+            rp = rp - (pdiag * ep + gh0 * ere + gl0 * el + gh1 * et + gl1 * eb);
+        }
+        // closed-form block solve
+        const cx<T> y0l = a00 * rl + a01 * rr, y0h = a01 * rl + a11 * rr;
+        const cx<T> y1l = b00 * rb_ + b01 * rt, y1h = b01 * rb_ + b11 * rt;
+        const cx<T> dp = (rp - (gl0 * y0l + gh0 * y0h + gl1 * y1l + gh1 * y1h)) * iS;
+        auto st = [&](U i, cx<T> v) {
+            eo.st(i, v.re);
+            eo.st(NB + i, v.im);
+        };
+        if (vl) st(kl, el + w * (y0l - z0l * dp));
+        if (vr) st(kr, ere + w * (y0h - z0h * dp));
+        if (vb) st(kb, eb + w * (y1l - z1l * dp));
+        if (vt) st(kt, et + w * (y1h - z1h * dp));
+        st(kp, ep + w * dp);
+        st(kpo, epo);
+    }
+}
+
 // ---------------------------------------------------- LDS-staged half-sweep (2D)
 // A block relaxes the red cells of a 16 x 8 tile (64 cells, eight lanes each as in
 // k_relax_plan).  For every right-hand side the vectors the tile's rows touch
@@ -795,6 +964,10 @@ template <typename T> static inline int rhs_block() {
     static const int v = env_int(sizeof(T) == 4 ? "EHH_RB32" : "EHH_RB64", 1);
     return v == 1 || v == 2 || v == 4 ? v : 1;
 }
+static inline bool cell2d_enabled() {
+    static const bool v = env_int("EHH_CELL2D", 1) != 0;
+    return v;
+}
 static inline bool lds2d_enabled() {
     static const bool v = env_int("EHH_LDS2D", 1) != 0;
     return v;
@@ -862,6 +1035,14 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
         const int rpl = rhs_per_block((int64_t)tiles * 8, nrhs, 1);
         const dim3 gl(tiles, (nrhs + rpl - 1) / rpl);
         hipLaunchKernelGGL((k_relax_lds2d<T, StOp<2, T>>), gl, 512, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride, rpl, 2);
+    } else if (L.g.dim == 2 && L.fine && cell2d_enabled() && 2 * L.g.N * (int64_t)sizeof(T) < (int64_t(1) << 32)) {
+        const int64_t cells = npair;
+        static const int64_t cell_waves = env_int("EHH_CELL_WAVES", 4096);
+        int64_t groups = (cell_waves + (cells + 63) / 64 - 1) / ((cells + 63) / 64);
+        groups = groups < 1 ? 1 : (groups > nrhs ? nrhs : groups);
+        const int rpc = (int)((nrhs + groups - 1) / groups);
+        const dim3 gc(nblk(cells), (nrhs + rpc - 1) / rpc);
+        hipLaunchKernelGGL((k_relax_cell2d<T>), gc, 256, 0, s, FineOp<2, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride, rpc);
     } else if (L.g.dim == 2) {
         if (L.fine)
             EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_relax_plan<2, T, FineOp<2, T>, RB>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb));

@@ -716,7 +716,8 @@ __global__ __launch_bounds__(256) void k_coarse_apply(const double* __restrict__
 // two rows; the row values are LDS broadcasts within a wavefront.
 template <typename T, int W>
 __global__ __launch_bounds__(256) void k_coarse_apply_multi(const double* __restrict__ inv, int64_t n,
-                                                            const T* __restrict__ r, T* __restrict__ e, int nrhs) {
+                                                            const T* __restrict__ r, T* __restrict__ e, int nrhs,
+                                                            int64_t kseg, double* __restrict__ part) {
     constexpr int ROWS = 512 / W;
     constexpr int KC = 64;
     __shared__ double Ms[ROWS][KC * 2];
@@ -725,13 +726,15 @@ __global__ __launch_bounds__(256) void k_coarse_apply_multi(const double* __rest
     const int q = t % W, rg = t / W;
     const int64_t i0 = (int64_t)blockIdx.x * ROWS;
     const int q0 = blockIdx.y * W;
+    const int64_t jb = (int64_t)blockIdx.z * kseg;
+    const int64_t je = jb + kseg < n ? jb + kseg : n;
     double a0r = 0.0, a0i = 0.0, a1r = 0.0, a1i = 0.0;
-    for (int64_t j0 = 0; j0 < n; j0 += KC) {
+    for (int64_t j0 = jb; j0 < je; j0 += KC) {
         for (int el = t; el < ROWS * KC; el += 256) {
             const int rr = el / KC, cc = el % KC;
             const int64_t gi = i0 + rr, gj = j0 + cc;
             double vr = 0.0, vi = 0.0;
-            if (gi < n && gj < n) {
+            if (gi < n && gj < je) {
                 vr = inv[2 * (gi * n + gj)];
                 vi = inv[2 * (gi * n + gj) + 1];
             }
@@ -742,7 +745,7 @@ __global__ __launch_bounds__(256) void k_coarse_apply_multi(const double* __rest
             const int kk = el % KC, qq = el / KC;
             const int64_t gj = j0 + kk;
             double vr = 0.0, vi = 0.0;
-            if (gj < n && q0 + qq < nrhs) {
+            if (gj < je && q0 + qq < nrhs) {
                 const T* rv = r + (int64_t)(q0 + qq) * 2 * n;
                 vr = (double)rv[gj];
                 vi = (double)rv[n + gj];
@@ -764,8 +767,20 @@ __global__ __launch_bounds__(256) void k_coarse_apply_multi(const double* __rest
         __syncthreads();
     }
     if (q0 + q >= nrhs) return;
-    T* ev = e + (int64_t)(q0 + q) * 2 * n;
     const int64_t g0 = i0 + 2 * rg;
+    if (part) {   // partial sum of column segment blockIdx.z, reduced by k_coarse_reduce
+        double* pv = part + ((int64_t)blockIdx.z * nrhs + q0 + q) * 2 * n;
+        if (g0 < n) {
+            pv[g0] = a0r;
+            pv[n + g0] = a0i;
+        }
+        if (g0 + 1 < n) {
+            pv[g0 + 1] = a1r;
+            pv[n + g0 + 1] = a1i;
+        }
+        return;
+    }
+    T* ev = e + (int64_t)(q0 + q) * 2 * n;
     if (g0 < n) {
         ev[g0] = (T)a0r;
         ev[n + g0] = (T)a0i;
@@ -776,24 +791,61 @@ __global__ __launch_bounds__(256) void k_coarse_apply_multi(const double* __rest
     }
 }
 
+// e = sum over the column segments of the partial products, in segment order.
 template <typename T>
-hipError_t launch_coarse_apply(const double* inv, int64_t n, const T* r, T* e, int nrhs, hipStream_t s) {
-    if (nrhs <= 4) {
+__global__ __launch_bounds__(256) void k_coarse_reduce(const double* __restrict__ part, int ks, int64_t n, int nrhs,
+                                                       T* __restrict__ e) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * n * nrhs) return;
+    double s = 0.0;
+    for (int z = 0; z < ks; ++z) s += part[(int64_t)z * 2 * n * nrhs + t];
+    e[t] = (T)s;
+}
+
+// Column segments of the multi-right-hand-side coarse apply: enough workgroups to
+// fill the chip (about 1024), segments of at least 256 columns.
+static int coarse_width(int nrhs) { return nrhs <= 4 ? 0 : nrhs <= 8 ? 8 : nrhs <= 16 ? 16 : 32; }
+int coarse_ksplit(int64_t n, int nrhs) {
+    const int W = coarse_width(nrhs);
+    if (W == 0) return 1;
+    const int64_t blocks = ((n + 512 / W - 1) / (512 / W)) * ((nrhs + W - 1) / W);
+    int64_t ks = (1024 + blocks - 1) / blocks;
+    const int64_t kmax = n / 256 > 1 ? n / 256 : 1;
+    ks = ks < 1 ? 1 : (ks > kmax ? kmax : ks);
+    return (int)ks;
+}
+size_t coarse_ws_doubles(int64_t n, int nrhs) {
+    const int ks = coarse_ksplit(n, nrhs);
+    return ks > 1 ? (size_t)ks * 2 * n * nrhs : 0;
+}
+
+template <typename T>
+hipError_t launch_coarse_apply(const double* inv, int64_t n, const T* r, T* e, int nrhs, double* ws, hipStream_t s) {
+    const int W = coarse_width(nrhs);
+    if (W == 0) {
         hipLaunchKernelGGL((k_coarse_apply<T>), dim3(nblk(n * 64), (nrhs + 3) / 4), 256, 0, s, inv, n, r, e, nrhs);
-    } else if (nrhs <= 8) {
-        hipLaunchKernelGGL((k_coarse_apply_multi<T, 8>), dim3((unsigned)((n + 63) / 64), 1), 256, 0, s, inv, n, r,
-                           e, nrhs);
-    } else if (nrhs <= 16) {
-        hipLaunchKernelGGL((k_coarse_apply_multi<T, 16>), dim3((unsigned)((n + 31) / 32), 1), 256, 0, s, inv, n, r,
-                           e, nrhs);
-    } else {
-        hipLaunchKernelGGL((k_coarse_apply_multi<T, 32>), dim3((unsigned)((n + 15) / 16), (nrhs + 31) / 32), 256, 0,
-                           s, inv, n, r, e, nrhs);
+        return hipGetLastError();
     }
+    int ks = coarse_ksplit(n, nrhs);
+    if (ks > 1 && !ws) ks = 1;
+    const int64_t kseg = ((n + ks - 1) / ks + 63) / 64 * 64;
+    ks = (int)((n + kseg - 1) / kseg);
+    double* part = ks > 1 ? ws : nullptr;
+    const unsigned rows = (unsigned)((n + 512 / W - 1) / (512 / W));
+    const dim3 grid(rows, (unsigned)((nrhs + W - 1) / W), (unsigned)ks);
+    if (W == 8)
+        hipLaunchKernelGGL((k_coarse_apply_multi<T, 8>), grid, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
+    else if (W == 16)
+        hipLaunchKernelGGL((k_coarse_apply_multi<T, 16>), grid, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
+    else
+        hipLaunchKernelGGL((k_coarse_apply_multi<T, 32>), grid, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
+    if (part) hipLaunchKernelGGL((k_coarse_reduce<T>), nblk(2 * n * nrhs), 256, 0, s, part, ks, n, nrhs, e);
     return hipGetLastError();
 }
-template hipError_t launch_coarse_apply<float>(const double*, int64_t, const float*, float*, int, hipStream_t);
-template hipError_t launch_coarse_apply<double>(const double*, int64_t, const double*, double*, int, hipStream_t);
+template hipError_t launch_coarse_apply<float>(const double*, int64_t, const float*, float*, int, double*,
+                                               hipStream_t);
+template hipError_t launch_coarse_apply<double>(const double*, int64_t, const double*, double*, int, double*,
+                                                hipStream_t);
 
 __global__ void k_zero_words(uint32_t* __restrict__ p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
