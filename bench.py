@@ -39,13 +39,18 @@ def rhs_tensor(S, w):
     return torch.as_tensor(B, device="cuda")
 
 
-def level_bytes(info, bits, nrhs, fine, dim):
+def level_bytes(info, bits, nrhs, fine, dim, with_e=True):
     """Algorithmic HBM bytes of one half-sweep launch on a level: b and e_in read,
-    e_out written (every unknown, complex, per right-hand side) plus the level's
-    operator coefficients read once (finest: mu, 1/(lambda+mu), rho, gamma per
-    cell; coarser: the stored Galerkin stencil)."""
+    e_out written (every unknown, complex, per right-hand side; without e_in when
+    the sweep starts from zero) plus the level's operator coefficients read once
+    (finest: mu, 1/(lambda+mu), rho, gamma per cell; coarser: the stored
+    Galerkin stencil)."""
     es = 4 if bits == 32 else 8
-    vec = 3 * info["N"] * 2 * es * nrhs
+    ncell_ = int(np.prod(info["n"][:dim]))
+    nu = info["N"] - ncell_          # displacement unknowns
+    # b: the rows of the colour's cells (every face, half the pressures);
+    # e_in: every unknown the rows touch; e_out: every unknown
+    vec = ((nu + ncell_ / 2) + (info["N"] if with_e else 0) + info["N"]) * 2 * es * nrhs
     ncell = int(np.prod(info["n"][:dim]))
     if fine:
         coef = 4 * ncell * es
@@ -111,47 +116,142 @@ def visits_per_cycle(w):
     return v
 
 
+def relax_kernel_name(w, level, ncell):
+    """The half-sweep kernel the library launches on a level (same routing as
+    its launcher): one thread per cell on the finest 2D level, LDS-staged tiles
+    on 2D Galerkin levels of at least 256^2 cells, eight lanes per cell with
+    row plans otherwise."""
+    t = "float" if w.precond_bits == 32 else "double"
+    if w.dim == 2:
+        if level == 0:
+            return f"k_relax_cell2d<{t}>"
+        if ncell >= 65536:
+            return f"k_relax_lds2d<{t}, StOp<2, {t}>>"
+        return f"k_relax_plan<2, {t}, StOp<2, {t}>, 1>"
+    if level == 0:
+        return f"k_relax_plan<3, {t}, FineOp<3, {t}>, 1>"
+    return f"k_relax<3, {t}, StOp<3, {t}>>"
+
+
+KERNEL_SOURCES = ["paper_1806_11277_amd/csrc/levels.hip", "paper_1806_11277_amd/csrc/ops.hpp",
+                  "paper_1806_11277_amd/csrc/common.hpp"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record(workload, kernel):
+    """HBM bytes per launch of a kernel from the committed counter summaries
+    (FETCH_SIZE and WRITE_SIZE runs scaled by a plain copy's reading), or None
+    when there is none or the kernel sources changed since it was taken."""
+    d = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(d):
+        return None
+    for f in sorted(os.listdir(d)):
+        if not f.endswith(".md"):
+            continue
+        for line in open(os.path.join(d, f)):
+            if line.startswith("traffic-record: "):
+                rec = json.loads(line[len("traffic-record: "):])
+                if rec.get("workload") == workload and rec.get("kernel") == kernel:
+                    if rec.get("source_hash") != kernel_source_hash():
+                        return None
+                    return rec
+    return None
+
+
 def kernel_roofline(w, reps=30):
-    """The dominant kernel is the red-black Vanka half-sweep.  Every level's
-    half-sweep is timed with HIP events on the stream the library launches on,
-    and the levels are weighted by their launch count in one cycle
-    (2 (nu1 + nu2) half-sweeps per visit)."""
+    """HBM roofline of the dominant kernel, the red-black Vanka half-sweep.
+    Every level's half-sweep is timed with HIP events around the replay of a
+    graph of its launches (captured from the library's launches on the
+    caller's stream).  Launches are weighted by their
+    count in one cycle (2 (nu1 + nu2) half-sweeps per visit) and grouped by the
+    kernel each level uses; the dominant kernel is the one with the largest
+    time per cycle.  achieved = its algorithmic bytes per launch / its average
+    launch duration."""
     import torch
     from paper_1806_11277_amd import ehh
     S = ehh.solver_for_workload(w)
     nrhs = len(w.sources())
     dt = torch.float32 if w.precond_bits == 32 else torch.float64
     stream = torch.cuda.current_stream()
+    visits = visits_per_cycle(w)
     rows = []
-    tot_b = tot_t = 0.0
+    groups = {}
     for l in range(w.levels - 1):
         info = S.level_info(0, l)
-        b = torch.randn((nrhs, 2 * info["N"]), dtype=dt, device="cuda")
-        e_in = torch.randn_like(b)
-        e_out = torch.zeros_like(b)
-        for _ in range(3):
-            S.level_relax(0, l, 0, b, e_in, e_out)
+        # several vector sets in turn, so that a visit does not find the previous
+        # visit's vectors in L2 (inside a solve the level's vectors were last
+        # touched by other kernels)
+        nset = 4
+        sets = []
+        for _ in range(nset):
+            b = torch.randn((nrhs, 2 * info["N"]), dtype=dt, device="cuda")
+            sets.append((b, torch.randn_like(b), torch.zeros_like(b)))
+        # one visit's sweeps as the cycle launches them: the first pre-smoothing
+        # half-sweep starts from zero (no e_in), the others read e_in
+        nsw = 2 * (w.nu1 + w.nu2)
+        nzero = 1 if w.nu1 > 0 else 0
+
+        def visit(v=0):
+            b, e_in, e_out = sets[v % nset]
+            for k in range(nsw):
+                S.level_relax(0, l, k % 2, b, None if k < nzero else e_in, e_out)
+        visit()
+        torch.cuda.synchronize()
+        # the sweeps are replayed from a captured graph, as the solver replays its
+        # Arnoldi steps, so that host launch gaps do not enter the timing
+        graph = torch.cuda.CUDAGraph()
+        cap = torch.cuda.Stream()
+        with torch.cuda.graph(graph, stream=cap):
+            for r in range(reps):
+                visit(r)
+        graph.replay()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         ev0.record(stream)
-        for _ in range(reps):
-            S.level_relax(0, l, 0, b, e_in, e_out)
+        graph.replay()
         ev1.record(stream)
         torch.cuda.synchronize()
-        t = ev0.elapsed_time(ev1) / reps / 1e3
-        nb = level_bytes(info, w.precond_bits, nrhs, l == 0, w.dim)
-        launches = 2 * (w.nu1 + w.nu2) * visits_per_cycle(w)[l]
-        rows.append(dict(level=l, n=info["n"][:w.dim], bytes=nb, us=t * 1e6, gbs=nb / t / 1e9,
+        t = ev0.elapsed_time(ev1) / (reps * nsw) / 1e3
+        del graph
+        nb = (nzero * level_bytes(info, w.precond_bits, nrhs, l == 0, w.dim, with_e=False) +
+              (nsw - nzero) * level_bytes(info, w.precond_bits, nrhs, l == 0, w.dim)) / nsw
+        launches = 2 * (w.nu1 + w.nu2) * visits[l]
+        ncell = int(np.prod(info["n"][:w.dim]))
+        name = relax_kernel_name(w, l, ncell)
+        rows.append(dict(level=l, n=info["n"][:w.dim], kernel=name, bytes=nb, us=t * 1e6, gbs=nb / t / 1e9,
                          launches_per_cycle=launches))
-        tot_b += launches * nb
-        tot_t += launches * t
-        del b, e_in, e_out
+        g = groups.setdefault(name, dict(kernel=name, launches_per_cycle=0, bytes_per_cycle=0.0,
+                                         us_per_cycle=0.0))
+        g["launches_per_cycle"] += launches
+        g["bytes_per_cycle"] += launches * nb
+        g["us_per_cycle"] += launches * t * 1e6
+        del sets
     S.close()
-    achieved = tot_b / tot_t / 1e9
-    return dict(bound="hbm", kernel="k_relax_plan (red-black Vanka half-sweep, all levels, "
-                                    "launch-weighted)",
-                achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s", frac=achieved / PEAK_HBM_GBS,
-                traffic=None, bytes_per_cycle=tot_b, us_per_cycle=tot_t * 1e6, levels=rows)
+    for g in groups.values():
+        g["avg_launch_us"] = g["us_per_cycle"] / g["launches_per_cycle"]
+        g["bytes_per_launch"] = g["bytes_per_cycle"] / g["launches_per_cycle"]
+        g["gbs"] = g["bytes_per_cycle"] / g["us_per_cycle"] / 1e3
+    dom = max(groups.values(), key=lambda g: g["us_per_cycle"])
+    achieved = dom["gbs"]
+    rec = traffic_record(w.name, dom["kernel"])
+    tot_b = sum(g["bytes_per_cycle"] for g in groups.values())
+    tot_t = sum(g["us_per_cycle"] for g in groups.values())
+    return dict(bound="hbm", kernel=dom["kernel"], achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s",
+                frac=achieved / PEAK_HBM_GBS,
+                traffic=(rec["hbm_bytes_per_launch"] if rec else None),
+                traffic_unit="HBM bytes per launch (counters scaled by a plain copy)",
+                bytes_per_launch=dom["bytes_per_launch"], avg_launch_us=dom["avg_launch_us"],
+                launches_per_cycle=dom["launches_per_cycle"],
+                all_levels={"gbs": tot_b / tot_t / 1e3, "us_per_cycle": tot_t, "bytes_per_cycle": tot_b},
+                kernels=sorted(groups.values(), key=lambda g: -g["us_per_cycle"]), levels=rows)
 
 
 def cpu_baseline(w, gpu_iters, budget_s=20.0):

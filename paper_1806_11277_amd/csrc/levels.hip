@@ -389,6 +389,17 @@ __global__ __launch_bounds__(256) void k_relax_plan(Op op, int colour, T w, int 
     }
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin (linear id mod 8), and each XCD
+// has its own L2.  Renumbering so that every XCD receives one contiguous range
+// of logical blocks keeps the rows above and below a block's cells (stencil
+// neighbours) in the same L2.  Bijective for any block count.
+EHH_DEV inline int64_t xcd_block(int64_t bid, int64_t nb) {
+    constexpr int64_t X = 8;
+    const int64_t q = nb / X, rem = nb % X;
+    const int64_t xcd = bid % X, local = bid / X;
+    return xcd < rem ? xcd * (q + 1) + local : rem * (q + 1) + (xcd - rem) * q + local;
+}
+
 // Raw buffer access: a scalar resource descriptor (base, size in bytes) plus a
 // 32-bit byte offset per lane, so that a kernel keeps one VGPR per address.
 // Reads past the descriptor's size return zero.
@@ -433,7 +444,7 @@ __global__ __launch_bounds__(256) void k_relax_cell2d(FineOp<2, T> op, int colou
     const Geo& g = op.g;
     const int n0 = g.n[0], n1 = g.n[1];
     const int hp = n0 >> 1;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (t >= (int64_t)hp * n1) return;
     const int r_begin = blockIdx.y * rpb;
     const int r_end = r_begin + rpb < nrhs ? r_begin + rpb : nrhs;
@@ -523,6 +534,7 @@ __global__ __launch_bounds__(256) void k_relax_cell2d(FineOp<2, T> op, int colou
         if (ein) {
             const Buf<T> ei(ein + (int64_t)r * stride, VB);
             auto ld = [&](U i) { return mk<T>(ei.ld(i), ei.ld(NB + i)); };
+            // every load of the iteration is issued before the arithmetic
             el = ld(kl);
             ere = ld(kr);
             eb = ld(kb);
@@ -530,15 +542,16 @@ __global__ __launch_bounds__(256) void k_relax_cell2d(FineOp<2, T> op, int colou
             ep = ld(kp);
             epo = ld(kpo);
             const cx<T> pl_ = ld(kp + sp_l), pr_ = ld(kp + sp_r), pb_ = ld(kp + sp_b), pt_ = ld(kp + sp_t);
+            const cx<T> l_n = ld(kl + sl_n), l_th = ld(kl + sl_th), l_tl = ld(kl + sl_tl);
+            const cx<T> r_n = ld(kr + sr_n), r_th = ld(kr + sr_th), r_tl = ld(kr + sr_tl);
+            const cx<T> b_n = ld(kb + sb_n), b_th = ld(kb + sb_th), b_tl = ld(kb + sb_tl);
+            const cx<T> t_n = ld(kt + st_n), t_th = ld(kt + st_th), t_tl = ld(kt + st_tl);
+            __builtin_amdgcn_sched_barrier(0);
             // residuals of the five rows: r = b - A e
-            rl = rl - (dl * el + c0 * ere + wl_nlo * ld(kl + sl_n) + wl_thi * ld(kl + sl_th) + wl_tlo * ld(kl + sl_tl) +
-                       gl0 * (ep - pl_));
-            rr = rr - (dr * ere + c0 * el + wr_nhi * ld(kr + sr_n) + wr_thi * ld(kr + sr_th) + wr_tlo * ld(kr + sr_tl) +
-                       (-gh0) * (pr_ - ep));
-            rb_ = rb_ - (db * eb + c1 * et + wb_nlo * ld(kb + sb_n) + wb_thi * ld(kb + sb_th) + wb_tlo * ld(kb + sb_tl) +
-                         gl1 * (ep - pb_));
-            rt = rt - (dt * et + c1 * eb + wt_nhi * ld(kt + st_n) + wt_thi * ld(kt + st_th) + wt_tlo * ld(kt + st_tl) +
-                       (-gh1) * (pt_ - ep));
+            rl = rl - (dl * el + c0 * ere + wl_nlo * l_n + wl_thi * l_th + wl_tlo * l_tl + gl0 * (ep - pl_));
+            rr = rr - (dr * ere + c0 * el + wr_nhi * r_n + wr_thi * r_th + wr_tlo * r_tl + (-gh0) * (pr_ - ep));
+            rb_ = rb_ - (db * eb + c1 * et + wb_nlo * b_n + wb_thi * b_th + wb_tlo * b_tl + gl1 * (ep - pb_));
+            rt = rt - (dt * et + c1 * eb + wt_nhi * t_n + wt_thi * t_th + wt_tlo * t_tl + (-gh1) * (pt_ - ep));
             rp = rp - (pdiag * ep + gh0 * ere + gl0 * el + gh1 * et + gl1 * eb);
         }
         // closed-form block solve
@@ -555,6 +568,110 @@ __global__ __launch_bounds__(256) void k_relax_cell2d(FineOp<2, T> op, int colou
         if (vt) st(kt, et + w * (y1h - z1h * dp));
         st(kp, ep + w * dp);
         st(kpo, epo);
+    }
+}
+
+// y = A x (or b - A x) on the finest 2D level, one thread per cell: the cell
+// owns its left u_0 face, its bottom u_1 face and its pressure (the faces on the
+// walls are not unknowns), so every unknown is written once; the three rows
+// need thirteen values of x.
+template <typename T>
+__global__ __launch_bounds__(256) void k_apply_cell2d(FineOp<2, T> op, const T* __restrict__ x,
+                                                      const T* __restrict__ b, T* __restrict__ y, int nrhs,
+                                                      int64_t stride, int rpb) {
+    const Geo& g = op.g;
+    const int n0 = g.n[0], n1 = g.n[1];
+    const int64_t t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n0 * n1) return;
+    const int r_begin = blockIdx.y * rpb;
+    const int r_end = r_begin + rpb < nrhs ? r_begin + rpb : nrhs;
+    const int cx_ = (int)(t % n0), cy = (int)(t / n0);
+    const bool vu = cx_ >= 1, vv = cy >= 1;           // the owned faces exist
+    const int pu[3] = {cx_, cy, 0}, pv[3] = {cx_, cy, 0};
+    using U = uint32_t;
+    constexpr U E = (U)sizeof(T);
+    const int d0 = n0 - 1;
+    // owned unknowns (clamped to a valid unknown when absent; not written then)
+    const U ku = E * (U)(g.off[0] + (int64_t)cy * d0 + (vu ? cx_ - 1 : 0));
+    const U kv = E * (U)(g.off[1] + (int64_t)(vv ? cy - 1 : 0) * n0 + cx_);
+    const U kp = E * (U)(g.off[3] + (int64_t)cy * n0 + cx_);
+    // u_0 row at face (cx, cy)
+    cx<T> du = mk<T>(T(0), T(0));
+    T wu_nh = T(0), wu_nl = T(0), wu_th = T(0), wu_tl = T(0);
+    if (vu) {
+        du = op.diag_u(0, pu);
+        int q[3] = {cx_, cy, 0};
+        if (cx_ + 1 <= n0 - 1) wu_nh = -op.mu_c(q);
+        q[0] = cx_ - 1;
+        if (cx_ - 1 >= 1) wu_nl = -op.mu_c(q);
+        if (cy + 1 < n1) wu_th = -op.mu_edge(0, pu, 1, cy + 1);
+        if (cy - 1 >= 0) wu_tl = -op.mu_edge(0, pu, 1, cy);
+    }
+    // u_1 row at face (cx, cy)
+    cx<T> dv = mk<T>(T(0), T(0));
+    T wv_nh = T(0), wv_nl = T(0), wv_th = T(0), wv_tl = T(0);
+    if (vv) {
+        dv = op.diag_u(1, pv);
+        int q[3] = {cx_, cy, 0};
+        if (cy + 1 <= n1 - 1) wv_nh = -op.mu_c(q);
+        q[1] = cy - 1;
+        if (cy - 1 >= 1) wv_nl = -op.mu_c(q);
+        if (cx_ + 1 < n0) wv_th = -op.mu_edge(1, pv, 0, cx_ + 1);
+        if (cx_ - 1 >= 0) wv_tl = -op.mu_edge(1, pv, 0, cx_);
+    }
+    const int cc[3] = {cx_, cy, 0};
+    const T pdiag = -op.c.dinv[cell_idx<2>(g, cc)];
+    // neighbour offsets relative to the owned unknowns (0 where the weight is 0)
+    const U ud0 = E * (U)d0, un0 = E * (U)n0;
+    const U su_nh = wu_nh != T(0) ? E : 0u, su_nl = wu_nl != T(0) ? 0u - E : 0u;
+    const U su_th = wu_th != T(0) ? ud0 : 0u, su_tl = wu_tl != T(0) ? 0u - ud0 : 0u;
+    const U sv_nh = wv_nh != T(0) ? un0 : 0u, sv_nl = wv_nl != T(0) ? 0u - un0 : 0u;
+    const U sv_th = wv_th != T(0) ? E : 0u, sv_tl = wv_tl != T(0) ? 0u - E : 0u;
+    const bool pl = cx_ >= 1, pb = cy >= 1;           // cells left and below exist
+    const U sp_l = pl ? 0u - E : 0u, sp_b = pb ? 0u - un0 : 0u;
+    // the p row: faces right (u_0 at cx+1) and top (u_1 at cy+1) when interior
+    const bool fr = cx_ + 1 <= n0 - 1, ft = cy + 1 <= n1 - 1;
+    const U kur = fr ? E * (U)(g.off[0] + (int64_t)cy * d0 + cx_) : ku;
+    const U kvt = ft ? E * (U)(g.off[1] + (int64_t)cy * n0 + cx_) : kv;
+    const T gr = fr ? T(-1) : T(0), gl = vu ? T(1) : T(0), gt = ft ? T(-1) : T(0), gb = vv ? T(1) : T(0);
+    const U NB = E * (U)g.N, VB = 2 * NB;
+    for (int r = r_begin; r < r_end; ++r) {
+        const Buf<T> xb(x + (int64_t)r * stride, VB);
+        const Buf<T> yb(y + (int64_t)r * stride, VB);
+        auto ld = [&](U i) { return mk<T>(xb.ld(i), xb.ld(NB + i)); };
+        // every load of the iteration is issued before the arithmetic (the
+        // scheduler would otherwise wait on each load in turn)
+        const cx<T> xu = ld(ku), xv = ld(kv), xp = ld(kp);
+        const cx<T> xpl = ld(kp + sp_l), xpb = ld(kp + sp_b);
+        const cx<T> u_nh = ld(ku + su_nh), u_nl = ld(ku + su_nl), u_th = ld(ku + su_th), u_tl = ld(ku + su_tl);
+        const cx<T> v_nh = ld(kv + sv_nh), v_nl = ld(kv + sv_nl), v_th = ld(kv + sv_th), v_tl = ld(kv + sv_tl);
+        const cx<T> x_r = ld(kur), x_t = ld(kvt);
+        cx<T> b_u = mk<T>(T(0), T(0)), b_v = b_u, b_p = b_u;
+        if (b) {
+            const Buf<T> bb(b + (int64_t)r * stride, VB);
+            b_u = mk<T>(bb.ld(ku), bb.ld(NB + ku));
+            b_v = mk<T>(bb.ld(kv), bb.ld(NB + kv));
+            b_p = mk<T>(bb.ld(kp), bb.ld(NB + kp));
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        cx<T> au = du * xu + wu_nh * u_nh + wu_nl * u_nl + wu_th * u_th + wu_tl * u_tl + (xp - xpl);
+        cx<T> av = dv * xv + wv_nh * v_nh + wv_nl * v_nl + wv_th * v_th + wv_tl * v_tl + (xp - xpb);
+        cx<T> ap = pdiag * xp + gr * x_r + gl * xu + gt * x_t + gb * xv;
+        if (b) {
+            au = b_u - au;
+            av = b_v - av;
+            ap = b_p - ap;
+        }
+        if (vu) {
+            yb.st(ku, au.re);
+            yb.st(NB + ku, au.im);
+        }
+        if (vv) {
+            yb.st(kv, av.re);
+            yb.st(NB + kv, av.im);
+        }
+        yb.st(kp, ap.re);
+        yb.st(NB + kp, ap.im);
     }
 }
 
@@ -1000,7 +1117,15 @@ hipError_t launch_apply(const LevelDesc<T>& L, const T* x, const T* b, T* y, int
     const int rb3 = rhs_block_3d_stencil<T>();
     const int rpb3 = rhs_per_block((L.g.N + 63) / 64, nrhs, rb3);
     const dim3 gb3(nblk(L.g.N), (nrhs + rpb3 - 1) / rpb3);
-    if (L.g.dim == 2) {
+    if (L.g.dim == 2 && L.fine && cell2d_enabled() && 2 * L.g.N * (int64_t)sizeof(T) < (int64_t(1) << 32)) {
+        const int64_t cells = L.g.ncell;
+        static const int64_t cell_waves = env_int("EHH_CELL_WAVES", 4096);
+        int64_t groups = (cell_waves + (cells + 63) / 64 - 1) / ((cells + 63) / 64);
+        groups = groups < 1 ? 1 : (groups > nrhs ? nrhs : groups);
+        const int rpc = (int)((nrhs + groups - 1) / groups);
+        const dim3 gc(nblk(cells), (nrhs + rpc - 1) / rpc);
+        hipLaunchKernelGGL((k_apply_cell2d<T>), gc, 256, 0, s, FineOp<2, T>{L.g, L.f}, x, b, y, nrhs, stride, rpc);
+    } else if (L.g.dim == 2) {
         if (L.fine)
             EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_apply_plan<2, T, FineOp<2, T>, RB>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, x, b, y, nrhs, stride, rpb));
         else
