@@ -675,6 +675,301 @@ __global__ __launch_bounds__(256) void k_apply_cell2d(FineOp<2, T> op, const T* 
     }
 }
 
+// ------------------------------------------- one thread per cell (3D finest level)
+// The 3D form of k_relax_cell2d: the cell's 7 x 7 block (a 2 x 2 block per
+// displacement component, the pressure coupled to all six faces) is inverted in
+// closed form once per thread; each source then needs 43 values of e_in (per
+// component the two faces, their outer normal neighbours and four tangential
+// neighbours each; the pressure and its six neighbours) and b at 7 unknowns.
+template <typename T>
+__global__ __launch_bounds__(256) void k_relax_cell3d(FineOp<3, T> op, int colour, T w, int econ,
+                                                      const T* __restrict__ b, const T* __restrict__ ein,
+                                                      T* __restrict__ eout, int nrhs, int64_t stride, int rpb) {
+    const Geo& g = op.g;
+    const int n[3] = {g.n[0], g.n[1], g.n[2]};
+    const int hp = n[0] >> 1;
+    const int64_t t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)hp * n[1] * n[2]) return;
+    const int r_begin = blockIdx.y * rpb;
+    const int r_end = r_begin + rpb < nrhs ? r_begin + rpb : nrhs;
+    const int px = (int)(t % hp);
+    const int yz = (int)(t / hp);
+    const int y = yz % n[1], z = yz / n[1];
+    const int par = (colour + y + z) & 1;
+    const int c[3] = {2 * px + par, y, z};
+    const int xo = 2 * px + 1 - par;
+    using U = uint32_t;
+    constexpr U E = (U)sizeof(T);
+    const cx<T> one = mk<T>(T(1), T(0));
+    // per component k: faces lo (p[k] = c[k]) and hi (p[k] = c[k] + 1)
+    bool vlo[3], vhi[3];
+    cx<T> dlo[3], dhi[3];
+    T cpl[3];                      // in-block coupling -mu(c) (0 if a face is absent)
+    T wn_lo[3], wn_hi[3];          // outer normal neighbours
+    T wt_lo[3][4], wt_hi[3][4];    // tangential neighbours: (t1+, t1-, t2+, t2-)
+    U klo[3], khi[3], sn_lo[3], sn_hi[3], st_lo[3][4], st_hi[3][4];
+    const T mu_k = op.mu_c(c);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int d0 = n[0] - (k == 0), d1 = n[1] - (k == 1);
+        const U sk[3] = {E, E * (U)d0, E * (U)d0 * (U)d1};   // byte strides of component k
+        const int t1 = tang1<3>(k), t2 = tang2<3>(k);
+        int pl[3] = {c[0], c[1], c[2]}, ph[3] = {c[0], c[1], c[2]};
+        ph[k] += 1;
+        vlo[k] = c[k] >= 1;
+        vhi[k] = c[k] + 1 <= n[k] - 1;
+        dlo[k] = vlo[k] ? op.diag_u(k, pl) : one;
+        dhi[k] = vhi[k] ? op.diag_u(k, ph) : one;
+        cpl[k] = (vlo[k] && vhi[k]) ? -mu_k : T(0);
+        int q[3] = {c[0], c[1], c[2]};
+        q[k] = c[k] - 1;
+        const bool nl = vlo[k] && c[k] - 1 >= 1;
+        wn_lo[k] = nl ? -op.mu_c(q) : T(0);
+        q[k] = c[k] + 1;
+        const bool nh = vhi[k] && c[k] + 2 <= n[k] - 1;
+        wn_hi[k] = nh ? -op.mu_c(q) : T(0);
+        int pcl[3] = {c[0], c[1], c[2]};
+        if (!vlo[k]) pcl[k] = 1;
+        int pch[3] = {c[0], c[1], c[2]};
+        pch[k] = vhi[k] ? c[k] + 1 : 1;
+        klo[k] = E * (U)(g.off[k]) + E * (U)face_idx<3>(g, k, pcl);
+        khi[k] = E * (U)(g.off[k]) + E * (U)face_idx<3>(g, k, pch);
+        sn_lo[k] = nl ? 0u - sk[k] : 0u;
+        sn_hi[k] = nh ? sk[k] : 0u;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int ta = j == 0 ? t1 : t2;
+            const bool up_ok = c[ta] + 1 < n[ta], dn_ok = c[ta] - 1 >= 0;
+            wt_lo[k][2 * j] = (vlo[k] && up_ok) ? -op.mu_edge(k, pl, ta, c[ta] + 1) : T(0);
+            wt_lo[k][2 * j + 1] = (vlo[k] && dn_ok) ? -op.mu_edge(k, pl, ta, c[ta]) : T(0);
+            wt_hi[k][2 * j] = (vhi[k] && up_ok) ? -op.mu_edge(k, ph, ta, c[ta] + 1) : T(0);
+            wt_hi[k][2 * j + 1] = (vhi[k] && dn_ok) ? -op.mu_edge(k, ph, ta, c[ta]) : T(0);
+            st_lo[k][2 * j] = wt_lo[k][2 * j] != T(0) ? sk[ta] : 0u;
+            st_lo[k][2 * j + 1] = wt_lo[k][2 * j + 1] != T(0) ? 0u - sk[ta] : 0u;
+            st_hi[k][2 * j] = wt_hi[k][2 * j] != T(0) ? sk[ta] : 0u;
+            st_hi[k][2 * j + 1] = wt_hi[k][2 * j + 1] != T(0) ? 0u - sk[ta] : 0u;
+        }
+    }
+    const T pdiag = -op.c.dinv[cell_idx<3>(g, c)];
+    // block inverse: per component [[d_lo, c], [c, d_hi]]^{-1}; g = (+1, -1) on present faces
+    cx<T> a00[3], a01[3], a11[3], zl[3], zh[3];
+    T gl[3], gh[3];
+    cx<T> S = mk<T>(pdiag, T(0));
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        gl[k] = vlo[k] ? T(1) : T(0);
+        gh[k] = vhi[k] ? T(-1) : T(0);
+        const T cu = econ ? T(0) : cpl[k];
+        const cx<T> id = cinv(dlo[k] * dhi[k] - mk<T>(cu * cu, T(0)));
+        a00[k] = dhi[k] * id;
+        a11[k] = dlo[k] * id;
+        a01[k] = (-cu) * id;
+        zl[k] = gl[k] * a00[k] + gh[k] * a01[k];
+        zh[k] = gl[k] * a01[k] + gh[k] * a11[k];
+        S = S - (gl[k] * zl[k] + gh[k] * zh[k]);
+    }
+    const cx<T> iS = cinv(S);
+    const U kp = E * (U)(g.off[3] + cell_idx<3>(g, c));
+    int co[3] = {xo, y, z};
+    const U kpo = E * (U)(g.off[3] + cell_idx<3>(g, co));
+    const U pstride[3] = {E, E * (U)n[0], E * (U)n[0] * (U)n[1]};
+    U sp_lo[3], sp_hi[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        sp_lo[k] = vlo[k] ? 0u - pstride[k] : 0u;
+        sp_hi[k] = vhi[k] ? pstride[k] : 0u;
+    }
+    const U NB = E * (U)g.N, VB = 2 * NB;
+    for (int r = r_begin; r < r_end; ++r) {
+        const Buf<T> bb(b + (int64_t)r * stride, VB);
+        const Buf<T> eo(eout + (int64_t)r * stride, VB);
+        auto ldb = [&](U i) { return mk<T>(bb.ld(i), bb.ld(NB + i)); };
+        cx<T> rlo[3], rhi[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            rlo[k] = vlo[k] ? ldb(klo[k]) : mk<T>(T(0), T(0));
+            rhi[k] = vhi[k] ? ldb(khi[k]) : mk<T>(T(0), T(0));
+        }
+        cx<T> rp = ldb(kp);
+        cx<T> elo[3], ehi[3], ep = mk<T>(T(0), T(0)), epo = ep;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) elo[k] = ehi[k] = mk<T>(T(0), T(0));
+        if (ein) {
+            const Buf<T> ei(ein + (int64_t)r * stride, VB);
+            auto ld = [&](U i) { return mk<T>(ei.ld(i), ei.ld(NB + i)); };
+            cx<T> nlo[3], nhi[3], tlo[3][4], thi[3][4], plo[3], phi[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                elo[k] = ld(klo[k]);
+                ehi[k] = ld(khi[k]);
+                nlo[k] = ld(klo[k] + sn_lo[k]);
+                nhi[k] = ld(khi[k] + sn_hi[k]);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    tlo[k][j] = ld(klo[k] + st_lo[k][j]);
+                    thi[k][j] = ld(khi[k] + st_hi[k][j]);
+                }
+                plo[k] = ld(kp + sp_lo[k]);
+                phi[k] = ld(kp + sp_hi[k]);
+            }
+            ep = ld(kp);
+            epo = ld(kpo);
+            __builtin_amdgcn_sched_barrier(0);
+            // residuals r = b - A e of the seven rows
+            cx<T> ap = pdiag * ep;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                cx<T> al = dlo[k] * elo[k] + cpl[k] * ehi[k] + wn_lo[k] * nlo[k] + gl[k] * (ep - plo[k]);
+                cx<T> ah = dhi[k] * ehi[k] + cpl[k] * elo[k] + wn_hi[k] * nhi[k] + (-gh[k]) * (phi[k] - ep);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    al = al + wt_lo[k][j] * tlo[k][j];
+                    ah = ah + wt_hi[k][j] * thi[k][j];
+                }
+                rlo[k] = rlo[k] - al;
+                rhi[k] = rhi[k] - ah;
+                ap = ap + gh[k] * ehi[k] + gl[k] * elo[k];
+            }
+            rp = rp - ap;
+        }
+        // closed-form block solve
+        cx<T> ylo[3], yhi[3];
+        cx<T> acc = rp;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            ylo[k] = a00[k] * rlo[k] + a01[k] * rhi[k];
+            yhi[k] = a01[k] * rlo[k] + a11[k] * rhi[k];
+            acc = acc - (gl[k] * ylo[k] + gh[k] * yhi[k]);
+        }
+        const cx<T> dp = acc * iS;
+        auto st = [&](U i, cx<T> v) {
+            eo.st(i, v.re);
+            eo.st(NB + i, v.im);
+        };
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (vlo[k]) st(klo[k], elo[k] + w * (ylo[k] - zl[k] * dp));
+            if (vhi[k]) st(khi[k], ehi[k] + w * (yhi[k] - zh[k] * dp));
+        }
+        st(kp, ep + w * dp);
+        st(kpo, epo);
+    }
+}
+
+// y = A x (or b - A x) on the finest 3D level, one thread per cell owning its
+// three lower faces (those on the walls are not unknowns) and its pressure.
+template <typename T>
+__global__ __launch_bounds__(256) void k_apply_cell3d(FineOp<3, T> op, const T* __restrict__ x,
+                                                      const T* __restrict__ b, T* __restrict__ y, int nrhs,
+                                                      int64_t stride, int rpb) {
+    const Geo& g = op.g;
+    const int n[3] = {g.n[0], g.n[1], g.n[2]};
+    const int64_t t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (t >= g.ncell) return;
+    const int r_begin = blockIdx.y * rpb;
+    const int r_end = r_begin + rpb < nrhs ? r_begin + rpb : nrhs;
+    int c[3];
+    cell_pos<3>(g, t, c);
+    using U = uint32_t;
+    constexpr U E = (U)sizeof(T);
+    bool v[3];
+    cx<T> dg[3];
+    T wnh[3], wnl[3], wt[3][4];
+    U ku[3], snh[3], snl[3], st[3][4], khi[3];
+    T ghi[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int d0 = n[0] - (k == 0), d1 = n[1] - (k == 1);
+        const U sk[3] = {E, E * (U)d0, E * (U)d0 * (U)d1};
+        const int t1 = tang1<3>(k), t2 = tang2<3>(k);
+        v[k] = c[k] >= 1;
+        int pc[3] = {c[0], c[1], c[2]};
+        if (!v[k]) pc[k] = 1;
+        ku[k] = E * (U)(g.off[k] + face_idx<3>(g, k, pc));
+        dg[k] = mk<T>(T(0), T(0));
+        wnh[k] = wnl[k] = T(0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) wt[k][j] = T(0);
+        if (v[k]) {
+            dg[k] = op.diag_u(k, c);
+            int q[3] = {c[0], c[1], c[2]};
+            if (c[k] + 1 <= n[k] - 1) wnh[k] = -op.mu_c(q);
+            q[k] = c[k] - 1;
+            if (c[k] - 1 >= 1) wnl[k] = -op.mu_c(q);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int ta = j == 0 ? t1 : t2;
+                if (c[ta] + 1 < n[ta]) wt[k][2 * j] = -op.mu_edge(k, c, ta, c[ta] + 1);
+                if (c[ta] - 1 >= 0) wt[k][2 * j + 1] = -op.mu_edge(k, c, ta, c[ta]);
+            }
+        }
+        snh[k] = wnh[k] != T(0) ? sk[k] : 0u;
+        snl[k] = wnl[k] != T(0) ? 0u - sk[k] : 0u;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int ta = j == 0 ? t1 : t2;
+            st[k][2 * j] = wt[k][2 * j] != T(0) ? sk[ta] : 0u;
+            st[k][2 * j + 1] = wt[k][2 * j + 1] != T(0) ? 0u - sk[ta] : 0u;
+        }
+        // the p row's upper face of component k (face c[k] + 1), when interior
+        const bool fh = c[k] + 1 <= n[k] - 1;
+        int ph[3] = {c[0], c[1], c[2]};
+        ph[k] = fh ? c[k] + 1 : 1;
+        khi[k] = E * (U)(g.off[k] + face_idx<3>(g, k, ph));
+        ghi[k] = fh ? T(-1) : T(0);
+    }
+    const T pdiag = -op.c.dinv[t];
+    const U kp = E * (U)(g.off[3] + t);
+    const U pstr[3] = {E, E * (U)n[0], E * (U)n[0] * (U)n[1]};
+    U spl[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) spl[k] = v[k] ? 0u - pstr[k] : 0u;
+    const U NB = E * (U)g.N, VB = 2 * NB;
+    for (int r = r_begin; r < r_end; ++r) {
+        const Buf<T> xb(x + (int64_t)r * stride, VB);
+        const Buf<T> yb(y + (int64_t)r * stride, VB);
+        auto ld = [&](U i) { return mk<T>(xb.ld(i), xb.ld(NB + i)); };
+        cx<T> xu[3], xnh[3], xnl[3], xt[3][4], xpl[3], xh[3], bu[3];
+        const cx<T> xp = ld(kp);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            xu[k] = ld(ku[k]);
+            xnh[k] = ld(ku[k] + snh[k]);
+            xnl[k] = ld(ku[k] + snl[k]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) xt[k][j] = ld(ku[k] + st[k][j]);
+            xpl[k] = ld(kp + spl[k]);
+            xh[k] = ld(khi[k]);
+        }
+        cx<T> bp = mk<T>(T(0), T(0));
+#pragma unroll
+        for (int k = 0; k < 3; ++k) bu[k] = bp;
+        if (b) {
+            const Buf<T> bb(b + (int64_t)r * stride, VB);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) bu[k] = mk<T>(bb.ld(ku[k]), bb.ld(NB + ku[k]));
+            bp = mk<T>(bb.ld(kp), bb.ld(NB + kp));
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        cx<T> ap = pdiag * xp;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            cx<T> au = dg[k] * xu[k] + wnh[k] * xnh[k] + wnl[k] * xnl[k] + (xp - xpl[k]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) au = au + wt[k][j] * xt[k][j];
+            if (b) au = bu[k] - au;
+            if (v[k]) {
+                yb.st(ku[k], au.re);
+                yb.st(NB + ku[k], au.im);
+            }
+            ap = ap + ghi[k] * xh[k] + (v[k] ? T(1) : T(0)) * xu[k];
+        }
+        if (b) ap = bp - ap;
+        yb.st(kp, ap.re);
+        yb.st(NB + kp, ap.im);
+    }
+}
+
 // ---------------------------------------------------- LDS-staged half-sweep (2D)
 // A block relaxes the red cells of a 16 x 8 tile (64 cells, eight lanes each as in
 // k_relax_plan).  For every right-hand side the vectors the tile's rows touch
@@ -1085,6 +1380,10 @@ static inline bool cell2d_enabled() {
     static const bool v = env_int("EHH_CELL2D", 1) != 0;
     return v;
 }
+static inline bool cell3d_enabled() {
+    static const bool v = env_int("EHH_CELL3D", 1) != 0;
+    return v;
+}
 static inline bool lds2d_enabled() {
     static const bool v = env_int("EHH_LDS2D", 1) != 0;
     return v;
@@ -1130,6 +1429,14 @@ hipError_t launch_apply(const LevelDesc<T>& L, const T* x, const T* b, T* y, int
             EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_apply_plan<2, T, FineOp<2, T>, RB>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, x, b, y, nrhs, stride, rpb));
         else
             EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_apply_plan<2, T, StOp<2, T>, RB>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, x, b, y, nrhs, stride, rpb));
+    } else if (L.g.dim == 3 && L.fine && cell3d_enabled() && 2 * L.g.N * (int64_t)sizeof(T) < (int64_t(1) << 32)) {
+        const int64_t cells = L.g.ncell;
+        static const int64_t cell_waves = env_int("EHH_CELL_WAVES", 4096);
+        int64_t groups = (cell_waves + (cells + 63) / 64 - 1) / ((cells + 63) / 64);
+        groups = groups < 1 ? 1 : (groups > nrhs ? nrhs : groups);
+        const int rpc = (int)((nrhs + groups - 1) / groups);
+        const dim3 gc(nblk(cells), (nrhs + rpc - 1) / rpc);
+        hipLaunchKernelGGL((k_apply_cell3d<T>), gc, 256, 0, s, FineOp<3, T>{L.g, L.f}, x, b, y, nrhs, stride, rpc);
     } else {
         if (L.fine)
             EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_apply_plan<3, T, FineOp<3, T>, RB>), gb, 256, 0, s, FineOp<3, T>{L.g, L.f}, x, b, y, nrhs, stride, rpb));
@@ -1173,6 +1480,14 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
             EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_relax_plan<2, T, FineOp<2, T>, RB>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb));
         else
             EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_relax_plan<2, T, StOp<2, T>, RB>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb));
+    } else if (L.fine && cell3d_enabled() && 2 * L.g.N * (int64_t)sizeof(T) < (int64_t(1) << 32)) {
+        const int64_t cells = npair;
+        static const int64_t cell_waves = env_int("EHH_CELL_WAVES", 4096);
+        int64_t groups = (cell_waves + (cells + 63) / 64 - 1) / ((cells + 63) / 64);
+        groups = groups < 1 ? 1 : (groups > nrhs ? nrhs : groups);
+        const int rpc = (int)((nrhs + groups - 1) / groups);
+        const dim3 gc(nblk(cells), (nrhs + rpc - 1) / rpc);
+        hipLaunchKernelGGL((k_relax_cell3d<T>), gc, 256, 0, s, FineOp<3, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride, rpc);
     } else {
         if (L.fine)
             EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_relax_plan<3, T, FineOp<3, T>, RB>), gb, 256, 0, s, FineOp<3, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb));
