@@ -85,6 +85,14 @@ struct Level {
     void* b = nullptr;          // right-hand side of this level (levels >= 1)
     void* e = nullptr;          // correction of this level (levels >= 1)
     void* t = nullptr;          // half-sweep ping-pong / residual
+    // row plans of the two colours' half-sweeps (cycle precision), where stored
+    int32_t* sp_ix[2] = {nullptr, nullptr};
+    void* sp_re[2] = {nullptr, nullptr};
+    void* sp_im[2] = {nullptr, nullptr};
+    int64_t sp_lanes = 0;
+    int32_t* rp_ix = nullptr;   // row plans of the residual, where stored
+    void* rp_re = nullptr;
+    void* rp_im = nullptr;
 };
 
 struct Sub {
@@ -182,6 +190,19 @@ template <typename T> LevelDesc<T> level_desc(const ehh_ctx* c, const Level& L, 
         d.f = FineCoef<T>{base, base + n, base + 2 * n, base + 3 * n, (T)(c->omega_nd * c->omega_nd), (T)alpha};
     } else if (L.g.dim == 2) {
         d.s = stencil_view<2, T>(L.g, base);
+        const bool mine = (sizeof(T) == 4) == (c->bits() == 32);   // plans are kept in the cycle precision
+        if (mine && L.sp_lanes)
+            for (int col = 0; col < 2; ++col) {
+                d.sp.ix[col] = L.sp_ix[col];
+                d.sp.re[col] = (const T*)L.sp_re[col];
+                d.sp.im[col] = (const T*)L.sp_im[col];
+            }
+        d.sp.lanes = L.sp_lanes;
+        if (mine && L.rp_ix) {
+            d.sp.rix = L.rp_ix;
+            d.sp.rre = (const T*)L.rp_re;
+            d.sp.rim = (const T*)L.rp_im;
+        }
     } else {
         d.s = stencil_view<3, T>(L.g, base);
     }
@@ -555,6 +576,36 @@ int32_t build_hierarchy(ehh_ctx* c, Sub& S, const double* lam, const double* mu,
             CHK(c->alloc((void**)&Q.coef32, sizeof(float) * cnt));
             HIPCHK(launch_cast_d2f(Q.coef64, Q.coef32, cnt, s));
         }
+    }
+    // row plans of the small 2D Galerkin levels, built once in the cycle precision
+    for (int l = 1; l < L - 1; ++l) {
+        Level& Q = S.lev[l];
+        if (!stored_plan_wanted(Q.g, Q.fine)) continue;
+        const int64_t lanes = stored_plan_lanes(Q.g);
+        const size_t es = c->bits() == 32 ? sizeof(float) : sizeof(double);
+        constexpr int NT = St<2>::NF + St<2>::NUP;
+        for (int col = 0; col < 2; ++col) {
+            CHK(c->alloc((void**)&Q.sp_ix[col], sizeof(int32_t) * NT * lanes));
+            CHK(c->alloc(&Q.sp_re[col], es * NT * lanes));
+            CHK(c->alloc(&Q.sp_im[col], es * NT * lanes));
+            if (c->bits() == 32)
+                HIPCHK(launch_build_plans<float>(level_desc<float>(c, Q, c->prob.shift), col, Q.sp_ix[col],
+                                                 (float*)Q.sp_re[col], (float*)Q.sp_im[col], s));
+            else
+                HIPCHK(launch_build_plans<double>(level_desc<double>(c, Q, c->prob.shift), col, Q.sp_ix[col],
+                                                  (double*)Q.sp_re[col], (double*)Q.sp_im[col], s));
+        }
+        Q.sp_lanes = lanes;
+        const int64_t N = Q.g.N;
+        CHK(c->alloc((void**)&Q.rp_ix, sizeof(int32_t) * NT * N));
+        CHK(c->alloc(&Q.rp_re, es * NT * N));
+        CHK(c->alloc(&Q.rp_im, es * NT * N));
+        if (c->bits() == 32)
+            HIPCHK(launch_build_row_plans<float>(level_desc<float>(c, Q, c->prob.shift), Q.rp_ix, (float*)Q.rp_re,
+                                                 (float*)Q.rp_im, s));
+        else
+            HIPCHK(launch_build_row_plans<double>(level_desc<double>(c, Q, c->prob.shift), Q.rp_ix,
+                                                  (double*)Q.rp_re, (double*)Q.rp_im, s));
     }
     return EHH_OK;
 }

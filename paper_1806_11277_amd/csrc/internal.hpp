@@ -9,11 +9,26 @@ namespace ehh {
 
 // Operator of one multigrid level in precision T: matrix-free on level 0 of a
 // (sub)domain, Galerkin stencils on the coarser levels.
+// Row plans of the 2D half-sweep stored in its lane order (one set per colour):
+// term j of lane i at [j * lanes + i]; null where a level builds its plans in the
+// kernel.
+template <typename T> struct StoredPlan {
+    const int32_t* ix[2] = {nullptr, nullptr};
+    const T* re[2] = {nullptr, nullptr};
+    const T* im[2] = {nullptr, nullptr};
+    int64_t lanes = 0;
+    // row plans of y = A x in row order (term j of row t at [j * N + t])
+    const int32_t* rix = nullptr;
+    const T* rre = nullptr;
+    const T* rim = nullptr;
+};
+
 template <typename T> struct LevelDesc {
     Geo g;
     bool fine;
     FineCoef<T> f;
     StCoef<T> s;
+    StoredPlan<T> sp;
 };
 
 // ---- levels.hip
@@ -22,6 +37,13 @@ hipError_t launch_apply(const LevelDesc<T>& L, const T* x, const T* b, T* y, int
 template <typename T>
 hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, const T* b, const T* ein,
                         T* eout, int nrhs, hipStream_t s);
+// Lanes (padded) of one colour's stored plans on a level, and the builder.
+int64_t stored_plan_lanes(const Geo& g);
+bool stored_plan_wanted(const Geo& g, bool fine);
+template <typename T>
+hipError_t launch_build_plans(const LevelDesc<T>& L, int colour, int32_t* ix, T* re, T* im, hipStream_t s);
+template <typename T>
+hipError_t launch_build_row_plans(const LevelDesc<T>& L, int32_t* ix, T* re, T* im, hipStream_t s);
 template <typename T>
 hipError_t launch_restrict(const Geo& gf, const Geo& gc, const T* rf, T* rc, int nrhs, hipStream_t s);
 template <typename T>

@@ -197,9 +197,12 @@ __global__ __launch_bounds__(256) void k_relax(Op op, int colour, T w, int econ,
 // ------------------------------------------------ plan-based apply and half-sweep
 // The row plan (indices and coefficients) is built once per row and reused for
 // every right-hand side, so a batch streams only the vectors.
-template <int D, typename T, class Op, int RB>
+template <int D, typename T, class Op, int RB, bool STORED = false>
 __global__ __launch_bounds__(256) void k_apply_plan(Op op, const T* __restrict__ x, const T* __restrict__ b,
-                                                    T* __restrict__ y, int nrhs, int64_t stride, int rpb) {
+                                                    T* __restrict__ y, int nrhs, int64_t stride, int rpb,
+                                                    const int32_t* __restrict__ spix = nullptr,
+                                                    const T* __restrict__ spre = nullptr,
+                                                    const T* __restrict__ spim = nullptr) {
     // right-hand sides [blockIdx.y * rpb, ...) of this grid row
     {
         const int rb0 = blockIdx.y * rpb;
@@ -216,7 +219,14 @@ __global__ __launch_bounds__(256) void k_apply_plan(Op op, const T* __restrict__
     const int64_t li = t - g.off[k];
     int p[3];
     Plan<T, Op::NT> P;
-    if (k == 3) {
+    if (STORED) {   // row plan built at setup, term j of row t at [j * N + t]
+#pragma unroll
+        for (int j = 0; j < Op::NT; ++j) {
+            P.ix[j] = spix[j * g.N + t];
+            P.re[j] = spre[j * g.N + t];
+            P.im[j] = spim[j * g.N + t];
+        }
+    } else if (k == 3) {
         cell_pos<D>(g, li, p);
         op.plan_p(p, P);
     } else {
@@ -245,10 +255,13 @@ __global__ __launch_bounds__(256) void k_apply_plan(Op op, const T* __restrict__
 // Eight lanes per relaxed cell as in k_relax, each lane holding the plan of its
 // block row; the block itself (diagonals, the coupling of the two faces of a
 // component, the couplings to the cell pressure) is read off the lanes' plans.
-template <int D, typename T, class Op, int RB>
+template <int D, typename T, class Op, int RB, bool STORED = false>
 __global__ __launch_bounds__(256) void k_relax_plan(Op op, int colour, T w, int econ,
                                                     const T* __restrict__ b, const T* __restrict__ ein,
-                                                    T* __restrict__ eout, int nrhs, int64_t stride, int rpb) {
+                                                    T* __restrict__ eout, int nrhs, int64_t stride, int rpb,
+                                                    const int32_t* __restrict__ spix = nullptr,
+                                                    const T* __restrict__ spre = nullptr,
+                                                    const T* __restrict__ spim = nullptr, int64_t splanes = 0) {
     {
         const int rb0 = blockIdx.y * rpb;
         b += rb0 * stride;
@@ -285,14 +298,20 @@ __global__ __launch_bounds__(256) void k_relax_plan(Op op, int colour, T w, int 
     }
     Plan<T, Op::NT> P;
     int64_t idx = 0;
-    if (ok) {
-        if (k == 3) {
-            op.plan_p(p, P);
-            idx = g.off[3] + cell_idx<D>(g, p);
-        } else {
-            op.plan_u(k, p, P);
-            idx = g.off[k] + face_idx<D>(g, k, p);
+    if (ok) idx = k == 3 ? g.off[3] + cell_idx<D>(g, p) : g.off[k] + face_idx<D>(g, k, p);
+    if (STORED) {   // the plan built at setup for this lane (coalesced over the lanes)
+        const int64_t gl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+#pragma unroll
+        for (int j = 0; j < Op::NT; ++j) {
+            P.ix[j] = spix[j * splanes + gl];
+            P.re[j] = spre[j * splanes + gl];
+            P.im[j] = spim[j * splanes + gl];
         }
+    } else if (ok) {
+        if (k == 3)
+            op.plan_p(p, P);
+        else
+            op.plan_u(k, p, P);
     } else {
 #pragma unroll
         for (int j = 0; j < Op::NT; ++j) P.set(j, 0, T(0), T(0));
@@ -970,6 +989,83 @@ __global__ __launch_bounds__(256) void k_apply_cell3d(FineOp<3, T> op, const T* 
     }
 }
 
+// Builds the row plans of one colour's half-sweep in the lane order of
+// k_relax_plan (same lane -> cell/row mapping, absent rows all zero).
+template <typename T>
+__global__ __launch_bounds__(256) void k_build_plans(StOp<2, T> op, int colour, int32_t* __restrict__ ix,
+                                                     T* __restrict__ re, T* __restrict__ im, int64_t lanes) {
+    constexpr int D = 2;
+    constexpr int R = 2 * D + 1;
+    using Op = StOp<2, T>;
+    const Geo& g = op.g;
+    const int64_t gl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gl >= lanes) return;
+    const int hp = g.n[0] >> 1;
+    const int64_t npair = (int64_t)hp * g.n[1] * g.n[2];
+    const int lane = (int)(gl & 63);
+    const int row = lane >> 3;
+    const int cig = lane & 7;
+    const int64_t t = (gl >> 6) * 8 + cig;
+    const bool live = t < npair;
+    const int64_t tt = live ? t : 0;
+    const int px = (int)(tt % hp);
+    const int64_t rest = tt / hp;
+    const int yy = (int)(rest % g.n[1]);
+    const int zz = (int)(rest / g.n[1]);
+    const int par = (colour + yy + zz) & 1;
+    const int k = row < 2 * D ? (row >> 1) : 3;
+    int p[3] = {2 * px + par, yy, zz};
+    bool ok = live && row < R;
+    if (k < 3) {
+        p[k] += row & 1;
+        ok = ok && p[k] >= 1 && p[k] <= g.n[k] - 1;
+    }
+    Plan<T, Op::NT> P;
+    if (ok) {
+        if (k == 3)
+            op.plan_p(p, P);
+        else
+            op.plan_u(k, p, P);
+    } else {
+#pragma unroll
+        for (int j = 0; j < Op::NT; ++j) P.set(j, 0, T(0), T(0));
+    }
+#pragma unroll
+    for (int j = 0; j < Op::NT; ++j) {
+        ix[j * lanes + gl] = P.ix[j];
+        re[j * lanes + gl] = P.re[j];
+        im[j * lanes + gl] = P.im[j];
+    }
+}
+
+// Row plans of y = A x in row order (term j of row t at [j * N + t]).
+template <typename T>
+__global__ __launch_bounds__(256) void k_build_row_plans(StOp<2, T> op, int32_t* __restrict__ ix,
+                                                         T* __restrict__ re, T* __restrict__ im) {
+    using Op = StOp<2, T>;
+    const Geo& g = op.g;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= g.N) return;
+    int k = 0;
+    while (k < 3 && t >= g.off[k + 1]) ++k;
+    const int64_t li = t - g.off[k];
+    int p[3];
+    Plan<T, Op::NT> P;
+    if (k == 3) {
+        cell_pos<2>(g, li, p);
+        op.plan_p(p, P);
+    } else {
+        face_pos<2>(g, k, li, p);
+        op.plan_u(k, p, P);
+    }
+#pragma unroll
+    for (int j = 0; j < Op::NT; ++j) {
+        ix[j * g.N + t] = P.ix[j];
+        re[j * g.N + t] = P.re[j];
+        im[j * g.N + t] = P.im[j];
+    }
+}
+
 // ---------------------------------------------------- LDS-staged half-sweep (2D)
 // A block relaxes the red cells of a 16 x 8 tile (64 cells, eight lanes each as in
 // k_relax_plan).  For every right-hand side the vectors the tile's rows touch
@@ -1427,6 +1523,8 @@ hipError_t launch_apply(const LevelDesc<T>& L, const T* x, const T* b, T* y, int
     } else if (L.g.dim == 2) {
         if (L.fine)
             EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_apply_plan<2, T, FineOp<2, T>, RB>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, x, b, y, nrhs, stride, rpb));
+        else if (L.sp.rix)
+            EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_apply_plan<2, T, StOp<2, T>, RB, true>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, x, b, y, nrhs, stride, rpb, L.sp.rix, L.sp.rre, L.sp.rim));
         else
             EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_apply_plan<2, T, StOp<2, T>, RB>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, x, b, y, nrhs, stride, rpb));
     } else if (L.g.dim == 3 && L.fine && cell3d_enabled() && 2 * L.g.N * (int64_t)sizeof(T) < (int64_t(1) << 32)) {
@@ -1478,6 +1576,8 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
     } else if (L.g.dim == 2) {
         if (L.fine)
             EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_relax_plan<2, T, FineOp<2, T>, RB>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb));
+        else if (L.sp.ix[colour])
+            EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_relax_plan<2, T, StOp<2, T>, RB, true>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb, L.sp.ix[colour], L.sp.re[colour], L.sp.im[colour], L.sp.lanes));
         else
             EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_relax_plan<2, T, StOp<2, T>, RB>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb));
     } else if (L.fine && cell3d_enabled() && 2 * L.g.N * (int64_t)sizeof(T) < (int64_t(1) << 32)) {
@@ -1496,6 +1596,32 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
     }
     return hipGetLastError();
 }
+
+int64_t stored_plan_lanes(const Geo& g) {
+    const int64_t npair = (int64_t)(g.n[0] / 2) * g.n[1] * g.n[2];
+    return (int64_t)nblk(npair * 8) * 256;
+}
+// Levels served by k_relax_plan on Galerkin stencils (2D, below the LDS size).
+bool stored_plan_wanted(const Geo& g, bool fine) {
+    static const bool on = env_int("EHH_SPLAN", 1) != 0;
+    return on && g.dim == 2 && !fine && !(g.ncell >= 65536 && lds2d_enabled());
+}
+template <typename T>
+hipError_t launch_build_plans(const LevelDesc<T>& L, int colour, int32_t* ix, T* re, T* im, hipStream_t s) {
+    const int64_t lanes = stored_plan_lanes(L.g);
+    hipLaunchKernelGGL((k_build_plans<T>), nblk(lanes), 256, 0, s, StOp<2, T>{L.g, L.s}, colour, ix, re, im, lanes);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_build_row_plans(const LevelDesc<T>& L, int32_t* ix, T* re, T* im, hipStream_t s) {
+    hipLaunchKernelGGL((k_build_row_plans<T>), nblk(L.g.N), 256, 0, s, StOp<2, T>{L.g, L.s}, ix, re, im);
+    return hipGetLastError();
+}
+template hipError_t launch_build_row_plans<float>(const LevelDesc<float>&, int32_t*, float*, float*, hipStream_t);
+template hipError_t launch_build_row_plans<double>(const LevelDesc<double>&, int32_t*, double*, double*,
+                                                   hipStream_t);
+template hipError_t launch_build_plans<float>(const LevelDesc<float>&, int, int32_t*, float*, float*, hipStream_t);
+template hipError_t launch_build_plans<double>(const LevelDesc<double>&, int, int32_t*, double*, double*, hipStream_t);
 
 template <typename T>
 hipError_t launch_restrict(const Geo& gf, const Geo& gc, const T* rf, T* rc, int nrhs, hipStream_t s) {
