@@ -119,16 +119,17 @@ def visits_per_cycle(w):
 def relax_kernel_name(w, level, ncell):
     """The half-sweep kernel the library launches on a level (same routing as
     its launcher): one thread per cell on the finest level, LDS-staged tiles on
-    2D Galerkin levels of at least 256^2 cells, eight lanes per cell with row
-    plans on smaller 2D Galerkin levels, right-hand-side blocks of 4 (FP32) or
-    2 (FP64) on 3D Galerkin levels."""
+    2D Galerkin levels of at least 256^2 cells with more than 8 sources, eight
+    lanes per cell with row plans stored at setup on the other 2D Galerkin
+    levels, right-hand-side blocks of 4 (FP32) or 2 (FP64) on 3D Galerkin
+    levels."""
     t = "float" if w.precond_bits == 32 else "double"
     if w.dim == 2:
         if level == 0:
             return f"k_relax_cell2d<{t}>"
-        if ncell >= 65536:
+        if ncell >= 65536 and len(w.sources()) > 8:
             return f"k_relax_lds2d<{t}, StOp<2, {t}>>"
-        return f"k_relax_plan<2, {t}, StOp<2, {t}>, 1>"
+        return f"k_relax_plan<2, {t}, StOp<2, {t}>, 1, true>"
     if level == 0:
         return f"k_relax_cell3d<{t}>"
     return f"k_relax<3, {t}, StOp<3, {t}>, 4>" if t == "float" else f"k_relax<3, {t}, StOp<3, {t}>, 2>"

@@ -1556,11 +1556,13 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
     const int rpb3 = rhs_per_block((npair * 8 + 63) / 64, nrhs, rb3);
     const dim3 gb3(nblk(npair * 8), (nrhs + rpb3 - 1) / rpb3);
     const T tw = (T)w;
-    // LDS staging pays on the 21-term Galerkin rows of large levels (measured on
-    // 256^2: 133 vs 217 us per half-sweep with 32 sources, 55 vs 62 us with one);
-    // at 128^2 and below the block-wide synchronisation costs more than it saves
-    // (24 vs 13 us with one source), and the 7-term finest rows gain nothing.
-    if (L.g.dim == 2 && !L.fine && L.g.ncell >= 65536 && lds2d_enabled()) {
+    // LDS staging pays on the 21-term Galerkin rows of large levels with many
+    // sources (measured on 256^2 with 32 sources: 123 us, against 178 us with
+    // stored row plans and 217 us with plans built in the kernel); with a few
+    // sources the stored plans win (one FP64 source: 30 us against 53 us), and at
+    // 128^2 and below the block-wide synchronisation costs more than it saves.
+    const bool big_batch = !(L.sp.ix[colour] && nrhs <= 8);
+    if (L.g.dim == 2 && !L.fine && L.g.ncell >= 65536 && lds2d_enabled() && big_batch) {
         const int tiles = ((L.g.n[0] + LT_X - 1) / LT_X) * ((L.g.n[1] + LT_Y - 1) / LT_Y);
         const int rpl = rhs_per_block((int64_t)tiles * 8, nrhs, 1);
         const dim3 gl(tiles, (nrhs + rpl - 1) / rpl);
@@ -1601,10 +1603,11 @@ int64_t stored_plan_lanes(const Geo& g) {
     const int64_t npair = (int64_t)(g.n[0] / 2) * g.n[1] * g.n[2];
     return (int64_t)nblk(npair * 8) * 256;
 }
-// Levels served by k_relax_plan on Galerkin stencils (2D, below the LDS size).
+// Every 2D Galerkin level keeps its row plans (the large ones use them for
+// small batches, see launch_relax).
 bool stored_plan_wanted(const Geo& g, bool fine) {
     static const bool on = env_int("EHH_SPLAN", 1) != 0;
-    return on && g.dim == 2 && !fine && !(g.ncell >= 65536 && lds2d_enabled());
+    return on && g.dim == 2 && !fine;
 }
 template <typename T>
 hipError_t launch_build_plans(const LevelDesc<T>& L, int colour, int32_t* ix, T* re, T* im, hipStream_t s) {
