@@ -293,6 +293,34 @@ def cpu_baseline(w, gpu_iters, budget_s=20.0):
                        f"{gpu_iters} iterations")
 
 
+def poisson_sweep_report():
+    """Preconditioning cycles to 1e-6 for constant mu = rho = 1 and lambda from 0.5
+    to 16 (section 6, Fig. 5), full and economic Vanka, on the grids whose
+    exact coarsest level fits a dense inverse."""
+    import torch
+    from paper_1806_11277_amd import ehh
+    from workloads.configs import poisson_sweep, SWEEP_LAMBDAS, SWEEP_GRIDS
+    out = {"experiment": "Poisson-ratio sweep, constant mu = rho = 1", "lambda": list(SWEEP_LAMBDAS), "grids": []}
+    for nx in (256, 512):
+        row = {"cells": [nx, nx // 2], "omega_over_pi": 3 * nx // 256, "levels": SWEEP_GRIDS[nx][0],
+               "shift": SWEEP_GRIDS[nx][1]}
+        for vanka, key in ((1, "full_vanka"), (0, "economic_vanka")):
+            its = []
+            for lam in SWEEP_LAMBDAS:
+                w = poisson_sweep(nx, lam, vanka)
+                S = ehh.solver_for_workload(w)
+                b = rhs_tensor(S, w)
+                x = torch.zeros_like(b)
+                st, stats = S.solve(b, x, tol=1e-6, maxit=600)
+                torch.cuda.synchronize()
+                S.close()
+                its.append(stats[0]["iters"] if st == 0 else None)
+                print(f"[sweep] {w.name}: {its[-1]}", file=sys.stderr, flush=True)
+            row[key] = its
+        out["grids"].append(row)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -305,6 +333,8 @@ def main():
     ap.add_argument("--batched", default="c3_hetero512_batch32_fp32",
                     help="batched companion workload reported in the same line ('' to skip)")
     ap.add_argument("--batched-steps", type=int, default=2)
+    ap.add_argument("--poisson-sweep", action="store_true",
+                    help="print the Poisson-ratio sweep (constant media, lambda 0.5..16) as one JSON line and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for traffic counters)")
     a = ap.parse_args()
@@ -314,6 +344,9 @@ def main():
         sys.exit(2)
     import torch
     from workloads import get_config
+    if a.poisson_sweep:
+        print(json.dumps(poisson_sweep_report()), flush=True)
+        return
     if a.calibrate_copy:
         src = torch.ones(256 * 2 ** 20 // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -535,7 +535,7 @@ int32_t build_hierarchy(ehh_ctx* c, Sub& S, const double* lam, const double* mu,
     }
     const Level& Lc = S.lev[L - 1];
     const int64_t nc = Lc.g.N;
-    if ((double)nc * nc * 16.0 > 8.0e9) return fail(EHH_ERR_UNSUPPORTED, "coarsest grid too large for a dense inverse");
+    if ((double)nc * nc * 16.0 > 2.4e10) return fail(EHH_ERR_UNSUPPORTED, "coarsest grid too large for a dense inverse (24 GB)");
     CHK(c->alloc((void**)&S.inv, sizeof(double) * 2 * nc * nc));
     HIPCHK(launch_dense_assemble(Lc.g, L == 1 ? st0 : Lc.coef64, S.inv, s));
     int* piv = nullptr;

@@ -231,5 +231,33 @@ _add(Workload(
     true_media_fn=lambda: M.fwi_true_media((64, 64), corr_vp=5.0, corr_nu=16.0)))
 
 
+def _constant_media(n, lam: float):
+    shape = tuple(reversed(n))
+    one = np.ones(shape)
+    return dict(lam=lam * one, mu=one.copy(), rho=one.copy(), vp=np.sqrt(lam + 2.0) * one, vs=one.copy())
+
+
+# Poisson-ratio sweep (section 6, first experiment): constant mu = rho = 1, lambda
+# from 0.5 to 16 (Poisson ratio 0.17 to 0.47) on 256x128, 512x256 and 1024x512
+# cells of a 16 x 8 box (h = 1/16, 1/32, 1/64) at w = 3 pi, 6 pi, 12 pi (10.7 cells
+# per shear wavelength), 20-cell layer, W(1,1) cycles with red-black Vanka
+# damped 0.75 / 0.5 / 0.25 and the shifts of section 6 (0.3 for three levels,
+# 0.4 for four and five), one x-force in the middle of the top, 5 cells deep.
+SWEEP_LAMBDAS = (0.5, 1.0, 2.0, 4.0, 8.0, 16.0)
+SWEEP_GRIDS = {256: (3, 0.3), 512: (3, 0.3), 1024: (4, 0.4)}   # n_x: (levels, shift)
+
+
+def poisson_sweep(nx: int, lam: float, vanka: int = 1) -> Workload:
+    levels, shift = SWEEP_GRIDS[nx]
+    n = (nx, nx // 2)
+    damping = (0.75, 0.5, 0.25, 0.25)[:levels - 1]
+    return Workload(
+        name=f"e3_const{nx}_lam{lam:g}_{'full' if vanka else 'econ'}",
+        description=f"constant mu = rho = 1, lambda = {lam:g}, {nx}x{nx // 2} cells, h = {16 / nx:g}",
+        dim=2, n=n, h=16.0 / nx, media_fn=lambda: _constant_media(n, lam), ppw=32.0 / 3.0,
+        abl_cells=(20, 20), shift=shift, levels=levels, cycle=2, damping=damping, vanka=vanka,
+        precond_bits=64, tol=1e-6, maxit=600, sources_fn=_src_top_single)
+
+
 def get_config(name: str) -> Workload:
     return CONFIGS[name]
