@@ -129,7 +129,7 @@ def relax_kernel_name(w, level, ncell):
             return f"k_relax_cell2d<{t}>"
         if ncell >= 65536 and len(w.sources()) > 8:
             return f"k_relax_lds2d<{t}, StOp<2, {t}>>"
-        return f"k_relax_plan<2, {t}, StOp<2, {t}>, 1, true>"
+        return f"k_relax_st2d<{t}, {'true' if t == 'float' else 'false'}>"
     if level == 0:
         return f"k_relax_cell3d<{t}>"
     return f"k_relax<3, {t}, StOp<3, {t}>, 4>" if t == "float" else f"k_relax<3, {t}, StOp<3, {t}>, 2>"

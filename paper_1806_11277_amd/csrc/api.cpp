@@ -85,13 +85,11 @@ struct Level {
     void* b = nullptr;          // right-hand side of this level (levels >= 1)
     void* e = nullptr;          // correction of this level (levels >= 1)
     void* t = nullptr;          // half-sweep ping-pong / residual
-    // row plans of the two colours' half-sweeps (cycle precision), where stored
-    int32_t* sp_ix[2] = {nullptr, nullptr};
+    // stored row coefficients of the two colours' half-sweeps (cycle precision)
     void* sp_re[2] = {nullptr, nullptr};
     void* sp_im[2] = {nullptr, nullptr};
     int64_t sp_lanes = 0;
-    int32_t* rp_ix = nullptr;   // row plans of the residual, where stored
-    void* rp_re = nullptr;
+    void* rp_re = nullptr;      // stored rows of the residual
     void* rp_im = nullptr;
 };
 
@@ -101,6 +99,7 @@ struct Sub {
     int colour = 0;
     std::vector<Level> lev;
     double* inv = nullptr;      // dense inverse of the coarsest operator
+    double* sym = nullptr;      // its lower 64 x 64 tiles, packed (few right-hand sides)
     void* r0 = nullptr;         // local level-0 right-hand side / correction (DD or FP32)
     void* e0 = nullptr;
 };
@@ -193,13 +192,11 @@ template <typename T> LevelDesc<T> level_desc(const ehh_ctx* c, const Level& L, 
         const bool mine = (sizeof(T) == 4) == (c->bits() == 32);   // plans are kept in the cycle precision
         if (mine && L.sp_lanes)
             for (int col = 0; col < 2; ++col) {
-                d.sp.ix[col] = L.sp_ix[col];
                 d.sp.re[col] = (const T*)L.sp_re[col];
                 d.sp.im[col] = (const T*)L.sp_im[col];
             }
         d.sp.lanes = L.sp_lanes;
-        if (mine && L.rp_ix) {
-            d.sp.rix = L.rp_ix;
+        if (mine && L.rp_re) {
             d.sp.rre = (const T*)L.rp_re;
             d.sp.rim = (const T*)L.rp_im;
         }
@@ -299,7 +296,7 @@ int32_t cycle(ehh_ctx* c, Sub& S, int l, const T* b, T* e, bool zero_init, int n
     Level& L = S.lev[l];
     const int nl = (int)S.lev.size();
     if (l == nl - 1) {
-        HIPCHK(launch_coarse_apply<T>(S.inv, L.g.N, b, e, nrhs, c->coarse_ws, s));
+        HIPCHK(launch_coarse_apply<T>(S.inv, S.sym, L.g.N, b, e, nrhs, c->coarse_ws, s));
         return EHH_OK;
     }
     const LevelDesc<T> D = level_desc<T>(c, L, c->prob.shift);
@@ -566,6 +563,8 @@ int32_t build_hierarchy(ehh_ctx* c, Sub& S, const double* lam, const double* mu,
         S.inv = inv;
         lg.mark("column permutation");
     }
+    CHK(c->alloc((void**)&S.sym, sizeof(double) * 2 * 64 * 64 * sym_tiles(nc)));
+    HIPCHK(launch_pack_sym(S.inv, nc, S.sym, s));
     c->release(piv);
     c->release(st0);
     if (c->bits() == 32) {
@@ -583,28 +582,26 @@ int32_t build_hierarchy(ehh_ctx* c, Sub& S, const double* lam, const double* mu,
         if (!stored_plan_wanted(Q.g, Q.fine)) continue;
         const int64_t lanes = stored_plan_lanes(Q.g);
         const size_t es = c->bits() == 32 ? sizeof(float) : sizeof(double);
-        constexpr int NT = St<2>::NF + St<2>::NUP;
+        constexpr int NT = St<2>::NF + St<2>::NUP, NF = St<2>::NF;
         for (int col = 0; col < 2; ++col) {
-            CHK(c->alloc((void**)&Q.sp_ix[col], sizeof(int32_t) * NT * lanes));
             CHK(c->alloc(&Q.sp_re[col], es * NT * lanes));
-            CHK(c->alloc(&Q.sp_im[col], es * NT * lanes));
+            CHK(c->alloc(&Q.sp_im[col], es * NF * lanes));
             if (c->bits() == 32)
-                HIPCHK(launch_build_plans<float>(level_desc<float>(c, Q, c->prob.shift), col, Q.sp_ix[col],
+                HIPCHK(launch_build_plans<float>(level_desc<float>(c, Q, c->prob.shift), col,
                                                  (float*)Q.sp_re[col], (float*)Q.sp_im[col], s));
             else
-                HIPCHK(launch_build_plans<double>(level_desc<double>(c, Q, c->prob.shift), col, Q.sp_ix[col],
+                HIPCHK(launch_build_plans<double>(level_desc<double>(c, Q, c->prob.shift), col,
                                                   (double*)Q.sp_re[col], (double*)Q.sp_im[col], s));
         }
         Q.sp_lanes = lanes;
         const int64_t N = Q.g.N;
-        CHK(c->alloc((void**)&Q.rp_ix, sizeof(int32_t) * NT * N));
         CHK(c->alloc(&Q.rp_re, es * NT * N));
-        CHK(c->alloc(&Q.rp_im, es * NT * N));
+        CHK(c->alloc(&Q.rp_im, es * NF * N));
         if (c->bits() == 32)
-            HIPCHK(launch_build_row_plans<float>(level_desc<float>(c, Q, c->prob.shift), Q.rp_ix, (float*)Q.rp_re,
+            HIPCHK(launch_build_row_plans<float>(level_desc<float>(c, Q, c->prob.shift), (float*)Q.rp_re,
                                                  (float*)Q.rp_im, s));
         else
-            HIPCHK(launch_build_row_plans<double>(level_desc<double>(c, Q, c->prob.shift), Q.rp_ix,
+            HIPCHK(launch_build_row_plans<double>(level_desc<double>(c, Q, c->prob.shift),
                                                   (double*)Q.rp_re, (double*)Q.rp_im, s));
     }
     return EHH_OK;
@@ -1176,10 +1173,10 @@ int32_t ehh_coarse_solve(ehh_handle_t h, int32_t sub, const void* r, void* e, in
     if (!r || !e || r == e || nrhs < 1) return fail(EHH_ERR_INVALID, "bad vectors or nrhs");
     CHK(ensure_ws(h, nrhs));   // sizes the coarse-apply workspace for nrhs
     if (h->bits() == 32)
-        HIPCHK(launch_coarse_apply<float>(S->inv, L->g.N, (const float*)r, (float*)e, nrhs, h->coarse_ws,
+        HIPCHK(launch_coarse_apply<float>(S->inv, S->sym, L->g.N, (const float*)r, (float*)e, nrhs, h->coarse_ws,
                                           as_stream(stream)));
     else
-        HIPCHK(launch_coarse_apply<double>(S->inv, L->g.N, (const double*)r, (double*)e, nrhs, h->coarse_ws,
+        HIPCHK(launch_coarse_apply<double>(S->inv, S->sym, L->g.N, (const double*)r, (double*)e, nrhs, h->coarse_ws,
                                            as_stream(stream)));
     return EHH_OK;
 }

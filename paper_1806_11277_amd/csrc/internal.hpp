@@ -9,16 +9,15 @@ namespace ehh {
 
 // Operator of one multigrid level in precision T: matrix-free on level 0 of a
 // (sub)domain, Galerkin stencils on the coarser levels.
-// Row plans of the 2D half-sweep stored in its lane order (one set per colour):
-// term j of lane i at [j * lanes + i]; null where a level builds its plans in the
-// kernel.
+// Row coefficients of the 2D half-sweep stored in its lane order (one set per
+// colour): term j of lane i at [j * lanes + i], real parts of all terms,
+// imaginary parts of the u-u terms; null where a level builds its rows in the
+// kernel.  Columns are computed from the row's position.
 template <typename T> struct StoredPlan {
-    const int32_t* ix[2] = {nullptr, nullptr};
     const T* re[2] = {nullptr, nullptr};
     const T* im[2] = {nullptr, nullptr};
     int64_t lanes = 0;
-    // row plans of y = A x in row order (term j of row t at [j * N + t])
-    const int32_t* rix = nullptr;
+    // rows of y = A x in row order (term j of row t at [j * N + t])
     const T* rre = nullptr;
     const T* rim = nullptr;
 };
@@ -41,9 +40,9 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
 int64_t stored_plan_lanes(const Geo& g);
 bool stored_plan_wanted(const Geo& g, bool fine);
 template <typename T>
-hipError_t launch_build_plans(const LevelDesc<T>& L, int colour, int32_t* ix, T* re, T* im, hipStream_t s);
+hipError_t launch_build_plans(const LevelDesc<T>& L, int colour, T* re, T* im, hipStream_t s);
 template <typename T>
-hipError_t launch_build_row_plans(const LevelDesc<T>& L, int32_t* ix, T* re, T* im, hipStream_t s);
+hipError_t launch_build_row_plans(const LevelDesc<T>& L, T* re, T* im, hipStream_t s);
 template <typename T>
 hipError_t launch_restrict(const Geo& gf, const Geo& gc, const T* rf, T* rc, int nrhs, hipStream_t s);
 template <typename T>
@@ -86,7 +85,11 @@ hipError_t launch_dense_invert(double* dense, int64_t n, int* piv, int* flag, hi
 hipError_t launch_permute_columns(const double* X, double* out, int64_t n, const int* qinv, hipStream_t s);
 // e = inv r for a batch of right-hand sides (FP64 accumulation).
 template <typename T>
-hipError_t launch_coarse_apply(const double* inv, int64_t n, const T* r, T* e, int nrhs, double* ws, hipStream_t s);
+hipError_t launch_coarse_apply(const double* inv, const double* sym, int64_t n, const T* r, T* e, int nrhs,
+                               double* ws, hipStream_t s);
+// Packed lower tiles of the (symmetric) inverse, used by launch_coarse_apply.
+int64_t sym_tiles(int64_t n);
+hipError_t launch_pack_sym(const double* inv, int64_t n, double* sym, hipStream_t s);
 // Column segments of the coarse apply and the FP64 workspace they need (0: none).
 int coarse_ksplit(int64_t n, int nrhs);
 size_t coarse_ws_doubles(int64_t n, int nrhs);

@@ -194,15 +194,56 @@ __global__ __launch_bounds__(256) void k_relax(Op op, int colour, T w, int econ,
     }
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin (linear id mod 8), and each XCD
+// has its own L2.  Renumbering so that every XCD receives one contiguous range
+// of logical blocks keeps the rows above and below a block's cells (stencil
+// neighbours) in the same L2.  Bijective for any block count.
+EHH_DEV inline int64_t xcd_block(int64_t bid, int64_t nb) {
+    constexpr int64_t X = 8;
+    const int64_t q = nb / X, rem = nb % X;
+    const int64_t xcd = bid % X, local = bid / X;
+    return xcd < rem ? xcd * (q + 1) + local : rem * (q + 1) + (xcd - rem) * q + local;
+}
+
+// Raw buffer access: a scalar resource descriptor (base, size in bytes) plus a
+// 32-bit byte offset per lane, so that a kernel keeps one VGPR per address.
+// Reads past the descriptor's size return zero.
+typedef uint32_t ehh_u2 __attribute__((ext_vector_type(2)));
+template <typename T> struct Buf;
+template <> struct Buf<float> {
+    __amdgpu_buffer_rsrc_t r;
+    EHH_DEV Buf(const void* p, uint32_t bytes)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000)) {}
+    EHH_DEV float ld(uint32_t off) const { return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0)); }
+    // per-lane offset plus a wave-uniform one (kept in a scalar register)
+    EHH_DEV float ld(uint32_t off, uint32_t soff) const {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
+    }
+    EHH_DEV void st(uint32_t off, float v) const {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
+    }
+};
+template <> struct Buf<double> {
+    __amdgpu_buffer_rsrc_t r;
+    EHH_DEV Buf(const void* p, uint32_t bytes)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000)) {}
+    EHH_DEV double ld(uint32_t off) const {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    }
+    EHH_DEV double ld(uint32_t off, uint32_t soff) const {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0));
+    }
+    EHH_DEV void st(uint32_t off, double v) const {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(ehh_u2, v), r, off, 0, 0);
+    }
+};
+
 // ------------------------------------------------ plan-based apply and half-sweep
 // The row plan (indices and coefficients) is built once per row and reused for
 // every right-hand side, so a batch streams only the vectors.
-template <int D, typename T, class Op, int RB, bool STORED = false>
+template <int D, typename T, class Op, int RB>
 __global__ __launch_bounds__(256) void k_apply_plan(Op op, const T* __restrict__ x, const T* __restrict__ b,
-                                                    T* __restrict__ y, int nrhs, int64_t stride, int rpb,
-                                                    const int32_t* __restrict__ spix = nullptr,
-                                                    const T* __restrict__ spre = nullptr,
-                                                    const T* __restrict__ spim = nullptr) {
+                                                    T* __restrict__ y, int nrhs, int64_t stride, int rpb) {
     // right-hand sides [blockIdx.y * rpb, ...) of this grid row
     {
         const int rb0 = blockIdx.y * rpb;
@@ -219,14 +260,7 @@ __global__ __launch_bounds__(256) void k_apply_plan(Op op, const T* __restrict__
     const int64_t li = t - g.off[k];
     int p[3];
     Plan<T, Op::NT> P;
-    if (STORED) {   // row plan built at setup, term j of row t at [j * N + t]
-#pragma unroll
-        for (int j = 0; j < Op::NT; ++j) {
-            P.ix[j] = spix[j * g.N + t];
-            P.re[j] = spre[j * g.N + t];
-            P.im[j] = spim[j * g.N + t];
-        }
-    } else if (k == 3) {
+    if (k == 3) {
         cell_pos<D>(g, li, p);
         op.plan_p(p, P);
     } else {
@@ -252,16 +286,87 @@ __global__ __launch_bounds__(256) void k_apply_plan(Op op, const T* __restrict__
     }
 }
 
+// Vanka block of one cell spread over the eight lanes of its rows (lane base + 8 j
+// holds row j: the low and high face of each component, then the pressure).
+// factor() gathers the block entries from those lanes (diagonal dre + i dim, the
+// coupling of a component's two faces cre + i cim given by the low row, zero in
+// the economic variant, and the real coupling gg of each face to the cell
+// pressure) and factorises the block in the lane of row 0: a 2 x 2 inverse per
+// component and the scalar Schur complement of the pressure.  solve() turns the
+// rows' residuals into this lane's correction.
+template <int D, typename T> struct VankaBlock {
+    static constexpr int R = 2 * D + 1;
+    cx<T> i00[D], i01[D], i11[D], zlo[D], zhi[D];
+    T glo[D], ghi[D];
+    cx<T> iS;
+
+    EHH_DEV void factor(T dre, T dim, T cre, T cim, T gg, int base, int row) {
+        const T pd = __shfl(dre, base + 8 * (2 * D), 64);
+        cx<T> S = mk<T>(pd, T(0));
+#pragma unroll
+        for (int kk = 0; kk < D; ++kk) {
+            const cx<T> all = mk<T>(__shfl(dre, base + 8 * (2 * kk), 64), __shfl(dim, base + 8 * (2 * kk), 64));
+            const cx<T> ahh = mk<T>(__shfl(dre, base + 8 * (2 * kk + 1), 64), __shfl(dim, base + 8 * (2 * kk + 1), 64));
+            const cx<T> alh = mk<T>(__shfl(cre, base + 8 * (2 * kk), 64), __shfl(cim, base + 8 * (2 * kk), 64));
+            glo[kk] = __shfl(gg, base + 8 * (2 * kk), 64);
+            ghi[kk] = __shfl(gg, base + 8 * (2 * kk + 1), 64);
+            if (row == 0) {
+                const cx<T> idet = cinv(all * ahh - alh * alh);
+                i00[kk] = ahh * idet;
+                i11[kk] = all * idet;
+                i01[kk] = mk<T>(T(0), T(0)) - alh * idet;
+                zlo[kk] = glo[kk] * i00[kk] + ghi[kk] * i01[kk];
+                zhi[kk] = glo[kk] * i01[kk] + ghi[kk] * i11[kk];
+                S = S - (glo[kk] * zlo[kk] + ghi[kk] * zhi[kk]);
+            }
+        }
+        iS = row == 0 ? cinv(S) : mk<T>(T(0), T(0));
+    }
+
+    EHH_DEV cx<T> solve(cx<T> res, int base, int row) const {
+        cx<T> rr[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            rr[j].re = __shfl(res.re, base + 8 * j, 64);
+            rr[j].im = __shfl(res.im, base + 8 * j, 64);
+        }
+        cx<T> d[R];
+        if (row == 0) {
+            cx<T> acc = rr[2 * D];
+            cx<T> ylo[D], yhi[D];
+#pragma unroll
+            for (int kk = 0; kk < D; ++kk) {
+                ylo[kk] = i00[kk] * rr[2 * kk] + i01[kk] * rr[2 * kk + 1];
+                yhi[kk] = i01[kk] * rr[2 * kk] + i11[kk] * rr[2 * kk + 1];
+                acc = acc - (glo[kk] * ylo[kk] + ghi[kk] * yhi[kk]);
+            }
+            const cx<T> dp = acc * iS;
+#pragma unroll
+            for (int kk = 0; kk < D; ++kk) {
+                d[2 * kk] = ylo[kk] - zlo[kk] * dp;
+                d[2 * kk + 1] = yhi[kk] - zhi[kk] * dp;
+            }
+            d[2 * D] = dp;
+        }
+        cx<T> mine = mk<T>(T(0), T(0));
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const T vr = __shfl(d[j].re, base, 64);
+            const T vi = __shfl(d[j].im, base, 64);
+            if (row == j) mine = mk<T>(vr, vi);
+        }
+        return mine;
+    }
+};
+
 // Eight lanes per relaxed cell as in k_relax, each lane holding the plan of its
-// block row; the block itself (diagonals, the coupling of the two faces of a
-// component, the couplings to the cell pressure) is read off the lanes' plans.
-template <int D, typename T, class Op, int RB, bool STORED = false>
+// block row, built in the kernel; the block itself (diagonals, the coupling of
+// the two faces of a component, the couplings to the cell pressure) is read off
+// the lanes' plans.
+template <int D, typename T, class Op, int RB>
 __global__ __launch_bounds__(256) void k_relax_plan(Op op, int colour, T w, int econ,
                                                     const T* __restrict__ b, const T* __restrict__ ein,
-                                                    T* __restrict__ eout, int nrhs, int64_t stride, int rpb,
-                                                    const int32_t* __restrict__ spix = nullptr,
-                                                    const T* __restrict__ spre = nullptr,
-                                                    const T* __restrict__ spim = nullptr, int64_t splanes = 0) {
+                                                    T* __restrict__ eout, int nrhs, int64_t stride, int rpb) {
     {
         const int rb0 = blockIdx.y * rpb;
         b += rb0 * stride;
@@ -298,152 +403,332 @@ __global__ __launch_bounds__(256) void k_relax_plan(Op op, int colour, T w, int 
     }
     Plan<T, Op::NT> P;
     int64_t idx = 0;
-    if (ok) idx = k == 3 ? g.off[3] + cell_idx<D>(g, p) : g.off[k] + face_idx<D>(g, k, p);
-    if (STORED) {   // the plan built at setup for this lane (coalesced over the lanes)
-        const int64_t gl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-#pragma unroll
-        for (int j = 0; j < Op::NT; ++j) {
-            P.ix[j] = spix[j * splanes + gl];
-            P.re[j] = spre[j * splanes + gl];
-            P.im[j] = spim[j * splanes + gl];
-        }
-    } else if (ok) {
-        if (k == 3)
+    if (ok) {
+        if (k == 3) {
             op.plan_p(p, P);
-        else
+            idx = g.off[3] + cell_idx<D>(g, p);
+        } else {
             op.plan_u(k, p, P);
+            idx = g.off[k] + face_idx<D>(g, k, p);
+        }
     } else {
 #pragma unroll
         for (int j = 0; j < Op::NT; ++j) P.set(j, 0, T(0), T(0));
     }
     const bool carry = live && row == R;
     const int64_t ipb = g.off[3] + cell_idx<D>(g, cb);
-    // this row's block entries
-    // the diagonal sits at T_SELF in a u row and at term 0 in the pressure row
-    const T dre = ok ? (k == 3 ? P.re[0] : P.re[Op::T_SELF]) : T(1);
-    const T dim = ok ? (k == 3 ? P.im[0] : P.im[Op::T_SELF]) : T(0);
+    // this row's block entries: the diagonal sits at T_SELF in a u row and at
+    // term 0 in the pressure row
     const bool lowrow = row < 2 * D && (row & 1) == 0;
-    const T cre = (ok && lowrow && !econ) ? P.re[Op::T_NHI] : T(0);
-    const T cim = (ok && lowrow && !econ) ? P.im[Op::T_NHI] : T(0);
-    const T gg = (ok && row < 2 * D) ? (lowrow ? P.re[Op::T_PHI] : P.re[Op::T_PLO]) : T(0);
-    cx<T> i00[D], i01[D], i11[D], zlo[D], zhi[D];
-    T glo[D], ghi[D];
-    cx<T> S;
-    {
-        const T pd = __shfl(dre, base + 8 * (2 * D), 64);
-        S = mk<T>(pd, T(0));
-#pragma unroll
-        for (int kk = 0; kk < D; ++kk) {
-            const cx<T> all = mk<T>(__shfl(dre, base + 8 * (2 * kk), 64), __shfl(dim, base + 8 * (2 * kk), 64));
-            const cx<T> ahh = mk<T>(__shfl(dre, base + 8 * (2 * kk + 1), 64), __shfl(dim, base + 8 * (2 * kk + 1), 64));
-            const cx<T> alh = mk<T>(__shfl(cre, base + 8 * (2 * kk), 64), __shfl(cim, base + 8 * (2 * kk), 64));
-            glo[kk] = __shfl(gg, base + 8 * (2 * kk), 64);
-            ghi[kk] = __shfl(gg, base + 8 * (2 * kk + 1), 64);
-            if (row == 0) {
-                const cx<T> idet = cinv(all * ahh - alh * alh);
-                i00[kk] = ahh * idet;
-                i11[kk] = all * idet;
-                i01[kk] = mk<T>(T(0), T(0)) - alh * idet;
-                zlo[kk] = glo[kk] * i00[kk] + ghi[kk] * i01[kk];
-                zhi[kk] = glo[kk] * i01[kk] + ghi[kk] * i11[kk];
-                S = S - (glo[kk] * zlo[kk] + ghi[kk] * zhi[kk]);
-            }
-        }
-    }
-    const cx<T> iS = row == 0 ? cinv(S) : mk<T>(T(0), T(0));
+    VankaBlock<D, T> V;
+    V.factor(ok ? (k == 3 ? P.re[0] : P.re[Op::T_SELF]) : T(1), ok ? (k == 3 ? P.im[0] : P.im[Op::T_SELF]) : T(0),
+             (ok && lowrow && !econ) ? P.re[Op::T_NHI] : T(0), (ok && lowrow && !econ) ? P.im[Op::T_NHI] : T(0),
+             (ok && row < 2 * D) ? (lowrow ? P.re[Op::T_PHI] : P.re[Op::T_PLO]) : T(0), base, row);
 
     for (int r0 = 0; r0 < nrhs; r0 += RB) {
-    // residual rows of a block of right-hand sides (independent load streams)
-    cx<T> resb[RB];
+        // residual rows of a block of right-hand sides (independent load streams)
+        cx<T> resb[RB];
 #pragma unroll
-    for (int q = 0; q < RB; ++q) {
-        resb[q] = mk<T>(T(0), T(0));
-        const int r = r0 + q;
-        if (ok && r < nrhs) {
-            resb[q] = CVec<T>{b + r * stride, g.N}.ld(idx);
-            if (ein) resb[q] = resb[q] - P.dot(CVec<T>{ein + r * stride, g.N});
+        for (int q = 0; q < RB; ++q) {
+            resb[q] = mk<T>(T(0), T(0));
+            const int r = r0 + q;
+            if (ok && r < nrhs) {
+                resb[q] = CVec<T>{b + r * stride, g.N}.ld(idx);
+                if (ein) resb[q] = resb[q] - P.dot(CVec<T>{ein + r * stride, g.N});
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const int r = r0 + q;
+            if (r >= nrhs) break;
+            const CVec<T> ev{ein ? ein + r * stride : nullptr, g.N};
+            const Vec<T> ov{eout + r * stride, g.N};
+            const cx<T> mine = V.solve(resb[q], base, row);
+            if (ok) ov.st(idx, (ein ? ev.ld(idx) : mk<T>(T(0), T(0))) + w * mine);
+            if (carry) ov.st(ipb, ein ? ev.ld(ipb) : mk<T>(T(0), T(0)));
         }
     }
+}
+
+// ------------------------------------ stored Galerkin rows with computed columns (2D)
+// The 2D Galerkin levels keep their rows' coefficients, built once at setup, in
+// the order the kernels read them: term j of lane (or row) i at [j * lanes + i],
+// imaginary parts for the NF u-u terms only (the u-p and p-p couplings are
+// real).  The column of a term is the row's own position plus the term's fixed
+// stencil offset; a term that leaves the grid holds a zero coefficient and reads
+// a clamped column.  So the vector loads depend on no loaded index and are in
+// flight together with the coefficient loads.
+struct Cols2 {
+    int self;        // global index of the row
+    int sn, st;      // u row: strides of its face grid along the normal / tangential axis
+    int pc, cn, ct;  // u row: global index of the cell above the face, cell strides
+    int f0, f1;      // p row: global index of the cell's low face in u_0 / u_1
+    int nx, last;    // cells along x, N - 1
+    bool isp;
+};
+
+EHH_DEV inline Cols2 cols2(const Geo& g, int k, const int* p) {
+    Cols2 c;
+    const int nx = g.n[0];
+    c.nx = nx;
+    c.last = (int)g.N - 1;
+    c.isp = k == 3;
+    const int ci = (int)g.off[3] + p[1] * nx + p[0];   // cell at p (for a face: the cell above it)
+    c.pc = ci;
+    c.f0 = (int)g.off[0] + p[1] * (nx - 1) + p[0] - 1;
+    c.f1 = (int)g.off[1] + (p[1] - 1) * nx + p[0];
+    if (k == 0) {
+        c.self = c.f0;
+        c.sn = 1;
+        c.st = nx - 1;
+        c.cn = 1;
+        c.ct = nx;
+    } else if (k == 1) {
+        c.self = c.f1;
+        c.sn = nx;
+        c.st = 1;
+        c.cn = nx;
+        c.ct = 1;
+    } else {
+        c.self = ci;
+        c.sn = c.st = c.cn = c.ct = 0;
+    }
+    return c;
+}
+
+// Column of term j (a compile-time constant after unrolling) of the row: u rows
+// follow the order of StOp::plan_u (full u-u offsets, then the u-p entries), the
+// pressure row that of StOp::plan_p (itself, then the u-p entries of u_0's and
+// u_1's faces).
+EHH_DEV inline int col2(const Cols2& c, int j) {
+    constexpr int NF = St<2>::NF, NUP = St<2>::NUP;
+    int iu;
+    if (j < NF) {
+        const int dn = j % 3 - 1, d1 = (j / 3) % 5 - 2;
+        iu = c.self + dn * c.sn + d1 * c.st;
+    } else {
+        const int qq = j - NF, side = qq & 1, e1 = (qq >> 1) % 3 - 1;
+        iu = c.pc + (side - 1) * c.cn + e1 * c.ct;
+    }
+    int ip = c.self;
+    if (j >= 1 && j <= 2 * NUP) {
+        const int kk = (j - 1) / NUP, qq = (j - 1) % NUP, side = qq & 1, e1 = (qq >> 1) % 3 - 1;
+        ip = kk == 0 ? c.f0 + (1 - side) - e1 * (c.nx - 1) : c.f1 + (1 - side) * c.nx - e1;
+    }
+    const int i = c.isp ? ip : iu;
+    return i < 0 ? 0 : (i > c.last ? c.last : i);
+}
+
+// Half-sweep over stored rows: the lane layout of k_relax_plan (eight lanes per
+// cell, lane 8 j + cell holds row j), blocks renumbered per XCD.  KEEP holds a
+// lane's coefficients in registers for the whole batch (FP32); otherwise (FP64)
+// they are re-read per right-hand side in three parts of the row (measured on
+// MI355X: three parts of 7 terms, 3 wavefronts per SIMD, beat two of 11 at 2 per
+// SIMD on a 256^2 level, and one batch of all 21 terms at 1 per SIMD even on the
+// 128^2 and 64^2 levels, where no SIMD holds more than one wavefront), and the
+// block is re-factorised per right-hand side.
+template <typename T, bool KEEP>
+__global__ __launch_bounds__(256) void k_relax_st2d(Geo g, int colour, T w, int econ, const T* __restrict__ b,
+                                                    const T* __restrict__ ein, T* __restrict__ eout, int nrhs,
+                                                    int64_t stride, int rpb, const T* __restrict__ cre,
+                                                    const T* __restrict__ cim, int64_t lanes) {
+    constexpr int D = 2, R = 2 * D + 1, NF = St<2>::NF, NT = NF + St<2>::NUP, H = 7;
+    constexpr int T_SELF = St<2>::CF, T_NHI = St<2>::CF + 1, T_PLO = NF + 2, T_PHI = NF + 3;
+    {
+        const int rb0 = blockIdx.y * rpb;
+        b += rb0 * stride;
+        if (ein) ein += rb0 * stride;
+        eout += rb0 * stride;
+        nrhs = nrhs - rb0 < rpb ? nrhs - rb0 : rpb;
+    }
+    const int hp = g.n[0] >> 1;
+    const int npair = hp * g.n[1];
+    const int lane = threadIdx.x & 63;
+    const int row = lane >> 3;
+    const int cig = lane & 7;
+    const int64_t gl = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int t = (int)(gl >> 6) * 8 + cig;
+    const int base = cig;
+    const bool live = t < npair;
+    const int tt = live ? t : 0;
+    const int px = tt % hp;
+    const int yy = tt / hp;
+    const int par = (colour + yy) & 1;
+    const int k = row < 2 * D ? (row >> 1) : 3;
+    int p[3] = {2 * px + par, yy, 0};
+    bool ok = live && row < R;
+    if (k < 3) {
+        p[k] += row & 1;
+        ok = ok && p[k] >= 1 && p[k] <= g.n[k] - 1;
+    }
+    const Cols2 cc = cols2(g, k, p);
+    const int idx = cc.self;
+    const bool carry = live && row == R;
+    const int ipb = (int)g.off[3] + yy * g.n[0] + 2 * px + 1 - par;
+    // coefficient loads: lane offset in a VGPR, term offset in a scalar register;
+    // absent rows and the unused terms of the pressure row are stored as zeros
+    const Buf<T> cR(cre, (uint32_t)(NT * lanes * sizeof(T))), cI(cim, (uint32_t)(NF * lanes * sizeof(T)));
+    const uint32_t lo = (uint32_t)gl * (uint32_t)sizeof(T), ls = (uint32_t)lanes * (uint32_t)sizeof(T);
+    const uint32_t vb = 2 * (uint32_t)g.N * (uint32_t)sizeof(T), nb = (uint32_t)g.N * (uint32_t)sizeof(T);
+    // this row's block entries: the diagonal sits at T_SELF in a u row and at
+    // term 0 in the pressure row
+    const bool lowrow = row < 2 * D && (row & 1) == 0;
+    T dre = T(1), dim = T(0), ore = T(0), oim = T(0), gg = T(0);
+    if (ok) {
+        const uint32_t js = (uint32_t)(k == 3 ? 0 : T_SELF) * ls;
+        dre = cR.ld(lo + js);
+        if (k < 3) {
+            dim = cI.ld(lo + js);
+            gg = cR.ld(lo + (uint32_t)(lowrow ? T_PHI : T_PLO) * ls);
+            if (lowrow && !econ) {
+                ore = cR.ld(lo + (uint32_t)T_NHI * ls);
+                oim = cI.ld(lo + (uint32_t)T_NHI * ls);
+            }
+        }
+    }
+    T are[KEEP ? NT : 1], aim[KEEP ? NF : 1];
+    if (KEEP) {
 #pragma unroll
-    for (int q = 0; q < RB; ++q) {
-        const int r = r0 + q;
-        if (r >= nrhs) break;
-        const CVec<T> ev{ein ? ein + r * stride : nullptr, g.N};
+        for (int j = 0; j < (KEEP ? NT : 0); ++j) are[j] = row < R ? cR.ld(lo, j * ls) : T(0);
+#pragma unroll
+        for (int j = 0; j < (KEEP ? NF : 0); ++j) aim[j] = row < R ? cI.ld(lo, j * ls) : T(0);
+    }
+
+    VankaBlock<D, T> V;
+    bool factored = false;
+    for (int r = 0; r < nrhs; ++r) {
+        const CVec<T> bv{b + r * stride, g.N};
+        cx<T> res = mk<T>(T(0), T(0));
+        cx<T> eown = mk<T>(T(0), T(0));
+        if (ok) {
+            res = bv.ld(idx);
+            if (ein) {
+                // every term's load first (columns are clamped into the vector),
+                // then the sums
+                const Buf<T> ev(ein + r * stride, vb);
+                T ar = T(0), ai = T(0);
+                const uint32_t o = (uint32_t)idx * (uint32_t)sizeof(T);
+                eown = mk<T>(ev.ld(o, 0), ev.ld(o, nb));
+                if (KEEP) {
+                    T vr[NT], vi[NT];
+#pragma unroll
+                    for (int j = 0; j < NT; ++j) {
+                        const uint32_t oj = (uint32_t)col2(cc, j) * (uint32_t)sizeof(T);
+                        vr[j] = ev.ld(oj, 0);
+                        vi[j] = ev.ld(oj, nb);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int j = 0; j < NT; ++j) {
+                        const T ci = j < NF ? aim[KEEP ? j : 0] : T(0);
+                        ar += are[KEEP ? j : 0] * vr[j] - ci * vi[j];
+                        ai += are[KEEP ? j : 0] * vi[j] + ci * vr[j];
+                    }
+                } else {
+                    // The columns are recomputed per right-hand side, and the
+                    // second half's addresses are made to depend on the first
+                    // half's sums (empty asm statements), so that the halves'
+                    // loads are not merged into one batch of registers.
+                    Cols2 cl = cc;
+                    uint32_t lh = lo;
+                    asm volatile("" : "+v"(cl.self), "+v"(cl.pc), "+v"(cl.f0), "+v"(cl.f1), "+v"(lh), "+v"(cl.sn),
+                                 "+v"(cl.st), "+v"(cl.cn), "+v"(cl.ct), "+v"(cl.nx));
+#pragma unroll
+                    for (int h = 0; h < NT; h += H) {
+                        if (h > 0)
+                            asm volatile("" : "+v"(cl.self), "+v"(cl.pc), "+v"(cl.f0), "+v"(cl.f1), "+v"(lh)
+                                         : "v"(ar), "v"(ai));
+                        T cr_[H], ci_[H], vr[H], vi[H];
+#pragma unroll
+                        for (int jj = 0; jj < H; ++jj) {
+                            const int j = h + jj;
+                            if (j < NT) {
+                                cr_[jj] = cR.ld(lh, j * ls);
+                                ci_[jj] = j < NF ? cI.ld(lh, j * ls) : T(0);
+                                const uint32_t oj = (uint32_t)col2(cl, j) * (uint32_t)sizeof(T);
+                                vr[jj] = ev.ld(oj, 0);
+                                vi[jj] = ev.ld(oj, nb);
+                            }
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                        for (int jj = 0; jj < H; ++jj) {
+                            if (h + jj < NT) {
+                                ar += cr_[jj] * vr[jj] - ci_[jj] * vi[jj];
+                                ai += cr_[jj] * vi[jj] + ci_[jj] * vr[jj];
+                            }
+                        }
+                    }
+                }
+                res = res - mk<T>(ar, ai);
+            }
+        }
+        if (!KEEP || !factored) {   // after the residual, so that its loads go first
+            V.factor(dre, dim, ore, oim, gg, base, row);
+            factored = true;
+        }
+        const cx<T> mine = V.solve(res, base, row);
         const Vec<T> ov{eout + r * stride, g.N};
-        const cx<T> res = resb[q];
-        cx<T> rr[R];
-#pragma unroll
-        for (int j = 0; j < R; ++j) {
-            rr[j].re = __shfl(res.re, base + 8 * j, 64);
-            rr[j].im = __shfl(res.im, base + 8 * j, 64);
-        }
-        cx<T> d[R];
-        if (row == 0) {
-            cx<T> acc = rr[2 * D];
-            cx<T> ylo[D], yhi[D];
-#pragma unroll
-            for (int kk = 0; kk < D; ++kk) {
-                ylo[kk] = i00[kk] * rr[2 * kk] + i01[kk] * rr[2 * kk + 1];
-                yhi[kk] = i01[kk] * rr[2 * kk] + i11[kk] * rr[2 * kk + 1];
-                acc = acc - (glo[kk] * ylo[kk] + ghi[kk] * yhi[kk]);
-            }
-            const cx<T> dp = acc * iS;
-#pragma unroll
-            for (int kk = 0; kk < D; ++kk) {
-                d[2 * kk] = ylo[kk] - zlo[kk] * dp;
-                d[2 * kk + 1] = yhi[kk] - zhi[kk] * dp;
-            }
-            d[2 * D] = dp;
-        }
-        cx<T> mine = mk<T>(T(0), T(0));
-#pragma unroll
-        for (int j = 0; j < R; ++j) {
-            const T vr = __shfl(d[j].re, base, 64);
-            const T vi = __shfl(d[j].im, base, 64);
-            if (row == j) mine = mk<T>(vr, vi);
-        }
-        if (ok) ov.st(idx, (ein ? ev.ld(idx) : mk<T>(T(0), T(0))) + w * mine);
-        if (carry) ov.st(ipb, ein ? ev.ld(ipb) : mk<T>(T(0), T(0)));
-    }
+        if (ok) ov.st(idx, eown + w * mine);
+        if (carry) ov.st(ipb, ein ? CVec<T>{ein + r * stride, g.N}.ld(ipb) : mk<T>(T(0), T(0)));
     }
 }
 
-// Workgroups are dealt to the 8 XCDs round-robin (linear id mod 8), and each XCD
-// has its own L2.  Renumbering so that every XCD receives one contiguous range
-// of logical blocks keeps the rows above and below a block's cells (stencil
-// neighbours) in the same L2.  Bijective for any block count.
-EHH_DEV inline int64_t xcd_block(int64_t bid, int64_t nb) {
-    constexpr int64_t X = 8;
-    const int64_t q = nb / X, rem = nb % X;
-    const int64_t xcd = bid % X, local = bid / X;
-    return xcd < rem ? xcd * (q + 1) + local : rem * (q + 1) + (xcd - rem) * q + local;
+// y = A x or r = b - A x over stored rows (term j of row t at [j * N + t]).
+template <typename T>
+__global__ __launch_bounds__(256) void k_apply_st2d(Geo g, const T* __restrict__ x, const T* __restrict__ b,
+                                                    T* __restrict__ y, int nrhs, int64_t stride, int rpb,
+                                                    const T* __restrict__ cre, const T* __restrict__ cim) {
+    constexpr int NF = St<2>::NF, NT = NF + St<2>::NUP;
+    {
+        const int rb0 = blockIdx.y * rpb;
+        x += rb0 * stride;
+        if (b) b += rb0 * stride;
+        y += rb0 * stride;
+        nrhs = nrhs - rb0 < rpb ? nrhs - rb0 : rpb;
+    }
+    const int N = (int)g.N;
+    const int t = (int)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (t >= N) return;
+    int k = 0;
+    while (k < 3 && t >= g.off[k + 1]) ++k;
+    const int li = t - (int)g.off[k];
+    const int d0 = g.n[0] - (k == 0);
+    int p[3] = {li % d0, li / d0, 0};
+    if (k == 0) p[0] += 1;
+    if (k == 1) p[1] += 1;
+    const Cols2 cc = cols2(g, k, p);
+    const Buf<T> cR(cre, (uint32_t)(NT * N * sizeof(T))), cI(cim, (uint32_t)(NF * N * sizeof(T)));
+    const uint32_t lo = (uint32_t)t * (uint32_t)sizeof(T), ls = (uint32_t)N * (uint32_t)sizeof(T);
+    // unused terms of the pressure rows are stored as zeros
+    T are[NT], aim[NF];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) are[j] = cR.ld(lo, j * ls);
+#pragma unroll
+    for (int j = 0; j < NF; ++j) aim[j] = cI.ld(lo, j * ls);
+    const uint32_t vb = 2 * ls;
+    for (int r = 0; r < nrhs; ++r) {
+        const Buf<T> xv(x + r * stride, vb);
+        T vr[NT], vi[NT];
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const uint32_t o = (uint32_t)col2(cc, j) * (uint32_t)sizeof(T);
+            vr[j] = xv.ld(o, 0);
+            vi[j] = xv.ld(o, ls);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        T ar = T(0), ai = T(0);
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const T ci = j < NF ? aim[j] : T(0);
+            ar += are[j] * vr[j] - ci * vi[j];
+            ai += are[j] * vi[j] + ci * vr[j];
+        }
+        cx<T> o = mk<T>(ar, ai);
+        if (b) o = CVec<T>{b + r * stride, g.N}.ld(t) - o;
+        Vec<T>{y + r * stride, g.N}.st(t, o);
+    }
 }
-
-// Raw buffer access: a scalar resource descriptor (base, size in bytes) plus a
-// 32-bit byte offset per lane, so that a kernel keeps one VGPR per address.
-// Reads past the descriptor's size return zero.
-typedef uint32_t ehh_u2 __attribute__((ext_vector_type(2)));
-template <typename T> struct Buf;
-template <> struct Buf<float> {
-    __amdgpu_buffer_rsrc_t r;
-    EHH_DEV Buf(const void* p, uint32_t bytes)
-        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000)) {}
-    EHH_DEV float ld(uint32_t off) const { return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0)); }
-    EHH_DEV void st(uint32_t off, float v) const {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
-    }
-};
-template <> struct Buf<double> {
-    __amdgpu_buffer_rsrc_t r;
-    EHH_DEV Buf(const void* p, uint32_t bytes)
-        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000)) {}
-    EHH_DEV double ld(uint32_t off) const {
-        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-    }
-    EHH_DEV void st(uint32_t off, double v) const {
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(ehh_u2, v), r, off, 0, 0);
-    }
-};
 
 // ------------------------------------------- one thread per cell (2D finest level)
 // The finest level's rows have few terms (self, two normal and two tangential
@@ -989,11 +1274,12 @@ __global__ __launch_bounds__(256) void k_apply_cell3d(FineOp<3, T> op, const T* 
     }
 }
 
-// Builds the row plans of one colour's half-sweep in the lane order of
-// k_relax_plan (same lane -> cell/row mapping, absent rows all zero).
+// Builds the stored rows of one colour's half-sweep in the lane order of
+// k_relax_st2d (same lane -> cell/row mapping, absent rows all zero): real parts
+// of all NT terms, imaginary parts of the NF u-u terms.
 template <typename T>
-__global__ __launch_bounds__(256) void k_build_plans(StOp<2, T> op, int colour, int32_t* __restrict__ ix,
-                                                     T* __restrict__ re, T* __restrict__ im, int64_t lanes) {
+__global__ __launch_bounds__(256) void k_build_plans(StOp<2, T> op, int colour, T* __restrict__ re,
+                                                     T* __restrict__ im, int64_t lanes) {
     constexpr int D = 2;
     constexpr int R = 2 * D + 1;
     using Op = StOp<2, T>;
@@ -1031,17 +1317,15 @@ __global__ __launch_bounds__(256) void k_build_plans(StOp<2, T> op, int colour, 
         for (int j = 0; j < Op::NT; ++j) P.set(j, 0, T(0), T(0));
     }
 #pragma unroll
-    for (int j = 0; j < Op::NT; ++j) {
-        ix[j * lanes + gl] = P.ix[j];
-        re[j * lanes + gl] = P.re[j];
-        im[j * lanes + gl] = P.im[j];
-    }
+    for (int j = 0; j < Op::NT; ++j) re[j * lanes + gl] = P.re[j];
+#pragma unroll
+    for (int j = 0; j < St<2>::NF; ++j) im[j * lanes + gl] = P.im[j];
 }
 
-// Row plans of y = A x in row order (term j of row t at [j * N + t]).
+// Stored rows of y = A x in row order (term j of row t at [j * N + t]; as above,
+// imaginary parts of the u-u terms only).
 template <typename T>
-__global__ __launch_bounds__(256) void k_build_row_plans(StOp<2, T> op, int32_t* __restrict__ ix,
-                                                         T* __restrict__ re, T* __restrict__ im) {
+__global__ __launch_bounds__(256) void k_build_row_plans(StOp<2, T> op, T* __restrict__ re, T* __restrict__ im) {
     using Op = StOp<2, T>;
     const Geo& g = op.g;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1059,11 +1343,9 @@ __global__ __launch_bounds__(256) void k_build_row_plans(StOp<2, T> op, int32_t*
         op.plan_u(k, p, P);
     }
 #pragma unroll
-    for (int j = 0; j < Op::NT; ++j) {
-        ix[j * g.N + t] = P.ix[j];
-        re[j * g.N + t] = P.re[j];
-        im[j * g.N + t] = P.im[j];
-    }
+    for (int j = 0; j < Op::NT; ++j) re[j * g.N + t] = P.re[j];
+#pragma unroll
+    for (int j = 0; j < St<2>::NF; ++j) im[j * g.N + t] = P.im[j];
 }
 
 // ---------------------------------------------------- LDS-staged half-sweep (2D)
@@ -1206,7 +1488,7 @@ __global__ __launch_bounds__(512) void k_relax_lds2d(Op op, int colour, T w, int
         cx<T> eown = mk<T>(T(0), T(0)), ecarry = mk<T>(T(0), T(0));
         if (ein) {
             const CVec<T> ev{ein + r * stride, g.N};
-            __syncthreads();   // the previous right-hand side is done with the tile
+            lds_barrier();   // the previous right-hand side is done with the tile
             for (int e = threadIdx.x; e < nreg; e += blockDim.x) {
                 int kk, q0, q1;
                 if (e < b1) {
@@ -1229,7 +1511,7 @@ __global__ __launch_bounds__(512) void k_relax_lds2d(Op op, int colour, T w, int
                 sre[e] = v.re;
                 sim[e] = v.im;
             }
-            __syncthreads();
+            lds_barrier();
             if (ok) {
                 T ar = T(0), ai = T(0);
 #pragma unroll
@@ -1523,8 +1805,8 @@ hipError_t launch_apply(const LevelDesc<T>& L, const T* x, const T* b, T* y, int
     } else if (L.g.dim == 2) {
         if (L.fine)
             EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_apply_plan<2, T, FineOp<2, T>, RB>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, x, b, y, nrhs, stride, rpb));
-        else if (L.sp.rix)
-            EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_apply_plan<2, T, StOp<2, T>, RB, true>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, x, b, y, nrhs, stride, rpb, L.sp.rix, L.sp.rre, L.sp.rim));
+        else if (L.sp.rre)
+            hipLaunchKernelGGL((k_apply_st2d<T>), gb, 256, 0, s, L.g, x, b, y, nrhs, stride, rpb, L.sp.rre, L.sp.rim);
         else
             EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_apply_plan<2, T, StOp<2, T>, RB>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, x, b, y, nrhs, stride, rpb));
     } else if (L.g.dim == 3 && L.fine && cell3d_enabled() && 2 * L.g.N * (int64_t)sizeof(T) < (int64_t(1) << 32)) {
@@ -1561,7 +1843,7 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
     // stored row plans and 217 us with plans built in the kernel); with a few
     // sources the stored plans win (one FP64 source: 30 us against 53 us), and at
     // 128^2 and below the block-wide synchronisation costs more than it saves.
-    const bool big_batch = !(L.sp.ix[colour] && nrhs <= 8);
+    const bool big_batch = !(L.sp.re[colour] && nrhs <= 8);
     if (L.g.dim == 2 && !L.fine && L.g.ncell >= 65536 && lds2d_enabled() && big_batch) {
         const int tiles = ((L.g.n[0] + LT_X - 1) / LT_X) * ((L.g.n[1] + LT_Y - 1) / LT_Y);
         const int rpl = rhs_per_block((int64_t)tiles * 8, nrhs, 1);
@@ -1578,8 +1860,8 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
     } else if (L.g.dim == 2) {
         if (L.fine)
             EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_relax_plan<2, T, FineOp<2, T>, RB>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb));
-        else if (L.sp.ix[colour])
-            EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_relax_plan<2, T, StOp<2, T>, RB, true>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb, L.sp.ix[colour], L.sp.re[colour], L.sp.im[colour], L.sp.lanes));
+        else if (L.sp.re[colour])
+            hipLaunchKernelGGL((k_relax_st2d<T, sizeof(T) == 4>), gb, 256, 0, s, L.g, colour, tw, econ, b, ein, eout, nrhs, stride, rpb, L.sp.re[colour], L.sp.im[colour], L.sp.lanes);
         else
             EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_relax_plan<2, T, StOp<2, T>, RB>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb));
     } else if (L.fine && cell3d_enabled() && 2 * L.g.N * (int64_t)sizeof(T) < (int64_t(1) << 32)) {
@@ -1607,24 +1889,25 @@ int64_t stored_plan_lanes(const Geo& g) {
 // small batches, see launch_relax).
 bool stored_plan_wanted(const Geo& g, bool fine) {
     static const bool on = env_int("EHH_SPLAN", 1) != 0;
-    return on && g.dim == 2 && !fine;
+    // the kernels address the stored rows and the vectors with 32-bit byte offsets
+    constexpr int64_t NT = St<2>::NF + St<2>::NUP, lim = int64_t(1) << 32;
+    return on && g.dim == 2 && !fine && NT * stored_plan_lanes(g) * 8 < lim && NT * g.N * 8 < lim && 16 * g.N < lim;
 }
 template <typename T>
-hipError_t launch_build_plans(const LevelDesc<T>& L, int colour, int32_t* ix, T* re, T* im, hipStream_t s) {
+hipError_t launch_build_plans(const LevelDesc<T>& L, int colour, T* re, T* im, hipStream_t s) {
     const int64_t lanes = stored_plan_lanes(L.g);
-    hipLaunchKernelGGL((k_build_plans<T>), nblk(lanes), 256, 0, s, StOp<2, T>{L.g, L.s}, colour, ix, re, im, lanes);
+    hipLaunchKernelGGL((k_build_plans<T>), nblk(lanes), 256, 0, s, StOp<2, T>{L.g, L.s}, colour, re, im, lanes);
     return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_build_row_plans(const LevelDesc<T>& L, int32_t* ix, T* re, T* im, hipStream_t s) {
-    hipLaunchKernelGGL((k_build_row_plans<T>), nblk(L.g.N), 256, 0, s, StOp<2, T>{L.g, L.s}, ix, re, im);
+hipError_t launch_build_row_plans(const LevelDesc<T>& L, T* re, T* im, hipStream_t s) {
+    hipLaunchKernelGGL((k_build_row_plans<T>), nblk(L.g.N), 256, 0, s, StOp<2, T>{L.g, L.s}, re, im);
     return hipGetLastError();
 }
-template hipError_t launch_build_row_plans<float>(const LevelDesc<float>&, int32_t*, float*, float*, hipStream_t);
-template hipError_t launch_build_row_plans<double>(const LevelDesc<double>&, int32_t*, double*, double*,
-                                                   hipStream_t);
-template hipError_t launch_build_plans<float>(const LevelDesc<float>&, int, int32_t*, float*, float*, hipStream_t);
-template hipError_t launch_build_plans<double>(const LevelDesc<double>&, int, int32_t*, double*, double*, hipStream_t);
+template hipError_t launch_build_row_plans<float>(const LevelDesc<float>&, float*, float*, hipStream_t);
+template hipError_t launch_build_row_plans<double>(const LevelDesc<double>&, double*, double*, hipStream_t);
+template hipError_t launch_build_plans<float>(const LevelDesc<float>&, int, float*, float*, hipStream_t);
+template hipError_t launch_build_plans<double>(const LevelDesc<double>&, int, double*, double*, hipStream_t);
 
 template <typename T>
 hipError_t launch_restrict(const Geo& gf, const Geo& gc, const T* rf, T* rc, int nrhs, hipStream_t s) {

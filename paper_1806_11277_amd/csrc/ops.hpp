@@ -15,6 +15,15 @@
 
 namespace ehh {
 
+// Workgroup barrier that orders LDS accesses only.  __syncthreads() also waits
+// for the workgroup's outstanding global stores (its fence covers all memory),
+// which costs a memory round trip per barrier in loops that store results.
+EHH_DEV void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // A matrix row as (index, coefficient) terms, built once per row and then
 // applied to every right-hand side: terms beyond the row's support point at a
 // valid index with a zero coefficient.

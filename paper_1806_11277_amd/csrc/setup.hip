@@ -4,6 +4,8 @@
 // application in every cycle.
 #include <math.h>
 
+#include <cstdlib>
+
 #include "internal.hpp"
 #include "ops.hpp"
 
@@ -455,91 +457,122 @@ __global__ __launch_bounds__(256) void k_swap_rows(double* __restrict__ A, int64
 }
 
 // A[K,K] <- (Pi_K A[K,K])^{-1} by Gauss-Jordan with partial pivoting inside the
-// block (one workgroup, the block in LDS); piv[k0 + k] = row swapped with k0 + k.
-__global__ __launch_bounds__(256) void k_diag_inverse(double* __restrict__ A, int64_t n, int64_t k0, int kb,
-                                                      int* __restrict__ piv, int* __restrict__ flag) {
-    __shared__ double W[GJ_NB * GJ_NB * 2];
-    __shared__ double fc[GJ_NB * 2], rr[GJ_NB * 2];
-    __shared__ int prow;
+// block; piv[k0 + k] = row swapped with k0 + k.  One workgroup of 1024 threads
+// holds the block in registers: thread (i0, j) owns the entries of column j in
+// rows i0 + 16 q.  A step publishes in LDS only what other threads need (the
+// pivot row, row k and column k, before the interchange of rows k and p) and
+// every thread updates its own entries from them, the interchange being folded
+// into the reads.  The pivot of the next step is chosen while its column is
+// updated: the owners of that column fold |a|^2 and the row into a 64-bit key
+// (the modulus's bits above the lowest six, then 63 - row) and take the maximum
+// with an LDS atomic, i.e. the largest modulus (ties within 2^-46 relative going
+// to the lowest row).
+__device__ inline unsigned long long gj_key(double m, int row) {
+    return (__double_as_longlong(m) & ~0x3FULL) | (unsigned long long)(63 - row);
+}
+
+__global__ __launch_bounds__(1024) void k_diag_inverse(double* __restrict__ A, int64_t n, int64_t k0, int kb,
+                                                       int* __restrict__ piv, int* __restrict__ flag) {
+    __shared__ double rowp[GJ_NB][2], rowk[GJ_NB][2], colk[GJ_NB][2];
+    __shared__ unsigned long long key[GJ_NB + 1];
     const int t = threadIdx.x;
-    for (int e = t; e < kb * kb; e += blockDim.x) {
-        const int i = e / kb, j = e % kb;
-        W[2 * (i * GJ_NB + j)] = A[2 * ((k0 + i) * n + k0 + j)];
-        W[2 * (i * GJ_NB + j) + 1] = A[2 * ((k0 + i) * n + k0 + j) + 1];
+    const int j = t & (GJ_NB - 1), i0 = t / GJ_NB;
+    constexpr int Q = GJ_NB * GJ_NB / 1024;
+    const bool jok = j < kb;
+    if (t <= GJ_NB) key[t] = 0ULL;
+    __syncthreads();
+    // No global store inside the step loop: a barrier waits for the workgroup's
+    // outstanding stores, so the pivots and the singularity flag are written
+    // after the loop.
+    bool singular = false;
+    double ar[Q], ai[Q];
+    unsigned long long kmax = 0ULL;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int i = i0 + 16 * q;
+        ar[q] = ai[q] = 0.0;
+        if (i < kb && jok) {
+            ar[q] = A[2 * ((k0 + i) * n + k0 + j)];
+            ai[q] = A[2 * ((k0 + i) * n + k0 + j) + 1];
+            if (j == 0) {
+                const unsigned long long kk = gj_key(ar[q] * ar[q] + ai[q] * ai[q], i);
+                kmax = kk > kmax ? kk : kmax;
+            }
+        }
     }
+    if (j == 0 && kmax) atomicMax(&key[0], kmax);
     __syncthreads();
     for (int k = 0; k < kb; ++k) {
-        if (t < 64) {   // pivot search by the first wavefront: largest modulus, lowest row on ties
-            double m = -1.0;
-            int idx = k;
-            if (t >= k && t < kb) {
-                const double xr = W[2 * (t * GJ_NB + k)], xi = W[2 * (t * GJ_NB + k) + 1];
-                m = xr * xr + xi * xi;
-                idx = t;
-            }
-            for (int o = 32; o > 0; o >>= 1) {
-                const double om = __shfl_xor(m, o, 64);
-                const int oi = __shfl_xor(idx, o, 64);
-                if (om > m || (om == m && oi < idx)) {
-                    m = om;
-                    idx = oi;
+        const int p = 63 - (int)(key[k] & 0x3FULL);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int i = i0 + 16 * q;
+            if (i < kb && jok) {
+                if (i == p) {
+                    rowp[j][0] = ar[q];
+                    rowp[j][1] = ai[q];
+                }
+                if (i == k) {
+                    rowk[j][0] = ar[q];
+                    rowk[j][1] = ai[q];
+                }
+                if (j == k) {
+                    colk[i][0] = ar[q];
+                    colk[i][1] = ai[q];
                 }
             }
-            if (t == 0) {
-                prow = idx;
-                piv[k0 + k] = (int)(k0 + idx);
-            }
         }
         __syncthreads();
-        const int p = prow;
-        if (p != k && t < kb) {
-            const double ar = W[2 * (k * GJ_NB + t)], ai = W[2 * (k * GJ_NB + t) + 1];
-            W[2 * (k * GJ_NB + t)] = W[2 * (p * GJ_NB + t)];
-            W[2 * (k * GJ_NB + t) + 1] = W[2 * (p * GJ_NB + t) + 1];
-            W[2 * (p * GJ_NB + t)] = ar;
-            W[2 * (p * GJ_NB + t) + 1] = ai;
-        }
-        __syncthreads();
-        const double pr = W[2 * (k * GJ_NB + k)], pi = W[2 * (k * GJ_NB + k) + 1];
+        // V = the block with rows k and p interchanged; pivot V(k, k) = A(p, k)
+        const double pr = rowp[k][0], pi = rowp[k][1];
         const double dd = pr * pr + pi * pi;
-        if (t == 0 && !(dd > 0.0)) *flag = 1;
+        singular = singular || !(dd > 0.0);
         const double ir = pr / dd, ii = -pi / dd;
-        if (t < kb) {
-            fc[2 * t] = W[2 * (t * GJ_NB + k)];
-            fc[2 * t + 1] = W[2 * (t * GJ_NB + k) + 1];
-            if (t == k) {
-                rr[2 * t] = ir;
-                rr[2 * t + 1] = ii;
-            } else {
-                const double ar = W[2 * (k * GJ_NB + t)], ai = W[2 * (k * GJ_NB + t) + 1];
-                rr[2 * t] = ar * ir - ai * ii;
-                rr[2 * t + 1] = ar * ii + ai * ir;
+        // row k of the result: V(k, j) / pivot, and 1 / pivot at j = k
+        double rkr = ir, rki = ii;
+        if (j != k && jok) {
+            const double vr = rowp[j][0], vi = rowp[j][1];
+            rkr = vr * ir - vi * ii;
+            rki = vr * ii + vi * ir;
+        }
+        unsigned long long km = 0ULL;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int i = i0 + 16 * q;
+            if (i < kb && jok) {
+                if (i == k) {
+                    ar[q] = rkr;
+                    ai[q] = rki;
+                } else {
+                    const int si = i == p ? k : i;
+                    const double fr = colk[si][0], fi = colk[si][1];
+                    if (j == k) {
+                        ar[q] = -(fr * ir - fi * ii);
+                        ai[q] = -(fr * ii + fi * ir);
+                    } else {
+                        const double vr = i == p ? rowk[j][0] : ar[q], vi = i == p ? rowk[j][1] : ai[q];
+                        ar[q] = vr - (fr * rkr - fi * rki);
+                        ai[q] = vi - (fr * rki + fi * rkr);
+                    }
+                }
+                if (j == k + 1 && i > k) {
+                    const unsigned long long kq = gj_key(ar[q] * ar[q] + ai[q] * ai[q], i);
+                    km = kq > km ? kq : km;
+                }
             }
         }
-        __syncthreads();
-        for (int e = t; e < kb * kb; e += blockDim.x) {
-            const int i = e / kb, j = e % kb;
-            double* w = W + 2 * (i * GJ_NB + j);
-            if (i == k) {
-                w[0] = rr[2 * j];
-                w[1] = rr[2 * j + 1];
-            } else if (j == k) {
-                const double fr = fc[2 * i], fi = fc[2 * i + 1];
-                w[0] = -(fr * ir - fi * ii);
-                w[1] = -(fr * ii + fi * ir);
-            } else {
-                const double fr = fc[2 * i], fi = fc[2 * i + 1];
-                const double br = rr[2 * j], bi = rr[2 * j + 1];
-                w[0] -= fr * br - fi * bi;
-                w[1] -= fr * bi + fi * br;
-            }
-        }
+        if (km) atomicMax(&key[k + 1], km);
         __syncthreads();
     }
-    for (int e = t; e < kb * kb; e += blockDim.x) {
-        const int i = e / kb, j = e % kb;
-        A[2 * ((k0 + i) * n + k0 + j)] = W[2 * (i * GJ_NB + j)];
-        A[2 * ((k0 + i) * n + k0 + j) + 1] = W[2 * (i * GJ_NB + j) + 1];
+    if (t < kb) piv[k0 + t] = (int)(k0 + 63 - (int)(key[t] & 0x3FULL));
+    if (t == 0 && singular) *flag = 1;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int i = i0 + 16 * q;
+        if (i < kb && jok) {
+            A[2 * ((k0 + i) * n + k0 + j)] = ar[q];
+            A[2 * ((k0 + i) * n + k0 + j) + 1] = ai[q];
+        }
     }
 }
 
@@ -641,7 +674,7 @@ hipError_t launch_dense_invert(double* A, int64_t n, int* piv, int* flag, hipStr
     if (e != hipSuccess) return e;
     for (int64_t k0 = 0; k0 < n; k0 += GJ_NB) {
         const int kb = (int)std::min<int64_t>(GJ_NB, n - k0);
-        hipLaunchKernelGGL(k_diag_inverse, 1, 256, 0, s, A, n, k0, kb, piv, flag);
+        hipLaunchKernelGGL(k_diag_inverse, 1, 1024, 0, s, A, n, k0, kb, piv, flag);
         hipLaunchKernelGGL(k_swap_rows, nblk(n), 256, 0, s, A, n, k0, kb, piv);
         double* AK = A + 2 * k0 * n;           // rows K
         double* AKK = AK + 2 * k0;             // the inverted block W
@@ -802,6 +835,212 @@ __global__ __launch_bounds__(256) void k_coarse_reduce(const double* __restrict_
     e[t] = (T)s;
 }
 
+// ------------------------------------------------ symmetric coarse apply
+// The coarsest operator is complex symmetric (a Galerkin product P^T A P of the
+// complex symmetric operator of eq. (14)), hence so is its inverse: only the
+// 64 x 64 tiles (I, J) with I >= J are kept, tile after tile (row-major inside a
+// tile, diagonal tiles whole, entries beyond n zero); tile (I, J) sits at
+// I (I + 1) / 2 + J.  A tile below the diagonal then serves both y_I += A_IJ x_J
+// and y_J += A_IJ^T x_I, so a solve streams half the inverse.
+constexpr int SY = 64;
+
+static inline __device__ void sym_tile_of(int64_t b, int& I, int& J) {
+    int i = (int)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+    while ((int64_t)(i + 1) * (i + 2) / 2 <= b) ++i;
+    while ((int64_t)i * (i + 1) / 2 > b) --i;
+    I = i;
+    J = (int)(b - (int64_t)i * (i + 1) / 2);
+}
+
+__global__ __launch_bounds__(256) void k_pack_sym(const double* __restrict__ inv, int64_t n,
+                                                  double* __restrict__ sym, int64_t total) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    int I, J;
+    sym_tile_of(e / (SY * SY), I, J);
+    const int w = (int)(e % (SY * SY));
+    const int64_t gi = (int64_t)I * SY + w / SY, gj = (int64_t)J * SY + w % SY;
+    double vr = 0.0, vi = 0.0;
+    if (gi < n && gj < n) {
+        vr = inv[2 * (gi * n + gj)];
+        vi = inv[2 * (gi * n + gj) + 1];
+    }
+    sym[2 * e] = vr;
+    sym[2 * e + 1] = vi;
+}
+
+// One step of a recursive-halving sum over lanes: lanes with bit M set keep the
+// upper HALF of their values, the others the lower half, each adding its
+// partner's copy (all exchanges issued before the sums).
+template <int HALF, int M>
+__device__ inline void halve_step(double* vr, double* vi, int lane) {
+    const bool up = (lane & M) != 0;
+    double gr[HALF], gi[HALF];
+#pragma unroll
+    for (int rr = 0; rr < HALF; ++rr) {
+        gr[rr] = __shfl_xor(up ? vr[rr] : vr[rr + HALF], M, 64);
+        gi[rr] = __shfl_xor(up ? vi[rr] : vi[rr + HALF], M, 64);
+    }
+#pragma unroll
+    for (int rr = 0; rr < HALF; ++rr) {
+        vr[rr] = (up ? vr[rr + HALF] : vr[rr]) + gr[rr];
+        vi[rr] = (up ? vi[rr + HALF] : vi[rr]) + gi[rr];
+    }
+}
+
+// One workgroup per stored tile and group of up to 4 right-hand sides; wave w
+// takes rows 16 w .. 16 w + 15 of the tile, lane = column.  The row products are
+// summed over the lanes by recursive halving (16 partial sums per lane folded
+// into one per lane in four exchange steps, then two more), the column products
+// over the rows of a wave in registers and over the four waves in LDS.  Partial
+// results go to ws[q][X_out][J_src][64] and are summed by k_sym_reduce (a
+// separate launch: a device-wide fence, which a last-workgroup-sums scheme would
+// need, writes back the L2 of each XCD and costs more than the launch).
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse_apply_sym(const double* __restrict__ sym, int64_t n, int nb,
+                                                          const T* __restrict__ r, int nrhs,
+                                                          double* __restrict__ ws) {
+    constexpr int RG = 4;
+    __shared__ double xs[2][RG][SY][2];
+    __shared__ double cs[4][RG][SY][2];
+    int I, J;
+    sym_tile_of(blockIdx.x, I, J);
+    const int r0 = blockIdx.y * RG;
+    const int nr = nrhs - r0 < RG ? nrhs - r0 : RG;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // x_I (side 0) and x_J (side 1) of the group's right-hand sides
+    for (int e2 = threadIdx.x; e2 < 2 * RG * SY; e2 += blockDim.x) {
+        const int side = e2 / (RG * SY), q = (e2 / SY) % RG, i = e2 % SY;
+        const int64_t gi = (int64_t)(side == 0 ? I : J) * SY + i;
+        double vr = 0.0, vi = 0.0;
+        if (q < nr && gi < n) {
+            const T* rv = r + (int64_t)(r0 + q) * 2 * n;
+            vr = (double)rv[gi];
+            vi = (double)rv[n + gi];
+        }
+        xs[side][q][i][0] = vr;
+        xs[side][q][i][1] = vi;
+    }
+    __syncthreads();
+    const double* tile = sym + (size_t)blockIdx.x * SY * SY * 2;
+    double ar[16], ai[16];
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr) {
+        const int i = 16 * w + rr;
+        ar[rr] = tile[2 * (i * SY + lane)];
+        ai[rr] = tile[2 * (i * SY + lane) + 1];
+    }
+    const bool offdiag = I != J;
+#pragma unroll 1
+    for (int q = 0; q < nr; ++q) {
+        const double xjr = xs[1][q][lane][0], xji = xs[1][q][lane][1];
+        double vr[16], vi[16];
+        double cr = 0.0, ci = 0.0;
+#pragma unroll
+        for (int rr = 0; rr < 16; ++rr) {
+            vr[rr] = ar[rr] * xjr - ai[rr] * xji;
+            vi[rr] = ar[rr] * xji + ai[rr] * xjr;
+            const double xir = xs[0][q][16 * w + rr][0], xii = xs[0][q][16 * w + rr][1];
+            cr += ar[rr] * xir - ai[rr] * xii;
+            ci += ar[rr] * xii + ai[rr] * xir;
+        }
+        // recursive halving over lane bits 5..2; afterwards lane l holds row l >> 2
+        halve_step<8, 32>(vr, vi, lane);
+        halve_step<4, 16>(vr, vi, lane);
+        halve_step<2, 8>(vr, vi, lane);
+        halve_step<1, 4>(vr, vi, lane);
+        double tr = vr[0], ti = vi[0];
+        tr += __shfl_xor(tr, 2, 64);
+        ti += __shfl_xor(ti, 2, 64);
+        tr += __shfl_xor(tr, 1, 64);
+        ti += __shfl_xor(ti, 1, 64);
+        if ((lane & 3) == 0) {
+            double* o = ws + 2 * ((((int64_t)(r0 + q) * nb + I) * nb + J) * SY + 16 * w + (lane >> 2));
+            o[0] = tr;
+            o[1] = ti;
+        }
+        cs[w][q][lane][0] = cr;
+        cs[w][q][lane][1] = ci;
+    }
+    lds_barrier();
+    if (offdiag) {
+        for (int e2 = threadIdx.x; e2 < nr * SY; e2 += blockDim.x) {
+            const int q = e2 / SY, j = e2 % SY;
+            double sr = 0.0, si = 0.0;
+#pragma unroll
+            for (int ww = 0; ww < 4; ++ww) {
+                sr += cs[ww][q][j][0];
+                si += cs[ww][q][j][1];
+            }
+            double* o = ws + 2 * ((((int64_t)(r0 + q) * nb + J) * nb + I) * SY + j);
+            o[0] = sr;
+            o[1] = si;
+        }
+    }
+}
+
+// e[q][X * 64 + i] = sum over the source blocks J of ws[q][X][J][i], four lanes
+// per output (each a fixed quarter of the sources, then a fixed pairwise sum).
+template <typename T>
+__global__ __launch_bounds__(256) void k_sym_reduce(const double* __restrict__ ws, int64_t n, int nb, int nrhs,
+                                                    T* __restrict__ e) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int part = (int)(t & 3);
+    const int64_t o = t >> 2;
+    const bool live = o < n * nrhs;
+    const int64_t q = live ? o / n : 0, gi = live ? o % n : 0;
+    const int64_t X = gi / SY, i = gi % SY;
+    const double* p = ws + 2 * (((q * nb + X) * nb) * SY + i);
+    const int per = (nb + 3) / 4;
+    const int j0 = part * per, j1 = j0 + per < nb ? j0 + per : nb;
+    double sr = 0.0, si = 0.0;
+    if (live) {
+        int Jb = j0;
+        for (; Jb + 4 <= j1; Jb += 4) {
+            double vr[4], vi[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                vr[u] = p[2 * (int64_t)(Jb + u) * SY];
+                vi[u] = p[2 * (int64_t)(Jb + u) * SY + 1];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                sr += vr[u];
+                si += vi[u];
+            }
+        }
+        for (; Jb < j1; ++Jb) {
+            sr += p[2 * (int64_t)Jb * SY];
+            si += p[2 * (int64_t)Jb * SY + 1];
+        }
+    }
+    sr += __shfl_xor(sr, 1, 64);
+    si += __shfl_xor(si, 1, 64);
+    sr += __shfl_xor(sr, 2, 64);
+    si += __shfl_xor(si, 2, 64);
+    if (live && part == 0) {
+        T* ev = e + q * 2 * n;
+        ev[gi] = (T)sr;
+        ev[n + gi] = (T)si;
+    }
+}
+
+int64_t sym_tiles(int64_t n) {
+    const int64_t nb = (n + SY - 1) / SY;
+    return nb * (nb + 1) / 2;
+}
+hipError_t launch_pack_sym(const double* inv, int64_t n, double* sym, hipStream_t s) {
+    const int64_t total = sym_tiles(n) * SY * SY;
+    hipLaunchKernelGGL(k_pack_sym, nblk(total), 256, 0, s, inv, n, sym, total);
+    return hipGetLastError();
+}
+// Workspace of the symmetric apply (partial results; rewritten by every call).
+static size_t sym_ws_doubles(int64_t n, int nrhs) {
+    const int64_t nb = (n + SY - 1) / SY;
+    return (size_t)2 * SY * nb * nb * nrhs;
+}
+
+
 // Column segments of the multi-right-hand-side coarse apply: enough workgroups to
 // fill the chip (about 1024), segments of at least 256 columns.
 static int coarse_width(int nrhs) { return nrhs <= 4 ? 0 : nrhs <= 8 ? 8 : nrhs <= 16 ? 16 : 32; }
@@ -815,13 +1054,28 @@ int coarse_ksplit(int64_t n, int nrhs) {
     return (int)ks;
 }
 size_t coarse_ws_doubles(int64_t n, int nrhs) {
+    if (coarse_width(nrhs) == 0) return sym_ws_doubles(n, nrhs);
     const int ks = coarse_ksplit(n, nrhs);
     return ks > 1 ? (size_t)ks * 2 * n * nrhs : 0;
 }
 
+// A few right-hand sides: the packed symmetric inverse (half the bytes) where it
+// is given with a workspace, else one wavefront per row of the full inverse.
 template <typename T>
-hipError_t launch_coarse_apply(const double* inv, int64_t n, const T* r, T* e, int nrhs, double* ws, hipStream_t s) {
+hipError_t launch_coarse_apply(const double* inv, const double* sym, int64_t n, const T* r, T* e, int nrhs,
+                               double* ws, hipStream_t s) {
     const int W = coarse_width(nrhs);
+    static const bool sym_on = [] {
+        const char* v = std::getenv("EHH_COARSE_SYM");
+        return !v || std::atoi(v) != 0;
+    }();
+    if (W == 0 && sym && ws && sym_on) {   // W == 0: one group of at most 4 right-hand sides
+        const int nb = (int)((n + SY - 1) / SY);
+        hipLaunchKernelGGL((k_coarse_apply_sym<T>), dim3((unsigned)sym_tiles(n), 1), 256, 0, s, sym, n, nb, r, nrhs,
+                           ws);
+        hipLaunchKernelGGL((k_sym_reduce<T>), nblk(4 * n * nrhs), 256, 0, s, ws, n, nb, nrhs, e);
+        return hipGetLastError();
+    }
     if (W == 0) {
         hipLaunchKernelGGL((k_coarse_apply<T>), dim3(nblk(n * 64), (nrhs + 3) / 4), 256, 0, s, inv, n, r, e, nrhs);
         return hipGetLastError();
@@ -842,10 +1096,10 @@ hipError_t launch_coarse_apply(const double* inv, int64_t n, const T* r, T* e, i
     if (part) hipLaunchKernelGGL((k_coarse_reduce<T>), nblk(2 * n * nrhs), 256, 0, s, part, ks, n, nrhs, e);
     return hipGetLastError();
 }
-template hipError_t launch_coarse_apply<float>(const double*, int64_t, const float*, float*, int, double*,
-                                               hipStream_t);
-template hipError_t launch_coarse_apply<double>(const double*, int64_t, const double*, double*, int, double*,
-                                                hipStream_t);
+template hipError_t launch_coarse_apply<float>(const double*, const double*, int64_t, const float*, float*, int,
+                                               double*, hipStream_t);
+template hipError_t launch_coarse_apply<double>(const double*, const double*, int64_t, const double*, double*, int,
+                                                double*, hipStream_t);
 
 __global__ void k_zero_words(uint32_t* __restrict__ p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
