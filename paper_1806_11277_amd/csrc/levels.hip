@@ -1726,6 +1726,143 @@ __global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const T* __rest
     }
 }
 
+// 2D transfers with 32-bit indices and every load issued before the sums, in the
+// same term order as k_restrict / k_prolong (a term outside the grid reads a
+// clamped index with weight zero).  One right-hand side per grid row.
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict2d(Geo gf, Geo gc, const T* __restrict__ rf, T* __restrict__ rc) {
+    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int Nc = (int)gc.N, Nf = (int)gf.N;
+    if (t >= Nc) return;
+    rf += (int64_t)blockIdx.y * 2 * gf.N;
+    rc += (int64_t)blockIdx.y * 2 * gc.N;
+    const int ncx = gc.n[0], nfx = gf.n[0], nfy = gf.n[1];
+    T sr = T(0), si = T(0);
+    if (t >= (int)gc.off[3]) {   // pressure: the four fine cells
+        const int li = t - (int)gc.off[3];
+        const int X = li % ncx, Y = li / ncx;
+        const int b = (int)gf.off[3] + 2 * Y * nfx + 2 * X;
+        const int ix[4] = {b, b + 1, b + nfx, b + nfx + 1};
+        T vr[4], vi[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            vr[j] = rf[ix[j]];
+            vi[j] = rf[Nf + ix[j]];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            sr += vr[j];
+            si += vi[j];
+        }
+    } else {
+        const bool k0 = t < (int)gc.off[1];
+        int X, Y;
+        if (k0) {
+            const int li = t - (int)gc.off[0];
+            X = li % (ncx - 1) + 1;
+            Y = li / (ncx - 1);
+        } else {
+            const int li = t - (int)gc.off[1];
+            X = li % ncx;
+            Y = li / ncx + 1;
+        }
+        int ix[12];
+        T wt[12];
+#pragma unroll
+        for (int a = -1; a <= 1; ++a)
+#pragma unroll
+            for (int b1 = -1; b1 <= 2; ++b1) {
+                const int j = (a + 1) * 4 + b1 + 1;
+                const int fn = 2 * (k0 ? X : Y) + a, ft = 2 * (k0 ? Y : X) + b1, nt = k0 ? nfy : nfx;
+                const bool ok = ft >= 0 && ft < nt;
+                const int fc = ft < 0 ? 0 : (ft >= nt ? nt - 1 : ft);
+                ix[j] = k0 ? (int)gf.off[0] + fc * (nfx - 1) + fn - 1 : (int)gf.off[1] + (fn - 1) * nfx + fc;
+                wt[j] = ok ? (a == 0 ? T(1) : T(0.5)) * T(w_tang(b1)) : T(0);
+            }
+        T vr[12], vi[12];
+#pragma unroll
+        for (int j = 0; j < 12; ++j) {
+            vr[j] = rf[ix[j]];
+            vi[j] = rf[Nf + ix[j]];
+        }
+#pragma unroll
+        for (int j = 0; j < 12; ++j) {
+            sr += wt[j] * vr[j];
+            si += wt[j] * vi[j];
+        }
+    }
+    rc[t] = sr;
+    rc[Nc + t] = si;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong2d(Geo gf, Geo gc, const T* __restrict__ ec, T* __restrict__ ef) {
+    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int Nc = (int)gc.N, Nf = (int)gf.N;
+    if (t >= Nf) return;
+    ec += (int64_t)blockIdx.y * 2 * gc.N;
+    ef += (int64_t)blockIdx.y * 2 * gf.N;
+    const int ncx = gc.n[0], ncy = gc.n[1], nfx = gf.n[0];
+    if (t >= (int)gf.off[3]) {   // pressure: piecewise constant
+        const int li = t - (int)gf.off[3];
+        const int x = li % nfx, y = li / nfx;
+        const int ci = (int)gc.off[3] + (y >> 1) * ncx + (x >> 1);
+        const T cr = ec[ci], cim = ec[Nc + ci];
+        const T fr = ef[t], fi = ef[Nf + t];
+        ef[t] = fr + cr;
+        ef[Nf + t] = fi + cim;
+        return;
+    }
+    const bool k0 = t < (int)gf.off[1];
+    int pn, pt;   // fine position along the normal and the tangential axis
+    if (k0) {
+        const int li = t - (int)gf.off[0];
+        pn = li % (nfx - 1) + 1;
+        pt = li / (nfx - 1);
+    } else {
+        const int li = t - (int)gf.off[1];
+        pt = li % nfx;
+        pn = li / nfx + 1;
+    }
+    const int ncn = k0 ? ncx : ncy, nct = k0 ? ncy : ncx;
+    // normal: the coincident coarse face (weight 1) or the two around it (1/2 each)
+    const int xn0 = (pn & 1) ? (pn - 1) >> 1 : pn >> 1, xn1 = (pn + 1) >> 1;
+    const T wn0 = (pn & 1) ? T(0.5) : T(1), wn1 = (pn & 1) ? T(0.5) : T(0);
+    // tangential: the nearer coarse row (3/4) and the other one (1/4) inside the grid
+    const int C = pt >> 1, o = (pt & 1) ? C + 1 : C - 1;
+    const bool ook = o >= 0 && o < nct;
+    const int xs[2] = {xn0, xn1};
+    const T ws[2] = {wn0, wn1};
+    const int ts[2] = {C, ook ? o : C};
+    const T wts[2] = {T(0.75), ook ? T(0.25) : T(0)};
+    int ix[4];
+    T wt[4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int i1 = 0; i1 < 2; ++i1) {
+            const int X = xs[a];
+            const bool ok = X >= 1 && X <= ncn - 1;
+            const int Xc = ok ? X : 1;
+            ix[2 * a + i1] = k0 ? (int)gc.off[0] + ts[i1] * (ncx - 1) + Xc - 1 : (int)gc.off[1] + (Xc - 1) * ncx + ts[i1];
+            wt[2 * a + i1] = ok ? ws[a] * wts[i1] : T(0);
+        }
+    T vr[4], vi[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        vr[j] = ec[ix[j]];
+        vi[j] = ec[Nc + ix[j]];
+    }
+    T sr = ef[t], si = ef[Nf + t];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        sr += wt[j] * vr[j];
+        si += wt[j] * vi[j];
+    }
+    ef[t] = sr;
+    ef[Nf + t] = si;
+}
+
 // ------------------------------------------------------------------------ launchers
 static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
@@ -1760,6 +1897,10 @@ static inline bool cell2d_enabled() {
 }
 static inline bool cell3d_enabled() {
     static const bool v = env_int("EHH_CELL3D", 1) != 0;
+    return v;
+}
+static inline bool transfer2d_enabled() {
+    static const bool v = env_int("EHH_TRANSFER2D", 1) != 0;
     return v;
 }
 static inline bool lds2d_enabled() {
@@ -1911,7 +2052,9 @@ template hipError_t launch_build_plans<double>(const LevelDesc<double>&, int, do
 
 template <typename T>
 hipError_t launch_restrict(const Geo& gf, const Geo& gc, const T* rf, T* rc, int nrhs, hipStream_t s) {
-    if (gf.dim == 2)
+    if (gf.dim == 2 && transfer2d_enabled() && 2 * gf.N < (int64_t(1) << 31))
+        hipLaunchKernelGGL((k_restrict2d<T>), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc);
+    else if (gf.dim == 2)
         hipLaunchKernelGGL((k_restrict<2, T>), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc, nrhs);
     else
         hipLaunchKernelGGL((k_restrict<3, T>), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc, nrhs);
@@ -1920,7 +2063,9 @@ hipError_t launch_restrict(const Geo& gf, const Geo& gc, const T* rf, T* rc, int
 
 template <typename T>
 hipError_t launch_prolong(const Geo& gf, const Geo& gc, const T* ec, T* ef, int nrhs, hipStream_t s) {
-    if (gf.dim == 2)
+    if (gf.dim == 2 && transfer2d_enabled() && 2 * gf.N < (int64_t(1) << 31))
+        hipLaunchKernelGGL((k_prolong2d<T>), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef);
+    else if (gf.dim == 2)
         hipLaunchKernelGGL((k_prolong<2, T>), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef, nrhs);
     else
         hipLaunchKernelGGL((k_prolong<3, T>), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef, nrhs);
