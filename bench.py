@@ -120,9 +120,8 @@ def relax_kernel_name(w, level, ncell):
     """The half-sweep kernel the library launches on a level (same routing as
     its launcher): one thread per cell on the finest level, LDS-staged tiles on
     2D Galerkin levels of at least 256^2 cells with more than 8 sources, eight
-    lanes per cell with row plans stored at setup on the other 2D Galerkin
-    levels, right-hand-side blocks of 4 (FP32) or 2 (FP64) on 3D Galerkin
-    levels."""
+    lanes per cell with row coefficients stored at setup on the other Galerkin
+    levels (3D: blocks of 8 (FP32) or 2 (FP64) sources per coefficient load)."""
     t = "float" if w.precond_bits == 32 else "double"
     if w.dim == 2:
         if level == 0:
@@ -132,7 +131,7 @@ def relax_kernel_name(w, level, ncell):
         return f"k_relax_st2d<{t}, {'true' if t == 'float' else 'false'}>"
     if level == 0:
         return f"k_relax_cell3d<{t}>"
-    return f"k_relax<3, {t}, StOp<3, {t}>, 4>" if t == "float" else f"k_relax<3, {t}, StOp<3, {t}>, 2>"
+    return f"k_relax_st3d<{t}, 8, 4>" if t == "float" else f"k_relax_st3d<{t}, 2, 4>"
 
 
 KERNEL_SOURCES = ["paper_1806_11277_amd/csrc/levels.hip", "paper_1806_11277_amd/csrc/ops.hpp",

@@ -187,9 +187,12 @@ template <typename T> LevelDesc<T> level_desc(const ehh_ctx* c, const Level& L, 
     if (L.fine) {
         const int64_t n = L.g.ncell;
         d.f = FineCoef<T>{base, base + n, base + 2 * n, base + 3 * n, (T)(c->omega_nd * c->omega_nd), (T)alpha};
-    } else if (L.g.dim == 2) {
-        d.s = stencil_view<2, T>(L.g, base);
-        const bool mine = (sizeof(T) == 4) == (c->bits() == 32);   // plans are kept in the cycle precision
+    } else {
+        if (L.g.dim == 2)
+            d.s = stencil_view<2, T>(L.g, base);
+        else
+            d.s = stencil_view<3, T>(L.g, base);
+        const bool mine = (sizeof(T) == 4) == (c->bits() == 32);   // rows are kept in the cycle precision
         if (mine && L.sp_lanes)
             for (int col = 0; col < 2; ++col) {
                 d.sp.re[col] = (const T*)L.sp_re[col];
@@ -200,8 +203,6 @@ template <typename T> LevelDesc<T> level_desc(const ehh_ctx* c, const Level& L, 
             d.sp.rre = (const T*)L.rp_re;
             d.sp.rim = (const T*)L.rp_im;
         }
-    } else {
-        d.s = stencil_view<3, T>(L.g, base);
     }
     return d;
 }
@@ -576,13 +577,13 @@ int32_t build_hierarchy(ehh_ctx* c, Sub& S, const double* lam, const double* mu,
             HIPCHK(launch_cast_d2f(Q.coef64, Q.coef32, cnt, s));
         }
     }
-    // row plans of the small 2D Galerkin levels, built once in the cycle precision
+    // stored rows of the Galerkin levels, built once in the cycle precision
     for (int l = 1; l < L - 1; ++l) {
         Level& Q = S.lev[l];
         if (!stored_plan_wanted(Q.g, Q.fine)) continue;
         const int64_t lanes = stored_plan_lanes(Q.g);
         const size_t es = c->bits() == 32 ? sizeof(float) : sizeof(double);
-        constexpr int NT = St<2>::NF + St<2>::NUP, NF = St<2>::NF;
+        const int NT = stored_terms(Q.g.dim), NF = stored_imag_terms(Q.g.dim);
         for (int col = 0; col < 2; ++col) {
             CHK(c->alloc(&Q.sp_re[col], es * NT * lanes));
             CHK(c->alloc(&Q.sp_im[col], es * NF * lanes));

@@ -39,6 +39,8 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
 // Lanes (padded) of one colour's stored plans on a level, and the builder.
 int64_t stored_plan_lanes(const Geo& g);
 bool stored_plan_wanted(const Geo& g, bool fine);
+int stored_terms(int dim);        // real parts per stored row
+int stored_imag_terms(int dim);   // imaginary parts per stored row (the u-u terms)
 template <typename T>
 hipError_t launch_build_plans(const LevelDesc<T>& L, int colour, T* re, T* im, hipStream_t s);
 template <typename T>

@@ -212,6 +212,7 @@ typedef uint32_t ehh_u2 __attribute__((ext_vector_type(2)));
 template <typename T> struct Buf;
 template <> struct Buf<float> {
     __amdgpu_buffer_rsrc_t r;
+    EHH_DEV Buf() {}
     EHH_DEV Buf(const void* p, uint32_t bytes)
         : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000)) {}
     EHH_DEV float ld(uint32_t off) const { return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0)); }
@@ -225,6 +226,7 @@ template <> struct Buf<float> {
 };
 template <> struct Buf<double> {
     __amdgpu_buffer_rsrc_t r;
+    EHH_DEV Buf() {}
     EHH_DEV Buf(const void* p, uint32_t bytes)
         : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000)) {}
     EHH_DEV double ld(uint32_t off) const {
@@ -728,6 +730,368 @@ __global__ __launch_bounds__(256) void k_apply_st2d(Geo g, const T* __restrict__
         if (b) o = CVec<T>{b + r * stride, g.N}.ld(t) - o;
         Vec<T>{y + r * stride, g.N}.st(t, o);
     }
+}
+
+// ------------------------------------ stored Galerkin rows with computed columns (3D)
+// As in 2D: a 3D Galerkin level keeps its rows' coefficients in the order the
+// kernels read them (93 real parts, 75 u-u imaginary parts per row), and a term's
+// column is the row's own position plus the term's stencil offset.  The rows are
+// long (75 u-u and 18 u-p terms), so a lane reads each coefficient once per block
+// of RB right-hand sides and applies it to all of them, walking the row in
+// chunks of terms.
+struct Cols3 {
+    int self;            // global index of the row
+    int sn, s1, s2;      // u row: face-grid strides of its component along normal, t1, t2
+    int pc, cn, c1, c2;  // u row: index of the cell above the face, cell strides along normal, t1, t2
+    int f[3];            // p row: index of the cell's low face in u_0, u_1, u_2
+    int fs[3][3];        // face-grid strides of component k along axis a
+    int last;
+    bool isp;
+};
+
+EHH_DEV inline Cols3 cols3(const Geo& g, int k, const int* p) {
+    Cols3 c;
+    const int n0 = g.n[0], n1 = g.n[1];
+    c.last = (int)g.N - 1;
+    c.isp = k == 3;
+    const int cs[3] = {1, n0, n0 * n1};
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk) {
+        const int d0 = n0 - (kk == 0), d1 = n1 - (kk == 1);
+        c.fs[kk][0] = 1;
+        c.fs[kk][1] = d0;
+        c.fs[kk][2] = d0 * d1;
+        const int q0 = p[0] - (kk == 0), q1 = p[1] - (kk == 1), q2 = p[2] - (kk == 2);
+        c.f[kk] = (int)g.off[kk] + (q2 * d1 + q1) * d0 + q0;
+    }
+    c.pc = (int)g.off[3] + (p[2] * n1 + p[1]) * n0 + p[0];
+    // the lane's component selects its strides (selects, not indexing, so that
+    // nothing lands in scratch): normal k, tangential t1 = (k == 0 ? 1 : 0),
+    // t2 = (k == 2 ? 1 : 2)
+    const int d00 = n0 - 1, d10 = n0, d11 = n1 - 1, d20 = n0;
+    c.self = k == 0 ? c.f[0] : (k == 1 ? c.f[1] : (k == 2 ? c.f[2] : c.pc));
+    c.sn = k == 0 ? 1 : (k == 1 ? d10 : d20 * n1);
+    c.s1 = k == 0 ? d00 : 1;
+    c.s2 = k == 0 ? d00 * n1 : (k == 1 ? d10 * d11 : d20);
+    c.cn = k == 0 ? cs[0] : (k == 1 ? cs[1] : cs[2]);
+    c.c1 = k == 0 ? cs[1] : cs[0];
+    c.c2 = k == 2 ? cs[1] : cs[2];
+    return c;
+}
+
+// Column of term j (compile-time after unrolling): u rows in the order of
+// StOp::plan_u, the pressure row in that of StOp::plan_p.
+EHH_DEV inline int col3(const Cols3& c, int j) {
+    constexpr int NF = St<3>::NF, NUP = St<3>::NUP;
+    int iu;
+    if (j < NF) {
+        int dn, d1, d2;
+        full_offset<3>(j, dn, d1, d2);
+        iu = c.self + dn * c.sn + d1 * c.s1 + d2 * c.s2;
+    } else {
+        int side, e1, e2;
+        up_decode<3>(j - NF, side, e1, e2);
+        iu = c.pc + (side - 1) * c.cn + e1 * c.c1 + e2 * c.c2;
+    }
+    int ip = c.self;
+    if (j >= 1 && j <= 3 * NUP) {
+        const int kk = (j - 1) / NUP;
+        int side, e1, e2;
+        up_decode<3>((j - 1) % NUP, side, e1, e2);
+        const int t1 = kk == 0 ? 1 : 0, t2 = kk == 2 ? 1 : 2;
+        ip = c.f[kk] + (1 - side) * c.fs[kk][kk] - e1 * c.fs[kk][t1] - e2 * c.fs[kk][t2];
+    }
+    const int i = c.isp ? ip : iu;
+    return i < 0 ? 0 : (i > c.last ? c.last : i);
+}
+
+// Residual terms of a row for a block of RB right-hand sides: coefficient j read
+// once (lane offset lo, term stride ls, both in bytes) and applied to every
+// vector; terms in chunks of CH, each chunk's loads issued before its sums and
+// the next chunk's addresses tied to them (empty asm), so that the registers
+// hold one chunk at a time.
+template <typename T, int RB, int CH>
+EHH_DEV void rows3_rb(const Buf<T>& cR, const Buf<T>& cI, uint32_t lo, uint32_t ls, const Cols3& cc,
+                      const T* const* ev, uint32_t vb, uint32_t nb, T* ar, T* ai) {
+    constexpr int NF = St<3>::NF, NT = NF + St<3>::NUP;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) ar[q] = ai[q] = T(0);
+    Cols3 cl = cc;
+    uint32_t lh = lo;
+    Buf<T> eb[RB] = {};
+#pragma unroll
+    for (int q = 0; q < RB; ++q) eb[q] = Buf<T>(ev[q], vb);
+#pragma unroll
+    for (int h = 0; h < NT; h += CH) {
+#pragma unroll
+        for (int q = 0; q < RB; ++q) asm volatile("" ::"v"(ar[q]), "v"(ai[q]));
+        asm volatile("" : "+v"(cl.self), "+v"(cl.pc), "+v"(cl.f[0]), "+v"(cl.f[1]), "+v"(cl.f[2]), "+v"(lh));
+        T cr[CH], ci[CH], vr[CH][RB], vi[CH][RB];
+#pragma unroll
+        for (int jj = 0; jj < CH; ++jj) {
+            const int j = h + jj;
+            if (j < NT) {
+                cr[jj] = cR.ld(lh, j * ls);
+                ci[jj] = j < NF ? cI.ld(lh, j * ls) : T(0);
+                const uint32_t o = (uint32_t)col3(cl, j) * (uint32_t)sizeof(T);
+#pragma unroll
+                for (int q = 0; q < RB; ++q) {
+                    vr[jj][q] = eb[q].ld(o, 0);
+                    vi[jj][q] = eb[q].ld(o, nb);
+                }
+            }
+        }
+#pragma unroll
+        for (int jj = 0; jj < CH; ++jj) {
+            if (h + jj < NT) {
+#pragma unroll
+                for (int q = 0; q < RB; ++q) {
+                    ar[q] += cr[jj] * vr[jj][q] - ci[jj] * vi[jj][q];
+                    ai[q] += cr[jj] * vi[jj][q] + ci[jj] * vr[jj][q];
+                }
+            }
+        }
+    }
+}
+
+// Half-sweep over stored rows on a 3D Galerkin level: eight lanes per cell as in
+// k_relax (lane 8 j + cell holds row j: low/high face of u_0, u_1, u_2, then the
+// pressure; lane 7 carries the other cell's pressure), blocks renumbered per XCD.
+template <typename T, int RB, int CH>
+__global__ __launch_bounds__(256) void k_relax_st3d(Geo g, int colour, T w, int econ, const T* __restrict__ b,
+                                                    const T* __restrict__ ein, T* __restrict__ eout, int nrhs,
+                                                    int64_t stride, int rpb, const T* __restrict__ cre,
+                                                    const T* __restrict__ cim, int64_t lanes) {
+    constexpr int D = 3, R = 2 * D + 1, NF = St<3>::NF, NT = NF + St<3>::NUP;
+    constexpr int T_SELF = St<3>::CF, T_NHI = St<3>::CF + 1, T_PLO = NF + 8, T_PHI = NF + 9;
+    {
+        const int rb0 = blockIdx.y * rpb;
+        b += rb0 * stride;
+        if (ein) ein += rb0 * stride;
+        eout += rb0 * stride;
+        nrhs = nrhs - rb0 < rpb ? nrhs - rb0 : rpb;
+    }
+    const int hp = g.n[0] >> 1;
+    const int npair = hp * g.n[1] * g.n[2];
+    const int lane = threadIdx.x & 63;
+    const int row = lane >> 3;
+    const int cig = lane & 7;
+    const int64_t gl = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int t = (int)(gl >> 6) * 8 + cig;
+    const int base = cig;
+    const bool live = t < npair;
+    const int tt = live ? t : 0;
+    const int px = tt % hp;
+    const int rest = tt / hp;
+    const int yy = rest % g.n[1], zz = rest / g.n[1];
+    const int par = (colour + yy + zz) & 1;
+    const int k = row < 2 * D ? (row >> 1) : 3;
+    int p[3] = {2 * px + par, yy, zz};
+    bool ok = live && row < R;
+    if (k < 3) {
+        p[k] += row & 1;
+        ok = ok && p[k] >= 1 && p[k] <= g.n[k] - 1;
+    }
+    const Cols3 cc = cols3(g, k, p);
+    const int idx = cc.self;
+    const bool carry = live && row == R;
+    const int ipb = (int)g.off[3] + (zz * g.n[1] + yy) * g.n[0] + 2 * px + 1 - par;
+    const Buf<T> cR(cre, (uint32_t)(NT * lanes * sizeof(T))), cI(cim, (uint32_t)(NF * lanes * sizeof(T)));
+    const uint32_t lo = (uint32_t)gl * (uint32_t)sizeof(T), ls = (uint32_t)lanes * (uint32_t)sizeof(T);
+    const uint32_t vb = 2 * (uint32_t)g.N * (uint32_t)sizeof(T), nb = (uint32_t)g.N * (uint32_t)sizeof(T);
+    // this row's block entries (the diagonal sits at T_SELF in a u row, at term 0
+    // in the pressure row), then the block factorisation, once for the batch
+    const bool lowrow = row < 2 * D && (row & 1) == 0;
+    T dre = T(1), dim = T(0), ore = T(0), oim = T(0), gg = T(0);
+    if (ok) {
+        const uint32_t js = (uint32_t)(k == 3 ? 0 : T_SELF) * ls;
+        dre = cR.ld(lo + js);
+        if (k < 3) {
+            dim = cI.ld(lo + js);
+            gg = cR.ld(lo + (uint32_t)(lowrow ? T_PHI : T_PLO) * ls);
+            if (lowrow && !econ) {
+                ore = cR.ld(lo + (uint32_t)T_NHI * ls);
+                oim = cI.ld(lo + (uint32_t)T_NHI * ls);
+            }
+        }
+    }
+    VankaBlock<D, T> V;
+    V.factor(dre, dim, ore, oim, gg, base, row);
+
+    for (int r0 = 0; r0 < nrhs; r0 += RB) {
+        T ar[RB], ai[RB];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) ar[q] = ai[q] = T(0);
+        if (ein && row < R) {
+            const T* ev[RB];
+#pragma unroll
+            for (int q = 0; q < RB; ++q) ev[q] = ein + (r0 + q < nrhs ? r0 + q : r0) * stride;
+            rows3_rb<T, RB, CH>(cR, cI, lo, ls, cc, ev, vb, nb, ar, ai);
+        }
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const int r = r0 + q;
+            if (r >= nrhs) break;
+            cx<T> res = mk<T>(T(0), T(0)), eown = mk<T>(T(0), T(0));
+            if (ok) {
+                res = CVec<T>{b + r * stride, g.N}.ld(idx) - mk<T>(ar[q], ai[q]);
+                if (ein) eown = CVec<T>{ein + r * stride, g.N}.ld(idx);
+            }
+            const cx<T> mine = V.solve(res, base, row);
+            const Vec<T> ov{eout + r * stride, g.N};
+            if (ok) ov.st(idx, eown + w * mine);
+            if (carry) ov.st(ipb, ein ? CVec<T>{ein + r * stride, g.N}.ld(ipb) : mk<T>(T(0), T(0)));
+        }
+    }
+}
+
+// y = A x or r = b - A x over stored rows on a 3D Galerkin level (term j of row t
+// at [j * N + t]).
+template <typename T, int RB, int CH>
+__global__ __launch_bounds__(256) void k_apply_st3d(Geo g, const T* __restrict__ x, const T* __restrict__ b,
+                                                    T* __restrict__ y, int nrhs, int64_t stride, int rpb,
+                                                    const T* __restrict__ cre, const T* __restrict__ cim) {
+    constexpr int NF = St<3>::NF, NT = NF + St<3>::NUP;
+    {
+        const int rb0 = blockIdx.y * rpb;
+        x += rb0 * stride;
+        if (b) b += rb0 * stride;
+        y += rb0 * stride;
+        nrhs = nrhs - rb0 < rpb ? nrhs - rb0 : rpb;
+    }
+    const int N = (int)g.N;
+    const int t = (int)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (t >= N) return;
+    int k = 0;
+    while (k < 3 && t >= g.off[k + 1]) ++k;
+    const int li = t - (int)g.off[k];
+    const int d0 = g.n[0] - (k == 0), d1 = g.n[1] - (k == 1);
+    int p[3] = {li % d0, (li / d0) % d1, li / (d0 * d1)};
+    if (k < 3) p[k] += 1;
+    const Cols3 cc = cols3(g, k, p);
+    const Buf<T> cR(cre, (uint32_t)(NT * N * sizeof(T))), cI(cim, (uint32_t)(NF * N * sizeof(T)));
+    const uint32_t lo = (uint32_t)t * (uint32_t)sizeof(T), ls = (uint32_t)N * (uint32_t)sizeof(T);
+    const uint32_t vb = 2 * ls;
+    for (int r0 = 0; r0 < nrhs; r0 += RB) {
+        const T* xv[RB];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) xv[q] = x + (r0 + q < nrhs ? r0 + q : r0) * stride;
+        T ar[RB], ai[RB];
+        rows3_rb<T, RB, CH>(cR, cI, lo, ls, cc, xv, vb, ls, ar, ai);
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const int r = r0 + q;
+            if (r >= nrhs) break;
+            cx<T> o = mk<T>(ar[q], ai[q]);
+            if (b) o = CVec<T>{b + r * stride, g.N}.ld(t) - o;
+            Vec<T>{y + r * stride, g.N}.st(t, o);
+        }
+    }
+}
+
+// Builders of the 3D stored rows: coefficient of term j of the u_k row at face
+// p (k < 3) or of the pressure row at cell p (k == 3), in the order of
+// StOp::plan_u / plan_p, zero for terms outside the grid.
+template <typename T>
+EHH_DEV void term3(const StOp<3, T>& op, int k, const int* p, int j, T& re, T& im) {
+    constexpr int D = 3, NF = St<3>::NF, NUP = St<3>::NUP, CF = St<3>::CF;
+    const Geo& g = op.g;
+    re = im = T(0);
+    if (k < 3) {
+        const int t1 = tang1<D>(k), t2 = tang2<D>(k);
+        const int64_t fi = face_idx<D>(g, k, p);
+        if (j < NF) {
+            int dn, d1, d2;
+            full_offset<D>(j, dn, d1, d2);
+            int q[3] = {p[0], p[1], p[2]};
+            q[k] += dn;
+            q[t1] += d1;
+            q[t2] += d2;
+            if (!face_ok<D>(g, k, q)) return;
+            const cx<T> a = j >= CF ? op.uu(k, fi, j - CF) : op.uu(k, face_idx<D>(g, k, q), CF - j);
+            re = a.re;
+            im = a.im;
+        } else {
+            int side, e1, e2;
+            up_decode<D>(j - NF, side, e1, e2);
+            int q[3] = {p[0], p[1], p[2]};
+            q[k] += side - 1;
+            q[t1] += e1;
+            q[t2] += e2;
+            if (!cell_ok<D>(g, q)) return;
+            re = op.up(k, fi, j - NF);
+        }
+    } else {
+        if (j == 0) {
+            re = op.c.pp[cell_idx<D>(g, p)];
+            return;
+        }
+        if (j > 3 * NUP) return;
+        const int kk = (j - 1) / NUP, qq = (j - 1) % NUP;
+        const int t1 = tang1<D>(kk), t2 = tang2<D>(kk);
+        int side, e1, e2;
+        up_decode<D>(qq, side, e1, e2);
+        int q[3] = {p[0], p[1], p[2]};
+        q[kk] += 1 - side;
+        q[t1] -= e1;
+        q[t2] -= e2;
+        if (!face_ok<D>(g, kk, q)) return;
+        re = op.up(kk, face_idx<D>(g, kk, q), qq);
+    }
+}
+
+// one thread per (lane, term): the lane order of k_relax_st3d
+template <typename T>
+__global__ __launch_bounds__(256) void k_build_rows3d(StOp<3, T> op, int colour, T* __restrict__ re,
+                                                      T* __restrict__ im, int64_t lanes) {
+    constexpr int D = 3, R = 2 * D + 1, NF = St<3>::NF, NT = NF + St<3>::NUP;
+    const Geo& g = op.g;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= lanes * NT) return;
+    const int j = (int)(e / lanes);
+    const int64_t gl = e % lanes;
+    const int hp = g.n[0] >> 1;
+    const int64_t npair = (int64_t)hp * g.n[1] * g.n[2];
+    const int lane = (int)(gl & 63), row = lane >> 3, cig = lane & 7;
+    const int64_t t = (gl >> 6) * 8 + cig;
+    const bool live = t < npair;
+    const int64_t tt = live ? t : 0;
+    const int px = (int)(tt % hp);
+    const int64_t rest = tt / hp;
+    const int yy = (int)(rest % g.n[1]), zz = (int)(rest / g.n[1]);
+    const int par = (colour + yy + zz) & 1;
+    const int k = row < 2 * D ? (row >> 1) : 3;
+    int p[3] = {2 * px + par, yy, zz};
+    bool ok = live && row < R;
+    if (k < 3) {
+        p[k] += row & 1;
+        ok = ok && p[k] >= 1 && p[k] <= g.n[k] - 1;
+    }
+    T a = T(0), bi = T(0);
+    if (ok) term3<T>(op, k, p, j, a, bi);
+    re[e] = a;
+    if (j < NF) im[e] = bi;
+}
+
+// one thread per (row, term): row order for k_apply_st3d
+template <typename T>
+__global__ __launch_bounds__(256) void k_build_row_rows3d(StOp<3, T> op, T* __restrict__ re, T* __restrict__ im) {
+    constexpr int NF = St<3>::NF, NT = NF + St<3>::NUP;
+    const Geo& g = op.g;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= g.N * NT) return;
+    const int j = (int)(e / g.N);
+    const int64_t t = e % g.N;
+    int k = 0;
+    while (k < 3 && t >= g.off[k + 1]) ++k;
+    const int64_t li = t - g.off[k];
+    int p[3];
+    if (k == 3) cell_pos<3>(g, li, p);
+    else face_pos<3>(g, k, li, p);
+    T a, bi;
+    term3<T>(op, k, p, j, a, bi);
+    re[e] = a;
+    if (j < NF) im[e] = bi;
 }
 
 // ------------------------------------------- one thread per cell (2D finest level)
@@ -1912,6 +2276,7 @@ template <typename T> static inline int rhs_block_3d_stencil() {
     return v == 1 || v == 2 || v == 4 ? v : 2;
 }
 
+
 #define EHH_RB_DISPATCH(RBV, CALL) \
     do {                           \
         if ((RBV) == 1) {          \
@@ -1961,7 +2326,17 @@ hipError_t launch_apply(const LevelDesc<T>& L, const T* x, const T* b, T* y, int
     } else {
         if (L.fine)
             EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_apply_plan<3, T, FineOp<3, T>, RB>), gb, 256, 0, s, FineOp<3, T>{L.g, L.f}, x, b, y, nrhs, stride, rpb));
-        else
+        else if (L.sp.rre) {
+#define EHH_APPLY_ST3D(RB, CH)                                                                                   \
+    {                                                                                                            \
+        const int rpbs = rhs_per_block((L.g.N + 63) / 64, nrhs, RB);                                             \
+        hipLaunchKernelGGL((k_apply_st3d<T, RB, CH>), dim3(nblk(L.g.N), (nrhs + rpbs - 1) / rpbs), 256, 0, s, L.g, \
+                           x, b, y, nrhs, stride, rpbs, L.sp.rre, L.sp.rim);                                     \
+    }
+            if (sizeof(T) == 8) EHH_APPLY_ST3D(2, 4)
+            else EHH_APPLY_ST3D(8, 4)
+#undef EHH_APPLY_ST3D
+        } else
             EHH_RB_DISPATCH(rb3, hipLaunchKernelGGL((k_apply<3, T, StOp<3, T>, RB>), gb3, 256, 0, s, StOp<3, T>{L.g, L.s}, x, b, y, nrhs, stride, rpb3));
     }
     return hipGetLastError();
@@ -2016,7 +2391,21 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
     } else {
         if (L.fine)
             EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_relax_plan<3, T, FineOp<3, T>, RB>), gb, 256, 0, s, FineOp<3, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb));
-        else
+        else if (L.sp.re[colour]) {
+#define EHH_RELAX_ST3D(RB, CH)                                                                                    \
+    {                                                                                                             \
+        const int rpbs = rhs_per_block((npair * 8 + 63) / 64, nrhs, RB);                                          \
+        hipLaunchKernelGGL((k_relax_st3d<T, RB, CH>), dim3(nblk(npair * 8), (nrhs + rpbs - 1) / rpbs), 256, 0, s, \
+                           L.g, colour, tw, econ, b, ein, eout, nrhs, stride, rpbs, L.sp.re[colour],              \
+                           L.sp.im[colour], L.sp.lanes);                                                          \
+    }
+            // measured on MI355X (36^3 level, 16 FP32 sources): 8 sources per
+            // coefficient load in chunks of 4 terms 331 us; 8 x 2: 335 us,
+            // 4 x 4: 358 us, 16 x 2: 322 us but 2x slower on 18^3
+            if (sizeof(T) == 8) EHH_RELAX_ST3D(2, 4)
+            else EHH_RELAX_ST3D(8, 4)
+#undef EHH_RELAX_ST3D
+        } else
             EHH_RB_DISPATCH(rb3, hipLaunchKernelGGL((k_relax<3, T, StOp<3, T>, RB>), gb3, 256, 0, s, StOp<3, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb3));
     }
     return hipGetLastError();
@@ -2026,23 +2415,35 @@ int64_t stored_plan_lanes(const Geo& g) {
     const int64_t npair = (int64_t)(g.n[0] / 2) * g.n[1] * g.n[2];
     return (int64_t)nblk(npair * 8) * 256;
 }
-// Every 2D Galerkin level keeps its row plans (the large ones use them for
-// small batches, see launch_relax).
+// Every Galerkin level keeps its rows (the large 2D ones use them for small
+// batches, see launch_relax).
 bool stored_plan_wanted(const Geo& g, bool fine) {
     static const bool on = env_int("EHH_SPLAN", 1) != 0;
+    static const bool on3 = env_int("EHH_SPLAN3D", 1) != 0;
     // the kernels address the stored rows and the vectors with 32-bit byte offsets
-    constexpr int64_t NT = St<2>::NF + St<2>::NUP, lim = int64_t(1) << 32;
-    return on && g.dim == 2 && !fine && NT * stored_plan_lanes(g) * 8 < lim && NT * g.N * 8 < lim && 16 * g.N < lim;
+    const int64_t NT = g.dim == 2 ? St<2>::NF + St<2>::NUP : St<3>::NF + St<3>::NUP, lim = int64_t(1) << 32;
+    return on && (g.dim == 2 || on3) && !fine && NT * stored_plan_lanes(g) * 8 < lim && NT * g.N * 8 < lim &&
+           16 * g.N < lim;
 }
+int stored_terms(int dim) { return dim == 2 ? St<2>::NF + St<2>::NUP : St<3>::NF + St<3>::NUP; }
+int stored_imag_terms(int dim) { return dim == 2 ? St<2>::NF : St<3>::NF; }
 template <typename T>
 hipError_t launch_build_plans(const LevelDesc<T>& L, int colour, T* re, T* im, hipStream_t s) {
     const int64_t lanes = stored_plan_lanes(L.g);
-    hipLaunchKernelGGL((k_build_plans<T>), nblk(lanes), 256, 0, s, StOp<2, T>{L.g, L.s}, colour, re, im, lanes);
+    if (L.g.dim == 2)
+        hipLaunchKernelGGL((k_build_plans<T>), nblk(lanes), 256, 0, s, StOp<2, T>{L.g, L.s}, colour, re, im, lanes);
+    else
+        hipLaunchKernelGGL((k_build_rows3d<T>), nblk(lanes * stored_terms(3)), 256, 0, s, StOp<3, T>{L.g, L.s},
+                           colour, re, im, lanes);
     return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_build_row_plans(const LevelDesc<T>& L, T* re, T* im, hipStream_t s) {
-    hipLaunchKernelGGL((k_build_row_plans<T>), nblk(L.g.N), 256, 0, s, StOp<2, T>{L.g, L.s}, re, im);
+    if (L.g.dim == 2)
+        hipLaunchKernelGGL((k_build_row_plans<T>), nblk(L.g.N), 256, 0, s, StOp<2, T>{L.g, L.s}, re, im);
+    else
+        hipLaunchKernelGGL((k_build_row_rows3d<T>), nblk(L.g.N * stored_terms(3)), 256, 0, s, StOp<3, T>{L.g, L.s},
+                           re, im);
     return hipGetLastError();
 }
 template hipError_t launch_build_row_plans<float>(const LevelDesc<float>&, float*, float*, hipStream_t);
