@@ -2227,6 +2227,158 @@ __global__ __launch_bounds__(256) void k_prolong2d(Geo gf, Geo gc, const T* __re
     ef[Nf + t] = si;
 }
 
+// 3D transfers in the same style: positions along the normal and the two
+// tangential axes of the row's component, strides chosen by selects, all loads
+// issued before the sums (term order of k_restrict / k_prolong).
+struct FaceAxes3 {
+    int n, t1, t2;        // position along normal, t1, t2
+    int sn, st1, st2;     // strides of the component's face grid along them
+    int dn, dt1, dt2;     // cells along normal, t1, t2
+};
+EHH_DEV inline FaceAxes3 face_axes3(int k, const int* p, int nx, int ny, int nz) {
+    FaceAxes3 a;
+    const int d0 = nx - (k == 0), d1 = ny - (k == 1);
+    a.n = k == 0 ? p[0] : (k == 1 ? p[1] : p[2]);
+    a.t1 = k == 0 ? p[1] : p[0];
+    a.t2 = k == 2 ? p[1] : p[2];
+    a.sn = k == 0 ? 1 : (k == 1 ? d0 : d0 * d1);
+    a.st1 = k == 0 ? d0 : 1;
+    a.st2 = k == 2 ? d0 : d0 * d1;
+    a.dn = k == 0 ? nx : (k == 1 ? ny : nz);
+    a.dt1 = k == 0 ? ny : nx;
+    a.dt2 = k == 2 ? ny : nz;
+    return a;
+}
+// decode a face (k < 3) or cell (k == 3) index into its position
+EHH_DEV inline void pos3(int k, int li, int nx, int ny, int* p) {
+    const int d0 = nx - (k == 0), d1 = ny - (k == 1);
+    p[0] = li % d0;
+    p[1] = (li / d0) % d1;
+    p[2] = li / (d0 * d1);
+    if (k == 0) p[0] += 1;
+    if (k == 1) p[1] += 1;
+    if (k == 2) p[2] += 1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict3d(Geo gf, Geo gc, const T* __restrict__ rf, T* __restrict__ rc) {
+    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int Nc = (int)gc.N, Nf = (int)gf.N;
+    if (t >= Nc) return;
+    rf += (int64_t)blockIdx.y * 2 * gf.N;
+    rc += (int64_t)blockIdx.y * 2 * gc.N;
+    const int fx = gf.n[0], fy = gf.n[1], fz = gf.n[2];
+    int k = 0;
+    while (k < 3 && t >= (int)gc.off[k + 1]) ++k;
+    const int li = t - (int)gc.off[k];
+    int P[3];
+    pos3(k, li, gc.n[0], gc.n[1], P);
+    T sr = T(0), si = T(0);
+    if (k == 3) {   // pressure: the eight fine cells
+        const int b = (int)gf.off[3] + ((2 * P[2]) * fy + 2 * P[1]) * fx + 2 * P[0];
+        T vr[8], vi[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int ix = b + ((j >> 2) * fy + ((j >> 1) & 1)) * fx + (j & 1);
+            vr[j] = rf[ix];
+            vi[j] = rf[Nf + ix];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            sr += vr[j];
+            si += vi[j];
+        }
+    } else {
+        // fine face grid of component k, addressed from the coarse position
+        const int Pf[3] = {2 * P[0], 2 * P[1], 2 * P[2]};
+        const FaceAxes3 A = face_axes3(k, Pf, fx, fy, fz);
+        const int base = (int)gf.off[k] + (A.n - 1) * A.sn + A.t1 * A.st1 + A.t2 * A.st2;
+        T vr[48], vi[48], wt[48];
+#pragma unroll
+        for (int a = -1; a <= 1; ++a)
+#pragma unroll
+            for (int b1 = -1; b1 <= 2; ++b1)
+#pragma unroll
+                for (int b2 = -1; b2 <= 2; ++b2) {
+                    const int j = ((a + 1) * 4 + b1 + 1) * 4 + b2 + 1;
+                    const int f1 = A.t1 + b1, f2 = A.t2 + b2;
+                    const bool ok = f1 >= 0 && f1 < A.dt1 && f2 >= 0 && f2 < A.dt2;
+                    const int c1 = f1 < 0 ? 0 : (f1 >= A.dt1 ? A.dt1 - 1 : f1);
+                    const int c2 = f2 < 0 ? 0 : (f2 >= A.dt2 ? A.dt2 - 1 : f2);
+                    const int ix = base + a * A.sn + (c1 - A.t1) * A.st1 + (c2 - A.t2) * A.st2;
+                    wt[j] = ok ? (a == 0 ? T(1) : T(0.5)) * T(w_tang(b1)) * T(w_tang(b2)) : T(0);
+                    vr[j] = rf[ix];
+                    vi[j] = rf[Nf + ix];
+                }
+#pragma unroll
+        for (int j = 0; j < 48; ++j) {
+            sr += wt[j] * vr[j];
+            si += wt[j] * vi[j];
+        }
+    }
+    rc[t] = sr;
+    rc[Nc + t] = si;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong3d(Geo gf, Geo gc, const T* __restrict__ ec, T* __restrict__ ef) {
+    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int Nc = (int)gc.N, Nf = (int)gf.N;
+    if (t >= Nf) return;
+    ec += (int64_t)blockIdx.y * 2 * gc.N;
+    ef += (int64_t)blockIdx.y * 2 * gf.N;
+    const int cx_ = gc.n[0], cy = gc.n[1], cz = gc.n[2];
+    int k = 0;
+    while (k < 3 && t >= (int)gf.off[k + 1]) ++k;
+    const int li = t - (int)gf.off[k];
+    int p[3];
+    pos3(k, li, gf.n[0], gf.n[1], p);
+    if (k == 3) {   // pressure: piecewise constant
+        const int ci = (int)gc.off[3] + ((p[2] >> 1) * cy + (p[1] >> 1)) * cx_ + (p[0] >> 1);
+        const T cr = ec[ci], cim = ec[Nc + ci];
+        const T fr = ef[t], fi = ef[Nf + t];
+        ef[t] = fr + cr;
+        ef[Nf + t] = fi + cim;
+        return;
+    }
+    const FaceAxes3 F = face_axes3(k, p, gf.n[0], gf.n[1], gf.n[2]);
+    int pc[3] = {0, 0, 0};
+    const FaceAxes3 C = face_axes3(k, pc, cx_, cy, cz);   // coarse strides and sizes
+    // normal: the coincident coarse face (weight 1) or the two around it (1/2 each)
+    const int xn0 = (F.n & 1) ? (F.n - 1) >> 1 : F.n >> 1, xn1 = (F.n + 1) >> 1;
+    const T wn0 = (F.n & 1) ? T(0.5) : T(1), wn1 = (F.n & 1) ? T(0.5) : T(0);
+    // tangential: the nearer coarse row (3/4) and the other one (1/4) inside the grid
+    const int C1 = F.t1 >> 1, o1 = (F.t1 & 1) ? C1 + 1 : C1 - 1;
+    const int C2 = F.t2 >> 1, o2 = (F.t2 & 1) ? C2 + 1 : C2 - 1;
+    const bool ok1 = o1 >= 0 && o1 < C.dt1, ok2 = o2 >= 0 && o2 < C.dt2;
+    const int xs[2] = {xn0, xn1}, y1s[2] = {C1, ok1 ? o1 : C1}, y2s[2] = {C2, ok2 ? o2 : C2};
+    const T wns[2] = {wn0, wn1}, w1s[2] = {T(0.75), ok1 ? T(0.25) : T(0)}, w2s[2] = {T(0.75), ok2 ? T(0.25) : T(0)};
+    T vr[8], vi[8], wt[8];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int i1 = 0; i1 < 2; ++i1)
+#pragma unroll
+            for (int i2 = 0; i2 < 2; ++i2) {
+                const int j = (a * 2 + i1) * 2 + i2;
+                const int X = xs[a];
+                const bool ok = X >= 1 && X <= C.dn - 1;
+                const int Xc = ok ? X : 1;
+                const int ix = (int)gc.off[k] + (Xc - 1) * C.sn + y1s[i1] * C.st1 + y2s[i2] * C.st2;
+                wt[j] = ok ? wns[a] * w1s[i1] * w2s[i2] : T(0);
+                vr[j] = ec[ix];
+                vi[j] = ec[Nc + ix];
+            }
+    T sr = ef[t], si = ef[Nf + t];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        sr += wt[j] * vr[j];
+        si += wt[j] * vi[j];
+    }
+    ef[t] = sr;
+    ef[Nf + t] = si;
+}
+
 // ------------------------------------------------------------------------ launchers
 static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
@@ -2263,7 +2415,7 @@ static inline bool cell3d_enabled() {
     static const bool v = env_int("EHH_CELL3D", 1) != 0;
     return v;
 }
-static inline bool transfer2d_enabled() {
+static inline bool transfer2d_enabled() {   // the 32-bit transfer kernels (2D and 3D)
     static const bool v = env_int("EHH_TRANSFER2D", 1) != 0;
     return v;
 }
@@ -2457,6 +2609,8 @@ hipError_t launch_restrict(const Geo& gf, const Geo& gc, const T* rf, T* rc, int
         hipLaunchKernelGGL((k_restrict2d<T>), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc);
     else if (gf.dim == 2)
         hipLaunchKernelGGL((k_restrict<2, T>), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc, nrhs);
+    else if (transfer2d_enabled() && 2 * gf.N < (int64_t(1) << 31))
+        hipLaunchKernelGGL((k_restrict3d<T>), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc);
     else
         hipLaunchKernelGGL((k_restrict<3, T>), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc, nrhs);
     return hipGetLastError();
@@ -2468,6 +2622,8 @@ hipError_t launch_prolong(const Geo& gf, const Geo& gc, const T* ec, T* ef, int 
         hipLaunchKernelGGL((k_prolong2d<T>), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef);
     else if (gf.dim == 2)
         hipLaunchKernelGGL((k_prolong<2, T>), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef, nrhs);
+    else if (transfer2d_enabled() && 2 * gf.N < (int64_t(1) << 31))
+        hipLaunchKernelGGL((k_prolong3d<T>), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef);
     else
         hipLaunchKernelGGL((k_prolong<3, T>), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef, nrhs);
     return hipGetLastError();
