@@ -128,7 +128,7 @@ def relax_kernel_name(w, level, ncell):
             return f"k_relax_cell2d<{t}>"
         if ncell >= 65536 and len(w.sources()) > 8:
             return f"k_relax_lds2d<{t}, StOp<2, {t}>>"
-        return f"k_relax_st2d<{t}, {'true' if t == 'float' else 'false'}>"
+        return f"k_relax_st2d<{t}, {'true' if t == 'float' else 'false'}, false>"
     if level == 0:
         return f"k_relax_cell3d<{t}>"
     return f"k_relax_st3d<{t}, 8, 4>" if t == "float" else f"k_relax_st3d<{t}, 2, 4>"

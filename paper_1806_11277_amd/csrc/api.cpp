@@ -293,7 +293,10 @@ int32_t ensure_krylov(ehh_ctx* c, int nrhs) {
 
 // ------------------------------------------------------------------- the cycle
 template <typename T>
-int32_t cycle(ehh_ctx* c, Sub& S, int l, const T* b, T* e, bool zero_init, int nrhs, hipStream_t s) {
+int32_t cycle(ehh_ctx* c, Sub& S, int l, const T* b, T* e, bool zero_init, int nrhs, hipStream_t s,
+              const T* rsrc = nullptr, const Geo* gsrc = nullptr) {
+    // rsrc: the finer level's residual (grid gsrc) when b = P^T rsrc is still to be
+    // formed; the first half-sweep then forms and writes it (zero_init, nu1 >= 1)
     Level& L = S.lev[l];
     const int nl = (int)S.lev.size();
     if (l == nl - 1) {
@@ -305,22 +308,32 @@ int32_t cycle(ehh_ctx* c, Sub& S, int l, const T* b, T* e, bool zero_init, int n
     T* t = (T*)L.t;
     bool have = !zero_init;
     for (int it = 0; it < c->opt.nu1; ++it) {
-        HIPCHK(launch_relax<T>(D, 0, L.damping, econ, b, have ? e : nullptr, t, nrhs, s));
+        if (it == 0 && rsrc)
+            HIPCHK(launch_relax_restrict<T>(D, L.damping, econ, *gsrc, rsrc, (T*)b, t, nrhs, s));
+        else
+            HIPCHK(launch_relax<T>(D, 0, L.damping, econ, b, have ? e : nullptr, t, nrhs, s));
         HIPCHK(launch_relax<T>(D, 1, L.damping, econ, b, t, e, nrhs, s));
         have = true;
     }
     Level& C = S.lev[l + 1];
+    // the restriction to a coarser level that is not the coarsest is fused into
+    // that level's first half-sweep where its kernels allow it
+    const bool fuse = l + 1 < nl - 1 && c->opt.nu1 >= 1 &&
+                      relax_restrict_supported<T>(level_desc<T>(c, C, c->prob.shift), nrhs);
     if (have) {
         HIPCHK(launch_apply<T>(D, e, b, t, nrhs, s));   // t = b - A e
-        HIPCHK(launch_restrict<T>(L.g, C.g, t, (T*)C.b, nrhs, s));
+        if (!fuse) HIPCHK(launch_restrict<T>(L.g, C.g, t, (T*)C.b, nrhs, s));
     } else {
         HIPCHK(launch_zero(e, sizeof(T) * 2 * (size_t)L.g.N * nrhs, s));
-        HIPCHK(launch_restrict<T>(L.g, C.g, b, (T*)C.b, nrhs, s));
+        if (!fuse) HIPCHK(launch_restrict<T>(L.g, C.g, b, (T*)C.b, nrhs, s));
     }
+    const T* rfine = have ? (const T*)t : b;
     // gamma_c recursive calls (V: 1, W: 2); the coarsest solve is exact, so a second
     // call there with the same right-hand side would repeat the same result.
     const int ncall = (l + 1 == nl - 1 || l < c->opt.cycle_level) ? 1 : c->opt.cycle;
-    for (int k = 0; k < ncall; ++k) CHK(cycle<T>(c, S, l + 1, (const T*)C.b, (T*)C.e, k == 0, nrhs, s));
+    for (int k = 0; k < ncall; ++k)
+        CHK(cycle<T>(c, S, l + 1, (const T*)C.b, (T*)C.e, k == 0, nrhs, s, (k == 0 && fuse) ? rfine : nullptr,
+                     &L.g));
     HIPCHK(launch_prolong<T>(L.g, C.g, (const T*)C.e, e, nrhs, s));
     for (int it = 0; it < c->opt.nu2; ++it) {
         HIPCHK(launch_relax<T>(D, 0, L.damping, econ, b, e, t, nrhs, s));

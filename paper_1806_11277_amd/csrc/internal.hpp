@@ -36,6 +36,13 @@ hipError_t launch_apply(const LevelDesc<T>& L, const T* x, const T* b, T* y, int
 template <typename T>
 hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, const T* b, const T* ein,
                         T* eout, int nrhs, hipStream_t s);
+// First half-sweep (colour 0) of a visit from zero with the restriction fused:
+// b = P^T rf (rf on the finer grid gf) is formed, written to b, and relaxed.
+template <typename T>
+bool relax_restrict_supported(const LevelDesc<T>& L, int nrhs);
+template <typename T>
+hipError_t launch_relax_restrict(const LevelDesc<T>& L, double w, int econ, const Geo& gf, const T* rf, T* b,
+                                 T* eout, int nrhs, hipStream_t s);
 // Lanes (padded) of one colour's stored plans on a level, and the builder.
 int64_t stored_plan_lanes(const Geo& g);
 bool stored_plan_wanted(const Geo& g, bool fine);

@@ -452,6 +452,64 @@ __global__ __launch_bounds__(256) void k_relax_plan(Op op, int colour, T w, int 
     }
 }
 
+// Staggered bilinear transfer weights along a tangential axis: 3/4 for the two
+// fine rows nearer the coarse row, 1/4 for the next ones, zero beyond.
+EHH_DEV float w_tang(int d) { return (d == 0 || d == 1) ? 0.75f : ((d == -1 || d == 2) ? 0.25f : 0.f); }
+
+// (P^T r_f) at the coarse 2D unknown of component k (0, 1, or 3 for the
+// pressure) at position (X, Y): twelve fine faces (weights 1 or 1/2 along the
+// normal, 3/4 or 1/4 along the tangential axis) or the four fine cells; every
+// load is issued before the sum, terms outside the grid read a clamped index
+// with weight zero.  rf: one right-hand side's fine vector (real plane, then
+// imaginary plane).
+template <typename T>
+EHH_DEV cx<T> restrict_at2d(const Geo& gf, const T* __restrict__ rf, int k, int X, int Y) {
+    const int Nf = (int)gf.N, nfx = gf.n[0], nfy = gf.n[1];
+    T sr = T(0), si = T(0);
+    if (k == 3) {
+        const int b = (int)gf.off[3] + 2 * Y * nfx + 2 * X;
+        const int ix[4] = {b, b + 1, b + nfx, b + nfx + 1};
+        T vr[4], vi[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            vr[j] = rf[ix[j]];
+            vi[j] = rf[Nf + ix[j]];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            sr += vr[j];
+            si += vi[j];
+        }
+        return mk<T>(sr, si);
+    }
+    const bool k0 = k == 0;
+    int ix[12];
+    T wt[12];
+#pragma unroll
+    for (int a = -1; a <= 1; ++a)
+#pragma unroll
+        for (int b1 = -1; b1 <= 2; ++b1) {
+            const int j = (a + 1) * 4 + b1 + 1;
+            const int fn = 2 * (k0 ? X : Y) + a, ft = 2 * (k0 ? Y : X) + b1, nt = k0 ? nfy : nfx;
+            const bool ok = ft >= 0 && ft < nt;
+            const int fc = ft < 0 ? 0 : (ft >= nt ? nt - 1 : ft);
+            ix[j] = k0 ? (int)gf.off[0] + fc * (nfx - 1) + fn - 1 : (int)gf.off[1] + (fn - 1) * nfx + fc;
+            wt[j] = ok ? (a == 0 ? T(1) : T(0.5)) * T(w_tang(b1)) : T(0);
+        }
+    T vr[12], vi[12];
+#pragma unroll
+    for (int j = 0; j < 12; ++j) {
+        vr[j] = rf[ix[j]];
+        vi[j] = rf[Nf + ix[j]];
+    }
+#pragma unroll
+    for (int j = 0; j < 12; ++j) {
+        sr += wt[j] * vr[j];
+        si += wt[j] * vi[j];
+    }
+    return mk<T>(sr, si);
+}
+
 // ------------------------------------ stored Galerkin rows with computed columns (2D)
 // The 2D Galerkin levels keep their rows' coefficients, built once at setup, in
 // the order the kernels read them: term j of lane (or row) i at [j * lanes + i],
@@ -529,18 +587,29 @@ EHH_DEV inline int col2(const Cols2& c, int j) {
 // SIMD on a 256^2 level, and one batch of all 21 terms at 1 per SIMD even on the
 // 128^2 and 64^2 levels, where no SIMD holds more than one wavefront), and the
 // block is re-factorised per right-hand side.
-template <typename T, bool KEEP>
+//
+// RST (first half-sweep of a visit, from zero): the right-hand side is formed
+// here as P^T of the finer level's residual rf (geometry gf) and written to bw,
+// one unknown per lane (the carry lane forms the other cell's pressure), which
+// saves the restriction's own launch.
+template <typename T, bool KEEP, bool RST>
 __global__ __launch_bounds__(256) void k_relax_st2d(Geo g, int colour, T w, int econ, const T* __restrict__ b,
                                                     const T* __restrict__ ein, T* __restrict__ eout, int nrhs,
                                                     int64_t stride, int rpb, const T* __restrict__ cre,
-                                                    const T* __restrict__ cim, int64_t lanes) {
+                                                    const T* __restrict__ cim, int64_t lanes, Geo gf,
+                                                    const T* __restrict__ rf, T* __restrict__ bw) {
     constexpr int D = 2, R = 2 * D + 1, NF = St<2>::NF, NT = NF + St<2>::NUP, H = 7;
     constexpr int T_SELF = St<2>::CF, T_NHI = St<2>::CF + 1, T_PLO = NF + 2, T_PHI = NF + 3;
+    const int64_t sf = 2 * gf.N;
     {
         const int rb0 = blockIdx.y * rpb;
         b += rb0 * stride;
         if (ein) ein += rb0 * stride;
         eout += rb0 * stride;
+        if (RST) {
+            rf += rb0 * sf;
+            bw += rb0 * stride;
+        }
         nrhs = nrhs - rb0 < rpb ? nrhs - rb0 : rpb;
     }
     const int hp = g.n[0] >> 1;
@@ -602,7 +671,14 @@ __global__ __launch_bounds__(256) void k_relax_st2d(Geo g, int colour, T w, int 
         const CVec<T> bv{b + r * stride, g.N};
         cx<T> res = mk<T>(T(0), T(0));
         cx<T> eown = mk<T>(T(0), T(0));
-        if (ok) {
+        if (RST) {
+            const Vec<T> bo{bw + r * stride, g.N};
+            if (ok) {
+                res = restrict_at2d<T>(gf, rf + r * sf, k, p[0], p[1]);
+                bo.st(idx, res);
+            }
+            if (carry) bo.st(ipb, restrict_at2d<T>(gf, rf + r * sf, 3, 2 * px + 1 - par, yy));
+        } else if (ok) {
             res = bv.ld(idx);
             if (ein) {
                 // every term's load first (columns are clamped into the vector),
@@ -1931,7 +2007,6 @@ __global__ __launch_bounds__(512) void k_relax_lds2d(Op op, int colour, T w, int
 // Staggered bilinear transfer: u_k linear along its normal (weights 1 / (1/2, 1/2)),
 // linear along each tangential axis (3/4 nearer coarse row, 1/4 the other, zero
 // beyond the wall); pressure piecewise constant.  Restriction is P^T.
-EHH_DEV float w_tang(int d) { return (d == 0 || d == 1) ? 0.75f : ((d == -1 || d == 2) ? 0.25f : 0.f); }
 
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_restrict(Geo gf, Geo gc, const T* __restrict__ rf,
@@ -2096,67 +2171,31 @@ __global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const T* __rest
 template <typename T>
 __global__ __launch_bounds__(256) void k_restrict2d(Geo gf, Geo gc, const T* __restrict__ rf, T* __restrict__ rc) {
     const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    const int Nc = (int)gc.N, Nf = (int)gf.N;
+    const int Nc = (int)gc.N;
     if (t >= Nc) return;
     rf += (int64_t)blockIdx.y * 2 * gf.N;
     rc += (int64_t)blockIdx.y * 2 * gc.N;
-    const int ncx = gc.n[0], nfx = gf.n[0], nfy = gf.n[1];
-    T sr = T(0), si = T(0);
-    if (t >= (int)gc.off[3]) {   // pressure: the four fine cells
+    const int ncx = gc.n[0];
+    int k, X, Y;
+    if (t >= (int)gc.off[3]) {
         const int li = t - (int)gc.off[3];
-        const int X = li % ncx, Y = li / ncx;
-        const int b = (int)gf.off[3] + 2 * Y * nfx + 2 * X;
-        const int ix[4] = {b, b + 1, b + nfx, b + nfx + 1};
-        T vr[4], vi[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            vr[j] = rf[ix[j]];
-            vi[j] = rf[Nf + ix[j]];
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            sr += vr[j];
-            si += vi[j];
-        }
+        k = 3;
+        X = li % ncx;
+        Y = li / ncx;
+    } else if (t < (int)gc.off[1]) {
+        const int li = t - (int)gc.off[0];
+        k = 0;
+        X = li % (ncx - 1) + 1;
+        Y = li / (ncx - 1);
     } else {
-        const bool k0 = t < (int)gc.off[1];
-        int X, Y;
-        if (k0) {
-            const int li = t - (int)gc.off[0];
-            X = li % (ncx - 1) + 1;
-            Y = li / (ncx - 1);
-        } else {
-            const int li = t - (int)gc.off[1];
-            X = li % ncx;
-            Y = li / ncx + 1;
-        }
-        int ix[12];
-        T wt[12];
-#pragma unroll
-        for (int a = -1; a <= 1; ++a)
-#pragma unroll
-            for (int b1 = -1; b1 <= 2; ++b1) {
-                const int j = (a + 1) * 4 + b1 + 1;
-                const int fn = 2 * (k0 ? X : Y) + a, ft = 2 * (k0 ? Y : X) + b1, nt = k0 ? nfy : nfx;
-                const bool ok = ft >= 0 && ft < nt;
-                const int fc = ft < 0 ? 0 : (ft >= nt ? nt - 1 : ft);
-                ix[j] = k0 ? (int)gf.off[0] + fc * (nfx - 1) + fn - 1 : (int)gf.off[1] + (fn - 1) * nfx + fc;
-                wt[j] = ok ? (a == 0 ? T(1) : T(0.5)) * T(w_tang(b1)) : T(0);
-            }
-        T vr[12], vi[12];
-#pragma unroll
-        for (int j = 0; j < 12; ++j) {
-            vr[j] = rf[ix[j]];
-            vi[j] = rf[Nf + ix[j]];
-        }
-#pragma unroll
-        for (int j = 0; j < 12; ++j) {
-            sr += wt[j] * vr[j];
-            si += wt[j] * vi[j];
-        }
+        const int li = t - (int)gc.off[1];
+        k = 1;
+        X = li % ncx;
+        Y = li / ncx + 1;
     }
-    rc[t] = sr;
-    rc[Nc + t] = si;
+    const cx<T> v = restrict_at2d<T>(gf, rf, k, X, Y);
+    rc[t] = v.re;
+    rc[Nc + t] = v.im;
 }
 
 template <typename T>
@@ -2529,7 +2568,7 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
         if (L.fine)
             EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_relax_plan<2, T, FineOp<2, T>, RB>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb));
         else if (L.sp.re[colour])
-            hipLaunchKernelGGL((k_relax_st2d<T, sizeof(T) == 4>), gb, 256, 0, s, L.g, colour, tw, econ, b, ein, eout, nrhs, stride, rpb, L.sp.re[colour], L.sp.im[colour], L.sp.lanes);
+            hipLaunchKernelGGL((k_relax_st2d<T, sizeof(T) == 4, false>), gb, 256, 0, s, L.g, colour, tw, econ, b, ein, eout, nrhs, stride, rpb, L.sp.re[colour], L.sp.im[colour], L.sp.lanes, L.g, (const T*)nullptr, (T*)nullptr);
         else
             EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_relax_plan<2, T, StOp<2, T>, RB>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb));
     } else if (L.fine && cell3d_enabled() && 2 * L.g.N * (int64_t)sizeof(T) < (int64_t(1) << 32)) {
@@ -2562,6 +2601,31 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
     }
     return hipGetLastError();
 }
+
+template <typename T>
+bool relax_restrict_supported(const LevelDesc<T>& L, int nrhs) {
+    static const bool on = env_int("EHH_RELAX_RESTRICT", 1) != 0;
+    if (!on || L.g.dim != 2 || L.fine || !L.sp.re[0]) return false;
+    // same routing as launch_relax: the LDS kernel serves large levels with many sources
+    return !(L.g.ncell >= 65536 && lds2d_enabled() && nrhs > 8);
+}
+template <typename T>
+hipError_t launch_relax_restrict(const LevelDesc<T>& L, double w, int econ, const Geo& gf, const T* rf, T* b,
+                                 T* eout, int nrhs, hipStream_t s) {
+    const int64_t stride = 2 * L.g.N;
+    const int64_t npair = (int64_t)(L.g.n[0] / 2) * L.g.n[1] * L.g.n[2];
+    const int rpb = rhs_per_block((npair * 8 + 63) / 64, nrhs, 1);
+    const dim3 gb(nblk(npair * 8), (nrhs + rpb - 1) / rpb);
+    hipLaunchKernelGGL((k_relax_st2d<T, sizeof(T) == 4, true>), gb, 256, 0, s, L.g, 0, (T)w, econ, (const T*)b,
+                       (const T*)nullptr, eout, nrhs, stride, rpb, L.sp.re[0], L.sp.im[0], L.sp.lanes, gf, rf, b);
+    return hipGetLastError();
+}
+template bool relax_restrict_supported<float>(const LevelDesc<float>&, int);
+template bool relax_restrict_supported<double>(const LevelDesc<double>&, int);
+template hipError_t launch_relax_restrict<float>(const LevelDesc<float>&, double, int, const Geo&, const float*,
+                                                 float*, float*, int, hipStream_t);
+template hipError_t launch_relax_restrict<double>(const LevelDesc<double>&, double, int, const Geo&, const double*,
+                                                  double*, double*, int, hipStream_t);
 
 int64_t stored_plan_lanes(const Geo& g) {
     const int64_t npair = (int64_t)(g.n[0] / 2) * g.n[1] * g.n[2];
