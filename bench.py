@@ -125,7 +125,7 @@ def relax_kernel_name(w, level, ncell):
     t = "float" if w.precond_bits == 32 else "double"
     if w.dim == 2:
         if level == 0:
-            return f"k_relax_cell2d<{t}>"
+            return f"k_relax_cell2d<{t}, {t}>"
         if ncell >= 65536 and len(w.sources()) > 8:
             return f"k_relax_lds2d<{t}, StOp<2, {t}>>"
         return f"k_relax_st2d<{t}, {'true' if t == 'float' else 'false'}, false>"

@@ -294,7 +294,9 @@ int32_t ensure_krylov(ehh_ctx* c, int nrhs) {
 // ------------------------------------------------------------------- the cycle
 template <typename T>
 int32_t cycle(ehh_ctx* c, Sub& S, int l, const T* b, T* e, bool zero_init, int nrhs, hipStream_t s,
-              const T* rsrc = nullptr, const Geo* gsrc = nullptr) {
+              const T* rsrc = nullptr, const Geo* gsrc = nullptr, double* z64 = nullptr, bool* wrote64 = nullptr) {
+    // z64 (level 0 of a complex64 cycle): where the kernels allow it, the last
+    // half-sweep writes its result there in FP64 (*wrote64 set) instead of to e
     // rsrc: the finer level's residual (grid gsrc) when b = P^T rsrc is still to be
     // formed; the first half-sweep then forms and writes it (zero_init, nu1 >= 1)
     Level& L = S.lev[l];
@@ -337,7 +339,15 @@ int32_t cycle(ehh_ctx* c, Sub& S, int l, const T* b, T* e, bool zero_init, int n
     HIPCHK(launch_prolong<T>(L.g, C.g, (const T*)C.e, e, nrhs, s));
     for (int it = 0; it < c->opt.nu2; ++it) {
         HIPCHK(launch_relax<T>(D, 0, L.damping, econ, b, e, t, nrhs, s));
-        HIPCHK(launch_relax<T>(D, 1, L.damping, econ, b, t, e, nrhs, s));
+        bool done = false;
+        if constexpr (std::is_same<T, float>::value) {
+            if (z64 && it == c->opt.nu2 - 1)
+                HIPCHK(launch_relax_to64(D, L.damping, econ, b, t, z64, nrhs, s, &done));
+        }
+        if (done)
+            *wrote64 = true;
+        else
+            HIPCHK(launch_relax<T>(D, 1, L.damping, econ, b, t, e, nrhs, s));
     }
     return EHH_OK;
 }
@@ -367,8 +377,9 @@ int32_t precondition_t(ehh_ctx* c, const double* v, double* z, int nrhs, hipStre
             return cycle<T>(c, S, 0, (const T*)v, (T*)z, true, nrhs, s);
         }
         if (!v_in_r0) HIPCHK(launch_cast_d2f(v, (float*)S.r0, 2 * gg.N * nrhs, s));
-        CHK(cycle<T>(c, S, 0, (const T*)S.r0, (T*)S.e0, true, nrhs, s));
-        HIPCHK(launch_cast_f2d((const float*)S.e0, z, 2 * gg.N * nrhs, s));
+        bool wrote = false;
+        CHK(cycle<T>(c, S, 0, (const T*)S.r0, (T*)S.e0, true, nrhs, s, nullptr, nullptr, z, &wrote));
+        if (!wrote) HIPCHK(launch_cast_f2d((const float*)S.e0, z, 2 * gg.N * nrhs, s));
         return EHH_OK;
     }
     HIPCHK(launch_zero(z, sizeof(double) * 2 * (size_t)gg.N * nrhs, s));

@@ -36,6 +36,10 @@ hipError_t launch_apply(const LevelDesc<T>& L, const T* x, const T* b, T* y, int
 template <typename T>
 hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, const T* b, const T* ein,
                         T* eout, int nrhs, hipStream_t s);
+// Colour-1 half-sweep of a finest 2D level with an FP64 e_out (*done = false
+// where no kernel serves it: the caller then converts after the cycle).
+hipError_t launch_relax_to64(const LevelDesc<float>& L, double w, int econ, const float* b, const float* ein,
+                             double* eout, int nrhs, hipStream_t s, bool* done);
 // First half-sweep (colour 0) of a visit from zero with the restriction fused:
 // b = P^T rf (rf on the finer grid gf) is formed, written to b, and relaxed.
 template <typename T>

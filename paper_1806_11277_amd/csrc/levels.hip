@@ -1181,10 +1181,12 @@ __global__ __launch_bounds__(256) void k_build_row_rows3d(StOp<3, T> op, T* __re
 // 128 consecutive cells and the other colour's half of each line is used by the
 // neighbour loads of the same wavefront.  The thread also copies the pressure
 // of the other cell of its x-pair (not relaxed in this half-sweep).
-template <typename T>
+// TO: type of e_out (double lets the last half-sweep of a complex64 cycle write
+// the FP64 result directly).
+template <typename T, typename TO = T>
 __global__ __launch_bounds__(256) void k_relax_cell2d(FineOp<2, T> op, int colour, T w, int econ,
                                                       const T* __restrict__ b, const T* __restrict__ ein,
-                                                      T* __restrict__ eout, int nrhs, int64_t stride, int rpb) {
+                                                      TO* __restrict__ eout, int nrhs, int64_t stride, int rpb) {
     const Geo& g = op.g;
     const int n0 = g.n[0], n1 = g.n[1];
     const int hp = n0 >> 1;
@@ -1269,7 +1271,8 @@ __global__ __launch_bounds__(256) void k_relax_cell2d(FineOp<2, T> op, int colou
     const U VB = 2 * NB;       // bytes of one right-hand side's vector
     for (int r = r_begin; r < r_end; ++r) {
         const Buf<T> bb(b + (int64_t)r * stride, VB);
-        const Buf<T> eo(eout + (int64_t)r * stride, VB);
+        constexpr U SO = (U)(sizeof(TO) / sizeof(T));   // output offsets scale
+        const Buf<TO> eo(eout + (int64_t)r * stride, VB * SO);
         auto ldb = [&](U i) { return mk<T>(bb.ld(i), bb.ld(NB + i)); };
         cx<T> rl = vl ? ldb(kl) : mk<T>(T(0), T(0)), rr = vr ? ldb(kr) : mk<T>(T(0), T(0));
         cx<T> rb_ = vb ? ldb(kb) : mk<T>(T(0), T(0)), rt = vt ? ldb(kt) : mk<T>(T(0), T(0));
@@ -1303,8 +1306,8 @@ __global__ __launch_bounds__(256) void k_relax_cell2d(FineOp<2, T> op, int colou
         const cx<T> y1l = b00 * rb_ + b01 * rt, y1h = b01 * rb_ + b11 * rt;
         const cx<T> dp = (rp - (gl0 * y0l + gh0 * y0h + gl1 * y1l + gh1 * y1h)) * iS;
         auto st = [&](U i, cx<T> v) {
-            eo.st(i, v.re);
-            eo.st(NB + i, v.im);
+            eo.st(SO * i, (TO)v.re);
+            eo.st(SO * (NB + i), (TO)v.im);
         };
         if (vl) st(kl, el + w * (y0l - z0l * dp));
         if (vr) st(kr, ere + w * (y0h - z0h * dp));
@@ -2599,6 +2602,27 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
         } else
             EHH_RB_DISPATCH(rb3, hipLaunchKernelGGL((k_relax<3, T, StOp<3, T>, RB>), gb3, 256, 0, s, StOp<3, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb3));
     }
+    return hipGetLastError();
+}
+
+// Colour-1 half-sweep of the finest 2D level writing e_out in FP64 (the last
+// half-sweep of a complex64 cycle); false where that level is not served by the
+// one-thread-per-cell kernel.
+hipError_t launch_relax_to64(const LevelDesc<float>& L, double w, int econ, const float* b, const float* ein,
+                             double* eout, int nrhs, hipStream_t s, bool* done) {
+    *done = false;
+    if (!(L.g.dim == 2 && L.fine && cell2d_enabled() && 2 * L.g.N * (int64_t)sizeof(double) < (int64_t(1) << 32)))
+        return hipSuccess;
+    const int64_t stride = 2 * L.g.N;
+    const int64_t cells = (int64_t)(L.g.n[0] / 2) * L.g.n[1];
+    static const int64_t cell_waves = env_int("EHH_CELL_WAVES", 4096);
+    int64_t groups = (cell_waves + (cells + 63) / 64 - 1) / ((cells + 63) / 64);
+    groups = groups < 1 ? 1 : (groups > nrhs ? nrhs : groups);
+    const int rpc = (int)((nrhs + groups - 1) / groups);
+    const dim3 gc(nblk(cells), (nrhs + rpc - 1) / rpc);
+    hipLaunchKernelGGL((k_relax_cell2d<float, double>), gc, 256, 0, s, FineOp<2, float>{L.g, L.f}, 1, (float)w,
+                       econ, b, ein, eout, nrhs, stride, rpc);
+    *done = true;
     return hipGetLastError();
 }
 
