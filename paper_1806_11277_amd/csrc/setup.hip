@@ -824,6 +824,208 @@ __global__ __launch_bounds__(256) void k_coarse_apply_multi(const double* __rest
     }
 }
 
+// Register-blocked variant for groups of up to 32 right-hand sides: a workgroup
+// owns 64 rows x 32 right-hand sides of one column segment and stages 16-column
+// chunks of the inverse (transposed) and of the vectors in LDS; thread (tr, tq)
+// accumulates rows tr + 16 a (a < 4) x right-hand sides tq + 16 b (b < 2), so a
+// staged column costs it 6 LDS reads for 8 complex multiply-adds (the
+// one-register-row variant above needs 6 for 2).
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse_apply_rb(const double* __restrict__ inv, int64_t n,
+                                                         const T* __restrict__ r, T* __restrict__ e, int nrhs,
+                                                         int64_t kseg, double* __restrict__ part) {
+    constexpr int ROWS = 64, W = 32, KC = 16, RT = 4, QT = 2;
+    __shared__ double Ms[KC][ROWS * 2 + 2];
+    __shared__ double Xs[KC][W * 2];
+    const int t = threadIdx.x;
+    const int tq = t & 15, tr = t >> 4;
+    const int64_t i0 = (int64_t)blockIdx.x * ROWS;
+    const int q0 = blockIdx.y * W;
+    const int64_t jb = (int64_t)blockIdx.z * kseg;
+    const int64_t je = jb + kseg < n ? jb + kseg : n;
+    double ar[RT][QT], ai[RT][QT];
+#pragma unroll
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+        for (int b = 0; b < QT; ++b) ar[a][b] = ai[a][b] = 0.0;
+    for (int64_t j0 = jb; j0 < je; j0 += KC) {
+        // 64 rows x 16 columns of the inverse: 16 consecutive columns per row read together
+#pragma unroll
+        for (int m = 0; m < ROWS * KC / 256; ++m) {
+            const int el = t + 256 * m;
+            const int rr = el / KC, cc = el % KC;
+            const int64_t gi = i0 + rr, gj = j0 + cc;
+            double vr = 0.0, vi = 0.0;
+            if (gi < n && gj < je) {
+                vr = inv[2 * (gi * n + gj)];
+                vi = inv[2 * (gi * n + gj) + 1];
+            }
+            Ms[cc][2 * rr] = vr;
+            Ms[cc][2 * rr + 1] = vi;
+        }
+#pragma unroll
+        for (int m = 0; m < KC * W / 256; ++m) {
+            const int el = t + 256 * m;
+            const int kk = el % KC, qq = el / KC;
+            const int64_t gj = j0 + kk;
+            double vr = 0.0, vi = 0.0;
+            if (gj < je && q0 + qq < nrhs) {
+                const T* rv = r + (int64_t)(q0 + qq) * 2 * n;
+                vr = (double)rv[gj];
+                vi = (double)rv[n + gj];
+            }
+            Xs[kk][2 * qq] = vr;
+            Xs[kk][2 * qq + 1] = vi;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < KC; ++kk) {
+            double mr[RT], mi[RT], xr[QT], xi[QT];
+#pragma unroll
+            for (int a = 0; a < RT; ++a) {
+                mr[a] = Ms[kk][2 * (tr + 16 * a)];
+                mi[a] = Ms[kk][2 * (tr + 16 * a) + 1];
+            }
+#pragma unroll
+            for (int b = 0; b < QT; ++b) {
+                xr[b] = Xs[kk][2 * (tq + 16 * b)];
+                xi[b] = Xs[kk][2 * (tq + 16 * b) + 1];
+            }
+#pragma unroll
+            for (int a = 0; a < RT; ++a)
+#pragma unroll
+                for (int b = 0; b < QT; ++b) {
+                    ar[a][b] = fma(mr[a], xr[b], fma(-mi[a], xi[b], ar[a][b]));
+                    ai[a][b] = fma(mr[a], xi[b], fma(mi[a], xr[b], ai[a][b]));
+                }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int b = 0; b < QT; ++b) {
+        const int q = q0 + tq + 16 * b;
+        if (q >= nrhs) continue;
+#pragma unroll
+        for (int a = 0; a < RT; ++a) {
+            const int64_t g = i0 + tr + 16 * a;
+            if (g >= n) continue;
+            if (part) {
+                double* pv = part + ((int64_t)blockIdx.z * nrhs + q) * 2 * n;
+                pv[g] = ar[a][b];
+                pv[n + g] = ai[a][b];
+            } else {
+                T* ev = e + (int64_t)q * 2 * n;
+                ev[g] = (T)ar[a][b];
+                ev[n + g] = (T)ai[a][b];
+            }
+        }
+    }
+}
+
+// Matrix-core variant (FP64 MFMA 16x16x4) for groups of up to 32 right-hand
+// sides: a workgroup owns 64 rows x 32 right-hand sides of one column segment and
+// stages 32-column chunks of the inverse and of the vectors in LDS (the next
+// chunk is loaded into registers during the products of the current); wave w keeps
+// the 16 x 16 output blocks of rows 16 w .. 16 w + 15 and both 16-source halves.
+// A complex product takes four real MFMAs (re*re - im*im, re*im + im*re).
+// Operand layout of v_mfma_f64_16x16x4 (checked on MI355X): lane l holds
+// A[l % 16][l / 16] and B[l / 16][l % 16]; register r of lane l holds the result
+// D[l / 16 + 4 r][l % 16].
+typedef double ehh_d4 __attribute__((ext_vector_type(4)));
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse_apply_mfma(const double* __restrict__ inv, int64_t n,
+                                                           const T* __restrict__ r, T* __restrict__ e, int nrhs,
+                                                           int64_t kseg, double* __restrict__ part) {
+    constexpr int ROWS = 64, W = 32, KC = 32, MS = KC + 1;   // MS: padded row of the staged chunk
+    constexpr int NM = ROWS * KC / 256, NX = KC * W / 256;   // staged values per thread
+    __shared__ double Ms[ROWS * MS * 2];
+    __shared__ double Xs[KC * W * 2];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t i0 = (int64_t)blockIdx.x * ROWS;
+    const int q0 = blockIdx.y * W;
+    const int64_t jb = (int64_t)blockIdx.z * kseg;
+    const int64_t je = jb + kseg < n ? jb + kseg : n;
+    ehh_d4 dre[2], dim[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) dre[h] = dim[h] = ehh_d4{0.0, 0.0, 0.0, 0.0};
+    const int li = lane & 15, lk = lane >> 4;
+    // the next chunk is read into registers while the current one is multiplied
+    double pmr[NM], pmi[NM], pxr[NX], pxi[NX];
+    auto fetch = [&](int64_t j0) {
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            const int el = t + 256 * m;
+            const int64_t gi = i0 + el / KC, gj = j0 + el % KC;
+            const bool ok = gi < n && gj < je;
+            pmr[m] = ok ? inv[2 * (gi * n + gj)] : 0.0;
+            pmi[m] = ok ? inv[2 * (gi * n + gj) + 1] : 0.0;
+        }
+#pragma unroll
+        for (int m = 0; m < NX; ++m) {
+            const int el = t + 256 * m;
+            const int kk = el % KC, qq = el / KC;
+            const int64_t gj = j0 + kk;
+            const bool ok = gj < je && q0 + qq < nrhs;
+            const T* rv = r + (int64_t)(ok ? q0 + qq : 0) * 2 * n;
+            pxr[m] = ok ? (double)rv[gj] : 0.0;
+            pxi[m] = ok ? (double)rv[n + gj] : 0.0;
+        }
+    };
+    if (jb < je) fetch(jb);
+    for (int64_t j0 = jb; j0 < je; j0 += KC) {
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            const int el = t + 256 * m;
+            const int rr = el / KC, cc = el % KC;
+            Ms[2 * (rr * MS + cc)] = pmr[m];
+            Ms[2 * (rr * MS + cc) + 1] = pmi[m];
+        }
+#pragma unroll
+        for (int m = 0; m < NX; ++m) {
+            const int el = t + 256 * m;
+            const int kk = el % KC, qq = el / KC;
+            Xs[2 * (kk * W + qq)] = pxr[m];
+            Xs[2 * (kk * W + qq) + 1] = pxi[m];
+        }
+        __syncthreads();
+        if (j0 + KC < je) fetch(j0 + KC);
+#pragma unroll
+        for (int kb = 0; kb < KC; kb += 4) {
+            const int row = 16 * w + li, col = kb + lk;
+            const double ar = Ms[2 * (row * MS + col)], ai = Ms[2 * (row * MS + col) + 1];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int q = 16 * h + li;
+                const double xr = Xs[2 * (col * W + q)], xi = Xs[2 * (col * W + q) + 1];
+                dre[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, xr, dre[h], 0, 0, 0);
+                dre[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, xi, dre[h], 0, 0, 0);
+                dim[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, xi, dim[h], 0, 0, 0);
+                dim[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, xr, dim[h], 0, 0, 0);
+            }
+        }
+        lds_barrier();
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int q = q0 + 16 * h + li;
+        if (q >= nrhs) continue;
+#pragma unroll
+        for (int rg = 0; rg < 4; ++rg) {
+            const int64_t g = i0 + 16 * w + lk + 4 * rg;
+            if (g >= n) continue;
+            if (part) {
+                double* pv = part + ((int64_t)blockIdx.z * nrhs + q) * 2 * n;
+                pv[g] = dre[h][rg];
+                pv[n + g] = dim[h][rg];
+            } else {
+                T* ev = e + (int64_t)q * 2 * n;
+                ev[g] = (T)dre[h][rg];
+                ev[n + g] = (T)dim[h][rg];
+            }
+        }
+    }
+}
+
 // e = sum over the column segments of the partial products, in segment order.
 template <typename T>
 __global__ __launch_bounds__(256) void k_coarse_reduce(const double* __restrict__ part, int ks, int64_t n, int nrhs,
@@ -1041,13 +1243,29 @@ static size_t sym_ws_doubles(int64_t n, int nrhs) {
 }
 
 
+static bool coarse_mfma_enabled() {
+    static const bool v = [] {
+        const char* e = std::getenv("EHH_COARSE_MFMA");
+        return !e || std::atoi(e) != 0;
+    }();
+    return v;
+}
+static bool coarse_rb_enabled() {
+    static const bool v = [] {
+        const char* e = std::getenv("EHH_COARSE_RB");
+        return !e || std::atoi(e) != 0;
+    }();
+    return v;
+}
+
 // Column segments of the multi-right-hand-side coarse apply: enough workgroups to
 // fill the chip (about 1024), segments of at least 256 columns.
 static int coarse_width(int nrhs) { return nrhs <= 4 ? 0 : nrhs <= 8 ? 8 : nrhs <= 16 ? 16 : 32; }
 int coarse_ksplit(int64_t n, int nrhs) {
     const int W = coarse_width(nrhs);
     if (W == 0) return 1;
-    const int64_t blocks = ((n + 512 / W - 1) / (512 / W)) * ((nrhs + W - 1) / W);
+    const int rows = W == 32 && coarse_rb_enabled() ? 64 : 512 / W;   // rows per workgroup
+    const int64_t blocks = ((n + rows - 1) / rows) * ((nrhs + W - 1) / W);
     int64_t ks = (1024 + blocks - 1) / blocks;
     const int64_t kmax = n / 256 > 1 ? n / 256 : 1;
     ks = ks < 1 ? 1 : (ks > kmax ? kmax : ks);
@@ -1085,6 +1303,15 @@ hipError_t launch_coarse_apply(const double* inv, const double* sym, int64_t n, 
     const int64_t kseg = ((n + ks - 1) / ks + 63) / 64 * 64;
     ks = (int)((n + kseg - 1) / kseg);
     double* part = ks > 1 ? ws : nullptr;
+    if (W == 32 && coarse_rb_enabled()) {
+        const dim3 grid_rb((unsigned)((n + 63) / 64), (unsigned)((nrhs + 31) / 32), (unsigned)ks);
+        if (coarse_mfma_enabled())
+            hipLaunchKernelGGL((k_coarse_apply_mfma<T>), grid_rb, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
+        else
+            hipLaunchKernelGGL((k_coarse_apply_rb<T>), grid_rb, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
+        if (part) hipLaunchKernelGGL((k_coarse_reduce<T>), nblk(2 * n * nrhs), 256, 0, s, part, ks, n, nrhs, e);
+        return hipGetLastError();
+    }
     const unsigned rows = (unsigned)((n + 512 / W - 1) / (512 / W));
     const dim3 grid(rows, (unsigned)((nrhs + W - 1) / W), (unsigned)ks);
     if (W == 8)
