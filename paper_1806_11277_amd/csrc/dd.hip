@@ -117,18 +117,37 @@ __global__ __launch_bounds__(256) void k_dd_gather_res(Geo gg, Geo gl, SubMap m,
         else face_pos<D>(gg, k, gi - gg.off[k], p);
     }
     const FineOp<D, double> op{gg, A};
-    for (int r = 0; r < nrhs; ++r) {
-        T* o = out + (int64_t)r * 2 * gl.N;
-        if (gi < 0) {
-            o[t] = T(0);
-            o[gl.N + t] = T(0);
-            continue;
+    // the row (its few terms and weights) is built once and applied to every
+    // right-hand side, four at a time so that their loads are in flight together
+    using Op = FineOp<D, double>;
+    Plan<double, Op::NT> P;
+    if (gi >= 0) {
+        // one call per component with a constant index, so that the row's local
+        // position arrays stay in registers (a runtime index puts them in scratch)
+        if (k == 0) op.plan_u(0, p, P);
+        else if (k == 1) op.plan_u(1, p, P);
+        else if (D == 3 && k == 2) op.plan_u(2, p, P);
+        else op.plan_p(p, P);
+    }
+    constexpr int RB = 4;
+    for (int r0 = 0; r0 < nrhs; r0 += RB) {
+        cx<double> az[RB], vz[RB];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const int r = r0 + q < nrhs ? r0 + q : r0;
+            az[q] = vz[q] = mk<double>(0.0, 0.0);
+            if (gi >= 0) {
+                az[q] = P.dot(CVec<double>{z + (int64_t)r * 2 * gg.N, gg.N});
+                vz[q] = CVec<double>{v + (int64_t)r * 2 * gg.N, gg.N}.ld(gi);
+            }
         }
-        const CVec<double> zv{z + (int64_t)r * 2 * gg.N, gg.N};
-        const double* vv = v + (int64_t)r * 2 * gg.N;
-        const cx<double> az = k == 3 ? op.row_p(p, zv) : op.row_u(k, p, zv);
-        o[t] = (T)(vv[gi] - az.re);
-        o[gl.N + t] = (T)(vv[gg.N + gi] - az.im);
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            if (r0 + q >= nrhs) break;
+            T* o = out + (int64_t)(r0 + q) * 2 * gl.N;
+            o[t] = (T)(vz[q].re - az[q].re);
+            o[gl.N + t] = (T)(vz[q].im - az[q].im);
+        }
     }
 }
 
