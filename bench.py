@@ -121,13 +121,17 @@ def relax_kernel_name(w, level, ncell):
     its launcher): one thread per cell on the finest level, LDS-staged tiles on
     2D Galerkin levels of at least 256^2 cells with more than 8 sources, eight
     lanes per cell with row coefficients stored at setup on the other Galerkin
-    levels (3D: blocks of 8 (FP32) or 2 (FP64) sources per coefficient load)."""
+    levels (3D: blocks of 8 (FP32) or 2 (FP64) sources per coefficient load; the
+    smallest FP64 2D levels split each row over two wavefronts for the sweeps
+    that start from e_in)."""
     t = "float" if w.precond_bits == 32 else "double"
     if w.dim == 2:
         if level == 0:
             return f"k_relax_cell2d<{t}, {t}>"
         if ncell >= 65536 and len(w.sources()) > 8:
             return f"k_relax_lds2d<{t}, StOp<2, {t}>>"
+        if t == "double" and -(-(ncell // 2) * 8 // 256) * 4 <= 256:
+            return "k_relax_st2d_split<double>"   # three of the visit's four half-sweeps
         return f"k_relax_st2d<{t}, {'true' if t == 'float' else 'false'}, false>"
     if level == 0:
         return f"k_relax_cell3d<{t}>"

@@ -763,8 +763,7 @@ int32_t enqueue_iter(ehh_ctx* c, const LevelDesc<double>& A, int j, int nrhs, hi
     HIPCHK(launch_dots(c->V, j + 1, c->w, N, nrhs, c->partial, c->hcol, m + 1, s));
     HIPCHK(launch_axpy_dots(c->V, j + 1, c->w, N, nrhs, c->hcol, m + 1, c->partial, c->hcol2, m + 1, s));
     HIPCHK(launch_axpy_multi(c->V, j + 1, c->w, N, nrhs, c->hcol2, m + 1, c->partial, c->nrm2, s));
-    HIPCHK(launch_axpby(c->hcol, c->hcol2, c->hcol, 2 * (int64_t)nrhs * (m + 1), 1.0, 1.0, s));
-    HIPCHK(launch_givens(c->H, c->cs, c->g, c->hcol, c->nrm2, j, m, nrhs, c->active, c->est, c->bnorm, s));
+    HIPCHK(launch_givens(c->H, c->cs, c->g, c->hcol, c->hcol2, c->nrm2, j, m, nrhs, c->active, c->est, c->bnorm, s));
     HIPCHK(launch_scale(c->w, c->V + (size_t)(j + 1) * nrhs * 2 * N, N, nrhs, c->nrm2, 1, s, v32));
     return EHH_OK;
 }

@@ -147,8 +147,9 @@ hipError_t launch_scale(const double* x, double* out, int64_t N, int nrhs, const
 hipError_t launch_axpy_dots(const double* V, int nv, double* w, int64_t N, int nrhs, const double* h, int ldh,
                             double* partial, double* hout, int ldo, hipStream_t s);
 // Givens update of column j of every right-hand side's Hessenberg matrix.
-hipError_t launch_givens(double* H, double* cs, double* g, const double* hcol, const double* hnext2, int j,
-                         int m, int nrhs, const int* active, double* est, const double* bnorm, hipStream_t s);
+hipError_t launch_givens(double* H, double* cs, double* g, const double* hcol, const double* hcol2,
+                         const double* hnext2, int j, int m, int nrhs, const int* active, double* est,
+                         const double* bnorm, hipStream_t s);
 // y = R^{-1} g (columns ncols[r]); x(r) += sum_i y_i Z_i(r)
 hipError_t launch_update_x(const double* H, const double* g, const double* Z, double* x, int64_t N, int nrhs,
                            int m, const int* ncols, double* y, hipStream_t s);

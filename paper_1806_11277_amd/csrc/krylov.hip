@@ -257,10 +257,12 @@ hipError_t launch_axpby(const double* x, const double* y, double* out, int64_t n
 
 // ------------------------------------------------------------------ Givens rotations
 // H[r][j][i] (column j, i <= m) complex; cs[r][i] = (c, s_re, s_im); g[r][i] complex.
-// hcol[r][i] for i <= j: <v_i, w> (complex, from CGS), hnext2[r] = |w|^2.
+// hcol[r][i] + hcol2[r][i] for i <= j: <v_i, w> (complex, the two CGS passes),
+// hnext2[r] = |w|^2.
 __global__ void k_givens(double* __restrict__ H, double* __restrict__ cs, double* __restrict__ g,
-                         const double* __restrict__ hcol, const double* __restrict__ hnext2, int j, int m, int nrhs,
-                         const int* __restrict__ active, double* __restrict__ est, const double* __restrict__ bnorm) {
+                         const double* __restrict__ hcol, const double* __restrict__ hcol2,
+                         const double* __restrict__ hnext2, int j, int m, int nrhs, const int* __restrict__ active,
+                         double* __restrict__ est, const double* __restrict__ bnorm) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrhs) return;
     if (!active[r]) return;
@@ -268,8 +270,9 @@ __global__ void k_givens(double* __restrict__ H, double* __restrict__ cs, double
     double* c = cs + 3 * (int64_t)r * m;
     double* gg = g + 2 * (int64_t)r * (m + 1);
     for (int i = 0; i <= j; ++i) {
-        col[2 * i] = hcol[2 * ((int64_t)r * (m + 1) + i)];
-        col[2 * i + 1] = hcol[2 * ((int64_t)r * (m + 1) + i) + 1];
+        const int64_t o = 2 * ((int64_t)r * (m + 1) + i);
+        col[2 * i] = hcol[o] + hcol2[o];
+        col[2 * i + 1] = hcol[o + 1] + hcol2[o + 1];
     }
     col[2 * (j + 1)] = sqrt(hnext2[r]);
     col[2 * (j + 1) + 1] = 0.0;
@@ -320,9 +323,11 @@ __global__ void k_givens(double* __restrict__ H, double* __restrict__ cs, double
     est[r] = sqrt(er * er + ei * ei) / bnorm[r];
 }
 
-hipError_t launch_givens(double* H, double* cs, double* g, const double* hcol, const double* hnext2, int j, int m,
-                         int nrhs, const int* active, double* est, const double* bnorm, hipStream_t s) {
-    hipLaunchKernelGGL(k_givens, nblk(nrhs, 64), 64, 0, s, H, cs, g, hcol, hnext2, j, m, nrhs, active, est, bnorm);
+hipError_t launch_givens(double* H, double* cs, double* g, const double* hcol, const double* hcol2,
+                         const double* hnext2, int j, int m, int nrhs, const int* active, double* est,
+                         const double* bnorm, hipStream_t s) {
+    hipLaunchKernelGGL(k_givens, nblk(nrhs, 64), 64, 0, s, H, cs, g, hcol, hcol2, hnext2, j, m, nrhs, active, est,
+                       bnorm);
     return hipGetLastError();
 }
 

@@ -752,6 +752,133 @@ __global__ __launch_bounds__(256) void k_relax_st2d(Geo g, int colour, T w, int 
     }
 }
 
+// FP64 half-sweep over stored rows with each row split over two wavefronts: the
+// lane layout and stored-row slots of k_relax_st2d (eight cells per wavefront,
+// lane 8 j + cell), but a pair of wavefronts per group of eight cells, the odd
+// one summing terms 11..20 of every row and handing its partial sums over in
+// LDS, the even one terms 0..10, then the block solve.  Each row's loads then go
+// out in one batch (the single-wavefront FP64 kernel needs three to stay within
+// its registers), which pays on small levels where a launch is one wave of
+// wavefronts deep.  Only for half-sweeps that start from e_in.
+template <typename T>
+__global__ __launch_bounds__(256) void k_relax_st2d_split(Geo g, int colour, T w, int econ, const T* __restrict__ b,
+                                                          const T* __restrict__ ein, T* __restrict__ eout, int nrhs,
+                                                          int64_t stride, int rpb, const T* __restrict__ cre,
+                                                          const T* __restrict__ cim, int64_t lanes) {
+    constexpr int D = 2, R = 2 * D + 1, NF = St<2>::NF, NT = NF + St<2>::NUP, HT = 11;
+    constexpr int T_SELF = St<2>::CF, T_NHI = St<2>::CF + 1, T_PLO = NF + 2, T_PHI = NF + 3;
+    __shared__ T part[2][2][2][64];   // [r parity][cell group of the block][re, im][lane]
+    {
+        const int rb0 = blockIdx.y * rpb;
+        b += rb0 * stride;
+        ein += rb0 * stride;
+        eout += rb0 * stride;
+        nrhs = nrhs - rb0 < rpb ? nrhs - rb0 : rpb;
+    }
+    const int hp = g.n[0] >> 1;
+    const int npair = hp * g.n[1];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int half = wv & 1, grp = wv >> 1;
+    const int row = lane >> 3, cig = lane & 7;
+    const int64_t group = xcd_block(blockIdx.x, gridDim.x) * 2 + grp;   // cell group of eight cells
+    const int64_t gl = group * 64 + lane;                                  // stored-row slot
+    const int t = (int)group * 8 + cig;
+    const int base = cig;
+    const bool live = t < npair;
+    const int tt = live ? t : 0;
+    const int px = tt % hp;
+    const int yy = tt / hp;
+    const int par = (colour + yy) & 1;
+    const int k = row < 2 * D ? (row >> 1) : 3;
+    int p[3] = {2 * px + par, yy, 0};
+    bool ok = live && row < R;
+    if (k < 3) {
+        p[k] += row & 1;
+        ok = ok && p[k] >= 1 && p[k] <= g.n[k] - 1;
+    }
+    const Cols2 cc = cols2(g, k, p);
+    const int idx = cc.self;
+    const bool carry = live && row == R;
+    const int ipb = (int)g.off[3] + yy * g.n[0] + 2 * px + 1 - par;
+    const bool slot_ok = gl < lanes;
+    const Buf<T> cR(cre, (uint32_t)(NT * lanes * sizeof(T))), cI(cim, (uint32_t)(NF * lanes * sizeof(T)));
+    const uint32_t lo = (uint32_t)(slot_ok ? gl : 0) * (uint32_t)sizeof(T), ls = (uint32_t)lanes * (uint32_t)sizeof(T);
+    const uint32_t vb = 2 * (uint32_t)g.N * (uint32_t)sizeof(T), nb = (uint32_t)g.N * (uint32_t)sizeof(T);
+    const bool lowrow = row < 2 * D && (row & 1) == 0;
+    VankaBlock<D, T> V;
+    for (int r = 0; r < nrhs; ++r) {
+        const Buf<T> ev(ein + r * stride, vb);
+        T ar = T(0), ai = T(0);
+        cx<T> res = mk<T>(T(0), T(0)), eown = mk<T>(T(0), T(0));
+        if (half == 1) {
+            if (row < R && slot_ok) {
+                T cr_[NT - HT], ci_[NT - HT], vr[NT - HT], vi[NT - HT];
+#pragma unroll
+                for (int jj = 0; jj < NT - HT; ++jj) {
+                    const int j = HT + jj;
+                    cr_[jj] = cR.ld(lo, j * ls);
+                    ci_[jj] = j < NF ? cI.ld(lo, j * ls) : T(0);
+                    const uint32_t o = (uint32_t)col2(cc, j) * (uint32_t)sizeof(T);
+                    vr[jj] = ev.ld(o, 0);
+                    vi[jj] = ev.ld(o, nb);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int jj = 0; jj < NT - HT; ++jj) {
+                    ar += cr_[jj] * vr[jj] - ci_[jj] * vi[jj];
+                    ai += cr_[jj] * vi[jj] + ci_[jj] * vr[jj];
+                }
+            }
+            part[r & 1][grp][0][lane] = ar;
+            part[r & 1][grp][1][lane] = ai;
+        } else {
+            T dre = T(1), dim = T(0), ore = T(0), oim = T(0), gg = T(0);
+            cx<T> bo = mk<T>(T(0), T(0));
+            if (row < R && slot_ok) {
+                T cr_[HT], ci_[HT], vr[HT], vi[HT];
+#pragma unroll
+                for (int jj = 0; jj < HT; ++jj) {
+                    cr_[jj] = cR.ld(lo, jj * ls);
+                    ci_[jj] = cI.ld(lo, jj * ls);
+                    const uint32_t o = (uint32_t)col2(cc, jj) * (uint32_t)sizeof(T);
+                    vr[jj] = ev.ld(o, 0);
+                    vi[jj] = ev.ld(o, nb);
+                }
+                const uint32_t o = (uint32_t)idx * (uint32_t)sizeof(T);
+                eown = mk<T>(ev.ld(o, 0), ev.ld(o, nb));
+                if (ok) bo = CVec<T>{b + r * stride, g.N}.ld(idx);
+                if (ok) {
+                    const uint32_t js = (uint32_t)(k == 3 ? 0 : T_SELF) * ls;
+                    dre = cR.ld(lo + js);
+                    if (k < 3) {
+                        dim = cI.ld(lo + js);
+                        gg = cR.ld(lo + (uint32_t)(lowrow ? T_PHI : T_PLO) * ls);
+                        if (lowrow && !econ) {
+                            ore = cR.ld(lo + (uint32_t)T_NHI * ls);
+                            oim = cI.ld(lo + (uint32_t)T_NHI * ls);
+                        }
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int jj = 0; jj < HT; ++jj) {
+                    ar += cr_[jj] * vr[jj] - ci_[jj] * vi[jj];
+                    ai += cr_[jj] * vi[jj] + ci_[jj] * vr[jj];
+                }
+            }
+            V.factor(dre, dim, ore, oim, gg, base, row);
+            lds_barrier();   // the odd wavefront's partial sums are in LDS
+            if (ok) res = bo - mk<T>(ar + part[r & 1][grp][0][lane], ai + part[r & 1][grp][1][lane]);
+            const cx<T> mine = V.solve(res, base, row);
+            const Vec<T> ov{eout + r * stride, g.N};
+            if (ok) ov.st(idx, eown + w * mine);
+            if (carry) ov.st(ipb, CVec<T>{ein + r * stride, g.N}.ld(ipb));
+            continue;
+        }
+        lds_barrier();
+    }
+}
+
 // y = A x or r = b - A x over stored rows (term j of row t at [j * N + t]).
 template <typename T>
 __global__ __launch_bounds__(256) void k_apply_st2d(Geo g, const T* __restrict__ x, const T* __restrict__ b,
@@ -2571,7 +2698,17 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
         if (L.fine)
             EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_relax_plan<2, T, FineOp<2, T>, RB>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb));
         else if (L.sp.re[colour])
-            hipLaunchKernelGGL((k_relax_st2d<T, sizeof(T) == 4, false>), gb, 256, 0, s, L.g, colour, tw, econ, b, ein, eout, nrhs, stride, rpb, L.sp.re[colour], L.sp.im[colour], L.sp.lanes, L.g, (const T*)nullptr, (T*)nullptr);
+        {
+            // the smallest FP64 levels (one wavefront per CU): rows split over two
+            // wavefronts, one batch of loads per row instead of three (measured on
+            // MI355X: 64^2 5.4 -> 4.8 us; no gain at 128^2)
+            static const bool split_on = env_int("EHH_SPLIT", 1) != 0;
+            const int64_t groups = L.sp.lanes / 64;
+            if (sizeof(T) == 8 && ein && split_on && groups <= 256)
+                hipLaunchKernelGGL((k_relax_st2d_split<T>), dim3((unsigned)((groups + 1) / 2), gb.y), 256, 0, s, L.g, colour, tw, econ, b, ein, eout, nrhs, stride, rpb, L.sp.re[colour], L.sp.im[colour], L.sp.lanes);
+            else
+                hipLaunchKernelGGL((k_relax_st2d<T, sizeof(T) == 4, false>), gb, 256, 0, s, L.g, colour, tw, econ, b, ein, eout, nrhs, stride, rpb, L.sp.re[colour], L.sp.im[colour], L.sp.lanes, L.g, (const T*)nullptr, (T*)nullptr);
+        }
         else
             EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_relax_plan<2, T, StOp<2, T>, RB>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb));
     } else if (L.fine && cell3d_enabled() && 2 * L.g.N * (int64_t)sizeof(T) < (int64_t(1) << 32)) {
