@@ -175,7 +175,8 @@ def kernel_roofline(w, reps=30):
     """HBM roofline of the dominant kernel, the red-black Vanka half-sweep.
     Every level's half-sweep is timed with HIP events around the replay of a
     graph of its launches (captured from the library's launches on the
-    caller's stream).  Launches are weighted by their
+    caller's stream), each visit preceded by a 512 MiB write that evicts the
+    caches as the rest of a solve does, whose own time is subtracted.  Launches are weighted by their
     count in one cycle (2 (nu1 + nu2) half-sweeps per visit) and grouped by the
     kernel each level uses; the dominant kernel is the one with the largest
     time per cycle.  achieved = its algorithmic bytes per launch / its average
@@ -189,6 +190,7 @@ def kernel_roofline(w, reps=30):
     visits = visits_per_cycle(w)
     rows = []
     groups = {}
+    scrub = torch.empty(64 * 2 ** 20, dtype=torch.float64, device="cuda")   # 512 MiB
     for l in range(w.levels - 1):
         info = S.level_info(0, l)
         # several vector sets in turn, so that a visit does not find the previous
@@ -210,22 +212,32 @@ def kernel_roofline(w, reps=30):
                 S.level_relax(0, l, k % 2, b, None if k < nzero else e_in, e_out)
         visit()
         torch.cuda.synchronize()
-        # the sweeps are replayed from a captured graph, as the solver replays its
-        # Arnoldi steps, so that host launch gaps do not enter the timing
-        graph = torch.cuda.CUDAGraph()
-        cap = torch.cuda.Stream()
-        with torch.cuda.graph(graph, stream=cap):
-            for r in range(reps):
-                visit(r)
-        graph.replay()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        ev0.record(stream)
-        graph.replay()
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        t = ev0.elapsed_time(ev1) / (reps * nsw) / 1e3
-        del graph
+        # The sweeps are replayed from a captured graph, as the solver replays its
+        # Arnoldi steps, so that host launch gaps do not enter the timing.  Each
+        # visit is preceded by a write of 512 MiB that evicts the L2s and the
+        # MALL, as the other kernels of a solve do between two visits of a level:
+        # t = (time of scrub + visit - time of scrub alone) per half-sweep.
+        def timed(with_visit):
+            graph = torch.cuda.CUDAGraph()
+            cap = torch.cuda.Stream()
+            with torch.cuda.graph(graph, stream=cap):
+                for r in range(reps):
+                    scrub.zero_()
+                    if with_visit:
+                        visit(r)
+            graph.replay()
+            best = float("inf")
+            for _ in range(3):
+                ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                torch.cuda.synchronize()
+                ev0.record(stream)
+                graph.replay()
+                ev1.record(stream)
+                torch.cuda.synchronize()
+                best = min(best, ev0.elapsed_time(ev1) / 1e3)
+            del graph
+            return best
+        t = max(timed(True) - timed(False), 0.0) / (reps * nsw)
         nb = (nzero * level_bytes(info, w.precond_bits, nrhs, l == 0, w.dim, with_e=False) +
               (nsw - nzero) * level_bytes(info, w.precond_bits, nrhs, l == 0, w.dim)) / nsw
         launches = 2 * (w.nu1 + w.nu2) * visits[l]
@@ -239,6 +251,7 @@ def kernel_roofline(w, reps=30):
         g["bytes_per_cycle"] += launches * nb
         g["us_per_cycle"] += launches * t * 1e6
         del sets
+    del scrub
     S.close()
     for g in groups.values():
         g["avg_launch_us"] = g["us_per_cycle"] / g["launches_per_cycle"]
