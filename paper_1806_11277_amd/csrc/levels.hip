@@ -240,6 +240,14 @@ template <> struct Buf<double> {
     }
 };
 
+// A per-lane offset past the end of every 2D stored-row buffer (their sizes stay
+// below 2 GiB, and the term offsets, also below 2 GiB, go in a scalar register, so
+// the sum cannot wrap): such a load returns zero and reads no memory.  The
+// pressure rows use it for their imaginary parts and their unused terms, which
+// are stored as zeros, so that a cache line holding only such slots is never
+// fetched.
+constexpr uint32_t OOB_OFF = 0x80000000u;
+
 // ------------------------------------------------ plan-based apply and half-sweep
 // The row plan (indices and coefficients) is built once per row and reused for
 // every right-hand side, so a batch streams only the vectors.
@@ -598,7 +606,7 @@ __global__ __launch_bounds__(256) void k_relax_st2d(Geo g, int colour, T w, int 
                                                     int64_t stride, int rpb, const T* __restrict__ cre,
                                                     const T* __restrict__ cim, int64_t lanes, Geo gf,
                                                     const T* __restrict__ rf, T* __restrict__ bw) {
-    constexpr int D = 2, R = 2 * D + 1, NF = St<2>::NF, NT = NF + St<2>::NUP, H = 7;
+    constexpr int D = 2, R = 2 * D + 1, NF = St<2>::NF, NUP = St<2>::NUP, NT = NF + NUP, H = 7;
     constexpr int T_SELF = St<2>::CF, T_NHI = St<2>::CF + 1, T_PLO = NF + 2, T_PHI = NF + 3;
     const int64_t sf = 2 * gf.N;
     {
@@ -657,12 +665,15 @@ __global__ __launch_bounds__(256) void k_relax_st2d(Geo g, int colour, T w, int 
             }
         }
     }
+    // pressure rows (and the lanes past the rows) skip the slots stored as zeros
+    const uint32_t lq = k == 3 ? OOB_OFF : lo;
     T are[KEEP ? NT : 1], aim[KEEP ? NF : 1];
     if (KEEP) {
+        const uint32_t lr = row < R ? lo : OOB_OFF;
 #pragma unroll
-        for (int j = 0; j < (KEEP ? NT : 0); ++j) are[j] = row < R ? cR.ld(lo, j * ls) : T(0);
+        for (int j = 0; j < (KEEP ? NT : 0); ++j) are[j] = cR.ld(j > 2 * NUP ? lq : lr, j * ls);
 #pragma unroll
-        for (int j = 0; j < (KEEP ? NF : 0); ++j) aim[j] = row < R ? cI.ld(lo, j * ls) : T(0);
+        for (int j = 0; j < (KEEP ? NF : 0); ++j) aim[j] = cI.ld(lq, j * ls);
     }
 
     VankaBlock<D, T> V;
@@ -708,21 +719,22 @@ __global__ __launch_bounds__(256) void k_relax_st2d(Geo g, int colour, T w, int 
                     // half's sums (empty asm statements), so that the halves'
                     // loads are not merged into one batch of registers.
                     Cols2 cl = cc;
-                    uint32_t lh = lo;
-                    asm volatile("" : "+v"(cl.self), "+v"(cl.pc), "+v"(cl.f0), "+v"(cl.f1), "+v"(lh), "+v"(cl.sn),
-                                 "+v"(cl.st), "+v"(cl.cn), "+v"(cl.ct), "+v"(cl.nx));
+                    uint32_t lh = lo, lhq = lq;
+                    asm volatile("" : "+v"(cl.self), "+v"(cl.pc), "+v"(cl.f0), "+v"(cl.f1), "+v"(lh), "+v"(lhq),
+                                 "+v"(cl.sn), "+v"(cl.st), "+v"(cl.cn), "+v"(cl.ct), "+v"(cl.nx));
 #pragma unroll
                     for (int h = 0; h < NT; h += H) {
                         if (h > 0)
-                            asm volatile("" : "+v"(cl.self), "+v"(cl.pc), "+v"(cl.f0), "+v"(cl.f1), "+v"(lh)
+                            asm volatile("" : "+v"(cl.self), "+v"(cl.pc), "+v"(cl.f0), "+v"(cl.f1), "+v"(lh),
+                                         "+v"(lhq)
                                          : "v"(ar), "v"(ai));
                         T cr_[H], ci_[H], vr[H], vi[H];
 #pragma unroll
                         for (int jj = 0; jj < H; ++jj) {
                             const int j = h + jj;
                             if (j < NT) {
-                                cr_[jj] = cR.ld(lh, j * ls);
-                                ci_[jj] = j < NF ? cI.ld(lh, j * ls) : T(0);
+                                cr_[jj] = cR.ld(j > 2 * NUP ? lhq : lh, j * ls);
+                                ci_[jj] = j < NF ? cI.ld(lhq, j * ls) : T(0);
                                 const uint32_t oj = (uint32_t)col2(cl, j) * (uint32_t)sizeof(T);
                                 vr[jj] = ev.ld(oj, 0);
                                 vi[jj] = ev.ld(oj, nb);
@@ -765,7 +777,7 @@ __global__ __launch_bounds__(256) void k_relax_st2d_split(Geo g, int colour, T w
                                                           const T* __restrict__ ein, T* __restrict__ eout, int nrhs,
                                                           int64_t stride, int rpb, const T* __restrict__ cre,
                                                           const T* __restrict__ cim, int64_t lanes) {
-    constexpr int D = 2, R = 2 * D + 1, NF = St<2>::NF, NT = NF + St<2>::NUP, HT = 11;
+    constexpr int D = 2, R = 2 * D + 1, NF = St<2>::NF, NUP = St<2>::NUP, NT = NF + NUP, HT = 11;
     constexpr int T_SELF = St<2>::CF, T_NHI = St<2>::CF + 1, T_PLO = NF + 2, T_PHI = NF + 3;
     __shared__ T part[2][2][2][64];   // [r parity][cell group of the block][re, im][lane]
     {
@@ -803,6 +815,7 @@ __global__ __launch_bounds__(256) void k_relax_st2d_split(Geo g, int colour, T w
     const bool slot_ok = gl < lanes;
     const Buf<T> cR(cre, (uint32_t)(NT * lanes * sizeof(T))), cI(cim, (uint32_t)(NF * lanes * sizeof(T)));
     const uint32_t lo = (uint32_t)(slot_ok ? gl : 0) * (uint32_t)sizeof(T), ls = (uint32_t)lanes * (uint32_t)sizeof(T);
+    const uint32_t lq = k == 3 ? OOB_OFF : lo;   // pressure rows: skip the slots stored as zeros
     const uint32_t vb = 2 * (uint32_t)g.N * (uint32_t)sizeof(T), nb = (uint32_t)g.N * (uint32_t)sizeof(T);
     const bool lowrow = row < 2 * D && (row & 1) == 0;
     VankaBlock<D, T> V;
@@ -816,8 +829,8 @@ __global__ __launch_bounds__(256) void k_relax_st2d_split(Geo g, int colour, T w
 #pragma unroll
                 for (int jj = 0; jj < NT - HT; ++jj) {
                     const int j = HT + jj;
-                    cr_[jj] = cR.ld(lo, j * ls);
-                    ci_[jj] = j < NF ? cI.ld(lo, j * ls) : T(0);
+                    cr_[jj] = cR.ld(j > 2 * NUP ? lq : lo, j * ls);
+                    ci_[jj] = j < NF ? cI.ld(lq, j * ls) : T(0);
                     const uint32_t o = (uint32_t)col2(cc, j) * (uint32_t)sizeof(T);
                     vr[jj] = ev.ld(o, 0);
                     vi[jj] = ev.ld(o, nb);
@@ -839,7 +852,7 @@ __global__ __launch_bounds__(256) void k_relax_st2d_split(Geo g, int colour, T w
 #pragma unroll
                 for (int jj = 0; jj < HT; ++jj) {
                     cr_[jj] = cR.ld(lo, jj * ls);
-                    ci_[jj] = cI.ld(lo, jj * ls);
+                    ci_[jj] = cI.ld(lq, jj * ls);
                     const uint32_t o = (uint32_t)col2(cc, jj) * (uint32_t)sizeof(T);
                     vr[jj] = ev.ld(o, 0);
                     vi[jj] = ev.ld(o, nb);
@@ -884,7 +897,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_apply_st2d(Geo g, const T* __restrict__ x, const T* __restrict__ b,
                                                     T* __restrict__ y, int nrhs, int64_t stride, int rpb,
                                                     const T* __restrict__ cre, const T* __restrict__ cim) {
-    constexpr int NF = St<2>::NF, NT = NF + St<2>::NUP;
+    constexpr int NF = St<2>::NF, NUP = St<2>::NUP, NT = NF + NUP;
     {
         const int rb0 = blockIdx.y * rpb;
         x += rb0 * stride;
@@ -905,12 +918,13 @@ __global__ __launch_bounds__(256) void k_apply_st2d(Geo g, const T* __restrict__
     const Cols2 cc = cols2(g, k, p);
     const Buf<T> cR(cre, (uint32_t)(NT * N * sizeof(T))), cI(cim, (uint32_t)(NF * N * sizeof(T)));
     const uint32_t lo = (uint32_t)t * (uint32_t)sizeof(T), ls = (uint32_t)N * (uint32_t)sizeof(T);
-    // unused terms of the pressure rows are stored as zeros
+    // unused terms of the pressure rows are stored as zeros, and not read
+    const uint32_t lq = k == 3 ? OOB_OFF : lo;
     T are[NT], aim[NF];
 #pragma unroll
-    for (int j = 0; j < NT; ++j) are[j] = cR.ld(lo, j * ls);
+    for (int j = 0; j < NT; ++j) are[j] = cR.ld(j > 2 * NUP ? lq : lo, j * ls);
 #pragma unroll
-    for (int j = 0; j < NF; ++j) aim[j] = cI.ld(lo, j * ls);
+    for (int j = 0; j < NF; ++j) aim[j] = cI.ld(lq, j * ls);
     const uint32_t vb = 2 * ls;
     for (int r = 0; r < nrhs; ++r) {
         const Buf<T> xv(x + r * stride, vb);
@@ -2798,7 +2812,9 @@ bool stored_plan_wanted(const Geo& g, bool fine) {
     static const bool on = env_int("EHH_SPLAN", 1) != 0;
     static const bool on3 = env_int("EHH_SPLAN3D", 1) != 0;
     // the kernels address the stored rows and the vectors with 32-bit byte offsets
-    const int64_t NT = g.dim == 2 ? St<2>::NF + St<2>::NUP : St<3>::NF + St<3>::NUP, lim = int64_t(1) << 32;
+    // (2D: below 2 GiB, which keeps the pressure rows' skipped slots out of range)
+    const int64_t NT = g.dim == 2 ? St<2>::NF + St<2>::NUP : St<3>::NF + St<3>::NUP;
+    const int64_t lim = g.dim == 2 ? int64_t(1) << 31 : int64_t(1) << 32;
     return on && (g.dim == 2 || on3) && !fine && NT * stored_plan_lanes(g) * 8 < lim && NT * g.N * 8 < lim &&
            16 * g.N < lim;
 }
