@@ -1401,13 +1401,13 @@ __global__ __launch_bounds__(256) void k_relax_cell2d(FineOp<2, T> op, int colou
     const U kb = E * (U)iu1(x, vb ? y : 1), kt = E * (U)iu1(x, vt ? y + 1 : 1);
     const U kp = E * (U)ip(x, y), kpo = E * (U)ip(xo, y);
     const U ud0 = E * (U)d0, un0 = E * (U)n0;
-    const U sl_n = l_nlo ? 0u - E : 0u, sr_n = r_nhi ? E : 0u;
-    const U sl_th = wl_thi != T(0) ? ud0 : 0u, sl_tl = wl_tlo != T(0) ? 0u - ud0 : 0u;
-    const U sr_th = wr_thi != T(0) ? ud0 : 0u, sr_tl = wr_tlo != T(0) ? 0u - ud0 : 0u;
-    const U sb_n = b_nlo ? 0u - un0 : 0u, st_n = t_nhi ? un0 : 0u;
-    const U sb_th = wb_thi != T(0) ? E : 0u, sb_tl = wb_tlo != T(0) ? 0u - E : 0u;
-    const U st_th = wt_thi != T(0) ? E : 0u, st_tl = wt_tlo != T(0) ? 0u - E : 0u;
-    const U sp_l = vl ? 0u - E : 0u, sp_r = vr ? E : 0u, sp_b = vb ? 0u - un0 : 0u, sp_t = vt ? un0 : 0u;
+    // which neighbours exist, one bit each; the offsets are formed from these bits
+    // inside the loop over sources, so that they hold no registers across it
+    const U nzm = (l_nlo ? 1u : 0u) | (r_nhi ? 2u : 0u) | (wl_thi != T(0) ? 4u : 0u) | (wl_tlo != T(0) ? 8u : 0u) |
+                  (wr_thi != T(0) ? 16u : 0u) | (wr_tlo != T(0) ? 32u : 0u) | (b_nlo ? 64u : 0u) |
+                  (t_nhi ? 128u : 0u) | (wb_thi != T(0) ? 256u : 0u) | (wb_tlo != T(0) ? 512u : 0u) |
+                  (wt_thi != T(0) ? 1024u : 0u) | (wt_tlo != T(0) ? 2048u : 0u) | (vl ? 4096u : 0u) |
+                  (vr ? 8192u : 0u) | (vb ? 16384u : 0u) | (vt ? 32768u : 0u);
     const U NB = E * (U)g.N;   // bytes of one plane (real or imaginary parts)
     const U VB = 2 * NB;       // bytes of one right-hand side's vector
     for (int r = r_begin; r < r_end; ++r) {
@@ -1422,6 +1422,14 @@ __global__ __launch_bounds__(256) void k_relax_cell2d(FineOp<2, T> op, int colou
         if (ein) {
             const Buf<T> ei(ein + (int64_t)r * stride, VB);
             auto ld = [&](U i) { return mk<T>(ei.ld(i), ei.ld(NB + i)); };
+            U nz = nzm;
+            asm volatile("" : "+v"(nz));
+            // offset s where bit b of nz is set, else 0
+            auto on = [&](int b, U s) { return (0u - ((nz >> b) & 1u)) & s; };
+            const U sl_n = on(0, 0u - E), sr_n = on(1, E), sl_th = on(2, ud0), sl_tl = on(3, 0u - ud0);
+            const U sr_th = on(4, ud0), sr_tl = on(5, 0u - ud0), sb_n = on(6, 0u - un0), st_n = on(7, un0);
+            const U sb_th = on(8, E), sb_tl = on(9, 0u - E), st_th = on(10, E), st_tl = on(11, 0u - E);
+            const U sp_l = on(12, 0u - E), sp_r = on(13, E), sp_b = on(14, 0u - un0), sp_t = on(15, un0);
             // every load of the iteration is issued before the arithmetic
             el = ld(kl);
             ere = ld(kr);
@@ -1595,12 +1603,15 @@ __global__ __launch_bounds__(256) void k_relax_cell3d(FineOp<3, T> op, int colou
     T cpl[3];                      // in-block coupling -mu(c) (0 if a face is absent)
     T wn_lo[3], wn_hi[3];          // outer normal neighbours
     T wt_lo[3][4], wt_hi[3][4];    // tangential neighbours: (t1+, t1-, t2+, t2-)
-    U klo[3], khi[3], sn_lo[3], sn_hi[3], st_lo[3][4], st_hi[3][4];
+    U klo[3], khi[3];
+    // which neighbours exist, 12 bits per component (outer normal lo / hi,
+    // tangential lo 0..3, tangential hi 0..3, pressure lo / hi): the neighbour
+    // offsets are formed from these bits inside the loop over sources, so that
+    // they hold no registers across it
+    U nzm[3];
     const T mu_k = op.mu_c(c);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const int d0 = n[0] - (k == 0), d1 = n[1] - (k == 1);
-        const U sk[3] = {E, E * (U)d0, E * (U)d0 * (U)d1};   // byte strides of component k
         const int t1 = tang1<3>(k), t2 = tang2<3>(k);
         int pl[3] = {c[0], c[1], c[2]}, ph[3] = {c[0], c[1], c[2]};
         ph[k] += 1;
@@ -1622,8 +1633,7 @@ __global__ __launch_bounds__(256) void k_relax_cell3d(FineOp<3, T> op, int colou
         pch[k] = vhi[k] ? c[k] + 1 : 1;
         klo[k] = E * (U)(g.off[k]) + E * (U)face_idx<3>(g, k, pcl);
         khi[k] = E * (U)(g.off[k]) + E * (U)face_idx<3>(g, k, pch);
-        sn_lo[k] = nl ? 0u - sk[k] : 0u;
-        sn_hi[k] = nh ? sk[k] : 0u;
+        U m = (nl ? 1u : 0u) | (nh ? 2u : 0u) | (vlo[k] ? 1u << 10 : 0u) | (vhi[k] ? 1u << 11 : 0u);
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int ta = j == 0 ? t1 : t2;
@@ -1632,11 +1642,13 @@ __global__ __launch_bounds__(256) void k_relax_cell3d(FineOp<3, T> op, int colou
             wt_lo[k][2 * j + 1] = (vlo[k] && dn_ok) ? -op.mu_edge(k, pl, ta, c[ta]) : T(0);
             wt_hi[k][2 * j] = (vhi[k] && up_ok) ? -op.mu_edge(k, ph, ta, c[ta] + 1) : T(0);
             wt_hi[k][2 * j + 1] = (vhi[k] && dn_ok) ? -op.mu_edge(k, ph, ta, c[ta]) : T(0);
-            st_lo[k][2 * j] = wt_lo[k][2 * j] != T(0) ? sk[ta] : 0u;
-            st_lo[k][2 * j + 1] = wt_lo[k][2 * j + 1] != T(0) ? 0u - sk[ta] : 0u;
-            st_hi[k][2 * j] = wt_hi[k][2 * j] != T(0) ? sk[ta] : 0u;
-            st_hi[k][2 * j + 1] = wt_hi[k][2 * j + 1] != T(0) ? 0u - sk[ta] : 0u;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                m |= (wt_lo[k][2 * j + h] != T(0) ? 1u : 0u) << (2 + 2 * j + h);
+                m |= (wt_hi[k][2 * j + h] != T(0) ? 1u : 0u) << (6 + 2 * j + h);
+            }
         }
+        nzm[k] = m;
     }
     const T pdiag = -op.c.dinv[cell_idx<3>(g, c)];
     // block inverse: per component [[d_lo, c], [c, d_hi]]^{-1}; g = (+1, -1) on present faces
@@ -1661,11 +1673,14 @@ __global__ __launch_bounds__(256) void k_relax_cell3d(FineOp<3, T> op, int colou
     int co[3] = {xo, y, z};
     const U kpo = E * (U)(g.off[3] + cell_idx<3>(g, co));
     const U pstride[3] = {E, E * (U)n[0], E * (U)n[0] * (U)n[1]};
-    U sp_lo[3], sp_hi[3];
+    // byte strides of component k's faces along each axis
+    U fst[3][3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        sp_lo[k] = vlo[k] ? 0u - pstride[k] : 0u;
-        sp_hi[k] = vhi[k] ? pstride[k] : 0u;
+        const U d0 = (U)(n[0] - (k == 0)), d1 = (U)(n[1] - (k == 1));
+        fst[k][0] = E;
+        fst[k][1] = E * d0;
+        fst[k][2] = E * d0 * d1;
     }
     const U NB = E * (U)g.N, VB = 2 * NB;
     for (int r = r_begin; r < r_end; ++r) {
@@ -1686,19 +1701,28 @@ __global__ __launch_bounds__(256) void k_relax_cell3d(FineOp<3, T> op, int colou
             const Buf<T> ei(ein + (int64_t)r * stride, VB);
             auto ld = [&](U i) { return mk<T>(ei.ld(i), ei.ld(NB + i)); };
             cx<T> nlo[3], nhi[3], tlo[3][4], thi[3][4], plo[3], phi[3];
+            U nz[3] = {nzm[0], nzm[1], nzm[2]};
+            asm volatile("" : "+v"(nz[0]), "+v"(nz[1]), "+v"(nz[2]));
+            // offset +s or -s where bit b of nz[k] is set, else 0
+            auto pos = [&](int k, int b, U s) { return (0u - ((nz[k] >> b) & 1u)) & s; };
+            auto neg = [&](int k, int b, U s) { return (0u - ((nz[k] >> b) & 1u)) & (0u - s); };
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
+                const int t1 = tang1<3>(k), t2 = tang2<3>(k);
                 elo[k] = ld(klo[k]);
                 ehi[k] = ld(khi[k]);
-                nlo[k] = ld(klo[k] + sn_lo[k]);
-                nhi[k] = ld(khi[k] + sn_hi[k]);
+                nlo[k] = ld(klo[k] + neg(k, 0, fst[k][k]));
+                nhi[k] = ld(khi[k] + pos(k, 1, fst[k][k]));
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    tlo[k][j] = ld(klo[k] + st_lo[k][j]);
-                    thi[k][j] = ld(khi[k] + st_hi[k][j]);
+                for (int j = 0; j < 2; ++j) {
+                    const U sa = fst[k][j == 0 ? t1 : t2];
+                    tlo[k][2 * j] = ld(klo[k] + pos(k, 2 + 2 * j, sa));
+                    tlo[k][2 * j + 1] = ld(klo[k] + neg(k, 3 + 2 * j, sa));
+                    thi[k][2 * j] = ld(khi[k] + pos(k, 6 + 2 * j, sa));
+                    thi[k][2 * j + 1] = ld(khi[k] + neg(k, 7 + 2 * j, sa));
                 }
-                plo[k] = ld(kp + sp_lo[k]);
-                phi[k] = ld(kp + sp_hi[k]);
+                plo[k] = ld(kp + neg(k, 10, pstride[k]));
+                phi[k] = ld(kp + pos(k, 11, pstride[k]));
             }
             ep = ld(kp);
             epo = ld(kpo);
