@@ -1518,23 +1518,31 @@ __global__ __launch_bounds__(256) void k_apply_cell2d(FineOp<2, T> op, const T* 
     const int cc[3] = {cx_, cy, 0};
     const T pdiag = -op.c.dinv[cell_idx<2>(g, cc)];
     // neighbour offsets relative to the owned unknowns (0 where the weight is 0)
+    // and the p row's faces right (u_0 at cx+1) and top (u_1 at cy+1) when
+    // interior: one bit each, the offsets and signs formed inside the loop over
+    // sources, so that they hold no registers across it
     const U ud0 = E * (U)d0, un0 = E * (U)n0;
-    const U su_nh = wu_nh != T(0) ? E : 0u, su_nl = wu_nl != T(0) ? 0u - E : 0u;
-    const U su_th = wu_th != T(0) ? ud0 : 0u, su_tl = wu_tl != T(0) ? 0u - ud0 : 0u;
-    const U sv_nh = wv_nh != T(0) ? un0 : 0u, sv_nl = wv_nl != T(0) ? 0u - un0 : 0u;
-    const U sv_th = wv_th != T(0) ? E : 0u, sv_tl = wv_tl != T(0) ? 0u - E : 0u;
     const bool pl = cx_ >= 1, pb = cy >= 1;           // cells left and below exist
-    const U sp_l = pl ? 0u - E : 0u, sp_b = pb ? 0u - un0 : 0u;
-    // the p row: faces right (u_0 at cx+1) and top (u_1 at cy+1) when interior
     const bool fr = cx_ + 1 <= n0 - 1, ft = cy + 1 <= n1 - 1;
-    const U kur = fr ? E * (U)(g.off[0] + (int64_t)cy * d0 + cx_) : ku;
-    const U kvt = ft ? E * (U)(g.off[1] + (int64_t)cy * n0 + cx_) : kv;
-    const T gr = fr ? T(-1) : T(0), gl = vu ? T(1) : T(0), gt = ft ? T(-1) : T(0), gb = vv ? T(1) : T(0);
+    const U nzm = (wu_nh != T(0) ? 1u : 0u) | (wu_nl != T(0) ? 2u : 0u) | (wu_th != T(0) ? 4u : 0u) |
+                  (wu_tl != T(0) ? 8u : 0u) | (wv_nh != T(0) ? 16u : 0u) | (wv_nl != T(0) ? 32u : 0u) |
+                  (wv_th != T(0) ? 64u : 0u) | (wv_tl != T(0) ? 128u : 0u) | (pl ? 256u : 0u) | (pb ? 512u : 0u) |
+                  (fr ? 1024u : 0u) | (ft ? 2048u : 0u) | (vu ? 4096u : 0u) | (vv ? 8192u : 0u) |
+                  (fr && vu ? 16384u : 0u) | (ft && vv ? 32768u : 0u);
     const U NB = E * (U)g.N, VB = 2 * NB;
     for (int r = r_begin; r < r_end; ++r) {
         const Buf<T> xb(x + (int64_t)r * stride, VB);
         const Buf<T> yb(y + (int64_t)r * stride, VB);
         auto ld = [&](U i) { return mk<T>(xb.ld(i), xb.ld(NB + i)); };
+        U nz = nzm;
+        asm volatile("" : "+v"(nz));
+        auto bit = [&](int b_) { return ((nz >> b_) & 1u) != 0u; };
+        auto on = [&](int b_, U s_) { return (0u - ((nz >> b_) & 1u)) & s_; };
+        const U su_nh = on(0, E), su_nl = on(1, 0u - E), su_th = on(2, ud0), su_tl = on(3, 0u - ud0);
+        const U sv_nh = on(4, un0), sv_nl = on(5, 0u - un0), sv_th = on(6, E), sv_tl = on(7, 0u - E);
+        const U sp_l = on(8, 0u - E), sp_b = on(9, 0u - un0);
+        const U kur = ku + on(14, E), kvt = kv + on(15, un0);   // the faces right and top
+        auto keep = [&](int b_, cx<T> v) { return bit(b_) ? v : mk<T>(T(0), T(0)); };
         // every load of the iteration is issued before the arithmetic (the
         // scheduler would otherwise wait on each load in turn)
         const cx<T> xu = ld(ku), xv = ld(kv), xp = ld(kp);
@@ -1552,7 +1560,7 @@ __global__ __launch_bounds__(256) void k_apply_cell2d(FineOp<2, T> op, const T* 
         __builtin_amdgcn_sched_barrier(0);
         cx<T> au = du * xu + wu_nh * u_nh + wu_nl * u_nl + wu_th * u_th + wu_tl * u_tl + (xp - xpl);
         cx<T> av = dv * xv + wv_nh * v_nh + wv_nl * v_nl + wv_th * v_th + wv_tl * v_tl + (xp - xpb);
-        cx<T> ap = pdiag * xp + gr * x_r + gl * xu + gt * x_t + gb * xv;
+        cx<T> ap = pdiag * xp - keep(10, x_r) + keep(12, xu) - keep(11, x_t) + keep(13, xv);
         if (b) {
             au = b_u - au;
             av = b_v - av;
@@ -1787,12 +1795,18 @@ __global__ __launch_bounds__(256) void k_apply_cell3d(FineOp<3, T> op, const T* 
     bool v[3];
     cx<T> dg[3];
     T wnh[3], wnl[3], wt[3][4];
-    U ku[3], snh[3], snl[3], st[3][4], khi[3];
-    T ghi[3];
+    U ku[3], fst[3][3];
+    // which neighbours exist, 10 bits per component (normal hi / lo, tangential
+    // 0..3, pressure below, upper face interior, and the two combined for the
+    // upper face's offset): the offsets are formed inside the loop over sources,
+    // so that they hold no registers across it
+    U nzm[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int d0 = n[0] - (k == 0), d1 = n[1] - (k == 1);
-        const U sk[3] = {E, E * (U)d0, E * (U)d0 * (U)d1};
+        fst[k][0] = E;
+        fst[k][1] = E * (U)d0;
+        fst[k][2] = E * (U)d0 * (U)d1;
         const int t1 = tang1<3>(k), t2 = tang2<3>(k);
         v[k] = c[k] >= 1;
         int pc[3] = {c[0], c[1], c[2]};
@@ -1815,43 +1829,44 @@ __global__ __launch_bounds__(256) void k_apply_cell3d(FineOp<3, T> op, const T* 
                 if (c[ta] - 1 >= 0) wt[k][2 * j + 1] = -op.mu_edge(k, c, ta, c[ta]);
             }
         }
-        snh[k] = wnh[k] != T(0) ? sk[k] : 0u;
-        snl[k] = wnl[k] != T(0) ? 0u - sk[k] : 0u;
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int ta = j == 0 ? t1 : t2;
-            st[k][2 * j] = wt[k][2 * j] != T(0) ? sk[ta] : 0u;
-            st[k][2 * j + 1] = wt[k][2 * j + 1] != T(0) ? 0u - sk[ta] : 0u;
-        }
-        // the p row's upper face of component k (face c[k] + 1), when interior
+        // the p row's upper face of component k (face c[k] + 1), when interior:
+        // the next face along axis k, or the owned face itself when that is
+        // absent (then c[k] = 0 and the clamped owned face is face 1)
         const bool fh = c[k] + 1 <= n[k] - 1;
-        int ph[3] = {c[0], c[1], c[2]};
-        ph[k] = fh ? c[k] + 1 : 1;
-        khi[k] = E * (U)(g.off[k] + face_idx<3>(g, k, ph));
-        ghi[k] = fh ? T(-1) : T(0);
+        U m = (wnh[k] != T(0) ? 1u : 0u) | (wnl[k] != T(0) ? 2u : 0u) | (v[k] ? 64u : 0u) | (fh ? 128u : 0u) |
+              (fh && v[k] ? 256u : 0u);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) m |= (wt[k][j] != T(0) ? 1u : 0u) << (2 + j);
+        nzm[k] = m;
     }
     const T pdiag = -op.c.dinv[t];
     const U kp = E * (U)(g.off[3] + t);
     const U pstr[3] = {E, E * (U)n[0], E * (U)n[0] * (U)n[1]};
-    U spl[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) spl[k] = v[k] ? 0u - pstr[k] : 0u;
     const U NB = E * (U)g.N, VB = 2 * NB;
     for (int r = r_begin; r < r_end; ++r) {
         const Buf<T> xb(x + (int64_t)r * stride, VB);
         const Buf<T> yb(y + (int64_t)r * stride, VB);
         auto ld = [&](U i) { return mk<T>(xb.ld(i), xb.ld(NB + i)); };
+        U nz[3] = {nzm[0], nzm[1], nzm[2]};
+        asm volatile("" : "+v"(nz[0]), "+v"(nz[1]), "+v"(nz[2]));
+        auto on = [&](int k, int b_, U s_) { return (0u - ((nz[k] >> b_) & 1u)) & s_; };
+        auto keep = [&](int k, int b_, cx<T> val) { return ((nz[k] >> b_) & 1u) ? val : mk<T>(T(0), T(0)); };
         cx<T> xu[3], xnh[3], xnl[3], xt[3][4], xpl[3], xh[3], bu[3];
         const cx<T> xp = ld(kp);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
+            const int t1 = tang1<3>(k), t2 = tang2<3>(k);
             xu[k] = ld(ku[k]);
-            xnh[k] = ld(ku[k] + snh[k]);
-            xnl[k] = ld(ku[k] + snl[k]);
+            xnh[k] = ld(ku[k] + on(k, 0, fst[k][k]));
+            xnl[k] = ld(ku[k] + on(k, 1, 0u - fst[k][k]));
 #pragma unroll
-            for (int j = 0; j < 4; ++j) xt[k][j] = ld(ku[k] + st[k][j]);
-            xpl[k] = ld(kp + spl[k]);
-            xh[k] = ld(khi[k]);
+            for (int j = 0; j < 2; ++j) {
+                const U sa = fst[k][j == 0 ? t1 : t2];
+                xt[k][2 * j] = ld(ku[k] + on(k, 2 + 2 * j, sa));
+                xt[k][2 * j + 1] = ld(ku[k] + on(k, 3 + 2 * j, 0u - sa));
+            }
+            xpl[k] = ld(kp + on(k, 6, 0u - pstr[k]));
+            xh[k] = ld(ku[k] + on(k, 8, fst[k][k]));
         }
         cx<T> bp = mk<T>(T(0), T(0));
 #pragma unroll
@@ -1874,7 +1889,7 @@ __global__ __launch_bounds__(256) void k_apply_cell3d(FineOp<3, T> op, const T* 
                 yb.st(ku[k], au.re);
                 yb.st(NB + ku[k], au.im);
             }
-            ap = ap + ghi[k] * xh[k] + (v[k] ? T(1) : T(0)) * xu[k];
+            ap = ap - keep(k, 7, xh[k]) + keep(k, 6, xu[k]);
         }
         if (b) ap = bp - ap;
         yb.st(kp, ap.re);
