@@ -1043,6 +1043,10 @@ EHH_DEV void rows3_rb(const Buf<T>& cR, const Buf<T>& cI, uint32_t lo, uint32_t 
 #pragma unroll
         for (int q = 0; q < RB; ++q) asm volatile("" ::"v"(ar[q]), "v"(ai[q]));
         asm volatile("" : "+v"(cl.self), "+v"(cl.pc), "+v"(cl.f[0]), "+v"(cl.f[1]), "+v"(cl.f[2]), "+v"(lh));
+        // the strides too, so that no column offset is formed ahead of its chunk
+        asm volatile("" : "+v"(cl.sn), "+v"(cl.s1), "+v"(cl.s2), "+v"(cl.cn), "+v"(cl.c1), "+v"(cl.c2));
+        asm volatile("" : "+v"(cl.fs[0][1]), "+v"(cl.fs[0][2]), "+v"(cl.fs[1][1]), "+v"(cl.fs[1][2]),
+                     "+v"(cl.fs[2][1]), "+v"(cl.fs[2][2]), "+v"(cl.last));
         T cr[CH], ci[CH], vr[CH][RB], vi[CH][RB];
 #pragma unroll
         for (int jj = 0; jj < CH; ++jj) {
@@ -1145,19 +1149,33 @@ __global__ __launch_bounds__(256) void k_relax_st3d(Geo g, int colour, T w, int 
             for (int q = 0; q < RB; ++q) ev[q] = ein + (r0 + q < nrhs ? r0 + q : r0) * stride;
             rows3_rb<T, RB, CH>(cR, cI, lo, ls, cc, ev, vb, nb, ar, ai);
         }
+        // the row's own unknown and the carried pressure as 32-bit byte offsets
+        // into buffer descriptors (wave-uniform bases), formed here so that no
+        // per-source address is kept across the row loop
+        uint32_t oi = (uint32_t)idx * (uint32_t)sizeof(T), ob = (uint32_t)ipb * (uint32_t)sizeof(T);
+        asm volatile("" : "+v"(oi), "+v"(ob));
 #pragma unroll
         for (int q = 0; q < RB; ++q) {
             const int r = r0 + q;
             if (r >= nrhs) break;
+            const Buf<T> bq(b + r * stride, vb), oq(eout + r * stride, vb);
+            const Buf<T> eq(ein ? ein + r * stride : b, vb);
             cx<T> res = mk<T>(T(0), T(0)), eown = mk<T>(T(0), T(0));
             if (ok) {
-                res = CVec<T>{b + r * stride, g.N}.ld(idx) - mk<T>(ar[q], ai[q]);
-                if (ein) eown = CVec<T>{ein + r * stride, g.N}.ld(idx);
+                res = mk<T>(bq.ld(oi, 0), bq.ld(oi, nb)) - mk<T>(ar[q], ai[q]);
+                if (ein) eown = mk<T>(eq.ld(oi, 0), eq.ld(oi, nb));
             }
             const cx<T> mine = V.solve(res, base, row);
-            const Vec<T> ov{eout + r * stride, g.N};
-            if (ok) ov.st(idx, eown + w * mine);
-            if (carry) ov.st(ipb, ein ? CVec<T>{ein + r * stride, g.N}.ld(ipb) : mk<T>(T(0), T(0)));
+            if (ok) {
+                const cx<T> v = eown + w * mine;
+                oq.st(oi, v.re);
+                oq.st(oi + nb, v.im);
+            }
+            if (carry) {
+                const cx<T> v = ein ? mk<T>(eq.ld(ob, 0), eq.ld(ob, nb)) : mk<T>(T(0), T(0));
+                oq.st(ob, v.re);
+                oq.st(ob + nb, v.im);
+            }
         }
     }
 }
@@ -1195,13 +1213,22 @@ __global__ __launch_bounds__(256) void k_apply_st3d(Geo g, const T* __restrict__
         for (int q = 0; q < RB; ++q) xv[q] = x + (r0 + q < nrhs ? r0 + q : r0) * stride;
         T ar[RB], ai[RB];
         rows3_rb<T, RB, CH>(cR, cI, lo, ls, cc, xv, vb, ls, ar, ai);
+        // per-source buffer descriptors (wave-uniform bases) and the row's byte
+        // offset formed here, so that no per-source address is kept across the row
+        uint32_t ot = lo;
+        asm volatile("" : "+v"(ot));
 #pragma unroll
         for (int q = 0; q < RB; ++q) {
             const int r = r0 + q;
             if (r >= nrhs) break;
             cx<T> o = mk<T>(ar[q], ai[q]);
-            if (b) o = CVec<T>{b + r * stride, g.N}.ld(t) - o;
-            Vec<T>{y + r * stride, g.N}.st(t, o);
+            if (b) {
+                const Buf<T> bq(b + r * stride, vb);
+                o = mk<T>(bq.ld(ot, 0), bq.ld(ot, ls)) - o;
+            }
+            const Buf<T> yq(y + r * stride, vb);
+            yq.st(ot, o.re);
+            yq.st(ot + ls, o.im);
         }
     }
 }
