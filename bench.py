@@ -135,7 +135,7 @@ def relax_kernel_name(w, level, ncell):
         return f"k_relax_st2d<{t}, {'true' if t == 'float' else 'false'}, false>"
     if level == 0:
         return f"k_relax_cell3d<{t}>"
-    return f"k_relax_st3d<{t}, 8, 4>" if t == "float" else f"k_relax_st3d<{t}, 2, 4>"
+    return f"k_relax_st3d<{t}, 8, 8>" if t == "float" else f"k_relax_st3d<{t}, 2, 4>"
 
 
 KERNEL_SOURCES = ["paper_1806_11277_amd/csrc/levels.hip", "paper_1806_11277_amd/csrc/ops.hpp",

@@ -2811,10 +2811,12 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
                            L.sp.im[colour], L.sp.lanes);                                                          \
     }
             // measured on MI355X (36^3 level, 16 FP32 sources): 8 sources per
-            // coefficient load in chunks of 4 terms 331 us; 8 x 2: 335 us,
-            // 4 x 4: 358 us, 16 x 2: 322 us but 2x slower on 18^3
+            // coefficient load in chunks of 8 terms 284 us, of 4 terms 299 us
+            // (both two wavefronts per SIMD); with the row-loop addresses held
+            // across the loop (one wavefront per SIMD) 8 x 4 took 331 us, 8 x 2
+            // 335 us, 4 x 4 358 us, 16 x 2 322 us but 2x slower on 18^3
             if (sizeof(T) == 8) EHH_RELAX_ST3D(2, 4)
-            else EHH_RELAX_ST3D(8, 4)
+            else EHH_RELAX_ST3D(8, 8)
 #undef EHH_RELAX_ST3D
         } else
             EHH_RB_DISPATCH(rb3, hipLaunchKernelGGL((k_relax<3, T, StOp<3, T>, RB>), gb3, 256, 0, s, StOp<3, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb3));
