@@ -579,14 +579,16 @@ __global__ __launch_bounds__(1024) void k_diag_inverse(double* __restrict__ A, i
 // C[i][j] = (beta_one ? C[i][j] : 0) + alpha sum_k A[i][k] B[k][j] on one 64 x 64
 // output tile (complex, interleaved, row-major; leading dimensions in complex
 // elements).  Rows in [rh_lo, rh_hi) and columns in [ch_lo, ch_hi) of C are left
-// untouched.  All reads of a tile's operands finish before its writes, so C may
-// alias the operand that only this tile reads.
+// untouched, and so is the output tile at (skip_r0, skip_c0) (-1: none).  All
+// reads of a tile's operands finish before its writes, so C may alias the
+// operand that only this tile reads.
 __global__ __launch_bounds__(256) void k_zgemm_tile(double* C, int64_t ldc, const double* A, int64_t lda,
                                                     const double* B, int64_t ldb, int64_t m, int64_t ncol, int kdim,
                                                     double alpha, int beta_one, int64_t rh_lo, int64_t rh_hi,
-                                                    int64_t ch_lo, int64_t ch_hi) {
+                                                    int64_t ch_lo, int64_t ch_hi, int64_t skip_r0, int64_t skip_c0) {
     const int64_t row0 = (int64_t)blockIdx.y * 64, col0 = (int64_t)blockIdx.x * 64;
     if ((row0 >= rh_lo && row0 + 64 <= rh_hi) || (col0 >= ch_lo && col0 + 64 <= ch_hi)) return;
+    if (row0 == skip_r0 && col0 == skip_c0) return;
     __shared__ double As[16][65 * 2];
     __shared__ double Bs[16][64 * 2];
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
@@ -669,28 +671,71 @@ __global__ __launch_bounds__(256) void k_permute_columns(const double* __restric
     out[2 * (i * n + j) + 1] = X[2 * (i * n + src) + 1];
 }
 
+// The next panel's diagonal block depends only on its own tile of the trailing
+// update, so a second stream updates that tile and inverts it while the first
+// runs the rest of the update (the inversion is one workgroup and would
+// otherwise leave the device idle for its whole duration).
 hipError_t launch_dense_invert(double* A, int64_t n, int* piv, int* flag, hipStream_t s) {
     hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), s);
     if (e != hipSuccess) return e;
+    hipStream_t s2 = nullptr;
+    hipEvent_t ev_row = nullptr, ev_tile = nullptr, ev_diag = nullptr;
+    auto cleanup = [&]() {
+        if (ev_row) (void)hipEventDestroy(ev_row);
+        if (ev_tile) (void)hipEventDestroy(ev_tile);
+        if (ev_diag) (void)hipEventDestroy(ev_diag);
+        if (s2) (void)hipStreamDestroy(s2);
+    };
+    if (n > GJ_NB) {
+        if ((e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&ev_row, hipEventDisableTiming)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&ev_tile, hipEventDisableTiming)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&ev_diag, hipEventDisableTiming)) != hipSuccess) {
+            cleanup();
+            return e;
+        }
+    }
+    const unsigned tiles = (unsigned)((n + 63) / 64);
     for (int64_t k0 = 0; k0 < n; k0 += GJ_NB) {
         const int kb = (int)std::min<int64_t>(GJ_NB, n - k0);
-        hipLaunchKernelGGL(k_diag_inverse, 1, 1024, 0, s, A, n, k0, kb, piv, flag);
+        const int64_t k1 = k0 + kb;   // first index of the next panel
+        if (k0 == 0)
+            hipLaunchKernelGGL(k_diag_inverse, 1, 1024, 0, s, A, n, k0, kb, piv, flag);
+        else if ((e = hipStreamWaitEvent(s, ev_diag, 0)) != hipSuccess)
+            break;
         hipLaunchKernelGGL(k_swap_rows, nblk(n), 256, 0, s, A, n, k0, kb, piv);
         double* AK = A + 2 * k0 * n;           // rows K
         double* AKK = AK + 2 * k0;             // the inverted block W
         double* ACK = A + 2 * k0;              // columns K
-        const unsigned tiles = (unsigned)((n + 63) / 64);
         // A[K,J] <- W A[K,J]
         hipLaunchKernelGGL(k_zgemm_tile, dim3(tiles, 1), 256, 0, s, AK, n, AKK, n, AK, n, (int64_t)kb, n, kb, 1.0, 0,
-                           (int64_t)0, (int64_t)0, k0, k0 + kb);
-        // A[I,J] <- A[I,J] - A[I,K] A[K,J]
+                           (int64_t)0, (int64_t)0, k0, k1, (int64_t)-1, (int64_t)-1);
+        int64_t skip = -1;
+        if (k1 < n) {
+            // the next diagonal tile: A[K1,K1] -= A[K1,K] A[K,K1] (A[K1,K] before
+            // its scaling below), then its inverse, on the second stream
+            const int kb1 = (int)std::min<int64_t>(GJ_NB, n - k1);
+            if ((e = hipEventRecord(ev_row, s)) != hipSuccess || (e = hipStreamWaitEvent(s2, ev_row, 0)) != hipSuccess)
+                break;
+            hipLaunchKernelGGL(k_zgemm_tile, dim3(1, 1), 256, 0, s2, A + 2 * (k1 * n + k1), n, A + 2 * (k1 * n + k0),
+                               n, A + 2 * (k0 * n + k1), n, (int64_t)kb1, (int64_t)kb1, kb, -1.0, 1, (int64_t)0,
+                               (int64_t)0, (int64_t)0, (int64_t)0, (int64_t)-1, (int64_t)-1);
+            if ((e = hipEventRecord(ev_tile, s2)) != hipSuccess) break;
+            hipLaunchKernelGGL(k_diag_inverse, 1, 1024, 0, s2, A, n, k1, kb1, piv, flag);
+            if ((e = hipEventRecord(ev_diag, s2)) != hipSuccess) break;
+            skip = k1;
+        }
+        // A[I,J] <- A[I,J] - A[I,K] A[K,J] (but the next diagonal tile)
         hipLaunchKernelGGL(k_zgemm_tile, dim3(tiles, tiles), 256, 0, s, A, n, ACK, n, AK, n, n, n, kb, -1.0, 1, k0,
-                           k0 + kb, k0, k0 + kb);
-        // A[I,K] <- -A[I,K] W
+                           k1, k0, k1, skip, skip);
+        // A[I,K] <- -A[I,K] W, once the next diagonal tile has read A[K1,K]
+        if (k1 < n && (e = hipStreamWaitEvent(s, ev_tile, 0)) != hipSuccess) break;
         hipLaunchKernelGGL(k_zgemm_tile, dim3(1, tiles), 256, 0, s, ACK, n, ACK, n, AKK, n, n, (int64_t)kb, kb, -1.0,
-                           0, k0, k0 + kb, (int64_t)0, (int64_t)0);
+                           0, k0, k1, (int64_t)0, (int64_t)0, (int64_t)-1, (int64_t)-1);
     }
-    return hipGetLastError();
+    if (e == hipSuccess) e = hipGetLastError();
+    cleanup();
+    return e;
 }
 
 hipError_t launch_permute_columns(const double* X, double* out, int64_t n, const int* qinv, hipStream_t s) {
