@@ -132,8 +132,17 @@ int32_t ehh_setup_operator(const ehh_problem_t* problem, const double* lambda,
                            const double* mu, const double* rho, const double* gamma,
                            const ehh_options_t* options, void* stream, ehh_handle_t* out);
 
-/* Release every device buffer of the handle (waits for the handle's work). */
+/* Release every device buffer of the handle (waits for the device's work).
+ * The buffers go to the library's device memory cache, from which later
+ * handles take buffers of the same size class instead of calling hipMalloc;
+ * the cache holds at most EHH_CACHE_MB MiB (environment, default 32768) and is
+ * emptied for a device when an allocation there fails. */
 void ehh_destroy(ehh_handle_t h);
+
+/* Return the cached device buffers of every device to the driver (hipFree).
+ * Handles that are alive keep their buffers.  Thread-safe; buffers released
+ * by other threads while it runs may stay cached. */
+void ehh_release_cached_memory(void);
 
 /* counts[4] = unknowns of u_0, u_1, u_2 (0 in 2D), p; *stride = 2 * N reals
  * between consecutive right-hand sides. */

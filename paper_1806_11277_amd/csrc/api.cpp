@@ -12,8 +12,11 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "ehh.h"
@@ -45,6 +48,78 @@ int32_t fail(int32_t code, const std::string& msg) {
 // Optional injected allocation failure (EHH_FAIL_ALLOC_AFTER=k: the (k+1)-th
 // device allocation of the process fails), for testing the OOM path.
 long g_alloc_count = 0;
+
+// Device memory cache.  A setup-solve-destroy cycle would otherwise pay
+// hipMalloc for every buffer and hipFree, which waits for the whole device, for
+// every release.  Released blocks are kept per device and size class (powers of
+// two up to 2 MiB, then multiples of 2 MiB) and handed to later allocations of
+// the same class.  The cache holds at most EHH_CACHE_MB MiB (default 32768), is
+// emptied for a device when hipMalloc fails there, and
+// ehh_release_cached_memory() hands it back to the driver.  A block enters the
+// cache only once the device has finished the work queued before its release
+// (the callers synchronise the device first).
+class BlockCache {
+  public:
+    static BlockCache& get() {
+        static BlockCache c;
+        return c;
+    }
+    static size_t size_class(size_t b) {
+        const size_t g = size_t(1) << 21;
+        if (b > g) return (b + g - 1) / g * g;
+        size_t c = 512;
+        while (c < b) c <<= 1;
+        return c;
+    }
+    void* take(int dev, size_t cls) {
+        std::lock_guard<std::mutex> l(m_);
+        auto it = free_.find({dev, cls});
+        if (it == free_.end() || it->second.empty()) return nullptr;
+        void* p = it->second.back();
+        it->second.pop_back();
+        cached_ -= cls;
+        return p;
+    }
+    // false: the cache is full, the caller frees the block
+    bool put(int dev, size_t cls, void* p) {
+        std::lock_guard<std::mutex> l(m_);
+        if (cached_ + cls > cap_) return false;
+        free_[{dev, cls}].push_back(p);
+        cached_ += cls;
+        return true;
+    }
+    // frees the cached blocks of device dev (every device for dev < 0)
+    void trim(int dev) {
+        std::vector<std::pair<int, void*>> out;
+        {
+            std::lock_guard<std::mutex> l(m_);
+            for (auto& kv : free_) {
+                if (dev >= 0 && kv.first.first != dev) continue;
+                for (void* p : kv.second) out.emplace_back(kv.first.first, p);
+                cached_ -= kv.first.second * kv.second.size();
+                kv.second.clear();
+            }
+        }
+        if (out.empty()) return;
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        for (auto& dp : out) {
+            (void)hipSetDevice(dp.first);
+            (void)hipFree(dp.second);
+        }
+        (void)hipSetDevice(cur);
+    }
+
+  private:
+    BlockCache() {
+        const char* v = std::getenv("EHH_CACHE_MB");
+        cap_ = (size_t)(v ? std::atol(v) : 32768L) << 20;
+    }
+    std::mutex m_;
+    std::map<std::pair<int, size_t>, std::vector<void*>> free_;
+    size_t cached_ = 0;
+    size_t cap_ = 0;
+};
 
 // EHH_LOG=1 prints the setup phases with their durations to stderr.
 bool log_enabled() {
@@ -130,7 +205,13 @@ struct ehh_ctx {
     // conjugated right-hand sides of the adjoint solve
     int adj_rhs = 0;
     double* adjb = nullptr;
-    std::vector<void*> allocs;
+    // device buffers of the handle: pointer, device and size class (BlockCache)
+    struct Block {
+        void* p;
+        int dev;
+        size_t cls;
+    };
+    std::vector<Block> allocs;
     // one captured graph per Arnoldi step j for the current batch size
     int graph_rhs = 0;
     std::vector<hipGraphExec_t> graphs;
@@ -139,8 +220,12 @@ struct ehh_ctx {
     ~ehh_ctx() {
         clear_graphs();
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
-        for (void* p : allocs) (void)hipFree(p);
+        (void)hipDeviceSynchronize();
+        for (const Block& b : allocs) give_back(b);
         if (host_pinned) (void)hipHostFree(host_pinned);
+    }
+    static void give_back(const Block& b) {
+        if (!BlockCache::get().put(b.dev, b.cls, b.p)) (void)hipFree(b.p);
     }
     void clear_graphs() {
         for (hipGraphExec_t e : graphs)
@@ -155,20 +240,37 @@ struct ehh_ctx {
         const long lim = fail_alloc_after();
         if (lim >= 0 && g_alloc_count >= lim) return fail(EHH_ERR_OOM, "injected allocation failure");
         ++g_alloc_count;
-        hipError_t e = hipMalloc(p, bytes);
-        if (e != hipSuccess) {
-            *p = nullptr;
-            (void)hipGetLastError();
-            return fail(EHH_ERR_OOM, std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        const size_t cls = BlockCache::size_class(bytes);
+        *p = BlockCache::get().take(dev, cls);
+        if (!*p) {
+            hipError_t e = hipMalloc(p, cls);
+            if (e != hipSuccess) {   // return the cached blocks to the driver and try once more
+                (void)hipGetLastError();
+                BlockCache::get().trim(dev);
+                e = hipMalloc(p, cls);
+            }
+            if (e != hipSuccess) {
+                *p = nullptr;
+                (void)hipGetLastError();
+                return fail(EHH_ERR_OOM, std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+            }
         }
-        allocs.push_back(*p);
+        allocs.push_back(Block{*p, dev, cls});
         return EHH_OK;
     }
     void release(void* p) {
         if (!p) return;
-        auto it = std::find(allocs.begin(), allocs.end(), p);
-        if (it != allocs.end()) allocs.erase(it);
-        (void)hipFree(p);
+        auto it = std::find_if(allocs.begin(), allocs.end(), [p](const Block& b) { return b.p == p; });
+        if (it == allocs.end()) {
+            (void)hipFree(p);
+            return;
+        }
+        const Block b = *it;
+        allocs.erase(it);
+        (void)hipDeviceSynchronize();   // work queued before the release may still read the block
+        give_back(b);
     }
     int bits() const { return opt.precond_bits; }
 };
@@ -853,6 +955,8 @@ void ehh_destroy(ehh_handle_t h) {
     (void)hipDeviceSynchronize();
     delete h;
 }
+
+void ehh_release_cached_memory(void) { BlockCache::get().trim(-1); }
 
 int32_t ehh_vector_layout(ehh_handle_t h, int64_t counts[4], int64_t* stride) {
     CHK(check_handle(h));

@@ -51,6 +51,7 @@ _SIGS = {
     "ehh_setup_operator": (_I, [ctypes.POINTER(ehh_problem_t), _P, _P, _P, _P,
                                 ctypes.POINTER(ehh_options_t), _P, ctypes.POINTER(_P)]),
     "ehh_destroy": (None, [_P]),
+    "ehh_release_cached_memory": (None, []),
     "ehh_vector_layout": (_I, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "ehh_scaling": (_I, [_P, ctypes.POINTER(ctypes.c_double)]),
     "ehh_apply": (_I, [_P, _I, _P, _P, _I, _P]),
@@ -106,6 +107,12 @@ def default_options() -> ehh_options_t:
     o = ehh_options_t()
     lib().ehh_default_options(ctypes.byref(o))
     return o
+
+
+def release_cached_memory():
+    """Return the library's cached device buffers (kept after Solver.close for
+    reuse by later solvers) to the driver."""
+    lib().ehh_release_cached_memory()
 
 
 def _stream(stream=None):

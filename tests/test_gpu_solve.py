@@ -181,3 +181,30 @@ def test_dd_2d_several_subdomains_per_colour(colors):
         ref = P.apply(v[r])
         assert np.linalg.norm(got[r] - ref) <= 1e-11 * np.linalg.norm(ref)
     S.close()
+
+
+def test_cached_device_buffers_give_identical_solves():
+    """Buffers released by a closed solver are reused by the next one (the
+    library's device memory cache): solving again with a new solver on reused
+    buffers, and after the cache was handed back to the driver, gives the same
+    bits and the direct solution."""
+    import torch
+    from paper_1806_11277_amd import ehh
+    w = workload("c2s_hetero128_fp64")
+    say("[cached buffers]")
+    pb = oracle_problem(w)
+    B = rhs_matrix(w)
+    xd = spla.splu(pb.matrix().tocsc()).solve(B[0])
+    got = []
+    for k in range(3):
+        if k == 2:
+            ehh.release_cached_memory()
+        S = _solver(w)
+        x = torch.zeros_like(to_dev(B))
+        st, stats = S.solve(to_dev(B), x, tol=1e-8, maxit=600)
+        torch.cuda.synchronize()
+        assert st == 0, stats
+        got.append(from_dev(x)[0])
+        S.close()
+    assert np.array_equal(got[0], got[1]) and np.array_equal(got[0], got[2])
+    assert np.linalg.norm(got[0] - xd) <= 1e-6 * np.linalg.norm(xd)
