@@ -725,11 +725,13 @@ hipError_t launch_dense_invert(double* A, int64_t n, int* piv, int* flag, hipStr
             if ((e = hipEventRecord(ev_diag, s2)) != hipSuccess) break;
             skip = k1;
         }
-        // A[I,J] <- A[I,J] - A[I,K] A[K,J] (but the next diagonal tile)
+        // A[I,J] <- A[I,J] - A[I,K] A[K,J] (but the next diagonal tile), after
+        // that tile: its inversion is then queued before the update fills the
+        // device, and A[K1,K] has been read before it is scaled below
+        if (k1 < n && (e = hipStreamWaitEvent(s, ev_tile, 0)) != hipSuccess) break;
         hipLaunchKernelGGL(k_zgemm_tile, dim3(tiles, tiles), 256, 0, s, A, n, ACK, n, AK, n, n, n, kb, -1.0, 1, k0,
                            k1, k0, k1, skip, skip);
-        // A[I,K] <- -A[I,K] W, once the next diagonal tile has read A[K1,K]
-        if (k1 < n && (e = hipStreamWaitEvent(s, ev_tile, 0)) != hipSuccess) break;
+        // A[I,K] <- -A[I,K] W
         hipLaunchKernelGGL(k_zgemm_tile, dim3(1, tiles), 256, 0, s, ACK, n, ACK, n, AKK, n, n, (int64_t)kb, kb, -1.0,
                            0, k0, k1, (int64_t)0, (int64_t)0, (int64_t)-1, (int64_t)-1);
     }
