@@ -39,12 +39,13 @@ def rhs_tensor(S, w):
     return torch.as_tensor(B, device="cuda")
 
 
-def level_bytes(info, bits, nrhs, fine, dim, with_e=True):
+def level_bytes(info, bits, nrhs, fine, dim, with_e=True, coef_bytes=None):
     """Algorithmic HBM bytes of one half-sweep launch on a level: b and e_in read,
     e_out written (every unknown, complex, per right-hand side; without e_in when
     the sweep starts from zero) plus the level's operator coefficients read once
     (finest: mu, 1/(lambda+mu), rho, gamma per cell; coarser: the stored
-    Galerkin stencil)."""
+    Galerkin stencil, at coef_bytes per real when the level keeps its
+    coefficients in another precision than the cycle's)."""
     es = 4 if bits == 32 else 8
     ncell_ = int(np.prod(info["n"][:dim]))
     nu = info["N"] - ncell_          # displacement unknowns
@@ -56,7 +57,7 @@ def level_bytes(info, bits, nrhs, fine, dim, with_e=True):
         coef = 4 * ncell * es
     else:
         nuu, nup = (8, 6) if dim == 2 else (38, 18)
-        coef = (sum(info["counts"][:dim]) * (2 * nuu + nup) + ncell) * es
+        coef = (sum(info["counts"][:dim]) * (2 * nuu + nup) + ncell) * (coef_bytes or es)
     return vec + coef
 
 
@@ -69,7 +70,7 @@ def run_gpu(w, steps, warmup, tol):
     opts = dict(levels=w.levels, cycle=w.cycle, cycle_level=w.cycle_level, nu1=w.nu1, nu2=w.nu2, vanka=w.vanka,
                 precond_bits=w.precond_bits, restart=w.restart, dd_parts=w.dd_parts,
                 dd_overlap=w.dd_overlap, dd_pad=w.dd_pad, dd_colors=w.dd_colors, damping=w.damping,
-                abl_max=w.abl_max, atten0=w.atten0)
+                abl_max=w.abl_max, atten0=w.atten0, coarse_bits=w.coarse_bits)
 
     def make():
         return ehh.Solver(w.dim, w.n, w.h, w.omega, w.shift, w.abl_cells, lam, mu, rho, **opts)
@@ -135,7 +136,9 @@ def relax_kernel_name(w, level, ncell):
         return f"k_relax_st2d<{t}, {'true' if t == 'float' else 'false'}, false>"
     if level == 0:
         return f"k_relax_cell3d<{t}>"
-    return f"k_relax_st3d<{t}, 8, 8>" if t == "float" else f"k_relax_st3d<{t}, 2, 4>"
+    if t == "double":
+        return "k_relax_st3d<double, 2, 4, double>"
+    return f"k_relax_st3d<float, 8, 8, {'_Float16' if w.coarse_bits == 16 else 'float'}>"
 
 
 KERNEL_SOURCES = ["paper_1806_11277_amd/csrc/levels.hip", "paper_1806_11277_amd/csrc/ops.hpp",
@@ -238,8 +241,9 @@ def kernel_roofline(w, reps=30):
             del graph
             return best
         t = max(timed(True) - timed(False), 0.0) / (reps * nsw)
-        nb = (nzero * level_bytes(info, w.precond_bits, nrhs, l == 0, w.dim, with_e=False) +
-              (nsw - nzero) * level_bytes(info, w.precond_bits, nrhs, l == 0, w.dim)) / nsw
+        cb = 2 if (w.coarse_bits == 16 and w.dim == 3) else None
+        nb = (nzero * level_bytes(info, w.precond_bits, nrhs, l == 0, w.dim, with_e=False, coef_bytes=cb) +
+              (nsw - nzero) * level_bytes(info, w.precond_bits, nrhs, l == 0, w.dim, coef_bytes=cb)) / nsw
         launches = 2 * (w.nu1 + w.nu2) * visits[l]
         ncell = int(np.prod(info["n"][:w.dim]))
         name = relax_kernel_name(w, l, ncell)
@@ -351,6 +355,9 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=2)
     ap.add_argument("--poisson-sweep", action="store_true",
                     help="print the Poisson-ratio sweep (constant media, lambda 0.5..16) as one JSON line and exit")
+    ap.add_argument("--coarse-bits", type=int, default=None, choices=(16, 32),
+                    help="storage of the 3D Galerkin levels' stored rows in the complex64 cycle "
+                         "(16: FP16 with a power-of-two scale per level)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for traffic counters)")
     a = ap.parse_args()
@@ -371,6 +378,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     w = get_config(a.config)
+    if a.coarse_bits is not None:
+        import dataclasses
+        w = dataclasses.replace(w, coarse_bits=a.coarse_bits)
     print(f"[bench] {w.name}: n={w.n} nrhs={len(w.sources())} levels={w.levels} cycle={w.cycle} "
           f"bits={w.precond_bits}", file=sys.stderr, flush=True)
     total, res, B, X = run_gpu(w, a.steps, a.warmup, a.tol)
@@ -394,7 +404,7 @@ def main():
                    "cycle_level": w.cycle_level,
                    "nu": [w.nu1, w.nu2], "vanka": "full" if w.vanka else "economic",
                    "shift": w.shift, "precond_bits": w.precond_bits, "restart": w.restart,
-                   "dd_parts": list(w.dd_parts[:w.dim]), "tol": a.tol},
+                   "dd_parts": list(w.dd_parts[:w.dim]), "coarse_bits": w.coarse_bits, "tol": a.tol},
         "setup_ms": setup_ms, "solve_ms": solve_ms,
         "iters": iters if nrhs <= 4 else [min(iters), max(iters)],
         "rel_res_true_max": max(s["rel_res_true"] for s in stats),

@@ -102,6 +102,10 @@ typedef struct {
     int32_t dd_colors;      /* 1 = one colour, local corrections averaged on the
                                overlaps; 0 = multicolour schedule of Algorithm 2 */
     double  damping[EHH_MAX_LEVELS];  /* Vanka damping per level, finest first */
+    int32_t coarse_bits;    /* 32 (default) or 16: with the complex64 cycle, the stored
+                               rows of the 3D Galerkin levels are kept in FP16, scaled by
+                               a power of two per level, and summed in FP32 (the paper's
+                               half-precision storage of coarse data, section 3) */
 } ehh_options_t;
 
 typedef struct {

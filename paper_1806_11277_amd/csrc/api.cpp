@@ -166,6 +166,8 @@ struct Level {
     int64_t sp_lanes = 0;
     void* rp_re = nullptr;      // stored rows of the residual
     void* rp_im = nullptr;
+    bool sp_half = false;       // the rows above hold FP16 values scaled by 1 / sp_scale
+    float sp_scale = 1.0f;
 };
 
 struct Sub {
@@ -305,6 +307,8 @@ template <typename T> LevelDesc<T> level_desc(const ehh_ctx* c, const Level& L, 
             d.sp.rre = (const T*)L.rp_re;
             d.sp.rim = (const T*)L.rp_im;
         }
+        d.sp.half = mine && L.sp_half;
+        d.sp.scale = L.sp_scale;
     }
     return d;
 }
@@ -554,6 +558,9 @@ int32_t check_problem(const ehh_problem_t* p, const ehh_options_t* o) {
     if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 > 8 || o->nu2 > 8) return fail(EHH_ERR_INVALID, "nu1, nu2 in [0, 8]");
     if (o->vanka != 0 && o->vanka != 1) return fail(EHH_ERR_INVALID, "vanka must be 0 or 1");
     if (o->precond_bits != 32 && o->precond_bits != 64) return fail(EHH_ERR_INVALID, "precond_bits must be 32 or 64");
+    if (o->coarse_bits != 16 && o->coarse_bits != 32) return fail(EHH_ERR_INVALID, "coarse_bits must be 16 or 32");
+    if (o->coarse_bits == 16 && o->precond_bits != 32)
+        return fail(EHH_ERR_INVALID, "coarse_bits = 16 needs the complex64 cycle (precond_bits = 32)");
     if (o->restart < 1 || o->restart > EHH_MAX_RESTART) return fail(EHH_ERR_INVALID, "restart out of range");
     for (int a = 0; a < p->dim; ++a)
         if (o->dd_parts[a] < 1 || o->dd_parts[a] > p->n[a]) return fail(EHH_ERR_INVALID, "dd_parts out of range");
@@ -599,6 +606,40 @@ void make_subdomains(ehh_ctx* c) {
                 S.colour = (px % 2) + 2 * (py % 2) + 4 * (pz % 2);
                 c->subs.push_back(std::move(S));
             }
+}
+
+
+// FP16 storage of a 3D Galerkin level's stored rows (coarse_bits = 16, section 3
+// of the paper suggests half precision for the coarse data): every row array
+// is divided by one power-of-two scale that brings the largest modulus to
+// about 2^14, rounded to FP16, and the FP32 arrays are released.
+int32_t rows_to_half(ehh_ctx* c, Level& Q, int NT, int NF, int64_t lanes, hipStream_t s) {
+    const int64_t N = Q.g.N;
+    void** arrs[6] = {&Q.sp_re[0], &Q.sp_im[0], &Q.sp_re[1], &Q.sp_im[1], &Q.rp_re, &Q.rp_im};
+    const int64_t cnt[6] = {NT * lanes, NF * lanes, NT * lanes, NF * lanes, NT * N, NF * N};
+    unsigned* mx = nullptr;
+    CHK(c->alloc((void**)&mx, sizeof(unsigned)));
+    HIPCHK(hipMemsetAsync(mx, 0, sizeof(unsigned), s));
+    for (int a = 0; a < 6; ++a) HIPCHK(launch_absmax_bits((const float*)*arrs[a], cnt[a], mx, s));
+    unsigned bits = 0;
+    HIPCHK(hipMemcpyAsync(&bits, mx, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    c->release(mx);
+    float amax = 0.0f;
+    std::memcpy(&amax, &bits, sizeof(float));
+    if (!std::isfinite(amax)) return fail(EHH_ERR_BREAKDOWN, "non-finite coarse-level coefficient");
+    const float scale = amax > 0.0f ? std::ldexp(1.0f, std::ilogb(amax) - 14) : 1.0f;
+    for (int a = 0; a < 6; ++a) {
+        void* h = nullptr;
+        CHK(c->alloc(&h, sizeof(uint16_t) * cnt[a]));
+        HIPCHK(launch_to_half((const float*)*arrs[a], h, cnt[a], 1.0f / scale, s));
+        HIPCHK(hipStreamSynchronize(s));
+        c->release(*arrs[a]);
+        *arrs[a] = h;
+    }
+    Q.sp_half = true;
+    Q.sp_scale = scale;
+    return EHH_OK;
 }
 
 int32_t build_hierarchy(ehh_ctx* c, Sub& S, const double* lam, const double* mu, const double* rho,
@@ -730,6 +771,7 @@ int32_t build_hierarchy(ehh_ctx* c, Sub& S, const double* lam, const double* mu,
         else
             HIPCHK(launch_build_row_plans<double>(level_desc<double>(c, Q, c->prob.shift),
                                                   (double*)Q.rp_re, (double*)Q.rp_im, s));
+        if (c->opt.coarse_bits == 16 && Q.g.dim == 3) CHK(rows_to_half(c, Q, NT, NF, lanes, s));
     }
     return EHH_OK;
 }
@@ -919,6 +961,7 @@ void ehh_default_options(ehh_options_t* o) {
     o->nu1 = o->nu2 = 1;
     o->vanka = 1;
     o->precond_bits = 64;
+    o->coarse_bits = 32;
     o->restart = 5;
     o->dd_parts[0] = o->dd_parts[1] = o->dd_parts[2] = 1;
     o->dd_colors = 1;

@@ -20,6 +20,10 @@ template <typename T> struct StoredPlan {
     // rows of y = A x in row order (term j of row t at [j * N + t])
     const T* rre = nullptr;
     const T* rim = nullptr;
+    // 3D complex64 cycle with FP16 rows: the pointers above hold FP16 values, the
+    // coefficients divided by scale (a power of two)
+    bool half = false;
+    float scale = 1.0f;
 };
 
 template <typename T> struct LevelDesc {
@@ -56,6 +60,10 @@ template <typename T>
 hipError_t launch_build_plans(const LevelDesc<T>& L, int colour, T* re, T* im, hipStream_t s);
 template <typename T>
 hipError_t launch_build_row_plans(const LevelDesc<T>& L, T* re, T* im, hipStream_t s);
+// FP16 copies of stored rows: *out = max over x of |x| as float bits (out
+// zeroed by the caller); y = x * inv_scale rounded to FP16.
+hipError_t launch_absmax_bits(const float* x, int64_t n, unsigned* out, hipStream_t s);
+hipError_t launch_to_half(const float* x, void* y, int64_t n, float inv_scale, hipStream_t s);
 template <typename T>
 hipError_t launch_restrict(const Geo& gf, const Geo& gc, const T* rf, T* rc, int nrhs, hipStream_t s);
 template <typename T>

@@ -248,6 +248,21 @@ template <> struct Buf<double> {
 // fetched.
 constexpr uint32_t OOB_OFF = 0x80000000u;
 
+// FP16 storage (stored rows of the 3D Galerkin levels in the complex64 cycle when
+// asked for): loads only, widened by the caller.
+template <> struct Buf<_Float16> {
+    __amdgpu_buffer_rsrc_t r;
+    EHH_DEV Buf() {}
+    EHH_DEV Buf(const void* p, uint32_t bytes)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000)) {}
+    EHH_DEV _Float16 ld(uint32_t off) const {
+        return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
+    }
+    EHH_DEV _Float16 ld(uint32_t off, uint32_t soff) const {
+        return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, off, soff, 0));
+    }
+};
+
 // ------------------------------------------------ plan-based apply and half-sweep
 // The row plan (indices and coefficients) is built once per row and reused for
 // every right-hand side, so a batch streams only the vectors.
@@ -1027,8 +1042,8 @@ EHH_DEV inline int col3(const Cols3& c, int j) {
 // vector; terms in chunks of CH, each chunk's loads issued before its sums and
 // the next chunk's addresses tied to them (empty asm), so that the registers
 // hold one chunk at a time.
-template <typename T, int RB, int CH>
-EHH_DEV void rows3_rb(const Buf<T>& cR, const Buf<T>& cI, uint32_t lo, uint32_t ls, const Cols3& cc,
+template <typename T, int RB, int CH, typename C = T>
+EHH_DEV void rows3_rb(const Buf<C>& cR, const Buf<C>& cI, uint32_t lo, uint32_t ls, const Cols3& cc,
                       const T* const* ev, uint32_t vb, uint32_t nb, T* ar, T* ai) {
     constexpr int NF = St<3>::NF, NT = NF + St<3>::NUP;
 #pragma unroll
@@ -1052,8 +1067,8 @@ EHH_DEV void rows3_rb(const Buf<T>& cR, const Buf<T>& cI, uint32_t lo, uint32_t 
         for (int jj = 0; jj < CH; ++jj) {
             const int j = h + jj;
             if (j < NT) {
-                cr[jj] = cR.ld(lh, j * ls);
-                ci[jj] = j < NF ? cI.ld(lh, j * ls) : T(0);
+                cr[jj] = (T)cR.ld(lh, j * ls);
+                ci[jj] = j < NF ? (T)cI.ld(lh, j * ls) : T(0);
                 const uint32_t o = (uint32_t)col3(cl, j) * (uint32_t)sizeof(T);
 #pragma unroll
                 for (int q = 0; q < RB; ++q) {
@@ -1078,11 +1093,15 @@ EHH_DEV void rows3_rb(const Buf<T>& cR, const Buf<T>& cI, uint32_t lo, uint32_t 
 // Half-sweep over stored rows on a 3D Galerkin level: eight lanes per cell as in
 // k_relax (lane 8 j + cell holds row j: low/high face of u_0, u_1, u_2, then the
 // pressure; lane 7 carries the other cell's pressure), blocks renumbered per XCD.
-template <typename T, int RB, int CH>
+//
+// C: storage type of the rows (T, or FP16 holding the coefficients divided by
+// the level's power-of-two scale csc, which the sums and the block entries are
+// multiplied by again; csc = 1 otherwise).
+template <typename T, int RB, int CH, typename C = T>
 __global__ __launch_bounds__(256) void k_relax_st3d(Geo g, int colour, T w, int econ, const T* __restrict__ b,
                                                     const T* __restrict__ ein, T* __restrict__ eout, int nrhs,
-                                                    int64_t stride, int rpb, const T* __restrict__ cre,
-                                                    const T* __restrict__ cim, int64_t lanes) {
+                                                    int64_t stride, int rpb, const C* __restrict__ cre,
+                                                    const C* __restrict__ cim, int64_t lanes, T csc) {
     constexpr int D = 3, R = 2 * D + 1, NF = St<3>::NF, NT = NF + St<3>::NUP;
     constexpr int T_SELF = St<3>::CF, T_NHI = St<3>::CF + 1, T_PLO = NF + 8, T_PHI = NF + 9;
     {
@@ -1117,8 +1136,8 @@ __global__ __launch_bounds__(256) void k_relax_st3d(Geo g, int colour, T w, int 
     const int idx = cc.self;
     const bool carry = live && row == R;
     const int ipb = (int)g.off[3] + (zz * g.n[1] + yy) * g.n[0] + 2 * px + 1 - par;
-    const Buf<T> cR(cre, (uint32_t)(NT * lanes * sizeof(T))), cI(cim, (uint32_t)(NF * lanes * sizeof(T)));
-    const uint32_t lo = (uint32_t)gl * (uint32_t)sizeof(T), ls = (uint32_t)lanes * (uint32_t)sizeof(T);
+    const Buf<C> cR(cre, (uint32_t)(NT * lanes * sizeof(C))), cI(cim, (uint32_t)(NF * lanes * sizeof(C)));
+    const uint32_t lo = (uint32_t)gl * (uint32_t)sizeof(C), ls = (uint32_t)lanes * (uint32_t)sizeof(C);
     const uint32_t vb = 2 * (uint32_t)g.N * (uint32_t)sizeof(T), nb = (uint32_t)g.N * (uint32_t)sizeof(T);
     // this row's block entries (the diagonal sits at T_SELF in a u row, at term 0
     // in the pressure row), then the block factorisation, once for the batch
@@ -1126,13 +1145,13 @@ __global__ __launch_bounds__(256) void k_relax_st3d(Geo g, int colour, T w, int 
     T dre = T(1), dim = T(0), ore = T(0), oim = T(0), gg = T(0);
     if (ok) {
         const uint32_t js = (uint32_t)(k == 3 ? 0 : T_SELF) * ls;
-        dre = cR.ld(lo + js);
+        dre = csc * (T)cR.ld(lo + js);
         if (k < 3) {
-            dim = cI.ld(lo + js);
-            gg = cR.ld(lo + (uint32_t)(lowrow ? T_PHI : T_PLO) * ls);
+            dim = csc * (T)cI.ld(lo + js);
+            gg = csc * (T)cR.ld(lo + (uint32_t)(lowrow ? T_PHI : T_PLO) * ls);
             if (lowrow && !econ) {
-                ore = cR.ld(lo + (uint32_t)T_NHI * ls);
-                oim = cI.ld(lo + (uint32_t)T_NHI * ls);
+                ore = csc * (T)cR.ld(lo + (uint32_t)T_NHI * ls);
+                oim = csc * (T)cI.ld(lo + (uint32_t)T_NHI * ls);
             }
         }
     }
@@ -1147,7 +1166,12 @@ __global__ __launch_bounds__(256) void k_relax_st3d(Geo g, int colour, T w, int 
             const T* ev[RB];
 #pragma unroll
             for (int q = 0; q < RB; ++q) ev[q] = ein + (r0 + q < nrhs ? r0 + q : r0) * stride;
-            rows3_rb<T, RB, CH>(cR, cI, lo, ls, cc, ev, vb, nb, ar, ai);
+            rows3_rb<T, RB, CH, C>(cR, cI, lo, ls, cc, ev, vb, nb, ar, ai);
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                ar[q] *= csc;
+                ai[q] *= csc;
+            }
         }
         // the row's own unknown and the carried pressure as 32-bit byte offsets
         // into buffer descriptors (wave-uniform bases), formed here so that no
@@ -1182,10 +1206,11 @@ __global__ __launch_bounds__(256) void k_relax_st3d(Geo g, int colour, T w, int 
 
 // y = A x or r = b - A x over stored rows on a 3D Galerkin level (term j of row t
 // at [j * N + t]).
-template <typename T, int RB, int CH>
+// (C, csc: storage of the rows and their scale, as in k_relax_st3d.)
+template <typename T, int RB, int CH, typename C = T>
 __global__ __launch_bounds__(256) void k_apply_st3d(Geo g, const T* __restrict__ x, const T* __restrict__ b,
                                                     T* __restrict__ y, int nrhs, int64_t stride, int rpb,
-                                                    const T* __restrict__ cre, const T* __restrict__ cim) {
+                                                    const C* __restrict__ cre, const C* __restrict__ cim, T csc) {
     constexpr int NF = St<3>::NF, NT = NF + St<3>::NUP;
     {
         const int rb0 = blockIdx.y * rpb;
@@ -1204,7 +1229,8 @@ __global__ __launch_bounds__(256) void k_apply_st3d(Geo g, const T* __restrict__
     int p[3] = {li % d0, (li / d0) % d1, li / (d0 * d1)};
     if (k < 3) p[k] += 1;
     const Cols3 cc = cols3(g, k, p);
-    const Buf<T> cR(cre, (uint32_t)(NT * N * sizeof(T))), cI(cim, (uint32_t)(NF * N * sizeof(T)));
+    const Buf<C> cR(cre, (uint32_t)(NT * N * sizeof(C))), cI(cim, (uint32_t)(NF * N * sizeof(C)));
+    const uint32_t lc = (uint32_t)t * (uint32_t)sizeof(C), lsc = (uint32_t)N * (uint32_t)sizeof(C);
     const uint32_t lo = (uint32_t)t * (uint32_t)sizeof(T), ls = (uint32_t)N * (uint32_t)sizeof(T);
     const uint32_t vb = 2 * ls;
     for (int r0 = 0; r0 < nrhs; r0 += RB) {
@@ -1212,7 +1238,12 @@ __global__ __launch_bounds__(256) void k_apply_st3d(Geo g, const T* __restrict__
 #pragma unroll
         for (int q = 0; q < RB; ++q) xv[q] = x + (r0 + q < nrhs ? r0 + q : r0) * stride;
         T ar[RB], ai[RB];
-        rows3_rb<T, RB, CH>(cR, cI, lo, ls, cc, xv, vb, ls, ar, ai);
+        rows3_rb<T, RB, CH, C>(cR, cI, lc, lsc, cc, xv, vb, ls, ar, ai);
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            ar[q] *= csc;
+            ai[q] *= csc;
+        }
         // per-source buffer descriptors (wave-uniform bases) and the row's byte
         // offset formed here, so that no per-source address is kept across the row
         uint32_t ot = lo;
@@ -2728,14 +2759,16 @@ hipError_t launch_apply(const LevelDesc<T>& L, const T* x, const T* b, T* y, int
         if (L.fine)
             EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_apply_plan<3, T, FineOp<3, T>, RB>), gb, 256, 0, s, FineOp<3, T>{L.g, L.f}, x, b, y, nrhs, stride, rpb));
         else if (L.sp.rre) {
-#define EHH_APPLY_ST3D(RB, CH)                                                                                   \
+#define EHH_APPLY_ST3D(RB, CH, C)                                                                                \
     {                                                                                                            \
         const int rpbs = rhs_per_block((L.g.N + 63) / 64, nrhs, RB);                                             \
-        hipLaunchKernelGGL((k_apply_st3d<T, RB, CH>), dim3(nblk(L.g.N), (nrhs + rpbs - 1) / rpbs), 256, 0, s, L.g, \
-                           x, b, y, nrhs, stride, rpbs, L.sp.rre, L.sp.rim);                                     \
+        hipLaunchKernelGGL((k_apply_st3d<T, RB, CH, C>), dim3(nblk(L.g.N), (nrhs + rpbs - 1) / rpbs), 256, 0, s,   \
+                           L.g, x, b, y, nrhs, stride, rpbs, (const C*)L.sp.rre, (const C*)L.sp.rim,             \
+                           (T)L.sp.scale);                                                                       \
     }
-            if (sizeof(T) == 8) EHH_APPLY_ST3D(2, 4)
-            else EHH_APPLY_ST3D(8, 4)
+            if constexpr (sizeof(T) == 8) EHH_APPLY_ST3D(2, 4, T)
+            else if (L.sp.half) EHH_APPLY_ST3D(8, 4, _Float16)
+            else EHH_APPLY_ST3D(8, 4, T)
 #undef EHH_APPLY_ST3D
         } else
             EHH_RB_DISPATCH(rb3, hipLaunchKernelGGL((k_apply<3, T, StOp<3, T>, RB>), gb3, 256, 0, s, StOp<3, T>{L.g, L.s}, x, b, y, nrhs, stride, rpb3));
@@ -2803,20 +2836,21 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
         if (L.fine)
             EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_relax_plan<3, T, FineOp<3, T>, RB>), gb, 256, 0, s, FineOp<3, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb));
         else if (L.sp.re[colour]) {
-#define EHH_RELAX_ST3D(RB, CH)                                                                                    \
+#define EHH_RELAX_ST3D(RB, CH, C)                                                                                 \
     {                                                                                                             \
         const int rpbs = rhs_per_block((npair * 8 + 63) / 64, nrhs, RB);                                          \
-        hipLaunchKernelGGL((k_relax_st3d<T, RB, CH>), dim3(nblk(npair * 8), (nrhs + rpbs - 1) / rpbs), 256, 0, s, \
-                           L.g, colour, tw, econ, b, ein, eout, nrhs, stride, rpbs, L.sp.re[colour],              \
-                           L.sp.im[colour], L.sp.lanes);                                                          \
+        hipLaunchKernelGGL((k_relax_st3d<T, RB, CH, C>), dim3(nblk(npair * 8), (nrhs + rpbs - 1) / rpbs), 256, 0,  \
+                           s, L.g, colour, tw, econ, b, ein, eout, nrhs, stride, rpbs, (const C*)L.sp.re[colour], \
+                           (const C*)L.sp.im[colour], L.sp.lanes, (T)L.sp.scale);                                 \
     }
             // measured on MI355X (36^3 level, 16 FP32 sources): 8 sources per
             // coefficient load in chunks of 8 terms 284 us, of 4 terms 299 us
             // (both two wavefronts per SIMD); with the row-loop addresses held
             // across the loop (one wavefront per SIMD) 8 x 4 took 331 us, 8 x 2
             // 335 us, 4 x 4 358 us, 16 x 2 322 us but 2x slower on 18^3
-            if (sizeof(T) == 8) EHH_RELAX_ST3D(2, 4)
-            else EHH_RELAX_ST3D(8, 8)
+            if constexpr (sizeof(T) == 8) EHH_RELAX_ST3D(2, 4, T)
+            else if (L.sp.half) EHH_RELAX_ST3D(8, 8, _Float16)
+            else EHH_RELAX_ST3D(8, 8, T)
 #undef EHH_RELAX_ST3D
         } else
             EHH_RB_DISPATCH(rb3, hipLaunchKernelGGL((k_relax<3, T, StOp<3, T>, RB>), gb3, 256, 0, s, StOp<3, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb3));
@@ -2935,6 +2969,38 @@ hipError_t launch_prolong(const Geo& gf, const Geo& gc, const T* ec, T* ef, int 
         hipLaunchKernelGGL((k_prolong3d<T>), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef);
     else
         hipLaunchKernelGGL((k_prolong<3, T>), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef, nrhs);
+    return hipGetLastError();
+}
+
+// FP16 copies of stored rows: max |x| over the rows (the bit patterns of
+// non-negative floats order as integers, so an integer maximum is exact), then
+// x / scale rounded to FP16, scale = a power of two that brings the largest
+// modulus to about 2^14 (FP16 overflows at 65504).
+__global__ __launch_bounds__(256) void k_absmax_bits(const float* __restrict__ x, int64_t n,
+                                                     unsigned* __restrict__ out) {
+    unsigned m = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned v = __float_as_uint(fabsf(x[i]));
+        m = v > m ? v : m;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned v = __shfl_xor(m, o, 64);
+        m = v > m ? v : m;
+    }
+    if ((threadIdx.x & 63) == 0 && m) atomicMax(out, m);
+}
+__global__ __launch_bounds__(256) void k_to_half(const float* __restrict__ x, _Float16* __restrict__ y, int64_t n,
+                                                 float inv_scale) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = (_Float16)(x[i] * inv_scale);
+}
+hipError_t launch_absmax_bits(const float* x, int64_t n, unsigned* out, hipStream_t s) {
+    const int64_t nb = std::min<int64_t>(1024, (n + 255) / 256);
+    hipLaunchKernelGGL(k_absmax_bits, (unsigned)(nb < 1 ? 1 : nb), 256, 0, s, x, n, out);
+    return hipGetLastError();
+}
+hipError_t launch_to_half(const float* x, void* y, int64_t n, float inv_scale, hipStream_t s) {
+    hipLaunchKernelGGL(k_to_half, nblk(n), 256, 0, s, x, (_Float16*)y, n, inv_scale);
     return hipGetLastError();
 }
 

@@ -36,7 +36,8 @@ class ehh_options_t(ctypes.Structure):
                 ("nu2", ctypes.c_int32), ("vanka", ctypes.c_int32), ("precond_bits", ctypes.c_int32),
                 ("restart", ctypes.c_int32), ("dd_parts", ctypes.c_int32 * 3),
                 ("dd_overlap", ctypes.c_int32), ("dd_pad", ctypes.c_int32),
-                ("dd_colors", ctypes.c_int32), ("damping", ctypes.c_double * EHH_MAX_LEVELS)]
+                ("dd_colors", ctypes.c_int32), ("damping", ctypes.c_double * EHH_MAX_LEVELS),
+                ("coarse_bits", ctypes.c_int32)]
 
 
 class ehh_stats_t(ctypes.Structure):
@@ -141,7 +142,7 @@ class Solver:
                  vanka: int = 1, precond_bits: int = 64, restart: int = 5,
                  dd_parts: Sequence[int] = (1, 1, 1), dd_overlap: int = 0, dd_pad: int = 0,
                  dd_colors: int = 1, damping: Optional[Sequence[float]] = None,
-                 mu_bar: float = 0.0, rho_bar: float = 0.0, stream=None):
+                 mu_bar: float = 0.0, rho_bar: float = 0.0, coarse_bits: int = 32, stream=None):
         import torch
         p = ehh_problem_t()
         p.dim = dim
@@ -154,7 +155,7 @@ class Solver:
         p.mu_bar, p.rho_bar = float(mu_bar), float(rho_bar)
         o = default_options()
         o.levels, o.cycle, o.cycle_level, o.nu1, o.nu2, o.vanka = levels, cycle, cycle_level, nu1, nu2, vanka
-        o.precond_bits, o.restart = precond_bits, restart
+        o.precond_bits, o.restart, o.coarse_bits = precond_bits, restart, coarse_bits
         dp = list(dd_parts) + [1] * (3 - len(dd_parts))
         for a in range(3):
             o.dd_parts[a] = int(dp[a])
@@ -271,7 +272,7 @@ def solver_for_workload(w, device="cuda", **overrides):
     kw = dict(levels=w.levels, cycle=w.cycle, cycle_level=w.cycle_level, nu1=w.nu1, nu2=w.nu2, vanka=w.vanka,
               precond_bits=w.precond_bits, restart=w.restart, dd_parts=w.dd_parts,
               dd_overlap=w.dd_overlap, dd_pad=w.dd_pad, dd_colors=w.dd_colors, damping=w.damping,
-              abl_max=w.abl_max, atten0=w.atten0)
+              abl_max=w.abl_max, atten0=w.atten0, coarse_bits=getattr(w, "coarse_bits", 32))
     kw.update(overrides)
     t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=device).contiguous()
     return Solver(w.dim, w.n, w.h, w.omega, kw.pop("shift", w.shift), w.abl_cells,

@@ -208,3 +208,50 @@ def test_cached_device_buffers_give_identical_solves():
         S.close()
     assert np.array_equal(got[0], got[1]) and np.array_equal(got[0], got[2])
     assert np.linalg.norm(got[0] - xd) <= 1e-6 * np.linalg.norm(xd)
+
+
+def test_fp16_coarse_rows_3d():
+    """coarse_bits = 16 (section 3: half-precision storage of coarse data): the
+    3D Galerkin level's stored rows in FP16 change the DD preconditioner by no
+    more than twice the FP16 unit roundoff of its coefficients (2 * 2^-11
+    relative; measured on MI355X: 8.8e-5 against 1.1e-7 with FP32 rows), the
+    FGMRES solve still reaches the true residual tolerance, and in no more than
+    10 % more iterations than with FP32 rows.  Asking for it with the FP64 cycle
+    is an invalid argument."""
+    import torch
+    from paper_1806_11277_amd import ehh
+    w = workload("c4s_layered32_dd8_batch4_fp32")
+    say("[fp16 coarse rows 3d]")
+    pb = oracle_problem(w)
+    P = oracle_dd(w, pb)
+    A = pb.matrix()
+    B = rhs_matrix(w)
+    v = rand_cvec(pb.size, 2, 61)
+    out, iters = {}, {}
+    for cb in (32, 16):
+        S = _solver(w, coarse_bits=cb)
+        z = torch.zeros_like(to_dev(v))
+        S.precondition(to_dev(v), z)
+        torch.cuda.synchronize()
+        out[cb] = from_dev(z)
+        x = torch.zeros_like(to_dev(B))
+        st, stats = S.solve(to_dev(B), x, tol=1e-8, maxit=600)
+        torch.cuda.synchronize()
+        assert st == 0, stats
+        got = from_dev(x)
+        for r in range(B.shape[0]):
+            assert np.linalg.norm(B[r] - A @ got[r]) / np.linalg.norm(B[r]) <= 1.01e-8
+        iters[cb] = max(s_["iters"] for s_ in stats)
+        S.close()
+    for r in range(2):
+        ref = P.apply(v[r])
+        e16 = np.linalg.norm(out[16][r] - ref) / np.linalg.norm(ref)
+        e32 = np.linalg.norm(out[32][r] - ref) / np.linalg.norm(ref)
+        say(f"  source {r}: preconditioner error vs oracle fp32 rows {e32:.2e}, fp16 rows {e16:.2e}")
+        assert e32 <= 2e-5
+        assert 0 < e16 <= 2 * 2.0 ** -11
+    say(f"  iterations fp32 rows {iters[32]}, fp16 rows {iters[16]}")
+    assert iters[16] <= int(1.1 * iters[32]) + 1
+    with pytest.raises(ehh.EHHError) as ei:
+        _solver(w, precond_bits=64, coarse_bits=16)
+    assert ei.value.status == ehh.EHH_ERR_INVALID

@@ -48,6 +48,7 @@ class Workload:
     dd_overlap: int = 0
     dd_pad: int = 0
     dd_colors: int = 1
+    coarse_bits: int = 32           # 16: FP16 stored rows on 3D Galerkin levels (complex64 cycle)
     sources_fn: Callable[["Workload"], List[Source]] = None
     receivers_fn: Callable[["Workload"], List[Tuple[int, Tuple[int, ...]]]] = None
     true_media_fn: Callable[[], dict] = None
