@@ -204,6 +204,11 @@ struct ehh_ctx {
     double *partial = nullptr, *scal = nullptr;
     int *active = nullptr, *ncols = nullptr;
     double* host_pinned = nullptr;
+    // g, scal, active and ncols live in one device block, rst_dev, mirrored by
+    // the pinned host block rst_host, so that a restart sends them with one
+    // asynchronous copy
+    void* rst_dev = nullptr;
+    char* rst_host = nullptr;
     // conjugated right-hand sides of the adjoint solve
     int adj_rhs = 0;
     double* adjb = nullptr;
@@ -225,6 +230,7 @@ struct ehh_ctx {
         (void)hipDeviceSynchronize();
         for (const Block& b : allocs) give_back(b);
         if (host_pinned) (void)hipHostFree(host_pinned);
+        if (rst_host) (void)hipHostFree(rst_host);
     }
     static void give_back(const Block& b) {
         if (!BlockCache::get().put(b.dev, b.cls, b.p)) (void)hipFree(b.p);
@@ -354,22 +360,31 @@ int32_t ensure_ws(ehh_ctx* c, int nrhs) {
     return EHH_OK;
 }
 
+// bytes of the restart block: g (2 nrhs (m + 1) doubles), scal (nrhs doubles),
+// active and ncols (nrhs ints each)
+size_t restart_block_bytes(int nrhs, int m) {
+    return sizeof(double) * (2 * (size_t)nrhs * (m + 1) + nrhs) + 2 * sizeof(int) * (size_t)nrhs;
+}
+
 int32_t ensure_krylov(ehh_ctx* c, int nrhs) {
     if (nrhs <= c->kr_rhs) return EHH_OK;
     c->clear_graphs();
     const int m = c->opt.restart;
     const size_t vec = 2 * (size_t)c->gg.N * nrhs * sizeof(double);
-    double** bufs[] = {&c->V, &c->Z, &c->w, &c->R, &c->H, &c->cs, &c->g, &c->hcol, &c->hcol2, &c->nrm2,
-                       &c->bnorm, &c->est, &c->y, &c->partial, &c->scal};
+    double** bufs[] = {&c->V, &c->Z, &c->w, &c->R, &c->H, &c->cs, &c->hcol, &c->hcol2, &c->nrm2,
+                       &c->bnorm, &c->est, &c->y, &c->partial};
     for (double** b : bufs) {
         c->release(*b);
         *b = nullptr;
     }
-    c->release(c->active);
-    c->release(c->ncols);
+    c->release(c->rst_dev);
+    c->rst_dev = nullptr;
+    c->g = c->scal = nullptr;
     c->active = c->ncols = nullptr;
     if (c->host_pinned) (void)hipHostFree(c->host_pinned);
     c->host_pinned = nullptr;
+    if (c->rst_host) (void)hipHostFree(c->rst_host);
+    c->rst_host = nullptr;
     const int nb = krylov_blocks(c->gg.N);
     CHK(c->alloc((void**)&c->V, vec * (m + 1)));
     CHK(c->alloc((void**)&c->Z, vec * m));
@@ -377,7 +392,6 @@ int32_t ensure_krylov(ehh_ctx* c, int nrhs) {
     CHK(c->alloc((void**)&c->R, vec));
     CHK(c->alloc((void**)&c->H, sizeof(double) * 2 * (size_t)nrhs * m * (m + 1)));
     CHK(c->alloc((void**)&c->cs, sizeof(double) * 3 * (size_t)nrhs * m));
-    CHK(c->alloc((void**)&c->g, sizeof(double) * 2 * (size_t)nrhs * (m + 1)));
     CHK(c->alloc((void**)&c->hcol, sizeof(double) * 2 * (size_t)nrhs * (m + 1)));
     CHK(c->alloc((void**)&c->hcol2, sizeof(double) * 2 * (size_t)nrhs * (m + 1)));
     CHK(c->alloc((void**)&c->nrm2, sizeof(double) * nrhs));
@@ -385,12 +399,15 @@ int32_t ensure_krylov(ehh_ctx* c, int nrhs) {
     CHK(c->alloc((void**)&c->est, sizeof(double) * nrhs));
     CHK(c->alloc((void**)&c->y, sizeof(double) * 2 * (size_t)nrhs * m));
     CHK(c->alloc((void**)&c->partial, sizeof(double) * (size_t)nb * nrhs * (m + 1) * 2));
-    CHK(c->alloc((void**)&c->scal, sizeof(double) * nrhs));
-    CHK(c->alloc((void**)&c->active, sizeof(int) * nrhs));
-    CHK(c->alloc((void**)&c->ncols, sizeof(int) * nrhs));
+    const size_t rst_bytes = restart_block_bytes(nrhs, m);
+    CHK(c->alloc(&c->rst_dev, rst_bytes));
+    c->g = (double*)c->rst_dev;
+    c->scal = c->g + 2 * (size_t)nrhs * (m + 1);
+    c->active = (int*)(c->scal + nrhs);
+    c->ncols = c->active + nrhs;
     hipError_t e = hipHostMalloc((void**)&c->host_pinned, sizeof(double) * 4 * nrhs);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c->rst_host, rst_bytes);
     if (e != hipSuccess) {
-        c->host_pinned = nullptr;
         return fail(EHH_ERR_OOM, "hipHostMalloc failed");
     }
     c->kr_rhs = nrhs;
@@ -1061,6 +1078,13 @@ int32_t ehh_solve(ehh_handle_t h, const double* b, double* x, int32_t nrhs, doub
     const int64_t N = c->gg.N;
     const size_t vb = sizeof(double) * 2 * (size_t)N;
     double* hp = c->host_pinned;
+    // pinned mirror of the restart block, at the offsets of its device copy
+    // (laid out for the batch size it was allocated for, possibly larger)
+    char* const hb = c->rst_host;
+    double* hg = (double*)hb;
+    double* hs = (double*)(hb + ((char*)c->scal - (char*)c->g));
+    int* ha = (int*)(hb + ((char*)c->active - (char*)c->g));
+    int* hn = (int*)(hb + ((char*)c->ncols - (char*)c->g));
     LevelDesc<double> A{};
     A.g = c->gg;
     A.fine = true;
@@ -1114,9 +1138,12 @@ int32_t ehh_solve(ehh_handle_t h, const double* b, double* x, int32_t nrhs, doub
             inv_beta[r] = active[r] ? 1.0 / beta[r] : 0.0;
             ncols[r] = 0;
         }
-        HIPCHK(hipMemcpyAsync(c->g, g0.data(), sizeof(double) * g0.size(), hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(c->scal, inv_beta.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(c->active, active.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+        // g, scal and active in one copy from the pinned mirror (the stream has
+        // been synchronised since the mirror was last read)
+        std::memcpy(hg, g0.data(), sizeof(double) * g0.size());
+        std::memcpy(hs, inv_beta.data(), sizeof(double) * nrhs);
+        std::memcpy(ha, active.data(), sizeof(int) * nrhs);
+        HIPCHK(hipMemcpyAsync(c->g, hb, (char*)c->ncols - (char*)c->g, hipMemcpyHostToDevice, s));
         HIPCHK(launch_scale(c->R, c->V, N, nrhs, c->scal, 0, s, krylov_copy32(c)));
         int j = 0;
         for (j = 0; j < m; ++j) {
@@ -1158,13 +1185,16 @@ int32_t ehh_solve(ehh_handle_t h, const double* b, double* x, int32_t nrhs, doub
                 std::fflush(stderr);
             }
             if (left == 0 || it >= maxit || breakdown) break;
-            if (changed)
-                HIPCHK(hipMemcpyAsync(c->active, active.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+            if (changed) {
+                std::memcpy(ha, active.data(), sizeof(int) * nrhs);
+                HIPCHK(hipMemcpyAsync(c->active, ha, sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+            }
         }
         const int done_cols = std::min(j + 1, m);
         for (int r = 0; r < nrhs; ++r)
             if (active[r]) ncols[r] = done_cols;
-        HIPCHK(hipMemcpyAsync(c->ncols, ncols.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+        std::memcpy(hn, ncols.data(), sizeof(int) * nrhs);
+        HIPCHK(hipMemcpyAsync(c->ncols, hn, sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
         HIPCHK(launch_update_x(c->H, c->g, c->Z, x, N, nrhs, m, c->ncols, c->y, s));
         if (breakdown) break;
     }
