@@ -227,10 +227,22 @@ struct ehh_ctx {
     ~ehh_ctx() {
         clear_graphs();
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
-        (void)hipDeviceSynchronize();
+        std::vector<int> devs;
+        for (const Block& b : allocs)
+            if (std::find(devs.begin(), devs.end(), b.dev) == devs.end()) devs.push_back(b.dev);
+        for (int d : devs) sync_device(d);
         for (const Block& b : allocs) give_back(b);
         if (host_pinned) (void)hipHostFree(host_pinned);
         if (rst_host) (void)hipHostFree(rst_host);
+    }
+    // waits for the work queued on device d (the buffers' device, which need not
+    // be the current one)
+    static void sync_device(int d) {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        if (cur != d) (void)hipSetDevice(d);
+        (void)hipDeviceSynchronize();
+        if (cur != d) (void)hipSetDevice(cur);
     }
     static void give_back(const Block& b) {
         if (!BlockCache::get().put(b.dev, b.cls, b.p)) (void)hipFree(b.p);
@@ -277,7 +289,7 @@ struct ehh_ctx {
         }
         const Block b = *it;
         allocs.erase(it);
-        (void)hipDeviceSynchronize();   // work queued before the release may still read the block
+        sync_device(b.dev);   // work queued before the release may still read the block
         give_back(b);
     }
     int bits() const { return opt.precond_bits; }
@@ -923,8 +935,9 @@ int32_t enqueue_iter(ehh_ctx* c, const LevelDesc<double>& A, int j, int nrhs, hi
     // CGS2: h1 = V^H w; w -= V h1 and h2 = V^H w (one sweep); w -= V h2 with |w|^2
     HIPCHK(launch_dots(c->V, j + 1, c->w, N, nrhs, c->partial, c->hcol, m + 1, s));
     HIPCHK(launch_axpy_dots(c->V, j + 1, c->w, N, nrhs, c->hcol, m + 1, c->partial, c->hcol2, m + 1, s));
-    HIPCHK(launch_axpy_multi(c->V, j + 1, c->w, N, nrhs, c->hcol2, m + 1, c->partial, c->nrm2, s));
-    HIPCHK(launch_givens(c->H, c->cs, c->g, c->hcol, c->hcol2, c->nrm2, j, m, nrhs, c->active, c->est, c->bnorm, s));
+    HIPCHK(launch_axpy_multi(c->V, j + 1, c->w, N, nrhs, c->hcol2, m + 1, c->partial, c->nrm2, s, false));
+    HIPCHK(launch_givens(c->H, c->cs, c->g, c->hcol, c->hcol2, c->partial, N, c->nrm2, j, m, nrhs, c->active,
+                         c->est, c->bnorm, s));
     HIPCHK(launch_scale(c->w, c->V + (size_t)(j + 1) * nrhs * 2 * N, N, nrhs, c->nrm2, 1, s, v32));
     return EHH_OK;
 }

@@ -143,8 +143,10 @@ int krylov_blocks(int64_t n2);
 hipError_t launch_dots(const double* V, int nv, const double* w, int64_t N, int nrhs, double* partial,
                        double* h, int ldh, hipStream_t s);
 // w(r) -= sum_i h[r*ldh+i] V_i(r); optionally nrm2[r] = |w(r)|^2 (partial used).
+// nrm2 != null: the block partials of |w|^2 go to partial, and (norm_final)
+// their sum to nrm2; without norm_final the sum is left to launch_givens.
 hipError_t launch_axpy_multi(const double* V, int nv, double* w, int64_t N, int nrhs, const double* h,
-                             int ldh, double* partial, double* nrm2, hipStream_t s);
+                             int ldh, double* partial, double* nrm2, hipStream_t s, bool norm_final = true);
 // nrm2[r] = |x(r)|^2
 hipError_t launch_norm2(const double* x, int64_t N, int nrhs, double* partial, double* nrm2, hipStream_t s);
 // out(r) = x(r) * scale[r] (scale real; mode 1: 1/sqrt(scale[r])); out32, if
@@ -155,9 +157,10 @@ hipError_t launch_scale(const double* x, double* out, int64_t N, int nrhs, const
 hipError_t launch_axpy_dots(const double* V, int nv, double* w, int64_t N, int nrhs, const double* h, int ldh,
                             double* partial, double* hout, int ldo, hipStream_t s);
 // Givens update of column j of every right-hand side's Hessenberg matrix.
+// also forms nrm2 = |w|^2 from the partials launch_axpy_multi left (N: vector length)
 hipError_t launch_givens(double* H, double* cs, double* g, const double* hcol, const double* hcol2,
-                         const double* hnext2, int j, int m, int nrhs, const int* active, double* est,
-                         const double* bnorm, hipStream_t s);
+                         const double* partial, int64_t N, double* nrm2, int j, int m, int nrhs, const int* active,
+                         double* est, const double* bnorm, hipStream_t s);
 // y = R^{-1} g (columns ncols[r]); x(r) += sum_i y_i Z_i(r)
 hipError_t launch_update_x(const double* H, const double* g, const double* Z, double* x, int64_t N, int nrhs,
                            int m, const int* ncols, double* y, hipStream_t s);

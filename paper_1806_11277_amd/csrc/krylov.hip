@@ -198,10 +198,11 @@ __global__ __launch_bounds__(256) void k_norm_final(const double* __restrict__ p
 }
 
 hipError_t launch_axpy_multi(const double* V, int nv, double* w, int64_t N, int nrhs, const double* h, int ldh,
-                             double* partial, double* nrm2, hipStream_t s) {
+                             double* partial, double* nrm2, hipStream_t s, bool norm_final) {
     const int nb = krylov_blocks(N);
     hipLaunchKernelGGL(k_axpy_multi, dim3(nb, nrhs), KB, 0, s, V, nv, w, N, nrhs, h, ldh, nrm2 ? partial : nullptr);
-    if (nrm2) hipLaunchKernelGGL(k_norm_final, nblk((int64_t)nrhs * 64), 256, 0, s, partial, nb, nrhs, nrm2);
+    if (nrm2 && norm_final)
+        hipLaunchKernelGGL(k_norm_final, nblk((int64_t)nrhs * 64), 256, 0, s, partial, nb, nrhs, nrm2);
     return hipGetLastError();
 }
 
@@ -259,12 +260,20 @@ hipError_t launch_axpby(const double* x, const double* y, double* out, int64_t n
 // H[r][j][i] (column j, i <= m) complex; cs[r][i] = (c, s_re, s_im); g[r][i] complex.
 // hcol[r][i] + hcol2[r][i] for i <= j: <v_i, w> (complex, the two CGS passes),
 // hnext2[r] = |w|^2.
-__global__ void k_givens(double* __restrict__ H, double* __restrict__ cs, double* __restrict__ g,
-                         const double* __restrict__ hcol, const double* __restrict__ hcol2,
-                         const double* __restrict__ hnext2, int j, int m, int nrhs, const int* __restrict__ active,
-                         double* __restrict__ est, const double* __restrict__ bnorm) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+// One wavefront per right-hand side: |w|^2 = the fixed-order sum of the block
+// partials of k_axpy_multi (the sum k_norm_final forms, written to nrm2 for the
+// scaling of w), then lane 0 applies the rotations.
+__global__ __launch_bounds__(64) void k_givens(double* __restrict__ H, double* __restrict__ cs,
+                                               double* __restrict__ g, const double* __restrict__ hcol,
+                                               const double* __restrict__ hcol2, const double* __restrict__ partial,
+                                               int nblk_w, double* __restrict__ nrm2, int j, int m, int nrhs,
+                                               const int* __restrict__ active, double* __restrict__ est,
+                                               const double* __restrict__ bnorm) {
+    const int r = blockIdx.x;
     if (r >= nrhs) return;
+    const double w2 = wave_sum(partial + (int64_t)r * nblk_w, nblk_w);
+    if (threadIdx.x != 0) return;
+    nrm2[r] = w2;
     if (!active[r]) return;
     double* col = H + 2 * (((int64_t)r * m + j) * (m + 1));
     double* c = cs + 3 * (int64_t)r * m;
@@ -274,7 +283,7 @@ __global__ void k_givens(double* __restrict__ H, double* __restrict__ cs, double
         col[2 * i] = hcol[o] + hcol2[o];
         col[2 * i + 1] = hcol[o + 1] + hcol2[o + 1];
     }
-    col[2 * (j + 1)] = sqrt(hnext2[r]);
+    col[2 * (j + 1)] = sqrt(w2);
     col[2 * (j + 1) + 1] = 0.0;
     for (int i = 0; i < j; ++i) {
         const double cc = c[3 * i], sr = c[3 * i + 1], si = c[3 * i + 2];
@@ -324,10 +333,10 @@ __global__ void k_givens(double* __restrict__ H, double* __restrict__ cs, double
 }
 
 hipError_t launch_givens(double* H, double* cs, double* g, const double* hcol, const double* hcol2,
-                         const double* hnext2, int j, int m, int nrhs, const int* active, double* est,
-                         const double* bnorm, hipStream_t s) {
-    hipLaunchKernelGGL(k_givens, nblk(nrhs, 64), 64, 0, s, H, cs, g, hcol, hcol2, hnext2, j, m, nrhs, active, est,
-                       bnorm);
+                         const double* partial, int64_t N, double* nrm2, int j, int m, int nrhs, const int* active,
+                         double* est, const double* bnorm, hipStream_t s) {
+    hipLaunchKernelGGL(k_givens, nrhs, 64, 0, s, H, cs, g, hcol, hcol2, partial, krylov_blocks(N), nrm2, j, m, nrhs,
+                       active, est, bnorm);
     return hipGetLastError();
 }
 
