@@ -458,8 +458,12 @@ int32_t cycle(ehh_ctx* c, Sub& S, int l, const T* b, T* e, bool zero_init, int n
     const bool fuse = l + 1 < nl - 1 && c->opt.nu1 >= 1 &&
                       relax_restrict_supported<T>(level_desc<T>(c, C, c->prob.shift), nrhs);
     if (have) {
-        HIPCHK(launch_apply<T>(D, e, b, t, nrhs, s));   // t = b - A e
-        if (!fuse) HIPCHK(launch_restrict<T>(L.g, C.g, t, (T*)C.b, nrhs, s));
+        bool done = false;   // C.b = P^T (b - A e) in one launch where the kernels allow it
+        if (!fuse) HIPCHK(launch_residual_restrict<T>(D, C.g, e, b, (T*)C.b, nrhs, s, &done));
+        if (!done) {
+            HIPCHK(launch_apply<T>(D, e, b, t, nrhs, s));   // t = b - A e
+            if (!fuse) HIPCHK(launch_restrict<T>(L.g, C.g, t, (T*)C.b, nrhs, s));
+        }
     } else {
         HIPCHK(launch_zero(e, sizeof(T) * 2 * (size_t)L.g.N * nrhs, s));
         if (!fuse) HIPCHK(launch_restrict<T>(L.g, C.g, b, (T*)C.b, nrhs, s));
@@ -1350,14 +1354,22 @@ int32_t ehh_level_restrict(ehh_handle_t h, int32_t sub, int32_t level, const voi
     CHK(ensure_ws(h, nrhs));
     hipStream_t s = as_stream(stream);
     const Geo& gc = S->lev[level + 1].g;
+    bool done = false;
     if (h->bits() == 32) {
-        HIPCHK(launch_apply<float>(level_desc<float>(h, *L, h->prob.shift), (const float*)e, (const float*)b,
-                                   (float*)L->t, nrhs, s));
-        HIPCHK(launch_restrict<float>(L->g, gc, (const float*)L->t, (float*)rc, nrhs, s));
+        const LevelDesc<float> D = level_desc<float>(h, *L, h->prob.shift);
+        HIPCHK(launch_residual_restrict<float>(D, gc, (const float*)e, (const float*)b, (float*)rc, nrhs, s, &done));
+        if (!done) {
+            HIPCHK(launch_apply<float>(D, (const float*)e, (const float*)b, (float*)L->t, nrhs, s));
+            HIPCHK(launch_restrict<float>(L->g, gc, (const float*)L->t, (float*)rc, nrhs, s));
+        }
     } else {
-        HIPCHK(launch_apply<double>(level_desc<double>(h, *L, h->prob.shift), (const double*)e, (const double*)b,
-                                    (double*)L->t, nrhs, s));
-        HIPCHK(launch_restrict<double>(L->g, gc, (const double*)L->t, (double*)rc, nrhs, s));
+        const LevelDesc<double> D = level_desc<double>(h, *L, h->prob.shift);
+        HIPCHK(launch_residual_restrict<double>(D, gc, (const double*)e, (const double*)b, (double*)rc, nrhs, s,
+                                                &done));
+        if (!done) {
+            HIPCHK(launch_apply<double>(D, (const double*)e, (const double*)b, (double*)L->t, nrhs, s));
+            HIPCHK(launch_restrict<double>(L->g, gc, (const double*)L->t, (double*)rc, nrhs, s));
+        }
     }
     return EHH_OK;
 }

@@ -60,6 +60,11 @@ template <typename T>
 hipError_t launch_build_plans(const LevelDesc<T>& L, int colour, T* re, T* im, hipStream_t s);
 template <typename T>
 hipError_t launch_build_row_plans(const LevelDesc<T>& L, T* re, T* im, hipStream_t s);
+// rc = P^T (b - A e) in one launch from a 2D level with stored rows (vectors of
+// nrhs sources back to back); *done = false (nothing launched) elsewhere.
+template <typename T>
+hipError_t launch_residual_restrict(const LevelDesc<T>& L, const Geo& gc, const T* e, const T* b, T* rc, int nrhs,
+                                    hipStream_t s, bool* done);
 // FP16 copies of stored rows: *out = max over x of |x| as float bits (out
 // zeroed by the caller); y = x * inv_scale rounded to FP16.
 hipError_t launch_absmax_bits(const float* x, int64_t n, unsigned* out, hipStream_t s);

@@ -964,6 +964,114 @@ __global__ __launch_bounds__(256) void k_apply_st2d(Geo g, const T* __restrict__
     }
 }
 
+// rc = P^T (b - A e) from a 2D level with stored rows in one launch: sixteen
+// lanes per coarse unknown, lane j forming the fine residual of the j-th fine
+// unknown the coarse one gathers (twelve faces of the restriction's stencil,
+// the weights of restrict_at2d, or the four cells of a pressure) from the
+// stored rows as k_apply_st2d does, scaled by its weight; the sixteen products
+// are summed by a butterfly over the lanes.  A fine residual shared by
+// neighbouring coarse unknowns is formed once for each (the level is small
+// and in the caches), which saves writing the fine residual and the
+// restriction's own launch.
+template <typename T>
+__global__ __launch_bounds__(256) void k_residual_restrict2d(Geo gf, Geo gc, const T* __restrict__ e,
+                                                             const T* __restrict__ b, T* __restrict__ rc,
+                                                             int nrhs, const T* __restrict__ cre,
+                                                             const T* __restrict__ cim) {
+    constexpr int NF = St<2>::NF, NUP = St<2>::NUP, NT = NF + NUP;
+    const int gl = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int Nc = (int)gc.N, N = (int)gf.N;
+    const int tc0 = gl >> 4, j = gl & 15;
+    const bool live = tc0 < Nc;
+    const int tc = live ? tc0 : 0;
+    const int ncx = gc.n[0], nfx = gf.n[0], nfy = gf.n[1];
+    int k, X, Y;
+    if (tc >= (int)gc.off[3]) {
+        const int li = tc - (int)gc.off[3];
+        k = 3;
+        X = li % ncx;
+        Y = li / ncx;
+    } else if (tc < (int)gc.off[1]) {
+        const int li = tc - (int)gc.off[0];
+        k = 0;
+        X = li % (ncx - 1) + 1;
+        Y = li / (ncx - 1);
+    } else {
+        const int li = tc - (int)gc.off[1];
+        k = 1;
+        X = li % ncx;
+        Y = li / ncx + 1;
+    }
+    // this lane's fine unknown (row position p, index ix) and weight
+    int p[3] = {0, 0, 0};
+    int ix = 0;
+    T wt = T(0);
+    if (k == 3) {
+        p[0] = 2 * X + (j & 1);
+        p[1] = 2 * Y + ((j >> 1) & 1);
+        ix = (int)gf.off[3] + p[1] * nfx + p[0];
+        wt = j < 4 ? T(1) : T(0);
+    } else {
+        const bool k0 = k == 0;
+        const int a = (j >> 2) - 1, b1 = (j & 3) - 1;
+        const int fn = 2 * (k0 ? X : Y) + a, ft = 2 * (k0 ? Y : X) + b1, nt = k0 ? nfy : nfx;
+        const bool ok = j < 12 && ft >= 0 && ft < nt;
+        const int fc = ft < 0 ? 0 : (ft >= nt ? nt - 1 : ft);
+        // (lanes 12..15, a = 2, carry no weight; their face is clamped into the grid)
+        const int nn = k0 ? nfx : nfy;
+        const int fnc = fn < 1 ? 1 : (fn > nn - 1 ? nn - 1 : fn);
+        p[0] = k0 ? fnc : fc;
+        p[1] = k0 ? fc : fnc;
+        ix = k0 ? (int)gf.off[0] + fc * (nfx - 1) + fnc - 1 : (int)gf.off[1] + (fnc - 1) * nfx + fc;
+        wt = ok ? (a == 0 ? T(1) : T(0.5)) * T(w_tang(b1)) : T(0);
+    }
+    const bool act = live && wt != T(0);
+    if (!act) ix = 0;
+    const int kf = k;
+    const Cols2 cc = cols2(gf, kf, p);
+    const Buf<T> cR(cre, (uint32_t)(NT * N * sizeof(T))), cI(cim, (uint32_t)(NF * N * sizeof(T)));
+    const uint32_t lo = (uint32_t)ix * (uint32_t)sizeof(T), ls = (uint32_t)N * (uint32_t)sizeof(T);
+    // pressure rows: unused terms and imaginary parts are stored as zeros, and
+    // inactive lanes read nothing
+    const uint32_t lr = act ? lo : OOB_OFF, lq = (act && kf != 3) ? lo : OOB_OFF;
+    T are[NT], aim[NF];
+#pragma unroll
+    for (int jj = 0; jj < NT; ++jj) are[jj] = cR.ld(jj > 2 * NUP ? lq : lr, jj * ls);
+#pragma unroll
+    for (int jj = 0; jj < NF; ++jj) aim[jj] = cI.ld(lq, jj * ls);
+    const uint32_t vb = 2 * ls;
+    for (int r = 0; r < nrhs; ++r) {
+        const Buf<T> xv(e + (int64_t)r * 2 * N, vb);
+        T vr[NT], vi[NT];
+#pragma unroll
+        for (int jj = 0; jj < NT; ++jj) {
+            const uint32_t o = (uint32_t)col2(cc, jj) * (uint32_t)sizeof(T);
+            vr[jj] = xv.ld(o, 0);
+            vi[jj] = xv.ld(o, ls);
+        }
+        const Buf<T> bv(b + (int64_t)r * 2 * N, vb);
+        const T br = bv.ld(lo, 0), bi = bv.ld(lo, ls);
+        __builtin_amdgcn_sched_barrier(0);
+        T ar = T(0), ai = T(0);
+#pragma unroll
+        for (int jj = 0; jj < NT; ++jj) {
+            const T ci = jj < NF ? aim[jj] : T(0);
+            ar += are[jj] * vr[jj] - ci * vi[jj];
+            ai += are[jj] * vi[jj] + ci * vr[jj];
+        }
+        T sr = act ? wt * (br - ar) : T(0), si = act ? wt * (bi - ai) : T(0);
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) {
+            sr += __shfl_xor(sr, o, 16);
+            si += __shfl_xor(si, o, 16);
+        }
+        if (live && j == 0) {
+            rc[(int64_t)r * 2 * Nc + tc] = sr;
+            rc[(int64_t)r * 2 * Nc + Nc + tc] = si;
+        }
+    }
+}
+
 // ------------------------------------ stored Galerkin rows with computed columns (3D)
 // As in 2D: a 3D Galerkin level keeps its rows' coefficients in the order the
 // kernels read them (93 real parts, 75 u-u imaginary parts per row), and a term's
@@ -2971,6 +3079,24 @@ hipError_t launch_prolong(const Geo& gf, const Geo& gc, const T* ec, T* ef, int 
         hipLaunchKernelGGL((k_prolong<3, T>), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef, nrhs);
     return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_residual_restrict(const LevelDesc<T>& L, const Geo& gc, const T* e, const T* b, T* rc, int nrhs,
+                                    hipStream_t s, bool* done) {
+    *done = false;
+    // one launch pays with few sources (c2, one FP64 source: 114.6 -> 113.1 ms per
+    // solve); a lane walks its sources in turn, so with 32 sources the separate
+    // residual and restriction, which spread them over more lanes, are faster
+    if (L.g.dim != 2 || L.fine || !L.sp.rre || L.sp.half || nrhs > 4) return hipSuccess;
+    hipLaunchKernelGGL((k_residual_restrict2d<T>), nblk((int64_t)gc.N * 16), 256, 0, s, L.g, gc, e, b, rc, nrhs,
+                       L.sp.rre, L.sp.rim);
+    *done = true;
+    return hipGetLastError();
+}
+template hipError_t launch_residual_restrict<float>(const LevelDesc<float>&, const Geo&, const float*, const float*,
+                                                    float*, int, hipStream_t, bool*);
+template hipError_t launch_residual_restrict<double>(const LevelDesc<double>&, const Geo&, const double*,
+                                                     const double*, double*, int, hipStream_t, bool*);
 
 // FP16 copies of stored rows: max |x| over the rows (the bit patterns of
 // non-negative floats order as integers, so an integer maximum is exact), then
