@@ -1027,13 +1027,12 @@ __global__ __launch_bounds__(256) void k_residual_restrict2d(Geo gf, Geo gc, con
     }
     const bool act = live && wt != T(0);
     if (!act) ix = 0;
-    const int kf = k;
-    const Cols2 cc = cols2(gf, kf, p);
+    const Cols2 cc = cols2(gf, k, p);
     const Buf<T> cR(cre, (uint32_t)(NT * N * sizeof(T))), cI(cim, (uint32_t)(NF * N * sizeof(T)));
     const uint32_t lo = (uint32_t)ix * (uint32_t)sizeof(T), ls = (uint32_t)N * (uint32_t)sizeof(T);
     // pressure rows: unused terms and imaginary parts are stored as zeros, and
     // inactive lanes read nothing
-    const uint32_t lr = act ? lo : OOB_OFF, lq = (act && kf != 3) ? lo : OOB_OFF;
+    const uint32_t lr = act ? lo : OOB_OFF, lq = (act && k != 3) ? lo : OOB_OFF;
     T are[NT], aim[NF];
 #pragma unroll
     for (int jj = 0; jj < NT; ++jj) are[jj] = cR.ld(jj > 2 * NUP ? lq : lr, jj * ls);
@@ -2777,8 +2776,9 @@ static inline int env_int(const char* name, int dflt) {
     const char* v = std::getenv(name);
     return v ? std::atoi(v) : dflt;
 }
-static inline int rhs_per_block(int64_t waves, int nrhs, int rb) {
-    static const int64_t target = env_int("EHH_WAVES", 2048);
+static inline int rhs_per_block(int64_t waves, int nrhs, int rb, int64_t target = 0) {
+    static const int64_t dflt = env_int("EHH_WAVES", 2048);
+    if (target <= 0) target = dflt;
     int64_t groups = waves >= target ? 1 : (target + waves - 1) / waves;
     const int64_t maxg = (nrhs + rb - 1) / rb;
     if (groups > maxg) groups = maxg;
@@ -2946,13 +2946,15 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
         else if (L.sp.re[colour]) {
 #define EHH_RELAX_ST3D(RB, CH, C)                                                                                 \
     {                                                                                                             \
-        const int rpbs = rhs_per_block((npair * 8 + 63) / 64, nrhs, RB);                                          \
+        const int rpbs = rhs_per_block((npair * 8 + 63) / 64, nrhs, RB, 4096);                                    \
         hipLaunchKernelGGL((k_relax_st3d<T, RB, CH, C>), dim3(nblk(npair * 8), (nrhs + rpbs - 1) / rpbs), 256, 0,  \
                            s, L.g, colour, tw, econ, b, ein, eout, nrhs, stride, rpbs, (const C*)L.sp.re[colour], \
                            (const C*)L.sp.im[colour], L.sp.lanes, (T)L.sp.scale);                                 \
     }
             // measured on MI355X (36^3 level, 16 FP32 sources): 8 sources per
-            // coefficient load in chunks of 8 terms 284 us, of 4 terms 299 us
+            // coefficient load in chunks of 8 terms 284 us, of 4 terms 299 us;
+            // source groups sized for 4096 wavefronts (two groups of 8 there)
+            // 273 us against 284 us for 2048 (one group of 16)
             // (both two wavefronts per SIMD); with the row-loop addresses held
             // across the loop (one wavefront per SIMD) 8 x 4 took 331 us, 8 x 2
             // 335 us, 4 x 4 358 us, 16 x 2 322 us but 2x slower on 18^3
