@@ -129,6 +129,14 @@ __global__ __launch_bounds__(256) void k_dd_gather_res(Geo gg, Geo gl, SubMap m,
         else if (D == 3 && k == 2) op.plan_u(2, p, P);
         else op.plan_p(p, P);
     }
+    // 32-bit byte offsets into per-source buffer descriptors (a global vector
+    // stays below 4 GiB, checked by the launcher) instead of a 64-bit address
+    // per term and source
+    uint32_t zo[Op::NT];
+#pragma unroll
+    for (int j = 0; j < Op::NT; ++j) zo[j] = (uint32_t)P.ix[j] * 8u;
+    const uint32_t vo = gi >= 0 ? (uint32_t)gi * 8u : 0u;
+    const uint32_t NB = (uint32_t)gg.N * 8u, VB = 2u * NB;
     constexpr int RB = 4;
     for (int r0 = 0; r0 < nrhs; r0 += RB) {
         cx<double> az[RB], vz[RB];
@@ -137,8 +145,16 @@ __global__ __launch_bounds__(256) void k_dd_gather_res(Geo gg, Geo gl, SubMap m,
             const int r = r0 + q < nrhs ? r0 + q : r0;
             az[q] = vz[q] = mk<double>(0.0, 0.0);
             if (gi >= 0) {
-                az[q] = P.dot(CVec<double>{z + (int64_t)r * 2 * gg.N, gg.N});
-                vz[q] = CVec<double>{v + (int64_t)r * 2 * gg.N, gg.N}.ld(gi);
+                const Buf<double> zb(z + (int64_t)r * 2 * gg.N, VB), vb(v + (int64_t)r * 2 * gg.N, VB);
+                double ar = 0.0, ai = 0.0;   // the sum of Plan::dot, in its order
+#pragma unroll
+                for (int j = 0; j < Op::NT; ++j) {
+                    const double er = zb.ld(zo[j], 0), ei = zb.ld(zo[j], NB);
+                    ar += P.re[j] * er - P.im[j] * ei;
+                    ai += P.re[j] * ei + P.im[j] * er;
+                }
+                az[q] = mk<double>(ar, ai);
+                vz[q] = mk<double>(vb.ld(vo, 0), vb.ld(vo, NB));
             }
         }
 #pragma unroll
@@ -154,6 +170,7 @@ __global__ __launch_bounds__(256) void k_dd_gather_res(Geo gg, Geo gl, SubMap m,
 template <typename T>
 hipError_t launch_dd_gather_res(const Geo& gg, const Geo& gl, const SubMap& m, const FineCoef<double>& A,
                                 const double* v, const double* z, T* out, int nrhs, hipStream_t s) {
+    if (16 * gg.N >= (int64_t(1) << 32)) return hipErrorInvalidValue;   // 32-bit byte offsets per source
     if (gg.dim == 2)
         hipLaunchKernelGGL((k_dd_gather_res<2, T>), nblk(gl.N), 256, 0, s, gg, gl, m, A, v, z, out, nrhs);
     else

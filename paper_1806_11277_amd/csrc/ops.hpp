@@ -27,6 +27,56 @@ EHH_DEV void lds_barrier() {
 // A matrix row as (index, coefficient) terms, built once per row and then
 // applied to every right-hand side: terms beyond the row's support point at a
 // valid index with a zero coefficient.
+// Raw buffer access: a scalar resource descriptor (base, size in bytes) plus a
+// 32-bit byte offset per lane, so that a kernel keeps one VGPR per address.
+// Reads past the descriptor's size return zero.
+typedef uint32_t ehh_u2 __attribute__((ext_vector_type(2)));
+template <typename T> struct Buf;
+template <> struct Buf<float> {
+    __amdgpu_buffer_rsrc_t r;
+    EHH_DEV Buf() {}
+    EHH_DEV Buf(const void* p, uint32_t bytes)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000)) {}
+    EHH_DEV float ld(uint32_t off) const { return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0)); }
+    // per-lane offset plus a wave-uniform one (kept in a scalar register)
+    EHH_DEV float ld(uint32_t off, uint32_t soff) const {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
+    }
+    EHH_DEV void st(uint32_t off, float v) const {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
+    }
+};
+template <> struct Buf<double> {
+    __amdgpu_buffer_rsrc_t r;
+    EHH_DEV Buf() {}
+    EHH_DEV Buf(const void* p, uint32_t bytes)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000)) {}
+    EHH_DEV double ld(uint32_t off) const {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    }
+    EHH_DEV double ld(uint32_t off, uint32_t soff) const {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0));
+    }
+    EHH_DEV void st(uint32_t off, double v) const {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(ehh_u2, v), r, off, 0, 0);
+    }
+};
+
+// FP16 storage (stored rows of the 3D Galerkin levels in the complex64 cycle when
+// asked for): loads only, widened by the caller.
+template <> struct Buf<_Float16> {
+    __amdgpu_buffer_rsrc_t r;
+    EHH_DEV Buf() {}
+    EHH_DEV Buf(const void* p, uint32_t bytes)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000)) {}
+    EHH_DEV _Float16 ld(uint32_t off) const {
+        return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
+    }
+    EHH_DEV _Float16 ld(uint32_t off, uint32_t soff) const {
+        return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, off, soff, 0));
+    }
+};
+
 template <typename T, int NT> struct Plan {
     int32_t ix[NT];
     T re[NT], im[NT];
