@@ -456,7 +456,7 @@ int32_t cycle(ehh_ctx* c, Sub& S, int l, const T* b, T* e, bool zero_init, int n
     // the restriction to a coarser level that is not the coarsest is fused into
     // that level's first half-sweep where its kernels allow it
     const bool fuse = l + 1 < nl - 1 && c->opt.nu1 >= 1 &&
-                      relax_restrict_supported<T>(level_desc<T>(c, C, c->prob.shift), nrhs);
+                      relax_restrict_supported<T>(level_desc<T>(c, C, c->prob.shift), L.g, nrhs);
     if (have) {
         bool done = false;   // C.b = P^T (b - A e) in one launch where the kernels allow it
         if (!fuse) HIPCHK(launch_residual_restrict<T>(D, C.g, e, b, (T*)C.b, nrhs, s, &done));

@@ -47,7 +47,7 @@ hipError_t launch_relax_to64(const LevelDesc<float>& L, double w, int econ, cons
 // First half-sweep (colour 0) of a visit from zero with the restriction fused:
 // b = P^T rf (rf on the finer grid gf) is formed, written to b, and relaxed.
 template <typename T>
-bool relax_restrict_supported(const LevelDesc<T>& L, int nrhs);
+bool relax_restrict_supported(const LevelDesc<T>& L, const Geo& gf, int nrhs);
 template <typename T>
 hipError_t launch_relax_restrict(const LevelDesc<T>& L, double w, int econ, const Geo& gf, const T* rf, T* b,
                                  T* eout, int nrhs, hipStream_t s);

@@ -440,6 +440,11 @@ EHH_DEV float w_tang(int d) { return (d == 0 || d == 1) ? 0.75f : ((d == -1 || d
 template <typename T>
 EHH_DEV cx<T> restrict_at2d(const Geo& gf, const T* __restrict__ rf, int k, int X, int Y) {
     const int Nf = (int)gf.N, nfx = gf.n[0], nfy = gf.n[1];
+    // 32-bit byte offsets into a buffer descriptor (the callers keep a vector
+    // below 4 GiB), the imaginary plane through the scalar offset
+    const Buf<T> rv(rf, 2u * (uint32_t)Nf * (uint32_t)sizeof(T));
+    const uint32_t NB = (uint32_t)Nf * (uint32_t)sizeof(T);
+    constexpr uint32_t E = (uint32_t)sizeof(T);
     T sr = T(0), si = T(0);
     if (k == 3) {
         const int b = (int)gf.off[3] + 2 * Y * nfx + 2 * X;
@@ -447,8 +452,8 @@ EHH_DEV cx<T> restrict_at2d(const Geo& gf, const T* __restrict__ rf, int k, int 
         T vr[4], vi[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            vr[j] = rf[ix[j]];
-            vi[j] = rf[Nf + ix[j]];
+            vr[j] = rv.ld(E * (uint32_t)ix[j], 0);
+            vi[j] = rv.ld(E * (uint32_t)ix[j], NB);
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -458,30 +463,37 @@ EHH_DEV cx<T> restrict_at2d(const Geo& gf, const T* __restrict__ rf, int k, int 
         return mk<T>(sr, si);
     }
     const bool k0 = k == 0;
+    // the weights are constants of (a, b1); only the tangential rows outside
+    // the grid (b1 = -1 at the low wall, b1 = 2 at the high wall) drop out, so
+    // the weights are applied as constants with a select on those two cases
+    const int fn0 = 2 * (k0 ? X : Y), ft0 = 2 * (k0 ? Y : X), nt = k0 ? nfy : nfx;
+    const bool lo_ok = ft0 - 1 >= 0, hi_ok = ft0 + 2 < nt;
     int ix[12];
-    T wt[12];
 #pragma unroll
     for (int a = -1; a <= 1; ++a)
 #pragma unroll
         for (int b1 = -1; b1 <= 2; ++b1) {
             const int j = (a + 1) * 4 + b1 + 1;
-            const int fn = 2 * (k0 ? X : Y) + a, ft = 2 * (k0 ? Y : X) + b1, nt = k0 ? nfy : nfx;
-            const bool ok = ft >= 0 && ft < nt;
+            const int fn = fn0 + a, ft = ft0 + b1;
             const int fc = ft < 0 ? 0 : (ft >= nt ? nt - 1 : ft);
             ix[j] = k0 ? (int)gf.off[0] + fc * (nfx - 1) + fn - 1 : (int)gf.off[1] + (fn - 1) * nfx + fc;
-            wt[j] = ok ? (a == 0 ? T(1) : T(0.5)) * T(w_tang(b1)) : T(0);
         }
     T vr[12], vi[12];
 #pragma unroll
     for (int j = 0; j < 12; ++j) {
-        vr[j] = rf[ix[j]];
-        vi[j] = rf[Nf + ix[j]];
+        vr[j] = rv.ld(E * (uint32_t)ix[j], 0);
+        vi[j] = rv.ld(E * (uint32_t)ix[j], NB);
     }
 #pragma unroll
-    for (int j = 0; j < 12; ++j) {
-        sr += wt[j] * vr[j];
-        si += wt[j] * vi[j];
-    }
+    for (int a = -1; a <= 1; ++a)
+#pragma unroll
+        for (int b1 = -1; b1 <= 2; ++b1) {
+            const int j = (a + 1) * 4 + b1 + 1;
+            const T wc = (a == 0 ? T(1) : T(0.5)) * T(w_tang(b1));
+            const T wt = b1 == -1 ? (lo_ok ? wc : T(0)) : (b1 == 2 ? (hi_ok ? wc : T(0)) : wc);
+            sr += wt * vr[j];
+            si += wt * vi[j];
+        }
     return mk<T>(sr, si);
 }
 
@@ -2944,9 +2956,11 @@ hipError_t launch_relax_to64(const LevelDesc<float>& L, double w, int econ, cons
 }
 
 template <typename T>
-bool relax_restrict_supported(const LevelDesc<T>& L, int nrhs) {
+bool relax_restrict_supported(const LevelDesc<T>& L, const Geo& gf, int nrhs) {
     static const bool on = env_int("EHH_RELAX_RESTRICT", 1) != 0;
     if (!on || L.g.dim != 2 || L.fine || !L.sp.re[0]) return false;
+    // the finer level's residual is read through a buffer descriptor
+    if (2 * gf.N * (int64_t)sizeof(T) >= (int64_t(1) << 32)) return false;
     // same routing as launch_relax: the LDS kernel serves large levels with many sources
     return !(L.g.ncell >= 65536 && lds2d_enabled() && nrhs > 8);
 }
@@ -2961,8 +2975,8 @@ hipError_t launch_relax_restrict(const LevelDesc<T>& L, double w, int econ, cons
                        (const T*)nullptr, eout, nrhs, stride, rpb, L.sp.re[0], L.sp.im[0], L.sp.lanes, gf, rf, b);
     return hipGetLastError();
 }
-template bool relax_restrict_supported<float>(const LevelDesc<float>&, int);
-template bool relax_restrict_supported<double>(const LevelDesc<double>&, int);
+template bool relax_restrict_supported<float>(const LevelDesc<float>&, const Geo&, int);
+template bool relax_restrict_supported<double>(const LevelDesc<double>&, const Geo&, int);
 template hipError_t launch_relax_restrict<float>(const LevelDesc<float>&, double, int, const Geo&, const float*,
                                                  float*, float*, int, hipStream_t);
 template hipError_t launch_relax_restrict<double>(const LevelDesc<double>&, double, int, const Geo&, const double*,
@@ -3012,7 +3026,8 @@ template hipError_t launch_build_plans<double>(const LevelDesc<double>&, int, do
 
 template <typename T>
 hipError_t launch_restrict(const Geo& gf, const Geo& gc, const T* rf, T* rc, int nrhs, hipStream_t s) {
-    if (gf.dim == 2 && transfer2d_enabled() && 2 * gf.N < (int64_t(1) << 31))
+    // (k_restrict2d reads the fine vector through a buffer descriptor: below 4 GiB)
+    if (gf.dim == 2 && transfer2d_enabled() && 2 * gf.N * (int64_t)sizeof(T) < (int64_t(1) << 32))
         hipLaunchKernelGGL((k_restrict2d<T>), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc);
     else if (gf.dim == 2)
         hipLaunchKernelGGL((k_restrict<2, T>), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc, nrhs);
