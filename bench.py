@@ -276,6 +276,26 @@ def kernel_roofline(w, reps=30):
                 kernels=sorted(groups.values(), key=lambda g: -g["us_per_cycle"]), levels=rows)
 
 
+def copy_bandwidth(mib=1024, reps=10):
+    """Achievable device bandwidth for context: a plain 1 GiB device-to-device
+    copy (read + write bytes over the best of `reps` timed copies)."""
+    import torch
+    src = torch.ones(mib * 2 ** 20 // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    del src, dst
+    return 2 * mib * 2 ** 20 / best / 1e9
+
+
 def cpu_baseline(w, gpu_iters, budget_s=20.0):
     """The oracle as it stands (numpy/scipy, FP64) on this host: hierarchy setup
     plus as many FGMRES iterations as fit in the budget, scaled to a full solve
@@ -413,6 +433,9 @@ def main():
     if not a.no_roofline:
         print("[bench] roofline of the dominant kernel", file=sys.stderr, flush=True)
         out["roofline"] = kernel_roofline(w)
+        cg = copy_bandwidth()
+        out["roofline"]["copy_gbs"] = cg          # achievable plain-copy bandwidth on this GPU (context)
+        out["roofline"]["frac_of_copy"] = out["roofline"]["achieved"] / cg
     if a.batched:
         wb = get_config(a.batched)
         print(f"[bench] batched companion {wb.name}", file=sys.stderr, flush=True)
@@ -428,6 +451,9 @@ def main():
                           "speedup_vs_plain_fp64_single_source": vb / out["value"]}
         if not a.no_roofline:
             out["batched"]["roofline"] = kernel_roofline(wb)
+            cg = out["roofline"]["copy_gbs"]
+            out["batched"]["roofline"]["copy_gbs"] = cg
+            out["batched"]["roofline"]["frac_of_copy"] = out["batched"]["roofline"]["achieved"] / cg
     if not a.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, int(np.median(iters)))
