@@ -2197,10 +2197,13 @@ __global__ __launch_bounds__(512) void k_relax_lds2d(Op op, int colour, T w, int
         }
         return o < 0 ? 0 : o;
     };
+    // LDS offsets (below 2^16) packed two to a register
+    uint32_t pk[(Op::NT + 1) / 2];
 #pragma unroll
-    for (int j = 0; j < Op::NT; ++j) {
-        const int o = to_lds(P.ix[j]);
-        P.ix[j] = o;
+    for (int j = 0; j < (Op::NT + 1) / 2; ++j) {
+        const uint32_t lo = (uint32_t)to_lds(P.ix[2 * j]);
+        const uint32_t hi = 2 * j + 1 < Op::NT ? (uint32_t)to_lds(P.ix[2 * j + 1]) : 0u;
+        pk[j] = lo | (hi << 16);
     }
     own = ok ? to_lds(idx) : 0;
     const bool carry = live && row == R;
@@ -2233,51 +2236,87 @@ __global__ __launch_bounds__(512) void k_relax_lds2d(Op op, int colour, T w, int
     }
     const cx<T> iS = row == 0 ? cinv(S) : mk<T>(T(0), T(0));
 
+    // Byte offset of each tile entry this thread stages (OOB_OFF outside the grid:
+    // the buffer load returns zero), computed once for all right-hand sides.
+    constexpr int NREG = (LT_X + 3) * (LT_Y + 4) + (LT_X + 4) * (LT_Y + 3) + (LT_X + 2) * (LT_Y + 2);
+    constexpr int NST = (NREG + 511) / 512;
+    uint32_t vo[NST];
+#pragma unroll
+    for (int i = 0; i < NST; ++i) {
+        const int e = threadIdx.x + i * 512;
+        vo[i] = OOB_OFF;
+        if (e < nreg) {
+            int kk, q0, q1;
+            if (e < b1) {
+                kk = 0;
+                q0 = e % w0x + o0x;
+                q1 = e / w0x + o0y;
+            } else if (e < bp) {
+                kk = 1;
+                q0 = (e - b1) % w1x + o1x;
+                q1 = (e - b1) / w1x + o1y;
+            } else {
+                kk = 3;
+                q0 = (e - bp) % wpx + opx;
+                q1 = (e - bp) / wpx + opy;
+            }
+            const int q[3] = {q0, q1, 0};
+            const bool in = kk == 3 ? cell_ok<D>(g, q) : face_ok<D>(g, kk, q);
+            if (in)
+                vo[i] = (uint32_t)(kk == 3 ? g.off[3] + cell_idx<D>(g, q) : g.off[kk] + face_idx<D>(g, kk, q)) * sizeof(T);
+        }
+    }
+    // The buffers span this block's right-hand sides (under 2 GiB, checked at
+    // launch); the source is selected by a wave-uniform offset.
+    const uint32_t span = (uint32_t)(nrhs * stride * (int64_t)sizeof(T));
+    const uint32_t imo = (uint32_t)(g.N * sizeof(T));
+    const Buf<T> eb(ein, ein ? span : 0u), bb(b, span);
+    const uint32_t bo = ok ? (uint32_t)idx * sizeof(T) : OOB_OFF;
+    cx<T> nst[NST], nb;
+    auto fetch = [&](int r) {
+        const uint32_t so = (uint32_t)(r * stride * (int64_t)sizeof(T));
+        if (ein) {
+#pragma unroll
+            for (int i = 0; i < NST; ++i) nst[i] = mk<T>(eb.ld(vo[i], so), eb.ld(vo[i], so + imo));
+        }
+        nb = mk<T>(bb.ld(bo, so), bb.ld(bo, so + imo));
+    };
     for (int r = 0; r < nrhs; ++r) {
-        const CVec<T> bv{b + r * stride, g.N};
+        fetch(r);
         const Vec<T> ov{eout + r * stride, g.N};
+        const cx<T> bcur = nb;
         cx<T> res = mk<T>(T(0), T(0));
         cx<T> eown = mk<T>(T(0), T(0)), ecarry = mk<T>(T(0), T(0));
         if (ein) {
-            const CVec<T> ev{ein + r * stride, g.N};
             lds_barrier();   // the previous right-hand side is done with the tile
-            for (int e = threadIdx.x; e < nreg; e += blockDim.x) {
-                int kk, q0, q1;
-                if (e < b1) {
-                    kk = 0;
-                    q0 = e % w0x + o0x;
-                    q1 = e / w0x + o0y;
-                } else if (e < bp) {
-                    kk = 1;
-                    q0 = (e - b1) % w1x + o1x;
-                    q1 = (e - b1) / w1x + o1y;
-                } else {
-                    kk = 3;
-                    q0 = (e - bp) % wpx + opx;
-                    q1 = (e - bp) / wpx + opy;
+#pragma unroll
+            for (int i = 0; i < NST; ++i) {
+                const int e = threadIdx.x + i * 512;
+                if (e < nreg) {
+                    sre[e] = nst[i].re;
+                    sim[e] = nst[i].im;
                 }
-                const int q[3] = {q0, q1, 0};
-                const bool in = kk == 3 ? cell_ok<D>(g, q) : face_ok<D>(g, kk, q);
-                cx<T> v = mk<T>(T(0), T(0));
-                if (in) v = ev.ld(kk == 3 ? g.off[3] + cell_idx<D>(g, q) : g.off[kk] + face_idx<D>(g, kk, q));
-                sre[e] = v.re;
-                sim[e] = v.im;
             }
             lds_barrier();
             if (ok) {
+                // keeps the unpacking inside the loop (hoisted, it would take a
+                // register per term again)
+#pragma unroll
+                for (int j = 0; j < (Op::NT + 1) / 2; ++j) asm volatile("" : "+v"(pk[j]));
                 T ar = T(0), ai = T(0);
 #pragma unroll
                 for (int j = 0; j < Op::NT; ++j) {
-                    const T vr = sre[P.ix[j]], vi = sim[P.ix[j]];
+                    const uint32_t o = (j & 1) ? (pk[j >> 1] >> 16) : (pk[j >> 1] & 0xffffu);
+                    const T vr = sre[o], vi = sim[o];
                     ar += P.re[j] * vr - P.im[j] * vi;
                     ai += P.re[j] * vi + P.im[j] * vr;
                 }
-                res = bv.ld(idx) - mk<T>(ar, ai);
+                res = bcur - mk<T>(ar, ai);
                 eown = mk<T>(sre[own], sim[own]);
             }
             if (carry) ecarry = mk<T>(sre[ownb], sim[ownb]);
         } else if (ok) {
-            res = bv.ld(idx);
+            res = bcur;
         }
         cx<T> rr[R];
 #pragma unroll
@@ -2866,9 +2905,11 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
     // sources the stored plans win (one FP64 source: 30 us against 53 us), and at
     // 128^2 and below the block-wide synchronisation costs more than it saves.
     const bool big_batch = !(L.sp.re[colour] && nrhs <= 8);
-    if (L.g.dim == 2 && !L.fine && L.g.ncell >= 65536 && lds2d_enabled() && big_batch) {
-        const int tiles = ((L.g.n[0] + LT_X - 1) / LT_X) * ((L.g.n[1] + LT_Y - 1) / LT_Y);
-        const int rpl = rhs_per_block((int64_t)tiles * 8, nrhs, 1);
+    const int lds_tiles = ((L.g.n[0] + LT_X - 1) / LT_X) * ((L.g.n[1] + LT_Y - 1) / LT_Y);
+    const int rpl = rhs_per_block((int64_t)lds_tiles * 8, nrhs, 1);
+    if (L.g.dim == 2 && !L.fine && L.g.ncell >= 65536 && rpl * stride * (int64_t)sizeof(T) < (int64_t(1) << 31) &&
+        lds2d_enabled() && big_batch) {
+        const int tiles = lds_tiles;
         const dim3 gl(tiles, (nrhs + rpl - 1) / rpl);
         hipLaunchKernelGGL((k_relax_lds2d<T, StOp<2, T>>), gl, 512, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride, rpl, 2);
     } else if (L.g.dim == 2 && L.fine && cell2d_enabled() && 2 * L.g.N * (int64_t)sizeof(T) < (int64_t(1) << 32)) {

@@ -153,3 +153,27 @@ def test_c5_gradient_matches_oracle_and_differences():
         say(f"  {names[which]} cell {c}: fd {fd:.6e} adjoint {an:.6e}")
         assert abs(fd - an) <= 1e-4 * abs(an)
     say(f"  worst relative difference {worst:.3e}")
+
+
+@pytest.mark.parametrize("with_e", [False, True])
+@pytest.mark.parametrize("colour", [0, 1])
+def test_c2_level1_relax_many_sources(c2_oracle, colour, with_e):
+    """The 256^2 Galerkin level relaxed for 12 right-hand sides at once, the
+    launch that stages each source's tile in LDS (more than eight sources),
+    compared source by source with the oracle's half-sweep."""
+    import torch
+    w, pb, H = c2_oracle
+    say(f"[c2 level 1 half-sweep, 12 sources, colour={colour} e_in={with_e}]")
+    S = _solver(w)
+    N = H.A[1].shape[0]
+    assert S.level_info(0, 1)["N"] == N
+    b = rand_cvec(N, 12, 80 + colour)
+    e = rand_cvec(N, 12, 90 + colour) if with_e else np.zeros((12, N), complex)
+    out = torch.zeros_like(to_dev(b))
+    S.level_relax(0, 1, colour, to_dev(b), to_dev(e) if with_e else None, out)
+    torch.cuda.synchronize()
+    got = from_dev(out)
+    for q in range(12):
+        ref = H.relax(1, b[q], e[q], colour)
+        assert np.linalg.norm(got[q] - ref) <= 1e-11 * np.linalg.norm(ref), q
+    S.close()
