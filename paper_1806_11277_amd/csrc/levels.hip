@@ -688,9 +688,12 @@ __global__ __launch_bounds__(256) void k_relax_st2d(Geo g, int colour, T w, int 
                     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                     for (int j = 0; j < NT; ++j) {
-                        const T ci = j < NF ? aim[KEEP ? j : 0] : T(0);
-                        ar += are[KEEP ? j : 0] * vr[j] - ci * vi[j];
-                        ai += are[KEEP ? j : 0] * vi[j] + ci * vr[j];
+                        ar = fma(are[KEEP ? j : 0], vr[j], ar);
+                        ai = fma(are[KEEP ? j : 0], vi[j], ai);
+                        if (j < NF) {
+                            ar = fma(-aim[KEEP ? j : 0], vi[j], ar);
+                            ai = fma(aim[KEEP ? j : 0], vr[j], ai);
+                        }
                     }
                 } else {
                     // The columns are recomputed per right-hand side, and the
@@ -723,8 +726,12 @@ __global__ __launch_bounds__(256) void k_relax_st2d(Geo g, int colour, T w, int 
 #pragma unroll
                         for (int jj = 0; jj < H; ++jj) {
                             if (h + jj < NT) {
-                                ar += cr_[jj] * vr[jj] - ci_[jj] * vi[jj];
-                                ai += cr_[jj] * vi[jj] + ci_[jj] * vr[jj];
+                                ar = fma(cr_[jj], vr[jj], ar);
+                                ai = fma(cr_[jj], vi[jj], ai);
+                                if (h + jj < NF) {
+                                    ar = fma(-ci_[jj], vi[jj], ar);
+                                    ai = fma(ci_[jj], vr[jj], ai);
+                                }
                             }
                         }
                     }
@@ -817,8 +824,12 @@ __global__ __launch_bounds__(256) void k_relax_st2d_split(Geo g, int colour, T w
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int jj = 0; jj < NT - HT; ++jj) {
-                    ar += cr_[jj] * vr[jj] - ci_[jj] * vi[jj];
-                    ai += cr_[jj] * vi[jj] + ci_[jj] * vr[jj];
+                    ar = fma(cr_[jj], vr[jj], ar);
+                    ai = fma(cr_[jj], vi[jj], ai);
+                    if (HT + jj < NF) {
+                        ar = fma(-ci_[jj], vi[jj], ar);
+                        ai = fma(ci_[jj], vr[jj], ai);
+                    }
                 }
             }
             part[r & 1][grp][0][lane] = ar;
@@ -854,8 +865,12 @@ __global__ __launch_bounds__(256) void k_relax_st2d_split(Geo g, int colour, T w
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int jj = 0; jj < HT; ++jj) {
-                    ar += cr_[jj] * vr[jj] - ci_[jj] * vi[jj];
-                    ai += cr_[jj] * vi[jj] + ci_[jj] * vr[jj];
+                    ar = fma(cr_[jj], vr[jj], ar);
+                    ai = fma(cr_[jj], vi[jj], ai);
+                    if (jj < NF) {
+                        ar = fma(-ci_[jj], vi[jj], ar);
+                        ai = fma(ci_[jj], vr[jj], ai);
+                    }
                 }
             }
             V.factor(dre, dim, ore, oim, gg, base, row);
@@ -918,9 +933,12 @@ __global__ __launch_bounds__(256) void k_apply_st2d(Geo g, const T* __restrict__
         T ar = T(0), ai = T(0);
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
-            const T ci = j < NF ? aim[j] : T(0);
-            ar += are[j] * vr[j] - ci * vi[j];
-            ai += are[j] * vi[j] + ci * vr[j];
+            ar = fma(are[j], vr[j], ar);
+            ai = fma(are[j], vi[j], ai);
+            if (j < NF) {
+                ar = fma(-aim[j], vi[j], ar);
+                ai = fma(aim[j], vr[j], ai);
+            }
         }
         cx<T> o = mk<T>(ar, ai);
         if (b) o = CVec<T>{b + r * stride, g.N}.ld(t) - o;
@@ -1018,9 +1036,12 @@ __global__ __launch_bounds__(256) void k_residual_restrict2d(Geo gf, Geo gc, con
         T ar = T(0), ai = T(0);
 #pragma unroll
         for (int jj = 0; jj < NT; ++jj) {
-            const T ci = jj < NF ? aim[jj] : T(0);
-            ar += are[jj] * vr[jj] - ci * vi[jj];
-            ai += are[jj] * vi[jj] + ci * vr[jj];
+            ar = fma(are[jj], vr[jj], ar);
+            ai = fma(are[jj], vi[jj], ai);
+            if (jj < NF) {
+                ar = fma(-aim[jj], vi[jj], ar);
+                ai = fma(aim[jj], vr[jj], ai);
+            }
         }
         T sr = act ? wt * (br - ar) : T(0), si = act ? wt * (bi - ai) : T(0);
 #pragma unroll
@@ -2282,6 +2303,10 @@ __global__ __launch_bounds__(512) void k_relax_lds2d(Op op, int colour, T w, int
         nb = mk<T>(bb.ld(bo, so), bb.ld(bo, so + imo));
     };
     for (int r = 0; r < nrhs; ++r) {
+        // keeps the unpacking of the LDS indices inside the loop (hoisted, it
+        // would take a register per term again)
+#pragma unroll
+        for (int j = 0; j < (Op::NT + 1) / 2; ++j) asm volatile("" : "+v"(pk[j]));
         fetch(r);
         const Vec<T> ov{eout + r * stride, g.N};
         const cx<T> bcur = nb;
@@ -2299,17 +2324,19 @@ __global__ __launch_bounds__(512) void k_relax_lds2d(Op op, int colour, T w, int
             }
             lds_barrier();
             if (ok) {
-                // keeps the unpacking inside the loop (hoisted, it would take a
-                // register per term again)
-#pragma unroll
-                for (int j = 0; j < (Op::NT + 1) / 2; ++j) asm volatile("" : "+v"(pk[j]));
+                // one fused multiply-add per real product; the u-p and p-u terms
+                // (from St<2>::NF on) are real
                 T ar = T(0), ai = T(0);
 #pragma unroll
                 for (int j = 0; j < Op::NT; ++j) {
                     const uint32_t o = (j & 1) ? (pk[j >> 1] >> 16) : (pk[j >> 1] & 0xffffu);
                     const T vr = sre[o], vi = sim[o];
-                    ar += P.re[j] * vr - P.im[j] * vi;
-                    ai += P.re[j] * vi + P.im[j] * vr;
+                    ar = fma(P.re[j], vr, ar);
+                    ai = fma(P.re[j], vi, ai);
+                    if (j < St<2>::NF) {
+                        ar = fma(-P.im[j], vi, ar);
+                        ai = fma(P.im[j], vr, ai);
+                    }
                 }
                 res = bcur - mk<T>(ar, ai);
                 eown = mk<T>(sre[own], sim[own]);
