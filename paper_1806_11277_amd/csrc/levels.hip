@@ -1174,8 +1174,10 @@ EHH_DEV void rows3_rb(const Buf<C>& cR, const Buf<C>& cI, uint32_t lo, uint32_t 
             if (h + jj < NT) {
 #pragma unroll
                 for (int q = 0; q < RB; ++q) {
-                    ar[q] += cr[jj] * vr[jj][q] - ci[jj] * vi[jj][q];
-                    ai[q] += cr[jj] * vi[jj][q] + ci[jj] * vr[jj][q];
+                    ar[q] = fma(cr[jj], vr[jj][q], ar[q]);
+                    ar[q] = fma(-ci[jj], vi[jj][q], ar[q]);
+                    ai[q] = fma(cr[jj], vi[jj][q], ai[q]);
+                    ai[q] = fma(ci[jj], vr[jj][q], ai[q]);
                 }
             }
         }
