@@ -177,3 +177,36 @@ def test_c2_level1_relax_many_sources(c2_oracle, colour, with_e):
         ref = H.relax(1, b[q], e[q], colour)
         assert np.linalg.norm(got[q] - ref) <= 1e-11 * np.linalg.norm(ref), q
     S.close()
+
+
+@pytest.fixture(scope="module")
+def ragged_oracle():
+    from _helpers import small_hetero
+    w = small_hetero((528, 520), "ragged528x520", levels=4)
+    say("[528 x 520: oracle problem and hierarchy]")
+    pb = oracle_problem(w)
+    H = oracle_hierarchy(w, pb)
+    return w, pb, H
+
+
+@pytest.mark.parametrize("colour", [0, 1])
+def test_ragged_level1_relax_many_sources(ragged_oracle, colour):
+    """The LDS-staged half-sweep on a 264 x 260 Galerkin level, whose sides are
+    not multiples of the 16 x 8 cell tile (partial tiles at the right and top
+    walls), for 12 sources, against the oracle's half-sweep."""
+    import torch
+    w, pb, H = ragged_oracle
+    say(f"[264 x 260 level half-sweep, 12 sources, colour={colour}]")
+    S = _solver(w)
+    N = H.A[1].shape[0]
+    assert S.level_info(0, 1)["N"] == N
+    b = rand_cvec(N, 12, 100 + colour)
+    e = rand_cvec(N, 12, 110 + colour)
+    out = torch.zeros_like(to_dev(b))
+    S.level_relax(0, 1, colour, to_dev(b), to_dev(e), out)
+    torch.cuda.synchronize()
+    got = from_dev(out)
+    for q in range(12):
+        ref = H.relax(1, b[q], e[q], colour)
+        assert np.linalg.norm(got[q] - ref) <= 1e-11 * np.linalg.norm(ref), q
+    S.close()
