@@ -661,6 +661,10 @@ __global__ __launch_bounds__(256) void k_relax_st2d(Geo g, int colour, T w, int 
         const CVec<T> bv{b + r * stride, g.N};
         cx<T> res = mk<T>(T(0), T(0));
         cx<T> eown = mk<T>(T(0), T(0));
+        // the other colour's pressure, loaded before the row's terms so that its
+        // latency is not added after the block solve
+        cx<T> ecarry = mk<T>(T(0), T(0));
+        if (carry && ein) ecarry = CVec<T>{ein + r * stride, g.N}.ld(ipb);
         if (RST) {
             const Vec<T> bo{bw + r * stride, g.N};
             if (ok) {
@@ -746,7 +750,7 @@ __global__ __launch_bounds__(256) void k_relax_st2d(Geo g, int colour, T w, int 
         const cx<T> mine = V.solve(res, base, row);
         const Vec<T> ov{eout + r * stride, g.N};
         if (ok) ov.st(idx, eown + w * mine);
-        if (carry) ov.st(ipb, ein ? CVec<T>{ein + r * stride, g.N}.ld(ipb) : mk<T>(T(0), T(0)));
+        if (carry) ov.st(ipb, ecarry);
     }
 }
 
@@ -837,6 +841,8 @@ __global__ __launch_bounds__(256) void k_relax_st2d_split(Geo g, int colour, T w
         } else {
             T dre = T(1), dim = T(0), ore = T(0), oim = T(0), gg = T(0);
             cx<T> bo = mk<T>(T(0), T(0));
+            cx<T> ecarry = mk<T>(T(0), T(0));
+            if (carry) ecarry = CVec<T>{ein + r * stride, g.N}.ld(ipb);
             if (row < R && slot_ok) {
                 T cr_[HT], ci_[HT], vr[HT], vi[HT];
 #pragma unroll
@@ -879,7 +885,7 @@ __global__ __launch_bounds__(256) void k_relax_st2d_split(Geo g, int colour, T w
             const cx<T> mine = V.solve(res, base, row);
             const Vec<T> ov{eout + r * stride, g.N};
             if (ok) ov.st(idx, eown + w * mine);
-            if (carry) ov.st(ipb, CVec<T>{ein + r * stride, g.N}.ld(ipb));
+            if (carry) ov.st(ipb, ecarry);
             continue;
         }
         lds_barrier();
