@@ -340,3 +340,151 @@ def test_dd_mg_fgmres_converges(colours):
     b = disc.point_source_vector(n, [(0, (10, 5), 1.0), (1, (20, 20), 0.5j)])
     x, st = krylov.fgmres(lambda v: A @ v, P.apply, b, tol=1e-8, restart=5, maxit=300)
     assert st["converged"] and st["rel_res_true"] <= 1e-8
+
+
+# ------------------------------------------------- W-cycle and Algorithm 2 schedule pins
+def _dense(M):
+    return M.toarray() if sp.issparse(M) else np.asarray(M)
+
+
+def _smoother_propagation(H, l):
+    """Error propagation of one red-black Vanka step on level l (red, then
+    black): S_c = I - w sum_K E_K B_K^{-1} E_K^T A over the cells K of colour c,
+    B_K the cell's local matrix (section 3)."""
+    B, dofs, colour = H.blocks[l]
+    A = _dense(H.A[l])
+    n = A.shape[0]
+    S = np.eye(n, dtype=complex)
+    for c in (0, 1):
+        Wc = np.zeros((n, n), complex)
+        for K in np.nonzero(colour == c)[0]:
+            d = dofs[K]
+            ok = d >= 0
+            Bi = np.linalg.inv(B[K])[np.ix_(ok, ok)]
+            Wc[np.ix_(d[ok], d[ok])] += H.damping[l] * Bi
+        S = (np.eye(n) - Wc @ A) @ S
+    return S
+
+
+@pytest.mark.parametrize("levels,cycle_level", [(3, 0), (4, 1)])
+def test_w_cycle_second_call_continues_from_the_first(levels, cycle_level):
+    """Algorithm 1 with gamma recursive calls (section 2.2), written as the
+    textbook error propagation: E_l = S^nu2 (I - P_l X_{l+1} P_l^T A_l) S^nu1 with
+    X_{l+1} = (I - E_{l+1}^gamma) A_{l+1}^{-1} (gamma calls, each continuing from
+    the previous one's result) and X_L = A_L^{-1}; one cycle from zero is
+    (I - E_0) A_0^{-1}.  A second call that restarts from zero gives
+    X = (I - E) A^{-1} instead and fails.  (Without smoothing both readings
+    agree: the Galerkin coarse correction is a projection.)"""
+    n = (32, 16) if levels == 4 else (16, 16)
+    lam, mu, rho, gam = _hetero(n, 30)
+    A = disc.assemble(n, 1.0, 0.8, lam, mu, rho, gam, 0.5)
+    H = mg.Hierarchy(A, n, levels, [0.75, 0.5, 0.5], cycle=2, nu1=1, nu2=1, cycle_level=cycle_level)
+    Ad = [_dense(a) for a in H.A]
+    Pd = [_dense(p) for p in H.P]
+    L = levels - 1
+
+    def propagation(restart_second_call):
+        X = np.linalg.inv(Ad[L])
+        E = None
+        for l in range(L - 1, -1, -1):
+            I = np.eye(Ad[l].shape[0])
+            S = _smoother_propagation(H, l)
+            E = S @ (I - Pd[l] @ X @ Pd[l].T @ Ad[l]) @ S
+            if l > 0:
+                g = 2 if (l - 1 >= cycle_level and l < L) else 1
+                Eg = E if (g == 1 or restart_second_call) else E @ E
+                X = (I - Eg) @ np.linalg.inv(Ad[l])
+        return E
+
+    rng = np.random.default_rng(31)
+    r = rng.standard_normal(A.shape[0]) + 1j * rng.standard_normal(A.shape[0])
+    x = np.linalg.solve(Ad[0], r)
+    want = x - propagation(False) @ x
+    got = H.cycle(r)
+    assert np.linalg.norm(got - want) <= 1e-10 * np.linalg.norm(want)
+    wrong = x - propagation(True) @ x
+    assert np.linalg.norm(got - wrong) > 1e-4 * np.linalg.norm(want)
+
+
+def _alg2_rows_solved(P, pb, v):
+    """Largest |v - A z| / |v| over the rows where Algorithm 2 with exact local
+    solves must leave no residual: after the last colour c, for every subdomain
+    of colour c, the rows of its extent whose global row couples only to unknowns
+    of the extent and equals the local operator's row.  Returns (max residual,
+    rows checked, rows of the subdomains)."""
+    A = pb.matrix()
+    z = P.apply(v)
+    res = v - A @ z
+    last = max(s.colour for s in P.subs)
+    worst, count, total = 0.0, 0, 0
+    for i, sub in enumerate(P.subs):
+        if sub.colour != last:
+            continue
+        m = P.maps[i]
+        inside = np.nonzero(m >= 0)[0]
+        total += inside.size
+        gset = np.zeros(A.shape[0], bool)
+        gset[m[inside]] = True
+        Al = sp.csr_matrix(P.hier[i].A[0])
+        for li in inside:
+            row = A.getrow(m[li]).tocoo()
+            if np.any(~gset[row.col] & (np.abs(row.data) > 0)):
+                continue
+            # the local row, mapped to global columns
+            lrow = Al.getrow(li).tocoo()
+            if np.any(m[lrow.col] < 0) and np.any(np.abs(lrow.data[m[lrow.col] < 0]) > 0):
+                continue
+            a = np.zeros(A.shape[0], complex)
+            a[row.col] = row.data
+            b = np.zeros(A.shape[0], complex)
+            ok = m[lrow.col] >= 0
+            b[m[lrow.col[ok]]] = lrow.data[ok]
+            if np.max(np.abs(a - b)) > 0:
+                continue
+            worst = max(worst, abs(res[m[li]]))
+            count += 1
+    return worst / np.linalg.norm(v), count, total
+
+
+class _AdditiveColours(ddm.DDPreconditioner):
+    """Planted mistake: every colour starts from v itself (no residual update
+    between colours)."""
+
+    def apply(self, v):
+        v = np.asarray(v, dtype=np.complex128)
+        z = np.zeros_like(v)
+        for i in range(len(self.subs)):
+            e = self.hier[i].cycle(self.restrict(i, v))
+            m = self.maps[i]
+            ok = m >= 0
+            np.add.at(z, m[ok], e[ok])
+        return z
+
+
+@pytest.mark.parametrize("n,parts", [((24, 12), (2, 1)), ((24, 24), (2, 2))])
+def test_algorithm2_colours_start_from_the_updated_residual(n, parts):
+    """Algorithm 2 (section 2.3) with exact local solves (one level), no padding
+    and no shift: each colour's local solve makes the global residual vanish on
+    the rows of its subdomains that only couple inside the extent, so after the
+    last colour those rows carry no residual.  The additive variant (all colours
+    from the same residual) leaves residual on the overlap rows and fails."""
+    pb = _dd_problem(n, 32)
+    pb.shift = 0.0
+    P = ddm.DDPreconditioner(pb, parts, 4, 0, 1, [], colours=2 ** len(n))
+    rng = np.random.default_rng(33)
+    v = rng.standard_normal(pb.size) + 1j * rng.standard_normal(pb.size)
+    worst, count, total = _alg2_rows_solved(P, pb, v)
+    assert count >= total // 2, (count, total)
+    assert worst <= 1e-12
+    bad = _AdditiveColours(pb, parts, 4, 0, 1, [], colours=2 ** len(n))
+    worst_bad, _, _ = _alg2_rows_solved(bad, pb, v)
+    assert worst_bad > 1e-3
+
+
+def test_convergence_factor_of_a_geometric_history():
+    """c_f = (r_k / r_w)^(1/(k - w)) (section 5.4): exactly rho for a residual
+    history that decays by rho per iteration after an arbitrary warm-up."""
+    rho = 0.83
+    hist = [1.0, 3.0, 0.5, 2.0, 0.9] + [0.7 * rho ** k for k in range(40)]
+    assert abs(krylov.convergence_factor(hist, warmup=5) - rho) < 1e-13
+    assert np.isnan(krylov.convergence_factor([1.0, 0.5], warmup=5))
