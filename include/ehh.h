@@ -39,6 +39,7 @@
  *   nondimensional w.
  *
  * Memory and streams
+ *   Pointers marked (host) are ordinary host memory, read during the call.
  *   Pointers marked (device) are HIP device pointers; the caller owns them and
  *   keeps them alive until the work on `stream` (a hipStream_t, NULL = default
  *   stream) has completed.  The handle owns everything it allocates.  A handle
@@ -124,14 +125,17 @@ void ehh_default_options(ehh_options_t* opt);
  * and the inverse of every coarsest operator) and, with domain decomposition,
  * one padded subdomain hierarchy per subdomain (section 2.1 for the
  * coefficients, eq. (9) for the hierarchy, section 4 for the subdomains).
- *   lambda, mu, rho: (device) FP64 cell arrays [Pa, Pa, kg/m^3], x fastest;
- *                    rho > 0, mu >= 0, lambda + mu > 0.
- *   gamma:           (device) FP64 physical attenuation [1/s] per cell, or NULL.
- *   stream:          work is enqueued on it; the call synchronises it once to
- *                    read the media means.
+ *   lambda, mu, rho: (host) FP64 cell arrays [Pa, Pa, kg/m^3], x fastest, copied
+ *                    to the device during the call (the handle keeps only its
+ *                    own nondimensional coefficients); rho > 0, mu >= 0,
+ *                    lambda + mu > 0.
+ *   gamma:           (host) FP64 physical attenuation [1/s] per cell, or NULL.
+ *   stream:          work is enqueued on it; the call synchronises it before
+ *                    returning.
  *   out:             receives the handle (set only on EHH_OK).
- * Errors: EHH_ERR_INVALID (sizes, levels, options), EHH_ERR_BREAKDOWN (non-finite
- * or non-physical media), EHH_ERR_OOM, EHH_ERR_HIP. */
+ * Errors: EHH_ERR_INVALID (sizes, levels, options, a media pointer that is
+ * device memory), EHH_ERR_BREAKDOWN (non-finite or non-physical media),
+ * EHH_ERR_OOM (nothing is kept: a later setup starts afresh), EHH_ERR_HIP. */
 int32_t ehh_setup_operator(const ehh_problem_t* problem, const double* lambda,
                            const double* mu, const double* rho, const double* gamma,
                            const ehh_options_t* options, void* stream, ehh_handle_t* out);
@@ -164,7 +168,11 @@ int32_t ehh_apply(ehh_handle_t h, int32_t shifted, const double* x, double* y,
 /* One multigrid cycle (Algorithm 1, recursive, zero initial guess) of the shifted
  * operator of subdomain `sub` (0 without domain decomposition): e ~ A_s^{-1} r.
  * r, e: (device) vectors in the subdomain's level-0 layout (ehh_level_info),
- * float when precond_bits == 32, double when 64; r and e distinct. */
+ * float when precond_bits == 32, double when 64; r and e distinct.
+ * The cycle precision is not an argument: it is fixed at setup
+ * (ehh_options_t.precond_bits), because the hierarchy's coefficients are built
+ * in that precision; the subdomain index takes its place, since with domain
+ * decomposition every padded subdomain has its own hierarchy. */
 int32_t ehh_vcycle(ehh_handle_t h, int32_t sub, const void* r, void* e, int32_t nrhs,
                    void* stream);
 

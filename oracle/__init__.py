@@ -12,4 +12,4 @@ batched dense solves) as the only building blocks.
 It shares no code with the HIP path.  The only common inputs are the seeded
 media and sources from ``workloads``.
 """
-from . import discretisation, multigrid, dd, krylov, gradient  # noqa: F401
+from . import discretisation, multigrid, dd, krylov, gradient, direct  # noqa: F401

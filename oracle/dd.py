@@ -127,6 +127,19 @@ def local_to_global(n, sub: Subdomain):
     return np.concatenate(out)
 
 
+def local_operator(problem: disc.Problem, sub: Subdomain, abl_max=1.0):
+    """Shifted operator of a padded subdomain (section 4): the global medium
+    copied onto the local grid (edge-replicated outside the domain), the
+    subdomain's padding given the quadratic absorbing ramp of section 2.1, and
+    the global shift."""
+    n = problem.n
+    lam = _take_cells(problem.lam, sub, n)
+    mu = _take_cells(problem.mu, sub, n)
+    rho = _take_cells(problem.rho, sub, n)
+    gam = _take_cells(problem.gamma_hat, sub, n) + padding_gamma(sub, abl_max)
+    return disc.assemble(sub.nloc, 1.0, problem.omega, lam, mu, rho, gam, problem.shift)
+
+
 class DDPreconditioner:
     """DD-MG: one multigrid cycle of the local shifted operator per subdomain."""
 
@@ -141,11 +154,7 @@ class DDPreconditioner:
         self.maps, self.hier = [], []
         cnt = np.zeros(problem.size)
         for sub in self.subs:
-            lam = _take_cells(problem.lam, sub, n)
-            mu = _take_cells(problem.mu, sub, n)
-            rho = _take_cells(problem.rho, sub, n)
-            gam = _take_cells(problem.gamma_hat, sub, n) + padding_gamma(sub, abl_max)
-            A_loc = disc.assemble(sub.nloc, 1.0, problem.omega, lam, mu, rho, gam, problem.shift)
+            A_loc = local_operator(problem, sub, abl_max)
             self.hier.append(mg.Hierarchy(A_loc, sub.nloc, levels, damping, economic, cycle))
             m = local_to_global(n, sub)
             self.maps.append(m)

@@ -35,7 +35,7 @@ def _flags(src: str):
     if src.endswith(".hip"):
         # packed FP32 instructions are kept out of the device code
         f += ["-x", "hip", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-              "-munsafe-fp-atomics", "-ffp-contract=fast"]
+              "-ffp-contract=fast"]
     return f
 
 

@@ -45,9 +45,26 @@ int32_t fail(int32_t code, const std::string& msg) {
         if (s_ != EHH_OK) return s_;   \
     } while (0)
 
-// Optional injected allocation failure (EHH_FAIL_ALLOC_AFTER=k: the (k+1)-th
-// device allocation of the process fails), for testing the OOM path.
+// Optional injected allocation failure, for testing the OOM path:
+// EHH_FAIL_ALLOC_AFTER=k makes the device allocation that follows k successful
+// ones fail, once; the count restarts whenever the variable's value changes
+// (read at every allocation), so one process can inject a failure at each
+// allocation point in turn.
+std::mutex g_inject_mutex;
+std::string g_inject_value;
 long g_alloc_count = 0;
+bool injected_failure() {
+    const char* s = std::getenv("EHH_FAIL_ALLOC_AFTER");
+    std::lock_guard<std::mutex> l(g_inject_mutex);
+    const std::string v = s ? s : "";
+    if (v != g_inject_value) {
+        g_inject_value = v;
+        g_alloc_count = 0;
+    }
+    if (v.empty()) return false;
+    const long lim = std::atol(v.c_str());
+    return lim >= 0 && g_alloc_count++ == lim;
+}
 
 // Device memory cache.  A setup-solve-destroy cycle would otherwise pay
 // hipMalloc for every buffer and hipFree, which waits for the whole device, for
@@ -143,13 +160,6 @@ struct PhaseLog {
         t0 = t1;
     }
 };
-long fail_alloc_after() {
-    static long v = [] {
-        const char* s = std::getenv("EHH_FAIL_ALLOC_AFTER");
-        return s ? std::atol(s) : -1L;
-    }();
-    return v;
-}
 
 struct Level {
     Geo g{};
@@ -257,9 +267,7 @@ struct ehh_ctx {
     int32_t alloc(void** p, size_t bytes) {
         *p = nullptr;
         if (bytes == 0) bytes = 8;
-        const long lim = fail_alloc_after();
-        if (lim >= 0 && g_alloc_count >= lim) return fail(EHH_ERR_OOM, "injected allocation failure");
-        ++g_alloc_count;
+        if (injected_failure()) return fail(EHH_ERR_OOM, "injected allocation failure");
         int dev = 0;
         (void)hipGetDevice(&dev);
         const size_t cls = BlockCache::size_class(bytes);
@@ -339,6 +347,9 @@ hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 int32_t ensure_ws(ehh_ctx* c, int nrhs) {
     if (nrhs <= c->ws_rhs) return EHH_OK;
     c->clear_graphs();
+    // a growth that fails part way leaves no capacity behind, so that the next
+    // call allocates again instead of using released buffers
+    c->ws_rhs = 0;
     const size_t es = c->bits() == 32 ? sizeof(float) : sizeof(double);
     for (Sub& S : c->subs) {
         for (size_t l = 0; l < S.lev.size(); ++l) {
@@ -381,6 +392,7 @@ size_t restart_block_bytes(int nrhs, int m) {
 int32_t ensure_krylov(ehh_ctx* c, int nrhs) {
     if (nrhs <= c->kr_rhs) return EHH_OK;
     c->clear_graphs();
+    c->kr_rhs = 0;   // as in ensure_ws: a failed growth leaves no capacity
     const int m = c->opt.restart;
     const size_t vec = 2 * (size_t)c->gg.N * nrhs * sizeof(double);
     double** bufs[] = {&c->V, &c->Z, &c->w, &c->R, &c->H, &c->cs, &c->hcol, &c->hcol2, &c->nrm2,
@@ -809,12 +821,37 @@ int32_t build_hierarchy(ehh_ctx* c, Sub& S, const double* lam, const double* mu,
     return EHH_OK;
 }
 
-int32_t setup_impl(ehh_ctx* c, const double* lam, const double* mu, const double* rho, const double* gam,
-                   hipStream_t s) {
+// A host array: rejects pointers the runtime knows as device memory (the media
+// of ehh_setup_operator are host arrays, copied at setup).
+bool is_device_pointer(const void* p) {
+    hipPointerAttribute_t a{};
+    const hipError_t e = hipPointerGetAttributes(&a, p);
+    (void)hipGetLastError();   // unregistered host memory may report an error here
+    return e == hipSuccess && a.type == hipMemoryTypeDevice;
+}
+
+int32_t setup_impl(ehh_ctx* c, const double* lam_h, const double* mu_h, const double* rho_h,
+                   const double* gam_h, hipStream_t s) {
     const ehh_problem_t& P = c->prob;
     c->dim = P.dim;
     int n[3] = {P.n[0], P.n[1], P.dim == 3 ? P.n[2] : 1};
     c->gg = make_geo(P.dim, n);
+    // the host media, copied to the device for the setup kernels and released at
+    // the end of the setup (the operator keeps its own nondimensional planes)
+    for (const double* hp : {lam_h, mu_h, rho_h, gam_h})
+        if (hp && is_device_pointer(hp)) return fail(EHH_ERR_INVALID, "media must be host arrays");
+    const int64_t ncell0 = c->gg.ncell;
+    double* media = nullptr;
+    CHK(c->alloc((void**)&media, sizeof(double) * (gam_h ? 4 : 3) * ncell0));
+    const double* lam = media;
+    const double* mu = media + ncell0;
+    const double* rho = media + 2 * ncell0;
+    const double* gam = gam_h ? media + 3 * ncell0 : nullptr;
+    const size_t mb = sizeof(double) * ncell0;
+    HIPCHK(hipMemcpyAsync((void*)lam, lam_h, mb, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync((void*)mu, mu_h, mb, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync((void*)rho, rho_h, mb, hipMemcpyHostToDevice, s));
+    if (gam_h) HIPCHK(hipMemcpyAsync((void*)gam, gam_h, mb, hipMemcpyHostToDevice, s));
     // media means and physical check
     const int nb = media_check_blocks(c->gg.ncell);
     double* part = nullptr;
@@ -907,6 +944,7 @@ int32_t setup_impl(ehh_ctx* c, const double* lam, const double* mu, const double
         if (fine32) S.lev[0].coef32 = fine32;
     }
     HIPCHK(hipStreamSynchronize(s));
+    c->release(media);
     return EHH_OK;
 }
 

@@ -130,10 +130,54 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _host_media(a, ncell, name):
+    """A host float64 copy of a media array (numpy or torch, any device), with
+    exactly ncell entries; the library copies it to the device at setup."""
+    import numpy as np
+    try:
+        import torch
+        if isinstance(a, torch.Tensor):
+            a = a.detach().to("cpu", torch.float64).numpy()
+    except ImportError:  # pragma: no cover
+        pass
+    out = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if out.size != ncell:
+        raise ValueError(f"{name} has {out.size} entries, the grid has {ncell} cells")
+    return out
+
+
+def _overlap(a, b):
+    a0, b0 = a.data_ptr(), b.data_ptr()
+    return a0 < b0 + b.numel() * b.element_size() and b0 < a0 + a.numel() * a.element_size()
+
+
+def _check_vectors(named, dtype, rows, cols, outputs=()):
+    """Every (name, tensor) in named must be a contiguous device tensor of the
+    given dtype and shape (rows, cols); a tensor named in `outputs` must not
+    share memory with any other listed tensor.  Raises ValueError before
+    anything reaches the library."""
+    for name, t in named:
+        if t is None:
+            continue
+        if not getattr(t, "is_cuda", False) or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous device tensor")
+        if t.dtype != dtype:
+            raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+        if tuple(t.shape) != (rows, cols):
+            raise ValueError(f"{name} must have shape ({rows}, {cols}), got {tuple(t.shape)}")
+    for on, o in named:
+        if on not in outputs or o is None:
+            continue
+        for n_, t in named:
+            if n_ != on and t is not None and _overlap(o, t):
+                raise ValueError(f"{on} must not overlap {n_}")
+
+
 class Solver:
-    """Owns one ehh handle.  Media: float64 device tensors shaped like the cell
-    grid (x fastest).  Vectors: (nrhs, 2N) tensors on the device, float64 for
-    the global vectors, the cycle precision for level vectors."""
+    """Owns one ehh handle.  Media: float64 arrays shaped like the cell grid (x
+    fastest), numpy or torch; they are handed to the library as host arrays and
+    copied to the device at setup.  Vectors: (nrhs, 2N) tensors on the device,
+    float64 for the global vectors, the cycle precision for level vectors."""
 
     def __init__(self, dim: int, n: Sequence[int], h: float, omega: float, shift: float,
                  abl_cells: Sequence[int], lam, mu, rho, gamma=None, abl_max: float = 1.0,
@@ -164,16 +208,19 @@ class Solver:
             for l, w in enumerate(damping[:EHH_MAX_LEVELS]):
                 o.damping[l] = float(w)
         self.problem, self.options = p, o
+        self.levels = int(levels)
         self.dim = dim
         self.precond_bits = precond_bits
-        self._media = [t.contiguous() for t in (lam, mu, rho)] + ([gamma.contiguous()] if gamma is not None else [])
-        for t in self._media:
-            if t.dtype != torch.float64 or not t.is_cuda:
-                raise ValueError("media must be float64 device tensors")
+        ncell = 1
+        for a in range(dim):
+            ncell *= int(nn[a])
+        names = ("lambda", "mu", "rho", "gamma")
+        media = [_host_media(t, ncell, nm) for t, nm in zip((lam, mu, rho, gamma), names) if t is not None]
+        hp = [ctypes.c_void_p(a.ctypes.data) for a in media] + [None] * (4 - len(media))
         h_ = ctypes.c_void_p()
-        _check(lib().ehh_setup_operator(ctypes.byref(p), _ptr(self._media[0]), _ptr(self._media[1]),
-                                        _ptr(self._media[2]), _ptr(gamma) if gamma is not None else None,
+        _check(lib().ehh_setup_operator(ctypes.byref(p), hp[0], hp[1], hp[2], hp[3],
                                         ctypes.byref(o), _stream(stream), ctypes.byref(h_)))
+        del media
         self.handle = h_
         counts = (ctypes.c_int64 * 4)()
         stride = ctypes.c_int64()
@@ -214,18 +261,44 @@ class Solver:
         _check(lib().ehh_level_info(self.handle, sub, level, n, counts, ctypes.byref(stride)))
         return dict(n=list(n), counts=list(counts), N=sum(counts), stride=stride.value)
 
+    # ------------------------------------------------------------- argument checks
+    def _cycle_dtype(self):
+        import torch
+        return torch.float32 if self.precond_bits == 32 else torch.float64
+
+    def _global(self, outputs=(), **vecs):
+        """Validate global FP64 vectors (nrhs, 2N) with a common nrhs."""
+        import torch
+        first = next(t for t in vecs.values() if t is not None)
+        if first.dim() != 2 or first.shape[0] < 1:
+            raise ValueError("vectors must be 2-D tensors (nrhs, 2N) with nrhs >= 1")
+        _check_vectors(list(vecs.items()), torch.float64, first.shape[0], self.stride, outputs)
+        return first.shape[0]
+
+    def _level(self, sub, level, outputs=(), **vecs):
+        """Validate level vectors (nrhs, 2 N_level) in the cycle precision."""
+        stride = self.level_info(sub, level)["stride"]
+        first = next(t for t in vecs.values() if t is not None)
+        if first.dim() != 2 or first.shape[0] < 1:
+            raise ValueError("vectors must be 2-D tensors (nrhs, 2N) with nrhs >= 1")
+        _check_vectors(list(vecs.items()), self._cycle_dtype(), first.shape[0], stride, outputs)
+        return first.shape[0]
+
     # ------------------------------------------------------------- calls
     def apply(self, x, y, shifted=False, stream=None):
-        _check(lib().ehh_apply(self.handle, int(shifted), _ptr(x), _ptr(y), x.shape[0], _stream(stream)))
+        nrhs = self._global(outputs=("y",), x=x, y=y)
+        _check(lib().ehh_apply(self.handle, int(shifted), _ptr(x), _ptr(y), nrhs, _stream(stream)))
 
     def vcycle(self, r, e, sub=0, stream=None):
-        _check(lib().ehh_vcycle(self.handle, sub, _ptr(r), _ptr(e), r.shape[0], _stream(stream)))
+        nrhs = self._level(sub, 0, outputs=("e",), r=r, e=e)
+        _check(lib().ehh_vcycle(self.handle, sub, _ptr(r), _ptr(e), nrhs, _stream(stream)))
 
     def precondition(self, v, z, stream=None):
-        _check(lib().ehh_precondition(self.handle, _ptr(v), _ptr(z), v.shape[0], _stream(stream)))
+        nrhs = self._global(outputs=("z",), v=v, z=z)
+        _check(lib().ehh_precondition(self.handle, _ptr(v), _ptr(z), nrhs, _stream(stream)))
 
     def solve(self, b, x, tol=1e-6, maxit=500, stream=None, raise_on_fail=False):
-        nrhs = b.shape[0]
+        nrhs = self._global(outputs=("x",), b=b, x=x)
         stats = (ehh_stats_t * nrhs)()
         st = lib().ehh_solve(self.handle, _ptr(b), _ptr(x), nrhs, float(tol), int(maxit), stats,
                              _stream(stream))
@@ -234,7 +307,7 @@ class Solver:
                          rel_res_true=s.rel_res_true, conv_factor=s.conv_factor) for s in stats]
 
     def solve_adjoint(self, g, y, tol=1e-6, maxit=500, stream=None, raise_on_fail=False):
-        nrhs = g.shape[0]
+        nrhs = self._global(outputs=("y",), g=g, y=y)
         stats = (ehh_stats_t * nrhs)()
         st = lib().ehh_solve_adjoint(self.handle, _ptr(g), _ptr(y), nrhs, float(tol), int(maxit), stats,
                                      _stream(stream))
@@ -243,37 +316,58 @@ class Solver:
                          rel_res_true=s.rel_res_true, conv_factor=s.conv_factor) for s in stats]
 
     def media_gradient(self, y, x, grad_lambda, grad_mu, grad_rho, accumulate=False, stream=None):
-        _check(lib().ehh_media_gradient(self.handle, _ptr(y), _ptr(x), x.shape[0], _ptr(grad_lambda),
+        import torch
+        nrhs = self._global(y=y, x=x)
+        ncell = self.counts[3]
+        for nm, t in (("grad_lambda", grad_lambda), ("grad_mu", grad_mu), ("grad_rho", grad_rho)):
+            if not getattr(t, "is_cuda", False) or not t.is_contiguous() or t.dtype != torch.float64 \
+                    or t.numel() != ncell:
+                raise ValueError(f"{nm} must be a contiguous float64 device tensor of {ncell} cells")
+        _check_vectors([("gl", grad_lambda.view(1, -1)), ("gm", grad_mu.view(1, -1)),
+                        ("gr", grad_rho.view(1, -1))], torch.float64, 1, ncell, ("gl", "gm", "gr"))
+        for g in (grad_lambda, grad_mu, grad_rho):
+            for v in (y, x):
+                if _overlap(g, v):
+                    raise ValueError("gradient outputs must not overlap the fields")
+        _check(lib().ehh_media_gradient(self.handle, _ptr(y), _ptr(x), nrhs, _ptr(grad_lambda),
                                         _ptr(grad_mu), _ptr(grad_rho), int(bool(accumulate)), _stream(stream)))
 
     def level_apply(self, sub, level, x, y, stream=None):
-        _check(lib().ehh_level_apply(self.handle, sub, level, _ptr(x), _ptr(y), x.shape[0], _stream(stream)))
+        nrhs = self._level(sub, level, outputs=("y",), x=x, y=y)
+        _check(lib().ehh_level_apply(self.handle, sub, level, _ptr(x), _ptr(y), nrhs, _stream(stream)))
 
     def level_relax(self, sub, level, colour, b, e_in, e_out, stream=None):
+        nrhs = self._level(sub, level, outputs=("e_out",), b=b, e_in=e_in, e_out=e_out)
         _check(lib().ehh_level_relax(self.handle, sub, level, colour, _ptr(b), _ptr(e_in), _ptr(e_out),
-                                     b.shape[0], _stream(stream)))
+                                     nrhs, _stream(stream)))
 
     def level_restrict(self, sub, level, b, e, rc, stream=None):
-        _check(lib().ehh_level_restrict(self.handle, sub, level, _ptr(b), _ptr(e), _ptr(rc), b.shape[0],
+        nrhs = self._level(sub, level, b=b, e=e)
+        self._level(sub, level + 1, rc=rc) if level + 1 < self.levels else None
+        if rc.shape[0] != nrhs:
+            raise ValueError("rc must have as many right-hand sides as b")
+        _check(lib().ehh_level_restrict(self.handle, sub, level, _ptr(b), _ptr(e), _ptr(rc), nrhs,
                                         _stream(stream)))
 
     def level_prolong(self, sub, level, ec, e, stream=None):
-        _check(lib().ehh_level_prolong(self.handle, sub, level, _ptr(ec), _ptr(e), ec.shape[0],
-                                       _stream(stream)))
+        nrhs = self._level(sub, level, e=e)
+        self._level(sub, level + 1, ec=ec) if level + 1 < self.levels else None
+        if ec.shape[0] != nrhs:
+            raise ValueError("ec must have as many right-hand sides as e")
+        _check(lib().ehh_level_prolong(self.handle, sub, level, _ptr(ec), _ptr(e), nrhs, _stream(stream)))
 
     def coarse_solve(self, sub, r, e, stream=None):
-        _check(lib().ehh_coarse_solve(self.handle, sub, _ptr(r), _ptr(e), r.shape[0], _stream(stream)))
+        nrhs = self._level(sub, self.levels - 1, outputs=("e",), r=r, e=e)
+        _check(lib().ehh_coarse_solve(self.handle, sub, _ptr(r), _ptr(e), nrhs, _stream(stream)))
 
 
-def solver_for_workload(w, device="cuda", **overrides):
-    """Solver for a workloads.Workload (media uploaded as float64 device tensors)."""
-    import torch
+def solver_for_workload(w, **overrides):
+    """Solver for a workloads.Workload (its host media are copied at setup)."""
     m = w.media()
     kw = dict(levels=w.levels, cycle=w.cycle, cycle_level=w.cycle_level, nu1=w.nu1, nu2=w.nu2, vanka=w.vanka,
               precond_bits=w.precond_bits, restart=w.restart, dd_parts=w.dd_parts,
               dd_overlap=w.dd_overlap, dd_pad=w.dd_pad, dd_colors=w.dd_colors, damping=w.damping,
               abl_max=w.abl_max, atten0=w.atten0, coarse_bits=getattr(w, "coarse_bits", 32))
     kw.update(overrides)
-    t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=device).contiguous()
     return Solver(w.dim, w.n, w.h, w.omega, kw.pop("shift", w.shift), w.abl_cells,
-                  t(m["lam"]), t(m["mu"]), t(m["rho"]), **kw)
+                  m["lam"], m["mu"], m["rho"], **kw)

@@ -80,3 +80,15 @@ def rel_err(a, b):
 def rhs_matrix(w):
     n = w.n
     return np.stack([disc.point_source_vector(n, [s]) for s in w.sources()])
+
+
+def component_errors(n, got, ref):
+    """max |got - ref| / max |ref| within each component block u_0, u_1, (u_2), p
+    of a vector of grid n (an error confined to one block, or to the small
+    entries of the absorbing layer, is not hidden by the others)."""
+    off = disc.offsets(n)
+    out = []
+    for k in range(len(off) - 1):
+        a, b = got[off[k]:off[k + 1]], ref[off[k]:off[k + 1]]
+        out.append(float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)))
+    return out

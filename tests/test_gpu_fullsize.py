@@ -1,15 +1,19 @@
 """Parity at the benchmark sizes, in the configuration bench.py times.
 
-c2 and c3 (512^2): one whole preconditioner cycle is compared element by element
-with the oracle's cycle, and a solve's true residual is recomputed by the oracle.
-c4 (128^3, 8 padded subdomains): the oracle's hierarchy is too large for a CPU
-test, so the solve is checked through properties that hold at any size: the
-residual recomputed by the oracle's sparse operator and the mirror of the
-library's own residual report."""
+c2 and c3 (512^2): one whole preconditioner cycle is compared with the oracle's
+cycle (every one of c3's 32 sources, norm-wise and per component), and solves at
+tol 1e-10 are compared with the oracle's direct solution (every source).
+c4 (128^3, 8 padded 72^3 subdomains): the cycle of one subdomain on all 16
+sources is compared with the oracle's cycle of that subdomain; a direct
+factorisation of the whole 128^3 operator is out of reach on the host, so the
+full solve is checked through its residual recomputed by the oracle's sparse
+operator.  (The c4 solver configuration is compared whole with the oracle's DD
+preconditioner at 32^3 and with its direct solution at 16^3.)"""
 import numpy as np
 import pytest
 
-from _helpers import say, workload, oracle_problem, oracle_hierarchy, rand_cvec, to_dev, from_dev, rhs_matrix
+from _helpers import (say, workload, oracle_problem, oracle_hierarchy, rand_cvec, to_dev, from_dev, rhs_matrix,
+                      component_errors)
 
 pytestmark = pytest.mark.gpu
 
@@ -42,12 +46,16 @@ def test_c2_cycle_matches_oracle(c2_oracle):
     got = from_dev(e)[0]
     ref = H.cycle(r[0])
     assert np.linalg.norm(got - ref) <= 1e-10 * np.linalg.norm(ref)
+    ec = component_errors(w.n, got, ref)
+    say(f"  per-component error {['%.1e' % v for v in ec]}")
+    assert max(ec) <= 1e-9
     S.close()
 
 
 def test_c3_cycle_matches_oracle(c2_oracle):
     """The complex64 cycle of c3 (same medium and hierarchy as c2) on 32
-    right-hand sides; two are compared with the FP64 oracle cycle."""
+    right-hand sides, every one compared with the FP64 oracle cycle, norm-wise
+    and per component."""
     import torch
     w2, pb, H = c2_oracle
     w = workload("c3_hetero512_batch32_fp32")
@@ -58,10 +66,106 @@ def test_c3_cycle_matches_oracle(c2_oracle):
     S.vcycle(to_dev(r, torch.float32), e)
     torch.cuda.synchronize()
     got = from_dev(e)
-    for q in (0, 31):
+    worst = [0.0, 0.0]
+    for q in range(32):
         ref = H.cycle(r[q])
-        assert np.linalg.norm(got[q] - ref) <= 2e-5 * np.linalg.norm(ref)
+        e2 = np.linalg.norm(got[q] - ref) / np.linalg.norm(ref)
+        ec = max(component_errors(w.n, got[q], ref))
+        worst = [max(worst[0], e2), max(worst[1], ec)]
+        assert e2 <= 2e-5 and ec <= 2e-4, (q, e2, ec)
+    say(f"  worst norm-wise {worst[0]:.2e}, worst per component {worst[1]:.2e}")
     S.close()
+
+
+@pytest.fixture(scope="module")
+def c2_direct(c2_oracle):
+    """The oracle's direct solver of the 512^2 operator (c2 and c3 share it)."""
+    from oracle import direct
+    w, pb, H = c2_oracle
+    say("[512^2 operator: oracle direct factorisation]")
+    return direct.factorize(pb)
+
+
+@pytest.mark.timeout(900)
+def test_c2_solve_matches_direct_solution(c2_oracle, c2_direct):
+    """c2 (FP64 cycle, one source) solved to 1e-10: within 1e-6 of the oracle's
+    direct solution."""
+    import torch
+    w, pb, H = c2_oracle
+    say("[c2 full-size solve at 1e-10 vs direct]")
+    B = rhs_matrix(w)
+    S = _solver(w)
+    x = torch.zeros_like(to_dev(B))
+    st, stats = S.solve(to_dev(B), x, tol=1e-10, maxit=1500)
+    torch.cuda.synchronize()
+    S.close()
+    assert st == 0, stats
+    xd = c2_direct.solve(B[0])
+    err = np.linalg.norm(from_dev(x)[0] - xd) / np.linalg.norm(xd)
+    say(f"  iters {stats[0]['iters']} residual {stats[0]['rel_res_true']:.2e} error vs direct {err:.2e}")
+    assert stats[0]["rel_res_true"] <= 1e-10 and err <= 1e-6
+
+
+@pytest.mark.timeout(900)
+def test_c3_solve_matches_direct_solution(c2_oracle, c2_direct):
+    """c3 (complex64 cycle in FP64 FGMRES, 32 sources) solved to 1e-10: every
+    source within 1e-6 of the oracle's direct solution."""
+    import torch
+    w = workload("c3_hetero512_batch32_fp32")
+    say("[c3 full-size solve at 1e-10 vs direct, 32 sources]")
+    B = rhs_matrix(w)
+    S = _solver(w)
+    x = torch.zeros_like(to_dev(B))
+    st, stats = S.solve(to_dev(B), x, tol=1e-10, maxit=1500)
+    torch.cuda.synchronize()
+    S.close()
+    assert st == 0, [s_["rel_res_true"] for s_ in stats]
+    got = from_dev(x)
+    worst = 0.0
+    for r in range(32):
+        xd = c2_direct.solve(B[r])
+        err = np.linalg.norm(got[r] - xd) / np.linalg.norm(xd)
+        worst = max(worst, err)
+        assert stats[r]["rel_res_true"] <= 1e-10 and err <= 1e-6, (r, err)
+    say(f"  iterations {min(s_['iters'] for s_ in stats)}-{max(s_['iters'] for s_ in stats)}, "
+        f"worst error vs direct {worst:.2e}")
+
+
+@pytest.mark.timeout(900)
+def test_c4_subdomain_cycle_matches_oracle():
+    """c4 at full size: the cycle of one padded 72^3 subdomain (4 levels, 36^3 and
+    18^3 Galerkin levels, 9^3 coarsest) on all 16 sources at once, the launch
+    shapes the bench runs, compared source by source with the oracle's cycle of
+    the same subdomain operator."""
+    import torch
+    from oracle import dd as ddm, multigrid as mg
+    w = workload("c4_layered128_dd8_batch16_fp32")
+    say("[c4 full size: oracle hierarchy of subdomain 0]")
+    pb = oracle_problem(w)
+    subs = ddm.make_subdomains(w.n, w.dd_parts[:3], w.dd_overlap, w.dd_pad)
+    sub = subs[0]
+    assert sub.nloc == (72, 72, 72)
+    H = mg.Hierarchy(ddm.local_operator(pb, sub, w.abl_max), sub.nloc, w.levels, list(w.damping),
+                     economic=(w.vanka == 0), cycle=w.cycle)
+    say("[c4 subdomain 0 cycle, 16 sources]")
+    S = _solver(w)
+    assert S.subdomain_info(0)["n"] == [72, 72, 72]
+    N = H.A[0].shape[0]
+    assert S.level_info(0, 0)["N"] == N
+    r = rand_cvec(N, 16, 72)
+    e = torch.zeros((16, 2 * N), dtype=torch.float32, device="cuda")
+    S.vcycle(to_dev(r, torch.float32), e, sub=0)
+    torch.cuda.synchronize()
+    S.close()
+    got = from_dev(e)
+    worst = [0.0, 0.0]
+    for q in range(16):
+        ref = H.cycle(r[q])
+        e2 = np.linalg.norm(got[q] - ref) / np.linalg.norm(ref)
+        ec = max(component_errors(sub.nloc, got[q], ref))
+        worst = [max(worst[0], e2), max(worst[1], ec)]
+        assert e2 <= 2e-5 and ec <= 2e-4, (q, e2, ec)
+    say(f"  worst norm-wise {worst[0]:.2e}, worst per component {worst[1]:.2e}")
 
 
 def test_c2_solve_true_residual(c2_oracle):

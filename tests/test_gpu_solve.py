@@ -6,7 +6,7 @@ import pytest
 import scipy.sparse.linalg as spla
 
 from _helpers import (say, workload, small_hetero, oracle_problem, oracle_hierarchy, oracle_dd,
-                      rand_cvec, to_dev, from_dev, rel_err, rhs_matrix)
+                      rand_cvec, to_dev, from_dev, rel_err, rhs_matrix, component_errors)
 from oracle import krylov
 
 pytestmark = pytest.mark.gpu
@@ -90,6 +90,77 @@ def test_dd_precondition_matches_oracle(bits, colors):
     for r in range(2):
         ref = P.apply(v[r])
         assert np.linalg.norm(got[r] - ref) <= tol * np.linalg.norm(ref)
+        assert max(component_errors(w.n, got[r], ref)) <= (1e-10 if bits == 64 else 2e-4)
+    S.close()
+
+
+@pytest.fixture(scope="module")
+def c4m_oracle():
+    w = workload("c4m_layered32_dd8_batch16_fp32")
+    say("[c4 configuration at 32^3: oracle DD preconditioner]")
+    pb = oracle_problem(w)
+    return w, pb, oracle_dd(w, pb)
+
+
+def test_c4_configuration_precondition_matches_oracle(c4m_oracle):
+    """The bench's c4 solver configuration at 32^3: complex64 cycle on 24^3 padded
+    subdomains (padding 6, 4 levels: the 12^3 and 6^3 Galerkin levels run the
+    stored-row half-sweep in two full groups of 8 sources), Algorithm 2 with its
+    local residual gather, shift 0.6, all 16 sources compared with the FP64
+    oracle, norm-wise and per component."""
+    import torch
+    w, pb, P = c4m_oracle
+    say("[c4 configuration precondition, 16 sources]")
+    S = _solver(w)
+    assert S.num_subdomains() == 8 and S.subdomain_info(0)["n"] == [24, 24, 24]
+    assert S.level_info(0, 1)["n"] == [12, 12, 12]
+    v = rand_cvec(pb.size, 16, 62)
+    z = torch.zeros_like(to_dev(v))
+    S.precondition(to_dev(v), z)
+    torch.cuda.synchronize()
+    got = from_dev(z)
+    worst = [0.0, 0.0]
+    for r in range(16):
+        ref = P.apply(v[r])
+        e2 = np.linalg.norm(got[r] - ref) / np.linalg.norm(ref)
+        ec = max(component_errors(w.n, got[r], ref))
+        worst = [max(worst[0], e2), max(worst[1], ec)]
+        assert e2 <= 2e-5 and ec <= 2e-4, (r, e2, ec)
+    say(f"  worst norm-wise {worst[0]:.2e}, worst per component {worst[1]:.2e}")
+    S.close()
+
+
+def test_c4_configuration_solve_matches_direct_solution():
+    """c4's solver settings (2 x 2 x 2 subdomains, padding 6, 4 levels, Algorithm 2,
+    shift 0.6, complex64 cycle) on a 16^3 grid, whose direct factorisation takes
+    seconds: 16 random right-hand sides solved to 1e-10, every solution within
+    1e-6 of the oracle's direct solution."""
+    import torch
+    from oracle import direct
+    c4 = workload("c4m_layered32_dd8_batch16_fp32")
+    w = small_hetero((16, 16, 16), "c4cfg16", levels=4, damping=c4.damping, shift=c4.shift,
+                     precond_bits=32, dd_parts=(2, 2, 2), dd_overlap=4, dd_pad=6, dd_colors=0,
+                     abl_cells=(4, 4, 4))
+    say("[c4 configuration at 16^3: solve vs direct, 16 sources]")
+    pb = oracle_problem(w)
+    lu = direct.factorize(pb)
+    B = rand_cvec(pb.size, 16, 63)
+    S = _solver(w)
+    assert S.subdomain_info(0)["n"] == [16, 16, 16]
+    x = torch.zeros_like(to_dev(B))
+    st, stats = S.solve(to_dev(B), x, tol=1e-10, maxit=1500)
+    torch.cuda.synchronize()
+    assert st == 0, stats
+    got = from_dev(x)
+    worst = 0.0
+    for r in range(16):
+        xd = lu.solve(B[r])
+        err = np.linalg.norm(got[r] - xd) / np.linalg.norm(xd)
+        worst = max(worst, err)
+        assert stats[r]["rel_res_true"] <= 1e-10
+        assert err <= 1e-6, (r, err)
+    say(f"  iterations {min(s_['iters'] for s_ in stats)}-{max(s_['iters'] for s_ in stats)}, "
+        f"worst error vs direct {worst:.2e}")
     S.close()
 
 
@@ -255,3 +326,70 @@ def test_fp16_coarse_rows_3d():
     with pytest.raises(ehh.EHHError) as ei:
         _solver(w, precond_bits=64, coarse_bits=16)
     assert ei.value.status == ehh.EHH_ERR_INVALID
+
+
+_OOM_SCRIPT = r'''
+import os, sys
+import numpy as np
+import torch
+sys.path[:0] = [sys.argv[1], os.path.join(sys.argv[1], "tests")]
+from paper_1806_11277_amd import ehh
+from _helpers import workload, rhs_matrix, to_dev, from_dev
+w = workload("c2s_hetero128_fp64", levels=3, damping=(0.75, 0.5))
+B1 = rhs_matrix(w)
+B2 = np.concatenate([B1, 1j * B1])
+def solve(S, B):
+    x = torch.zeros_like(to_dev(B))
+    st, stats = S.solve(to_dev(B), x, tol=1e-8, maxit=300)
+    torch.cuda.synchronize()
+    return st, from_dev(x)
+S = ehh.solver_for_workload(w)
+st, ref1 = solve(S, B1)
+assert st == 0
+S.close()
+counts = {"setup": 0, "solve": 0}
+for k in range(0, 400):
+    os.environ["EHH_FAIL_ALLOC_AFTER"] = str(k)
+    try:
+        S = ehh.solver_for_workload(w)
+    except ehh.EHHError as e:
+        assert e.status == ehh.EHH_ERR_OOM, e
+        counts["setup"] += 1
+        continue
+    try:
+        st, _ = solve(S, B2)
+        injected = False
+    except ehh.EHHError as e:
+        assert e.status == ehh.EHH_ERR_OOM, e
+        injected = True
+        counts["solve"] += 1
+    # a smaller follow-up solve on the same handle allocates again and matches
+    st, got = solve(S, B1)
+    assert st == 0 and np.array_equal(got, ref1), (k, st)
+    S.close()
+    if not injected:
+        break
+os.environ.pop("EHH_FAIL_ALLOC_AFTER")
+print("injected failures", counts, "last point", k, flush=True)
+assert counts["setup"] > 5 and counts["solve"] > 5 and k < 399
+'''
+
+
+def test_injected_allocation_failures_leave_a_usable_library():
+    """EHH_FAIL_ALLOC_AFTER=k fails the device allocation that follows k
+    successful ones.  Swept over every allocation point of a setup and of a
+    two-source solve (fresh process): each failure reports EHH_ERR_OOM, a failed
+    setup returns no handle, and after a failed solve a one-source solve on the
+    same handle allocates its workspaces again and gives the same bits as a
+    solve that never failed."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    say("[injected allocation failures, fresh process]")
+    env = dict(os.environ)
+    env.pop("EHH_FAIL_ALLOC_AFTER", None)
+    r = subprocess.run([sys.executable, "-c", _OOM_SCRIPT, root], env=env, capture_output=True, text=True,
+                       timeout=110)
+    say(r.stdout[-2000:], r.stderr[-2000:])
+    assert r.returncode == 0

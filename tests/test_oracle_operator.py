@@ -264,6 +264,40 @@ def test_dense_bruteforce_matches_sparse_lu(n):
     assert np.linalg.norm(x_dense - x_lu) <= 1e-12 * np.linalg.norm(x_dense) * 10
 
 
+@pytest.mark.parametrize("n", [(12, 10), (16, 16), (6, 4, 6)])
+def test_nested_dissection_direct_solve_matches_dense_bruteforce(n):
+    """The oracle's direct solver (SuperLU on the nested-dissection order of the
+    staggered unknowns) gives the dense brute-force solution, and its order is
+    a permutation of every unknown."""
+    from oracle import direct
+    lam, mu, rho, gam = _hetero(n, 17)
+    A = disc.assemble(n, 1.0, 0.9, lam, mu, rho, gam, 0.0)
+    perm = direct.nested_dissection(n, leaf=8)
+    assert np.array_equal(np.sort(perm), np.arange(A.shape[0]))
+    rng = np.random.default_rng(18)
+    b = rng.standard_normal(A.shape[0]) + 1j * rng.standard_normal(A.shape[0])
+    x_dense = np.linalg.solve(A.toarray(), b)
+    x = direct.DirectSolver(A, n).solve(b)
+    assert np.linalg.norm(x - x_dense) <= 1e-11 * np.linalg.norm(x_dense)
+
+
+@pytest.mark.parametrize("n", [(16, 12), (8, 6, 10)])
+def test_nested_dissection_band_separates(n):
+    """The separator reading: no nonzero of A couples an unknown below the band
+    [c - 1/2, c] of the first cut with one above it."""
+    from oracle import direct
+    lam, mu, rho, gam = _hetero(n, 19)
+    A = sp.coo_matrix(disc.assemble(n, 1.0, 0.9, lam, mu, rho, gam, 0.3))
+    X = direct.unknown_coordinates(n)
+    a = int(np.argmax(n))
+    c = np.round(np.median(X[:, a]))
+    lo, hi = X[:, a] < c - 0.5, X[:, a] > c
+    nz = np.abs(A.data) > 0
+    assert lo.sum() > 0 and hi.sum() > 0
+    assert not np.any(nz & lo[A.row] & hi[A.col])
+    assert not np.any(nz & hi[A.row] & lo[A.col])
+
+
 def test_discrete_manufactured_solution():
     n = (24, 20)
     lam, mu, rho, gam = _hetero(n, 9)

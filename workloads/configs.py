@@ -185,6 +185,16 @@ _add(Workload(
     precond_bits=32, dd_parts=(2, 2, 2), dd_overlap=4, dd_pad=2, dd_colors=1,
     sources_fn=_src_lattice(2, 16, 8, 5, seed=7)))
 
+_add(Workload(
+    name="c4m_layered32_dd8_batch16_fp32",
+    description="c4 at 32^3 in c4's solver configuration: 2x2x2 subdomains (overlap 4, padding 6, "
+                "multicolour schedule), 4 levels per 24^3 subdomain, shift 0.6, 16 sources, complex64 cycle "
+                "(parity size of the bench configuration)",
+    dim=3, n=(32, 32, 32), h=10.0, media_fn=lambda: M.layered_3d_media((32, 32, 32)),
+    ppw=8.0, abl_cells=(6, 6, 6), shift=0.6, levels=4, damping=(0.5, 0.5, 0.2),
+    precond_bits=32, dd_parts=(2, 2, 2), dd_overlap=4, dd_pad=6, dd_colors=0,
+    sources_fn=_src_lattice(4, 8, 4, 5, seed=7)))
+
 
 def _rec_line(count: int, spacing: int, first: int, depth: int):
     def fn(w: Workload):
