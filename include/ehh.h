@@ -39,7 +39,6 @@
  *   nondimensional w.
  *
  * Memory and streams
- *   Pointers marked (host) are ordinary host memory, read during the call.
  *   Pointers marked (device) are HIP device pointers; the caller owns them and
  *   keeps them alive until the work on `stream` (a hipStream_t, NULL = default
  *   stream) has completed.  The handle owns everything it allocates.  A handle
@@ -125,16 +124,20 @@ void ehh_default_options(ehh_options_t* opt);
  * and the inverse of every coarsest operator) and, with domain decomposition,
  * one padded subdomain hierarchy per subdomain (section 2.1 for the
  * coefficients, eq. (9) for the hierarchy, section 4 for the subdomains).
- *   lambda, mu, rho: (host) FP64 cell arrays [Pa, Pa, kg/m^3], x fastest, copied
- *                    to the device during the call (the handle keeps only its
- *                    own nondimensional coefficients); rho > 0, mu >= 0,
- *                    lambda + mu > 0.
- *   gamma:           (host) FP64 physical attenuation [1/s] per cell, or NULL.
+ *   lambda, mu, rho: FP64 cell arrays [Pa, Pa, kg/m^3], x fastest; rho > 0,
+ *                    mu >= 0, lambda + mu > 0.  Host arrays are copied to the
+ *                    device during the call; arrays in device memory (as the
+ *                    runtime reports the pointer) are read in place, e.g. a
+ *                    model updated on the device between solves.  Either way
+ *                    the handle keeps only its own nondimensional coefficients
+ *                    and the caller may reuse the arrays once the call returns.
+ *   gamma:           FP64 physical attenuation [1/s] per cell (host or device,
+ *                    as above), or NULL.
  *   stream:          work is enqueued on it; the call synchronises it before
  *                    returning.
  *   out:             receives the handle (set only on EHH_OK).
- * Errors: EHH_ERR_INVALID (sizes, levels, options, a media pointer that is
- * device memory), EHH_ERR_BREAKDOWN (non-finite or non-physical media),
+ * Errors: EHH_ERR_INVALID (sizes, levels, options, null media), EHH_ERR_BREAKDOWN
+ * (non-finite or non-physical media),
  * EHH_ERR_OOM (nothing is kept: a later setup starts afresh), EHH_ERR_HIP. */
 int32_t ehh_setup_operator(const ehh_problem_t* problem, const double* lambda,
                            const double* mu, const double* rho, const double* gamma,

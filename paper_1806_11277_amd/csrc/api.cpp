@@ -821,8 +821,8 @@ int32_t build_hierarchy(ehh_ctx* c, Sub& S, const double* lam, const double* mu,
     return EHH_OK;
 }
 
-// A host array: rejects pointers the runtime knows as device memory (the media
-// of ehh_setup_operator are host arrays, copied at setup).
+// Memory the runtime knows as device memory (read in place by the setup
+// kernels); anything else is host memory and is copied first.
 bool is_device_pointer(const void* p) {
     hipPointerAttribute_t a{};
     const hipError_t e = hipPointerGetAttributes(&a, p);
@@ -836,22 +836,30 @@ int32_t setup_impl(ehh_ctx* c, const double* lam_h, const double* mu_h, const do
     c->dim = P.dim;
     int n[3] = {P.n[0], P.n[1], P.dim == 3 ? P.n[2] : 1};
     c->gg = make_geo(P.dim, n);
-    // the host media, copied to the device for the setup kernels and released at
-    // the end of the setup (the operator keeps its own nondimensional planes)
-    for (const double* hp : {lam_h, mu_h, rho_h, gam_h})
-        if (hp && is_device_pointer(hp)) return fail(EHH_ERR_INVALID, "media must be host arrays");
+    // media in host memory are copied to the device for the setup kernels (the
+    // copies are released at the end of the setup: the operator keeps its own
+    // nondimensional planes); media already in device memory are read in place
     const int64_t ncell0 = c->gg.ncell;
+    const double* src[4] = {lam_h, mu_h, rho_h, gam_h};
+    const double* dev[4] = {nullptr, nullptr, nullptr, nullptr};
+    int nhost = 0;
+    for (int a = 0; a < 4; ++a) {
+        if (!src[a]) continue;
+        if (is_device_pointer(src[a])) dev[a] = src[a];
+        else ++nhost;
+    }
     double* media = nullptr;
-    CHK(c->alloc((void**)&media, sizeof(double) * (gam_h ? 4 : 3) * ncell0));
-    const double* lam = media;
-    const double* mu = media + ncell0;
-    const double* rho = media + 2 * ncell0;
-    const double* gam = gam_h ? media + 3 * ncell0 : nullptr;
-    const size_t mb = sizeof(double) * ncell0;
-    HIPCHK(hipMemcpyAsync((void*)lam, lam_h, mb, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync((void*)mu, mu_h, mb, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync((void*)rho, rho_h, mb, hipMemcpyHostToDevice, s));
-    if (gam_h) HIPCHK(hipMemcpyAsync((void*)gam, gam_h, mb, hipMemcpyHostToDevice, s));
+    if (nhost) CHK(c->alloc((void**)&media, sizeof(double) * nhost * ncell0));
+    for (int a = 0, h = 0; a < 4; ++a) {
+        if (!src[a] || dev[a]) continue;
+        double* d = media + (int64_t)h++ * ncell0;
+        HIPCHK(hipMemcpyAsync(d, src[a], sizeof(double) * ncell0, hipMemcpyHostToDevice, s));
+        dev[a] = d;
+    }
+    const double* lam = dev[0];
+    const double* mu = dev[1];
+    const double* rho = dev[2];
+    const double* gam = dev[3];
     // media means and physical check
     const int nb = media_check_blocks(c->gg.ncell);
     double* part = nullptr;

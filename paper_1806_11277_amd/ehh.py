@@ -130,20 +130,27 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _host_media(a, ncell, name):
-    """A host float64 copy of a media array (numpy or torch, any device), with
-    exactly ncell entries; the library copies it to the device at setup."""
+def _media(a, ncell, name):
+    """(keep-alive object, address) of a media array with exactly ncell float64
+    entries: a float64 device tensor is passed in place (read on the device at
+    setup), anything else (numpy, a CPU tensor) as a contiguous host copy that
+    the library uploads."""
     import numpy as np
     try:
         import torch
         if isinstance(a, torch.Tensor):
+            if a.is_cuda and a.dtype == torch.float64:
+                t = a.detach().contiguous()
+                if t.numel() != ncell:
+                    raise ValueError(f"{name} has {t.numel()} entries, the grid has {ncell} cells")
+                return t, t.data_ptr()
             a = a.detach().to("cpu", torch.float64).numpy()
     except ImportError:  # pragma: no cover
         pass
     out = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
     if out.size != ncell:
         raise ValueError(f"{name} has {out.size} entries, the grid has {ncell} cells")
-    return out
+    return out, out.ctypes.data
 
 
 def _overlap(a, b):
@@ -175,8 +182,8 @@ def _check_vectors(named, dtype, rows, cols, outputs=()):
 
 class Solver:
     """Owns one ehh handle.  Media: float64 arrays shaped like the cell grid (x
-    fastest), numpy or torch; they are handed to the library as host arrays and
-    copied to the device at setup.  Vectors: (nrhs, 2N) tensors on the device,
+    fastest): numpy or CPU tensors (host arrays, uploaded at setup) or float64
+    device tensors (read in place).  Vectors: (nrhs, 2N) tensors on the device,
     float64 for the global vectors, the cycle precision for level vectors."""
 
     def __init__(self, dim: int, n: Sequence[int], h: float, omega: float, shift: float,
@@ -215,8 +222,8 @@ class Solver:
         for a in range(dim):
             ncell *= int(nn[a])
         names = ("lambda", "mu", "rho", "gamma")
-        media = [_host_media(t, ncell, nm) for t, nm in zip((lam, mu, rho, gamma), names) if t is not None]
-        hp = [ctypes.c_void_p(a.ctypes.data) for a in media] + [None] * (4 - len(media))
+        media = [_media(t, ncell, nm) for t, nm in zip((lam, mu, rho, gamma), names) if t is not None]
+        hp = [ctypes.c_void_p(addr) for _, addr in media] + [None] * (4 - len(media))
         h_ = ctypes.c_void_p()
         _check(lib().ehh_setup_operator(ctypes.byref(p), hp[0], hp[1], hp[2], hp[3],
                                         ctypes.byref(o), _stream(stream), ctypes.byref(h_)))

@@ -35,11 +35,11 @@ class _FakeDeviceTensor:
 
 
 def test_host_media_must_match_the_grid():
-    a = ehh._host_media(np.ones((4, 6)), 24, "mu")
-    assert a.dtype == np.float64 and a.flags.c_contiguous and a.size == 24
-    assert ehh._host_media(torch.ones(24, dtype=torch.float32), 24, "rho").dtype == np.float64
+    a, addr = ehh._media(np.ones((4, 6)), 24, "mu")
+    assert a.dtype == np.float64 and a.flags.c_contiguous and a.size == 24 and addr == a.ctypes.data
+    assert ehh._media(torch.ones(24, dtype=torch.float32), 24, "rho")[0].dtype == np.float64
     with pytest.raises(ValueError, match="mu has 20 entries"):
-        ehh._host_media(np.ones(20), 24, "mu")
+        ehh._media(np.ones(20), 24, "mu")
 
 
 def test_vectors_need_the_right_dtype_shape_and_device():

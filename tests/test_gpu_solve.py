@@ -393,3 +393,26 @@ def test_injected_allocation_failures_leave_a_usable_library():
                        timeout=110)
     say(r.stdout[-2000:], r.stderr[-2000:])
     assert r.returncode == 0
+
+
+def test_host_and_device_media_build_the_same_operator():
+    """Media handed over as host arrays (copied at setup) and as device arrays
+    (read in place) give bit-identical solves."""
+    import torch
+    from paper_1806_11277_amd import ehh
+    w = workload("c2s_hetero128_fp64")
+    say("[host vs device media]")
+    m = w.media()
+    B = rhs_matrix(w)
+    out = []
+    for dev in (False, True):
+        conv = (lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda")) if dev else (lambda a: a)
+        S = ehh.Solver(w.dim, w.n, w.h, w.omega, w.shift, w.abl_cells, conv(m["lam"]), conv(m["mu"]),
+                       conv(m["rho"]), levels=w.levels, damping=w.damping, atten0=w.atten0)
+        x = torch.zeros_like(to_dev(B))
+        st, _ = S.solve(to_dev(B), x, tol=1e-8, maxit=400)
+        torch.cuda.synchronize()
+        assert st == 0
+        out.append(x.cpu().numpy())
+        S.close()
+    assert np.array_equal(out[0], out[1])
