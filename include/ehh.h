@@ -246,6 +246,20 @@ int32_t ehh_level_prolong(ehh_handle_t h, int32_t sub, int32_t level, const void
 int32_t ehh_coarse_solve(ehh_handle_t h, int32_t sub, const void* r, void* e,
                          int32_t nrhs, void* stream);
 
+/* The coarsest solve of ehh_coarse_solve, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  It allocates nothing: the column-segment partial sums
+ * of its kernels live in a library-wide device array of 2^22 doubles (32 MiB)
+ * per device, which each device that the library runs on holds until the
+ * process ends.  Every call rewrites the partial sums it reads, so nothing
+ * carries over between calls; calls that overlap in time on one device share
+ * that array and race.  The handle's device must be current.  r, e: (device)
+ * as for ehh_coarse_solve.  Returns EHH_ERR_UNSUPPORTED (nothing launched)
+ * when the coarsest size and nrhs need more partial sums than the array holds
+ * (e.g. 3,008 unknowns: up to 32 right-hand sides fit). */
+int32_t ehh_coarse_solve_noalloc(ehh_handle_t h, int32_t sub, const void* r, void* e,
+                                 int32_t nrhs, void* stream);
+
 const char* ehh_last_error(void);
 
 #ifdef __cplusplus

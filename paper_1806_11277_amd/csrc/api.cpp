@@ -196,6 +196,7 @@ struct Sub {
 struct ehh_ctx {
     ehh_problem_t prob{};
     ehh_options_t opt{};
+    int device = 0;             // the device current at setup, which holds every buffer
     int dim = 2;
     Geo gg{};
     double mu_bar = 1, rho_bar = 1, omega_nd = 1;
@@ -1058,6 +1059,7 @@ int32_t ehh_setup_operator(const ehh_problem_t* problem, const double* lambda, c
     ehh_ctx* c = new ehh_ctx();
     c->prob = *problem;
     c->opt = *options;
+    (void)hipGetDevice(&c->device);
     if (c->prob.dim == 2) {
         c->prob.n[2] = 1;
         c->prob.abl_cells[2] = 0;
@@ -1069,6 +1071,11 @@ int32_t ehh_setup_operator(const ehh_problem_t* problem, const double* lambda, c
         delete c;
         return st;
     }
+    // the address of this device's scratch array for ehh_coarse_solve_noalloc
+    // (taken once per device; a failure here only disables that entry point,
+    // which then reports it)
+    (void)noalloc_scratch_init(c->device);
+    (void)hipGetLastError();
     *out = c;
     return EHH_OK;
 }
@@ -1449,6 +1456,36 @@ int32_t ehh_coarse_solve(ehh_handle_t h, int32_t sub, const void* r, void* e, in
                                           as_stream(stream)));
     else
         HIPCHK(launch_coarse_apply<double>(S->inv, S->sym, L->g.N, (const double*)r, (double*)e, nrhs, h->coarse_ws,
+                                           as_stream(stream)));
+    return EHH_OK;
+}
+
+int32_t ehh_coarse_solve_noalloc(ehh_handle_t h, int32_t sub, const void* r, void* e, int32_t nrhs, void* stream) {
+    CHK(check_handle(h));
+    if (sub < 0 || sub >= (int)h->subs.size()) return fail(EHH_ERR_INVALID, "subdomain index out of range");
+    if (!r || !e || r == e || nrhs < 1) return fail(EHH_ERR_INVALID, "bad vectors or nrhs");
+    int cur = -1;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != h->device) return fail(EHH_ERR_INVALID, "the handle's device must be current");
+    double* scratch = noalloc_scratch(h->device);
+    if (!scratch) {
+        const hipError_t ie = noalloc_scratch_init(h->device);
+        if (ie != hipSuccess) return fail(EHH_ERR_HIP, std::string("scratch address: ") + hipGetErrorString(ie));
+        scratch = noalloc_scratch(h->device);
+    }
+    const Sub& S = h->subs[sub];
+    const int64_t n = S.lev.back().g.N;
+    const size_t need = coarse_ws_doubles(n, nrhs);
+    if (need > (size_t)kNoallocScratchDoubles)
+        return fail(EHH_ERR_UNSUPPORTED, "ehh_coarse_solve_noalloc: " + std::to_string(n) + " unknowns x " +
+                                             std::to_string(nrhs) + " right-hand sides need " +
+                                             std::to_string(need) + " doubles of scratch; the array holds " +
+                                             std::to_string(kNoallocScratchDoubles));
+    if (h->bits() == 32)
+        HIPCHK(launch_coarse_apply<float>(S.inv, S.sym, n, (const float*)r, (float*)e, nrhs, scratch,
+                                          as_stream(stream)));
+    else
+        HIPCHK(launch_coarse_apply<double>(S.inv, S.sym, n, (const double*)r, (double*)e, nrhs, scratch,
                                            as_stream(stream)));
     return EHH_OK;
 }

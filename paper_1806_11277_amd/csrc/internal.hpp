@@ -113,6 +113,14 @@ hipError_t launch_permute_columns(const double* X, double* out, int64_t n, const
 template <typename T>
 hipError_t launch_coarse_apply(const double* inv, const double* sym, int64_t n, const T* r, T* e, int nrhs,
                                double* ws, hipStream_t s);
+// Scratch array of the coarsest solve that allocates nothing: kNoallocScratchDoubles
+// FP64 values per device (32 MiB).  noalloc_scratch_init takes the address of
+// device dev's copy (dev must be current) once; noalloc_scratch returns it
+// (null before the first init on that device).
+constexpr int64_t kNoallocScratchDoubles = int64_t(1) << 22;
+constexpr int kMaxDevices = 64;
+hipError_t noalloc_scratch_init(int dev);
+double* noalloc_scratch(int dev);
 // Packed lower tiles of the (symmetric) inverse, used by launch_coarse_apply.
 int64_t sym_tiles(int64_t n);
 hipError_t launch_pack_sym(const double* inv, int64_t n, double* sym, hipStream_t s);

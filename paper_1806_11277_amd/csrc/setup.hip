@@ -6,6 +6,8 @@
 
 #include <cstdlib>
 
+#include <mutex>
+
 #include "internal.hpp"
 #include "ops.hpp"
 
@@ -1370,6 +1372,40 @@ hipError_t launch_coarse_apply(const double* inv, const double* sym, int64_t n, 
     if (part) hipLaunchKernelGGL((k_coarse_reduce<T>), nblk(2 * n * nrhs), 256, 0, s, part, ks, n, nrhs, e);
     return hipGetLastError();
 }
+// Scratch of the coarsest solve for callers that cannot allocate
+// (ehh_coarse_solve_noalloc): the column-segment partial sums live in this
+// library-wide array, one copy per device, held until the process ends.  In
+// host code the name stands for a host-side symbol, never a device address:
+// the address of each device's copy comes from hipGetSymbolAddress, taken once
+// per device with that device current, and only that address is used.
+static __device__ __align__(256) double scratch[kNoallocScratchDoubles];
+
+namespace {
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_init(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> l(g_scratch_mutex);
+    if (g_scratch_ptr[dev]) return hipSuccess;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != dev) return hipErrorInvalidDevice;   // the caller makes dev current
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = (double*)p;
+    return hipSuccess;
+}
+
+double* noalloc_scratch(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> l(g_scratch_mutex);
+    return g_scratch_ptr[dev];
+}
+
 template hipError_t launch_coarse_apply<float>(const double*, const double*, int64_t, const float*, float*, int,
                                                double*, hipStream_t);
 template hipError_t launch_coarse_apply<double>(const double*, const double*, int64_t, const double*, double*, int,

@@ -71,6 +71,7 @@ _SIGS = {
     "ehh_level_restrict": (_I, [_P, _I, _I, _P, _P, _P, _I, _P]),
     "ehh_level_prolong": (_I, [_P, _I, _I, _P, _P, _I, _P]),
     "ehh_coarse_solve": (_I, [_P, _I, _P, _P, _I, _P]),
+    "ehh_coarse_solve_noalloc": (_I, [_P, _I, _P, _P, _I, _P]),
     "ehh_last_error": (ctypes.c_char_p, []),
 }
 
@@ -366,6 +367,10 @@ class Solver:
     def coarse_solve(self, sub, r, e, stream=None):
         nrhs = self._level(sub, self.levels - 1, outputs=("e",), r=r, e=e)
         _check(lib().ehh_coarse_solve(self.handle, sub, _ptr(r), _ptr(e), nrhs, _stream(stream)))
+
+    def coarse_solve_noalloc(self, sub, r, e, stream=None):
+        nrhs = self._level(sub, self.levels - 1, outputs=("e",), r=r, e=e)
+        _check(lib().ehh_coarse_solve_noalloc(self.handle, sub, _ptr(r), _ptr(e), nrhs, _stream(stream)))
 
 
 def solver_for_workload(w, **overrides):
