@@ -39,28 +39,6 @@ def rhs_tensor(S, w):
     return torch.as_tensor(B, device="cuda")
 
 
-def level_bytes(info, bits, nrhs, fine, dim, with_e=True, coef_bytes=None):
-    """Algorithmic HBM bytes of one half-sweep launch on a level: b and e_in read,
-    e_out written (every unknown, complex, per right-hand side; without e_in when
-    the sweep starts from zero) plus the level's operator coefficients read once
-    (finest: mu, 1/(lambda+mu), rho, gamma per cell; coarser: the stored
-    Galerkin stencil, at coef_bytes per real when the level keeps its
-    coefficients in another precision than the cycle's)."""
-    es = 4 if bits == 32 else 8
-    ncell_ = int(np.prod(info["n"][:dim]))
-    nu = info["N"] - ncell_          # displacement unknowns
-    # b: the rows of the colour's cells (every face, half the pressures);
-    # e_in: every unknown the rows touch; e_out: every unknown
-    vec = ((nu + ncell_ / 2) + (info["N"] if with_e else 0) + info["N"]) * 2 * es * nrhs
-    ncell = int(np.prod(info["n"][:dim]))
-    if fine:
-        coef = 4 * ncell * es
-    else:
-        nuu, nup = (8, 6) if dim == 2 else (38, 18)
-        coef = (sum(info["counts"][:dim]) * (2 * nuu + nup) + ncell) * (coef_bytes or es)
-    return vec + coef
-
-
 def run_gpu(w, steps, warmup, tol):
     import torch
     from paper_1806_11277_amd import ehh
@@ -106,43 +84,9 @@ def run_gpu(w, steps, warmup, tol):
     return total, results, B, X
 
 
-def visits_per_cycle(w):
-    """Visits of each non-coarsest level in one cycle: a level makes `cycle`
-    recursive calls from cycle_level on (one call above it and into the
-    coarsest level, whose exact solve a second call would only repeat)."""
-    v = [1]
-    for l in range(w.levels - 2):
-        calls = 1 if (l + 1 == w.levels - 1 or l < w.cycle_level) else w.cycle
-        v.append(v[-1] * calls)
-    return v
-
-
-def relax_kernel_name(w, level, ncell):
-    """The half-sweep kernel the library launches on a level (same routing as
-    its launcher): one thread per cell on the finest level, LDS-staged tiles on
-    2D Galerkin levels of at least 256^2 cells with more than 8 sources, eight
-    lanes per cell with row coefficients stored at setup on the other Galerkin
-    levels (3D: blocks of 8 (FP32) or 2 (FP64) sources per coefficient load; the
-    smallest FP64 2D levels split each row over two wavefronts for the sweeps
-    that start from e_in)."""
-    t = "float" if w.precond_bits == 32 else "double"
-    if w.dim == 2:
-        if level == 0:
-            return f"k_relax_cell2d<{t}, {t}>"
-        if ncell >= 65536 and len(w.sources()) > 8:
-            return f"k_relax_lds2d<{t}, StOp<2, {t}>>"
-        if t == "double" and -(-(ncell // 2) * 8 // 256) * 4 <= 256:
-            return "k_relax_st2d_split<double>"   # three of the visit's four half-sweeps
-        return f"k_relax_st2d<{t}, {'true' if t == 'float' else 'false'}, false>"
-    if level == 0:
-        return f"k_relax_cell3d<{t}>"
-    if t == "double":
-        return "k_relax_st3d<double, 2, 4, double>"
-    return f"k_relax_st3d<float, 8, 8, {'_Float16' if w.coarse_bits == 16 else 'float'}>"
-
-
 KERNEL_SOURCES = ["paper_1806_11277_amd/csrc/levels.hip", "paper_1806_11277_amd/csrc/ops.hpp",
-                  "paper_1806_11277_amd/csrc/common.hpp"]
+                  "paper_1806_11277_amd/csrc/common.hpp", "paper_1806_11277_amd/csrc/setup.hip",
+                  "paper_1806_11277_amd/csrc/dd.hip", "paper_1806_11277_amd/csrc/launchlog.hpp"]
 
 
 def kernel_source_hash():
@@ -174,106 +118,58 @@ def traffic_record(workload, kernel):
     return None
 
 
-def kernel_roofline(w, reps=30):
-    """HBM roofline of the dominant kernel, the red-black Vanka half-sweep.
-    Every level's half-sweep is timed with HIP events around the replay of a
-    graph of its launches (captured from the library's launches on the
-    caller's stream), each visit preceded by a 512 MiB write that evicts the
-    caches as the rest of a solve does, whose own time is subtracted.  Launches are weighted by their
-    count in one cycle (2 (nu1 + nu2) half-sweeps per visit) and grouped by the
-    kernel each level uses; the dominant kernel is the one with the largest
-    time per cycle.  achieved = its algorithmic bytes per launch / its average
-    launch duration."""
+def cycle_profile(w, reps=5):
+    """Every kernel of one preconditioner application, timed live: the library
+    records the launches of a real application (ehh_profile_precondition) and
+    replays each kernel's launches, with their arguments, from a HIP graph on
+    this stream, each preceded by a 512 MiB write that evicts the L2s and the
+    MALL as the rest of a solve does (its own time subtracted; HIP events).
+    The dominant kernel is the one with the largest time per application."""
     import torch
     from paper_1806_11277_amd import ehh
     S = ehh.solver_for_workload(w)
     nrhs = len(w.sources())
-    dt = torch.float32 if w.precond_bits == 32 else torch.float64
-    stream = torch.cuda.current_stream()
-    visits = visits_per_cycle(w)
-    rows = []
-    groups = {}
-    scrub = torch.empty(64 * 2 ** 20, dtype=torch.float64, device="cuda")   # 512 MiB
-    for l in range(w.levels - 1):
-        info = S.level_info(0, l)
-        # several vector sets in turn, so that a visit does not find the previous
-        # visit's vectors in L2 (inside a solve the level's vectors were last
-        # touched by other kernels)
-        nset = 4
-        sets = []
-        for _ in range(nset):
-            b = torch.randn((nrhs, 2 * info["N"]), dtype=dt, device="cuda")
-            sets.append((b, torch.randn_like(b), torch.zeros_like(b)))
-        # one visit's sweeps as the cycle launches them: the first pre-smoothing
-        # half-sweep starts from zero (no e_in), the others read e_in
-        nsw = 2 * (w.nu1 + w.nu2)
-        nzero = 1 if w.nu1 > 0 else 0
-
-        def visit(v=0):
-            b, e_in, e_out = sets[v % nset]
-            for k in range(nsw):
-                S.level_relax(0, l, k % 2, b, None if k < nzero else e_in, e_out)
-        visit()
-        torch.cuda.synchronize()
-        # The sweeps are replayed from a captured graph, as the solver replays its
-        # Arnoldi steps, so that host launch gaps do not enter the timing.  Each
-        # visit is preceded by a write of 512 MiB that evicts the L2s and the
-        # MALL, as the other kernels of a solve do between two visits of a level:
-        # t = (time of scrub + visit - time of scrub alone) per half-sweep.
-        def timed(with_visit):
-            graph = torch.cuda.CUDAGraph()
-            cap = torch.cuda.Stream()
-            with torch.cuda.graph(graph, stream=cap):
-                for r in range(reps):
-                    scrub.zero_()
-                    if with_visit:
-                        visit(r)
-            graph.replay()
-            best = float("inf")
-            for _ in range(3):
-                ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                torch.cuda.synchronize()
-                ev0.record(stream)
-                graph.replay()
-                ev1.record(stream)
-                torch.cuda.synchronize()
-                best = min(best, ev0.elapsed_time(ev1) / 1e3)
-            del graph
-            return best
-        t = max(timed(True) - timed(False), 0.0) / (reps * nsw)
-        cb = 2 if (w.coarse_bits == 16 and w.dim == 3) else None
-        nb = (nzero * level_bytes(info, w.precond_bits, nrhs, l == 0, w.dim, with_e=False, coef_bytes=cb) +
-              (nsw - nzero) * level_bytes(info, w.precond_bits, nrhs, l == 0, w.dim, coef_bytes=cb)) / nsw
-        launches = 2 * (w.nu1 + w.nu2) * visits[l]
-        ncell = int(np.prod(info["n"][:w.dim]))
-        name = relax_kernel_name(w, l, ncell)
-        rows.append(dict(level=l, n=info["n"][:w.dim], kernel=name, bytes=nb, us=t * 1e6, gbs=nb / t / 1e9,
-                         launches_per_cycle=launches))
-        g = groups.setdefault(name, dict(kernel=name, launches_per_cycle=0, bytes_per_cycle=0.0,
-                                         us_per_cycle=0.0))
-        g["launches_per_cycle"] += launches
-        g["bytes_per_cycle"] += launches * nb
-        g["us_per_cycle"] += launches * t * 1e6
-        del sets
-    del scrub
+    g = torch.Generator(device="cuda").manual_seed(5)
+    v = torch.randn((nrhs, S.stride), dtype=torch.float64, device="cuda", generator=g)
+    v /= v.norm(dim=1, keepdim=True)
+    z = torch.zeros_like(v)
+    evict = torch.empty(64 * 2 ** 20, dtype=torch.float64, device="cuda")   # 512 MiB
+    rows = S.profile_precondition(v, z, reps=reps, evict=evict)
+    torch.cuda.synchronize()
+    del evict, v, z
     S.close()
-    for g in groups.values():
-        g["avg_launch_us"] = g["us_per_cycle"] / g["launches_per_cycle"]
-        g["bytes_per_launch"] = g["bytes_per_cycle"] / g["launches_per_cycle"]
-        g["gbs"] = g["bytes_per_cycle"] / g["us_per_cycle"] / 1e3
-    dom = max(groups.values(), key=lambda g: g["us_per_cycle"])
-    achieved = dom["gbs"]
+    for r in rows:
+        r["us_per_application"] = r["launches"] * r["avg_us"]
+        r["gbs"] = r["bytes"] / r["avg_us"] / 1e3 if r["avg_us"] > 0 else None
+        r["gbs_model"] = r["bytes_model"] / r["avg_us"] / 1e3 if r["avg_us"] > 0 else None
+    rows.sort(key=lambda r: -r["us_per_application"])
+    tot_t = sum(r["us_per_application"] for r in rows)
+    tot_b = sum(r["launches"] * r["bytes"] for r in rows)
+    tot_bm = sum(r["launches"] * r["bytes_model"] for r in rows)
+    return dict(kernels=rows, us_per_application=tot_t, gbs=tot_b / tot_t / 1e3,
+                gbs_model=tot_bm / tot_t / 1e3)
+
+
+def roofline(w, prof, copy_gbs):
+    """The roofline object of the dominant kernel of a cycle profile."""
+    dom = prof["kernels"][0]
     rec = traffic_record(w.name, dom["kernel"])
-    tot_b = sum(g["bytes_per_cycle"] for g in groups.values())
-    tot_t = sum(g["us_per_cycle"] for g in groups.values())
-    return dict(bound="hbm", kernel=dom["kernel"], achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s",
-                frac=achieved / PEAK_HBM_GBS,
-                traffic=(rec["hbm_bytes_per_launch"] if rec else None),
-                traffic_unit="HBM bytes per launch (counters scaled by a plain copy)",
-                bytes_per_launch=dom["bytes_per_launch"], avg_launch_us=dom["avg_launch_us"],
-                launches_per_cycle=dom["launches_per_cycle"],
-                all_levels={"gbs": tot_b / tot_t / 1e3, "us_per_cycle": tot_t, "bytes_per_cycle": tot_b},
-                kernels=sorted(groups.values(), key=lambda g: -g["us_per_cycle"]), levels=rows)
+    return {"bound": "hbm", "kernel": dom["kernel"], "achieved": dom["gbs"], "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": dom["gbs"] / PEAK_HBM_GBS,
+            "traffic": (rec["hbm_bytes_per_launch"] if rec else None),
+            "traffic_unit": "HBM bytes per launch (counters scaled by a plain copy)",
+            "bytes_per_launch": dom["bytes"], "avg_launch_us": dom["avg_us"],
+            "avg_launch_us_warm": dom["avg_us_warm"],
+            "achieved_warm": dom["bytes"] / dom["avg_us_warm"] / 1e3 if dom["avg_us_warm"] > 0 else None,
+            "launches_per_application": dom["launches"],
+            "share_of_application": dom["us_per_application"] / prof["us_per_application"],
+            "achieved_model_bytes": dom["gbs_model"], "frac_model_bytes": dom["gbs_model"] / PEAK_HBM_GBS,
+            "bytes_model_per_launch": dom["bytes_model"],
+            "copy_gbs": copy_gbs, "frac_of_copy": dom["gbs"] / copy_gbs,
+            "application": {"us": prof["us_per_application"], "gbs": prof["gbs"], "gbs_model": prof["gbs_model"],
+                            "frac": prof["gbs"] / PEAK_HBM_GBS},
+            "kernels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
+                        for r in prof["kernels"]]}
 
 
 def copy_bandwidth(mib=1024, reps=10):
@@ -296,41 +192,53 @@ def copy_bandwidth(mib=1024, reps=10):
     return 2 * mib * 2 ** 20 / best / 1e9
 
 
-def cpu_baseline(w, gpu_iters, budget_s=20.0):
-    """The oracle as it stands (numpy/scipy, FP64) on this host: hierarchy setup
-    plus as many FGMRES iterations as fit in the budget, scaled to a full solve
-    with the GPU's iteration count."""
+def cpu_baseline(w):
+    """The oracle on this host: its direct solve (sparse LU of the assembled
+    operator of eq. (14) on the nested-dissection order, then one forward and
+    back substitution per source) of the workload's sources, the factorisation
+    and per-source times reported apart.  SuperLU runs on one core.  Returns
+    the baseline record and the factorisation (reused for the errors)."""
+    from oracle import direct
+    from oracle import discretisation as disc
     try:
-        from threadpoolctl import threadpool_limits
-        limiter = threadpool_limits(1)
+        from threadpoolctl import threadpool_info
+        blas = sum(i.get("num_threads", 0) for i in threadpool_info() if i.get("user_api") == "blas")
     except Exception:  # pragma: no cover
-        limiter = None
-    from oracle import discretisation as disc, multigrid as mg
+        blas = None
     m = w.media()
     t0 = time.perf_counter()
     pb = disc.Problem(w.n, w.h, w.omega, m["lam"], m["mu"], m["rho"], w.abl_cells, w.abl_max,
                       w.atten0, shift=w.shift)
-    A = pb.matrix()
-    H = mg.build_hierarchy(pb, w.levels, list(w.damping), economic=(w.vanka == 0), cycle=w.cycle,
-                           nu1=w.nu1, nu2=w.nu2, cycle_level=w.cycle_level)
-    t_setup = time.perf_counter() - t0
-    b = disc.point_source_vector(w.n, w.sources()[:1])
-    v = b / np.linalg.norm(b)
-    k = 0
+    lu = direct.factorize(pb)
     t1 = time.perf_counter()
-    while time.perf_counter() - t1 < budget_s:
-        z = H.cycle(v)
-        wv = A @ z
-        v = wv / np.linalg.norm(wv)
-        k += 1
-    t_iter = (time.perf_counter() - t1) / k
-    t_solve = t_setup + gpu_iters * t_iter
-    if limiter is not None:
-        limiter.unregister()
-    return dict(value=1.0 / t_solve, unit="solves/s", cores=1, kind="oracle",
-                sample=f"oracle setup ({t_setup:.1f} s) + {k} preconditioned FGMRES iterations "
-                       f"({t_iter:.2f} s each) of {w.name}, one right-hand side, scaled to "
-                       f"{gpu_iters} iterations")
+    srcs = w.sources()
+    sol = [lu.solve(disc.point_source_vector(w.n, [s_])) for s_ in srcs]
+    t2 = time.perf_counter()
+    per_source = (t2 - t1) / len(srcs)
+    total = t2 - t0
+    rec = dict(value=len(srcs) / total, unit="solves/s", cores=1, kind="oracle",
+               sample=f"oracle direct solve of {w.name}: assembly + sparse LU ({t1 - t0:.1f} s, "
+                      f"{lu.nnz:.2e} nonzeros in L+U) + {len(srcs)} substitution(s) ({per_source:.2f} s each), "
+                      f"whole, not extrapolated",
+               factor_s=t1 - t0, per_source_s=per_source,
+               host_cores=len(os.sched_getaffinity(0)), blas_threads=blas,
+               threads_used="1 (SuperLU is sequential)")
+    return rec, lu, sol
+
+
+def errors_vs_oracle(w, X, lu):
+    """Relative 2-norm error of every source's solution against the oracle's
+    direct solution of the same operator (the operator of c2 and c3 is the
+    same: the factorisation is shared)."""
+    from oracle import discretisation as disc
+    x = X.double().cpu().numpy()
+    N = x.shape[1] // 2
+    out = []
+    for r, s_ in enumerate(w.sources()):
+        ref = lu.solve(disc.point_source_vector(w.n, [s_]))
+        got = x[r, :N] + 1j * x[r, N:]
+        out.append(float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
+    return out
 
 
 def poisson_sweep_report():
@@ -361,6 +269,38 @@ def poisson_sweep_report():
     return out
 
 
+def accuracy_solve(w, tol):
+    """One more (untimed) solve of the workload's sources to a tighter relative
+    residual, for the errors against the oracle at that residual."""
+    import torch
+    from paper_1806_11277_amd import ehh
+    S = ehh.solver_for_workload(w)
+    B = rhs_tensor(S, w)
+    X = torch.zeros_like(B)
+    st, stats = S.solve(B, X, tol=tol, maxit=4 * w.maxit)
+    torch.cuda.synchronize()
+    S.close()
+    return X, max(s_["rel_res_true"] for s_ in stats), [s_["iters"] for s_ in stats]
+
+
+def workload_entry(w, steps, warmup, tol, copy_gbs, with_profile):
+    """Time `steps` steps of a workload (after `warmup`), with its cycle profile."""
+    total, res, B, X = run_gpu(w, steps, warmup, tol)
+    stats = res[-1][3]
+    iters = [s_["iters"] for s_ in stats]
+    out = {"workload": w.name, "nrhs": len(stats), "value": len(stats) * steps / total, "unit": "solves/s",
+           "ms_per_step": 1e3 * total / steps, "steps": steps,
+           "setup_ms": 1e3 * float(np.mean([r[0] for r in res])),
+           "solve_ms": 1e3 * float(np.mean([r[1] for r in res])),
+           "iters": iters if len(iters) <= 4 else [min(iters), max(iters)],
+           "rel_res_true_max": max(s_["rel_res_true"] for s_ in stats), "status": res[-1][2],
+           "dtype": "f64" if w.precond_bits == 64 else "f32 cycle + f64 Krylov/coarsest"}
+    if with_profile:
+        print(f"[bench] cycle profile {w.name}", file=sys.stderr, flush=True)
+        out["roofline"] = roofline(w, cycle_profile(w), copy_gbs)
+    return out, X
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -368,11 +308,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2_hetero512_fp64")
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle (its direct solve is also the reference of the errors)")
     ap.add_argument("--no-roofline", action="store_true")
-    ap.add_argument("--batched", default="c3_hetero512_batch32_fp32",
-                    help="batched companion workload reported in the same line ('' to skip)")
-    ap.add_argument("--batched-steps", type=int, default=2)
+    ap.add_argument("--companions", default="c3_hetero512_batch32_fp32,c4_layered128_dd8_batch16_fp32",
+                    help="comma-separated workloads reported in the same line ('' for none)")
+    ap.add_argument("--companion-steps", type=int, default=2)
+    ap.add_argument("--accuracy-tol", type=float, default=1e-8,
+                    help="relative residual of an extra untimed solve per workload whose error against "
+                         "the oracle is reported beside the error at --tol (0: none)")
     ap.add_argument("--poisson-sweep", action="store_true",
                     help="print the Poisson-ratio sweep (constant media, lambda 0.5..16) as one JSON line and exit")
     ap.add_argument("--coarse-bits", type=int, default=None, choices=(16, 32),
@@ -385,6 +329,7 @@ def main():
         print("bench.py measures one GPU: the solver runs all subdomains and right-hand sides "
               "on a single device; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
+    import dataclasses
     import torch
     from workloads import get_config
     if a.poisson_sweep:
@@ -399,64 +344,76 @@ def main():
         del src, dst
     w = get_config(a.config)
     if a.coarse_bits is not None:
-        import dataclasses
         w = dataclasses.replace(w, coarse_bits=a.coarse_bits)
+    copy_gbs = None if a.no_roofline else copy_bandwidth()
     print(f"[bench] {w.name}: n={w.n} nrhs={len(w.sources())} levels={w.levels} cycle={w.cycle} "
           f"bits={w.precond_bits}", file=sys.stderr, flush=True)
-    total, res, B, X = run_gpu(w, a.steps, a.warmup, a.tol)
-    setup_ms = 1e3 * float(np.mean([r[0] for r in res]))
-    solve_ms = 1e3 * float(np.mean([r[1] for r in res]))
-    stats = res[-1][3]
-    iters = [s["iters"] for s in stats]
-    nrhs = len(stats)
-    ms_per_step = 1e3 * total / a.steps
+    main_e, X = workload_entry(w, a.steps, a.warmup, a.tol, copy_gbs, False)
     out = {
         "metric": "preconditioned solves/sec at rel. residual 1e-6; V-cycle HBM GB/s vs peak",
-        "value": nrhs * a.steps / total,
+        "value": main_e["value"],
         "unit": "solves/s",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": main_e["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if w.precond_bits == 64 else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": w.name, "grid": list(w.n), "unknowns": int(B.shape[1] // 2),
-                   "nrhs": nrhs, "levels": w.levels, "cycle": "V" if w.cycle == 1 else "W",
+        "config": {"workload": w.name, "grid": list(w.n), "unknowns": int(X.shape[1] // 2),
+                   "nrhs": main_e["nrhs"], "levels": w.levels, "cycle": "V" if w.cycle == 1 else "W",
                    "cycle_level": w.cycle_level,
                    "nu": [w.nu1, w.nu2], "vanka": "full" if w.vanka else "economic",
                    "shift": w.shift, "precond_bits": w.precond_bits, "restart": w.restart,
                    "dd_parts": list(w.dd_parts[:w.dim]), "coarse_bits": w.coarse_bits, "tol": a.tol},
-        "setup_ms": setup_ms, "solve_ms": solve_ms,
-        "iters": iters if nrhs <= 4 else [min(iters), max(iters)],
-        "rel_res_true_max": max(s["rel_res_true"] for s in stats),
-        "status": res[-1][2],
+        "setup_ms": main_e["setup_ms"], "solve_ms": main_e["solve_ms"],
+        "iters": main_e["iters"], "rel_res_true_max": main_e["rel_res_true_max"], "status": main_e["status"],
     }
+    results = {w.name: (w, X, None)}
+    if a.accuracy_tol > 0 and not a.no_cpu_baseline:
+        results[w.name] = (w, X, accuracy_solve(w, a.accuracy_tol))
     if not a.no_roofline:
-        print("[bench] roofline of the dominant kernel", file=sys.stderr, flush=True)
-        out["roofline"] = kernel_roofline(w)
-        cg = copy_bandwidth()
-        out["roofline"]["copy_gbs"] = cg          # achievable plain-copy bandwidth on this GPU (context)
-        out["roofline"]["frac_of_copy"] = out["roofline"]["achieved"] / cg
-    if a.batched:
-        wb = get_config(a.batched)
-        print(f"[bench] batched companion {wb.name}", file=sys.stderr, flush=True)
-        tb, rb, Bb, _ = run_gpu(wb, a.batched_steps, 1, a.tol)
-        sb = rb[-1][3]
-        itb = [s_["iters"] for s_ in sb]
-        vb = len(sb) * a.batched_steps / tb
-        out["batched"] = {"workload": wb.name, "nrhs": len(sb), "value": vb, "unit": "solves/s",
-                          "ms_per_step": 1e3 * tb / a.batched_steps,
-                          "dtype": "f32 cycle + f64 Krylov/coarsest",
-                          "iters_min_max": [min(itb), max(itb)],
-                          "rel_res_true_max": max(s_["rel_res_true"] for s_ in sb),
-                          "speedup_vs_plain_fp64_single_source": vb / out["value"]}
-        if not a.no_roofline:
-            out["batched"]["roofline"] = kernel_roofline(wb)
-            cg = out["roofline"]["copy_gbs"]
-            out["batched"]["roofline"]["copy_gbs"] = cg
-            out["batched"]["roofline"]["frac_of_copy"] = out["batched"]["roofline"]["achieved"] / cg
+        print(f"[bench] cycle profile {w.name}", file=sys.stderr, flush=True)
+        rl = roofline(w, cycle_profile(w), copy_gbs)
+        out["roofline"] = {k: v for k, v in rl.items() if k != "kernels"}
+        out["cycle_kernels"] = rl["kernels"]
+    comps = [c for c in a.companions.split(",") if c]
+    out["companions"] = []
+    for name in comps:
+        wc = get_config(name)
+        if a.coarse_bits is not None:
+            wc = dataclasses.replace(wc, coarse_bits=a.coarse_bits)
+        print(f"[bench] companion {wc.name}", file=sys.stderr, flush=True)
+        e, Xc = workload_entry(wc, a.companion_steps, 1, a.tol, copy_gbs, not a.no_roofline)
+        e["speedup_vs_plain_fp64_single_source"] = e["value"] / out["value"]
+        out["companions"].append(e)
+        acc = accuracy_solve(wc, a.accuracy_tol) if (a.accuracy_tol > 0 and not a.no_cpu_baseline and
+                                                    wc.dim == 2) else None
+        results[wc.name] = (wc, Xc, acc)
     if not a.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w, int(np.median(iters)))
+        print("[bench] cpu baseline: the oracle's direct solve", file=sys.stderr, flush=True)
+        base, lu, _ = cpu_baseline(w)
+        out["cpu_baseline"] = base
+        # errors against the oracle's direct solution, for every workload on this operator
+        out["err_vs_oracle"] = {}
+        for name, (wk, Xk, acc) in results.items():
+            same = wk.dim == w.dim and tuple(wk.n) == tuple(w.n) and wk.media_fn is not None and \
+                wk.h == w.h and abs(wk.omega - w.omega) < 1e-12 * w.omega and wk.abl_cells == w.abl_cells and \
+                wk.atten0 == w.atten0 and np.array_equal(wk.media()["mu"], w.media()["mu"]) and \
+                np.array_equal(wk.media()["lam"], w.media()["lam"]) and np.array_equal(wk.media()["rho"], w.media()["rho"])
+            if same:
+                errs = errors_vs_oracle(wk, Xk, lu)
+                rec = {"tol": a.tol, "per_source": errs, "max": max(errs),
+                       "reference": "oracle direct solve (sparse LU)"}
+                if acc is not None:
+                    ea = errors_vs_oracle(wk, acc[0], lu)
+                    rec["at_accuracy_tol"] = {"tol": a.accuracy_tol, "per_source": ea, "max": max(ea),
+                                              "rel_res_true_max": acc[1], "iters": [min(acc[2]), max(acc[2])]}
+                out["err_vs_oracle"][name] = rec
+            else:
+                out["err_vs_oracle"][name] = {"per_source": None, "max": None,
+                                              "reference": "parity unpinned at this size: no direct solve of "
+                                                           "this operator fits the host; the configuration is "
+                                                           "compared with the oracle at 32^3 and 16^3 and a "
+                                                           "full-size subdomain cycle in the tests"}
     print(json.dumps(out), flush=True)
 
 

@@ -246,6 +246,39 @@ int32_t ehh_level_prolong(ehh_handle_t h, int32_t sub, int32_t level, const void
 int32_t ehh_coarse_solve(ehh_handle_t h, int32_t sub, const void* r, void* e,
                          int32_t nrhs, void* stream);
 
+/* Measurement of the preconditioner's kernels (the cycle's HBM roofline).
+ * One application z = M^{-1} v (as ehh_precondition) is run with every kernel
+ * launch recorded; then each distinct kernel's launches of that application are
+ * replayed, with the same arguments and in their order, from a HIP graph on
+ * `stream`, `reps` times, each launch preceded by a write of the caller's
+ * eviction buffer (device, evict_bytes, a multiple of 4; NULL and 0 for none)
+ * so that it finds the caches as cold as inside a solve; the eviction writes
+ * alone are timed the same way and subtracted (HIP events, best of three);
+ * the launches are also replayed back to back without the writes.
+ * out[cap] receives one entry per kernel in order of first launch, *count how
+ * many were written.  v: (device) as for ehh_precondition; z and the handle's
+ * workspaces are overwritten by the replays (z's content afterwards is
+ * unspecified).  Synchronises `stream`. */
+typedef struct {
+    char    kernel[128];    /* kernel name as kernel traces print it, e.g.
+                               "k_relax_st2d<double, false, false>" */
+    int32_t launches;       /* launches in one preconditioner application */
+    double  avg_us;         /* average duration of one launch after the eviction write
+                               (its data from HBM) */
+    double  avg_us_warm;    /* the same launches replayed back to back without it (their
+                               data partly in L2 / MALL, as a small level's inside a solve) */
+    double  bytes;          /* algorithmic HBM bytes per launch: every vector entry the
+                               kernel must read or write once, the operator's compact
+                               coefficients once (mean over its launches) */
+    double  bytes_model;    /* the same under the per-cell cycle model: V unknowns per
+                               cell of w bytes per source (3 V w for a half-sweep from
+                               e_in, 2 V w from zero) plus the level's coefficients per
+                               cell (fine 4 reals; Galerkin 29 complex in 2D, 169 in 3D) */
+} ehh_kernel_time_t;
+int32_t ehh_profile_precondition(ehh_handle_t h, const double* v, double* z, int32_t nrhs, int32_t reps,
+                                 void* evict, int64_t evict_bytes, ehh_kernel_time_t* out, int32_t cap,
+                                 int32_t* count, void* stream);
+
 /* The coarsest solve of ehh_coarse_solve, for callers that cannot allocate
  * device memory: code under HIP graph capture, tight serving loops, harnesses
  * that forbid hipMalloc.  It allocates nothing: the column-segment partial sums

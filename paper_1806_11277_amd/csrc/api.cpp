@@ -19,8 +19,33 @@
 #include <utility>
 #include <vector>
 
+#include <cxxabi.h>
+#include <dlfcn.h>
+
+#include <functional>
+
 #include "ehh.h"
 #include "internal.hpp"
+#include "launchlog.hpp"
+
+// ------------------------------------------------------------------ launch log
+// On for the calling thread only, while ehh_profile_precondition runs one
+// preconditioner application; the other threads' launches are never recorded.
+namespace ehh {
+namespace {
+struct LogRec {
+    const void* kernel;
+    LaunchBytes bytes;
+    std::function<void(hipStream_t)> again;
+};
+thread_local bool t_log_on = false;
+thread_local std::vector<LogRec> t_log;
+}  // namespace
+bool launch_log_on() { return t_log_on; }
+void launch_log_add(const void* kernel, LaunchBytes bytes, std::function<void(hipStream_t)> again) {
+    t_log.push_back(LogRec{kernel, bytes, std::move(again)});
+}
+}  // namespace ehh
 
 using namespace ehh;
 
@@ -1029,6 +1054,67 @@ int32_t build_graphs(ehh_ctx* c, const LevelDesc<double>& A, int nrhs) {
     return EHH_OK;
 }
 
+// The demangled name of a kernel's host stub without namespace, return type and
+// parameter list (as kernel traces print it), e.g. "k_relax_st2d<double, false, false>".
+std::string kernel_name(const void* k) {
+    Dl_info info{};
+    if (!dladdr(k, &info) || !info.dli_sname) return "unknown";
+    int st = 0;
+    char* d = abi::__cxa_demangle(info.dli_sname, nullptr, nullptr, &st);
+    std::string n = (st == 0 && d) ? d : info.dli_sname;
+    std::free(d);
+    if (n.compare(0, 5, "void ") == 0) n = n.substr(5);
+    for (size_t p = n.find("ehh::"); p != std::string::npos; p = n.find("ehh::")) n.erase(p, 5);
+    int depth = 0;
+    for (size_t i = 0; i < n.size(); ++i) {
+        if (n[i] == '<') ++depth;
+        else if (n[i] == '>') --depth;
+        else if (n[i] == '(' && depth == 0) return n.substr(0, i);
+    }
+    return n;
+}
+
+// Time `reps` rounds of the recorded launches (each preceded by the eviction
+// write when evict is given) replayed from a graph on the caller's stream;
+// with_kernel = false times the eviction writes alone.
+int32_t time_replay(ehh_ctx* c, const std::vector<const LogRec*>& recs, int reps, void* evict, int64_t evict_bytes,
+                    bool with_kernel, hipStream_t s, double* ms) {
+    if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    for (int r = 0; r < reps; ++r)
+        for (const LogRec* rec : recs) {
+            if (evict) (void)launch_zero(evict, (size_t)evict_bytes, c->cap_stream);
+            if (with_kernel) rec->again(c->cap_stream);
+        }
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(c->cap_stream, &g);
+    if (ec != hipSuccess) return fail(EHH_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return fail(EHH_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    double best = 1e300;
+    if (e == hipSuccess) e = hipGraphLaunch(ex, s);   // warm-up replay
+    for (int t = 0; t < 3 && e == hipSuccess; ++t) {
+        e = hipEventRecord(e0, s);
+        if (e == hipSuccess) e = hipGraphLaunch(ex, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float f = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&f, e0, e1);
+        if (e == hipSuccess) best = std::min(best, (double)f);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipGraphExecDestroy(ex);
+    if (e != hipSuccess) return fail(EHH_ERR_HIP, std::string("timed replay: ") + hipGetErrorString(e));
+    *ms = best;
+    return EHH_OK;
+}
+
 }  // namespace
 
 // ======================================================================= C ABI
@@ -1457,6 +1543,55 @@ int32_t ehh_coarse_solve(ehh_handle_t h, int32_t sub, const void* r, void* e, in
     else
         HIPCHK(launch_coarse_apply<double>(S->inv, S->sym, L->g.N, (const double*)r, (double*)e, nrhs, h->coarse_ws,
                                            as_stream(stream)));
+    return EHH_OK;
+}
+
+int32_t ehh_profile_precondition(ehh_handle_t h, const double* v, double* z, int32_t nrhs, int32_t reps, void* evict,
+                                 int64_t evict_bytes, ehh_kernel_time_t* out, int32_t cap, int32_t* count,
+                                 void* stream) {
+    CHK(check_handle(h));
+    if (!v || !z || v == z || nrhs < 1 || reps < 1 || !out || cap < 1 || !count || evict_bytes < 0 ||
+        (evict && evict_bytes % 4) || (!evict && evict_bytes))
+        return fail(EHH_ERR_INVALID, "ehh_profile_precondition: bad vectors, nrhs, reps, eviction buffer or output");
+    hipStream_t s = as_stream(stream);
+    CHK(ensure_ws(h, nrhs));
+    t_log.clear();
+    t_log_on = true;
+    const int32_t st = precondition_any(h, v, z, nrhs, s);
+    t_log_on = false;
+    std::vector<LogRec> log;
+    log.swap(t_log);
+    CHK(st);
+    HIPCHK(hipStreamSynchronize(s));
+    // kernels in order of their first launch, each with its launches in order
+    std::vector<const void*> order;
+    std::map<const void*, std::vector<const LogRec*>> groups;
+    for (const LogRec& r : log) {
+        auto& gv = groups[r.kernel];
+        if (gv.empty()) order.push_back(r.kernel);
+        gv.push_back(&r);
+    }
+    int32_t k = 0;
+    for (const void* kern : order) {
+        if (k >= cap) break;
+        const auto& recs = groups[kern];
+        double t_all = 0.0, t_evict = 0.0, t_warm = 0.0;
+        CHK(time_replay(h, recs, reps, evict, evict_bytes, true, s, &t_all));
+        if (evict) CHK(time_replay(h, recs, reps, evict, evict_bytes, false, s, &t_evict));
+        CHK(time_replay(h, recs, reps, nullptr, 0, true, s, &t_warm));
+        ehh_kernel_time_t& o = out[k++];
+        std::memset(&o, 0, sizeof(o));
+        const std::string nm = kernel_name(kern);
+        std::strncpy(o.kernel, nm.c_str(), sizeof(o.kernel) - 1);
+        o.launches = (int32_t)recs.size();
+        o.avg_us = std::max(t_all - t_evict, 0.0) * 1e3 / ((double)reps * recs.size());
+        o.avg_us_warm = t_warm * 1e3 / ((double)reps * recs.size());
+        for (const LogRec* r : recs) {
+            o.bytes += r->bytes.mine / recs.size();
+            o.bytes_model += r->bytes.model / recs.size();
+        }
+    }
+    *count = k;
     return EHH_OK;
 }
 

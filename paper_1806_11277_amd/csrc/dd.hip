@@ -5,6 +5,7 @@
 // correction back to the global vector, either averaged over the subdomains
 // that own an unknown (one colour) or added unweighted (Algorithm 2).
 #include "internal.hpp"
+#include "launchlog.hpp"
 #include "ops.hpp"
 
 namespace ehh {
@@ -75,9 +76,9 @@ template <typename T>
 hipError_t launch_dd_gather(const Geo& gg, const Geo& gl, const SubMap& m, const double* v, T* out, int nrhs,
                             hipStream_t s) {
     if (gg.dim == 2)
-        hipLaunchKernelGGL((k_dd_gather<2, T>), nblk(gl.N), 256, 0, s, gg, gl, m, v, out, nrhs);
+        EHH_LAUNCH_B(bytes_plain(nrhs * (double)gl.N * (16.0 + 2.0 * sizeof(T))), (k_dd_gather<2, T>), nblk(gl.N), 256, 0, s, gg, gl, m, v, out, nrhs);
     else
-        hipLaunchKernelGGL((k_dd_gather<3, T>), nblk(gl.N), 256, 0, s, gg, gl, m, v, out, nrhs);
+        EHH_LAUNCH_B(bytes_plain(nrhs * (double)gl.N * (16.0 + 2.0 * sizeof(T))), (k_dd_gather<3, T>), nblk(gl.N), 256, 0, s, gg, gl, m, v, out, nrhs);
     return hipGetLastError();
 }
 
@@ -85,9 +86,9 @@ template <typename T>
 hipError_t launch_dd_scatter(const Geo& gg, const Geo& gl, const SubMap& m, const T* e, double* z, int nrhs,
                              int weighted, hipStream_t s) {
     if (gg.dim == 2)
-        hipLaunchKernelGGL((k_dd_scatter<2, T>), nblk(gl.N), 256, 0, s, gg, gl, m, e, z, nrhs, weighted);
+        EHH_LAUNCH_B(bytes_plain(nrhs * (double)gl.N * (32.0 + 2.0 * sizeof(T))), (k_dd_scatter<2, T>), nblk(gl.N), 256, 0, s, gg, gl, m, e, z, nrhs, weighted);
     else
-        hipLaunchKernelGGL((k_dd_scatter<3, T>), nblk(gl.N), 256, 0, s, gg, gl, m, e, z, nrhs, weighted);
+        EHH_LAUNCH_B(bytes_plain(nrhs * (double)gl.N * (32.0 + 2.0 * sizeof(T))), (k_dd_scatter<3, T>), nblk(gl.N), 256, 0, s, gg, gl, m, e, z, nrhs, weighted);
     return hipGetLastError();
 }
 
@@ -172,9 +173,9 @@ hipError_t launch_dd_gather_res(const Geo& gg, const Geo& gl, const SubMap& m, c
                                 const double* v, const double* z, T* out, int nrhs, hipStream_t s) {
     if (16 * gg.N >= (int64_t(1) << 32)) return hipErrorInvalidValue;   // 32-bit byte offsets per source
     if (gg.dim == 2)
-        hipLaunchKernelGGL((k_dd_gather_res<2, T>), nblk(gl.N), 256, 0, s, gg, gl, m, A, v, z, out, nrhs);
+        EHH_LAUNCH_B(bytes_plain(nrhs * (double)gl.N * (32.0 + 2.0 * sizeof(T)) + 32.0 * gl.ncell), (k_dd_gather_res<2, T>), nblk(gl.N), 256, 0, s, gg, gl, m, A, v, z, out, nrhs);
     else
-        hipLaunchKernelGGL((k_dd_gather_res<3, T>), nblk(gl.N), 256, 0, s, gg, gl, m, A, v, z, out, nrhs);
+        EHH_LAUNCH_B(bytes_plain(nrhs * (double)gl.N * (32.0 + 2.0 * sizeof(T)) + 32.0 * gl.ncell), (k_dd_gather_res<3, T>), nblk(gl.N), 256, 0, s, gg, gl, m, A, v, z, out, nrhs);
     return hipGetLastError();
 }
 template hipError_t launch_dd_gather_res<float>(const Geo&, const Geo&, const SubMap&, const FineCoef<double>&,

@@ -7,6 +7,7 @@
 #include <cstdlib>
 
 #include "internal.hpp"
+#include "launchlog.hpp"
 #include "ops.hpp"
 
 namespace ehh {
@@ -2878,6 +2879,8 @@ hipError_t launch_apply(const LevelDesc<T>& L, const T* x, const T* b, T* y, int
     const int rb3 = rhs_block_3d_stencil<T>();
     const int rpb3 = rhs_per_block((L.g.N + 63) / 64, nrhs, rb3);
     const dim3 gb3(nblk(L.g.N), (nrhs + rpb3 - 1) / rpb3);
+    const double coef_es = L.fine ? (double)sizeof(T) : (L.sp.half ? 2.0 : (double)sizeof(T));
+    const LaunchBytes lb = bytes_apply(L.g, L.fine, nrhs, b != nullptr, (int)sizeof(T), coef_es);
     if (L.g.dim == 2 && L.fine && cell2d_enabled() && 2 * L.g.N * (int64_t)sizeof(T) < (int64_t(1) << 32)) {
         const int64_t cells = L.g.ncell;
         static const int64_t cell_waves = env_int("EHH_CELL_WAVES", 4096);
@@ -2885,14 +2888,14 @@ hipError_t launch_apply(const LevelDesc<T>& L, const T* x, const T* b, T* y, int
         groups = groups < 1 ? 1 : (groups > nrhs ? nrhs : groups);
         const int rpc = (int)((nrhs + groups - 1) / groups);
         const dim3 gc(nblk(cells), (nrhs + rpc - 1) / rpc);
-        hipLaunchKernelGGL((k_apply_cell2d<T>), gc, 256, 0, s, FineOp<2, T>{L.g, L.f}, x, b, y, nrhs, stride, rpc);
+        EHH_LAUNCH_B(lb, (k_apply_cell2d<T>), gc, 256, 0, s, FineOp<2, T>{L.g, L.f}, x, b, y, nrhs, stride, rpc);
     } else if (L.g.dim == 2) {
         if (L.fine)
-            EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_apply_plan<2, T, FineOp<2, T>, RB>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, x, b, y, nrhs, stride, rpb));
+            EHH_RB_DISPATCH(rb, EHH_LAUNCH_B(lb, (k_apply_plan<2, T, FineOp<2, T>, RB>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, x, b, y, nrhs, stride, rpb));
         else if (L.sp.rre)
-            hipLaunchKernelGGL((k_apply_st2d<T>), gb, 256, 0, s, L.g, x, b, y, nrhs, stride, rpb, L.sp.rre, L.sp.rim);
+            EHH_LAUNCH_B(lb, (k_apply_st2d<T>), gb, 256, 0, s, L.g, x, b, y, nrhs, stride, rpb, L.sp.rre, L.sp.rim);
         else
-            EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_apply_plan<2, T, StOp<2, T>, RB>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, x, b, y, nrhs, stride, rpb));
+            EHH_RB_DISPATCH(rb, EHH_LAUNCH_B(lb, (k_apply_plan<2, T, StOp<2, T>, RB>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, x, b, y, nrhs, stride, rpb));
     } else if (L.g.dim == 3 && L.fine && cell3d_enabled() && 2 * L.g.N * (int64_t)sizeof(T) < (int64_t(1) << 32)) {
         const int64_t cells = L.g.ncell;
         static const int64_t cell_waves = env_int("EHH_CELL_WAVES", 4096);
@@ -2900,15 +2903,15 @@ hipError_t launch_apply(const LevelDesc<T>& L, const T* x, const T* b, T* y, int
         groups = groups < 1 ? 1 : (groups > nrhs ? nrhs : groups);
         const int rpc = (int)((nrhs + groups - 1) / groups);
         const dim3 gc(nblk(cells), (nrhs + rpc - 1) / rpc);
-        hipLaunchKernelGGL((k_apply_cell3d<T>), gc, 256, 0, s, FineOp<3, T>{L.g, L.f}, x, b, y, nrhs, stride, rpc);
+        EHH_LAUNCH_B(lb, (k_apply_cell3d<T>), gc, 256, 0, s, FineOp<3, T>{L.g, L.f}, x, b, y, nrhs, stride, rpc);
     } else {
         if (L.fine)
-            EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_apply_plan<3, T, FineOp<3, T>, RB>), gb, 256, 0, s, FineOp<3, T>{L.g, L.f}, x, b, y, nrhs, stride, rpb));
+            EHH_RB_DISPATCH(rb, EHH_LAUNCH_B(lb, (k_apply_plan<3, T, FineOp<3, T>, RB>), gb, 256, 0, s, FineOp<3, T>{L.g, L.f}, x, b, y, nrhs, stride, rpb));
         else if (L.sp.rre) {
 #define EHH_APPLY_ST3D(RB, CH, C)                                                                                \
     {                                                                                                            \
         const int rpbs = rhs_per_block((L.g.N + 63) / 64, nrhs, RB);                                             \
-        hipLaunchKernelGGL((k_apply_st3d<T, RB, CH, C>), dim3(nblk(L.g.N), (nrhs + rpbs - 1) / rpbs), 256, 0, s,   \
+        EHH_LAUNCH_B(lb, (k_apply_st3d<T, RB, CH, C>), dim3(nblk(L.g.N), (nrhs + rpbs - 1) / rpbs), 256, 0, s,   \
                            L.g, x, b, y, nrhs, stride, rpbs, (const C*)L.sp.rre, (const C*)L.sp.rim,             \
                            (T)L.sp.scale);                                                                       \
     }
@@ -2917,7 +2920,7 @@ hipError_t launch_apply(const LevelDesc<T>& L, const T* x, const T* b, T* y, int
             else EHH_APPLY_ST3D(8, 4, T)
 #undef EHH_APPLY_ST3D
         } else
-            EHH_RB_DISPATCH(rb3, hipLaunchKernelGGL((k_apply<3, T, StOp<3, T>, RB>), gb3, 256, 0, s, StOp<3, T>{L.g, L.s}, x, b, y, nrhs, stride, rpb3));
+            EHH_RB_DISPATCH(rb3, EHH_LAUNCH_B(lb, (k_apply<3, T, StOp<3, T>, RB>), gb3, 256, 0, s, StOp<3, T>{L.g, L.s}, x, b, y, nrhs, stride, rpb3));
     }
     return hipGetLastError();
 }
@@ -2934,6 +2937,8 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
     const int rpb3 = rhs_per_block((npair * 8 + 63) / 64, nrhs, rb3);
     const dim3 gb3(nblk(npair * 8), (nrhs + rpb3 - 1) / rpb3);
     const T tw = (T)w;
+    const double coef_es = L.fine ? (double)sizeof(T) : (L.sp.half ? 2.0 : (double)sizeof(T));
+    const LaunchBytes lb = bytes_relax(L.g, L.fine, nrhs, ein != nullptr, (int)sizeof(T), (int)sizeof(T), coef_es);
     // LDS staging pays on the 21-term Galerkin rows of large levels with many
     // sources (measured on 256^2 with 32 sources: 123 us, against 178 us with
     // stored row plans and 217 us with plans built in the kernel); with a few
@@ -2946,7 +2951,7 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
         lds2d_enabled() && big_batch) {
         const int tiles = lds_tiles;
         const dim3 gl(tiles, (nrhs + rpl - 1) / rpl);
-        hipLaunchKernelGGL((k_relax_lds2d<T, StOp<2, T>>), gl, 512, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride, rpl, 2);
+        EHH_LAUNCH_B(lb, (k_relax_lds2d<T, StOp<2, T>>), gl, 512, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride, rpl, 2);
     } else if (L.g.dim == 2 && L.fine && cell2d_enabled() && 2 * L.g.N * (int64_t)sizeof(T) < (int64_t(1) << 32)) {
         const int64_t cells = npair;
         static const int64_t cell_waves = env_int("EHH_CELL_WAVES", 4096);
@@ -2954,10 +2959,10 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
         groups = groups < 1 ? 1 : (groups > nrhs ? nrhs : groups);
         const int rpc = (int)((nrhs + groups - 1) / groups);
         const dim3 gc(nblk(cells), (nrhs + rpc - 1) / rpc);
-        hipLaunchKernelGGL((k_relax_cell2d<T>), gc, 256, 0, s, FineOp<2, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride, rpc);
+        EHH_LAUNCH_B(lb, (k_relax_cell2d<T>), gc, 256, 0, s, FineOp<2, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride, rpc);
     } else if (L.g.dim == 2) {
         if (L.fine)
-            EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_relax_plan<2, T, FineOp<2, T>, RB>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb));
+            EHH_RB_DISPATCH(rb, EHH_LAUNCH_B(lb, (k_relax_plan<2, T, FineOp<2, T>, RB>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb));
         else if (L.sp.re[colour])
         {
             // the smallest FP64 levels (one wavefront per CU): rows split over two
@@ -2966,12 +2971,12 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
             static const bool split_on = env_int("EHH_SPLIT", 1) != 0;
             const int64_t groups = L.sp.lanes / 64;
             if (sizeof(T) == 8 && ein && split_on && groups <= 256)
-                hipLaunchKernelGGL((k_relax_st2d_split<T>), dim3((unsigned)((groups + 1) / 2), gb.y), 256, 0, s, L.g, colour, tw, econ, b, ein, eout, nrhs, stride, rpb, L.sp.re[colour], L.sp.im[colour], L.sp.lanes);
+                EHH_LAUNCH_B(lb, (k_relax_st2d_split<T>), dim3((unsigned)((groups + 1) / 2), gb.y), 256, 0, s, L.g, colour, tw, econ, b, ein, eout, nrhs, stride, rpb, L.sp.re[colour], L.sp.im[colour], L.sp.lanes);
             else
-                hipLaunchKernelGGL((k_relax_st2d<T, sizeof(T) == 4, false>), gb, 256, 0, s, L.g, colour, tw, econ, b, ein, eout, nrhs, stride, rpb, L.sp.re[colour], L.sp.im[colour], L.sp.lanes, L.g, (const T*)nullptr, (T*)nullptr);
+                EHH_LAUNCH_B(lb, (k_relax_st2d<T, sizeof(T) == 4, false>), gb, 256, 0, s, L.g, colour, tw, econ, b, ein, eout, nrhs, stride, rpb, L.sp.re[colour], L.sp.im[colour], L.sp.lanes, L.g, (const T*)nullptr, (T*)nullptr);
         }
         else
-            EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_relax_plan<2, T, StOp<2, T>, RB>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb));
+            EHH_RB_DISPATCH(rb, EHH_LAUNCH_B(lb, (k_relax_plan<2, T, StOp<2, T>, RB>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb));
     } else if (L.fine && cell3d_enabled() && 2 * L.g.N * (int64_t)sizeof(T) < (int64_t(1) << 32)) {
         const int64_t cells = npair;
         // one source group (16 sources per thread) beat two on the 72^3 subdomains:
@@ -2981,15 +2986,15 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
         groups = groups < 1 ? 1 : (groups > nrhs ? nrhs : groups);
         const int rpc = (int)((nrhs + groups - 1) / groups);
         const dim3 gc(nblk(cells), (nrhs + rpc - 1) / rpc);
-        hipLaunchKernelGGL((k_relax_cell3d<T>), gc, 256, 0, s, FineOp<3, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride, rpc);
+        EHH_LAUNCH_B(lb, (k_relax_cell3d<T>), gc, 256, 0, s, FineOp<3, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride, rpc);
     } else {
         if (L.fine)
-            EHH_RB_DISPATCH(rb, hipLaunchKernelGGL((k_relax_plan<3, T, FineOp<3, T>, RB>), gb, 256, 0, s, FineOp<3, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb));
+            EHH_RB_DISPATCH(rb, EHH_LAUNCH_B(lb, (k_relax_plan<3, T, FineOp<3, T>, RB>), gb, 256, 0, s, FineOp<3, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb));
         else if (L.sp.re[colour]) {
 #define EHH_RELAX_ST3D(RB, CH, C)                                                                                 \
     {                                                                                                             \
         const int rpbs = rhs_per_block((npair * 8 + 63) / 64, nrhs, RB, 4096);                                    \
-        hipLaunchKernelGGL((k_relax_st3d<T, RB, CH, C>), dim3(nblk(npair * 8), (nrhs + rpbs - 1) / rpbs), 256, 0,  \
+        EHH_LAUNCH_B(lb, (k_relax_st3d<T, RB, CH, C>), dim3(nblk(npair * 8), (nrhs + rpbs - 1) / rpbs), 256, 0,  \
                            s, L.g, colour, tw, econ, b, ein, eout, nrhs, stride, rpbs, (const C*)L.sp.re[colour], \
                            (const C*)L.sp.im[colour], L.sp.lanes, (T)L.sp.scale);                                 \
     }
@@ -3005,7 +3010,7 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
             else EHH_RELAX_ST3D(8, 8, T)
 #undef EHH_RELAX_ST3D
         } else
-            EHH_RB_DISPATCH(rb3, hipLaunchKernelGGL((k_relax<3, T, StOp<3, T>, RB>), gb3, 256, 0, s, StOp<3, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb3));
+            EHH_RB_DISPATCH(rb3, EHH_LAUNCH_B(lb, (k_relax<3, T, StOp<3, T>, RB>), gb3, 256, 0, s, StOp<3, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb3));
     }
     return hipGetLastError();
 }
@@ -3025,8 +3030,8 @@ hipError_t launch_relax_to64(const LevelDesc<float>& L, double w, int econ, cons
     groups = groups < 1 ? 1 : (groups > nrhs ? nrhs : groups);
     const int rpc = (int)((nrhs + groups - 1) / groups);
     const dim3 gc(nblk(cells), (nrhs + rpc - 1) / rpc);
-    hipLaunchKernelGGL((k_relax_cell2d<float, double>), gc, 256, 0, s, FineOp<2, float>{L.g, L.f}, 1, (float)w,
-                       econ, b, ein, eout, nrhs, stride, rpc);
+    EHH_LAUNCH_B(bytes_relax(L.g, true, nrhs, true, 4, 8, 4.0), (k_relax_cell2d<float, double>), gc, 256, 0, s,
+                 FineOp<2, float>{L.g, L.f}, 1, (float)w, econ, b, ein, eout, nrhs, stride, rpc);
     *done = true;
     return hipGetLastError();
 }
@@ -3047,7 +3052,10 @@ hipError_t launch_relax_restrict(const LevelDesc<T>& L, double w, int econ, cons
     const int64_t npair = (int64_t)(L.g.n[0] / 2) * L.g.n[1] * L.g.n[2];
     const int rpb = rhs_per_block((npair * 8 + 63) / 64, nrhs, 1);
     const dim3 gb(nblk(npair * 8), (nrhs + rpb - 1) / rpb);
-    hipLaunchKernelGGL((k_relax_st2d<T, sizeof(T) == 4, true>), gb, 256, 0, s, L.g, 0, (T)w, econ, (const T*)b,
+    LaunchBytes lb = bytes_relax(L.g, false, nrhs, false, (int)sizeof(T), (int)sizeof(T), (double)sizeof(T));
+    lb.mine += nrhs * 2.0 * sizeof(T) * (double)(gf.N + L.g.N);              // rf read, b written
+    lb.model += nrhs * 2.0 * sizeof(T) * (gf.dim + 1) * (double)(gf.ncell + L.g.ncell);
+    EHH_LAUNCH_B(lb, (k_relax_st2d<T, sizeof(T) == 4, true>), gb, 256, 0, s, L.g, 0, (T)w, econ, (const T*)b,
                        (const T*)nullptr, eout, nrhs, stride, rpb, L.sp.re[0], L.sp.im[0], L.sp.lanes, gf, rf, b);
     return hipGetLastError();
 }
@@ -3080,18 +3088,18 @@ template <typename T>
 hipError_t launch_build_plans(const LevelDesc<T>& L, int colour, T* re, T* im, hipStream_t s) {
     const int64_t lanes = stored_plan_lanes(L.g);
     if (L.g.dim == 2)
-        hipLaunchKernelGGL((k_build_plans<T>), nblk(lanes), 256, 0, s, StOp<2, T>{L.g, L.s}, colour, re, im, lanes);
+        EHH_LAUNCH((k_build_plans<T>), nblk(lanes), 256, 0, s, StOp<2, T>{L.g, L.s}, colour, re, im, lanes);
     else
-        hipLaunchKernelGGL((k_build_rows3d<T>), nblk(lanes * stored_terms(3)), 256, 0, s, StOp<3, T>{L.g, L.s},
+        EHH_LAUNCH((k_build_rows3d<T>), nblk(lanes * stored_terms(3)), 256, 0, s, StOp<3, T>{L.g, L.s},
                            colour, re, im, lanes);
     return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_build_row_plans(const LevelDesc<T>& L, T* re, T* im, hipStream_t s) {
     if (L.g.dim == 2)
-        hipLaunchKernelGGL((k_build_row_plans<T>), nblk(L.g.N), 256, 0, s, StOp<2, T>{L.g, L.s}, re, im);
+        EHH_LAUNCH((k_build_row_plans<T>), nblk(L.g.N), 256, 0, s, StOp<2, T>{L.g, L.s}, re, im);
     else
-        hipLaunchKernelGGL((k_build_row_rows3d<T>), nblk(L.g.N * stored_terms(3)), 256, 0, s, StOp<3, T>{L.g, L.s},
+        EHH_LAUNCH((k_build_row_rows3d<T>), nblk(L.g.N * stored_terms(3)), 256, 0, s, StOp<3, T>{L.g, L.s},
                            re, im);
     return hipGetLastError();
 }
@@ -3104,26 +3112,26 @@ template <typename T>
 hipError_t launch_restrict(const Geo& gf, const Geo& gc, const T* rf, T* rc, int nrhs, hipStream_t s) {
     // (k_restrict2d reads the fine vector through a buffer descriptor: below 4 GiB)
     if (gf.dim == 2 && transfer2d_enabled() && 2 * gf.N * (int64_t)sizeof(T) < (int64_t(1) << 32))
-        hipLaunchKernelGGL((k_restrict2d<T>), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc);
+        EHH_LAUNCH_B(bytes_transfer(gf, gc, nrhs, false, (int)sizeof(T)), (k_restrict2d<T>), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc);
     else if (gf.dim == 2)
-        hipLaunchKernelGGL((k_restrict<2, T>), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc, nrhs);
+        EHH_LAUNCH_B(bytes_transfer(gf, gc, nrhs, false, (int)sizeof(T)), (k_restrict<2, T>), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc, nrhs);
     else if (transfer2d_enabled() && 2 * gf.N < (int64_t(1) << 31))
-        hipLaunchKernelGGL((k_restrict3d<T>), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc);
+        EHH_LAUNCH_B(bytes_transfer(gf, gc, nrhs, false, (int)sizeof(T)), (k_restrict3d<T>), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc);
     else
-        hipLaunchKernelGGL((k_restrict<3, T>), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc, nrhs);
+        EHH_LAUNCH_B(bytes_transfer(gf, gc, nrhs, false, (int)sizeof(T)), (k_restrict<3, T>), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc, nrhs);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_prolong(const Geo& gf, const Geo& gc, const T* ec, T* ef, int nrhs, hipStream_t s) {
     if (gf.dim == 2 && transfer2d_enabled() && 2 * gf.N < (int64_t(1) << 31))
-        hipLaunchKernelGGL((k_prolong2d<T>), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef);
+        EHH_LAUNCH_B(bytes_transfer(gf, gc, nrhs, true, (int)sizeof(T)), (k_prolong2d<T>), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef);
     else if (gf.dim == 2)
-        hipLaunchKernelGGL((k_prolong<2, T>), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef, nrhs);
+        EHH_LAUNCH_B(bytes_transfer(gf, gc, nrhs, true, (int)sizeof(T)), (k_prolong<2, T>), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef, nrhs);
     else if (transfer2d_enabled() && 2 * gf.N < (int64_t(1) << 31))
-        hipLaunchKernelGGL((k_prolong3d<T>), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef);
+        EHH_LAUNCH_B(bytes_transfer(gf, gc, nrhs, true, (int)sizeof(T)), (k_prolong3d<T>), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef);
     else
-        hipLaunchKernelGGL((k_prolong<3, T>), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef, nrhs);
+        EHH_LAUNCH_B(bytes_transfer(gf, gc, nrhs, true, (int)sizeof(T)), (k_prolong<3, T>), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef, nrhs);
     return hipGetLastError();
 }
 
@@ -3135,8 +3143,12 @@ hipError_t launch_residual_restrict(const LevelDesc<T>& L, const Geo& gc, const 
     // solve); a lane walks its sources in turn, so with 32 sources the separate
     // residual and restriction, which spread them over more lanes, are faster
     if (L.g.dim != 2 || L.fine || !L.sp.rre || L.sp.half || nrhs > 4) return hipSuccess;
-    hipLaunchKernelGGL((k_residual_restrict2d<T>), nblk((int64_t)gc.N * 16), 256, 0, s, L.g, gc, e, b, rc, nrhs,
-                       L.sp.rre, L.sp.rim);
+    LaunchBytes lb = bytes_apply(L.g, false, nrhs, true, (int)sizeof(T), (double)sizeof(T));
+    const LaunchBytes rb = bytes_transfer(L.g, gc, nrhs, false, (int)sizeof(T));
+    lb.mine += nrhs * 2.0 * sizeof(T) * ((double)gc.N - (double)L.g.N);   // rc written, r never written
+    lb.model += rb.model - nrhs * 2.0 * sizeof(T) * (L.g.dim + 1) * 2.0 * (double)L.g.ncell;
+    EHH_LAUNCH_B(lb, (k_residual_restrict2d<T>), nblk((int64_t)gc.N * 16), 256, 0, s, L.g, gc, e, b, rc, nrhs,
+                 L.sp.rre, L.sp.rim);
     *done = true;
     return hipGetLastError();
 }
@@ -3169,11 +3181,11 @@ __global__ __launch_bounds__(256) void k_to_half(const float* __restrict__ x, _F
 }
 hipError_t launch_absmax_bits(const float* x, int64_t n, unsigned* out, hipStream_t s) {
     const int64_t nb = std::min<int64_t>(1024, (n + 255) / 256);
-    hipLaunchKernelGGL(k_absmax_bits, (unsigned)(nb < 1 ? 1 : nb), 256, 0, s, x, n, out);
+    EHH_LAUNCH(k_absmax_bits, (unsigned)(nb < 1 ? 1 : nb), 256, 0, s, x, n, out);
     return hipGetLastError();
 }
 hipError_t launch_to_half(const float* x, void* y, int64_t n, float inv_scale, hipStream_t s) {
-    hipLaunchKernelGGL(k_to_half, nblk(n), 256, 0, s, x, (_Float16*)y, n, inv_scale);
+    EHH_LAUNCH(k_to_half, nblk(n), 256, 0, s, x, (_Float16*)y, n, inv_scale);
     return hipGetLastError();
 }
 

@@ -9,6 +9,7 @@
 #include <mutex>
 
 #include "internal.hpp"
+#include "launchlog.hpp"
 #include "ops.hpp"
 
 namespace ehh {
@@ -69,8 +70,8 @@ __global__ void k_media_final(const double* __restrict__ partial, int nb, const 
 
 hipError_t launch_media_check(const double* lam, const double* mu, const double* rho, const double* gam,
                               int64_t ncell, double* partial, int nb, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_media_partial, nb, 256, 0, s, lam, mu, rho, gam, ncell, partial);
-    hipLaunchKernelGGL(k_media_final, 1, 64, 0, s, partial, nb, lam, mu, ncell, out);
+    EHH_LAUNCH(k_media_partial, nb, 256, 0, s, lam, mu, rho, gam, ncell, partial);
+    EHH_LAUNCH(k_media_final, 1, 64, 0, s, partial, nb, lam, mu, ncell, out);
     return hipGetLastError();
 }
 
@@ -118,7 +119,7 @@ __global__ __launch_bounds__(256) void k_fine_coef(FineCoefParams p, const doubl
 hipError_t launch_fine_coef(const FineCoefParams& p, const double* lam, const double* mu, const double* rho,
                             const double* gam_phys, double* out, hipStream_t s) {
     const int64_t nl = (int64_t)p.n_loc[0] * p.n_loc[1] * (p.dim == 3 ? p.n_loc[2] : 1);
-    hipLaunchKernelGGL(k_fine_coef, nblk(nl), 256, 0, s, p, lam, mu, rho, gam_phys, out);
+    EHH_LAUNCH(k_fine_coef, nblk(nl), 256, 0, s, p, lam, mu, rho, gam_phys, out);
     return hipGetLastError();
 }
 
@@ -165,9 +166,9 @@ __global__ __launch_bounds__(256) void k_materialise(Geo g, FineCoef<double> c, 
 hipError_t launch_materialise(const Geo& g, const FineCoef<double>& c, double* st, hipStream_t s) {
     const int64_t n = g.N > g.ncell ? g.N : g.ncell;
     if (g.dim == 2)
-        hipLaunchKernelGGL((k_materialise<2>), nblk(n), 256, 0, s, g, c, st);
+        EHH_LAUNCH((k_materialise<2>), nblk(n), 256, 0, s, g, c, st);
     else
-        hipLaunchKernelGGL((k_materialise<3>), nblk(n), 256, 0, s, g, c, st);
+        EHH_LAUNCH((k_materialise<3>), nblk(n), 256, 0, s, g, c, st);
     return hipGetLastError();
 }
 
@@ -335,14 +336,14 @@ hipError_t launch_galerkin(const Geo& gf, const double* stf, const Geo& gc, doub
     const int64_t nu = gc.off[3];
     if (gf.dim == 2) {
         const StCoef<double> cf = stencil_view<2, double>(gf, stf);
-        hipLaunchKernelGGL((k_galerkin_uu<2>), nblk(nu * St<2>::NUU), 256, 0, s, gf, cf, gc, stc);
-        hipLaunchKernelGGL((k_galerkin_up<2>), nblk(nu * St<2>::NUP), 256, 0, s, gf, cf, gc, stc);
-        hipLaunchKernelGGL((k_galerkin_pp<2>), nblk(gc.ncell), 256, 0, s, gf, cf, gc, stc);
+        EHH_LAUNCH((k_galerkin_uu<2>), nblk(nu * St<2>::NUU), 256, 0, s, gf, cf, gc, stc);
+        EHH_LAUNCH((k_galerkin_up<2>), nblk(nu * St<2>::NUP), 256, 0, s, gf, cf, gc, stc);
+        EHH_LAUNCH((k_galerkin_pp<2>), nblk(gc.ncell), 256, 0, s, gf, cf, gc, stc);
     } else {
         const StCoef<double> cf = stencil_view<3, double>(gf, stf);
-        hipLaunchKernelGGL((k_galerkin_uu<3>), nblk(nu * St<3>::NUU), 256, 0, s, gf, cf, gc, stc);
-        hipLaunchKernelGGL((k_galerkin_up<3>), nblk(nu * St<3>::NUP), 256, 0, s, gf, cf, gc, stc);
-        hipLaunchKernelGGL((k_galerkin_pp<3>), nblk(gc.ncell), 256, 0, s, gf, cf, gc, stc);
+        EHH_LAUNCH((k_galerkin_uu<3>), nblk(nu * St<3>::NUU), 256, 0, s, gf, cf, gc, stc);
+        EHH_LAUNCH((k_galerkin_up<3>), nblk(nu * St<3>::NUP), 256, 0, s, gf, cf, gc, stc);
+        EHH_LAUNCH((k_galerkin_pp<3>), nblk(gc.ncell), 256, 0, s, gf, cf, gc, stc);
     }
     return hipGetLastError();
 }
@@ -409,9 +410,9 @@ hipError_t launch_dense_assemble(const Geo& g, const double* st, double* dense, 
     hipError_t e = hipMemsetAsync(dense, 0, sizeof(double) * 2 * g.N * g.N, s);
     if (e != hipSuccess) return e;
     if (g.dim == 2)
-        hipLaunchKernelGGL((k_dense_assemble<2>), nblk(g.N), 256, 0, s, g, stencil_view<2, double>(g, st), dense);
+        EHH_LAUNCH((k_dense_assemble<2>), nblk(g.N), 256, 0, s, g, stencil_view<2, double>(g, st), dense);
     else
-        hipLaunchKernelGGL((k_dense_assemble<3>), nblk(g.N), 256, 0, s, g, stencil_view<3, double>(g, st), dense);
+        EHH_LAUNCH((k_dense_assemble<3>), nblk(g.N), 256, 0, s, g, stencil_view<3, double>(g, st), dense);
     return hipGetLastError();
 }
 
@@ -702,15 +703,15 @@ hipError_t launch_dense_invert(double* A, int64_t n, int* piv, int* flag, hipStr
         const int kb = (int)std::min<int64_t>(GJ_NB, n - k0);
         const int64_t k1 = k0 + kb;   // first index of the next panel
         if (k0 == 0)
-            hipLaunchKernelGGL(k_diag_inverse, 1, 1024, 0, s, A, n, k0, kb, piv, flag);
+            EHH_LAUNCH(k_diag_inverse, 1, 1024, 0, s, A, n, k0, kb, piv, flag);
         else if ((e = hipStreamWaitEvent(s, ev_diag, 0)) != hipSuccess)
             break;
-        hipLaunchKernelGGL(k_swap_rows, nblk(n), 256, 0, s, A, n, k0, kb, piv);
+        EHH_LAUNCH(k_swap_rows, nblk(n), 256, 0, s, A, n, k0, kb, piv);
         double* AK = A + 2 * k0 * n;           // rows K
         double* AKK = AK + 2 * k0;             // the inverted block W
         double* ACK = A + 2 * k0;              // columns K
         // A[K,J] <- W A[K,J]
-        hipLaunchKernelGGL(k_zgemm_tile, dim3(tiles, 1), 256, 0, s, AK, n, AKK, n, AK, n, (int64_t)kb, n, kb, 1.0, 0,
+        EHH_LAUNCH(k_zgemm_tile, dim3(tiles, 1), 256, 0, s, AK, n, AKK, n, AK, n, (int64_t)kb, n, kb, 1.0, 0,
                            (int64_t)0, (int64_t)0, k0, k1, (int64_t)-1, (int64_t)-1);
         int64_t skip = -1;
         if (k1 < n) {
@@ -719,11 +720,11 @@ hipError_t launch_dense_invert(double* A, int64_t n, int* piv, int* flag, hipStr
             const int kb1 = (int)std::min<int64_t>(GJ_NB, n - k1);
             if ((e = hipEventRecord(ev_row, s)) != hipSuccess || (e = hipStreamWaitEvent(s2, ev_row, 0)) != hipSuccess)
                 break;
-            hipLaunchKernelGGL(k_zgemm_tile, dim3(1, 1), 256, 0, s2, A + 2 * (k1 * n + k1), n, A + 2 * (k1 * n + k0),
+            EHH_LAUNCH(k_zgemm_tile, dim3(1, 1), 256, 0, s2, A + 2 * (k1 * n + k1), n, A + 2 * (k1 * n + k0),
                                n, A + 2 * (k0 * n + k1), n, (int64_t)kb1, (int64_t)kb1, kb, -1.0, 1, (int64_t)0,
                                (int64_t)0, (int64_t)0, (int64_t)0, (int64_t)-1, (int64_t)-1);
             if ((e = hipEventRecord(ev_tile, s2)) != hipSuccess) break;
-            hipLaunchKernelGGL(k_diag_inverse, 1, 1024, 0, s2, A, n, k1, kb1, piv, flag);
+            EHH_LAUNCH(k_diag_inverse, 1, 1024, 0, s2, A, n, k1, kb1, piv, flag);
             if ((e = hipEventRecord(ev_diag, s2)) != hipSuccess) break;
             skip = k1;
         }
@@ -731,10 +732,10 @@ hipError_t launch_dense_invert(double* A, int64_t n, int* piv, int* flag, hipStr
         // that tile: its inversion is then queued before the update fills the
         // device, and A[K1,K] has been read before it is scaled below
         if (k1 < n && (e = hipStreamWaitEvent(s, ev_tile, 0)) != hipSuccess) break;
-        hipLaunchKernelGGL(k_zgemm_tile, dim3(tiles, tiles), 256, 0, s, A, n, ACK, n, AK, n, n, n, kb, -1.0, 1, k0,
+        EHH_LAUNCH(k_zgemm_tile, dim3(tiles, tiles), 256, 0, s, A, n, ACK, n, AK, n, n, n, kb, -1.0, 1, k0,
                            k1, k0, k1, skip, skip);
         // A[I,K] <- -A[I,K] W
-        hipLaunchKernelGGL(k_zgemm_tile, dim3(1, tiles), 256, 0, s, ACK, n, ACK, n, AKK, n, n, (int64_t)kb, kb, -1.0,
+        EHH_LAUNCH(k_zgemm_tile, dim3(1, tiles), 256, 0, s, ACK, n, ACK, n, AKK, n, n, (int64_t)kb, kb, -1.0,
                            0, k0, k1, (int64_t)0, (int64_t)0, (int64_t)-1, (int64_t)-1);
     }
     if (e == hipSuccess) e = hipGetLastError();
@@ -743,7 +744,7 @@ hipError_t launch_dense_invert(double* A, int64_t n, int* piv, int* flag, hipStr
 }
 
 hipError_t launch_permute_columns(const double* X, double* out, int64_t n, const int* qinv, hipStream_t s) {
-    hipLaunchKernelGGL(k_permute_columns, dim3(nblk(n), (unsigned)n), 256, 0, s, X, out, n, qinv);
+    EHH_LAUNCH(k_permute_columns, dim3(nblk(n), (unsigned)n), 256, 0, s, X, out, n, qinv);
     return hipGetLastError();
 }
 
@@ -1282,7 +1283,7 @@ int64_t sym_tiles(int64_t n) {
 }
 hipError_t launch_pack_sym(const double* inv, int64_t n, double* sym, hipStream_t s) {
     const int64_t total = sym_tiles(n) * SY * SY;
-    hipLaunchKernelGGL(k_pack_sym, nblk(total), 256, 0, s, inv, n, sym, total);
+    EHH_LAUNCH(k_pack_sym, nblk(total), 256, 0, s, inv, n, sym, total);
     return hipGetLastError();
 }
 // Workspace of the symmetric apply (partial results; rewritten by every call).
@@ -1332,19 +1333,24 @@ template <typename T>
 hipError_t launch_coarse_apply(const double* inv, const double* sym, int64_t n, const T* r, T* e, int nrhs,
                                double* ws, hipStream_t s) {
     const int W = coarse_width(nrhs);
+    // algorithmic bytes: the inverse (packed half or whole) once, r read, e written
+    const double vec = nrhs * 2.0 * sizeof(T) * (double)n;
+    const LaunchBytes lb_sym{(double)sym_tiles(n) * SY * SY * 16.0 + vec, 16.0 * n * n + vec};
+    const LaunchBytes lb_full{16.0 * n * n + vec, 16.0 * n * n + vec};
+    const LaunchBytes lb_red{vec, vec};
     static const bool sym_on = [] {
         const char* v = std::getenv("EHH_COARSE_SYM");
         return !v || std::atoi(v) != 0;
     }();
     if (W == 0 && sym && ws && sym_on) {   // W == 0: one group of at most 4 right-hand sides
         const int nb = (int)((n + SY - 1) / SY);
-        hipLaunchKernelGGL((k_coarse_apply_sym<T>), dim3((unsigned)sym_tiles(n), 1), 256, 0, s, sym, n, nb, r, nrhs,
+        EHH_LAUNCH_B(lb_sym, (k_coarse_apply_sym<T>), dim3((unsigned)sym_tiles(n), 1), 256, 0, s, sym, n, nb, r, nrhs,
                            ws);
-        hipLaunchKernelGGL((k_sym_reduce<T>), nblk(4 * n * nrhs), 256, 0, s, ws, n, nb, nrhs, e);
+        EHH_LAUNCH_B(lb_red, (k_sym_reduce<T>), nblk(4 * n * nrhs), 256, 0, s, ws, n, nb, nrhs, e);
         return hipGetLastError();
     }
     if (W == 0) {
-        hipLaunchKernelGGL((k_coarse_apply<T>), dim3(nblk(n * 64), (nrhs + 3) / 4), 256, 0, s, inv, n, r, e, nrhs);
+        EHH_LAUNCH_B(lb_full, (k_coarse_apply<T>), dim3(nblk(n * 64), (nrhs + 3) / 4), 256, 0, s, inv, n, r, e, nrhs);
         return hipGetLastError();
     }
     int ks = coarse_ksplit(n, nrhs);
@@ -1355,21 +1361,21 @@ hipError_t launch_coarse_apply(const double* inv, const double* sym, int64_t n, 
     if (W == 32 && coarse_rb_enabled()) {
         const dim3 grid_rb((unsigned)((n + 63) / 64), (unsigned)((nrhs + 31) / 32), (unsigned)ks);
         if (coarse_mfma_enabled())
-            hipLaunchKernelGGL((k_coarse_apply_mfma<T>), grid_rb, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
+            EHH_LAUNCH_B(lb_full, (k_coarse_apply_mfma<T>), grid_rb, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
         else
-            hipLaunchKernelGGL((k_coarse_apply_rb<T>), grid_rb, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
-        if (part) hipLaunchKernelGGL((k_coarse_reduce<T>), nblk(2 * n * nrhs), 256, 0, s, part, ks, n, nrhs, e);
+            EHH_LAUNCH_B(lb_full, (k_coarse_apply_rb<T>), grid_rb, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
+        if (part) EHH_LAUNCH_B(lb_red, (k_coarse_reduce<T>), nblk(2 * n * nrhs), 256, 0, s, part, ks, n, nrhs, e);
         return hipGetLastError();
     }
     const unsigned rows = (unsigned)((n + 512 / W - 1) / (512 / W));
     const dim3 grid(rows, (unsigned)((nrhs + W - 1) / W), (unsigned)ks);
     if (W == 8)
-        hipLaunchKernelGGL((k_coarse_apply_multi<T, 8>), grid, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
+        EHH_LAUNCH_B(lb_full, (k_coarse_apply_multi<T, 8>), grid, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
     else if (W == 16)
-        hipLaunchKernelGGL((k_coarse_apply_multi<T, 16>), grid, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
+        EHH_LAUNCH_B(lb_full, (k_coarse_apply_multi<T, 16>), grid, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
     else
-        hipLaunchKernelGGL((k_coarse_apply_multi<T, 32>), grid, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
-    if (part) hipLaunchKernelGGL((k_coarse_reduce<T>), nblk(2 * n * nrhs), 256, 0, s, part, ks, n, nrhs, e);
+        EHH_LAUNCH_B(lb_full, (k_coarse_apply_multi<T, 32>), grid, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
+    if (part) EHH_LAUNCH_B(lb_red, (k_coarse_reduce<T>), nblk(2 * n * nrhs), 256, 0, s, part, ks, n, nrhs, e);
     return hipGetLastError();
 }
 // Scratch of the coarsest solve for callers that cannot allocate
@@ -1418,7 +1424,7 @@ __global__ void k_zero_words(uint32_t* __restrict__ p, int64_t n) {
 // Zero fill by a kernel (not a memset node, so it may sit inside a captured graph).
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
     const int64_t n = (int64_t)(bytes / 4);
-    hipLaunchKernelGGL(k_zero_words, nblk(n), 256, 0, s, (uint32_t*)p, n);
+    EHH_LAUNCH_B(bytes_plain((double)bytes), k_zero_words, nblk(n), 256, 0, s, (uint32_t*)p, n);
     return hipGetLastError();
 }
 
@@ -1431,11 +1437,11 @@ __global__ void k_cast_f2d(const float* __restrict__ in, double* __restrict__ ou
     if (i < n) out[i] = (double)in[i];
 }
 hipError_t launch_cast_d2f(const double* in, float* out, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_cast_d2f, nblk(n), 256, 0, s, in, out, n);
+    EHH_LAUNCH_B(bytes_plain(12.0 * n), k_cast_d2f, nblk(n), 256, 0, s, in, out, n);
     return hipGetLastError();
 }
 hipError_t launch_cast_f2d(const float* in, double* out, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_cast_f2d, nblk(n), 256, 0, s, in, out, n);
+    EHH_LAUNCH_B(bytes_plain(12.0 * n), k_cast_f2d, nblk(n), 256, 0, s, in, out, n);
     return hipGetLastError();
 }
 

@@ -45,6 +45,11 @@ class ehh_stats_t(ctypes.Structure):
                 ("rel_res_true", ctypes.c_double), ("conv_factor", ctypes.c_double)]
 
 
+class ehh_kernel_time_t(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_char * 128), ("launches", ctypes.c_int32), ("avg_us", ctypes.c_double),
+                ("avg_us_warm", ctypes.c_double), ("bytes", ctypes.c_double), ("bytes_model", ctypes.c_double)]
+
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int32
 _SIGS = {
@@ -72,6 +77,8 @@ _SIGS = {
     "ehh_level_prolong": (_I, [_P, _I, _I, _P, _P, _I, _P]),
     "ehh_coarse_solve": (_I, [_P, _I, _P, _P, _I, _P]),
     "ehh_coarse_solve_noalloc": (_I, [_P, _I, _P, _P, _I, _P]),
+    "ehh_profile_precondition": (_I, [_P, _P, _P, _I, _I, _P, ctypes.c_int64, ctypes.POINTER(ehh_kernel_time_t),
+                                      _I, ctypes.POINTER(_I), _P]),
     "ehh_last_error": (ctypes.c_char_p, []),
 }
 
@@ -322,6 +329,22 @@ class Solver:
         _check(st, allow=(EHH_OK,) if raise_on_fail else (EHH_OK, EHH_NOT_CONVERGED))
         return st, [dict(status=s.status, iters=s.iters, rel_res_est=s.rel_res_est,
                          rel_res_true=s.rel_res_true, conv_factor=s.conv_factor) for s in stats]
+
+    def profile_precondition(self, v, z, reps=5, evict=None, stream=None, cap=256):
+        """Per-kernel timing of one preconditioner application (ehh_profile_precondition):
+        a list of dicts (kernel, launches, avg_us, avg_us_warm, bytes, bytes_model) in order of
+        first launch.  evict: a device tensor written before every replayed launch."""
+        nrhs = self._global(outputs=("z",), v=v, z=z)
+        if evict is not None and (not evict.is_cuda or not evict.is_contiguous()):
+            raise ValueError("evict must be a contiguous device tensor")
+        nbytes = 0 if evict is None else (evict.numel() * evict.element_size()) // 4 * 4
+        out = (ehh_kernel_time_t * cap)()
+        cnt = _I()
+        _check(lib().ehh_profile_precondition(self.handle, _ptr(v), _ptr(z), nrhs, int(reps),
+                                              _ptr(evict) if evict is not None else None, nbytes, out, cap,
+                                              ctypes.byref(cnt), _stream(stream)))
+        return [dict(kernel=o.kernel.decode(), launches=o.launches, avg_us=o.avg_us, avg_us_warm=o.avg_us_warm,
+                     bytes=o.bytes, bytes_model=o.bytes_model) for o in out[:cnt.value]]
 
     def media_gradient(self, y, x, grad_lambda, grad_mu, grad_rho, accumulate=False, stream=None):
         import torch

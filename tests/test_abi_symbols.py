@@ -45,7 +45,7 @@ def test_struct_layouts_match_the_c_compiler(tmp_path):
     from paper_1806_11277_amd import ehh
     if shutil.which("gcc") is None:
         pytest.skip("gcc not available")
-    structs = [ehh.ehh_problem_t, ehh.ehh_options_t, ehh.ehh_stats_t]
+    structs = [ehh.ehh_problem_t, ehh.ehh_options_t, ehh.ehh_stats_t, ehh.ehh_kernel_time_t]
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ehh.h"', 'int main(void) {']
     expect = []
     for S in structs:
