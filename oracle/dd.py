@@ -1,4 +1,5 @@
-"""Overlapping domain decomposition around the multigrid cycle (oracle, DD-MG).
+"""Overlapping domain decomposition around the multigrid cycle (oracle, DD-MG;
+DD-MG-DD when the subdomain hierarchies solve their coarsest level by DD too).
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
@@ -144,7 +145,7 @@ class DDPreconditioner:
     """DD-MG: one multigrid cycle of the local shifted operator per subdomain."""
 
     def __init__(self, problem: disc.Problem, parts, overlap, pad, levels, damping,
-                 economic=False, cycle=1, colours=1, abl_max=1.0):
+                 economic=False, cycle=1, colours=1, abl_max=1.0, coarse_dd=None, cycle_level=0):
         n = problem.n
         self.n = n
         self.problem = problem
@@ -155,7 +156,8 @@ class DDPreconditioner:
         cnt = np.zeros(problem.size)
         for sub in self.subs:
             A_loc = local_operator(problem, sub, abl_max)
-            self.hier.append(mg.Hierarchy(A_loc, sub.nloc, levels, damping, economic, cycle))
+            self.hier.append(mg.Hierarchy(A_loc, sub.nloc, levels, damping, economic, cycle,
+                                          cycle_level=cycle_level, coarse_dd=coarse_dd))
             m = local_to_global(n, sub)
             self.maps.append(m)
             cnt[m[m >= 0]] += 1

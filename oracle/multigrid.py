@@ -18,6 +18,10 @@ faces takes 1/2 of each) and linearly along each tangential axis (weights 3/4
 for the nearer coarse row, 1/4 for the other, zero beyond the wall); the
 pressure is interpolated piecewise constantly.
 
+MG-DD (section 4): the coarsest level may instead be solved by one sweep of
+domain decomposition over its own subdomains (CoarseDD); with top-level DD
+around the cycle (oracle.dd) this is DD-MG-DD.
+
 Red-black reading ("simultaneously sweep over all the red cells"): within one
 colour every cell's correction is computed from the residual at the start of
 that half-sweep; cells of one colour share no unknown, so the corrections are
@@ -159,11 +163,59 @@ def vanka_half_sweep(A, B, dofs, colour, c, b, e, w):
 
 
 # ------------------------------------------------------------------------- hierarchy
+class CoarseDD:
+    """Domain decomposition as the coarsest-grid solver (MG-DD, section 4).
+
+    Reading: the coarsest grid is split into overlapping subdomains as the fine
+    grid is (core n/parts per axis, the overlap split around each cut, no
+    padding); the local operator of a subdomain is the coarsest Galerkin
+    operator restricted to the unknowns of its extent (the shift already makes
+    the coarse system local, so no absorbing layer is added), solved exactly.
+    One application from the guess z is one sweep of Algorithm 2 over the
+    colours (each colour from the residual b - A_c z left by the previous ones),
+    or with one colour the corrections of all subdomains from the same residual,
+    averaged over the subdomains that own an unknown."""
+
+    def __init__(self, A, n, parts, overlap, colours=0):
+        from . import dd as ddm
+        self.A = sp.csr_matrix(A)
+        self.subs = ddm.make_subdomains(n, parts, overlap, 0)
+        self.colours = colours
+        self.idx, self.lu = [], []
+        cnt = np.zeros(self.A.shape[0])
+        for sub in self.subs:
+            m = ddm.local_to_global(n, sub)
+            g = m[m >= 0]
+            self.idx.append(g)
+            self.lu.append(spla.splu(sp.csc_matrix(self.A[g][:, g])))
+            cnt[g] += 1
+        if np.any(cnt == 0):
+            raise ValueError("coarse subdomains do not cover every unknown")
+        self.weight = 1.0 / cnt
+
+    def solve(self, b, z=None):
+        b = np.asarray(b, dtype=np.complex128)
+        z = np.zeros_like(b) if z is None else np.asarray(z, dtype=np.complex128).copy()
+        if self.colours == 1:
+            r = b - self.A @ z
+            for g, lu in zip(self.idx, self.lu):
+                z[g] += self.weight[g] * lu.solve(r[g])
+            return z
+        for c in sorted(set(s.colour for s in self.subs)):
+            r = b - self.A @ z
+            for sub, g, lu in zip(self.subs, self.idx, self.lu):
+                if sub.colour == c:
+                    z[g] += lu.solve(r[g])
+        return z
+
+
 class Hierarchy:
-    """Galerkin hierarchy of a shifted operator A0 on grid n."""
+    """Galerkin hierarchy of a shifted operator A0 on grid n.  coarse_dd =
+    (parts, overlap, colours) solves the coarsest level by domain
+    decomposition (CoarseDD) instead of exactly."""
 
     def __init__(self, A0, n, levels, damping: Sequence[float], economic=False,
-                 cycle=1, nu1=1, nu2=1, cycle_level=0):
+                 cycle=1, nu1=1, nu2=1, cycle_level=0, coarse_dd=None):
         self.n = [tuple(n)]
         self.A = [sp.csr_matrix(A0)]
         self.P = []
@@ -184,7 +236,12 @@ class Hierarchy:
         self.blocks = []
         for l in range(levels - 1):
             self.blocks.append(vanka_blocks(self.A[l], self.n[l], economic))
-        self.coarse_lu = spla.splu(sp.csc_matrix(self.A[-1]))
+        self.coarse_dd = None
+        if coarse_dd is not None and any(v > 1 for v in coarse_dd[0]):
+            self.coarse_dd = CoarseDD(self.A[-1], self.n[-1], coarse_dd[0], coarse_dd[1], coarse_dd[2])
+            self.coarse_lu = None
+        else:
+            self.coarse_lu = spla.splu(sp.csc_matrix(self.A[-1]))
 
     def relax(self, l, b, e, c):
         B, dofs, colour = self.blocks[l]
@@ -193,6 +250,8 @@ class Hierarchy:
     def cycle(self, b, l=0, e=None):
         """Algorithm 1 applied recursively; e = initial guess (zero if None)."""
         if l == self.levels - 1:
+            if self.coarse_dd is not None:   # continues from the guess e (a second W call)
+                return self.coarse_dd.solve(b, e)
             return self.coarse_lu.solve(np.asarray(b, dtype=np.complex128))
         e = np.zeros_like(b, dtype=np.complex128) if e is None else e.astype(np.complex128)
         for _ in range(self.nu1):
@@ -210,6 +269,6 @@ class Hierarchy:
 
 
 def build_hierarchy(problem: disc.Problem, levels, damping, economic=False, cycle=1,
-                    nu1=1, nu2=1, cycle_level=0):
+                    nu1=1, nu2=1, cycle_level=0, coarse_dd=None):
     return Hierarchy(problem.matrix(shifted=True), problem.n, levels, damping,
-                     economic, cycle, nu1, nu2, cycle_level)
+                     economic, cycle, nu1, nu2, cycle_level, coarse_dd)

@@ -42,17 +42,26 @@ def oracle_problem(w):
                         w.atten0, shift=w.shift)
 
 
+def coarse_dd_of(w):
+    """(parts, overlap, colours) of the workload's coarsest-level DD, or None."""
+    parts = tuple(w.coarse_dd_parts[:w.dim])
+    if all(v == 1 for v in parts):
+        return None
+    return parts, w.coarse_dd_overlap, w.coarse_dd_colors
+
+
 def oracle_hierarchy(w, pb=None):
     pb = pb or oracle_problem(w)
     return mg.build_hierarchy(pb, w.levels, list(w.damping), economic=(w.vanka == 0), cycle=w.cycle,
-                              nu1=w.nu1, nu2=w.nu2, cycle_level=w.cycle_level)
+                              nu1=w.nu1, nu2=w.nu2, cycle_level=w.cycle_level, coarse_dd=coarse_dd_of(w))
 
 
 def oracle_dd(w, pb=None):
     pb = pb or oracle_problem(w)
     return ddm.DDPreconditioner(pb, w.dd_parts[:w.dim], w.dd_overlap, w.dd_pad, w.levels,
                                 list(w.damping), economic=(w.vanka == 0), cycle=w.cycle,
-                                colours=(1 if w.dd_colors == 1 else 2 ** w.dim), abl_max=w.abl_max)
+                                colours=(1 if w.dd_colors == 1 else 2 ** w.dim), abl_max=w.abl_max,
+                                coarse_dd=coarse_dd_of(w), cycle_level=w.cycle_level)
 
 
 def rand_cvec(N, nrhs, seed):

@@ -488,3 +488,117 @@ def test_convergence_factor_of_a_geometric_history():
     hist = [1.0, 3.0, 0.5, 2.0, 0.9] + [0.7 * rho ** k for k in range(40)]
     assert abs(krylov.convergence_factor(hist, warmup=5) - rho) < 1e-13
     assert np.isnan(krylov.convergence_factor([1.0, 0.5], warmup=5))
+
+
+# ------------------------------------------------------ DD as the coarsest solver (MG-DD)
+def _coarse_problem(n, seed):
+    lam, mu, rho, gam = _hetero(n, seed)
+    A = disc.assemble(n, 1.0, 0.8, lam, mu, rho, gam, 0.5)
+    H = mg.Hierarchy(A, n, 3, [0.75, 0.5])
+    return H.A[-1], H.n[-1]
+
+
+def test_coarse_dd_with_one_subdomain_is_the_exact_solve():
+    Ac, nc = _coarse_problem((32, 32), 40)
+    cdd = mg.CoarseDD(Ac, nc, (1, 1), 2, 0)
+    rng = np.random.default_rng(41)
+    b = rng.standard_normal(Ac.shape[0]) + 1j * rng.standard_normal(Ac.shape[0])
+    x = spla.spsolve(sp.csc_matrix(Ac), b)
+    assert np.linalg.norm(cdd.solve(b) - x) <= 1e-12 * np.linalg.norm(x)
+
+
+class _AdditiveCoarse(mg.CoarseDD):
+    """Planted mistake: every colour from the same residual."""
+
+    def solve(self, b, z=None):
+        z = np.zeros_like(b, dtype=complex)
+        r = b - self.A @ z
+        for g, lu in zip(self.idx, self.lu):
+            z[g] += lu.solve(r[g])
+        return z
+
+
+@pytest.mark.parametrize("n,parts", [((32, 32), (2, 2)), ((48, 16), (3, 1)), ((16, 16, 16), (2, 2, 1))])
+def test_coarse_dd_colour_leaves_no_residual_on_its_rows(n, parts):
+    """Algorithm 2 on the coarsest operator with restricted local operators and
+    exact local solves: after the last colour, b - A_c z vanishes on every row of
+    that colour's subdomains that couples only inside the extent (there the
+    restricted local row is the global row); the additive variant leaves
+    residual there."""
+    Ac, nc = _coarse_problem(n, 42)
+    cdd = mg.CoarseDD(Ac, nc, parts, 2, 0)
+    rng = np.random.default_rng(43)
+    b = rng.standard_normal(Ac.shape[0]) + 1j * rng.standard_normal(Ac.shape[0])
+
+    def worst(solver):
+        z = solver.solve(b)
+        res = b - Ac @ z
+        A = sp.csr_matrix(Ac)
+        last = max(s_.colour for s_ in solver.subs)
+        out, count = 0.0, 0
+        for sub, g in zip(solver.subs, solver.idx):
+            if sub.colour != last:
+                continue
+            inside = np.zeros(A.shape[0], bool)
+            inside[g] = True
+            for r in g:
+                row = A.getrow(r)
+                if np.all(inside[row.indices[np.abs(row.data) > 0]]):
+                    out = max(out, abs(res[r]))
+                    count += 1
+        return out / np.linalg.norm(b), count
+
+    w, count = worst(cdd)
+    assert count > 0 and w <= 1e-12
+    wb, _ = worst(_AdditiveCoarse(Ac, nc, parts, 2, 0))
+    assert wb > 1e-4
+
+
+def test_coarse_dd_one_colour_averages_the_corrections():
+    """One colour: z = sum_i W E_i A_i^{-1} E_i^T b with W the inverse owner
+    count, written out densely; its weights sum to one on every unknown."""
+    Ac, nc = _coarse_problem((32, 32), 44)
+    cdd = mg.CoarseDD(Ac, nc, (2, 2), 2, 1)
+    rng = np.random.default_rng(45)
+    b = rng.standard_normal(Ac.shape[0]) + 1j * rng.standard_normal(Ac.shape[0])
+    Ad = Ac.toarray()
+    want = np.zeros_like(b)
+    cnt = np.zeros(Ac.shape[0])
+    for g in cdd.idx:
+        cnt[g] += 1
+    for g in cdd.idx:
+        want[g] += np.linalg.solve(Ad[np.ix_(g, g)], b[g]) / cnt[g]
+    assert np.linalg.norm(cdd.solve(b) - want) <= 1e-12 * np.linalg.norm(want)
+    assert cnt.max() == 4 and cnt.min() == 1
+
+
+def test_mg_dd_w_cycle_continues_the_coarse_solve():
+    """With an inexact coarsest solve the W-cycle's second call into the
+    coarsest level continues from the first call's result: z + DD(b - A_c z)."""
+    Ac, nc = _coarse_problem((32, 32), 46)
+    cdd = mg.CoarseDD(Ac, nc, (2, 2), 2, 0)
+    rng = np.random.default_rng(47)
+    b = rng.standard_normal(Ac.shape[0]) + 1j * rng.standard_normal(Ac.shape[0])
+    z1 = cdd.solve(b)
+    z2 = cdd.solve(b, z1)
+    assert np.linalg.norm(z2 - (z1 + cdd.solve(b - Ac @ z1))) <= 1e-12 * np.linalg.norm(z2)
+    x = spla.spsolve(sp.csc_matrix(Ac), b)
+    assert np.linalg.norm(z2 - x) < np.linalg.norm(z1 - x)
+
+
+def test_mg_dd_preconditioned_fgmres_converges_like_mg_exact():
+    """MG-DD (section 4, Table 5): FGMRES with 3-level cycles whose coarsest
+    level is solved by 2 x 2 overlapping subdomains converges to 1e-8, within a
+    few iterations of the exact coarsest solve."""
+    n = (64, 64)
+    lam, mu, rho, gam = _hetero(n, 48, abl=8)
+    A = disc.assemble(n, 1.0, 0.6, lam, mu, rho, gam, 0.0)
+    As = disc.assemble(n, 1.0, 0.6, lam, mu, rho, gam, 0.5)
+    b = disc.point_source_vector(n, [(0, (32, 6), 1.0)])
+    its = {}
+    for key, cdd in (("exact", None), ("dd", ((2, 2), 2, 0))):
+        H = mg.Hierarchy(As, n, 3, [0.75, 0.5], cycle=2, coarse_dd=cdd)
+        x, st = krylov.fgmres(lambda v: A @ v, H.cycle, b, tol=1e-8, restart=5, maxit=300)
+        assert st["converged"] and st["rel_res_true"] <= 1e-8
+        its[key] = st["iters"]
+    assert its["dd"] <= 1.5 * its["exact"] + 5, its

@@ -49,6 +49,9 @@ class Workload:
     dd_pad: int = 0
     dd_colors: int = 1
     coarse_bits: int = 32           # 16: FP16 stored rows on 3D Galerkin levels (complex64 cycle)
+    coarse_dd_parts: Tuple[int, ...] = (1, 1, 1)   # subdomains of the coarsest level (MG-DD); 1s: exact
+    coarse_dd_overlap: int = 2
+    coarse_dd_colors: int = 0       # 0: Algorithm 2 over the coarsest level's subdomains, 1: one colour
     sources_fn: Callable[["Workload"], List[Source]] = None
     receivers_fn: Callable[["Workload"], List[Tuple[int, Tuple[int, ...]]]] = None
     true_media_fn: Callable[[], dict] = None
