@@ -48,7 +48,9 @@ def run_gpu(w, steps, warmup, tol):
     opts = dict(levels=w.levels, cycle=w.cycle, cycle_level=w.cycle_level, nu1=w.nu1, nu2=w.nu2, vanka=w.vanka,
                 precond_bits=w.precond_bits, restart=w.restart, dd_parts=w.dd_parts,
                 dd_overlap=w.dd_overlap, dd_pad=w.dd_pad, dd_colors=w.dd_colors, damping=w.damping,
-                abl_max=w.abl_max, atten0=w.atten0, coarse_bits=w.coarse_bits)
+                abl_max=w.abl_max, atten0=w.atten0, coarse_bits=w.coarse_bits,
+                coarse_dd_parts=w.coarse_dd_parts, coarse_dd_overlap=w.coarse_dd_overlap,
+                coarse_dd_colors=w.coarse_dd_colors, damping_p=w.damping_p)
 
     def make():
         return ehh.Solver(w.dim, w.n, w.h, w.omega, w.shift, w.abl_cells, lam, mu, rho, **opts)

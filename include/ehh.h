@@ -106,6 +106,21 @@ typedef struct {
                                rows of the 3D Galerkin levels are kept in FP16, scaled by
                                a power of two per level, and summed in FP32 (the paper's
                                half-precision storage of coarse data, section 3) */
+    int32_t coarse_dd_parts[3];  /* DD as the coarsest-level solver (MG-DD, section 4;
+                               with dd_parts > 1 as well: DD-MG-DD): subdomains per axis of
+                               every hierarchy's coarsest level; all 1 (default) = the
+                               exact solve by a dense inverse.  Each subdomain's operator
+                               is the coarsest Galerkin operator restricted to its cells
+                               and their interior faces, inverted exactly (FP64); one
+                               coarsest solve is one sweep over them */
+    int32_t coarse_dd_overlap;   /* overlap of those subdomains [coarsest cells] (default 2) */
+    int32_t coarse_dd_colors;    /* 0 (default): Algorithm 2 over the coarsest level's
+                               subdomains (each colour from the residual left by the
+                               previous ones); 1: one colour, corrections averaged */
+    double  damping_p[EHH_MAX_LEVELS];  /* Vanka damping of the pressure row of a cell
+                               block per level (component-dependent damping (w_u, w_p),
+                               section 5.2; damping[] then damps the displacement rows);
+                               0 (default) = damping[l] */
 } ehh_options_t;
 
 typedef struct {
@@ -242,7 +257,8 @@ int32_t ehh_level_restrict(ehh_handle_t h, int32_t sub, int32_t level, const voi
 /* e += P ec, ec on level + 1. */
 int32_t ehh_level_prolong(ehh_handle_t h, int32_t sub, int32_t level, const void* ec,
                           void* e, int32_t nrhs, void* stream);
-/* e = A_coarsest^{-1} r (FP64 dense inverse; r, e in the cycle precision). */
+/* e = A_coarsest^{-1} r (FP64 dense inverse; r, e in the cycle precision), or
+ * with coarse_dd_parts one sweep of the coarsest-level DD from e = 0 (FP64). */
 int32_t ehh_coarse_solve(ehh_handle_t h, int32_t sub, const void* r, void* e,
                          int32_t nrhs, void* stream);
 
@@ -289,7 +305,8 @@ int32_t ehh_profile_precondition(ehh_handle_t h, const double* v, double* z, int
  * that array and race.  The handle's device must be current.  r, e: (device)
  * as for ehh_coarse_solve.  Returns EHH_ERR_UNSUPPORTED (nothing launched)
  * when the coarsest size and nrhs need more partial sums than the array holds
- * (e.g. 3,008 unknowns: up to 32 right-hand sides fit). */
+ * (e.g. 3,008 unknowns: up to 32 right-hand sides fit), and for a coarsest
+ * level solved by DD (coarse_dd_parts), whose workspaces it cannot allocate. */
 int32_t ehh_coarse_solve_noalloc(ehh_handle_t h, int32_t sub, const void* r, void* e,
                                  int32_t nrhs, void* stream);
 

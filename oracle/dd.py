@@ -145,7 +145,7 @@ class DDPreconditioner:
     """DD-MG: one multigrid cycle of the local shifted operator per subdomain."""
 
     def __init__(self, problem: disc.Problem, parts, overlap, pad, levels, damping,
-                 economic=False, cycle=1, colours=1, abl_max=1.0, coarse_dd=None, cycle_level=0):
+                 economic=False, cycle=1, colours=1, abl_max=1.0, coarse_dd=None, cycle_level=0, damping_p=None):
         n = problem.n
         self.n = n
         self.problem = problem
@@ -157,7 +157,7 @@ class DDPreconditioner:
         for sub in self.subs:
             A_loc = local_operator(problem, sub, abl_max)
             self.hier.append(mg.Hierarchy(A_loc, sub.nloc, levels, damping, economic, cycle,
-                                          cycle_level=cycle_level, coarse_dd=coarse_dd))
+                                          cycle_level=cycle_level, coarse_dd=coarse_dd, damping_p=damping_p))
             m = local_to_global(n, sub)
             self.maps.append(m)
             cnt[m[m >= 0]] += 1

@@ -148,17 +148,22 @@ def vanka_blocks(A, n, economic=False):
     return B, dofs, colour
 
 
-def vanka_half_sweep(A, B, dofs, colour, c, b, e, w):
+def vanka_half_sweep(A, B, dofs, colour, c, b, e, w, wp=None):
     """One damped red-black half-sweep on colour c (Jacobi within the colour):
-    r = b - A e; for every cell K of colour c, e_K += w * B_K^{-1} r_K."""
+    r = b - A e; for every cell K of colour c, e_K += W B_K^{-1} r_K with
+    W = diag(w, .., w, wp): the component-dependent damping of section 5.2
+    (w on the displacement rows, wp on the pressure row; wp = w by default)."""
     r = b - A @ e
     sel = np.nonzero(colour == c)[0]
     D = dofs[sel]
     rK = np.where(D >= 0, r[np.maximum(D, 0)], 0.0)
     cK = np.linalg.solve(B[sel], rK[..., None])[..., 0]
+    W = np.full(D.shape[1], float(w))
+    W[-1] = float(w if wp is None else wp)
+    cK = cK * W
     e = e.copy()
     ok = D >= 0
-    e[D[ok]] += w * cK[ok]
+    e[D[ok]] += cK[ok]
     return e
 
 
@@ -215,7 +220,7 @@ class Hierarchy:
     decomposition (CoarseDD) instead of exactly."""
 
     def __init__(self, A0, n, levels, damping: Sequence[float], economic=False,
-                 cycle=1, nu1=1, nu2=1, cycle_level=0, coarse_dd=None):
+                 cycle=1, nu1=1, nu2=1, cycle_level=0, coarse_dd=None, damping_p=None):
         self.n = [tuple(n)]
         self.A = [sp.csr_matrix(A0)]
         self.P = []
@@ -229,6 +234,7 @@ class Hierarchy:
             self.n.append(tuple(v // 2 for v in nl))
         self.levels = levels
         self.damping = list(damping)
+        self.damping_p = list(damping_p) if damping_p is not None else list(damping)
         self.economic = economic
         self.cycle_index = cycle
         self.cycle_level = cycle_level
@@ -245,7 +251,7 @@ class Hierarchy:
 
     def relax(self, l, b, e, c):
         B, dofs, colour = self.blocks[l]
-        return vanka_half_sweep(self.A[l], B, dofs, colour, c, b, e, self.damping[l])
+        return vanka_half_sweep(self.A[l], B, dofs, colour, c, b, e, self.damping[l], self.damping_p[l])
 
     def cycle(self, b, l=0, e=None):
         """Algorithm 1 applied recursively; e = initial guess (zero if None)."""
@@ -269,6 +275,6 @@ class Hierarchy:
 
 
 def build_hierarchy(problem: disc.Problem, levels, damping, economic=False, cycle=1,
-                    nu1=1, nu2=1, cycle_level=0, coarse_dd=None):
+                    nu1=1, nu2=1, cycle_level=0, coarse_dd=None, damping_p=None):
     return Hierarchy(problem.matrix(shifted=True), problem.n, levels, damping,
-                     economic, cycle, nu1, nu2, cycle_level, coarse_dd)
+                     economic, cycle, nu1, nu2, cycle_level, coarse_dd, damping_p)

@@ -43,7 +43,9 @@ class SolveSpec:
 def spec_for_workload(w, mu_bar=0.0, rho_bar=0.0, tol=None, maxit=None, **solver_over) -> SolveSpec:
     kw = dict(levels=w.levels, cycle=w.cycle, cycle_level=w.cycle_level, nu1=w.nu1, nu2=w.nu2, vanka=w.vanka,
               precond_bits=w.precond_bits, restart=w.restart, dd_parts=w.dd_parts,
-              dd_overlap=w.dd_overlap, dd_pad=w.dd_pad, dd_colors=w.dd_colors, damping=w.damping)
+              dd_overlap=w.dd_overlap, dd_pad=w.dd_pad, dd_colors=w.dd_colors, damping=w.damping,
+              coarse_dd_parts=w.coarse_dd_parts, coarse_dd_overlap=w.coarse_dd_overlap,
+              coarse_dd_colors=w.coarse_dd_colors, damping_p=w.damping_p)
     kw.update(solver_over)
     return SolveSpec(dim=w.dim, n=tuple(w.n), h=w.h, omega=w.omega, shift=w.shift,
                      abl_cells=tuple(w.abl_cells), abl_max=w.abl_max, atten0=w.atten0,

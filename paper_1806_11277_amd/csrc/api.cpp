@@ -189,7 +189,8 @@ struct PhaseLog {
 struct Level {
     Geo g{};
     bool fine = false;
-    double damping = 0.0;
+    double damping = 0.0;       // Vanka damping of the displacement rows
+    double damping_p = 0.0;     // and of the pressure row
     double* coef64 = nullptr;   // fine: mu, dinv, rho, gam planes; coarse: stencil
     float* coef32 = nullptr;
     void* b = nullptr;          // right-hand side of this level (levels >= 1)
@@ -205,6 +206,29 @@ struct Level {
     float sp_scale = 1.0f;
 };
 
+// DD as the coarsest-grid solver: the boxes (subdomains) of a hierarchy's
+// coarsest level, ordered by colour, each with the dense inverse of the
+// coarsest operator restricted to it.
+struct CoarseBox {
+    int lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
+    int colour = 0;
+    Geo g{};                    // the box's own grid
+    double* inv = nullptr;
+    double* sym = nullptr;
+    int64_t base = 0;           // first local unknown in the box numbering
+};
+struct CoarseDD {
+    std::vector<CoarseBox> box;
+    std::vector<int> col_begin;  // box index where colour c starts (ncol + 1 entries)
+    int* idx = nullptr;          // device: map, bsub, bn (int) in one block
+    int64_t* bbase = nullptr;    // device: first local unknown of each box
+    double* wgt = nullptr;       // device: inverse owner count per coarsest unknown (one colour)
+    int64_t ntot = 0;            // local unknowns of all boxes
+    bool active() const { return !box.empty(); }
+    // idx holds map (ntot), bsub (ntot) and bn (one per box) back to back
+    BoxMap view() const { return BoxMap{idx, idx + ntot, bbase, idx + 2 * ntot}; }
+};
+
 struct Sub {
     int origin[3] = {0, 0, 0}, lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
     int pad_lo[3] = {0, 0, 0}, pad_hi[3] = {0, 0, 0}, nloc[3] = {1, 1, 1};
@@ -214,6 +238,10 @@ struct Sub {
     double* sym = nullptr;      // its lower 64 x 64 tiles, packed (few right-hand sides)
     void* r0 = nullptr;         // local level-0 right-hand side / correction (DD or FP32)
     void* e0 = nullptr;
+    CoarseDD cdd;               // DD as the coarsest solver (empty: dense inverse)
+    // its FP64 workspaces: right-hand side and iterate (complex64 cycle), residual,
+    // and the boxes' local right-hand sides and corrections
+    double *cdd_r = nullptr, *cdd_e = nullptr, *cdd_t = nullptr, *cdd_lr = nullptr, *cdd_le = nullptr;
 };
 
 }  // namespace
@@ -397,11 +425,29 @@ int32_t ensure_ws(ehh_ctx* c, int nrhs) {
         const size_t b0 = es * 2 * (size_t)S.lev[0].g.N * nrhs;
         CHK(c->alloc(&S.r0, b0));
         CHK(c->alloc(&S.e0, b0));
+        for (double** p : {&S.cdd_r, &S.cdd_e, &S.cdd_t, &S.cdd_lr, &S.cdd_le}) {
+            c->release(*p);
+            *p = nullptr;
+        }
+        if (S.cdd.active()) {
+            const size_t bc = sizeof(double) * 2 * (size_t)S.lev.back().g.N * nrhs;
+            const size_t bl = sizeof(double) * 2 * (size_t)S.cdd.ntot * nrhs;
+            CHK(c->alloc((void**)&S.cdd_r, bc));
+            CHK(c->alloc((void**)&S.cdd_e, bc));
+            CHK(c->alloc((void**)&S.cdd_t, bc));
+            CHK(c->alloc((void**)&S.cdd_lr, bl));
+            CHK(c->alloc((void**)&S.cdd_le, bl));
+        }
     }
     // the split depends on the batch size: cover every batch up to nrhs
     size_t cw = 0;
     for (const Sub& S : c->subs)
-        for (int q = 1; q <= nrhs; ++q) cw = std::max(cw, coarse_ws_doubles(S.lev.back().g.N, q));
+        for (int q = 1; q <= nrhs; ++q) {
+            if (S.cdd.active())
+                for (const CoarseBox& B : S.cdd.box) cw = std::max(cw, coarse_ws_doubles(B.g.N, q));
+            else
+                cw = std::max(cw, coarse_ws_doubles(S.lev.back().g.N, q));
+        }
     c->release(c->coarse_ws);
     c->coarse_ws = nullptr;
     if (cw) CHK(c->alloc((void**)&c->coarse_ws, sizeof(double) * cw));
@@ -465,6 +511,61 @@ int32_t ensure_krylov(ehh_ctx* c, int nrhs) {
 }
 
 // ------------------------------------------------------------------- the cycle
+// The coarsest solve: e = A_c^{-1} b by the dense inverse, or one sweep of the
+// coarsest level's DD (section 4), in FP64, from e = 0 (zero_init) or continuing
+// from e (a W-cycle's second call).
+template <typename T>
+int32_t coarse_solve(ehh_ctx* c, Sub& S, const T* b, T* e, bool zero_init, int nrhs, hipStream_t s) {
+    Level& L = S.lev.back();
+    const int64_t Nc = L.g.N;
+    if (!S.cdd.active()) {
+        HIPCHK(launch_coarse_apply<T>(S.inv, S.sym, Nc, b, e, nrhs, c->coarse_ws, s));
+        return EHH_OK;
+    }
+    const CoarseDD& D = S.cdd;
+    const BoxMap M = D.view();
+    const double* r;
+    double* z;
+    if constexpr (std::is_same<T, double>::value) {
+        r = b;
+        z = e;
+    } else {
+        HIPCHK(launch_cast_f2d(b, S.cdd_r, 2 * Nc * nrhs, s));
+        if (!zero_init) HIPCHK(launch_cast_f2d(e, S.cdd_e, 2 * Nc * nrhs, s));
+        r = S.cdd_r;
+        z = S.cdd_e;
+    }
+    if (zero_init) HIPCHK(launch_zero(z, sizeof(double) * 2 * (size_t)Nc * nrhs, s));
+    const LevelDesc<double> A = level_desc<double>(c, L, c->prob.shift);
+    const bool one = c->opt.coarse_dd_colors == 1;
+    const int ncol = one ? 1 : (int)D.col_begin.size() - 1;
+    for (int col = 0; col < ncol; ++col) {
+        const int b0 = one ? 0 : D.col_begin[col], b1 = one ? (int)D.box.size() : D.col_begin[col + 1];
+        const double* src = r;
+        if (!(col == 0 && zero_init)) {   // the residual left by the previous colours
+            HIPCHK(launch_apply<double>(A, z, r, S.cdd_t, nrhs, s));
+            src = S.cdd_t;
+        }
+        const int64_t j0 = D.box[b0].base, j1 = b1 < (int)D.box.size() ? D.box[b1].base : D.ntot;
+        HIPCHK(launch_box_gather(M, j0, j1, src, Nc, S.cdd_lr, nrhs, s));
+        for (int bi = b0; bi < b1; ++bi) {
+            const CoarseBox& B = D.box[bi];
+            const size_t off = 2 * (size_t)nrhs * B.base;
+            HIPCHK(launch_coarse_apply<double>(B.inv, B.sym, B.g.N, S.cdd_lr + off, S.cdd_le + off, nrhs,
+                                               c->coarse_ws, s));
+        }
+        if (one)   // the boxes overlap: one scatter per box, in turn
+            for (int bi = b0; bi < b1; ++bi) {
+                const int64_t k0 = D.box[bi].base, k1 = bi + 1 < (int)D.box.size() ? D.box[bi + 1].base : D.ntot;
+                HIPCHK(launch_box_scatter(M, k0, k1, S.cdd_le, D.wgt, Nc, z, nrhs, s));
+            }
+        else       // the boxes of one colour are disjoint
+            HIPCHK(launch_box_scatter(M, j0, j1, S.cdd_le, nullptr, Nc, z, nrhs, s));
+    }
+    if constexpr (!std::is_same<T, double>::value) HIPCHK(launch_cast_d2f(z, e, 2 * Nc * nrhs, s));
+    return EHH_OK;
+}
+
 template <typename T>
 int32_t cycle(ehh_ctx* c, Sub& S, int l, const T* b, T* e, bool zero_init, int nrhs, hipStream_t s,
               const T* rsrc = nullptr, const Geo* gsrc = nullptr, double* z64 = nullptr, bool* wrote64 = nullptr) {
@@ -474,20 +575,17 @@ int32_t cycle(ehh_ctx* c, Sub& S, int l, const T* b, T* e, bool zero_init, int n
     // formed; the first half-sweep then forms and writes it (zero_init, nu1 >= 1)
     Level& L = S.lev[l];
     const int nl = (int)S.lev.size();
-    if (l == nl - 1) {
-        HIPCHK(launch_coarse_apply<T>(S.inv, S.sym, L.g.N, b, e, nrhs, c->coarse_ws, s));
-        return EHH_OK;
-    }
+    if (l == nl - 1) return coarse_solve<T>(c, S, b, e, zero_init, nrhs, s);
     const LevelDesc<T> D = level_desc<T>(c, L, c->prob.shift);
     const int econ = c->opt.vanka == 0;
     T* t = (T*)L.t;
     bool have = !zero_init;
     for (int it = 0; it < c->opt.nu1; ++it) {
         if (it == 0 && rsrc)
-            HIPCHK(launch_relax_restrict<T>(D, L.damping, econ, *gsrc, rsrc, (T*)b, t, nrhs, s));
+            HIPCHK(launch_relax_restrict<T>(D, Damp{L.damping, L.damping_p}, econ, *gsrc, rsrc, (T*)b, t, nrhs, s));
         else
-            HIPCHK(launch_relax<T>(D, 0, L.damping, econ, b, have ? e : nullptr, t, nrhs, s));
-        HIPCHK(launch_relax<T>(D, 1, L.damping, econ, b, t, e, nrhs, s));
+            HIPCHK(launch_relax<T>(D, 0, Damp{L.damping, L.damping_p}, econ, b, have ? e : nullptr, t, nrhs, s));
+        HIPCHK(launch_relax<T>(D, 1, Damp{L.damping, L.damping_p}, econ, b, t, e, nrhs, s));
         have = true;
     }
     Level& C = S.lev[l + 1];
@@ -507,24 +605,25 @@ int32_t cycle(ehh_ctx* c, Sub& S, int l, const T* b, T* e, bool zero_init, int n
         if (!fuse) HIPCHK(launch_restrict<T>(L.g, C.g, b, (T*)C.b, nrhs, s));
     }
     const T* rfine = have ? (const T*)t : b;
-    // gamma_c recursive calls (V: 1, W: 2); the coarsest solve is exact, so a second
-    // call there with the same right-hand side would repeat the same result.
-    const int ncall = (l + 1 == nl - 1 || l < c->opt.cycle_level) ? 1 : c->opt.cycle;
+    // gamma_c recursive calls (V: 1, W: 2); an exact coarsest solve would repeat
+    // the same result in a second call, a DD coarsest solve continues from it.
+    const bool exact_next = l + 1 == nl - 1 && !S.cdd.active();
+    const int ncall = (exact_next || l < c->opt.cycle_level) ? 1 : c->opt.cycle;
     for (int k = 0; k < ncall; ++k)
         CHK(cycle<T>(c, S, l + 1, (const T*)C.b, (T*)C.e, k == 0, nrhs, s, (k == 0 && fuse) ? rfine : nullptr,
                      &L.g));
     HIPCHK(launch_prolong<T>(L.g, C.g, (const T*)C.e, e, nrhs, s));
     for (int it = 0; it < c->opt.nu2; ++it) {
-        HIPCHK(launch_relax<T>(D, 0, L.damping, econ, b, e, t, nrhs, s));
+        HIPCHK(launch_relax<T>(D, 0, Damp{L.damping, L.damping_p}, econ, b, e, t, nrhs, s));
         bool done = false;
         if constexpr (std::is_same<T, float>::value) {
             if (z64 && it == c->opt.nu2 - 1)
-                HIPCHK(launch_relax_to64(D, L.damping, econ, b, t, z64, nrhs, s, &done));
+                HIPCHK(launch_relax_to64(D, Damp{L.damping, L.damping_p}, econ, b, t, z64, nrhs, s, &done));
         }
         if (done)
             *wrote64 = true;
         else
-            HIPCHK(launch_relax<T>(D, 1, L.damping, econ, b, t, e, nrhs, s));
+            HIPCHK(launch_relax<T>(D, 1, Damp{L.damping, L.damping_p}, econ, b, t, e, nrhs, s));
     }
     return EHH_OK;
 }
@@ -634,11 +733,18 @@ int32_t check_problem(const ehh_problem_t* p, const ehh_options_t* o) {
         return fail(EHH_ERR_INVALID, "coarse_bits = 16 needs the complex64 cycle (precond_bits = 32)");
     if (o->restart < 1 || o->restart > EHH_MAX_RESTART) return fail(EHH_ERR_INVALID, "restart out of range");
     for (int a = 0; a < p->dim; ++a)
+        if (o->coarse_dd_parts[a] < 1) return fail(EHH_ERR_INVALID, "coarse_dd_parts must be >= 1");
+    if (o->coarse_dd_overlap < 0) return fail(EHH_ERR_INVALID, "coarse_dd_overlap >= 0");
+    if (o->coarse_dd_colors != 0 && o->coarse_dd_colors != 1) return fail(EHH_ERR_INVALID, "coarse_dd_colors must be 0 or 1");
+    for (int a = 0; a < p->dim; ++a)
         if (o->dd_parts[a] < 1 || o->dd_parts[a] > p->n[a]) return fail(EHH_ERR_INVALID, "dd_parts out of range");
     if (o->dd_overlap < 0 || o->dd_pad < 0) return fail(EHH_ERR_INVALID, "dd_overlap, dd_pad >= 0");
     if (o->dd_colors != 0 && o->dd_colors != 1) return fail(EHH_ERR_INVALID, "dd_colors must be 0 or 1");
-    for (int l = 0; l < o->levels - 1; ++l)
+    for (int l = 0; l < o->levels - 1; ++l) {
         if (!(o->damping[l] > 0 && o->damping[l] <= 2)) return fail(EHH_ERR_INVALID, "damping must be in (0, 2]");
+        if (!(o->damping_p[l] >= 0 && o->damping_p[l] <= 2))
+            return fail(EHH_ERR_INVALID, "damping_p must be in (0, 2] (0: as damping)");
+    }
     return EHH_OK;
 }
 
@@ -713,6 +819,147 @@ int32_t rows_to_half(ehh_ctx* c, Level& Q, int NT, int NF, int64_t lanes, hipStr
     return EHH_OK;
 }
 
+// Dense inverse of the operator of a stencil-format level (grid g, FP64 stencil
+// st) and its lower 64 x 64 tiles packed.
+int32_t build_dense_inverse(ehh_ctx* c, const Geo& g, const double* st, double** inv_out, double** sym_out,
+                            hipStream_t s) {
+    const int64_t nc = g.N;
+    if ((double)nc * nc * 16.0 > 2.4e10)
+        return fail(EHH_ERR_UNSUPPORTED, "coarsest grid too large for a dense inverse (24 GB)");
+    double* inv0 = nullptr;
+    CHK(c->alloc((void**)&inv0, sizeof(double) * 2 * nc * nc));
+    HIPCHK(launch_dense_assemble(g, st, inv0, s));
+    int* piv = nullptr;
+    CHK(c->alloc((void**)&piv, sizeof(int) * (nc + 1)));
+    HIPCHK(launch_dense_invert(inv0, nc, piv, piv + nc, s));
+    std::vector<int> hp(nc + 1);
+    HIPCHK(hipMemcpyAsync(hp.data(), piv, sizeof(int) * (nc + 1), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hp[nc]) {
+        c->release(piv);
+        c->release(inv0);
+        return fail(EHH_ERR_BREAKDOWN, "singular coarsest operator");
+    }
+    // A^{-1} = (Pi A)^{-1} Pi: column q[k] of A^{-1} is column k of the result,
+    // with q the row order after the interchanges.
+    std::vector<int> q(nc), qinv(nc);
+    for (int64_t k = 0; k < nc; ++k) q[k] = (int)k;
+    for (int64_t k = 0; k < nc; ++k) std::swap(q[k], q[hp[k]]);
+    for (int64_t k = 0; k < nc; ++k) qinv[q[k]] = (int)k;
+    HIPCHK(hipMemcpyAsync(piv, qinv.data(), sizeof(int) * nc, hipMemcpyHostToDevice, s));
+    double* inv = nullptr;
+    CHK(c->alloc((void**)&inv, sizeof(double) * 2 * nc * nc));
+    HIPCHK(launch_permute_columns(inv0, inv, nc, piv, s));
+    HIPCHK(hipStreamSynchronize(s));
+    c->release(inv0);
+    double* sym = nullptr;
+    CHK(c->alloc((void**)&sym, sizeof(double) * 2 * 64 * 64 * sym_tiles(nc)));
+    HIPCHK(launch_pack_sym(inv, nc, sym, s));
+    c->release(piv);
+    *inv_out = inv;
+    *sym_out = sym;
+    return EHH_OK;
+}
+
+// Boxes (subdomains) of the coarsest level gc with their index maps and the
+// dense inverses of the restricted operators (DD as the coarsest solver).
+// Extents per axis as for the fine subdomains without padding: core n / parts,
+// the overlap split around each cut; colour = parity of the box index per axis.
+int32_t build_coarse_dd(ehh_ctx* c, Sub& S, const Geo& gc, const double* stc, hipStream_t s) {
+    const int d = c->dim, ov = c->opt.coarse_dd_overlap;
+    int parts[3] = {1, 1, 1};
+    for (int a = 0; a < d; ++a) {
+        parts[a] = c->opt.coarse_dd_parts[a];
+        if (parts[a] > gc.n[a]) return fail(EHH_ERR_INVALID, "coarse_dd_parts exceeds the coarsest grid");
+        if (parts[a] > 1 && gc.n[a] / parts[a] <= ov)
+            return fail(EHH_ERR_INVALID, "coarse_dd_overlap must be smaller than a coarsest subdomain's core");
+    }
+    CoarseDD& D = S.cdd;
+    std::vector<CoarseBox> boxes;
+    for (int pz = 0; pz < parts[2]; ++pz)
+        for (int py = 0; py < parts[1]; ++py)
+            for (int px = 0; px < parts[0]; ++px) {
+                CoarseBox B;
+                const int idx[3] = {px, py, pz};
+                int nb[3] = {1, 1, 1};
+                for (int a = 0; a < d; ++a) {
+                    const int n = gc.n[a], P = parts[a], p = idx[a], core = n / P;
+                    B.lo[a] = p == 0 ? 0 : std::max(0, p * core - ov / 2);
+                    B.hi[a] = p < P - 1 ? std::min(n, (p + 1) * core + (ov - ov / 2)) : n;
+                    nb[a] = B.hi[a] - B.lo[a];
+                }
+                B.colour = (px % 2) + 2 * (py % 2) + 4 * (pz % 2);
+                B.g = make_geo(d, nb);
+                boxes.push_back(B);
+            }
+    std::stable_sort(boxes.begin(), boxes.end(),
+                     [](const CoarseBox& a, const CoarseBox& b) { return a.colour < b.colour; });
+    D.box = boxes;
+    D.col_begin.clear();
+    int64_t base = 0;
+    for (size_t i = 0; i < D.box.size(); ++i) {
+        if (i == 0 || D.box[i].colour != D.box[i - 1].colour) D.col_begin.push_back((int)i);
+        D.box[i].base = base;
+        base += D.box[i].g.N;
+    }
+    D.col_begin.push_back((int)D.box.size());
+    D.ntot = base;
+    // index maps (host) and owner counts
+    const int nbox = (int)D.box.size();
+    std::vector<int> hidx(2 * D.ntot + nbox);
+    std::vector<int64_t> hbase(nbox);
+    std::vector<int> cnt(gc.N, 0);
+    for (int b = 0; b < nbox; ++b) {
+        const CoarseBox& B = D.box[b];
+        hbase[b] = B.base;
+        hidx[2 * D.ntot + b] = (int)B.g.N;
+        for (int64_t t = 0; t < B.g.N; ++t) {
+            int k = 0;
+            while (k < 3 && t >= B.g.off[k + 1]) ++k;
+            if (k >= d) k = 3;
+            const int64_t li = t - B.g.off[k];
+            int p[3] = {0, 0, 0};
+            int64_t gi;
+            if (d == 2) {
+                if (k == 3) cell_pos<2>(B.g, li, p);
+                else face_pos<2>(B.g, k, li, p);
+                for (int a = 0; a < 2; ++a) p[a] += B.lo[a];
+                gi = k == 3 ? gc.off[3] + cell_idx<2>(gc, p) : gc.off[k] + face_idx<2>(gc, k, p);
+            } else {
+                if (k == 3) cell_pos<3>(B.g, li, p);
+                else face_pos<3>(B.g, k, li, p);
+                for (int a = 0; a < 3; ++a) p[a] += B.lo[a];
+                gi = k == 3 ? gc.off[3] + cell_idx<3>(gc, p) : gc.off[k] + face_idx<3>(gc, k, p);
+            }
+            hidx[B.base + t] = (int)gi;
+            hidx[D.ntot + B.base + t] = b;
+            cnt[gi] += 1;
+        }
+    }
+    std::vector<double> hw(gc.N);
+    for (int64_t i = 0; i < gc.N; ++i) {
+        if (cnt[i] == 0) return fail(EHH_ERR_INVALID, "coarsest-level subdomains leave an unknown uncovered");
+        hw[i] = 1.0 / cnt[i];
+    }
+    CHK(c->alloc((void**)&D.idx, sizeof(int) * hidx.size()));
+    CHK(c->alloc((void**)&D.bbase, sizeof(int64_t) * nbox));
+    CHK(c->alloc((void**)&D.wgt, sizeof(double) * gc.N));
+    HIPCHK(hipMemcpyAsync(D.idx, hidx.data(), sizeof(int) * hidx.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(D.bbase, hbase.data(), sizeof(int64_t) * nbox, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(D.wgt, hw.data(), sizeof(double) * gc.N, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    // each box's restricted operator, inverted
+    for (CoarseBox& B : D.box) {
+        double* stb = nullptr;
+        CHK(c->alloc((void**)&stb, sizeof(double) * stencil_size(B.g)));
+        HIPCHK(launch_zero(stb, sizeof(double) * stencil_size(B.g), s));
+        HIPCHK(launch_box_stencil(gc, stc, B.g, stb, B.lo, s));
+        CHK(build_dense_inverse(c, B.g, stb, &B.inv, &B.sym, s));
+        c->release(stb);
+    }
+    return EHH_OK;
+}
+
 int32_t build_hierarchy(ehh_ctx* c, Sub& S, const double* lam, const double* mu, const double* rho,
                         const double* gam, hipStream_t s) {
     const int L = c->opt.levels;
@@ -729,6 +976,7 @@ int32_t build_hierarchy(ehh_ctx* c, Sub& S, const double* lam, const double* mu,
         S.lev[l].g = make_geo(c->dim, n);
         S.lev[l].fine = l == 0;
         S.lev[l].damping = l < L - 1 ? c->opt.damping[l] : 0.0;
+        S.lev[l].damping_p = l < L - 1 ? (c->opt.damping_p[l] > 0 ? c->opt.damping_p[l] : c->opt.damping[l]) : 0.0;
     }
     // level 0 coefficients
     Level& L0 = S.lev[0];
@@ -770,41 +1018,14 @@ int32_t build_hierarchy(ehh_ctx* c, Sub& S, const double* lam, const double* mu,
         lg.mark("galerkin level");
     }
     const Level& Lc = S.lev[L - 1];
-    const int64_t nc = Lc.g.N;
-    if ((double)nc * nc * 16.0 > 2.4e10) return fail(EHH_ERR_UNSUPPORTED, "coarsest grid too large for a dense inverse (24 GB)");
-    CHK(c->alloc((void**)&S.inv, sizeof(double) * 2 * nc * nc));
-    HIPCHK(launch_dense_assemble(Lc.g, L == 1 ? st0 : Lc.coef64, S.inv, s));
-    int* piv = nullptr;
-    CHK(c->alloc((void**)&piv, sizeof(int) * (nc + 1)));
-    lg.mark("dense assemble");
-    HIPCHK(launch_dense_invert(S.inv, nc, piv, piv + nc, s));
-    std::vector<int> hp(nc + 1);
-    HIPCHK(hipMemcpyAsync(hp.data(), piv, sizeof(int) * (nc + 1), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    lg.mark("dense invert");
-    if (hp[nc]) {
-        c->release(piv);
-        return fail(EHH_ERR_BREAKDOWN, "singular coarsest operator");
-    }
-    // A^{-1} = (Pi A)^{-1} Pi: column q[k] of A^{-1} is column k of the result,
-    // with q the row order after the interchanges.
-    {
-        std::vector<int> q(nc), qinv(nc);
-        for (int64_t k = 0; k < nc; ++k) q[k] = (int)k;
-        for (int64_t k = 0; k < nc; ++k) std::swap(q[k], q[hp[k]]);
-        for (int64_t k = 0; k < nc; ++k) qinv[q[k]] = (int)k;
-        HIPCHK(hipMemcpyAsync(piv, qinv.data(), sizeof(int) * nc, hipMemcpyHostToDevice, s));
-        double* inv = nullptr;
-        CHK(c->alloc((void**)&inv, sizeof(double) * 2 * nc * nc));
-        HIPCHK(launch_permute_columns(S.inv, inv, nc, piv, s));
-        HIPCHK(hipStreamSynchronize(s));
-        c->release(S.inv);
-        S.inv = inv;
-        lg.mark("column permutation");
-    }
-    CHK(c->alloc((void**)&S.sym, sizeof(double) * 2 * 64 * 64 * sym_tiles(nc)));
-    HIPCHK(launch_pack_sym(S.inv, nc, S.sym, s));
-    c->release(piv);
+    const double* stc = L == 1 ? st0 : Lc.coef64;
+    bool cdd = false;
+    for (int a = 0; a < c->dim; ++a) cdd = cdd || c->opt.coarse_dd_parts[a] > 1;
+    if (cdd)
+        CHK(build_coarse_dd(c, S, Lc.g, stc, s));
+    else
+        CHK(build_dense_inverse(c, Lc.g, stc, &S.inv, &S.sym, s));
+    lg.mark(cdd ? "coarsest-level subdomain inverses" : "coarsest inverse");
     c->release(st0);
     if (c->bits() == 32) {
         for (int l = 0; l < L; ++l) {
@@ -1129,6 +1350,9 @@ void ehh_default_options(ehh_options_t* o) {
     o->vanka = 1;
     o->precond_bits = 64;
     o->coarse_bits = 32;
+    o->coarse_dd_parts[0] = o->coarse_dd_parts[1] = o->coarse_dd_parts[2] = 1;
+    o->coarse_dd_overlap = 2;
+    o->coarse_dd_colors = 0;
     o->restart = 5;
     o->dd_parts[0] = o->dd_parts[1] = o->dd_parts[2] = 1;
     o->dd_colors = 1;
@@ -1150,6 +1374,7 @@ int32_t ehh_setup_operator(const ehh_problem_t* problem, const double* lambda, c
         c->prob.n[2] = 1;
         c->prob.abl_cells[2] = 0;
         c->opt.dd_parts[2] = 1;
+        c->opt.coarse_dd_parts[2] = 1;
     }
     int32_t st = setup_impl(c, lambda, mu, rho, gamma, as_stream(stream));
     if (st != EHH_OK) {
@@ -1474,10 +1699,12 @@ int32_t ehh_level_relax(ehh_handle_t h, int32_t sub, int32_t level, int32_t colo
         return fail(EHH_ERR_INVALID, "bad vectors, colour or nrhs");
     const int econ = h->opt.vanka == 0;
     if (h->bits() == 32)
-        HIPCHK(launch_relax<float>(level_desc<float>(h, *L, h->prob.shift), colour, L->damping, econ, (const float*)b,
+        HIPCHK(launch_relax<float>(level_desc<float>(h, *L, h->prob.shift), colour, Damp{L->damping, L->damping_p},
+                                   econ, (const float*)b,
                                    (const float*)e_in, (float*)e_out, nrhs, as_stream(stream)));
     else
-        HIPCHK(launch_relax<double>(level_desc<double>(h, *L, h->prob.shift), colour, L->damping, econ,
+        HIPCHK(launch_relax<double>(level_desc<double>(h, *L, h->prob.shift), colour, Damp{L->damping, L->damping_p},
+                                    econ,
                                     (const double*)b, (const double*)e_in, (double*)e_out, nrhs, as_stream(stream)));
     return EHH_OK;
 }
@@ -1537,13 +1764,8 @@ int32_t ehh_coarse_solve(ehh_handle_t h, int32_t sub, const void* r, void* e, in
     CHK(level_of(h, sub, (int)h->subs[sub].lev.size() - 1, &S, &L));
     if (!r || !e || r == e || nrhs < 1) return fail(EHH_ERR_INVALID, "bad vectors or nrhs");
     CHK(ensure_ws(h, nrhs));   // sizes the coarse-apply workspace for nrhs
-    if (h->bits() == 32)
-        HIPCHK(launch_coarse_apply<float>(S->inv, S->sym, L->g.N, (const float*)r, (float*)e, nrhs, h->coarse_ws,
-                                          as_stream(stream)));
-    else
-        HIPCHK(launch_coarse_apply<double>(S->inv, S->sym, L->g.N, (const double*)r, (double*)e, nrhs, h->coarse_ws,
-                                           as_stream(stream)));
-    return EHH_OK;
+    if (h->bits() == 32) return coarse_solve<float>(h, *S, (const float*)r, (float*)e, true, nrhs, as_stream(stream));
+    return coarse_solve<double>(h, *S, (const double*)r, (double*)e, true, nrhs, as_stream(stream));
 }
 
 int32_t ehh_profile_precondition(ehh_handle_t h, const double* v, double* z, int32_t nrhs, int32_t reps, void* evict,
@@ -1609,6 +1831,9 @@ int32_t ehh_coarse_solve_noalloc(ehh_handle_t h, int32_t sub, const void* r, voi
         scratch = noalloc_scratch(h->device);
     }
     const Sub& S = h->subs[sub];
+    if (S.cdd.active())
+        return fail(EHH_ERR_UNSUPPORTED, "ehh_coarse_solve_noalloc: the coarsest level is solved by domain "
+                                         "decomposition, whose workspaces would have to be allocated");
     const int64_t n = S.lev.back().g.N;
     const size_t need = coarse_ws_doubles(n, nrhs);
     if (need > (size_t)kNoallocScratchDoubles)

@@ -184,3 +184,105 @@ template hipError_t launch_dd_gather_res<double>(const Geo&, const Geo&, const S
                                                  const double*, const double*, double*, int, hipStream_t);
 
 }  // namespace ehh
+
+// ------------------------------------------------ DD as the coarsest-grid solver
+// The subdomains ("boxes") of the coarsest level of one hierarchy have their
+// unknowns numbered one box after the other; local unknown j of box b (starting
+// at bbase[b], bn[b] unknowns) is the coarsest unknown map[j].  A box's local
+// vectors are stored like any level vector of its own grid: for source r the
+// real plane then the imaginary plane, at loc + 2 nrhs bbase[b] + 2 bn[b] r.
+
+namespace ehh {
+
+// Copy the coarsest stencil of every face and cell of a box (cells [lo, hi) of
+// grid gc) into the stencil arrays of the box's own grid gb.  Couplings of the
+// copied rows that leave the box are simply not reached from the box's grid,
+// which restricts the operator to the box.
+template <int D>
+__global__ __launch_bounds__(256) void k_box_stencil(Geo gc, StCoef<double> sc, Geo gb, StCoef<double> sb, int lo0,
+                                                     int lo1, int lo2) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= gb.N) return;
+    const int lo[3] = {lo0, lo1, lo2};
+    int k = 0;
+    while (k < 3 && t >= gb.off[k + 1]) ++k;
+    if (k >= D) k = 3;
+    const int64_t li = t - gb.off[k];
+    int p[3];
+    if (k == 3) {
+        cell_pos<D>(gb, li, p);
+        for (int a = 0; a < D; ++a) p[a] += lo[a];
+        ((double*)sb.pp)[li] = sc.pp[cell_idx<D>(gc, p)];
+        return;
+    }
+    face_pos<D>(gb, k, li, p);
+    for (int a = 0; a < D; ++a) p[a] += lo[a];
+    const int64_t gi = face_idx<D>(gc, k, p);
+    for (int q = 0; q < 2 * St<D>::NUU; ++q)
+        ((double*)sb.uu[k])[(int64_t)q * gb.cnt[k] + li] = sc.uu[k][(int64_t)q * gc.cnt[k] + gi];
+    for (int q = 0; q < St<D>::NUP; ++q)
+        ((double*)sb.up[k])[(int64_t)q * gb.cnt[k] + li] = sc.up[k][(int64_t)q * gc.cnt[k] + gi];
+}
+
+hipError_t launch_box_stencil(const Geo& gc, const double* stc, const Geo& gb, double* stb, const int* lo,
+                              hipStream_t s) {
+    if (gc.dim == 2)
+        EHH_LAUNCH((k_box_stencil<2>), nblk(gb.N), 256, 0, s, gc, stencil_view<2, double>(gc, stc), gb,
+                   stencil_view<2, double>(gb, (const double*)stb), lo[0], lo[1], lo[2]);
+    else
+        EHH_LAUNCH((k_box_stencil<3>), nblk(gb.N), 256, 0, s, gc, stencil_view<3, double>(gc, stc), gb,
+                   stencil_view<3, double>(gb, (const double*)stb), lo[0], lo[1], lo[2]);
+    return hipGetLastError();
+}
+
+// loc(box) <- src restricted to the box, for the local unknowns [j0, j1)
+__global__ __launch_bounds__(256) void k_box_gather(const int* __restrict__ map, const int* __restrict__ bsub,
+                                                    const int64_t* __restrict__ bbase, const int* __restrict__ bn,
+                                                    int64_t j0, int64_t j1, const double* __restrict__ src,
+                                                    int64_t Nc, double* __restrict__ loc, int nrhs) {
+    const int64_t j = j0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= j1) return;
+    const int b = bsub[j];
+    const int64_t base = bbase[b], n = bn[b], li = j - base, g = map[j];
+    double* o = loc + 2 * (int64_t)nrhs * base + li;
+    for (int r = 0; r < nrhs; ++r) {
+        o[2 * n * r] = src[2 * Nc * r + g];
+        o[2 * n * r + n] = src[2 * Nc * r + Nc + g];
+    }
+}
+
+// z += w loc(box) for the local unknowns [j0, j1) (boxes of the range disjoint);
+// w = wgt[g] (the inverse owner count) when wgt is given, else 1
+__global__ __launch_bounds__(256) void k_box_scatter(const int* __restrict__ map, const int* __restrict__ bsub,
+                                                     const int64_t* __restrict__ bbase, const int* __restrict__ bn,
+                                                     int64_t j0, int64_t j1, const double* __restrict__ loc,
+                                                     const double* __restrict__ wgt, int64_t Nc,
+                                                     double* __restrict__ z, int nrhs) {
+    const int64_t j = j0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= j1) return;
+    const int b = bsub[j];
+    const int64_t base = bbase[b], n = bn[b], li = j - base, g = map[j];
+    const double w = wgt ? wgt[g] : 1.0;
+    const double* o = loc + 2 * (int64_t)nrhs * base + li;
+    for (int r = 0; r < nrhs; ++r) {
+        z[2 * Nc * r + g] += w * o[2 * n * r];
+        z[2 * Nc * r + Nc + g] += w * o[2 * n * r + n];
+    }
+}
+
+hipError_t launch_box_gather(const BoxMap& m, int64_t j0, int64_t j1, const double* src, int64_t Nc, double* loc,
+                             int nrhs, hipStream_t s) {
+    if (j1 <= j0) return hipSuccess;
+    EHH_LAUNCH_B(bytes_plain(nrhs * 32.0 * (double)(j1 - j0)), k_box_gather, nblk(j1 - j0), 256, 0, s, m.map, m.bsub,
+                 m.bbase, m.bn, j0, j1, src, Nc, loc, nrhs);
+    return hipGetLastError();
+}
+hipError_t launch_box_scatter(const BoxMap& m, int64_t j0, int64_t j1, const double* loc, const double* wgt,
+                              int64_t Nc, double* z, int nrhs, hipStream_t s) {
+    if (j1 <= j0) return hipSuccess;
+    EHH_LAUNCH_B(bytes_plain(nrhs * 48.0 * (double)(j1 - j0)), k_box_scatter, nblk(j1 - j0), 256, 0, s, m.map,
+                 m.bsub, m.bbase, m.bn, j0, j1, loc, wgt, Nc, z, nrhs);
+    return hipGetLastError();
+}
+
+}  // namespace ehh

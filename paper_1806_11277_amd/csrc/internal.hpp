@@ -34,22 +34,29 @@ template <typename T> struct LevelDesc {
     StoredPlan<T> sp;
 };
 
+// Vanka damping of one level: u for the displacement rows of a cell block, p for
+// its pressure row (the component-dependent damping W = diag(w_u, .., w_p) of
+// the damped block update in section 5.2; u == p for the plain damping).
+struct Damp {
+    double u, p;
+};
+
 // ---- levels.hip
 template <typename T>
 hipError_t launch_apply(const LevelDesc<T>& L, const T* x, const T* b, T* y, int nrhs, hipStream_t s);
 template <typename T>
-hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, const T* b, const T* ein,
+hipError_t launch_relax(const LevelDesc<T>& L, int colour, Damp w, int econ, const T* b, const T* ein,
                         T* eout, int nrhs, hipStream_t s);
 // Colour-1 half-sweep of a finest 2D level with an FP64 e_out (*done = false
 // where no kernel serves it: the caller then converts after the cycle).
-hipError_t launch_relax_to64(const LevelDesc<float>& L, double w, int econ, const float* b, const float* ein,
+hipError_t launch_relax_to64(const LevelDesc<float>& L, Damp w, int econ, const float* b, const float* ein,
                              double* eout, int nrhs, hipStream_t s, bool* done);
 // First half-sweep (colour 0) of a visit from zero with the restriction fused:
 // b = P^T rf (rf on the finer grid gf) is formed, written to b, and relaxed.
 template <typename T>
 bool relax_restrict_supported(const LevelDesc<T>& L, const Geo& gf, int nrhs);
 template <typename T>
-hipError_t launch_relax_restrict(const LevelDesc<T>& L, double w, int econ, const Geo& gf, const T* rf, T* b,
+hipError_t launch_relax_restrict(const LevelDesc<T>& L, Damp w, int econ, const Geo& gf, const T* rf, T* b,
                                  T* eout, int nrhs, hipStream_t s);
 // Lanes (padded) of one colour's stored plans on a level, and the builder.
 int64_t stored_plan_lanes(const Geo& g);
@@ -148,6 +155,23 @@ hipError_t launch_dd_gather_res(const Geo& gg, const Geo& gl, const SubMap& m, c
 template <typename T>
 hipError_t launch_dd_scatter(const Geo& gg, const Geo& gl, const SubMap& m, const T* e, double* z, int nrhs,
                              int weighted, hipStream_t s);
+
+// DD as the coarsest-grid solver: device index arrays of the boxes (subdomains)
+// of a coarsest level, local unknowns numbered box after box.
+struct BoxMap {
+    const int* map;        // coarsest unknown of each local unknown
+    const int* bsub;       // box of each local unknown
+    const int64_t* bbase;  // first local unknown of each box
+    const int* bn;         // unknowns of each box
+};
+// Stencil of the box [lo, lo + gb.n) of the coarsest grid gc, on the box's grid.
+hipError_t launch_box_stencil(const Geo& gc, const double* stc, const Geo& gb, double* stb, const int* lo,
+                              hipStream_t s);
+// loc <- src on the local unknowns [j0, j1); z += (wgt or 1) loc there.
+hipError_t launch_box_gather(const BoxMap& m, int64_t j0, int64_t j1, const double* src, int64_t Nc, double* loc,
+                             int nrhs, hipStream_t s);
+hipError_t launch_box_scatter(const BoxMap& m, int64_t j0, int64_t j1, const double* loc, const double* wgt,
+                              int64_t Nc, double* z, int nrhs, hipStream_t s);
 
 // ---- krylov.hip (FP64, vectors of 2N reals per right-hand side)
 int krylov_blocks(int64_t n2);

@@ -65,7 +65,7 @@ __global__ __launch_bounds__(256) void k_apply(Op op, const T* __restrict__ x, c
 // unknown; the residual is taken from e_in (the state at the start of the
 // half-sweep).
 template <int D, typename T, class Op, int RB>
-__global__ __launch_bounds__(256) void k_relax(Op op, int colour, T w, int econ,
+__global__ __launch_bounds__(256) void k_relax(Op op, int colour, T w, T wp, int econ,
                                                const T* __restrict__ b, const T* __restrict__ ein,
                                                T* __restrict__ eout, int nrhs, int64_t stride, int rpb) {
     {
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(256) void k_relax(Op op, int colour, T w, int econ,
             const T vi = __shfl(d[j].im, base, 64);
             if (row == j) mine = mk<T>(vr, vi);
         }
-        if (ok) ov.st(idx, (ein ? ev.ld(idx) : mk<T>(T(0), T(0))) + w * mine);
+        if (ok) ov.st(idx, (ein ? ev.ld(idx) : mk<T>(T(0), T(0))) + (row == 2 * D ? wp : w) * mine);
         if (carry) ov.st(ipb, ein ? ev.ld(ipb) : mk<T>(T(0), T(0)));
     }
     }
@@ -342,7 +342,7 @@ template <int D, typename T> struct VankaBlock {
 // the two faces of a component, the couplings to the cell pressure) is read off
 // the lanes' plans.
 template <int D, typename T, class Op, int RB>
-__global__ __launch_bounds__(256) void k_relax_plan(Op op, int colour, T w, int econ,
+__global__ __launch_bounds__(256) void k_relax_plan(Op op, int colour, T w, T wp, int econ,
                                                     const T* __restrict__ b, const T* __restrict__ ein,
                                                     T* __restrict__ eout, int nrhs, int64_t stride, int rpb) {
     {
@@ -422,7 +422,7 @@ __global__ __launch_bounds__(256) void k_relax_plan(Op op, int colour, T w, int 
             const CVec<T> ev{ein ? ein + r * stride : nullptr, g.N};
             const Vec<T> ov{eout + r * stride, g.N};
             const cx<T> mine = V.solve(resb[q], base, row);
-            if (ok) ov.st(idx, (ein ? ev.ld(idx) : mk<T>(T(0), T(0))) + w * mine);
+            if (ok) ov.st(idx, (ein ? ev.ld(idx) : mk<T>(T(0), T(0))) + (row == 2 * D ? wp : w) * mine);
             if (carry) ov.st(ipb, ein ? ev.ld(ipb) : mk<T>(T(0), T(0)));
         }
     }
@@ -581,7 +581,7 @@ EHH_DEV inline int col2(const Cols2& c, int j) {
 // one unknown per lane (the carry lane forms the other cell's pressure), which
 // saves the restriction's own launch.
 template <typename T, bool KEEP, bool RST>
-__global__ __launch_bounds__(256) void k_relax_st2d(Geo g, int colour, T w, int econ, const T* __restrict__ b,
+__global__ __launch_bounds__(256) void k_relax_st2d(Geo g, int colour, T w, T wp, int econ, const T* __restrict__ b,
                                                     const T* __restrict__ ein, T* __restrict__ eout, int nrhs,
                                                     int64_t stride, int rpb, const T* __restrict__ cre,
                                                     const T* __restrict__ cim, int64_t lanes, Geo gf,
@@ -750,7 +750,7 @@ __global__ __launch_bounds__(256) void k_relax_st2d(Geo g, int colour, T w, int 
         }
         const cx<T> mine = V.solve(res, base, row);
         const Vec<T> ov{eout + r * stride, g.N};
-        if (ok) ov.st(idx, eown + w * mine);
+        if (ok) ov.st(idx, eown + (row == 4 ? wp : w) * mine);
         if (carry) ov.st(ipb, ecarry);
     }
 }
@@ -764,7 +764,7 @@ __global__ __launch_bounds__(256) void k_relax_st2d(Geo g, int colour, T w, int 
 // its registers), which pays on small levels where a launch is one wave of
 // wavefronts deep.  Only for half-sweeps that start from e_in.
 template <typename T>
-__global__ __launch_bounds__(256) void k_relax_st2d_split(Geo g, int colour, T w, int econ, const T* __restrict__ b,
+__global__ __launch_bounds__(256) void k_relax_st2d_split(Geo g, int colour, T w, T wp, int econ, const T* __restrict__ b,
                                                           const T* __restrict__ ein, T* __restrict__ eout, int nrhs,
                                                           int64_t stride, int rpb, const T* __restrict__ cre,
                                                           const T* __restrict__ cim, int64_t lanes) {
@@ -885,7 +885,7 @@ __global__ __launch_bounds__(256) void k_relax_st2d_split(Geo g, int colour, T w
             if (ok) res = bo - mk<T>(ar + part[r & 1][grp][0][lane], ai + part[r & 1][grp][1][lane]);
             const cx<T> mine = V.solve(res, base, row);
             const Vec<T> ov{eout + r * stride, g.N};
-            if (ok) ov.st(idx, eown + w * mine);
+            if (ok) ov.st(idx, eown + (row == 4 ? wp : w) * mine);
             if (carry) ov.st(ipb, ecarry);
             continue;
         }
@@ -1199,7 +1199,7 @@ EHH_DEV void rows3_rb(const Buf<C>& cR, const Buf<C>& cI, uint32_t lo, uint32_t 
 // the level's power-of-two scale csc, which the sums and the block entries are
 // multiplied by again; csc = 1 otherwise).
 template <typename T, int RB, int CH, typename C = T>
-__global__ __launch_bounds__(256) void k_relax_st3d(Geo g, int colour, T w, int econ, const T* __restrict__ b,
+__global__ __launch_bounds__(256) void k_relax_st3d(Geo g, int colour, T w, T wp, int econ, const T* __restrict__ b,
                                                     const T* __restrict__ ein, T* __restrict__ eout, int nrhs,
                                                     int64_t stride, int rpb, const C* __restrict__ cre,
                                                     const C* __restrict__ cim, int64_t lanes, T csc) {
@@ -1292,7 +1292,7 @@ __global__ __launch_bounds__(256) void k_relax_st3d(Geo g, int colour, T w, int 
             }
             const cx<T> mine = V.solve(res, base, row);
             if (ok) {
-                const cx<T> v = eown + w * mine;
+                const cx<T> v = eown + (row == 2 * D ? wp : w) * mine;
                 oq.st(oi, v.re);
                 oq.st(oi + nb, v.im);
             }
@@ -1484,7 +1484,7 @@ __global__ __launch_bounds__(256) void k_build_row_rows3d(StOp<3, T> op, T* __re
 // TO: type of e_out (double lets the last half-sweep of a complex64 cycle write
 // the FP64 result directly).
 template <typename T, typename TO = T>
-__global__ __launch_bounds__(256) void k_relax_cell2d(FineOp<2, T> op, int colour, T w, int econ,
+__global__ __launch_bounds__(256) void k_relax_cell2d(FineOp<2, T> op, int colour, T w, T wp, int econ,
                                                       const T* __restrict__ b, const T* __restrict__ ein,
                                                       TO* __restrict__ eout, int nrhs, int64_t stride, int rpb) {
     const Geo& g = op.g;
@@ -1621,7 +1621,7 @@ __global__ __launch_bounds__(256) void k_relax_cell2d(FineOp<2, T> op, int colou
         if (vr) st(kr, ere + w * (y0h - z0h * dp));
         if (vb) st(kb, eb + w * (y1l - z1l * dp));
         if (vt) st(kt, et + w * (y1h - z1h * dp));
-        st(kp, ep + w * dp);
+        st(kp, ep + wp * dp);
         st(kpo, epo);
     }
 }
@@ -1745,7 +1745,7 @@ __global__ __launch_bounds__(256) void k_apply_cell2d(FineOp<2, T> op, const T* 
 // component the two faces, their outer normal neighbours and four tangential
 // neighbours each; the pressure and its six neighbours) and b at 7 unknowns.
 template <typename T>
-__global__ __launch_bounds__(256) void k_relax_cell3d(FineOp<3, T> op, int colour, T w, int econ,
+__global__ __launch_bounds__(256) void k_relax_cell3d(FineOp<3, T> op, int colour, T w, T wp, int econ,
                                                       const T* __restrict__ b, const T* __restrict__ ein,
                                                       T* __restrict__ eout, int nrhs, int64_t stride, int rpb) {
     const Geo& g = op.g;
@@ -1930,7 +1930,7 @@ __global__ __launch_bounds__(256) void k_relax_cell3d(FineOp<3, T> op, int colou
             if (vlo[k]) st(klo[k], elo[k] + w * (ylo[k] - zl[k] * dp));
             if (vhi[k]) st(khi[k], ehi[k] + w * (yhi[k] - zh[k] * dp));
         }
-        st(kp, ep + w * dp);
+        st(kp, ep + wp * dp);
         st(kpo, epo);
     }
 }
@@ -2140,7 +2140,7 @@ __global__ __launch_bounds__(256) void k_build_row_plans(StOp<2, T> op, T* __res
 static constexpr int LT_X = 16, LT_Y = 8;
 
 template <typename T, class Op>
-__global__ __launch_bounds__(512) void k_relax_lds2d(Op op, int colour, T w, int econ, const T* __restrict__ b,
+__global__ __launch_bounds__(512) void k_relax_lds2d(Op op, int colour, T w, T wp, int econ, const T* __restrict__ b,
                                                      const T* __restrict__ ein, T* __restrict__ eout, int nrhs,
                                                      int64_t stride, int rpb, int ht) {
     constexpr int D = 2, R = 5;
@@ -2385,7 +2385,7 @@ __global__ __launch_bounds__(512) void k_relax_lds2d(Op op, int colour, T w, int
             const T vi = __shfl(d[j].im, base, 64);
             if (row == j) mine = mk<T>(vr, vi);
         }
-        if (ok) ov.st(idx, eown + w * mine);
+        if (ok) ov.st(idx, eown + (row == 4 ? wp : w) * mine);
         if (carry) ov.st(ipb, ecarry);
     }
 }
@@ -2926,7 +2926,7 @@ hipError_t launch_apply(const LevelDesc<T>& L, const T* x, const T* b, T* y, int
 }
 
 template <typename T>
-hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, const T* b, const T* ein,
+hipError_t launch_relax(const LevelDesc<T>& L, int colour, Damp w, int econ, const T* b, const T* ein,
                         T* eout, int nrhs, hipStream_t s) {
     const int64_t stride = 2 * L.g.N;
     const int64_t npair = (int64_t)(L.g.n[0] / 2) * L.g.n[1] * L.g.n[2];
@@ -2936,7 +2936,7 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
     const int rb3 = rhs_block_3d_stencil<T>();
     const int rpb3 = rhs_per_block((npair * 8 + 63) / 64, nrhs, rb3);
     const dim3 gb3(nblk(npair * 8), (nrhs + rpb3 - 1) / rpb3);
-    const T tw = (T)w;
+    const T tw = (T)w.u, twp = (T)w.p;
     const double coef_es = L.fine ? (double)sizeof(T) : (L.sp.half ? 2.0 : (double)sizeof(T));
     const LaunchBytes lb = bytes_relax(L.g, L.fine, nrhs, ein != nullptr, (int)sizeof(T), (int)sizeof(T), coef_es);
     // LDS staging pays on the 21-term Galerkin rows of large levels with many
@@ -2951,7 +2951,7 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
         lds2d_enabled() && big_batch) {
         const int tiles = lds_tiles;
         const dim3 gl(tiles, (nrhs + rpl - 1) / rpl);
-        EHH_LAUNCH_B(lb, (k_relax_lds2d<T, StOp<2, T>>), gl, 512, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride, rpl, 2);
+        EHH_LAUNCH_B(lb, (k_relax_lds2d<T, StOp<2, T>>), gl, 512, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpl, 2);
     } else if (L.g.dim == 2 && L.fine && cell2d_enabled() && 2 * L.g.N * (int64_t)sizeof(T) < (int64_t(1) << 32)) {
         const int64_t cells = npair;
         static const int64_t cell_waves = env_int("EHH_CELL_WAVES", 4096);
@@ -2959,10 +2959,10 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
         groups = groups < 1 ? 1 : (groups > nrhs ? nrhs : groups);
         const int rpc = (int)((nrhs + groups - 1) / groups);
         const dim3 gc(nblk(cells), (nrhs + rpc - 1) / rpc);
-        EHH_LAUNCH_B(lb, (k_relax_cell2d<T>), gc, 256, 0, s, FineOp<2, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride, rpc);
+        EHH_LAUNCH_B(lb, (k_relax_cell2d<T>), gc, 256, 0, s, FineOp<2, T>{L.g, L.f}, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpc);
     } else if (L.g.dim == 2) {
         if (L.fine)
-            EHH_RB_DISPATCH(rb, EHH_LAUNCH_B(lb, (k_relax_plan<2, T, FineOp<2, T>, RB>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb));
+            EHH_RB_DISPATCH(rb, EHH_LAUNCH_B(lb, (k_relax_plan<2, T, FineOp<2, T>, RB>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpb));
         else if (L.sp.re[colour])
         {
             // the smallest FP64 levels (one wavefront per CU): rows split over two
@@ -2971,12 +2971,12 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
             static const bool split_on = env_int("EHH_SPLIT", 1) != 0;
             const int64_t groups = L.sp.lanes / 64;
             if (sizeof(T) == 8 && ein && split_on && groups <= 256)
-                EHH_LAUNCH_B(lb, (k_relax_st2d_split<T>), dim3((unsigned)((groups + 1) / 2), gb.y), 256, 0, s, L.g, colour, tw, econ, b, ein, eout, nrhs, stride, rpb, L.sp.re[colour], L.sp.im[colour], L.sp.lanes);
+                EHH_LAUNCH_B(lb, (k_relax_st2d_split<T>), dim3((unsigned)((groups + 1) / 2), gb.y), 256, 0, s, L.g, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpb, L.sp.re[colour], L.sp.im[colour], L.sp.lanes);
             else
-                EHH_LAUNCH_B(lb, (k_relax_st2d<T, sizeof(T) == 4, false>), gb, 256, 0, s, L.g, colour, tw, econ, b, ein, eout, nrhs, stride, rpb, L.sp.re[colour], L.sp.im[colour], L.sp.lanes, L.g, (const T*)nullptr, (T*)nullptr);
+                EHH_LAUNCH_B(lb, (k_relax_st2d<T, sizeof(T) == 4, false>), gb, 256, 0, s, L.g, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpb, L.sp.re[colour], L.sp.im[colour], L.sp.lanes, L.g, (const T*)nullptr, (T*)nullptr);
         }
         else
-            EHH_RB_DISPATCH(rb, EHH_LAUNCH_B(lb, (k_relax_plan<2, T, StOp<2, T>, RB>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb));
+            EHH_RB_DISPATCH(rb, EHH_LAUNCH_B(lb, (k_relax_plan<2, T, StOp<2, T>, RB>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpb));
     } else if (L.fine && cell3d_enabled() && 2 * L.g.N * (int64_t)sizeof(T) < (int64_t(1) << 32)) {
         const int64_t cells = npair;
         // one source group (16 sources per thread) beat two on the 72^3 subdomains:
@@ -2986,16 +2986,16 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
         groups = groups < 1 ? 1 : (groups > nrhs ? nrhs : groups);
         const int rpc = (int)((nrhs + groups - 1) / groups);
         const dim3 gc(nblk(cells), (nrhs + rpc - 1) / rpc);
-        EHH_LAUNCH_B(lb, (k_relax_cell3d<T>), gc, 256, 0, s, FineOp<3, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride, rpc);
+        EHH_LAUNCH_B(lb, (k_relax_cell3d<T>), gc, 256, 0, s, FineOp<3, T>{L.g, L.f}, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpc);
     } else {
         if (L.fine)
-            EHH_RB_DISPATCH(rb, EHH_LAUNCH_B(lb, (k_relax_plan<3, T, FineOp<3, T>, RB>), gb, 256, 0, s, FineOp<3, T>{L.g, L.f}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb));
+            EHH_RB_DISPATCH(rb, EHH_LAUNCH_B(lb, (k_relax_plan<3, T, FineOp<3, T>, RB>), gb, 256, 0, s, FineOp<3, T>{L.g, L.f}, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpb));
         else if (L.sp.re[colour]) {
 #define EHH_RELAX_ST3D(RB, CH, C)                                                                                 \
     {                                                                                                             \
         const int rpbs = rhs_per_block((npair * 8 + 63) / 64, nrhs, RB, 4096);                                    \
         EHH_LAUNCH_B(lb, (k_relax_st3d<T, RB, CH, C>), dim3(nblk(npair * 8), (nrhs + rpbs - 1) / rpbs), 256, 0,  \
-                           s, L.g, colour, tw, econ, b, ein, eout, nrhs, stride, rpbs, (const C*)L.sp.re[colour], \
+                           s, L.g, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpbs, (const C*)L.sp.re[colour], \
                            (const C*)L.sp.im[colour], L.sp.lanes, (T)L.sp.scale);                                 \
     }
             // measured on MI355X (36^3 level, 16 FP32 sources): 8 sources per
@@ -3010,7 +3010,7 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
             else EHH_RELAX_ST3D(8, 8, T)
 #undef EHH_RELAX_ST3D
         } else
-            EHH_RB_DISPATCH(rb3, EHH_LAUNCH_B(lb, (k_relax<3, T, StOp<3, T>, RB>), gb3, 256, 0, s, StOp<3, T>{L.g, L.s}, colour, tw, econ, b, ein, eout, nrhs, stride, rpb3));
+            EHH_RB_DISPATCH(rb3, EHH_LAUNCH_B(lb, (k_relax<3, T, StOp<3, T>, RB>), gb3, 256, 0, s, StOp<3, T>{L.g, L.s}, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpb3));
     }
     return hipGetLastError();
 }
@@ -3018,7 +3018,7 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, double w, int econ, c
 // Colour-1 half-sweep of the finest 2D level writing e_out in FP64 (the last
 // half-sweep of a complex64 cycle); false where that level is not served by the
 // one-thread-per-cell kernel.
-hipError_t launch_relax_to64(const LevelDesc<float>& L, double w, int econ, const float* b, const float* ein,
+hipError_t launch_relax_to64(const LevelDesc<float>& L, Damp w, int econ, const float* b, const float* ein,
                              double* eout, int nrhs, hipStream_t s, bool* done) {
     *done = false;
     if (!(L.g.dim == 2 && L.fine && cell2d_enabled() && 2 * L.g.N * (int64_t)sizeof(double) < (int64_t(1) << 32)))
@@ -3031,7 +3031,7 @@ hipError_t launch_relax_to64(const LevelDesc<float>& L, double w, int econ, cons
     const int rpc = (int)((nrhs + groups - 1) / groups);
     const dim3 gc(nblk(cells), (nrhs + rpc - 1) / rpc);
     EHH_LAUNCH_B(bytes_relax(L.g, true, nrhs, true, 4, 8, 4.0), (k_relax_cell2d<float, double>), gc, 256, 0, s,
-                 FineOp<2, float>{L.g, L.f}, 1, (float)w, econ, b, ein, eout, nrhs, stride, rpc);
+                 FineOp<2, float>{L.g, L.f}, 1, (float)w.u, (float)w.p, econ, b, ein, eout, nrhs, stride, rpc);
     *done = true;
     return hipGetLastError();
 }
@@ -3046,7 +3046,7 @@ bool relax_restrict_supported(const LevelDesc<T>& L, const Geo& gf, int nrhs) {
     return !(L.g.ncell >= 65536 && lds2d_enabled() && nrhs > 8);
 }
 template <typename T>
-hipError_t launch_relax_restrict(const LevelDesc<T>& L, double w, int econ, const Geo& gf, const T* rf, T* b,
+hipError_t launch_relax_restrict(const LevelDesc<T>& L, Damp w, int econ, const Geo& gf, const T* rf, T* b,
                                  T* eout, int nrhs, hipStream_t s) {
     const int64_t stride = 2 * L.g.N;
     const int64_t npair = (int64_t)(L.g.n[0] / 2) * L.g.n[1] * L.g.n[2];
@@ -3055,15 +3055,15 @@ hipError_t launch_relax_restrict(const LevelDesc<T>& L, double w, int econ, cons
     LaunchBytes lb = bytes_relax(L.g, false, nrhs, false, (int)sizeof(T), (int)sizeof(T), (double)sizeof(T));
     lb.mine += nrhs * 2.0 * sizeof(T) * (double)(gf.N + L.g.N);              // rf read, b written
     lb.model += nrhs * 2.0 * sizeof(T) * (gf.dim + 1) * (double)(gf.ncell + L.g.ncell);
-    EHH_LAUNCH_B(lb, (k_relax_st2d<T, sizeof(T) == 4, true>), gb, 256, 0, s, L.g, 0, (T)w, econ, (const T*)b,
+    EHH_LAUNCH_B(lb, (k_relax_st2d<T, sizeof(T) == 4, true>), gb, 256, 0, s, L.g, 0, (T)w.u, (T)w.p, econ, (const T*)b,
                        (const T*)nullptr, eout, nrhs, stride, rpb, L.sp.re[0], L.sp.im[0], L.sp.lanes, gf, rf, b);
     return hipGetLastError();
 }
 template bool relax_restrict_supported<float>(const LevelDesc<float>&, const Geo&, int);
 template bool relax_restrict_supported<double>(const LevelDesc<double>&, const Geo&, int);
-template hipError_t launch_relax_restrict<float>(const LevelDesc<float>&, double, int, const Geo&, const float*,
+template hipError_t launch_relax_restrict<float>(const LevelDesc<float>&, Damp, int, const Geo&, const float*,
                                                  float*, float*, int, hipStream_t);
-template hipError_t launch_relax_restrict<double>(const LevelDesc<double>&, double, int, const Geo&, const double*,
+template hipError_t launch_relax_restrict<double>(const LevelDesc<double>&, Damp, int, const Geo&, const double*,
                                                   double*, double*, int, hipStream_t);
 
 int64_t stored_plan_lanes(const Geo& g) {
@@ -3191,7 +3191,7 @@ hipError_t launch_to_half(const float* x, void* y, int64_t n, float inv_scale, h
 
 #define EHH_INST(T)                                                                                       \
     template hipError_t launch_apply<T>(const LevelDesc<T>&, const T*, const T*, T*, int, hipStream_t);  \
-    template hipError_t launch_relax<T>(const LevelDesc<T>&, int, double, int, const T*, const T*, T*,    \
+    template hipError_t launch_relax<T>(const LevelDesc<T>&, int, Damp, int, const T*, const T*, T*,      \
                                         int, hipStream_t);                                               \
     template hipError_t launch_restrict<T>(const Geo&, const Geo&, const T*, T*, int, hipStream_t);      \
     template hipError_t launch_prolong<T>(const Geo&, const Geo&, const T*, T*, int, hipStream_t);

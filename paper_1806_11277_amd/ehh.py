@@ -37,7 +37,9 @@ class ehh_options_t(ctypes.Structure):
                 ("restart", ctypes.c_int32), ("dd_parts", ctypes.c_int32 * 3),
                 ("dd_overlap", ctypes.c_int32), ("dd_pad", ctypes.c_int32),
                 ("dd_colors", ctypes.c_int32), ("damping", ctypes.c_double * EHH_MAX_LEVELS),
-                ("coarse_bits", ctypes.c_int32)]
+                ("coarse_bits", ctypes.c_int32), ("coarse_dd_parts", ctypes.c_int32 * 3),
+                ("coarse_dd_overlap", ctypes.c_int32), ("coarse_dd_colors", ctypes.c_int32),
+                ("damping_p", ctypes.c_double * EHH_MAX_LEVELS)]
 
 
 class ehh_stats_t(ctypes.Structure):
@@ -201,7 +203,9 @@ class Solver:
                  vanka: int = 1, precond_bits: int = 64, restart: int = 5,
                  dd_parts: Sequence[int] = (1, 1, 1), dd_overlap: int = 0, dd_pad: int = 0,
                  dd_colors: int = 1, damping: Optional[Sequence[float]] = None,
-                 mu_bar: float = 0.0, rho_bar: float = 0.0, coarse_bits: int = 32, stream=None):
+                 mu_bar: float = 0.0, rho_bar: float = 0.0, coarse_bits: int = 32,
+                 coarse_dd_parts: Sequence[int] = (1, 1, 1), coarse_dd_overlap: int = 2, coarse_dd_colors: int = 0,
+                 damping_p: Optional[Sequence[float]] = None, stream=None):
         import torch
         p = ehh_problem_t()
         p.dim = dim
@@ -215,6 +219,10 @@ class Solver:
         o = default_options()
         o.levels, o.cycle, o.cycle_level, o.nu1, o.nu2, o.vanka = levels, cycle, cycle_level, nu1, nu2, vanka
         o.precond_bits, o.restart, o.coarse_bits = precond_bits, restart, coarse_bits
+        cp = list(coarse_dd_parts) + [1] * (3 - len(coarse_dd_parts))
+        for a in range(3):
+            o.coarse_dd_parts[a] = int(cp[a])
+        o.coarse_dd_overlap, o.coarse_dd_colors = int(coarse_dd_overlap), int(coarse_dd_colors)
         dp = list(dd_parts) + [1] * (3 - len(dd_parts))
         for a in range(3):
             o.dd_parts[a] = int(dp[a])
@@ -222,6 +230,9 @@ class Solver:
         if damping is not None:
             for l, w in enumerate(damping[:EHH_MAX_LEVELS]):
                 o.damping[l] = float(w)
+        if damping_p is not None:
+            for l, w in enumerate(damping_p[:EHH_MAX_LEVELS]):
+                o.damping_p[l] = float(w)
         self.problem, self.options = p, o
         self.levels = int(levels)
         self.dim = dim
@@ -402,7 +413,10 @@ def solver_for_workload(w, **overrides):
     kw = dict(levels=w.levels, cycle=w.cycle, cycle_level=w.cycle_level, nu1=w.nu1, nu2=w.nu2, vanka=w.vanka,
               precond_bits=w.precond_bits, restart=w.restart, dd_parts=w.dd_parts,
               dd_overlap=w.dd_overlap, dd_pad=w.dd_pad, dd_colors=w.dd_colors, damping=w.damping,
-              abl_max=w.abl_max, atten0=w.atten0, coarse_bits=getattr(w, "coarse_bits", 32))
+              abl_max=w.abl_max, atten0=w.atten0, coarse_bits=getattr(w, "coarse_bits", 32),
+              coarse_dd_parts=getattr(w, "coarse_dd_parts", (1, 1, 1)),
+              coarse_dd_overlap=getattr(w, "coarse_dd_overlap", 2), coarse_dd_colors=getattr(w, "coarse_dd_colors", 0),
+              damping_p=getattr(w, "damping_p", None))
     kw.update(overrides)
     return Solver(w.dim, w.n, w.h, w.omega, kw.pop("shift", w.shift), w.abl_cells,
                   m["lam"], m["mu"], m["rho"], **kw)

@@ -53,7 +53,8 @@ def coarse_dd_of(w):
 def oracle_hierarchy(w, pb=None):
     pb = pb or oracle_problem(w)
     return mg.build_hierarchy(pb, w.levels, list(w.damping), economic=(w.vanka == 0), cycle=w.cycle,
-                              nu1=w.nu1, nu2=w.nu2, cycle_level=w.cycle_level, coarse_dd=coarse_dd_of(w))
+                              nu1=w.nu1, nu2=w.nu2, cycle_level=w.cycle_level, coarse_dd=coarse_dd_of(w),
+                              damping_p=(list(w.damping_p) if w.damping_p is not None else None))
 
 
 def oracle_dd(w, pb=None):
@@ -61,7 +62,8 @@ def oracle_dd(w, pb=None):
     return ddm.DDPreconditioner(pb, w.dd_parts[:w.dim], w.dd_overlap, w.dd_pad, w.levels,
                                 list(w.damping), economic=(w.vanka == 0), cycle=w.cycle,
                                 colours=(1 if w.dd_colors == 1 else 2 ** w.dim), abl_max=w.abl_max,
-                                coarse_dd=coarse_dd_of(w), cycle_level=w.cycle_level)
+                                coarse_dd=coarse_dd_of(w), cycle_level=w.cycle_level,
+                                damping_p=(list(w.damping_p) if w.damping_p is not None else None))
 
 
 def rand_cvec(N, nrhs, seed):

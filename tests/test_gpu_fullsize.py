@@ -314,3 +314,29 @@ def test_ragged_level1_relax_many_sources(ragged_oracle, colour):
         ref = H.relax(1, b[q], e[q], colour)
         assert np.linalg.norm(got[q] - ref) <= 1e-11 * np.linalg.norm(ref), q
     S.close()
+
+
+def test_c2_level1_relax_component_damping(c2_oracle):
+    """The LDS-staged half-sweep (256^2 Galerkin level, 12 sources) with the
+    component damping (w_u, w_p) = (0.6, 0.4), against the oracle."""
+    import torch
+    from oracle import multigrid as mg
+    w, pb, H = c2_oracle
+    say("[c2 level 1 half-sweep, 12 sources, component damping]")
+    H2 = mg.Hierarchy(H.A[0], pb.n, 2, [0.85], damping_p=[0.65])
+    H2.A[1] = H.A[1]
+    H2.blocks = [H2.blocks[0], mg.vanka_blocks(H.A[1], H.n[1])]
+    H2.damping, H2.damping_p = [0.85, 0.6], [0.65, 0.4]
+    S = _solver(w, damping=(0.85, 0.6, 0.5, 0.5), damping_p=(0.65, 0.4, 0.5, 0.5))
+    N = H.A[1].shape[0]
+    b = rand_cvec(N, 12, 170)
+    e = rand_cvec(N, 12, 171)
+    for colour in (0, 1):
+        out = torch.zeros_like(to_dev(b))
+        S.level_relax(0, 1, colour, to_dev(b), to_dev(e), out)
+        torch.cuda.synchronize()
+        got = from_dev(out)
+        for q in range(12):
+            ref = H2.relax(1, b[q], e[q], colour)
+            assert np.linalg.norm(got[q] - ref) <= 1e-11 * np.linalg.norm(ref), (colour, q)
+    S.close()

@@ -187,3 +187,31 @@ def test_dense_inverse_of_the_whole_grid(nrhs):
         ref = lu.solve(r_[r])
         assert np.linalg.norm(got[r] - ref) <= 1e-10 * np.linalg.norm(ref)
     S.close()
+
+
+@pytest.mark.parametrize("bits", [64, 32])
+@pytest.mark.parametrize("name", ["het2d", "het3d"])
+def test_relax_component_damping(name, bits):
+    """Half-sweeps with the component damping (w_u, w_p) = (0.85, 0.65) on the
+    finest level and (0.6, 0.4) below (section 5.2, Table 2), every level and
+    colour from a nonzero e_in, against the oracle's damped block update."""
+    import torch
+    w = CASES[name](precond_bits=bits, damping=(0.85, 0.6), damping_p=(0.65, 0.4))
+    say(f"[component damping {name} bits={bits}]")
+    H = oracle_hierarchy(w)
+    S = _solver(w)
+    dt = torch.float32 if bits == 32 else torch.float64
+    tol = 1e-11 if bits == 64 else 2e-5
+    for l in range(w.levels - 1):
+        N = H.A[l].shape[0]
+        b = rand_cvec(N, 2, 150 + l)
+        e = rand_cvec(N, 2, 160 + l)
+        for colour in (0, 1):
+            out = torch.zeros((2, 2 * N), dtype=dt, device="cuda")
+            S.level_relax(0, l, colour, to_dev(b, dt), to_dev(e, dt), out)
+            torch.cuda.synchronize()
+            got = from_dev(out)
+            for r in range(2):
+                ref = H.relax(l, b[r], e[r], colour)
+                assert rel_err(got[r], ref) < tol, (l, colour, r)
+    S.close()

@@ -602,3 +602,38 @@ def test_mg_dd_preconditioned_fgmres_converges_like_mg_exact():
         assert st["converged"] and st["rel_res_true"] <= 1e-8
         its[key] = st["iters"]
     assert its["dd"] <= 1.5 * its["exact"] + 5, its
+
+
+@pytest.mark.parametrize("economic", [False, True])
+def test_component_damping_leaves_the_undamped_fraction_of_each_block_row(economic):
+    """Damped block update with W = diag(w_u, .., w_u, w_p) (section 5.2): for a
+    cell K of the colour whose unknowns couple to no other cell of that colour,
+    solving its block again after the half-sweep gives (I - W) times the block
+    solution before it, i.e. the fraction 1 - w_u of the displacement rows and
+    1 - w_p of the pressure row remains."""
+    n = (10, 8)
+    lam, mu, rho, gam = _hetero(n, 50)
+    A = disc.assemble(n, 1.0, 0.8, lam, mu, rho, gam, 0.5)
+    B, dofs, colour = mg.vanka_blocks(A, n, economic)
+    rng = np.random.default_rng(51)
+    b = rng.standard_normal(A.shape[0]) + 1j * rng.standard_normal(A.shape[0])
+    e0 = np.zeros(A.shape[0], complex)
+    wu, wp = 0.85, 0.65
+    e1 = mg.vanka_half_sweep(A, B, dofs, colour, 0, b, e0, wu, wp)
+    r0, r1 = b - A @ e0, b - A @ e1
+    cell = 3 * n[0] + 5          # interior red cell
+    assert colour[cell] == 0
+    d = dofs[cell]
+    before = np.linalg.solve(B[cell], r0[d])
+    after = np.linalg.solve(B[cell], r1[d])
+    # the residual on K's rows also changed through the neighbours' updates: take
+    # the block's own part only (the neighbours of a red cell are black)
+    own = np.zeros(A.shape[0], complex)
+    own[d] = e1[d]
+    after_own = np.linalg.solve(B[cell], (b - A @ own)[d])
+    W = np.array([wu] * 4 + [wp])
+    if not economic:
+        assert np.max(np.abs(after_own - (1 - W) * before)) <= 1e-12 * np.max(np.abs(before))
+    else:   # the economic block is not the cell's full matrix: only the diagonal scaling is exact
+        assert np.max(np.abs(e1[d] - W * before)) <= 1e-12 * np.max(np.abs(before))
+    assert np.linalg.norm(after) > 0

@@ -52,6 +52,7 @@ class Workload:
     coarse_dd_parts: Tuple[int, ...] = (1, 1, 1)   # subdomains of the coarsest level (MG-DD); 1s: exact
     coarse_dd_overlap: int = 2
     coarse_dd_colors: int = 0       # 0: Algorithm 2 over the coarsest level's subdomains, 1: one colour
+    damping_p: Tuple[float, ...] = None   # pressure-row damping per level (component damping); None: = damping
     sources_fn: Callable[["Workload"], List[Source]] = None
     receivers_fn: Callable[["Workload"], List[Tuple[int, Tuple[int, ...]]]] = None
     true_media_fn: Callable[[], dict] = None
