@@ -245,29 +245,34 @@ def errors_vs_oracle(w, X, lu):
 
 def poisson_sweep_report():
     """Preconditioning cycles to 1e-6 for constant mu = rho = 1 and lambda from 0.5
-    to 16 (section 6, Fig. 5), full and economic Vanka, on the grids whose
-    exact coarsest level fits a dense inverse."""
+    to 16 (section 6, Fig. 5), full and economic Vanka, on 256x128, 512x256 and
+    1024x512 (its coarsest level solved by DD), and Table 2's rows (lambda = 16,
+    constant against component damping)."""
     import torch
     from paper_1806_11277_amd import ehh
-    from workloads.configs import poisson_sweep, SWEEP_LAMBDAS, SWEEP_GRIDS
-    out = {"experiment": "Poisson-ratio sweep, constant mu = rho = 1", "lambda": list(SWEEP_LAMBDAS), "grids": []}
-    for nx in (256, 512):
+    from workloads.configs import poisson_sweep, SWEEP_LAMBDAS, SWEEP_GRIDS, SWEEP_COARSE_DD
+
+    def iters(w):
+        S = ehh.solver_for_workload(w)
+        b = rhs_tensor(S, w)
+        x = torch.zeros_like(b)
+        st, stats = S.solve(b, x, tol=1e-6, maxit=600)
+        torch.cuda.synchronize()
+        S.close()
+        print(f"[sweep] {w.name}: {stats[0]['iters'] if st == 0 else None}", file=sys.stderr, flush=True)
+        return stats[0]["iters"] if st == 0 else None
+
+    out = {"experiment": "Poisson-ratio sweep, constant mu = rho = 1", "lambda": list(SWEEP_LAMBDAS), "grids": [],
+           "table2": []}
+    for nx in (256, 512, 1024):
         row = {"cells": [nx, nx // 2], "omega_over_pi": 3 * nx // 256, "levels": SWEEP_GRIDS[nx][0],
-               "shift": SWEEP_GRIDS[nx][1]}
+               "shift": SWEEP_GRIDS[nx][1], "coarse_dd_parts": list(SWEEP_COARSE_DD.get(nx, ((1, 1, 1), 0))[0][:2]),
+               "coarse_dd_overlap": SWEEP_COARSE_DD.get(nx, ((1, 1, 1), 0))[1]}
         for vanka, key in ((1, "full_vanka"), (0, "economic_vanka")):
-            its = []
-            for lam in SWEEP_LAMBDAS:
-                w = poisson_sweep(nx, lam, vanka)
-                S = ehh.solver_for_workload(w)
-                b = rhs_tensor(S, w)
-                x = torch.zeros_like(b)
-                st, stats = S.solve(b, x, tol=1e-6, maxit=600)
-                torch.cuda.synchronize()
-                S.close()
-                its.append(stats[0]["iters"] if st == 0 else None)
-                print(f"[sweep] {w.name}: {its[-1]}", file=sys.stderr, flush=True)
-            row[key] = its
+            row[key] = [iters(poisson_sweep(nx, lam, vanka)) for lam in SWEEP_LAMBDAS]
         out["grids"].append(row)
+        out["table2"].append({"cells": [nx, nx // 2], "red_black_constant_0.75": iters(poisson_sweep(nx, 16.0, 1)),
+                              "red_black_component_0.85_0.65": iters(poisson_sweep(nx, 16.0, 1, "component"))})
     return out
 
 

@@ -252,26 +252,37 @@ def _constant_media(n, lam: float):
     return dict(lam=lam * one, mu=one.copy(), rho=one.copy(), vp=np.sqrt(lam + 2.0) * one, vs=one.copy())
 
 
-# Poisson-ratio sweep (section 6, first experiment): constant mu = rho = 1, lambda
-# from 0.5 to 16 (Poisson ratio 0.17 to 0.47) on 256x128, 512x256 and 1024x512
-# cells of a 16 x 8 box (h = 1/16, 1/32, 1/64) at w = 3 pi, 6 pi, 12 pi (10.7 cells
-# per shear wavelength), 20-cell layer, W(1,1) cycles with red-black Vanka
-# damped 0.75 / 0.5 / 0.25 and the shifts of section 6 (0.3 for three levels,
-# 0.4 for four and five), one x-force in the middle of the top, 5 cells deep.
+# Poisson-ratio sweep (section 6, first experiment, Fig. 5): constant mu = rho = 1,
+# lambda from 0.5 to 16 (Poisson ratio 0.17 to 0.47) on 256x128, 512x256 and
+# 1024x512 cells of a 16 x 8 box (h = 1/16, 1/32, 1/64) at w = 3 pi, 6 pi, 12 pi
+# (10.7 cells per shear wavelength), 20-cell layer, three-level W(1,1) cycles
+# with red-black Vanka damped 0.75 / 0.5 and the shift of section 6 for three
+# levels (0.3), one x-force in the middle of the top, 5 cells deep.  The
+# 1024x512 grid's 256x128 coarsest level is solved by 8 x 4 overlapping
+# subdomains (MG-DD, section 4): its dense inverse would need 154 GB.  Measured
+# on MI355X (full Vanka, lambda 0.5 / 16): overlap 2 gives 113 / 264 cycles,
+# overlap 6 gives 109 / 124, 4 x 2 subdomains with overlap 8 give 109 / 125.
+# Table 2: lambda = 16 with constant damping (0.75, 0.5) against the
+# component damping (w_u, w_p) = (0.85, 0.65) on the finest grid, (0.6, 0.4) on
+# the second.
 SWEEP_LAMBDAS = (0.5, 1.0, 2.0, 4.0, 8.0, 16.0)
-SWEEP_GRIDS = {256: (3, 0.3), 512: (3, 0.3), 1024: (4, 0.4)}   # n_x: (levels, shift)
+SWEEP_GRIDS = {256: (3, 0.3), 512: (3, 0.3), 1024: (3, 0.3)}   # n_x: (levels, shift)
+SWEEP_COARSE_DD = {1024: ((8, 4, 1), 6)}                         # coarsest-level subdomains, overlap
+TABLE2_DAMPING = {"constant": ((0.75, 0.5), None), "component": ((0.85, 0.6), (0.65, 0.4))}
 
 
-def poisson_sweep(nx: int, lam: float, vanka: int = 1) -> Workload:
+def poisson_sweep(nx: int, lam: float, vanka: int = 1, damping: str = "constant") -> Workload:
     levels, shift = SWEEP_GRIDS[nx]
     n = (nx, nx // 2)
-    damping = (0.75, 0.5, 0.25, 0.25)[:levels - 1]
+    dmp, dmp_p = TABLE2_DAMPING[damping]
     return Workload(
-        name=f"e3_const{nx}_lam{lam:g}_{'full' if vanka else 'econ'}",
+        name=f"e3_const{nx}_lam{lam:g}_{'full' if vanka else 'econ'}_{damping}",
         description=f"constant mu = rho = 1, lambda = {lam:g}, {nx}x{nx // 2} cells, h = {16 / nx:g}",
         dim=2, n=n, h=16.0 / nx, media_fn=lambda: _constant_media(n, lam), ppw=32.0 / 3.0,
-        abl_cells=(20, 20), shift=shift, levels=levels, cycle=2, damping=damping, vanka=vanka,
-        precond_bits=64, tol=1e-6, maxit=600, sources_fn=_src_top_single)
+        abl_cells=(20, 20), shift=shift, levels=levels, cycle=2, damping=dmp, damping_p=dmp_p, vanka=vanka,
+        precond_bits=64, tol=1e-6, maxit=600, sources_fn=_src_top_single,
+        coarse_dd_parts=SWEEP_COARSE_DD.get(nx, ((1, 1, 1), 2))[0],
+        coarse_dd_overlap=SWEEP_COARSE_DD.get(nx, ((1, 1, 1), 2))[1])
 
 
 def get_config(name: str) -> Workload:
