@@ -117,6 +117,11 @@ typedef struct {
     int32_t coarse_dd_colors;    /* 0 (default): Algorithm 2 over the coarsest level's
                                subdomains (each colour from the residual left by the
                                previous ones); 1: one colour, corrections averaged */
+    int32_t dd_batch;       /* 1 (default): with domain decomposition, each step of the
+                               subdomains' cycles (and their gathers and scatters) runs
+                               for all subdomains of a colour in one launch over a flat
+                               (subdomain, block) list, up to 8 subdomains per launch;
+                               0: one launch per subdomain and step */
     double  damping_p[EHH_MAX_LEVELS];  /* Vanka damping of the pressure row of a cell
                                block per level (component-dependent damping (w_u, w_p),
                                section 5.2; damping[] then damps the displacement rows);

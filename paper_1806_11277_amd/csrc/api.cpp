@@ -27,6 +27,7 @@
 #include "ehh.h"
 #include "internal.hpp"
 #include "launchlog.hpp"
+#include "batch.hpp"
 
 // ------------------------------------------------------------------ launch log
 // On for the calling thread only, while ehh_profile_precondition runs one
@@ -41,7 +42,11 @@ struct LogRec {
 thread_local bool t_log_on = false;
 thread_local std::vector<LogRec> t_log;
 }  // namespace
+thread_local bool t_batch_on = false;
+thread_local std::vector<BatchRec> t_batch;
 bool launch_log_on() { return t_log_on; }
+bool batch_recording() { return t_batch_on; }
+void batch_record(BatchRec&& r) { t_batch.push_back(std::move(r)); }
 void launch_log_add(const void* kernel, LaunchBytes bytes, std::function<void(hipStream_t)> again) {
     t_log.push_back(LogRec{kernel, bytes, std::move(again)});
 }
@@ -242,6 +247,8 @@ struct Sub {
     // its FP64 workspaces: right-hand side and iterate (complex64 cycle), residual,
     // and the boxes' local right-hand sides and corrections
     double *cdd_r = nullptr, *cdd_e = nullptr, *cdd_t = nullptr, *cdd_lr = nullptr, *cdd_le = nullptr;
+    double* coarse_ws = nullptr;   // partial sums of the split coarse apply (one per subdomain: the
+                                   // coarse applies of several subdomains may run in one launch)
 };
 
 }  // namespace
@@ -260,7 +267,6 @@ struct ehh_ctx {
     const int* cnt_cell[3] = {nullptr, nullptr, nullptr};
     const int* cnt_face[3] = {nullptr, nullptr, nullptr};
     int ws_rhs = 0;
-    double* coarse_ws = nullptr;   // partial sums of the split coarse apply
     // Krylov workspace
     int kr_rhs = 0;
     double *V = nullptr, *Z = nullptr, *w = nullptr, *R = nullptr, *H = nullptr, *cs = nullptr, *g = nullptr;
@@ -440,17 +446,18 @@ int32_t ensure_ws(ehh_ctx* c, int nrhs) {
         }
     }
     // the split depends on the batch size: cover every batch up to nrhs
-    size_t cw = 0;
-    for (const Sub& S : c->subs)
+    for (Sub& S : c->subs) {
+        size_t cw = 0;
         for (int q = 1; q <= nrhs; ++q) {
             if (S.cdd.active())
                 for (const CoarseBox& B : S.cdd.box) cw = std::max(cw, coarse_ws_doubles(B.g.N, q));
             else
                 cw = std::max(cw, coarse_ws_doubles(S.lev.back().g.N, q));
         }
-    c->release(c->coarse_ws);
-    c->coarse_ws = nullptr;
-    if (cw) CHK(c->alloc((void**)&c->coarse_ws, sizeof(double) * cw));
+        c->release(S.coarse_ws);
+        S.coarse_ws = nullptr;
+        if (cw) CHK(c->alloc((void**)&S.coarse_ws, sizeof(double) * cw));
+    }
     c->ws_rhs = nrhs;
     return EHH_OK;
 }
@@ -519,7 +526,7 @@ int32_t coarse_solve(ehh_ctx* c, Sub& S, const T* b, T* e, bool zero_init, int n
     Level& L = S.lev.back();
     const int64_t Nc = L.g.N;
     if (!S.cdd.active()) {
-        HIPCHK(launch_coarse_apply<T>(S.inv, S.sym, Nc, b, e, nrhs, c->coarse_ws, s));
+        HIPCHK(launch_coarse_apply<T>(S.inv, S.sym, Nc, b, e, nrhs, S.coarse_ws, s));
         return EHH_OK;
     }
     const CoarseDD& D = S.cdd;
@@ -552,7 +559,7 @@ int32_t coarse_solve(ehh_ctx* c, Sub& S, const T* b, T* e, bool zero_init, int n
             const CoarseBox& B = D.box[bi];
             const size_t off = 2 * (size_t)nrhs * B.base;
             HIPCHK(launch_coarse_apply<double>(B.inv, B.sym, B.g.N, S.cdd_lr + off, S.cdd_le + off, nrhs,
-                                               c->coarse_ws, s));
+                                               S.coarse_ws, s));
         }
         if (one)   // the boxes overlap: one scatter per box, in turn
             for (int bi = b0; bi < b1; ++bi) {
@@ -641,6 +648,54 @@ SubMap submap(const ehh_ctx* c, const Sub& S) {
     return m;
 }
 
+// Runs fn(S) for every subdomain of subs with the kernel launches recorded, then
+// launches position k of every subdomain's launch sequence as one batch launch
+// (the same step of all subdomains in one launch over a flat (subdomain, block)
+// list).  The sequences coincide when the subdomains' levels take the same
+// kernels; where they do not, every subdomain's steps are launched on their own.
+int32_t run_batched(ehh_ctx* c, const std::vector<Sub*>& subs, const std::function<int32_t(Sub&)>& fn,
+                    hipStream_t s) {
+    if (subs.size() == 1 || !c->opt.dd_batch) {
+        for (Sub* S : subs) CHK(fn(*S));
+        return EHH_OK;
+    }
+    std::vector<std::vector<BatchRec>> seq(subs.size());
+    for (size_t i = 0; i < subs.size(); ++i) {
+        t_batch.clear();
+        t_batch_on = true;
+        const int32_t st = fn(*subs[i]);
+        t_batch_on = false;
+        seq[i].swap(t_batch);
+        if (st != EHH_OK) return st;
+    }
+    bool same = true;
+    for (const auto& q : seq) {
+        if (q.size() != seq[0].size()) {
+            same = false;
+            break;
+        }
+        for (size_t k = 0; k < q.size() && same; ++k)
+            same = q[k].kernel == seq[0][k].kernel && q[k].block.x == seq[0][k].block.x &&
+                   q[k].shmem == seq[0][k].shmem;
+    }
+    if (!same) {
+        for (const auto& q : seq)
+            for (const BatchRec& r : q) {
+                const BatchRec* one = &r;
+                HIPCHK(r.launch(&one, 1, s));
+            }
+        return EHH_OK;
+    }
+    std::vector<const BatchRec*> recs;
+    for (size_t k = 0; k < seq[0].size(); ++k)
+        for (size_t i0 = 0; i0 < seq.size(); i0 += kMaxBatch) {
+            recs.clear();
+            for (size_t i = i0; i < seq.size() && i < i0 + kMaxBatch; ++i) recs.push_back(&seq[i][k]);
+            HIPCHK(recs[0]->launch(recs.data(), (int)recs.size(), s));
+        }
+    return EHH_OK;
+}
+
 // z = M^{-1} v (FP64 global vectors).
 // v_in_r0: the complex64 copy of v is already in the cycle's input buffer
 // (written by the scaling that produced v).
@@ -660,12 +715,16 @@ int32_t precondition_t(ehh_ctx* c, const double* v, double* z, int nrhs, hipStre
     }
     HIPCHK(launch_zero(z, sizeof(double) * 2 * (size_t)gg.N * nrhs, s));
     if (c->opt.dd_colors == 1) {
-        for (Sub& S : c->subs) {
-            const SubMap m = submap(c, S);
-            HIPCHK(launch_dd_gather<T>(gg, S.lev[0].g, m, v, (T*)S.r0, nrhs, s));
-            CHK(cycle<T>(c, S, 0, (const T*)S.r0, (T*)S.e0, true, nrhs, s));
-            HIPCHK(launch_dd_scatter<T>(gg, S.lev[0].g, m, (const T*)S.e0, z, nrhs, 1, s));
-        }
+        std::vector<Sub*> all;
+        for (Sub& S : c->subs) all.push_back(&S);
+        // the gathers and cycles of all subdomains in batch launches; the averaging
+        // scatters one subdomain at a time, their extents overlapping
+        CHK(run_batched(c, all, [&](Sub& S) -> int32_t {
+            HIPCHK(launch_dd_gather<T>(gg, S.lev[0].g, submap(c, S), v, (T*)S.r0, nrhs, s));
+            return cycle<T>(c, S, 0, (const T*)S.r0, (T*)S.e0, true, nrhs, s);
+        }, s));
+        for (Sub& S : c->subs)
+            HIPCHK(launch_dd_scatter<T>(gg, S.lev[0].g, submap(c, S), (const T*)S.e0, z, nrhs, 1, s));
         return EHH_OK;
     }
     // Algorithm 2: colours in turn, each from the residual of the unshifted operator
@@ -678,22 +737,22 @@ int32_t precondition_t(ehh_ctx* c, const double* v, double* z, int nrhs, hipStre
     A.f = FineCoef<double>{c->fine64, c->fine64 + n, c->fine64 + 2 * n, c->fine64 + 3 * n,
                            c->omega_nd * c->omega_nd, 0.0};
     for (int col = 0; col < ncol; ++col) {
+        std::vector<Sub*> mine;
+        for (Sub& S : c->subs)
+            if (S.colour == col) mine.push_back(&S);
         // every subdomain of the colour takes its residual before any of them
-        // adds its correction (the subdomains of one colour are handled together)
-        for (Sub& S : c->subs) {
-            if (S.colour != col) continue;
+        // adds its correction: the merged launches keep that order (all gathers,
+        // then each cycle step, then all scatters, the colour's extents disjoint)
+        CHK(run_batched(c, mine, [&](Sub& S) -> int32_t {
             const SubMap m = submap(c, S);
             if (col == 0)   // z = 0: the local residual is v itself
                 HIPCHK(launch_dd_gather<T>(gg, S.lev[0].g, m, v, (T*)S.r0, nrhs, s));
             else            // local residual of the unshifted operator on the extent only
                 HIPCHK(launch_dd_gather_res<T>(gg, S.lev[0].g, m, A.f, v, z, (T*)S.r0, nrhs, s));
-        }
-        for (Sub& S : c->subs) {
-            if (S.colour != col) continue;
-            const SubMap m = submap(c, S);
             CHK(cycle<T>(c, S, 0, (const T*)S.r0, (T*)S.e0, true, nrhs, s));
             HIPCHK(launch_dd_scatter<T>(gg, S.lev[0].g, m, (const T*)S.e0, z, nrhs, 0, s));
-        }
+            return EHH_OK;
+        }, s));
     }
     return EHH_OK;
 }
@@ -736,6 +795,7 @@ int32_t check_problem(const ehh_problem_t* p, const ehh_options_t* o) {
         if (o->coarse_dd_parts[a] < 1) return fail(EHH_ERR_INVALID, "coarse_dd_parts must be >= 1");
     if (o->coarse_dd_overlap < 0) return fail(EHH_ERR_INVALID, "coarse_dd_overlap >= 0");
     if (o->coarse_dd_colors != 0 && o->coarse_dd_colors != 1) return fail(EHH_ERR_INVALID, "coarse_dd_colors must be 0 or 1");
+    if (o->dd_batch != 0 && o->dd_batch != 1) return fail(EHH_ERR_INVALID, "dd_batch must be 0 or 1");
     for (int a = 0; a < p->dim; ++a)
         if (o->dd_parts[a] < 1 || o->dd_parts[a] > p->n[a]) return fail(EHH_ERR_INVALID, "dd_parts out of range");
     if (o->dd_overlap < 0 || o->dd_pad < 0) return fail(EHH_ERR_INVALID, "dd_overlap, dd_pad >= 0");
@@ -1286,6 +1346,18 @@ std::string kernel_name(const void* k) {
     std::free(d);
     if (n.compare(0, 5, "void ") == 0) n = n.substr(5);
     for (size_t p = n.find("ehh::"); p != std::string::npos; p = n.find("ehh::")) n.erase(p, 5);
+    // a batch kernel's first template argument is its argument pack: left out
+    const size_t pk = n.find("_batch<Pack<");
+    if (pk != std::string::npos) {
+        size_t i = pk + 7, depth = 0;
+        for (; i < n.size(); ++i) {
+            if (n[i] == '<') ++depth;
+            else if (n[i] == '>' && --depth == 0) break;
+        }
+        size_t j = i + 1;
+        while (j < n.size() && (n[j] == ',' || n[j] == ' ')) ++j;
+        n.erase(pk + 7, j - (pk + 7));
+    }
     int depth = 0;
     for (size_t i = 0; i < n.size(); ++i) {
         if (n[i] == '<') ++depth;
@@ -1353,6 +1425,7 @@ void ehh_default_options(ehh_options_t* o) {
     o->coarse_dd_parts[0] = o->coarse_dd_parts[1] = o->coarse_dd_parts[2] = 1;
     o->coarse_dd_overlap = 2;
     o->coarse_dd_colors = 0;
+    o->dd_batch = 1;
     o->restart = 5;
     o->dd_parts[0] = o->dd_parts[1] = o->dd_parts[2] = 1;
     o->dd_colors = 1;

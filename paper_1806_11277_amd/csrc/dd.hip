@@ -6,6 +6,7 @@
 // that own an unknown (one colour) or added unweighted (Algorithm 2).
 #include "internal.hpp"
 #include "launchlog.hpp"
+#include "batch.hpp"
 #include "ops.hpp"
 
 namespace ehh {
@@ -41,9 +42,8 @@ EHH_DEV int64_t local_to_global(const Geo& gg, const Geo& gl, const SubMap& m, i
 }
 
 template <int D, typename T>
-__global__ __launch_bounds__(256) void k_dd_gather(Geo gg, Geo gl, SubMap m, const double* __restrict__ v,
-                                                   T* __restrict__ out, int nrhs) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+EHH_DEV void k_dd_gather_body(VB ehh_vb, const Geo& gg, const Geo& gl, const SubMap& m, const double* __restrict__ v, T* __restrict__ out, int nrhs) {
+    const int64_t t = (int64_t)ehh_vb.x * blockDim.x + threadIdx.x;
     if (t >= gl.N) return;
     int k, cnt;
     const int64_t gi = local_to_global<D>(gg, gl, m, t, k, &cnt);
@@ -54,11 +54,22 @@ __global__ __launch_bounds__(256) void k_dd_gather(Geo gg, Geo gl, SubMap m, con
         o[gl.N + t] = gi >= 0 ? (T)vv[gg.N + gi] : T(0);
     }
 }
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_dd_gather(Geo gg, Geo gl, SubMap m, const double* __restrict__ v,
+                                                   T* __restrict__ out, int nrhs) {
+    k_dd_gather_body<D, T>(single_block<false>(), gg, gl, m, v, out, nrhs);
+}
+template <class PK, int D, typename T>
+__global__ __launch_bounds__(256) void k_dd_gather_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<false>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_dd_gather_body<D, T>(ehh_vb, a...); }, b.arg[ehh_s]);
+}
 
 template <int D, typename T>
-__global__ __launch_bounds__(256) void k_dd_scatter(Geo gg, Geo gl, SubMap m, const T* __restrict__ e,
-                                                    double* __restrict__ z, int nrhs, int weighted) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+EHH_DEV void k_dd_scatter_body(VB ehh_vb, const Geo& gg, const Geo& gl, const SubMap& m, const T* __restrict__ e, double* __restrict__ z, int nrhs, int weighted) {
+    const int64_t t = (int64_t)ehh_vb.x * blockDim.x + threadIdx.x;
     if (t >= gl.N) return;
     int k, cnt;
     const int64_t gi = local_to_global<D>(gg, gl, m, t, k, &cnt);
@@ -71,14 +82,26 @@ __global__ __launch_bounds__(256) void k_dd_scatter(Geo gg, Geo gl, SubMap m, co
         zz[gg.N + gi] += w * (double)ee[gl.N + t];
     }
 }
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_dd_scatter(Geo gg, Geo gl, SubMap m, const T* __restrict__ e,
+                                                    double* __restrict__ z, int nrhs, int weighted) {
+    k_dd_scatter_body<D, T>(single_block<false>(), gg, gl, m, e, z, nrhs, weighted);
+}
+template <class PK, int D, typename T>
+__global__ __launch_bounds__(256) void k_dd_scatter_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<false>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_dd_scatter_body<D, T>(ehh_vb, a...); }, b.arg[ehh_s]);
+}
 
 template <typename T>
 hipError_t launch_dd_gather(const Geo& gg, const Geo& gl, const SubMap& m, const double* v, T* out, int nrhs,
                             hipStream_t s) {
     if (gg.dim == 2)
-        EHH_LAUNCH_B(bytes_plain(nrhs * (double)gl.N * (16.0 + 2.0 * sizeof(T))), (k_dd_gather<2, T>), nblk(gl.N), 256, 0, s, gg, gl, m, v, out, nrhs);
+        EHH_LAUNCHK(bytes_plain(nrhs * (double)gl.N * (16.0 + 2.0 * sizeof(T))), k_dd_gather, (2, T), nblk(gl.N), 256, 0, s, gg, gl, m, v, out, nrhs);
     else
-        EHH_LAUNCH_B(bytes_plain(nrhs * (double)gl.N * (16.0 + 2.0 * sizeof(T))), (k_dd_gather<3, T>), nblk(gl.N), 256, 0, s, gg, gl, m, v, out, nrhs);
+        EHH_LAUNCHK(bytes_plain(nrhs * (double)gl.N * (16.0 + 2.0 * sizeof(T))), k_dd_gather, (3, T), nblk(gl.N), 256, 0, s, gg, gl, m, v, out, nrhs);
     return hipGetLastError();
 }
 
@@ -86,9 +109,9 @@ template <typename T>
 hipError_t launch_dd_scatter(const Geo& gg, const Geo& gl, const SubMap& m, const T* e, double* z, int nrhs,
                              int weighted, hipStream_t s) {
     if (gg.dim == 2)
-        EHH_LAUNCH_B(bytes_plain(nrhs * (double)gl.N * (32.0 + 2.0 * sizeof(T))), (k_dd_scatter<2, T>), nblk(gl.N), 256, 0, s, gg, gl, m, e, z, nrhs, weighted);
+        EHH_LAUNCHK(bytes_plain(nrhs * (double)gl.N * (32.0 + 2.0 * sizeof(T))), k_dd_scatter, (2, T), nblk(gl.N), 256, 0, s, gg, gl, m, e, z, nrhs, weighted);
     else
-        EHH_LAUNCH_B(bytes_plain(nrhs * (double)gl.N * (32.0 + 2.0 * sizeof(T))), (k_dd_scatter<3, T>), nblk(gl.N), 256, 0, s, gg, gl, m, e, z, nrhs, weighted);
+        EHH_LAUNCHK(bytes_plain(nrhs * (double)gl.N * (32.0 + 2.0 * sizeof(T))), k_dd_scatter, (3, T), nblk(gl.N), 256, 0, s, gg, gl, m, e, z, nrhs, weighted);
     return hipGetLastError();
 }
 
@@ -105,10 +128,8 @@ template hipError_t launch_dd_scatter<double>(const Geo&, const Geo&, const SubM
 // global (unshifted) operator, evaluated only at the unknowns of the
 // subdomain's extent and written straight into its padded local vector.
 template <int D, typename T>
-__global__ __launch_bounds__(256) void k_dd_gather_res(Geo gg, Geo gl, SubMap m, FineCoef<double> A,
-                                                       const double* __restrict__ v, const double* __restrict__ z,
-                                                       T* __restrict__ out, int nrhs) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+EHH_DEV void k_dd_gather_res_body(VB ehh_vb, const Geo& gg, const Geo& gl, const SubMap& m, const FineCoef<double>& A, const double* __restrict__ v, const double* __restrict__ z, T* __restrict__ out, int nrhs) {
+    const int64_t t = (int64_t)ehh_vb.x * blockDim.x + threadIdx.x;
     if (t >= gl.N) return;
     int k, cnt;
     const int64_t gi = local_to_global<D>(gg, gl, m, t, k, &cnt);
@@ -167,15 +188,28 @@ __global__ __launch_bounds__(256) void k_dd_gather_res(Geo gg, Geo gl, SubMap m,
         }
     }
 }
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_dd_gather_res(Geo gg, Geo gl, SubMap m, FineCoef<double> A,
+                                                       const double* __restrict__ v, const double* __restrict__ z,
+                                                       T* __restrict__ out, int nrhs) {
+    k_dd_gather_res_body<D, T>(single_block<false>(), gg, gl, m, A, v, z, out, nrhs);
+}
+template <class PK, int D, typename T>
+__global__ __launch_bounds__(256) void k_dd_gather_res_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<false>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_dd_gather_res_body<D, T>(ehh_vb, a...); }, b.arg[ehh_s]);
+}
 
 template <typename T>
 hipError_t launch_dd_gather_res(const Geo& gg, const Geo& gl, const SubMap& m, const FineCoef<double>& A,
                                 const double* v, const double* z, T* out, int nrhs, hipStream_t s) {
     if (16 * gg.N >= (int64_t(1) << 32)) return hipErrorInvalidValue;   // 32-bit byte offsets per source
     if (gg.dim == 2)
-        EHH_LAUNCH_B(bytes_plain(nrhs * (double)gl.N * (32.0 + 2.0 * sizeof(T)) + 32.0 * gl.ncell), (k_dd_gather_res<2, T>), nblk(gl.N), 256, 0, s, gg, gl, m, A, v, z, out, nrhs);
+        EHH_LAUNCHK(bytes_plain(nrhs * (double)gl.N * (32.0 + 2.0 * sizeof(T)) + 32.0 * gl.ncell), k_dd_gather_res, (2, T), nblk(gl.N), 256, 0, s, gg, gl, m, A, v, z, out, nrhs);
     else
-        EHH_LAUNCH_B(bytes_plain(nrhs * (double)gl.N * (32.0 + 2.0 * sizeof(T)) + 32.0 * gl.ncell), (k_dd_gather_res<3, T>), nblk(gl.N), 256, 0, s, gg, gl, m, A, v, z, out, nrhs);
+        EHH_LAUNCHK(bytes_plain(nrhs * (double)gl.N * (32.0 + 2.0 * sizeof(T)) + 32.0 * gl.ncell), k_dd_gather_res, (3, T), nblk(gl.N), 256, 0, s, gg, gl, m, A, v, z, out, nrhs);
     return hipGetLastError();
 }
 template hipError_t launch_dd_gather_res<float>(const Geo&, const Geo&, const SubMap&, const FineCoef<double>&,
@@ -236,11 +270,9 @@ hipError_t launch_box_stencil(const Geo& gc, const double* stc, const Geo& gb, d
 }
 
 // loc(box) <- src restricted to the box, for the local unknowns [j0, j1)
-__global__ __launch_bounds__(256) void k_box_gather(const int* __restrict__ map, const int* __restrict__ bsub,
-                                                    const int64_t* __restrict__ bbase, const int* __restrict__ bn,
-                                                    int64_t j0, int64_t j1, const double* __restrict__ src,
-                                                    int64_t Nc, double* __restrict__ loc, int nrhs) {
-    const int64_t j = j0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+template <int Z = 0>
+EHH_DEV void k_box_gather_body(VB ehh_vb, const int* __restrict__ map, const int* __restrict__ bsub, const int64_t* __restrict__ bbase, const int* __restrict__ bn, int64_t j0, int64_t j1, const double* __restrict__ src, int64_t Nc, double* __restrict__ loc, int nrhs) {
+    const int64_t j = j0 + (int64_t)ehh_vb.x * blockDim.x + threadIdx.x;
     if (j >= j1) return;
     const int b = bsub[j];
     const int64_t base = bbase[b], n = bn[b], li = j - base, g = map[j];
@@ -250,15 +282,26 @@ __global__ __launch_bounds__(256) void k_box_gather(const int* __restrict__ map,
         o[2 * n * r + n] = src[2 * Nc * r + Nc + g];
     }
 }
+template <int Z = 0>
+__global__ __launch_bounds__(256) void k_box_gather(const int* __restrict__ map, const int* __restrict__ bsub,
+                                                    const int64_t* __restrict__ bbase, const int* __restrict__ bn,
+                                                    int64_t j0, int64_t j1, const double* __restrict__ src,
+                                                    int64_t Nc, double* __restrict__ loc, int nrhs) {
+    k_box_gather_body<Z>(single_block<false>(), map, bsub, bbase, bn, j0, j1, src, Nc, loc, nrhs);
+}
+template <class PK, int Z = 0>
+__global__ __launch_bounds__(256) void k_box_gather_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<false>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_box_gather_body<Z>(ehh_vb, a...); }, b.arg[ehh_s]);
+}
 
 // z += w loc(box) for the local unknowns [j0, j1) (boxes of the range disjoint);
 // w = wgt[g] (the inverse owner count) when wgt is given, else 1
-__global__ __launch_bounds__(256) void k_box_scatter(const int* __restrict__ map, const int* __restrict__ bsub,
-                                                     const int64_t* __restrict__ bbase, const int* __restrict__ bn,
-                                                     int64_t j0, int64_t j1, const double* __restrict__ loc,
-                                                     const double* __restrict__ wgt, int64_t Nc,
-                                                     double* __restrict__ z, int nrhs) {
-    const int64_t j = j0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+template <int Z = 0>
+EHH_DEV void k_box_scatter_body(VB ehh_vb, const int* __restrict__ map, const int* __restrict__ bsub, const int64_t* __restrict__ bbase, const int* __restrict__ bn, int64_t j0, int64_t j1, const double* __restrict__ loc, const double* __restrict__ wgt, int64_t Nc, double* __restrict__ z, int nrhs) {
+    const int64_t j = j0 + (int64_t)ehh_vb.x * blockDim.x + threadIdx.x;
     if (j >= j1) return;
     const int b = bsub[j];
     const int64_t base = bbase[b], n = bn[b], li = j - base, g = map[j];
@@ -269,18 +312,33 @@ __global__ __launch_bounds__(256) void k_box_scatter(const int* __restrict__ map
         z[2 * Nc * r + Nc + g] += w * o[2 * n * r + n];
     }
 }
+template <int Z = 0>
+__global__ __launch_bounds__(256) void k_box_scatter(const int* __restrict__ map, const int* __restrict__ bsub,
+                                                     const int64_t* __restrict__ bbase, const int* __restrict__ bn,
+                                                     int64_t j0, int64_t j1, const double* __restrict__ loc,
+                                                     const double* __restrict__ wgt, int64_t Nc,
+                                                     double* __restrict__ z, int nrhs) {
+    k_box_scatter_body<Z>(single_block<false>(), map, bsub, bbase, bn, j0, j1, loc, wgt, Nc, z, nrhs);
+}
+template <class PK, int Z = 0>
+__global__ __launch_bounds__(256) void k_box_scatter_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<false>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_box_scatter_body<Z>(ehh_vb, a...); }, b.arg[ehh_s]);
+}
 
 hipError_t launch_box_gather(const BoxMap& m, int64_t j0, int64_t j1, const double* src, int64_t Nc, double* loc,
                              int nrhs, hipStream_t s) {
     if (j1 <= j0) return hipSuccess;
-    EHH_LAUNCH_B(bytes_plain(nrhs * 32.0 * (double)(j1 - j0)), k_box_gather, nblk(j1 - j0), 256, 0, s, m.map, m.bsub,
+    EHH_LAUNCHK(bytes_plain(nrhs * 32.0 * (double)(j1 - j0)), k_box_gather, (0), nblk(j1 - j0), 256, 0, s, m.map, m.bsub,
                  m.bbase, m.bn, j0, j1, src, Nc, loc, nrhs);
     return hipGetLastError();
 }
 hipError_t launch_box_scatter(const BoxMap& m, int64_t j0, int64_t j1, const double* loc, const double* wgt,
                               int64_t Nc, double* z, int nrhs, hipStream_t s) {
     if (j1 <= j0) return hipSuccess;
-    EHH_LAUNCH_B(bytes_plain(nrhs * 48.0 * (double)(j1 - j0)), k_box_scatter, nblk(j1 - j0), 256, 0, s, m.map,
+    EHH_LAUNCHK(bytes_plain(nrhs * 48.0 * (double)(j1 - j0)), k_box_scatter, (0), nblk(j1 - j0), 256, 0, s, m.map,
                  m.bsub, m.bbase, m.bn, j0, j1, loc, wgt, Nc, z, nrhs);
     return hipGetLastError();
 }

@@ -8,6 +8,7 @@
 
 #include "internal.hpp"
 #include "launchlog.hpp"
+#include "batch.hpp"
 #include "ops.hpp"
 
 namespace ehh {
@@ -16,8 +17,7 @@ namespace ehh {
 // One thread per unknown (row): short independent load chains, so that small
 // coarse levels are not bound by the latency of one long serial row loop.
 template <int D, typename T, class Op, int RB>
-__global__ __launch_bounds__(256) void k_apply(Op op, const T* __restrict__ x, const T* __restrict__ b,
-                                               T* __restrict__ y, int nrhs, int64_t stride, int rpb) {
+EHH_DEV void k_apply_body(VB ehh_vb, const Op& op, const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ y, int nrhs, int64_t stride, int rpb) {
     // right-hand sides [blockIdx.y * rpb, ...) of this grid row
     {
         const int rb0 = blockIdx.y * rpb;
@@ -27,7 +27,7 @@ __global__ __launch_bounds__(256) void k_apply(Op op, const T* __restrict__ x, c
         nrhs = nrhs - rb0 < rpb ? nrhs - rb0 : rpb;
     }
     const Geo& g = op.g;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)ehh_vb.x * blockDim.x + threadIdx.x;
     if (t >= g.N) return;
     int k = 0;
     while (k < 3 && t >= g.off[k + 1]) ++k;
@@ -52,6 +52,18 @@ __global__ __launch_bounds__(256) void k_apply(Op op, const T* __restrict__ x, c
         }
     }
 }
+template <int D, typename T, class Op, int RB>
+__global__ __launch_bounds__(256) void k_apply(Op op, const T* __restrict__ x, const T* __restrict__ b,
+                                               T* __restrict__ y, int nrhs, int64_t stride, int rpb) {
+    k_apply_body<D, T, Op, RB>(single_block<false>(), op, x, b, y, nrhs, stride, rpb);
+}
+template <class PK, int D, typename T, class Op, int RB>
+__global__ __launch_bounds__(256) void k_apply_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<false>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_apply_body<D, T, Op, RB>(ehh_vb, a...); }, b.arg[ehh_s]);
+}
 
 // ------------------------------------------------------------ red-black Vanka half-sweep
 // Eight lanes of a wavefront per relaxed cell: lane j < 2D+1 evaluates row j of
@@ -65,9 +77,7 @@ __global__ __launch_bounds__(256) void k_apply(Op op, const T* __restrict__ x, c
 // unknown; the residual is taken from e_in (the state at the start of the
 // half-sweep).
 template <int D, typename T, class Op, int RB>
-__global__ __launch_bounds__(256) void k_relax(Op op, int colour, T w, T wp, int econ,
-                                               const T* __restrict__ b, const T* __restrict__ ein,
-                                               T* __restrict__ eout, int nrhs, int64_t stride, int rpb) {
+EHH_DEV void k_relax_body(VB ehh_vb, const Op& op, int colour, T w, T wp, int econ, const T* __restrict__ b, const T* __restrict__ ein, T* __restrict__ eout, int nrhs, int64_t stride, int rpb) {
     {
         const int rb0 = blockIdx.y * rpb;
         b += rb0 * stride;
@@ -84,7 +94,7 @@ __global__ __launch_bounds__(256) void k_relax(Op op, int colour, T w, T wp, int
     const int lane = threadIdx.x & 63;
     const int row = lane >> 3;
     const int cig = lane & 7;
-    const int64_t t = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 8 + cig;
+    const int64_t t = (((int64_t)ehh_vb.x * blockDim.x + threadIdx.x) >> 6) * 8 + cig;
     const int base = cig;   // lane of row 0 of this cell
     const bool live = t < npair;
     const int64_t tt = live ? t : 0;
@@ -194,17 +204,20 @@ __global__ __launch_bounds__(256) void k_relax(Op op, int colour, T w, T wp, int
     }
     }
 }
-
-// Workgroups are dealt to the 8 XCDs round-robin (linear id mod 8), and each XCD
-// has its own L2.  Renumbering so that every XCD receives one contiguous range
-// of logical blocks keeps the rows above and below a block's cells (stencil
-// neighbours) in the same L2.  Bijective for any block count.
-EHH_DEV inline int64_t xcd_block(int64_t bid, int64_t nb) {
-    constexpr int64_t X = 8;
-    const int64_t q = nb / X, rem = nb % X;
-    const int64_t xcd = bid % X, local = bid / X;
-    return xcd < rem ? xcd * (q + 1) + local : rem * (q + 1) + (xcd - rem) * q + local;
+template <int D, typename T, class Op, int RB>
+__global__ __launch_bounds__(256) void k_relax(Op op, int colour, T w, T wp, int econ,
+                                               const T* __restrict__ b, const T* __restrict__ ein,
+                                               T* __restrict__ eout, int nrhs, int64_t stride, int rpb) {
+    k_relax_body<D, T, Op, RB>(single_block<false>(), op, colour, w, wp, econ, b, ein, eout, nrhs, stride, rpb);
 }
+template <class PK, int D, typename T, class Op, int RB>
+__global__ __launch_bounds__(256) void k_relax_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<false>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_relax_body<D, T, Op, RB>(ehh_vb, a...); }, b.arg[ehh_s]);
+}
+
 
 
 // A per-lane offset past the end of every 2D stored-row buffer (their sizes stay
@@ -220,8 +233,7 @@ constexpr uint32_t OOB_OFF = 0x80000000u;
 // The row plan (indices and coefficients) is built once per row and reused for
 // every right-hand side, so a batch streams only the vectors.
 template <int D, typename T, class Op, int RB>
-__global__ __launch_bounds__(256) void k_apply_plan(Op op, const T* __restrict__ x, const T* __restrict__ b,
-                                                    T* __restrict__ y, int nrhs, int64_t stride, int rpb) {
+EHH_DEV void k_apply_plan_body(VB ehh_vb, const Op& op, const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ y, int nrhs, int64_t stride, int rpb) {
     // right-hand sides [blockIdx.y * rpb, ...) of this grid row
     {
         const int rb0 = blockIdx.y * rpb;
@@ -231,7 +243,7 @@ __global__ __launch_bounds__(256) void k_apply_plan(Op op, const T* __restrict__
         nrhs = nrhs - rb0 < rpb ? nrhs - rb0 : rpb;
     }
     const Geo& g = op.g;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)ehh_vb.x * blockDim.x + threadIdx.x;
     if (t >= g.N) return;
     int k = 0;
     while (k < 3 && t >= g.off[k + 1]) ++k;
@@ -262,6 +274,18 @@ __global__ __launch_bounds__(256) void k_apply_plan(Op op, const T* __restrict__
         if (b) v = CVec<T>{b + r * stride, g.N}.ld(t) - v;
         Vec<T>{y + r * stride, g.N}.st(t, v);
     }
+}
+template <int D, typename T, class Op, int RB>
+__global__ __launch_bounds__(256) void k_apply_plan(Op op, const T* __restrict__ x, const T* __restrict__ b,
+                                                    T* __restrict__ y, int nrhs, int64_t stride, int rpb) {
+    k_apply_plan_body<D, T, Op, RB>(single_block<false>(), op, x, b, y, nrhs, stride, rpb);
+}
+template <class PK, int D, typename T, class Op, int RB>
+__global__ __launch_bounds__(256) void k_apply_plan_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<false>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_apply_plan_body<D, T, Op, RB>(ehh_vb, a...); }, b.arg[ehh_s]);
 }
 
 // Vanka block of one cell spread over the eight lanes of its rows (lane base + 8 j
@@ -342,9 +366,7 @@ template <int D, typename T> struct VankaBlock {
 // the two faces of a component, the couplings to the cell pressure) is read off
 // the lanes' plans.
 template <int D, typename T, class Op, int RB>
-__global__ __launch_bounds__(256) void k_relax_plan(Op op, int colour, T w, T wp, int econ,
-                                                    const T* __restrict__ b, const T* __restrict__ ein,
-                                                    T* __restrict__ eout, int nrhs, int64_t stride, int rpb) {
+EHH_DEV void k_relax_plan_body(VB ehh_vb, const Op& op, int colour, T w, T wp, int econ, const T* __restrict__ b, const T* __restrict__ ein, T* __restrict__ eout, int nrhs, int64_t stride, int rpb) {
     {
         const int rb0 = blockIdx.y * rpb;
         b += rb0 * stride;
@@ -361,7 +383,7 @@ __global__ __launch_bounds__(256) void k_relax_plan(Op op, int colour, T w, T wp
     const int lane = threadIdx.x & 63;
     const int row = lane >> 3;
     const int cig = lane & 7;
-    const int64_t t = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 8 + cig;
+    const int64_t t = (((int64_t)ehh_vb.x * blockDim.x + threadIdx.x) >> 6) * 8 + cig;
     const int base = cig;   // lane of row 0 of this cell
     const bool live = t < npair;
     const int64_t tt = live ? t : 0;
@@ -426,6 +448,19 @@ __global__ __launch_bounds__(256) void k_relax_plan(Op op, int colour, T w, T wp
             if (carry) ov.st(ipb, ein ? ev.ld(ipb) : mk<T>(T(0), T(0)));
         }
     }
+}
+template <int D, typename T, class Op, int RB>
+__global__ __launch_bounds__(256) void k_relax_plan(Op op, int colour, T w, T wp, int econ,
+                                                    const T* __restrict__ b, const T* __restrict__ ein,
+                                                    T* __restrict__ eout, int nrhs, int64_t stride, int rpb) {
+    k_relax_plan_body<D, T, Op, RB>(single_block<false>(), op, colour, w, wp, econ, b, ein, eout, nrhs, stride, rpb);
+}
+template <class PK, int D, typename T, class Op, int RB>
+__global__ __launch_bounds__(256) void k_relax_plan_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<false>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_relax_plan_body<D, T, Op, RB>(ehh_vb, a...); }, b.arg[ehh_s]);
 }
 
 // Staggered bilinear transfer weights along a tangential axis: 3/4 for the two
@@ -581,11 +616,7 @@ EHH_DEV inline int col2(const Cols2& c, int j) {
 // one unknown per lane (the carry lane forms the other cell's pressure), which
 // saves the restriction's own launch.
 template <typename T, bool KEEP, bool RST>
-__global__ __launch_bounds__(256) void k_relax_st2d(Geo g, int colour, T w, T wp, int econ, const T* __restrict__ b,
-                                                    const T* __restrict__ ein, T* __restrict__ eout, int nrhs,
-                                                    int64_t stride, int rpb, const T* __restrict__ cre,
-                                                    const T* __restrict__ cim, int64_t lanes, Geo gf,
-                                                    const T* __restrict__ rf, T* __restrict__ bw) {
+EHH_DEV void k_relax_st2d_body(VB ehh_vb, const Geo& g, int colour, T w, T wp, int econ, const T* __restrict__ b, const T* __restrict__ ein, T* __restrict__ eout, int nrhs, int64_t stride, int rpb, const T* __restrict__ cre, const T* __restrict__ cim, int64_t lanes, const Geo& gf, const T* __restrict__ rf, T* __restrict__ bw) {
     constexpr int D = 2, R = 2 * D + 1, NF = St<2>::NF, NUP = St<2>::NUP, NT = NF + NUP, H = 7;
     constexpr int T_SELF = St<2>::CF, T_NHI = St<2>::CF + 1, T_PLO = NF + 2, T_PHI = NF + 3;
     const int64_t sf = 2 * gf.N;
@@ -605,7 +636,7 @@ __global__ __launch_bounds__(256) void k_relax_st2d(Geo g, int colour, T w, T wp
     const int lane = threadIdx.x & 63;
     const int row = lane >> 3;
     const int cig = lane & 7;
-    const int64_t gl = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int64_t gl = (int64_t)ehh_vb.x * blockDim.x + threadIdx.x;
     const int t = (int)(gl >> 6) * 8 + cig;
     const int base = cig;
     const bool live = t < npair;
@@ -754,6 +785,21 @@ __global__ __launch_bounds__(256) void k_relax_st2d(Geo g, int colour, T w, T wp
         if (carry) ov.st(ipb, ecarry);
     }
 }
+template <typename T, bool KEEP, bool RST>
+__global__ __launch_bounds__(256) void k_relax_st2d(Geo g, int colour, T w, T wp, int econ, const T* __restrict__ b,
+                                                    const T* __restrict__ ein, T* __restrict__ eout, int nrhs,
+                                                    int64_t stride, int rpb, const T* __restrict__ cre,
+                                                    const T* __restrict__ cim, int64_t lanes, Geo gf,
+                                                    const T* __restrict__ rf, T* __restrict__ bw) {
+    k_relax_st2d_body<T, KEEP, RST>(single_block<true>(), g, colour, w, wp, econ, b, ein, eout, nrhs, stride, rpb, cre, cim, lanes, gf, rf, bw);
+}
+template <class PK, typename T, bool KEEP, bool RST>
+__global__ __launch_bounds__(256) void k_relax_st2d_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<true>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_relax_st2d_body<T, KEEP, RST>(ehh_vb, a...); }, b.arg[ehh_s]);
+}
 
 // FP64 half-sweep over stored rows with each row split over two wavefronts: the
 // lane layout and stored-row slots of k_relax_st2d (eight cells per wavefront,
@@ -764,10 +810,7 @@ __global__ __launch_bounds__(256) void k_relax_st2d(Geo g, int colour, T w, T wp
 // its registers), which pays on small levels where a launch is one wave of
 // wavefronts deep.  Only for half-sweeps that start from e_in.
 template <typename T>
-__global__ __launch_bounds__(256) void k_relax_st2d_split(Geo g, int colour, T w, T wp, int econ, const T* __restrict__ b,
-                                                          const T* __restrict__ ein, T* __restrict__ eout, int nrhs,
-                                                          int64_t stride, int rpb, const T* __restrict__ cre,
-                                                          const T* __restrict__ cim, int64_t lanes) {
+EHH_DEV void k_relax_st2d_split_body(VB ehh_vb, const Geo& g, int colour, T w, T wp, int econ, const T* __restrict__ b, const T* __restrict__ ein, T* __restrict__ eout, int nrhs, int64_t stride, int rpb, const T* __restrict__ cre, const T* __restrict__ cim, int64_t lanes) {
     constexpr int D = 2, R = 2 * D + 1, NF = St<2>::NF, NUP = St<2>::NUP, NT = NF + NUP, HT = 11;
     constexpr int T_SELF = St<2>::CF, T_NHI = St<2>::CF + 1, T_PLO = NF + 2, T_PHI = NF + 3;
     __shared__ T part[2][2][2][64];   // [r parity][cell group of the block][re, im][lane]
@@ -783,7 +826,7 @@ __global__ __launch_bounds__(256) void k_relax_st2d_split(Geo g, int colour, T w
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int half = wv & 1, grp = wv >> 1;
     const int row = lane >> 3, cig = lane & 7;
-    const int64_t group = xcd_block(blockIdx.x, gridDim.x) * 2 + grp;   // cell group of eight cells
+    const int64_t group = (int64_t)ehh_vb.x * 2 + grp;   // cell group of eight cells
     const int64_t gl = group * 64 + lane;                                  // stored-row slot
     const int t = (int)group * 8 + cig;
     const int base = cig;
@@ -892,12 +935,24 @@ __global__ __launch_bounds__(256) void k_relax_st2d_split(Geo g, int colour, T w
         lds_barrier();
     }
 }
+template <typename T>
+__global__ __launch_bounds__(256) void k_relax_st2d_split(Geo g, int colour, T w, T wp, int econ, const T* __restrict__ b,
+                                                          const T* __restrict__ ein, T* __restrict__ eout, int nrhs,
+                                                          int64_t stride, int rpb, const T* __restrict__ cre,
+                                                          const T* __restrict__ cim, int64_t lanes) {
+    k_relax_st2d_split_body<T>(single_block<true>(), g, colour, w, wp, econ, b, ein, eout, nrhs, stride, rpb, cre, cim, lanes);
+}
+template <class PK, typename T>
+__global__ __launch_bounds__(256) void k_relax_st2d_split_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<true>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_relax_st2d_split_body<T>(ehh_vb, a...); }, b.arg[ehh_s]);
+}
 
 // y = A x or r = b - A x over stored rows (term j of row t at [j * N + t]).
 template <typename T>
-__global__ __launch_bounds__(256) void k_apply_st2d(Geo g, const T* __restrict__ x, const T* __restrict__ b,
-                                                    T* __restrict__ y, int nrhs, int64_t stride, int rpb,
-                                                    const T* __restrict__ cre, const T* __restrict__ cim) {
+EHH_DEV void k_apply_st2d_body(VB ehh_vb, const Geo& g, const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ y, int nrhs, int64_t stride, int rpb, const T* __restrict__ cre, const T* __restrict__ cim) {
     constexpr int NF = St<2>::NF, NUP = St<2>::NUP, NT = NF + NUP;
     {
         const int rb0 = blockIdx.y * rpb;
@@ -907,7 +962,7 @@ __global__ __launch_bounds__(256) void k_apply_st2d(Geo g, const T* __restrict__
         nrhs = nrhs - rb0 < rpb ? nrhs - rb0 : rpb;
     }
     const int N = (int)g.N;
-    const int t = (int)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int t = (int)(int64_t)ehh_vb.x * blockDim.x + threadIdx.x;
     if (t >= N) return;
     int k = 0;
     while (k < 3 && t >= g.off[k + 1]) ++k;
@@ -952,6 +1007,19 @@ __global__ __launch_bounds__(256) void k_apply_st2d(Geo g, const T* __restrict__
         Vec<T>{y + r * stride, g.N}.st(t, o);
     }
 }
+template <typename T>
+__global__ __launch_bounds__(256) void k_apply_st2d(Geo g, const T* __restrict__ x, const T* __restrict__ b,
+                                                    T* __restrict__ y, int nrhs, int64_t stride, int rpb,
+                                                    const T* __restrict__ cre, const T* __restrict__ cim) {
+    k_apply_st2d_body<T>(single_block<true>(), g, x, b, y, nrhs, stride, rpb, cre, cim);
+}
+template <class PK, typename T>
+__global__ __launch_bounds__(256) void k_apply_st2d_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<true>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_apply_st2d_body<T>(ehh_vb, a...); }, b.arg[ehh_s]);
+}
 
 // rc = P^T (b - A e) from a 2D level with stored rows in one launch: sixteen
 // lanes per coarse unknown, lane j forming the fine residual of the j-th fine
@@ -963,12 +1031,9 @@ __global__ __launch_bounds__(256) void k_apply_st2d(Geo g, const T* __restrict__
 // and in the caches), which saves writing the fine residual and the
 // restriction's own launch.
 template <typename T>
-__global__ __launch_bounds__(256) void k_residual_restrict2d(Geo gf, Geo gc, const T* __restrict__ e,
-                                                             const T* __restrict__ b, T* __restrict__ rc,
-                                                             int nrhs, const T* __restrict__ cre,
-                                                             const T* __restrict__ cim) {
+EHH_DEV void k_residual_restrict2d_body(VB ehh_vb, const Geo& gf, const Geo& gc, const T* __restrict__ e, const T* __restrict__ b, T* __restrict__ rc, int nrhs, const T* __restrict__ cre, const T* __restrict__ cim) {
     constexpr int NF = St<2>::NF, NUP = St<2>::NUP, NT = NF + NUP;
-    const int gl = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int gl = (int)(ehh_vb.x * blockDim.x + threadIdx.x);
     const int Nc = (int)gc.N, N = (int)gf.N;
     const int tc0 = gl >> 4, j = gl & 15;
     const bool live = tc0 < Nc;
@@ -1061,6 +1126,20 @@ __global__ __launch_bounds__(256) void k_residual_restrict2d(Geo gf, Geo gc, con
             rc[(int64_t)r * 2 * Nc + Nc + tc] = si;
         }
     }
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_residual_restrict2d(Geo gf, Geo gc, const T* __restrict__ e,
+                                                             const T* __restrict__ b, T* __restrict__ rc,
+                                                             int nrhs, const T* __restrict__ cre,
+                                                             const T* __restrict__ cim) {
+    k_residual_restrict2d_body<T>(single_block<false>(), gf, gc, e, b, rc, nrhs, cre, cim);
+}
+template <class PK, typename T>
+__global__ __launch_bounds__(256) void k_residual_restrict2d_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<false>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_residual_restrict2d_body<T>(ehh_vb, a...); }, b.arg[ehh_s]);
 }
 
 // ------------------------------------ stored Galerkin rows with computed columns (3D)
@@ -1199,10 +1278,7 @@ EHH_DEV void rows3_rb(const Buf<C>& cR, const Buf<C>& cI, uint32_t lo, uint32_t 
 // the level's power-of-two scale csc, which the sums and the block entries are
 // multiplied by again; csc = 1 otherwise).
 template <typename T, int RB, int CH, typename C = T>
-__global__ __launch_bounds__(256) void k_relax_st3d(Geo g, int colour, T w, T wp, int econ, const T* __restrict__ b,
-                                                    const T* __restrict__ ein, T* __restrict__ eout, int nrhs,
-                                                    int64_t stride, int rpb, const C* __restrict__ cre,
-                                                    const C* __restrict__ cim, int64_t lanes, T csc) {
+EHH_DEV void k_relax_st3d_body(VB ehh_vb, const Geo& g, int colour, T w, T wp, int econ, const T* __restrict__ b, const T* __restrict__ ein, T* __restrict__ eout, int nrhs, int64_t stride, int rpb, const C* __restrict__ cre, const C* __restrict__ cim, int64_t lanes, T csc) {
     constexpr int D = 3, R = 2 * D + 1, NF = St<3>::NF, NT = NF + St<3>::NUP;
     constexpr int T_SELF = St<3>::CF, T_NHI = St<3>::CF + 1, T_PLO = NF + 8, T_PHI = NF + 9;
     {
@@ -1217,7 +1293,7 @@ __global__ __launch_bounds__(256) void k_relax_st3d(Geo g, int colour, T w, T wp
     const int lane = threadIdx.x & 63;
     const int row = lane >> 3;
     const int cig = lane & 7;
-    const int64_t gl = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int64_t gl = (int64_t)ehh_vb.x * blockDim.x + threadIdx.x;
     const int t = (int)(gl >> 6) * 8 + cig;
     const int base = cig;
     const bool live = t < npair;
@@ -1304,14 +1380,26 @@ __global__ __launch_bounds__(256) void k_relax_st3d(Geo g, int colour, T w, T wp
         }
     }
 }
+template <typename T, int RB, int CH, typename C = T>
+__global__ __launch_bounds__(256) void k_relax_st3d(Geo g, int colour, T w, T wp, int econ, const T* __restrict__ b,
+                                                    const T* __restrict__ ein, T* __restrict__ eout, int nrhs,
+                                                    int64_t stride, int rpb, const C* __restrict__ cre,
+                                                    const C* __restrict__ cim, int64_t lanes, T csc) {
+    k_relax_st3d_body<T, RB, CH, C>(single_block<true>(), g, colour, w, wp, econ, b, ein, eout, nrhs, stride, rpb, cre, cim, lanes, csc);
+}
+template <class PK, typename T, int RB, int CH, typename C = T>
+__global__ __launch_bounds__(256) void k_relax_st3d_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<true>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_relax_st3d_body<T, RB, CH, C>(ehh_vb, a...); }, b.arg[ehh_s]);
+}
 
 // y = A x or r = b - A x over stored rows on a 3D Galerkin level (term j of row t
 // at [j * N + t]).
 // (C, csc: storage of the rows and their scale, as in k_relax_st3d.)
 template <typename T, int RB, int CH, typename C = T>
-__global__ __launch_bounds__(256) void k_apply_st3d(Geo g, const T* __restrict__ x, const T* __restrict__ b,
-                                                    T* __restrict__ y, int nrhs, int64_t stride, int rpb,
-                                                    const C* __restrict__ cre, const C* __restrict__ cim, T csc) {
+EHH_DEV void k_apply_st3d_body(VB ehh_vb, const Geo& g, const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ y, int nrhs, int64_t stride, int rpb, const C* __restrict__ cre, const C* __restrict__ cim, T csc) {
     constexpr int NF = St<3>::NF, NT = NF + St<3>::NUP;
     {
         const int rb0 = blockIdx.y * rpb;
@@ -1321,7 +1409,7 @@ __global__ __launch_bounds__(256) void k_apply_st3d(Geo g, const T* __restrict__
         nrhs = nrhs - rb0 < rpb ? nrhs - rb0 : rpb;
     }
     const int N = (int)g.N;
-    const int t = (int)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int t = (int)(int64_t)ehh_vb.x * blockDim.x + threadIdx.x;
     if (t >= N) return;
     int k = 0;
     while (k < 3 && t >= g.off[k + 1]) ++k;
@@ -1363,6 +1451,19 @@ __global__ __launch_bounds__(256) void k_apply_st3d(Geo g, const T* __restrict__
             yq.st(ot + ls, o.im);
         }
     }
+}
+template <typename T, int RB, int CH, typename C = T>
+__global__ __launch_bounds__(256) void k_apply_st3d(Geo g, const T* __restrict__ x, const T* __restrict__ b,
+                                                    T* __restrict__ y, int nrhs, int64_t stride, int rpb,
+                                                    const C* __restrict__ cre, const C* __restrict__ cim, T csc) {
+    k_apply_st3d_body<T, RB, CH, C>(single_block<true>(), g, x, b, y, nrhs, stride, rpb, cre, cim, csc);
+}
+template <class PK, typename T, int RB, int CH, typename C = T>
+__global__ __launch_bounds__(256) void k_apply_st3d_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<true>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_apply_st3d_body<T, RB, CH, C>(ehh_vb, a...); }, b.arg[ehh_s]);
 }
 
 // Builders of the 3D stored rows: coefficient of term j of the u_k row at face
@@ -1484,13 +1585,11 @@ __global__ __launch_bounds__(256) void k_build_row_rows3d(StOp<3, T> op, T* __re
 // TO: type of e_out (double lets the last half-sweep of a complex64 cycle write
 // the FP64 result directly).
 template <typename T, typename TO = T>
-__global__ __launch_bounds__(256) void k_relax_cell2d(FineOp<2, T> op, int colour, T w, T wp, int econ,
-                                                      const T* __restrict__ b, const T* __restrict__ ein,
-                                                      TO* __restrict__ eout, int nrhs, int64_t stride, int rpb) {
+EHH_DEV void k_relax_cell2d_body(VB ehh_vb, const FineOp<2, T>& op, int colour, T w, T wp, int econ, const T* __restrict__ b, const T* __restrict__ ein, TO* __restrict__ eout, int nrhs, int64_t stride, int rpb) {
     const Geo& g = op.g;
     const int n0 = g.n[0], n1 = g.n[1];
     const int hp = n0 >> 1;
-    const int64_t t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)ehh_vb.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)hp * n1) return;
     const int r_begin = blockIdx.y * rpb;
     const int r_end = r_begin + rpb < nrhs ? r_begin + rpb : nrhs;
@@ -1625,18 +1724,29 @@ __global__ __launch_bounds__(256) void k_relax_cell2d(FineOp<2, T> op, int colou
         st(kpo, epo);
     }
 }
+template <typename T, typename TO = T>
+__global__ __launch_bounds__(256) void k_relax_cell2d(FineOp<2, T> op, int colour, T w, T wp, int econ,
+                                                      const T* __restrict__ b, const T* __restrict__ ein,
+                                                      TO* __restrict__ eout, int nrhs, int64_t stride, int rpb) {
+    k_relax_cell2d_body<T, TO>(single_block<true>(), op, colour, w, wp, econ, b, ein, eout, nrhs, stride, rpb);
+}
+template <class PK, typename T, typename TO = T>
+__global__ __launch_bounds__(256) void k_relax_cell2d_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<true>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_relax_cell2d_body<T, TO>(ehh_vb, a...); }, b.arg[ehh_s]);
+}
 
 // y = A x (or b - A x) on the finest 2D level, one thread per cell: the cell
 // owns its left u_0 face, its bottom u_1 face and its pressure (the faces on the
 // walls are not unknowns), so every unknown is written once; the three rows
 // need thirteen values of x.
 template <typename T>
-__global__ __launch_bounds__(256) void k_apply_cell2d(FineOp<2, T> op, const T* __restrict__ x,
-                                                      const T* __restrict__ b, T* __restrict__ y, int nrhs,
-                                                      int64_t stride, int rpb) {
+EHH_DEV void k_apply_cell2d_body(VB ehh_vb, const FineOp<2, T>& op, const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ y, int nrhs, int64_t stride, int rpb) {
     const Geo& g = op.g;
     const int n0 = g.n[0], n1 = g.n[1];
-    const int64_t t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)ehh_vb.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)n0 * n1) return;
     const int r_begin = blockIdx.y * rpb;
     const int r_end = r_begin + rpb < nrhs ? r_begin + rpb : nrhs;
@@ -1737,6 +1847,19 @@ __global__ __launch_bounds__(256) void k_apply_cell2d(FineOp<2, T> op, const T* 
         yb.st(NB + kp, ap.im);
     }
 }
+template <typename T>
+__global__ __launch_bounds__(256) void k_apply_cell2d(FineOp<2, T> op, const T* __restrict__ x,
+                                                      const T* __restrict__ b, T* __restrict__ y, int nrhs,
+                                                      int64_t stride, int rpb) {
+    k_apply_cell2d_body<T>(single_block<true>(), op, x, b, y, nrhs, stride, rpb);
+}
+template <class PK, typename T>
+__global__ __launch_bounds__(256) void k_apply_cell2d_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<true>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_apply_cell2d_body<T>(ehh_vb, a...); }, b.arg[ehh_s]);
+}
 
 // ------------------------------------------- one thread per cell (3D finest level)
 // The 3D form of k_relax_cell2d: the cell's 7 x 7 block (a 2 x 2 block per
@@ -1745,13 +1868,11 @@ __global__ __launch_bounds__(256) void k_apply_cell2d(FineOp<2, T> op, const T* 
 // component the two faces, their outer normal neighbours and four tangential
 // neighbours each; the pressure and its six neighbours) and b at 7 unknowns.
 template <typename T>
-__global__ __launch_bounds__(256) void k_relax_cell3d(FineOp<3, T> op, int colour, T w, T wp, int econ,
-                                                      const T* __restrict__ b, const T* __restrict__ ein,
-                                                      T* __restrict__ eout, int nrhs, int64_t stride, int rpb) {
+EHH_DEV void k_relax_cell3d_body(VB ehh_vb, const FineOp<3, T>& op, int colour, T w, T wp, int econ, const T* __restrict__ b, const T* __restrict__ ein, T* __restrict__ eout, int nrhs, int64_t stride, int rpb) {
     const Geo& g = op.g;
     const int n[3] = {g.n[0], g.n[1], g.n[2]};
     const int hp = n[0] >> 1;
-    const int64_t t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)ehh_vb.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)hp * n[1] * n[2]) return;
     const int r_begin = blockIdx.y * rpb;
     const int r_end = r_begin + rpb < nrhs ? r_begin + rpb : nrhs;
@@ -1934,16 +2055,27 @@ __global__ __launch_bounds__(256) void k_relax_cell3d(FineOp<3, T> op, int colou
         st(kpo, epo);
     }
 }
+template <typename T>
+__global__ __launch_bounds__(256) void k_relax_cell3d(FineOp<3, T> op, int colour, T w, T wp, int econ,
+                                                      const T* __restrict__ b, const T* __restrict__ ein,
+                                                      T* __restrict__ eout, int nrhs, int64_t stride, int rpb) {
+    k_relax_cell3d_body<T>(single_block<true>(), op, colour, w, wp, econ, b, ein, eout, nrhs, stride, rpb);
+}
+template <class PK, typename T>
+__global__ __launch_bounds__(256) void k_relax_cell3d_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<true>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_relax_cell3d_body<T>(ehh_vb, a...); }, b.arg[ehh_s]);
+}
 
 // y = A x (or b - A x) on the finest 3D level, one thread per cell owning its
 // three lower faces (those on the walls are not unknowns) and its pressure.
 template <typename T>
-__global__ __launch_bounds__(256) void k_apply_cell3d(FineOp<3, T> op, const T* __restrict__ x,
-                                                      const T* __restrict__ b, T* __restrict__ y, int nrhs,
-                                                      int64_t stride, int rpb) {
+EHH_DEV void k_apply_cell3d_body(VB ehh_vb, const FineOp<3, T>& op, const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ y, int nrhs, int64_t stride, int rpb) {
     const Geo& g = op.g;
     const int n[3] = {g.n[0], g.n[1], g.n[2]};
-    const int64_t t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)ehh_vb.x * blockDim.x + threadIdx.x;
     if (t >= g.ncell) return;
     const int r_begin = blockIdx.y * rpb;
     const int r_end = r_begin + rpb < nrhs ? r_begin + rpb : nrhs;
@@ -2055,6 +2187,19 @@ __global__ __launch_bounds__(256) void k_apply_cell3d(FineOp<3, T> op, const T* 
         yb.st(NB + kp, ap.im);
     }
 }
+template <typename T>
+__global__ __launch_bounds__(256) void k_apply_cell3d(FineOp<3, T> op, const T* __restrict__ x,
+                                                      const T* __restrict__ b, T* __restrict__ y, int nrhs,
+                                                      int64_t stride, int rpb) {
+    k_apply_cell3d_body<T>(single_block<true>(), op, x, b, y, nrhs, stride, rpb);
+}
+template <class PK, typename T>
+__global__ __launch_bounds__(256) void k_apply_cell3d_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<true>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_apply_cell3d_body<T>(ehh_vb, a...); }, b.arg[ehh_s]);
+}
 
 // Builds the stored rows of one colour's half-sweep in the lane order of
 // k_relax_st2d (same lane -> cell/row mapping, absent rows all zero): real parts
@@ -2140,9 +2285,7 @@ __global__ __launch_bounds__(256) void k_build_row_plans(StOp<2, T> op, T* __res
 static constexpr int LT_X = 16, LT_Y = 8;
 
 template <typename T, class Op>
-__global__ __launch_bounds__(512) void k_relax_lds2d(Op op, int colour, T w, T wp, int econ, const T* __restrict__ b,
-                                                     const T* __restrict__ ein, T* __restrict__ eout, int nrhs,
-                                                     int64_t stride, int rpb, int ht) {
+EHH_DEV void k_relax_lds2d_body(VB ehh_vb, const Op& op, int colour, T w, T wp, int econ, const T* __restrict__ b, const T* __restrict__ ein, T* __restrict__ eout, int nrhs, int64_t stride, int rpb, int ht) {
     constexpr int D = 2, R = 5;
     __shared__ T sre[(LT_X + 3) * (LT_Y + 4) + (LT_X + 4) * (LT_Y + 3) + (LT_X + 2) * (LT_Y + 2)];
     __shared__ T sim[(LT_X + 3) * (LT_Y + 4) + (LT_X + 4) * (LT_Y + 3) + (LT_X + 2) * (LT_Y + 2)];
@@ -2155,7 +2298,7 @@ __global__ __launch_bounds__(512) void k_relax_lds2d(Op op, int colour, T w, T w
     }
     const Geo& g = op.g;
     const int tiles_x = (g.n[0] + LT_X - 1) / LT_X;
-    const int x0 = (blockIdx.x % tiles_x) * LT_X, y0 = (blockIdx.x / tiles_x) * LT_Y;
+    const int x0 = (ehh_vb.x % tiles_x) * LT_X, y0 = (ehh_vb.x / tiles_x) * LT_Y;
     const int lane = threadIdx.x & 63, row = lane >> 3, cig = lane & 7;
     const int yl = threadIdx.x >> 6;   // one tile row per wavefront
     const int yy = y0 + yl;
@@ -2389,6 +2532,19 @@ __global__ __launch_bounds__(512) void k_relax_lds2d(Op op, int colour, T w, T w
         if (carry) ov.st(ipb, ecarry);
     }
 }
+template <typename T, class Op>
+__global__ __launch_bounds__(512) void k_relax_lds2d(Op op, int colour, T w, T wp, int econ, const T* __restrict__ b,
+                                                     const T* __restrict__ ein, T* __restrict__ eout, int nrhs,
+                                                     int64_t stride, int rpb, int ht) {
+    k_relax_lds2d_body<T, Op>(single_block<false>(), op, colour, w, wp, econ, b, ein, eout, nrhs, stride, rpb, ht);
+}
+template <class PK, typename T, class Op>
+__global__ __launch_bounds__(512) void k_relax_lds2d_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<false>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_relax_lds2d_body<T, Op>(ehh_vb, a...); }, b.arg[ehh_s]);
+}
 
 // --------------------------------------------------------------------- transfers
 // Staggered bilinear transfer: u_k linear along its normal (weights 1 / (1/2, 1/2)),
@@ -2396,9 +2552,8 @@ __global__ __launch_bounds__(512) void k_relax_lds2d(Op op, int colour, T w, T w
 // beyond the wall); pressure piecewise constant.  Restriction is P^T.
 
 template <int D, typename T>
-__global__ __launch_bounds__(256) void k_restrict(Geo gf, Geo gc, const T* __restrict__ rf,
-                                                  T* __restrict__ rc, int nrhs) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+EHH_DEV void k_restrict_body(VB ehh_vb, const Geo& gf, const Geo& gc, const T* __restrict__ rf, T* __restrict__ rc, int nrhs) {
+    const int64_t t = (int64_t)ehh_vb.x * blockDim.x + threadIdx.x;
     if (t >= gc.N) return;
     int k = 0;
     while (k < 3 && t >= gc.off[k + 1]) ++k;
@@ -2460,11 +2615,22 @@ __global__ __launch_bounds__(256) void k_restrict(Geo gf, Geo gc, const T* __res
         Vec<T>{rc + r * sc, gc.N}.st(t, s);
     }
 }
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_restrict(Geo gf, Geo gc, const T* __restrict__ rf,
+                                                  T* __restrict__ rc, int nrhs) {
+    k_restrict_body<D, T>(single_block<false>(), gf, gc, rf, rc, nrhs);
+}
+template <class PK, int D, typename T>
+__global__ __launch_bounds__(256) void k_restrict_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<false>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_restrict_body<D, T>(ehh_vb, a...); }, b.arg[ehh_s]);
+}
 
 template <int D, typename T>
-__global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const T* __restrict__ ec,
-                                                 T* __restrict__ ef, int nrhs) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+EHH_DEV void k_prolong_body(VB ehh_vb, const Geo& gf, const Geo& gc, const T* __restrict__ ec, T* __restrict__ ef, int nrhs) {
+    const int64_t t = (int64_t)ehh_vb.x * blockDim.x + threadIdx.x;
     if (t >= gf.N) return;
     int k = 0;
     while (k < 3 && t >= gf.off[k + 1]) ++k;
@@ -2551,13 +2717,25 @@ __global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const T* __rest
         fv.st(t, s);
     }
 }
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_prolong(Geo gf, Geo gc, const T* __restrict__ ec,
+                                                 T* __restrict__ ef, int nrhs) {
+    k_prolong_body<D, T>(single_block<false>(), gf, gc, ec, ef, nrhs);
+}
+template <class PK, int D, typename T>
+__global__ __launch_bounds__(256) void k_prolong_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<false>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_prolong_body<D, T>(ehh_vb, a...); }, b.arg[ehh_s]);
+}
 
 // 2D transfers with 32-bit indices and every load issued before the sums, in the
 // same term order as k_restrict / k_prolong (a term outside the grid reads a
 // clamped index with weight zero).  One right-hand side per grid row.
 template <typename T>
-__global__ __launch_bounds__(256) void k_restrict2d(Geo gf, Geo gc, const T* __restrict__ rf, T* __restrict__ rc) {
-    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+EHH_DEV void k_restrict2d_body(VB ehh_vb, const Geo& gf, const Geo& gc, const T* __restrict__ rf, T* __restrict__ rc) {
+    const int t = (int)(ehh_vb.x * blockDim.x + threadIdx.x);
     const int Nc = (int)gc.N;
     if (t >= Nc) return;
     rf += (int64_t)blockIdx.y * 2 * gf.N;
@@ -2584,10 +2762,21 @@ __global__ __launch_bounds__(256) void k_restrict2d(Geo gf, Geo gc, const T* __r
     rc[t] = v.re;
     rc[Nc + t] = v.im;
 }
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict2d(Geo gf, Geo gc, const T* __restrict__ rf, T* __restrict__ rc) {
+    k_restrict2d_body<T>(single_block<false>(), gf, gc, rf, rc);
+}
+template <class PK, typename T>
+__global__ __launch_bounds__(256) void k_restrict2d_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<false>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_restrict2d_body<T>(ehh_vb, a...); }, b.arg[ehh_s]);
+}
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_prolong2d(Geo gf, Geo gc, const T* __restrict__ ec, T* __restrict__ ef) {
-    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+EHH_DEV void k_prolong2d_body(VB ehh_vb, const Geo& gf, const Geo& gc, const T* __restrict__ ec, T* __restrict__ ef) {
+    const int t = (int)(ehh_vb.x * blockDim.x + threadIdx.x);
     const int Nc = (int)gc.N, Nf = (int)gf.N;
     if (t >= Nf) return;
     ec += (int64_t)blockIdx.y * 2 * gc.N;
@@ -2652,6 +2841,17 @@ __global__ __launch_bounds__(256) void k_prolong2d(Geo gf, Geo gc, const T* __re
     ef[t] = sr;
     ef[Nf + t] = si;
 }
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong2d(Geo gf, Geo gc, const T* __restrict__ ec, T* __restrict__ ef) {
+    k_prolong2d_body<T>(single_block<false>(), gf, gc, ec, ef);
+}
+template <class PK, typename T>
+__global__ __launch_bounds__(256) void k_prolong2d_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<false>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_prolong2d_body<T>(ehh_vb, a...); }, b.arg[ehh_s]);
+}
 
 // 3D transfers in the same style: positions along the normal and the two
 // tangential axes of the row's component, strides chosen by selects, all loads
@@ -2687,8 +2887,8 @@ EHH_DEV inline void pos3(int k, int li, int nx, int ny, int* p) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_restrict3d(Geo gf, Geo gc, const T* __restrict__ rf, T* __restrict__ rc) {
-    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+EHH_DEV void k_restrict3d_body(VB ehh_vb, const Geo& gf, const Geo& gc, const T* __restrict__ rf, T* __restrict__ rc) {
+    const int t = (int)(ehh_vb.x * blockDim.x + threadIdx.x);
     const int Nc = (int)gc.N, Nf = (int)gf.N;
     if (t >= Nc) return;
     rf += (int64_t)blockIdx.y * 2 * gf.N;
@@ -2745,10 +2945,21 @@ __global__ __launch_bounds__(256) void k_restrict3d(Geo gf, Geo gc, const T* __r
     rc[t] = sr;
     rc[Nc + t] = si;
 }
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict3d(Geo gf, Geo gc, const T* __restrict__ rf, T* __restrict__ rc) {
+    k_restrict3d_body<T>(single_block<false>(), gf, gc, rf, rc);
+}
+template <class PK, typename T>
+__global__ __launch_bounds__(256) void k_restrict3d_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<false>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_restrict3d_body<T>(ehh_vb, a...); }, b.arg[ehh_s]);
+}
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_prolong3d(Geo gf, Geo gc, const T* __restrict__ ec, T* __restrict__ ef) {
-    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+EHH_DEV void k_prolong3d_body(VB ehh_vb, const Geo& gf, const Geo& gc, const T* __restrict__ ec, T* __restrict__ ef) {
+    const int t = (int)(ehh_vb.x * blockDim.x + threadIdx.x);
     const int Nc = (int)gc.N, Nf = (int)gf.N;
     if (t >= Nf) return;
     ec += (int64_t)blockIdx.y * 2 * gc.N;
@@ -2803,6 +3014,17 @@ __global__ __launch_bounds__(256) void k_prolong3d(Geo gf, Geo gc, const T* __re
     }
     ef[t] = sr;
     ef[Nf + t] = si;
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong3d(Geo gf, Geo gc, const T* __restrict__ ec, T* __restrict__ ef) {
+    k_prolong3d_body<T>(single_block<false>(), gf, gc, ec, ef);
+}
+template <class PK, typename T>
+__global__ __launch_bounds__(256) void k_prolong3d_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<false>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_prolong3d_body<T>(ehh_vb, a...); }, b.arg[ehh_s]);
 }
 
 // ------------------------------------------------------------------------ launchers
@@ -2888,14 +3110,14 @@ hipError_t launch_apply(const LevelDesc<T>& L, const T* x, const T* b, T* y, int
         groups = groups < 1 ? 1 : (groups > nrhs ? nrhs : groups);
         const int rpc = (int)((nrhs + groups - 1) / groups);
         const dim3 gc(nblk(cells), (nrhs + rpc - 1) / rpc);
-        EHH_LAUNCH_B(lb, (k_apply_cell2d<T>), gc, 256, 0, s, FineOp<2, T>{L.g, L.f}, x, b, y, nrhs, stride, rpc);
+        EHH_LAUNCHK(lb, k_apply_cell2d, (T), gc, 256, 0, s, FineOp<2, T>{L.g, L.f}, x, b, y, nrhs, stride, rpc);
     } else if (L.g.dim == 2) {
         if (L.fine)
-            EHH_RB_DISPATCH(rb, EHH_LAUNCH_B(lb, (k_apply_plan<2, T, FineOp<2, T>, RB>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, x, b, y, nrhs, stride, rpb));
+            EHH_RB_DISPATCH(rb, EHH_LAUNCHK(lb, k_apply_plan, (2, T, FineOp<2, T>, RB), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, x, b, y, nrhs, stride, rpb));
         else if (L.sp.rre)
-            EHH_LAUNCH_B(lb, (k_apply_st2d<T>), gb, 256, 0, s, L.g, x, b, y, nrhs, stride, rpb, L.sp.rre, L.sp.rim);
+            EHH_LAUNCHK(lb, k_apply_st2d, (T), gb, 256, 0, s, L.g, x, b, y, nrhs, stride, rpb, L.sp.rre, L.sp.rim);
         else
-            EHH_RB_DISPATCH(rb, EHH_LAUNCH_B(lb, (k_apply_plan<2, T, StOp<2, T>, RB>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, x, b, y, nrhs, stride, rpb));
+            EHH_RB_DISPATCH(rb, EHH_LAUNCHK(lb, k_apply_plan, (2, T, StOp<2, T>, RB), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, x, b, y, nrhs, stride, rpb));
     } else if (L.g.dim == 3 && L.fine && cell3d_enabled() && 2 * L.g.N * (int64_t)sizeof(T) < (int64_t(1) << 32)) {
         const int64_t cells = L.g.ncell;
         static const int64_t cell_waves = env_int("EHH_CELL_WAVES", 4096);
@@ -2903,15 +3125,15 @@ hipError_t launch_apply(const LevelDesc<T>& L, const T* x, const T* b, T* y, int
         groups = groups < 1 ? 1 : (groups > nrhs ? nrhs : groups);
         const int rpc = (int)((nrhs + groups - 1) / groups);
         const dim3 gc(nblk(cells), (nrhs + rpc - 1) / rpc);
-        EHH_LAUNCH_B(lb, (k_apply_cell3d<T>), gc, 256, 0, s, FineOp<3, T>{L.g, L.f}, x, b, y, nrhs, stride, rpc);
+        EHH_LAUNCHK(lb, k_apply_cell3d, (T), gc, 256, 0, s, FineOp<3, T>{L.g, L.f}, x, b, y, nrhs, stride, rpc);
     } else {
         if (L.fine)
-            EHH_RB_DISPATCH(rb, EHH_LAUNCH_B(lb, (k_apply_plan<3, T, FineOp<3, T>, RB>), gb, 256, 0, s, FineOp<3, T>{L.g, L.f}, x, b, y, nrhs, stride, rpb));
+            EHH_RB_DISPATCH(rb, EHH_LAUNCHK(lb, k_apply_plan, (3, T, FineOp<3, T>, RB), gb, 256, 0, s, FineOp<3, T>{L.g, L.f}, x, b, y, nrhs, stride, rpb));
         else if (L.sp.rre) {
 #define EHH_APPLY_ST3D(RB, CH, C)                                                                                \
     {                                                                                                            \
         const int rpbs = rhs_per_block((L.g.N + 63) / 64, nrhs, RB);                                             \
-        EHH_LAUNCH_B(lb, (k_apply_st3d<T, RB, CH, C>), dim3(nblk(L.g.N), (nrhs + rpbs - 1) / rpbs), 256, 0, s,   \
+        EHH_LAUNCHK(lb, k_apply_st3d, (T, RB, CH, C), dim3(nblk(L.g.N), (nrhs + rpbs - 1) / rpbs), 256, 0, s,   \
                            L.g, x, b, y, nrhs, stride, rpbs, (const C*)L.sp.rre, (const C*)L.sp.rim,             \
                            (T)L.sp.scale);                                                                       \
     }
@@ -2920,7 +3142,7 @@ hipError_t launch_apply(const LevelDesc<T>& L, const T* x, const T* b, T* y, int
             else EHH_APPLY_ST3D(8, 4, T)
 #undef EHH_APPLY_ST3D
         } else
-            EHH_RB_DISPATCH(rb3, EHH_LAUNCH_B(lb, (k_apply<3, T, StOp<3, T>, RB>), gb3, 256, 0, s, StOp<3, T>{L.g, L.s}, x, b, y, nrhs, stride, rpb3));
+            EHH_RB_DISPATCH(rb3, EHH_LAUNCHK(lb, k_apply, (3, T, StOp<3, T>, RB), gb3, 256, 0, s, StOp<3, T>{L.g, L.s}, x, b, y, nrhs, stride, rpb3));
     }
     return hipGetLastError();
 }
@@ -2951,7 +3173,7 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, Damp w, int econ, con
         lds2d_enabled() && big_batch) {
         const int tiles = lds_tiles;
         const dim3 gl(tiles, (nrhs + rpl - 1) / rpl);
-        EHH_LAUNCH_B(lb, (k_relax_lds2d<T, StOp<2, T>>), gl, 512, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpl, 2);
+        EHH_LAUNCHK(lb, k_relax_lds2d, (T, StOp<2, T>), gl, 512, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpl, 2);
     } else if (L.g.dim == 2 && L.fine && cell2d_enabled() && 2 * L.g.N * (int64_t)sizeof(T) < (int64_t(1) << 32)) {
         const int64_t cells = npair;
         static const int64_t cell_waves = env_int("EHH_CELL_WAVES", 4096);
@@ -2959,10 +3181,10 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, Damp w, int econ, con
         groups = groups < 1 ? 1 : (groups > nrhs ? nrhs : groups);
         const int rpc = (int)((nrhs + groups - 1) / groups);
         const dim3 gc(nblk(cells), (nrhs + rpc - 1) / rpc);
-        EHH_LAUNCH_B(lb, (k_relax_cell2d<T>), gc, 256, 0, s, FineOp<2, T>{L.g, L.f}, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpc);
+        EHH_LAUNCHK(lb, k_relax_cell2d, (T), gc, 256, 0, s, FineOp<2, T>{L.g, L.f}, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpc);
     } else if (L.g.dim == 2) {
         if (L.fine)
-            EHH_RB_DISPATCH(rb, EHH_LAUNCH_B(lb, (k_relax_plan<2, T, FineOp<2, T>, RB>), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpb));
+            EHH_RB_DISPATCH(rb, EHH_LAUNCHK(lb, k_relax_plan, (2, T, FineOp<2, T>, RB), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpb));
         else if (L.sp.re[colour])
         {
             // the smallest FP64 levels (one wavefront per CU): rows split over two
@@ -2971,12 +3193,12 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, Damp w, int econ, con
             static const bool split_on = env_int("EHH_SPLIT", 1) != 0;
             const int64_t groups = L.sp.lanes / 64;
             if (sizeof(T) == 8 && ein && split_on && groups <= 256)
-                EHH_LAUNCH_B(lb, (k_relax_st2d_split<T>), dim3((unsigned)((groups + 1) / 2), gb.y), 256, 0, s, L.g, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpb, L.sp.re[colour], L.sp.im[colour], L.sp.lanes);
+                EHH_LAUNCHK(lb, k_relax_st2d_split, (T), dim3((unsigned)((groups + 1) / 2), gb.y), 256, 0, s, L.g, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpb, L.sp.re[colour], L.sp.im[colour], L.sp.lanes);
             else
-                EHH_LAUNCH_B(lb, (k_relax_st2d<T, sizeof(T) == 4, false>), gb, 256, 0, s, L.g, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpb, L.sp.re[colour], L.sp.im[colour], L.sp.lanes, L.g, (const T*)nullptr, (T*)nullptr);
+                EHH_LAUNCHK(lb, k_relax_st2d, (T, sizeof(T) == 4, false), gb, 256, 0, s, L.g, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpb, L.sp.re[colour], L.sp.im[colour], L.sp.lanes, L.g, (const T*)nullptr, (T*)nullptr);
         }
         else
-            EHH_RB_DISPATCH(rb, EHH_LAUNCH_B(lb, (k_relax_plan<2, T, StOp<2, T>, RB>), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpb));
+            EHH_RB_DISPATCH(rb, EHH_LAUNCHK(lb, k_relax_plan, (2, T, StOp<2, T>, RB), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpb));
     } else if (L.fine && cell3d_enabled() && 2 * L.g.N * (int64_t)sizeof(T) < (int64_t(1) << 32)) {
         const int64_t cells = npair;
         // one source group (16 sources per thread) beat two on the 72^3 subdomains:
@@ -2986,15 +3208,15 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, Damp w, int econ, con
         groups = groups < 1 ? 1 : (groups > nrhs ? nrhs : groups);
         const int rpc = (int)((nrhs + groups - 1) / groups);
         const dim3 gc(nblk(cells), (nrhs + rpc - 1) / rpc);
-        EHH_LAUNCH_B(lb, (k_relax_cell3d<T>), gc, 256, 0, s, FineOp<3, T>{L.g, L.f}, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpc);
+        EHH_LAUNCHK(lb, k_relax_cell3d, (T), gc, 256, 0, s, FineOp<3, T>{L.g, L.f}, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpc);
     } else {
         if (L.fine)
-            EHH_RB_DISPATCH(rb, EHH_LAUNCH_B(lb, (k_relax_plan<3, T, FineOp<3, T>, RB>), gb, 256, 0, s, FineOp<3, T>{L.g, L.f}, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpb));
+            EHH_RB_DISPATCH(rb, EHH_LAUNCHK(lb, k_relax_plan, (3, T, FineOp<3, T>, RB), gb, 256, 0, s, FineOp<3, T>{L.g, L.f}, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpb));
         else if (L.sp.re[colour]) {
 #define EHH_RELAX_ST3D(RB, CH, C)                                                                                 \
     {                                                                                                             \
         const int rpbs = rhs_per_block((npair * 8 + 63) / 64, nrhs, RB, 4096);                                    \
-        EHH_LAUNCH_B(lb, (k_relax_st3d<T, RB, CH, C>), dim3(nblk(npair * 8), (nrhs + rpbs - 1) / rpbs), 256, 0,  \
+        EHH_LAUNCHK(lb, k_relax_st3d, (T, RB, CH, C), dim3(nblk(npair * 8), (nrhs + rpbs - 1) / rpbs), 256, 0,  \
                            s, L.g, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpbs, (const C*)L.sp.re[colour], \
                            (const C*)L.sp.im[colour], L.sp.lanes, (T)L.sp.scale);                                 \
     }
@@ -3010,7 +3232,7 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, Damp w, int econ, con
             else EHH_RELAX_ST3D(8, 8, T)
 #undef EHH_RELAX_ST3D
         } else
-            EHH_RB_DISPATCH(rb3, EHH_LAUNCH_B(lb, (k_relax<3, T, StOp<3, T>, RB>), gb3, 256, 0, s, StOp<3, T>{L.g, L.s}, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpb3));
+            EHH_RB_DISPATCH(rb3, EHH_LAUNCHK(lb, k_relax, (3, T, StOp<3, T>, RB), gb3, 256, 0, s, StOp<3, T>{L.g, L.s}, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpb3));
     }
     return hipGetLastError();
 }
@@ -3030,7 +3252,7 @@ hipError_t launch_relax_to64(const LevelDesc<float>& L, Damp w, int econ, const 
     groups = groups < 1 ? 1 : (groups > nrhs ? nrhs : groups);
     const int rpc = (int)((nrhs + groups - 1) / groups);
     const dim3 gc(nblk(cells), (nrhs + rpc - 1) / rpc);
-    EHH_LAUNCH_B(bytes_relax(L.g, true, nrhs, true, 4, 8, 4.0), (k_relax_cell2d<float, double>), gc, 256, 0, s,
+    EHH_LAUNCHK(bytes_relax(L.g, true, nrhs, true, 4, 8, 4.0), k_relax_cell2d, (float, double), gc, 256, 0, s,
                  FineOp<2, float>{L.g, L.f}, 1, (float)w.u, (float)w.p, econ, b, ein, eout, nrhs, stride, rpc);
     *done = true;
     return hipGetLastError();
@@ -3055,7 +3277,7 @@ hipError_t launch_relax_restrict(const LevelDesc<T>& L, Damp w, int econ, const 
     LaunchBytes lb = bytes_relax(L.g, false, nrhs, false, (int)sizeof(T), (int)sizeof(T), (double)sizeof(T));
     lb.mine += nrhs * 2.0 * sizeof(T) * (double)(gf.N + L.g.N);              // rf read, b written
     lb.model += nrhs * 2.0 * sizeof(T) * (gf.dim + 1) * (double)(gf.ncell + L.g.ncell);
-    EHH_LAUNCH_B(lb, (k_relax_st2d<T, sizeof(T) == 4, true>), gb, 256, 0, s, L.g, 0, (T)w.u, (T)w.p, econ, (const T*)b,
+    EHH_LAUNCHK(lb, k_relax_st2d, (T, sizeof(T) == 4, true), gb, 256, 0, s, L.g, 0, (T)w.u, (T)w.p, econ, (const T*)b,
                        (const T*)nullptr, eout, nrhs, stride, rpb, L.sp.re[0], L.sp.im[0], L.sp.lanes, gf, rf, b);
     return hipGetLastError();
 }
@@ -3112,26 +3334,26 @@ template <typename T>
 hipError_t launch_restrict(const Geo& gf, const Geo& gc, const T* rf, T* rc, int nrhs, hipStream_t s) {
     // (k_restrict2d reads the fine vector through a buffer descriptor: below 4 GiB)
     if (gf.dim == 2 && transfer2d_enabled() && 2 * gf.N * (int64_t)sizeof(T) < (int64_t(1) << 32))
-        EHH_LAUNCH_B(bytes_transfer(gf, gc, nrhs, false, (int)sizeof(T)), (k_restrict2d<T>), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc);
+        EHH_LAUNCHK(bytes_transfer(gf, gc, nrhs, false, (int)sizeof(T)), k_restrict2d, (T), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc);
     else if (gf.dim == 2)
-        EHH_LAUNCH_B(bytes_transfer(gf, gc, nrhs, false, (int)sizeof(T)), (k_restrict<2, T>), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc, nrhs);
+        EHH_LAUNCHK(bytes_transfer(gf, gc, nrhs, false, (int)sizeof(T)), k_restrict, (2, T), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc, nrhs);
     else if (transfer2d_enabled() && 2 * gf.N < (int64_t(1) << 31))
-        EHH_LAUNCH_B(bytes_transfer(gf, gc, nrhs, false, (int)sizeof(T)), (k_restrict3d<T>), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc);
+        EHH_LAUNCHK(bytes_transfer(gf, gc, nrhs, false, (int)sizeof(T)), k_restrict3d, (T), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc);
     else
-        EHH_LAUNCH_B(bytes_transfer(gf, gc, nrhs, false, (int)sizeof(T)), (k_restrict<3, T>), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc, nrhs);
+        EHH_LAUNCHK(bytes_transfer(gf, gc, nrhs, false, (int)sizeof(T)), k_restrict, (3, T), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc, nrhs);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_prolong(const Geo& gf, const Geo& gc, const T* ec, T* ef, int nrhs, hipStream_t s) {
     if (gf.dim == 2 && transfer2d_enabled() && 2 * gf.N < (int64_t(1) << 31))
-        EHH_LAUNCH_B(bytes_transfer(gf, gc, nrhs, true, (int)sizeof(T)), (k_prolong2d<T>), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef);
+        EHH_LAUNCHK(bytes_transfer(gf, gc, nrhs, true, (int)sizeof(T)), k_prolong2d, (T), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef);
     else if (gf.dim == 2)
-        EHH_LAUNCH_B(bytes_transfer(gf, gc, nrhs, true, (int)sizeof(T)), (k_prolong<2, T>), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef, nrhs);
+        EHH_LAUNCHK(bytes_transfer(gf, gc, nrhs, true, (int)sizeof(T)), k_prolong, (2, T), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef, nrhs);
     else if (transfer2d_enabled() && 2 * gf.N < (int64_t(1) << 31))
-        EHH_LAUNCH_B(bytes_transfer(gf, gc, nrhs, true, (int)sizeof(T)), (k_prolong3d<T>), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef);
+        EHH_LAUNCHK(bytes_transfer(gf, gc, nrhs, true, (int)sizeof(T)), k_prolong3d, (T), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef);
     else
-        EHH_LAUNCH_B(bytes_transfer(gf, gc, nrhs, true, (int)sizeof(T)), (k_prolong<3, T>), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef, nrhs);
+        EHH_LAUNCHK(bytes_transfer(gf, gc, nrhs, true, (int)sizeof(T)), k_prolong, (3, T), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef, nrhs);
     return hipGetLastError();
 }
 
@@ -3147,7 +3369,7 @@ hipError_t launch_residual_restrict(const LevelDesc<T>& L, const Geo& gc, const 
     const LaunchBytes rb = bytes_transfer(L.g, gc, nrhs, false, (int)sizeof(T));
     lb.mine += nrhs * 2.0 * sizeof(T) * ((double)gc.N - (double)L.g.N);   // rc written, r never written
     lb.model += rb.model - nrhs * 2.0 * sizeof(T) * (L.g.dim + 1) * 2.0 * (double)L.g.ncell;
-    EHH_LAUNCH_B(lb, (k_residual_restrict2d<T>), nblk((int64_t)gc.N * 16), 256, 0, s, L.g, gc, e, b, rc, nrhs,
+    EHH_LAUNCHK(lb, k_residual_restrict2d, (T), nblk((int64_t)gc.N * 16), 256, 0, s, L.g, gc, e, b, rc, nrhs,
                  L.sp.rre, L.sp.rim);
     *done = true;
     return hipGetLastError();

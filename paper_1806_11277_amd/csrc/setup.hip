@@ -10,6 +10,7 @@
 
 #include "internal.hpp"
 #include "launchlog.hpp"
+#include "batch.hpp"
 #include "ops.hpp"
 
 namespace ehh {
@@ -753,11 +754,10 @@ hipError_t launch_permute_columns(const double* X, double* out, int64_t n, const
 // over the columns with FP64 accumulation and a butterfly reduction.  The grid
 // spans rows x right-hand-side groups so that a batch fills the chip.
 template <typename T>
-__global__ __launch_bounds__(256) void k_coarse_apply(const double* __restrict__ inv, int64_t n, const T* __restrict__ r,
-                                                      T* __restrict__ e, int nrhs) {
+EHH_DEV void k_coarse_apply_body(VB ehh_vb, const double* __restrict__ inv, int64_t n, const T* __restrict__ r, T* __restrict__ e, int nrhs) {
     constexpr int RG = 4;
     const int lane = threadIdx.x & 63;
-    const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t row = (int64_t)ehh_vb.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (row >= n) return;
     const int r0 = blockIdx.y * RG;
     const int nr = nrhs - r0 < RG ? nrhs - r0 : RG;
@@ -791,6 +791,18 @@ __global__ __launch_bounds__(256) void k_coarse_apply(const double* __restrict__
         }
     }
 }
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse_apply(const double* __restrict__ inv, int64_t n, const T* __restrict__ r,
+                                                      T* __restrict__ e, int nrhs) {
+    k_coarse_apply_body<T>(single_block<false>(), inv, n, r, e, nrhs);
+}
+template <class PK, typename T>
+__global__ __launch_bounds__(256) void k_coarse_apply_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<false>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_coarse_apply_body<T>(ehh_vb, a...); }, b.arg[ehh_s]);
+}
 
 // Many right-hand sides: a workgroup owns 512/W rows and W right-hand sides and
 // walks the columns in chunks of 64, staging the rows' chunk of the inverse and
@@ -798,16 +810,14 @@ __global__ __launch_bounds__(256) void k_coarse_apply(const double* __restrict__
 // per W right-hand sides instead of once per 4.  Thread: one right-hand side,
 // two rows; the row values are LDS broadcasts within a wavefront.
 template <typename T, int W>
-__global__ __launch_bounds__(256) void k_coarse_apply_multi(const double* __restrict__ inv, int64_t n,
-                                                            const T* __restrict__ r, T* __restrict__ e, int nrhs,
-                                                            int64_t kseg, double* __restrict__ part) {
+EHH_DEV void k_coarse_apply_multi_body(VB ehh_vb, const double* __restrict__ inv, int64_t n, const T* __restrict__ r, T* __restrict__ e, int nrhs, int64_t kseg, double* __restrict__ part) {
     constexpr int ROWS = 512 / W;
     constexpr int KC = 64;
     __shared__ double Ms[ROWS][KC * 2];
     __shared__ double Xs[KC][W * 2];
     const int t = threadIdx.x;
     const int q = t % W, rg = t / W;
-    const int64_t i0 = (int64_t)blockIdx.x * ROWS;
+    const int64_t i0 = (int64_t)ehh_vb.x * ROWS;
     const int q0 = blockIdx.y * W;
     const int64_t jb = (int64_t)blockIdx.z * kseg;
     const int64_t je = jb + kseg < n ? jb + kseg : n;
@@ -873,6 +883,19 @@ __global__ __launch_bounds__(256) void k_coarse_apply_multi(const double* __rest
         ev[n + g0 + 1] = (T)a1i;
     }
 }
+template <typename T, int W>
+__global__ __launch_bounds__(256) void k_coarse_apply_multi(const double* __restrict__ inv, int64_t n,
+                                                            const T* __restrict__ r, T* __restrict__ e, int nrhs,
+                                                            int64_t kseg, double* __restrict__ part) {
+    k_coarse_apply_multi_body<T, W>(single_block<false>(), inv, n, r, e, nrhs, kseg, part);
+}
+template <class PK, typename T, int W>
+__global__ __launch_bounds__(256) void k_coarse_apply_multi_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<false>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_coarse_apply_multi_body<T, W>(ehh_vb, a...); }, b.arg[ehh_s]);
+}
 
 // Register-blocked variant for groups of up to 32 right-hand sides: a workgroup
 // owns 64 rows x 32 right-hand sides of one column segment and stages 16-column
@@ -881,15 +904,13 @@ __global__ __launch_bounds__(256) void k_coarse_apply_multi(const double* __rest
 // staged column costs it 6 LDS reads for 8 complex multiply-adds (the
 // one-register-row variant above needs 6 for 2).
 template <typename T>
-__global__ __launch_bounds__(256) void k_coarse_apply_rb(const double* __restrict__ inv, int64_t n,
-                                                         const T* __restrict__ r, T* __restrict__ e, int nrhs,
-                                                         int64_t kseg, double* __restrict__ part) {
+EHH_DEV void k_coarse_apply_rb_body(VB ehh_vb, const double* __restrict__ inv, int64_t n, const T* __restrict__ r, T* __restrict__ e, int nrhs, int64_t kseg, double* __restrict__ part) {
     constexpr int ROWS = 64, W = 32, KC = 16, RT = 4, QT = 2;
     __shared__ double Ms[KC][ROWS * 2 + 2];
     __shared__ double Xs[KC][W * 2];
     const int t = threadIdx.x;
     const int tq = t & 15, tr = t >> 4;
-    const int64_t i0 = (int64_t)blockIdx.x * ROWS;
+    const int64_t i0 = (int64_t)ehh_vb.x * ROWS;
     const int q0 = blockIdx.y * W;
     const int64_t jb = (int64_t)blockIdx.z * kseg;
     const int64_t je = jb + kseg < n ? jb + kseg : n;
@@ -971,6 +992,19 @@ __global__ __launch_bounds__(256) void k_coarse_apply_rb(const double* __restric
         }
     }
 }
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse_apply_rb(const double* __restrict__ inv, int64_t n,
+                                                         const T* __restrict__ r, T* __restrict__ e, int nrhs,
+                                                         int64_t kseg, double* __restrict__ part) {
+    k_coarse_apply_rb_body<T>(single_block<false>(), inv, n, r, e, nrhs, kseg, part);
+}
+template <class PK, typename T>
+__global__ __launch_bounds__(256) void k_coarse_apply_rb_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<false>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_coarse_apply_rb_body<T>(ehh_vb, a...); }, b.arg[ehh_s]);
+}
 
 // Matrix-core variant (FP64 MFMA 16x16x4) for groups of up to 32 right-hand
 // sides: a workgroup owns 64 rows x 32 right-hand sides of one column segment and
@@ -983,15 +1017,13 @@ __global__ __launch_bounds__(256) void k_coarse_apply_rb(const double* __restric
 // D[l / 16 + 4 r][l % 16].
 typedef double ehh_d4 __attribute__((ext_vector_type(4)));
 template <typename T>
-__global__ __launch_bounds__(256) void k_coarse_apply_mfma(const double* __restrict__ inv, int64_t n,
-                                                           const T* __restrict__ r, T* __restrict__ e, int nrhs,
-                                                           int64_t kseg, double* __restrict__ part) {
+EHH_DEV void k_coarse_apply_mfma_body(VB ehh_vb, const double* __restrict__ inv, int64_t n, const T* __restrict__ r, T* __restrict__ e, int nrhs, int64_t kseg, double* __restrict__ part) {
     constexpr int ROWS = 64, W = 32, KC = 32, MS = KC + 1;   // MS: padded row of the staged chunk
     constexpr int NM = ROWS * KC / 256, NX = KC * W / 256;   // staged values per thread
     __shared__ double Ms[ROWS * MS * 2];
     __shared__ double Xs[KC * W * 2];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int64_t i0 = (int64_t)blockIdx.x * ROWS;
+    const int64_t i0 = (int64_t)ehh_vb.x * ROWS;
     const int q0 = blockIdx.y * W;
     const int64_t jb = (int64_t)blockIdx.z * kseg;
     const int64_t je = jb + kseg < n ? jb + kseg : n;
@@ -1075,16 +1107,40 @@ __global__ __launch_bounds__(256) void k_coarse_apply_mfma(const double* __restr
         }
     }
 }
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse_apply_mfma(const double* __restrict__ inv, int64_t n,
+                                                           const T* __restrict__ r, T* __restrict__ e, int nrhs,
+                                                           int64_t kseg, double* __restrict__ part) {
+    k_coarse_apply_mfma_body<T>(single_block<false>(), inv, n, r, e, nrhs, kseg, part);
+}
+template <class PK, typename T>
+__global__ __launch_bounds__(256) void k_coarse_apply_mfma_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<false>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_coarse_apply_mfma_body<T>(ehh_vb, a...); }, b.arg[ehh_s]);
+}
 
 // e = sum over the column segments of the partial products, in segment order.
 template <typename T>
-__global__ __launch_bounds__(256) void k_coarse_reduce(const double* __restrict__ part, int ks, int64_t n, int nrhs,
-                                                       T* __restrict__ e) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+EHH_DEV void k_coarse_reduce_body(VB ehh_vb, const double* __restrict__ part, int ks, int64_t n, int nrhs, T* __restrict__ e) {
+    const int64_t t = (int64_t)ehh_vb.x * blockDim.x + threadIdx.x;
     if (t >= 2 * n * nrhs) return;
     double s = 0.0;
     for (int z = 0; z < ks; ++z) s += part[(int64_t)z * 2 * n * nrhs + t];
     e[t] = (T)s;
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse_reduce(const double* __restrict__ part, int ks, int64_t n, int nrhs,
+                                                       T* __restrict__ e) {
+    k_coarse_reduce_body<T>(single_block<false>(), part, ks, n, nrhs, e);
+}
+template <class PK, typename T>
+__global__ __launch_bounds__(256) void k_coarse_reduce_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<false>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_coarse_reduce_body<T>(ehh_vb, a...); }, b.arg[ehh_s]);
 }
 
 // ------------------------------------------------ symmetric coarse apply
@@ -1149,14 +1205,12 @@ __device__ inline void halve_step(double* vr, double* vi, int lane) {
 // separate launch: a device-wide fence, which a last-workgroup-sums scheme would
 // need, writes back the L2 of each XCD and costs more than the launch).
 template <typename T>
-__global__ __launch_bounds__(256) void k_coarse_apply_sym(const double* __restrict__ sym, int64_t n, int nb,
-                                                          const T* __restrict__ r, int nrhs,
-                                                          double* __restrict__ ws) {
+EHH_DEV void k_coarse_apply_sym_body(VB ehh_vb, const double* __restrict__ sym, int64_t n, int nb, const T* __restrict__ r, int nrhs, double* __restrict__ ws) {
     constexpr int RG = 4;
     __shared__ double xs[2][RG][SY][2];
     __shared__ double cs[4][RG][SY][2];
     int I, J;
-    sym_tile_of(blockIdx.x, I, J);
+    sym_tile_of(ehh_vb.x, I, J);
     const int r0 = blockIdx.y * RG;
     const int nr = nrhs - r0 < RG ? nrhs - r0 : RG;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -1174,7 +1228,7 @@ __global__ __launch_bounds__(256) void k_coarse_apply_sym(const double* __restri
         xs[side][q][i][1] = vi;
     }
     __syncthreads();
-    const double* tile = sym + (size_t)blockIdx.x * SY * SY * 2;
+    const double* tile = sym + (size_t)ehh_vb.x * SY * SY * 2;
     double ar[16], ai[16];
 #pragma unroll
     for (int rr = 0; rr < 16; ++rr) {
@@ -1230,13 +1284,25 @@ __global__ __launch_bounds__(256) void k_coarse_apply_sym(const double* __restri
         }
     }
 }
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse_apply_sym(const double* __restrict__ sym, int64_t n, int nb,
+                                                          const T* __restrict__ r, int nrhs,
+                                                          double* __restrict__ ws) {
+    k_coarse_apply_sym_body<T>(single_block<false>(), sym, n, nb, r, nrhs, ws);
+}
+template <class PK, typename T>
+__global__ __launch_bounds__(256) void k_coarse_apply_sym_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<false>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_coarse_apply_sym_body<T>(ehh_vb, a...); }, b.arg[ehh_s]);
+}
 
 // e[q][X * 64 + i] = sum over the source blocks J of ws[q][X][J][i], four lanes
 // per output (each a fixed quarter of the sources, then a fixed pairwise sum).
 template <typename T>
-__global__ __launch_bounds__(256) void k_sym_reduce(const double* __restrict__ ws, int64_t n, int nb, int nrhs,
-                                                    T* __restrict__ e) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+EHH_DEV void k_sym_reduce_body(VB ehh_vb, const double* __restrict__ ws, int64_t n, int nb, int nrhs, T* __restrict__ e) {
+    const int64_t t = (int64_t)ehh_vb.x * blockDim.x + threadIdx.x;
     const int part = (int)(t & 3);
     const int64_t o = t >> 2;
     const bool live = o < n * nrhs;
@@ -1275,6 +1341,18 @@ __global__ __launch_bounds__(256) void k_sym_reduce(const double* __restrict__ w
         ev[gi] = (T)sr;
         ev[n + gi] = (T)si;
     }
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_sym_reduce(const double* __restrict__ ws, int64_t n, int nb, int nrhs,
+                                                    T* __restrict__ e) {
+    k_sym_reduce_body<T>(single_block<false>(), ws, n, nb, nrhs, e);
+}
+template <class PK, typename T>
+__global__ __launch_bounds__(256) void k_sym_reduce_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<false>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_sym_reduce_body<T>(ehh_vb, a...); }, b.arg[ehh_s]);
 }
 
 int64_t sym_tiles(int64_t n) {
@@ -1344,13 +1422,13 @@ hipError_t launch_coarse_apply(const double* inv, const double* sym, int64_t n, 
     }();
     if (W == 0 && sym && ws && sym_on) {   // W == 0: one group of at most 4 right-hand sides
         const int nb = (int)((n + SY - 1) / SY);
-        EHH_LAUNCH_B(lb_sym, (k_coarse_apply_sym<T>), dim3((unsigned)sym_tiles(n), 1), 256, 0, s, sym, n, nb, r, nrhs,
+        EHH_LAUNCHK(lb_sym, k_coarse_apply_sym, (T), dim3((unsigned)sym_tiles(n), 1), 256, 0, s, sym, n, nb, r, nrhs,
                            ws);
-        EHH_LAUNCH_B(lb_red, (k_sym_reduce<T>), nblk(4 * n * nrhs), 256, 0, s, ws, n, nb, nrhs, e);
+        EHH_LAUNCHK(lb_red, k_sym_reduce, (T), nblk(4 * n * nrhs), 256, 0, s, ws, n, nb, nrhs, e);
         return hipGetLastError();
     }
     if (W == 0) {
-        EHH_LAUNCH_B(lb_full, (k_coarse_apply<T>), dim3(nblk(n * 64), (nrhs + 3) / 4), 256, 0, s, inv, n, r, e, nrhs);
+        EHH_LAUNCHK(lb_full, k_coarse_apply, (T), dim3(nblk(n * 64), (nrhs + 3) / 4), 256, 0, s, inv, n, r, e, nrhs);
         return hipGetLastError();
     }
     int ks = coarse_ksplit(n, nrhs);
@@ -1361,21 +1439,21 @@ hipError_t launch_coarse_apply(const double* inv, const double* sym, int64_t n, 
     if (W == 32 && coarse_rb_enabled()) {
         const dim3 grid_rb((unsigned)((n + 63) / 64), (unsigned)((nrhs + 31) / 32), (unsigned)ks);
         if (coarse_mfma_enabled())
-            EHH_LAUNCH_B(lb_full, (k_coarse_apply_mfma<T>), grid_rb, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
+            EHH_LAUNCHK(lb_full, k_coarse_apply_mfma, (T), grid_rb, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
         else
-            EHH_LAUNCH_B(lb_full, (k_coarse_apply_rb<T>), grid_rb, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
-        if (part) EHH_LAUNCH_B(lb_red, (k_coarse_reduce<T>), nblk(2 * n * nrhs), 256, 0, s, part, ks, n, nrhs, e);
+            EHH_LAUNCHK(lb_full, k_coarse_apply_rb, (T), grid_rb, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
+        if (part) EHH_LAUNCHK(lb_red, k_coarse_reduce, (T), nblk(2 * n * nrhs), 256, 0, s, part, ks, n, nrhs, e);
         return hipGetLastError();
     }
     const unsigned rows = (unsigned)((n + 512 / W - 1) / (512 / W));
     const dim3 grid(rows, (unsigned)((nrhs + W - 1) / W), (unsigned)ks);
     if (W == 8)
-        EHH_LAUNCH_B(lb_full, (k_coarse_apply_multi<T, 8>), grid, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
+        EHH_LAUNCHK(lb_full, k_coarse_apply_multi, (T, 8), grid, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
     else if (W == 16)
-        EHH_LAUNCH_B(lb_full, (k_coarse_apply_multi<T, 16>), grid, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
+        EHH_LAUNCHK(lb_full, k_coarse_apply_multi, (T, 16), grid, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
     else
-        EHH_LAUNCH_B(lb_full, (k_coarse_apply_multi<T, 32>), grid, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
-    if (part) EHH_LAUNCH_B(lb_red, (k_coarse_reduce<T>), nblk(2 * n * nrhs), 256, 0, s, part, ks, n, nrhs, e);
+        EHH_LAUNCHK(lb_full, k_coarse_apply_multi, (T, 32), grid, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
+    if (part) EHH_LAUNCHK(lb_red, k_coarse_reduce, (T), nblk(2 * n * nrhs), 256, 0, s, part, ks, n, nrhs, e);
     return hipGetLastError();
 }
 // Scratch of the coarsest solve for callers that cannot allocate
@@ -1417,31 +1495,67 @@ template hipError_t launch_coarse_apply<float>(const double*, const double*, int
 template hipError_t launch_coarse_apply<double>(const double*, const double*, int64_t, const double*, double*, int,
                                                 double*, hipStream_t);
 
-__global__ void k_zero_words(uint32_t* __restrict__ p, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+template <int Z = 0>
+EHH_DEV void k_zero_words_body(VB ehh_vb, uint32_t* __restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)ehh_vb.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0u;
+}
+template <int Z = 0>
+__global__ void k_zero_words(uint32_t* __restrict__ p, int64_t n) {
+    k_zero_words_body<Z>(single_block<false>(), p, n);
+}
+template <class PK, int Z = 0>
+__global__ __launch_bounds__(256) void k_zero_words_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<false>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_zero_words_body<Z>(ehh_vb, a...); }, b.arg[ehh_s]);
 }
 // Zero fill by a kernel (not a memset node, so it may sit inside a captured graph).
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
     const int64_t n = (int64_t)(bytes / 4);
-    EHH_LAUNCH_B(bytes_plain((double)bytes), k_zero_words, nblk(n), 256, 0, s, (uint32_t*)p, n);
+    EHH_LAUNCHK(bytes_plain((double)bytes), k_zero_words, (0), nblk(n), 256, 0, s, (uint32_t*)p, n);
     return hipGetLastError();
 }
 
-__global__ void k_cast_d2f(const double* __restrict__ in, float* __restrict__ out, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+template <int Z = 0>
+EHH_DEV void k_cast_d2f_body(VB ehh_vb, const double* __restrict__ in, float* __restrict__ out, int64_t n) {
+    const int64_t i = (int64_t)ehh_vb.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = (float)in[i];
 }
-__global__ void k_cast_f2d(const float* __restrict__ in, double* __restrict__ out, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+template <int Z = 0>
+__global__ void k_cast_d2f(const double* __restrict__ in, float* __restrict__ out, int64_t n) {
+    k_cast_d2f_body<Z>(single_block<false>(), in, out, n);
+}
+template <class PK, int Z = 0>
+__global__ __launch_bounds__(256) void k_cast_d2f_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<false>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_cast_d2f_body<Z>(ehh_vb, a...); }, b.arg[ehh_s]);
+}
+template <int Z = 0>
+EHH_DEV void k_cast_f2d_body(VB ehh_vb, const float* __restrict__ in, double* __restrict__ out, int64_t n) {
+    const int64_t i = (int64_t)ehh_vb.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = (double)in[i];
 }
+template <int Z = 0>
+__global__ void k_cast_f2d(const float* __restrict__ in, double* __restrict__ out, int64_t n) {
+    k_cast_f2d_body<Z>(single_block<false>(), in, out, n);
+}
+template <class PK, int Z = 0>
+__global__ __launch_bounds__(256) void k_cast_f2d_batch(Batch<PK> b) {
+    VB ehh_vb;
+    int ehh_s;
+    if (!batch_block<false>(b, ehh_vb, ehh_s)) return;
+    call_pack([&](auto&&... a) { k_cast_f2d_body<Z>(ehh_vb, a...); }, b.arg[ehh_s]);
+}
 hipError_t launch_cast_d2f(const double* in, float* out, int64_t n, hipStream_t s) {
-    EHH_LAUNCH_B(bytes_plain(12.0 * n), k_cast_d2f, nblk(n), 256, 0, s, in, out, n);
+    EHH_LAUNCHK(bytes_plain(12.0 * n), k_cast_d2f, (0), nblk(n), 256, 0, s, in, out, n);
     return hipGetLastError();
 }
 hipError_t launch_cast_f2d(const float* in, double* out, int64_t n, hipStream_t s) {
-    EHH_LAUNCH_B(bytes_plain(12.0 * n), k_cast_f2d, nblk(n), 256, 0, s, in, out, n);
+    EHH_LAUNCHK(bytes_plain(12.0 * n), k_cast_f2d, (0), nblk(n), 256, 0, s, in, out, n);
     return hipGetLastError();
 }
 
