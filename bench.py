@@ -39,9 +39,9 @@ def rhs_tensor(S, w):
     return torch.as_tensor(B, device="cuda")
 
 
-def run_gpu(w, steps, warmup, tol):
+def run_gpu(w, steps, warmup, tol, tune=True):
     import torch
-    from paper_1806_11277_amd import ehh
+    from paper_1806_11277_amd import ehh, tuning
     m = w.media()
     dev = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda").contiguous()
     lam, mu, rho = dev(m["lam"]), dev(m["mu"]), dev(m["rho"])
@@ -58,6 +58,9 @@ def run_gpu(w, steps, warmup, tol):
     S0 = make()
     B = rhs_tensor(S0, w)
     X = torch.zeros_like(B)
+    # launch shapes: the autotuner's table for this configuration (untimed; from
+    # the cache when an earlier run stored it), installed in every step's solver
+    table, how = tuning.tune(S0, B.shape[0]) if tune else (None, "heuristic")
     S0.close()
     torch.cuda.synchronize()
     results = []
@@ -65,6 +68,8 @@ def run_gpu(w, steps, warmup, tol):
     def step():
         t0 = time.perf_counter()
         S = make()
+        if table is not None:
+            S.set_tuning(table)
         t1 = time.perf_counter()
         st, stats = S.solve(B, X, tol=tol, maxit=w.maxit)
         torch.cuda.synchronize()
@@ -83,7 +88,7 @@ def run_gpu(w, steps, warmup, tol):
         step()
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
-    return total, results, B, X
+    return total, results, B, X, {"source": how, "table": table}
 
 
 KERNEL_SOURCES = ["paper_1806_11277_amd/csrc/levels.hip", "paper_1806_11277_amd/csrc/ops.hpp",
@@ -120,7 +125,7 @@ def traffic_record(workload, kernel):
     return None
 
 
-def cycle_profile(w, reps=5):
+def cycle_profile(w, reps=5, table=None):
     """Every kernel of one preconditioner application, timed live: the library
     records the launches of a real application (ehh_profile_precondition) and
     replays each kernel's launches, with their arguments, from a HIP graph on
@@ -130,6 +135,8 @@ def cycle_profile(w, reps=5):
     import torch
     from paper_1806_11277_amd import ehh
     S = ehh.solver_for_workload(w)
+    if table is not None:
+        S.set_tuning(table)
     nrhs = len(w.sources())
     g = torch.Generator(device="cuda").manual_seed(5)
     v = torch.randn((nrhs, S.stride), dtype=torch.float64, device="cuda", generator=g)
@@ -276,12 +283,14 @@ def poisson_sweep_report():
     return out
 
 
-def accuracy_solve(w, tol):
+def accuracy_solve(w, tol, table=None):
     """One more (untimed) solve of the workload's sources to a tighter relative
     residual, for the errors against the oracle at that residual."""
     import torch
     from paper_1806_11277_amd import ehh
     S = ehh.solver_for_workload(w)
+    if table is not None:
+        S.set_tuning(table)
     B = rhs_tensor(S, w)
     X = torch.zeros_like(B)
     st, stats = S.solve(B, X, tol=tol, maxit=4 * w.maxit)
@@ -290,9 +299,9 @@ def accuracy_solve(w, tol):
     return X, max(s_["rel_res_true"] for s_ in stats), [s_["iters"] for s_ in stats]
 
 
-def workload_entry(w, steps, warmup, tol, copy_gbs, with_profile):
+def workload_entry(w, steps, warmup, tol, copy_gbs, with_profile, tune=True):
     """Time `steps` steps of a workload (after `warmup`), with its cycle profile."""
-    total, res, B, X = run_gpu(w, steps, warmup, tol)
+    total, res, B, X, tuned = run_gpu(w, steps, warmup, tol, tune)
     stats = res[-1][3]
     iters = [s_["iters"] for s_ in stats]
     out = {"workload": w.name, "nrhs": len(stats), "value": len(stats) * steps / total, "unit": "solves/s",
@@ -301,10 +310,11 @@ def workload_entry(w, steps, warmup, tol, copy_gbs, with_profile):
            "solve_ms": 1e3 * float(np.mean([r[1] for r in res])),
            "iters": iters if len(iters) <= 4 else [min(iters), max(iters)],
            "rel_res_true_max": max(s_["rel_res_true"] for s_ in stats), "status": res[-1][2],
-           "dtype": "f64" if w.precond_bits == 64 else "f32 cycle + f64 Krylov/coarsest"}
+           "dtype": "f64" if w.precond_bits == 64 else "f32 cycle + f64 Krylov/coarsest",
+           "launch_shapes": tuned}
     if with_profile:
         print(f"[bench] cycle profile {w.name}", file=sys.stderr, flush=True)
-        out["roofline"] = roofline(w, cycle_profile(w), copy_gbs)
+        out["roofline"] = roofline(w, cycle_profile(w, table=tuned["table"]), copy_gbs)
     return out, X
 
 
@@ -329,6 +339,8 @@ def main():
     ap.add_argument("--coarse-bits", type=int, default=None, choices=(16, 32),
                     help="storage of the 3D Galerkin levels' stored rows in the complex64 cycle "
                          "(16: FP16 with a power-of-two scale per level)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the heuristic launch shapes instead of the autotuner's (cached) table")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for traffic counters)")
     a = ap.parse_args()
@@ -355,7 +367,8 @@ def main():
     copy_gbs = None if a.no_roofline else copy_bandwidth()
     print(f"[bench] {w.name}: n={w.n} nrhs={len(w.sources())} levels={w.levels} cycle={w.cycle} "
           f"bits={w.precond_bits}", file=sys.stderr, flush=True)
-    main_e, X = workload_entry(w, a.steps, a.warmup, a.tol, copy_gbs, False)
+    main_e, X = workload_entry(w, a.steps, a.warmup, a.tol, copy_gbs, False, not a.no_tune)
+    table = main_e["launch_shapes"]["table"]
     out = {
         "metric": "preconditioned solves/sec at rel. residual 1e-6; V-cycle HBM GB/s vs peak",
         "value": main_e["value"],
@@ -373,13 +386,14 @@ def main():
                    "dd_parts": list(w.dd_parts[:w.dim]), "coarse_bits": w.coarse_bits, "tol": a.tol},
         "setup_ms": main_e["setup_ms"], "solve_ms": main_e["solve_ms"],
         "iters": main_e["iters"], "rel_res_true_max": main_e["rel_res_true_max"], "status": main_e["status"],
+        "launch_shapes": main_e["launch_shapes"],
     }
     results = {w.name: (w, X, None)}
     if a.accuracy_tol > 0 and not a.no_cpu_baseline:
-        results[w.name] = (w, X, accuracy_solve(w, a.accuracy_tol))
+        results[w.name] = (w, X, accuracy_solve(w, a.accuracy_tol, table))
     if not a.no_roofline:
         print(f"[bench] cycle profile {w.name}", file=sys.stderr, flush=True)
-        rl = roofline(w, cycle_profile(w), copy_gbs)
+        rl = roofline(w, cycle_profile(w, table=table), copy_gbs)
         out["roofline"] = {k: v for k, v in rl.items() if k != "kernels"}
         out["cycle_kernels"] = rl["kernels"]
     comps = [c for c in a.companions.split(",") if c]
@@ -389,10 +403,10 @@ def main():
         if a.coarse_bits is not None:
             wc = dataclasses.replace(wc, coarse_bits=a.coarse_bits)
         print(f"[bench] companion {wc.name}", file=sys.stderr, flush=True)
-        e, Xc = workload_entry(wc, a.companion_steps, 1, a.tol, copy_gbs, not a.no_roofline)
+        e, Xc = workload_entry(wc, a.companion_steps, 1, a.tol, copy_gbs, not a.no_roofline, not a.no_tune)
         e["speedup_vs_plain_fp64_single_source"] = e["value"] / out["value"]
         out["companions"].append(e)
-        acc = accuracy_solve(wc, a.accuracy_tol) if (a.accuracy_tol > 0 and not a.no_cpu_baseline and
+        acc = accuracy_solve(wc, a.accuracy_tol, e["launch_shapes"]["table"]) if (a.accuracy_tol > 0 and not a.no_cpu_baseline and
                                                     wc.dim == 2) else None
         results[wc.name] = (wc, Xc, acc)
     if not a.no_cpu_baseline:

@@ -267,6 +267,21 @@ int32_t ehh_level_prolong(ehh_handle_t h, int32_t sub, int32_t level, const void
 int32_t ehh_coarse_solve(ehh_handle_t h, int32_t sub, const void* r, void* e,
                          int32_t nrhs, void* stream);
 
+/* Launch-shape autotuner.  For every level (on the first subdomain, applied to
+ * all), the half-sweep and the residual are launched with each candidate
+ * number of source groups per launch (the heuristic one, 1, 2, 4, ..., up to
+ * nrhs) on zeroed workspaces and timed with HIP events on `stream` (best of
+ * three rounds of 8 launches); another shape replaces the heuristic one when
+ * it is at least 2 % faster.  The choice only changes which grid rows handle
+ * which sources, so results are the same to the bit for any table.
+ * table[2 * levels] receives (half-sweep groups, residual groups) per level,
+ * finest first (0 = the heuristic); captured graphs are rebuilt.  Synchronises
+ * `stream`. */
+int32_t ehh_autotune(ehh_handle_t h, int32_t nrhs, int32_t* table, int32_t len, void* stream);
+/* Install a table from ehh_autotune (e.g. kept in a cache across runs);
+ * len = 2 * levels, entries in [0, 4096]. */
+int32_t ehh_set_tuning(ehh_handle_t h, const int32_t* table, int32_t len);
+
 /* Measurement of the preconditioner's kernels (the cycle's HBM roofline).
  * One application z = M^{-1} v (as ehh_precondition) is run with every kernel
  * launch recorded; then each distinct kernel's launches of that application are

@@ -194,6 +194,7 @@ struct PhaseLog {
 struct Level {
     Geo g{};
     bool fine = false;
+    int tune_relax = 0, tune_apply = 0;   // source groups per launch (autotuner; 0: heuristic)
     double damping = 0.0;       // Vanka damping of the displacement rows
     double damping_p = 0.0;     // and of the pressure row
     double* coef64 = nullptr;   // fine: mu, dinv, rho, gam planes; coarse: stencil
@@ -373,6 +374,8 @@ template <typename T> LevelDesc<T> level_desc(const ehh_ctx* c, const Level& L, 
     LevelDesc<T> d{};
     d.g = L.g;
     d.fine = L.fine;
+    d.tune_relax = L.tune_relax;
+    d.tune_apply = L.tune_apply;
     const T* base = coef_of<T>(L);
     if (L.fine) {
         const int64_t n = L.g.ncell;
@@ -1411,6 +1414,81 @@ int32_t time_replay(ehh_ctx* c, const std::vector<const LogRec*>& recs, int reps
 }  // namespace
 
 // ======================================================================= C ABI
+namespace {
+// Best of three timings of `reps` back-to-back calls of f on stream s [ms].
+template <class F> int32_t time_calls(hipStream_t s, int reps, F&& f, double* ms) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    double best = 1e300;
+    int32_t st = EHH_OK;
+    for (int w = 0; w < 2 && st == EHH_OK; ++w) st = f();   // warm-up
+    for (int t = 0; t < 3 && st == EHH_OK; ++t) {
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < reps && st == EHH_OK; ++r) st = f();
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float f_ms = 0.0f;
+        (void)hipEventElapsedTime(&f_ms, e0, e1);
+        best = std::min(best, (double)f_ms);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = best;
+    return st;
+}
+
+template <typename T> int32_t autotune_t(ehh_ctx* c, int nrhs, hipStream_t s) {
+    Sub& S = c->subs[0];
+    const int L = (int)S.lev.size();
+    const int econ = c->opt.vanka == 0;
+    const int cand[] = {0, 1, 2, 4, 8, 16, 32, 64};
+    for (int l = 0; l < L; ++l) {
+        Level& Q = S.lev[l];
+        const size_t bytes = sizeof(T) * 2 * (size_t)Q.g.N * nrhs;
+        T* b = (T*)(l == 0 ? S.r0 : Q.b);
+        T* e = (T*)(l == 0 ? S.e0 : Q.e);
+        T* t = (T*)Q.t;
+        HIPCHK(launch_zero(b, bytes, s));
+        HIPCHK(launch_zero(e, bytes, s));
+        for (int kind = 0; kind < 2; ++kind) {
+            if (kind == 0 && l == L - 1) continue;   // the coarsest level is not relaxed
+            int& knob = kind == 0 ? Q.tune_relax : Q.tune_apply;
+            double best = 1e300;
+            int pick = 0;
+            for (int g : cand) {
+                if (g > nrhs) break;
+                knob = g;
+                const LevelDesc<T> D = level_desc<T>(c, Q, c->prob.shift);
+                double ms = 0.0;
+                if (kind == 0)
+                    CHK(time_calls(s, 8, [&]() -> int32_t {
+                        HIPCHK(launch_relax<T>(D, 0, Damp{Q.damping, Q.damping_p}, econ, b, e, t, nrhs, s));
+                        return EHH_OK;
+                    }, &ms));
+                else
+                    CHK(time_calls(s, 8, [&]() -> int32_t {
+                        HIPCHK(launch_apply<T>(D, e, b, t, nrhs, s));
+                        return EHH_OK;
+                    }, &ms));
+                // another shape must beat the heuristic one by 2 % to replace it
+                if (g == 0 || ms < 0.98 * best) {
+                    if (g == 0 || ms < best) pick = g;
+                    best = std::min(best, ms);
+                }
+            }
+            knob = pick;
+        }
+    }
+    for (Sub& O : c->subs)
+        for (int l = 0; l < L && l < (int)O.lev.size(); ++l) {
+            O.lev[l].tune_relax = S.lev[l].tune_relax;
+            O.lev[l].tune_apply = S.lev[l].tune_apply;
+        }
+    return EHH_OK;
+}
+}  // namespace
+
 extern "C" {
 
 void ehh_default_options(ehh_options_t* o) {
@@ -1887,6 +1965,40 @@ int32_t ehh_profile_precondition(ehh_handle_t h, const double* v, double* z, int
         }
     }
     *count = k;
+    return EHH_OK;
+}
+
+
+int32_t ehh_autotune(ehh_handle_t h, int32_t nrhs, int32_t* table, int32_t len, void* stream) {
+    CHK(check_handle(h));
+    const int L = (int)h->subs[0].lev.size();
+    if (nrhs < 1 || !table || len < 2 * L) return fail(EHH_ERR_INVALID, "ehh_autotune: nrhs >= 1, table of 2 x levels");
+    hipStream_t s = as_stream(stream);
+    CHK(ensure_ws(h, nrhs));
+    h->clear_graphs();
+    for (Sub& S : h->subs)
+        for (Level& Q : S.lev) Q.tune_relax = Q.tune_apply = 0;
+    CHK(h->bits() == 32 ? autotune_t<float>(h, nrhs, s) : autotune_t<double>(h, nrhs, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int l = 0; l < L; ++l) {
+        table[2 * l] = h->subs[0].lev[l].tune_relax;
+        table[2 * l + 1] = h->subs[0].lev[l].tune_apply;
+    }
+    return EHH_OK;
+}
+
+int32_t ehh_set_tuning(ehh_handle_t h, const int32_t* table, int32_t len) {
+    CHK(check_handle(h));
+    const int L = (int)h->subs[0].lev.size();
+    if (!table || len != 2 * L) return fail(EHH_ERR_INVALID, "ehh_set_tuning: table of 2 x levels entries");
+    for (int i = 0; i < len; ++i)
+        if (table[i] < 0 || table[i] > 4096) return fail(EHH_ERR_INVALID, "ehh_set_tuning: entries in [0, 4096]");
+    h->clear_graphs();
+    for (Sub& S : h->subs)
+        for (int l = 0; l < L && l < (int)S.lev.size(); ++l) {
+            S.lev[l].tune_relax = table[2 * l];
+            S.lev[l].tune_apply = table[2 * l + 1];
+        }
     return EHH_OK;
 }
 

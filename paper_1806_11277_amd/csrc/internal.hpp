@@ -32,6 +32,10 @@ template <typename T> struct LevelDesc {
     FineCoef<T> f;
     StCoef<T> s;
     StoredPlan<T> sp;
+    // source groups per launch chosen by the autotuner for the level's half-sweeps
+    // and residuals (0: the launchers' own heuristic); launch shapes only, the
+    // arithmetic of every source is the same for any value
+    int tune_relax = 0, tune_apply = 0;
 };
 
 // Vanka damping of one level: u for the displacement rows of a cell block, p for

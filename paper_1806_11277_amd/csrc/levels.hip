@@ -3031,15 +3031,11 @@ __global__ __launch_bounds__(256) void k_prolong3d_batch(Batch<PK> b) {
 static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
 // Right-hand sides per grid row: a level whose rows fill fewer than a target
-// number of wavefronts gets its batch split over grid rows (the coefficients of a
-// small level stay in cache, so re-reading them per group costs little).
-static inline int env_int(const char* name, int dflt) {
-    const char* v = std::getenv(name);
-    return v ? std::atoi(v) : dflt;
-}
-static inline int rhs_per_block(int64_t waves, int nrhs, int rb, int64_t target = 0) {
-    static const int64_t dflt = env_int("EHH_WAVES", 2048);
-    if (target <= 0) target = dflt;
+// number of wavefronts (2048; 4096 for the one-thread-per-cell finest-level
+// kernels, 2048 in 3D) gets its batch split over grid rows (the coefficients of
+// a small level stay in cache, so re-reading them per group costs little).
+static constexpr int64_t kWaves = 2048, kCellWaves = 4096, kCell3dWaves = 2048;
+static inline int rhs_per_block(int64_t waves, int nrhs, int rb, int64_t target = kWaves) {
     int64_t groups = waves >= target ? 1 : (target + waves - 1) / waves;
     const int64_t maxg = (nrhs + rb - 1) / rb;
     if (groups > maxg) groups = maxg;
@@ -3048,34 +3044,28 @@ static inline int rhs_per_block(int64_t waves, int nrhs, int rb, int64_t target 
     rpb = ((rpb + rb - 1) / rb) * rb;
     return rpb < 1 ? 1 : rpb;
 }
-// Right-hand sides evaluated together per row.  Measured on MI355X: one per row
-// is fastest for the row-plan kernels (fewer registers, more wavefronts in
-// flight outweigh the extra independent loads); the 3D Galerkin rows (93 terms)
-// share each coefficient load across a block of right-hand sides.
-template <typename T> static inline int rhs_block() {
-    static const int v = env_int(sizeof(T) == 4 ? "EHH_RB32" : "EHH_RB64", 1);
-    return v == 1 || v == 2 || v == 4 ? v : 1;
+// Sources per grid row of the one-thread-per-cell kernels (groups of whole sources).
+static inline int rhs_per_cells(int64_t cells, int nrhs, int64_t target) {
+    int64_t groups = (target + (cells + 63) / 64 - 1) / ((cells + 63) / 64);
+    groups = groups < 1 ? 1 : (groups > nrhs ? nrhs : groups);
+    return (int)((nrhs + groups - 1) / groups);
 }
-static inline bool cell2d_enabled() {
-    static const bool v = env_int("EHH_CELL2D", 1) != 0;
-    return v;
+// The autotuner's choice for a launch (tune = source groups per launch, 0: keep
+// the heuristic value dflt), as sources per grid row in multiples of rb.
+static inline int tuned(int tune, int nrhs, int rb, int dflt) {
+    if (tune <= 0) return dflt;
+    const int g = tune < nrhs ? tune : nrhs;
+    int r = (nrhs + g - 1) / g;
+    r = (r + rb - 1) / rb * rb;
+    return r < 1 ? 1 : r;
 }
-static inline bool cell3d_enabled() {
-    static const bool v = env_int("EHH_CELL3D", 1) != 0;
-    return v;
-}
-static inline bool transfer2d_enabled() {   // the 32-bit transfer kernels (2D and 3D)
-    static const bool v = env_int("EHH_TRANSFER2D", 1) != 0;
-    return v;
-}
-static inline bool lds2d_enabled() {
-    static const bool v = env_int("EHH_LDS2D", 1) != 0;
-    return v;
-}
-template <typename T> static inline int rhs_block_3d_stencil() {
-    static const int v = env_int("EHH_RB3D", sizeof(T) == 4 ? 4 : 2);
-    return v == 1 || v == 2 || v == 4 ? v : 2;
-}
+// Right-hand sides evaluated together per row by the row-plan kernels (the
+// fallbacks where no stored rows or one-thread-per-cell kernel serve a level):
+// one per row (measured on MI355X: fewer registers, more wavefronts in flight
+// outweigh the extra independent loads); the 3D Galerkin rows (93 terms) share
+// each coefficient load across a block of right-hand sides.
+template <typename T> static inline int rhs_block() { return 1; }
+template <typename T> static inline int rhs_block_3d_stencil() { return sizeof(T) == 4 ? 4 : 2; }
 
 
 #define EHH_RB_DISPATCH(RBV, CALL) \
@@ -3095,20 +3085,18 @@ template <typename T> static inline int rhs_block_3d_stencil() {
 template <typename T>
 hipError_t launch_apply(const LevelDesc<T>& L, const T* x, const T* b, T* y, int nrhs, hipStream_t s) {
     const int64_t stride = 2 * L.g.N;
+#define TUNE(V, RBV) tuned(L.tune_apply, nrhs, (RBV), (V))
     const int rb = rhs_block<T>();
-    const int rpb = rhs_per_block((L.g.N + 63) / 64, nrhs, rb);
+    const int rpb = TUNE(rhs_per_block((L.g.N + 63) / 64, nrhs, rb), rb);
     const dim3 gb(nblk(L.g.N), (nrhs + rpb - 1) / rpb);
     const int rb3 = rhs_block_3d_stencil<T>();
-    const int rpb3 = rhs_per_block((L.g.N + 63) / 64, nrhs, rb3);
+    const int rpb3 = TUNE(rhs_per_block((L.g.N + 63) / 64, nrhs, rb3), rb3);
     const dim3 gb3(nblk(L.g.N), (nrhs + rpb3 - 1) / rpb3);
     const double coef_es = L.fine ? (double)sizeof(T) : (L.sp.half ? 2.0 : (double)sizeof(T));
     const LaunchBytes lb = bytes_apply(L.g, L.fine, nrhs, b != nullptr, (int)sizeof(T), coef_es);
-    if (L.g.dim == 2 && L.fine && cell2d_enabled() && 2 * L.g.N * (int64_t)sizeof(T) < (int64_t(1) << 32)) {
+    if (L.g.dim == 2 && L.fine && 2 * L.g.N * (int64_t)sizeof(T) < (int64_t(1) << 32)) {
         const int64_t cells = L.g.ncell;
-        static const int64_t cell_waves = env_int("EHH_CELL_WAVES", 4096);
-        int64_t groups = (cell_waves + (cells + 63) / 64 - 1) / ((cells + 63) / 64);
-        groups = groups < 1 ? 1 : (groups > nrhs ? nrhs : groups);
-        const int rpc = (int)((nrhs + groups - 1) / groups);
+        const int rpc = TUNE(rhs_per_cells(cells, nrhs, kCellWaves), 1);
         const dim3 gc(nblk(cells), (nrhs + rpc - 1) / rpc);
         EHH_LAUNCHK(lb, k_apply_cell2d, (T), gc, 256, 0, s, FineOp<2, T>{L.g, L.f}, x, b, y, nrhs, stride, rpc);
     } else if (L.g.dim == 2) {
@@ -3118,12 +3106,9 @@ hipError_t launch_apply(const LevelDesc<T>& L, const T* x, const T* b, T* y, int
             EHH_LAUNCHK(lb, k_apply_st2d, (T), gb, 256, 0, s, L.g, x, b, y, nrhs, stride, rpb, L.sp.rre, L.sp.rim);
         else
             EHH_RB_DISPATCH(rb, EHH_LAUNCHK(lb, k_apply_plan, (2, T, StOp<2, T>, RB), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, x, b, y, nrhs, stride, rpb));
-    } else if (L.g.dim == 3 && L.fine && cell3d_enabled() && 2 * L.g.N * (int64_t)sizeof(T) < (int64_t(1) << 32)) {
+    } else if (L.g.dim == 3 && L.fine && 2 * L.g.N * (int64_t)sizeof(T) < (int64_t(1) << 32)) {
         const int64_t cells = L.g.ncell;
-        static const int64_t cell_waves = env_int("EHH_CELL_WAVES", 4096);
-        int64_t groups = (cell_waves + (cells + 63) / 64 - 1) / ((cells + 63) / 64);
-        groups = groups < 1 ? 1 : (groups > nrhs ? nrhs : groups);
-        const int rpc = (int)((nrhs + groups - 1) / groups);
+        const int rpc = TUNE(rhs_per_cells(cells, nrhs, kCellWaves), 1);
         const dim3 gc(nblk(cells), (nrhs + rpc - 1) / rpc);
         EHH_LAUNCHK(lb, k_apply_cell3d, (T), gc, 256, 0, s, FineOp<3, T>{L.g, L.f}, x, b, y, nrhs, stride, rpc);
     } else {
@@ -3132,7 +3117,7 @@ hipError_t launch_apply(const LevelDesc<T>& L, const T* x, const T* b, T* y, int
         else if (L.sp.rre) {
 #define EHH_APPLY_ST3D(RB, CH, C)                                                                                \
     {                                                                                                            \
-        const int rpbs = rhs_per_block((L.g.N + 63) / 64, nrhs, RB);                                             \
+        const int rpbs = TUNE(rhs_per_block((L.g.N + 63) / 64, nrhs, RB), RB);                                   \
         EHH_LAUNCHK(lb, k_apply_st3d, (T, RB, CH, C), dim3(nblk(L.g.N), (nrhs + rpbs - 1) / rpbs), 256, 0, s,   \
                            L.g, x, b, y, nrhs, stride, rpbs, (const C*)L.sp.rre, (const C*)L.sp.rim,             \
                            (T)L.sp.scale);                                                                       \
@@ -3144,6 +3129,7 @@ hipError_t launch_apply(const LevelDesc<T>& L, const T* x, const T* b, T* y, int
         } else
             EHH_RB_DISPATCH(rb3, EHH_LAUNCHK(lb, k_apply, (3, T, StOp<3, T>, RB), gb3, 256, 0, s, StOp<3, T>{L.g, L.s}, x, b, y, nrhs, stride, rpb3));
     }
+#undef TUNE
     return hipGetLastError();
 }
 
@@ -3151,12 +3137,13 @@ template <typename T>
 hipError_t launch_relax(const LevelDesc<T>& L, int colour, Damp w, int econ, const T* b, const T* ein,
                         T* eout, int nrhs, hipStream_t s) {
     const int64_t stride = 2 * L.g.N;
+#define TUNE(V, RBV) tuned(L.tune_relax, nrhs, (RBV), (V))
     const int64_t npair = (int64_t)(L.g.n[0] / 2) * L.g.n[1] * L.g.n[2];
     const int rb = rhs_block<T>();
-    const int rpb = rhs_per_block((npair * 8 + 63) / 64, nrhs, rb);
+    const int rpb = TUNE(rhs_per_block((npair * 8 + 63) / 64, nrhs, rb), rb);
     const dim3 gb(nblk(npair * 8), (nrhs + rpb - 1) / rpb);
     const int rb3 = rhs_block_3d_stencil<T>();
-    const int rpb3 = rhs_per_block((npair * 8 + 63) / 64, nrhs, rb3);
+    const int rpb3 = TUNE(rhs_per_block((npair * 8 + 63) / 64, nrhs, rb3), rb3);
     const dim3 gb3(nblk(npair * 8), (nrhs + rpb3 - 1) / rpb3);
     const T tw = (T)w.u, twp = (T)w.p;
     const double coef_es = L.fine ? (double)sizeof(T) : (L.sp.half ? 2.0 : (double)sizeof(T));
@@ -3168,18 +3155,15 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, Damp w, int econ, con
     // 128^2 and below the block-wide synchronisation costs more than it saves.
     const bool big_batch = !(L.sp.re[colour] && nrhs <= 8);
     const int lds_tiles = ((L.g.n[0] + LT_X - 1) / LT_X) * ((L.g.n[1] + LT_Y - 1) / LT_Y);
-    const int rpl = rhs_per_block((int64_t)lds_tiles * 8, nrhs, 1);
+    const int rpl = TUNE(rhs_per_block((int64_t)lds_tiles * 8, nrhs, 1), 1);
     if (L.g.dim == 2 && !L.fine && L.g.ncell >= 65536 && rpl * stride * (int64_t)sizeof(T) < (int64_t(1) << 31) &&
-        lds2d_enabled() && big_batch) {
+        big_batch) {
         const int tiles = lds_tiles;
         const dim3 gl(tiles, (nrhs + rpl - 1) / rpl);
         EHH_LAUNCHK(lb, k_relax_lds2d, (T, StOp<2, T>), gl, 512, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpl, 2);
-    } else if (L.g.dim == 2 && L.fine && cell2d_enabled() && 2 * L.g.N * (int64_t)sizeof(T) < (int64_t(1) << 32)) {
+    } else if (L.g.dim == 2 && L.fine && 2 * L.g.N * (int64_t)sizeof(T) < (int64_t(1) << 32)) {
         const int64_t cells = npair;
-        static const int64_t cell_waves = env_int("EHH_CELL_WAVES", 4096);
-        int64_t groups = (cell_waves + (cells + 63) / 64 - 1) / ((cells + 63) / 64);
-        groups = groups < 1 ? 1 : (groups > nrhs ? nrhs : groups);
-        const int rpc = (int)((nrhs + groups - 1) / groups);
+        const int rpc = TUNE(rhs_per_cells(cells, nrhs, kCellWaves), 1);
         const dim3 gc(nblk(cells), (nrhs + rpc - 1) / rpc);
         EHH_LAUNCHK(lb, k_relax_cell2d, (T), gc, 256, 0, s, FineOp<2, T>{L.g, L.f}, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpc);
     } else if (L.g.dim == 2) {
@@ -3190,23 +3174,19 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, Damp w, int econ, con
             // the smallest FP64 levels (one wavefront per CU): rows split over two
             // wavefronts, one batch of loads per row instead of three (measured on
             // MI355X: 64^2 5.4 -> 4.8 us; no gain at 128^2)
-            static const bool split_on = env_int("EHH_SPLIT", 1) != 0;
             const int64_t groups = L.sp.lanes / 64;
-            if (sizeof(T) == 8 && ein && split_on && groups <= 256)
+            if (sizeof(T) == 8 && ein && groups <= 256)
                 EHH_LAUNCHK(lb, k_relax_st2d_split, (T), dim3((unsigned)((groups + 1) / 2), gb.y), 256, 0, s, L.g, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpb, L.sp.re[colour], L.sp.im[colour], L.sp.lanes);
             else
                 EHH_LAUNCHK(lb, k_relax_st2d, (T, sizeof(T) == 4, false), gb, 256, 0, s, L.g, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpb, L.sp.re[colour], L.sp.im[colour], L.sp.lanes, L.g, (const T*)nullptr, (T*)nullptr);
         }
         else
             EHH_RB_DISPATCH(rb, EHH_LAUNCHK(lb, k_relax_plan, (2, T, StOp<2, T>, RB), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpb));
-    } else if (L.fine && cell3d_enabled() && 2 * L.g.N * (int64_t)sizeof(T) < (int64_t(1) << 32)) {
+    } else if (L.fine && 2 * L.g.N * (int64_t)sizeof(T) < (int64_t(1) << 32)) {
         const int64_t cells = npair;
         // one source group (16 sources per thread) beat two on the 72^3 subdomains:
         // the 7 x 7 block inverse is then formed once per cell (c4 solve 8.60 -> 8.51 s)
-        static const int64_t cell_waves = env_int("EHH_CELL3D_WAVES", 2048);
-        int64_t groups = (cell_waves + (cells + 63) / 64 - 1) / ((cells + 63) / 64);
-        groups = groups < 1 ? 1 : (groups > nrhs ? nrhs : groups);
-        const int rpc = (int)((nrhs + groups - 1) / groups);
+        const int rpc = TUNE(rhs_per_cells(cells, nrhs, kCell3dWaves), 1);
         const dim3 gc(nblk(cells), (nrhs + rpc - 1) / rpc);
         EHH_LAUNCHK(lb, k_relax_cell3d, (T), gc, 256, 0, s, FineOp<3, T>{L.g, L.f}, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpc);
     } else {
@@ -3215,7 +3195,7 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, Damp w, int econ, con
         else if (L.sp.re[colour]) {
 #define EHH_RELAX_ST3D(RB, CH, C)                                                                                 \
     {                                                                                                             \
-        const int rpbs = rhs_per_block((npair * 8 + 63) / 64, nrhs, RB, 4096);                                    \
+        const int rpbs = TUNE(rhs_per_block((npair * 8 + 63) / 64, nrhs, RB, 4096), RB);                          \
         EHH_LAUNCHK(lb, k_relax_st3d, (T, RB, CH, C), dim3(nblk(npair * 8), (nrhs + rpbs - 1) / rpbs), 256, 0,  \
                            s, L.g, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpbs, (const C*)L.sp.re[colour], \
                            (const C*)L.sp.im[colour], L.sp.lanes, (T)L.sp.scale);                                 \
@@ -3234,6 +3214,7 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, Damp w, int econ, con
         } else
             EHH_RB_DISPATCH(rb3, EHH_LAUNCHK(lb, k_relax, (3, T, StOp<3, T>, RB), gb3, 256, 0, s, StOp<3, T>{L.g, L.s}, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpb3));
     }
+#undef TUNE
     return hipGetLastError();
 }
 
@@ -3243,14 +3224,11 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, Damp w, int econ, con
 hipError_t launch_relax_to64(const LevelDesc<float>& L, Damp w, int econ, const float* b, const float* ein,
                              double* eout, int nrhs, hipStream_t s, bool* done) {
     *done = false;
-    if (!(L.g.dim == 2 && L.fine && cell2d_enabled() && 2 * L.g.N * (int64_t)sizeof(double) < (int64_t(1) << 32)))
+    if (!(L.g.dim == 2 && L.fine && 2 * L.g.N * (int64_t)sizeof(double) < (int64_t(1) << 32)))
         return hipSuccess;
     const int64_t stride = 2 * L.g.N;
     const int64_t cells = (int64_t)(L.g.n[0] / 2) * L.g.n[1];
-    static const int64_t cell_waves = env_int("EHH_CELL_WAVES", 4096);
-    int64_t groups = (cell_waves + (cells + 63) / 64 - 1) / ((cells + 63) / 64);
-    groups = groups < 1 ? 1 : (groups > nrhs ? nrhs : groups);
-    const int rpc = (int)((nrhs + groups - 1) / groups);
+    const int rpc = tuned(L.tune_relax, nrhs, 1, rhs_per_cells(cells, nrhs, kCellWaves));
     const dim3 gc(nblk(cells), (nrhs + rpc - 1) / rpc);
     EHH_LAUNCHK(bytes_relax(L.g, true, nrhs, true, 4, 8, 4.0), k_relax_cell2d, (float, double), gc, 256, 0, s,
                  FineOp<2, float>{L.g, L.f}, 1, (float)w.u, (float)w.p, econ, b, ein, eout, nrhs, stride, rpc);
@@ -3260,19 +3238,18 @@ hipError_t launch_relax_to64(const LevelDesc<float>& L, Damp w, int econ, const 
 
 template <typename T>
 bool relax_restrict_supported(const LevelDesc<T>& L, const Geo& gf, int nrhs) {
-    static const bool on = env_int("EHH_RELAX_RESTRICT", 1) != 0;
-    if (!on || L.g.dim != 2 || L.fine || !L.sp.re[0]) return false;
+    if (L.g.dim != 2 || L.fine || !L.sp.re[0]) return false;
     // the finer level's residual is read through a buffer descriptor
     if (2 * gf.N * (int64_t)sizeof(T) >= (int64_t(1) << 32)) return false;
     // same routing as launch_relax: the LDS kernel serves large levels with many sources
-    return !(L.g.ncell >= 65536 && lds2d_enabled() && nrhs > 8);
+    return !(L.g.ncell >= 65536 && nrhs > 8);
 }
 template <typename T>
 hipError_t launch_relax_restrict(const LevelDesc<T>& L, Damp w, int econ, const Geo& gf, const T* rf, T* b,
                                  T* eout, int nrhs, hipStream_t s) {
     const int64_t stride = 2 * L.g.N;
     const int64_t npair = (int64_t)(L.g.n[0] / 2) * L.g.n[1] * L.g.n[2];
-    const int rpb = rhs_per_block((npair * 8 + 63) / 64, nrhs, 1);
+    const int rpb = tuned(L.tune_relax, nrhs, 1, rhs_per_block((npair * 8 + 63) / 64, nrhs, 1));
     const dim3 gb(nblk(npair * 8), (nrhs + rpb - 1) / rpb);
     LaunchBytes lb = bytes_relax(L.g, false, nrhs, false, (int)sizeof(T), (int)sizeof(T), (double)sizeof(T));
     lb.mine += nrhs * 2.0 * sizeof(T) * (double)(gf.N + L.g.N);              // rf read, b written
@@ -3295,13 +3272,11 @@ int64_t stored_plan_lanes(const Geo& g) {
 // Every Galerkin level keeps its rows (the large 2D ones use them for small
 // batches, see launch_relax).
 bool stored_plan_wanted(const Geo& g, bool fine) {
-    static const bool on = env_int("EHH_SPLAN", 1) != 0;
-    static const bool on3 = env_int("EHH_SPLAN3D", 1) != 0;
     // the kernels address the stored rows and the vectors with 32-bit byte offsets
     // (2D: below 2 GiB, which keeps the pressure rows' skipped slots out of range)
     const int64_t NT = g.dim == 2 ? St<2>::NF + St<2>::NUP : St<3>::NF + St<3>::NUP;
     const int64_t lim = g.dim == 2 ? int64_t(1) << 31 : int64_t(1) << 32;
-    return on && (g.dim == 2 || on3) && !fine && NT * stored_plan_lanes(g) * 8 < lim && NT * g.N * 8 < lim &&
+    return !fine && NT * stored_plan_lanes(g) * 8 < lim && NT * g.N * 8 < lim &&
            16 * g.N < lim;
 }
 int stored_terms(int dim) { return dim == 2 ? St<2>::NF + St<2>::NUP : St<3>::NF + St<3>::NUP; }
@@ -3333,11 +3308,11 @@ template hipError_t launch_build_plans<double>(const LevelDesc<double>&, int, do
 template <typename T>
 hipError_t launch_restrict(const Geo& gf, const Geo& gc, const T* rf, T* rc, int nrhs, hipStream_t s) {
     // (k_restrict2d reads the fine vector through a buffer descriptor: below 4 GiB)
-    if (gf.dim == 2 && transfer2d_enabled() && 2 * gf.N * (int64_t)sizeof(T) < (int64_t(1) << 32))
+    if (gf.dim == 2 && 2 * gf.N * (int64_t)sizeof(T) < (int64_t(1) << 32))
         EHH_LAUNCHK(bytes_transfer(gf, gc, nrhs, false, (int)sizeof(T)), k_restrict2d, (T), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc);
     else if (gf.dim == 2)
         EHH_LAUNCHK(bytes_transfer(gf, gc, nrhs, false, (int)sizeof(T)), k_restrict, (2, T), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc, nrhs);
-    else if (transfer2d_enabled() && 2 * gf.N < (int64_t(1) << 31))
+    else if (2 * gf.N < (int64_t(1) << 31))
         EHH_LAUNCHK(bytes_transfer(gf, gc, nrhs, false, (int)sizeof(T)), k_restrict3d, (T), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc);
     else
         EHH_LAUNCHK(bytes_transfer(gf, gc, nrhs, false, (int)sizeof(T)), k_restrict, (3, T), dim3(nblk(gc.N), nrhs), 256, 0, s, gf, gc, rf, rc, nrhs);
@@ -3346,11 +3321,11 @@ hipError_t launch_restrict(const Geo& gf, const Geo& gc, const T* rf, T* rc, int
 
 template <typename T>
 hipError_t launch_prolong(const Geo& gf, const Geo& gc, const T* ec, T* ef, int nrhs, hipStream_t s) {
-    if (gf.dim == 2 && transfer2d_enabled() && 2 * gf.N < (int64_t(1) << 31))
+    if (gf.dim == 2 && 2 * gf.N < (int64_t(1) << 31))
         EHH_LAUNCHK(bytes_transfer(gf, gc, nrhs, true, (int)sizeof(T)), k_prolong2d, (T), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef);
     else if (gf.dim == 2)
         EHH_LAUNCHK(bytes_transfer(gf, gc, nrhs, true, (int)sizeof(T)), k_prolong, (2, T), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef, nrhs);
-    else if (transfer2d_enabled() && 2 * gf.N < (int64_t(1) << 31))
+    else if (2 * gf.N < (int64_t(1) << 31))
         EHH_LAUNCHK(bytes_transfer(gf, gc, nrhs, true, (int)sizeof(T)), k_prolong3d, (T), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef);
     else
         EHH_LAUNCHK(bytes_transfer(gf, gc, nrhs, true, (int)sizeof(T)), k_prolong, (3, T), dim3(nblk(gf.N), nrhs), 256, 0, s, gf, gc, ec, ef, nrhs);

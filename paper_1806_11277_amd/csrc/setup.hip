@@ -897,114 +897,6 @@ __global__ __launch_bounds__(256) void k_coarse_apply_multi_batch(Batch<PK> b) {
     call_pack([&](auto&&... a) { k_coarse_apply_multi_body<T, W>(ehh_vb, a...); }, b.arg[ehh_s]);
 }
 
-// Register-blocked variant for groups of up to 32 right-hand sides: a workgroup
-// owns 64 rows x 32 right-hand sides of one column segment and stages 16-column
-// chunks of the inverse (transposed) and of the vectors in LDS; thread (tr, tq)
-// accumulates rows tr + 16 a (a < 4) x right-hand sides tq + 16 b (b < 2), so a
-// staged column costs it 6 LDS reads for 8 complex multiply-adds (the
-// one-register-row variant above needs 6 for 2).
-template <typename T>
-EHH_DEV void k_coarse_apply_rb_body(VB ehh_vb, const double* __restrict__ inv, int64_t n, const T* __restrict__ r, T* __restrict__ e, int nrhs, int64_t kseg, double* __restrict__ part) {
-    constexpr int ROWS = 64, W = 32, KC = 16, RT = 4, QT = 2;
-    __shared__ double Ms[KC][ROWS * 2 + 2];
-    __shared__ double Xs[KC][W * 2];
-    const int t = threadIdx.x;
-    const int tq = t & 15, tr = t >> 4;
-    const int64_t i0 = (int64_t)ehh_vb.x * ROWS;
-    const int q0 = blockIdx.y * W;
-    const int64_t jb = (int64_t)blockIdx.z * kseg;
-    const int64_t je = jb + kseg < n ? jb + kseg : n;
-    double ar[RT][QT], ai[RT][QT];
-#pragma unroll
-    for (int a = 0; a < RT; ++a)
-#pragma unroll
-        for (int b = 0; b < QT; ++b) ar[a][b] = ai[a][b] = 0.0;
-    for (int64_t j0 = jb; j0 < je; j0 += KC) {
-        // 64 rows x 16 columns of the inverse: 16 consecutive columns per row read together
-#pragma unroll
-        for (int m = 0; m < ROWS * KC / 256; ++m) {
-            const int el = t + 256 * m;
-            const int rr = el / KC, cc = el % KC;
-            const int64_t gi = i0 + rr, gj = j0 + cc;
-            double vr = 0.0, vi = 0.0;
-            if (gi < n && gj < je) {
-                vr = inv[2 * (gi * n + gj)];
-                vi = inv[2 * (gi * n + gj) + 1];
-            }
-            Ms[cc][2 * rr] = vr;
-            Ms[cc][2 * rr + 1] = vi;
-        }
-#pragma unroll
-        for (int m = 0; m < KC * W / 256; ++m) {
-            const int el = t + 256 * m;
-            const int kk = el % KC, qq = el / KC;
-            const int64_t gj = j0 + kk;
-            double vr = 0.0, vi = 0.0;
-            if (gj < je && q0 + qq < nrhs) {
-                const T* rv = r + (int64_t)(q0 + qq) * 2 * n;
-                vr = (double)rv[gj];
-                vi = (double)rv[n + gj];
-            }
-            Xs[kk][2 * qq] = vr;
-            Xs[kk][2 * qq + 1] = vi;
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int kk = 0; kk < KC; ++kk) {
-            double mr[RT], mi[RT], xr[QT], xi[QT];
-#pragma unroll
-            for (int a = 0; a < RT; ++a) {
-                mr[a] = Ms[kk][2 * (tr + 16 * a)];
-                mi[a] = Ms[kk][2 * (tr + 16 * a) + 1];
-            }
-#pragma unroll
-            for (int b = 0; b < QT; ++b) {
-                xr[b] = Xs[kk][2 * (tq + 16 * b)];
-                xi[b] = Xs[kk][2 * (tq + 16 * b) + 1];
-            }
-#pragma unroll
-            for (int a = 0; a < RT; ++a)
-#pragma unroll
-                for (int b = 0; b < QT; ++b) {
-                    ar[a][b] = fma(mr[a], xr[b], fma(-mi[a], xi[b], ar[a][b]));
-                    ai[a][b] = fma(mr[a], xi[b], fma(mi[a], xr[b], ai[a][b]));
-                }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int b = 0; b < QT; ++b) {
-        const int q = q0 + tq + 16 * b;
-        if (q >= nrhs) continue;
-#pragma unroll
-        for (int a = 0; a < RT; ++a) {
-            const int64_t g = i0 + tr + 16 * a;
-            if (g >= n) continue;
-            if (part) {
-                double* pv = part + ((int64_t)blockIdx.z * nrhs + q) * 2 * n;
-                pv[g] = ar[a][b];
-                pv[n + g] = ai[a][b];
-            } else {
-                T* ev = e + (int64_t)q * 2 * n;
-                ev[g] = (T)ar[a][b];
-                ev[n + g] = (T)ai[a][b];
-            }
-        }
-    }
-}
-template <typename T>
-__global__ __launch_bounds__(256) void k_coarse_apply_rb(const double* __restrict__ inv, int64_t n,
-                                                         const T* __restrict__ r, T* __restrict__ e, int nrhs,
-                                                         int64_t kseg, double* __restrict__ part) {
-    k_coarse_apply_rb_body<T>(single_block<false>(), inv, n, r, e, nrhs, kseg, part);
-}
-template <class PK, typename T>
-__global__ __launch_bounds__(256) void k_coarse_apply_rb_batch(Batch<PK> b) {
-    VB ehh_vb;
-    int ehh_s;
-    if (!batch_block<false>(b, ehh_vb, ehh_s)) return;
-    call_pack([&](auto&&... a) { k_coarse_apply_rb_body<T>(ehh_vb, a...); }, b.arg[ehh_s]);
-}
 
 // Matrix-core variant (FP64 MFMA 16x16x4) for groups of up to 32 right-hand
 // sides: a workgroup owns 64 rows x 32 right-hand sides of one column segment and
@@ -1371,28 +1263,13 @@ static size_t sym_ws_doubles(int64_t n, int nrhs) {
 }
 
 
-static bool coarse_mfma_enabled() {
-    static const bool v = [] {
-        const char* e = std::getenv("EHH_COARSE_MFMA");
-        return !e || std::atoi(e) != 0;
-    }();
-    return v;
-}
-static bool coarse_rb_enabled() {
-    static const bool v = [] {
-        const char* e = std::getenv("EHH_COARSE_RB");
-        return !e || std::atoi(e) != 0;
-    }();
-    return v;
-}
-
 // Column segments of the multi-right-hand-side coarse apply: enough workgroups to
 // fill the chip (about 1024), segments of at least 256 columns.
 static int coarse_width(int nrhs) { return nrhs <= 4 ? 0 : nrhs <= 8 ? 8 : nrhs <= 16 ? 16 : 32; }
 int coarse_ksplit(int64_t n, int nrhs) {
     const int W = coarse_width(nrhs);
     if (W == 0) return 1;
-    const int rows = W == 32 && coarse_rb_enabled() ? 64 : 512 / W;   // rows per workgroup
+    const int rows = W == 32 ? 64 : 512 / W;   // rows per workgroup
     const int64_t blocks = ((n + rows - 1) / rows) * ((nrhs + W - 1) / W);
     int64_t ks = (1024 + blocks - 1) / blocks;
     const int64_t kmax = n / 256 > 1 ? n / 256 : 1;
@@ -1416,11 +1293,7 @@ hipError_t launch_coarse_apply(const double* inv, const double* sym, int64_t n, 
     const LaunchBytes lb_sym{(double)sym_tiles(n) * SY * SY * 16.0 + vec, 16.0 * n * n + vec};
     const LaunchBytes lb_full{16.0 * n * n + vec, 16.0 * n * n + vec};
     const LaunchBytes lb_red{vec, vec};
-    static const bool sym_on = [] {
-        const char* v = std::getenv("EHH_COARSE_SYM");
-        return !v || std::atoi(v) != 0;
-    }();
-    if (W == 0 && sym && ws && sym_on) {   // W == 0: one group of at most 4 right-hand sides
+    if (W == 0 && sym && ws) {   // W == 0: one group of at most 4 right-hand sides
         const int nb = (int)((n + SY - 1) / SY);
         EHH_LAUNCHK(lb_sym, k_coarse_apply_sym, (T), dim3((unsigned)sym_tiles(n), 1), 256, 0, s, sym, n, nb, r, nrhs,
                            ws);
@@ -1436,12 +1309,9 @@ hipError_t launch_coarse_apply(const double* inv, const double* sym, int64_t n, 
     const int64_t kseg = ((n + ks - 1) / ks + 63) / 64 * 64;
     ks = (int)((n + kseg - 1) / kseg);
     double* part = ks > 1 ? ws : nullptr;
-    if (W == 32 && coarse_rb_enabled()) {
+    if (W == 32) {   // the FP64 matrix cores (groups of 32 right-hand sides)
         const dim3 grid_rb((unsigned)((n + 63) / 64), (unsigned)((nrhs + 31) / 32), (unsigned)ks);
-        if (coarse_mfma_enabled())
-            EHH_LAUNCHK(lb_full, k_coarse_apply_mfma, (T), grid_rb, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
-        else
-            EHH_LAUNCHK(lb_full, k_coarse_apply_rb, (T), grid_rb, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
+        EHH_LAUNCHK(lb_full, k_coarse_apply_mfma, (T), grid_rb, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
         if (part) EHH_LAUNCHK(lb_red, k_coarse_reduce, (T), nblk(2 * n * nrhs), 256, 0, s, part, ks, n, nrhs, e);
         return hipGetLastError();
     }
@@ -1449,10 +1319,8 @@ hipError_t launch_coarse_apply(const double* inv, const double* sym, int64_t n, 
     const dim3 grid(rows, (unsigned)((nrhs + W - 1) / W), (unsigned)ks);
     if (W == 8)
         EHH_LAUNCHK(lb_full, k_coarse_apply_multi, (T, 8), grid, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
-    else if (W == 16)
-        EHH_LAUNCHK(lb_full, k_coarse_apply_multi, (T, 16), grid, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
     else
-        EHH_LAUNCHK(lb_full, k_coarse_apply_multi, (T, 32), grid, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
+        EHH_LAUNCHK(lb_full, k_coarse_apply_multi, (T, 16), grid, 256, 0, s, inv, n, r, e, nrhs, kseg, part);
     if (part) EHH_LAUNCHK(lb_red, k_coarse_reduce, (T), nblk(2 * n * nrhs), 256, 0, s, part, ks, n, nrhs, e);
     return hipGetLastError();
 }

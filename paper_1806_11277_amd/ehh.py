@@ -79,6 +79,8 @@ _SIGS = {
     "ehh_level_prolong": (_I, [_P, _I, _I, _P, _P, _I, _P]),
     "ehh_coarse_solve": (_I, [_P, _I, _P, _P, _I, _P]),
     "ehh_coarse_solve_noalloc": (_I, [_P, _I, _P, _P, _I, _P]),
+    "ehh_autotune": (_I, [_P, _I, ctypes.POINTER(_I), _I, _P]),
+    "ehh_set_tuning": (_I, [_P, ctypes.POINTER(_I), _I]),
     "ehh_profile_precondition": (_I, [_P, _P, _P, _I, _I, _P, ctypes.c_int64, ctypes.POINTER(ehh_kernel_time_t),
                                       _I, ctypes.POINTER(_I), _P]),
     "ehh_last_error": (ctypes.c_char_p, []),
@@ -341,6 +343,17 @@ class Solver:
         _check(st, allow=(EHH_OK,) if raise_on_fail else (EHH_OK, EHH_NOT_CONVERGED))
         return st, [dict(status=s.status, iters=s.iters, rel_res_est=s.rel_res_est,
                          rel_res_true=s.rel_res_true, conv_factor=s.conv_factor) for s in stats]
+
+    def autotune(self, nrhs, stream=None):
+        """Launch shapes for nrhs sources chosen by timing (ehh_autotune): the
+        table, 2 entries per level."""
+        t = (_I * (2 * self.levels))()
+        _check(lib().ehh_autotune(self.handle, int(nrhs), t, len(t), _stream(stream)))
+        return list(t)
+
+    def set_tuning(self, table):
+        t = (_I * len(table))(*[int(v) for v in table])
+        _check(lib().ehh_set_tuning(self.handle, t, len(t)))
 
     def profile_precondition(self, v, z, reps=5, evict=None, stream=None, cap=256):
         """Per-kernel timing of one preconditioner application (ehh_profile_precondition):
