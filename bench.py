@@ -318,6 +318,43 @@ def workload_entry(w, steps, warmup, tol, copy_gbs, with_profile, tune=True):
     return out, X
 
 
+def profile_solves(w, solves, tune=True):
+    """Solves alone, for kernel traces: the solver is set up and tuned, solves
+    once (warm-up), then a short spin kernel (torch.cuda._sleep) marks the start
+    of `solves` solves of the workload's sources and another their end; the
+    dispatches between the two markers in a trace are the solves' only.  The
+    cycle profile (HIP events around replays, the figures of the bench line)
+    follows the second marker."""
+    import torch
+    from paper_1806_11277_amd import ehh, tuning
+    S = ehh.solver_for_workload(w)
+    B = rhs_tensor(S, w)
+    table, how = tuning.tune(S, B.shape[0]) if tune else (None, "heuristic")
+    X = torch.zeros_like(B)
+    S.solve(B, X, tol=1e-6, maxit=w.maxit)
+    torch.cuda.synchronize()
+    torch.cuda._sleep(1000)
+    torch.cuda.synchronize()
+    per = []
+    for _ in range(solves):
+        X.zero_()
+        t0 = time.perf_counter()
+        st, stats = S.solve(B, X, tol=1e-6, maxit=w.maxit)
+        torch.cuda.synchronize()
+        per.append(1e3 * (time.perf_counter() - t0))
+    torch.cuda._sleep(1000)
+    torch.cuda.synchronize()
+    S.close()
+    prof = cycle_profile(w, table=table)
+    dom = prof["kernels"][0]
+    return {"workload": w.name, "solves": solves, "solve_ms": per, "iters": [s_["iters"] for s_ in stats],
+            "launch_shapes": {"source": how, "table": table},
+            "cycle_us": prof["us_per_application"],
+            "cycle_kernels": [{k: r[k] for k in ("kernel", "launches", "avg_us", "avg_us_warm", "bytes", "bytes_model")}
+                              for r in prof["kernels"]],
+            "dominant": dom["kernel"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -339,6 +376,9 @@ def main():
     ap.add_argument("--coarse-bits", type=int, default=None, choices=(16, 32),
                     help="storage of the 3D Galerkin levels' stored rows in the complex64 cycle "
                          "(16: FP16 with a power-of-two scale per level)")
+    ap.add_argument("--profile-solves", type=int, default=0,
+                    help="for kernel traces: set up once, then time this many solves of --config between two "
+                         "marker kernels and print their record as one JSON line (no bench line)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the heuristic launch shapes instead of the autotuner's (cached) table")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -364,6 +404,9 @@ def main():
     w = get_config(a.config)
     if a.coarse_bits is not None:
         w = dataclasses.replace(w, coarse_bits=a.coarse_bits)
+    if a.profile_solves > 0:
+        print(json.dumps(profile_solves(w, a.profile_solves, not a.no_tune)), flush=True)
+        return
     copy_gbs = None if a.no_roofline else copy_bandwidth()
     print(f"[bench] {w.name}: n={w.n} nrhs={len(w.sources())} levels={w.levels} cycle={w.cycle} "
           f"bits={w.precond_bits}", file=sys.stderr, flush=True)
