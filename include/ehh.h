@@ -103,9 +103,11 @@ typedef struct {
                                overlaps; 0 = multicolour schedule of Algorithm 2 */
     double  damping[EHH_MAX_LEVELS];  /* Vanka damping per level, finest first */
     int32_t coarse_bits;    /* 32 (default) or 16: with the complex64 cycle, the stored
-                               rows of the 3D Galerkin levels are kept in FP16, scaled by
-                               a power of two per level, and summed in FP32 (the paper's
-                               half-precision storage of coarse data, section 3) */
+                               rows of the Galerkin levels (2D and 3D) are kept in FP16,
+                               scaled by a power of two per level, and summed in FP32 (the
+                               paper's half-precision storage of coarse data, section 3);
+                               the 2D levels served by LDS-staged tiles (>= 256^2 cells with
+                               more than 8 sources) read the FP32 compact stencil instead */
     int32_t coarse_dd_parts[3];  /* DD as the coarsest-level solver (MG-DD, section 4;
                                with dd_parts > 1 as well: DD-MG-DD): subdomains per axis of
                                every hierarchy's coarsest level; all 1 (default) = the

@@ -849,7 +849,7 @@ void make_subdomains(ehh_ctx* c) {
 }
 
 
-// FP16 storage of a 3D Galerkin level's stored rows (coarse_bits = 16, section 3
+// FP16 storage of a Galerkin level's stored rows (coarse_bits = 16, section 3
 // of the paper suggests half precision for the coarse data): every row array
 // is divided by one power-of-two scale that brings the largest modulus to
 // about 2^14, rounded to FP16, and the FP32 arrays are released.
@@ -1126,7 +1126,7 @@ int32_t build_hierarchy(ehh_ctx* c, Sub& S, const double* lam, const double* mu,
         else
             HIPCHK(launch_build_row_plans<double>(level_desc<double>(c, Q, c->prob.shift),
                                                   (double*)Q.rp_re, (double*)Q.rp_im, s));
-        if (c->opt.coarse_bits == 16 && Q.g.dim == 3) CHK(rows_to_half(c, Q, NT, NF, lanes, s));
+        if (c->opt.coarse_bits == 16) CHK(rows_to_half(c, Q, NT, NF, lanes, s));
     }
     return EHH_OK;
 }

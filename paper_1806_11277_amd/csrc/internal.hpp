@@ -20,7 +20,7 @@ template <typename T> struct StoredPlan {
     // rows of y = A x in row order (term j of row t at [j * N + t])
     const T* rre = nullptr;
     const T* rim = nullptr;
-    // 3D complex64 cycle with FP16 rows: the pointers above hold FP16 values, the
+    // complex64 cycle with FP16 rows: the pointers above hold FP16 values, the
     // coefficients divided by scale (a power of two)
     bool half = false;
     float scale = 1.0f;

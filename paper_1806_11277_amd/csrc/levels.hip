@@ -615,8 +615,8 @@ EHH_DEV inline int col2(const Cols2& c, int j) {
 // here as P^T of the finer level's residual rf (geometry gf) and written to bw,
 // one unknown per lane (the carry lane forms the other cell's pressure), which
 // saves the restriction's own launch.
-template <typename T, bool KEEP, bool RST>
-EHH_DEV void k_relax_st2d_body(VB ehh_vb, const Geo& g, int colour, T w, T wp, int econ, const T* __restrict__ b, const T* __restrict__ ein, T* __restrict__ eout, int nrhs, int64_t stride, int rpb, const T* __restrict__ cre, const T* __restrict__ cim, int64_t lanes, const Geo& gf, const T* __restrict__ rf, T* __restrict__ bw) {
+template <typename T, bool KEEP, bool RST, typename C = T>
+EHH_DEV void k_relax_st2d_body(VB ehh_vb, const Geo& g, int colour, T w, T wp, int econ, const T* __restrict__ b, const T* __restrict__ ein, T* __restrict__ eout, int nrhs, int64_t stride, int rpb, const C* __restrict__ cre, const C* __restrict__ cim, int64_t lanes, const Geo& gf, const T* __restrict__ rf, T* __restrict__ bw, T csc) {
     constexpr int D = 2, R = 2 * D + 1, NF = St<2>::NF, NUP = St<2>::NUP, NT = NF + NUP, H = 7;
     constexpr int T_SELF = St<2>::CF, T_NHI = St<2>::CF + 1, T_PLO = NF + 2, T_PHI = NF + 3;
     const int64_t sf = 2 * gf.N;
@@ -656,23 +656,28 @@ EHH_DEV void k_relax_st2d_body(VB ehh_vb, const Geo& g, int colour, T w, T wp, i
     const bool carry = live && row == R;
     const int ipb = (int)g.off[3] + yy * g.n[0] + 2 * px + 1 - par;
     // coefficient loads: lane offset in a VGPR, term offset in a scalar register;
-    // absent rows and the unused terms of the pressure row are stored as zeros
-    const Buf<T> cR(cre, (uint32_t)(NT * lanes * sizeof(T))), cI(cim, (uint32_t)(NF * lanes * sizeof(T)));
-    const uint32_t lo = (uint32_t)gl * (uint32_t)sizeof(T), ls = (uint32_t)lanes * (uint32_t)sizeof(T);
+    // absent rows and the unused terms of the pressure row are stored as zeros.
+    // C = FP16: the rows hold the coefficients divided by csc (a power of two).
+    const Buf<C> cR(cre, (uint32_t)(NT * lanes * sizeof(C))), cI(cim, (uint32_t)(NF * lanes * sizeof(C)));
+    const uint32_t lo = (uint32_t)gl * (uint32_t)sizeof(C), ls = (uint32_t)lanes * (uint32_t)sizeof(C);
     const uint32_t vb = 2 * (uint32_t)g.N * (uint32_t)sizeof(T), nb = (uint32_t)g.N * (uint32_t)sizeof(T);
+    const auto cv = [csc](C v) -> T {
+        if constexpr (std::is_same<C, T>::value) return v;
+        else return csc * (T)v;
+    };
     // this row's block entries: the diagonal sits at T_SELF in a u row and at
     // term 0 in the pressure row
     const bool lowrow = row < 2 * D && (row & 1) == 0;
     T dre = T(1), dim = T(0), ore = T(0), oim = T(0), gg = T(0);
     if (ok) {
         const uint32_t js = (uint32_t)(k == 3 ? 0 : T_SELF) * ls;
-        dre = cR.ld(lo + js);
+        dre = cv(cR.ld(lo + js));
         if (k < 3) {
-            dim = cI.ld(lo + js);
-            gg = cR.ld(lo + (uint32_t)(lowrow ? T_PHI : T_PLO) * ls);
+            dim = cv(cI.ld(lo + js));
+            gg = cv(cR.ld(lo + (uint32_t)(lowrow ? T_PHI : T_PLO) * ls));
             if (lowrow && !econ) {
-                ore = cR.ld(lo + (uint32_t)T_NHI * ls);
-                oim = cI.ld(lo + (uint32_t)T_NHI * ls);
+                ore = cv(cR.ld(lo + (uint32_t)T_NHI * ls));
+                oim = cv(cI.ld(lo + (uint32_t)T_NHI * ls));
             }
         }
     }
@@ -682,9 +687,9 @@ EHH_DEV void k_relax_st2d_body(VB ehh_vb, const Geo& g, int colour, T w, T wp, i
     if (KEEP) {
         const uint32_t lr = row < R ? lo : OOB_OFF;
 #pragma unroll
-        for (int j = 0; j < (KEEP ? NT : 0); ++j) are[j] = cR.ld(j > 2 * NUP ? lq : lr, j * ls);
+        for (int j = 0; j < (KEEP ? NT : 0); ++j) are[j] = cv(cR.ld(j > 2 * NUP ? lq : lr, j * ls));
 #pragma unroll
-        for (int j = 0; j < (KEEP ? NF : 0); ++j) aim[j] = cI.ld(lq, j * ls);
+        for (int j = 0; j < (KEEP ? NF : 0); ++j) aim[j] = cv(cI.ld(lq, j * ls));
     }
 
     VankaBlock<D, T> V;
@@ -751,8 +756,8 @@ EHH_DEV void k_relax_st2d_body(VB ehh_vb, const Geo& g, int colour, T w, T wp, i
                         for (int jj = 0; jj < H; ++jj) {
                             const int j = h + jj;
                             if (j < NT) {
-                                cr_[jj] = cR.ld(j > 2 * NUP ? lhq : lh, j * ls);
-                                ci_[jj] = j < NF ? cI.ld(lhq, j * ls) : T(0);
+                                cr_[jj] = cv(cR.ld(j > 2 * NUP ? lhq : lh, j * ls));
+                                ci_[jj] = j < NF ? cv(cI.ld(lhq, j * ls)) : T(0);
                                 const uint32_t oj = (uint32_t)col2(cl, j) * (uint32_t)sizeof(T);
                                 vr[jj] = ev.ld(oj, 0);
                                 vi[jj] = ev.ld(oj, nb);
@@ -785,20 +790,20 @@ EHH_DEV void k_relax_st2d_body(VB ehh_vb, const Geo& g, int colour, T w, T wp, i
         if (carry) ov.st(ipb, ecarry);
     }
 }
-template <typename T, bool KEEP, bool RST>
+template <typename T, bool KEEP, bool RST, typename C = T>
 __global__ __launch_bounds__(256) void k_relax_st2d(Geo g, int colour, T w, T wp, int econ, const T* __restrict__ b,
                                                     const T* __restrict__ ein, T* __restrict__ eout, int nrhs,
-                                                    int64_t stride, int rpb, const T* __restrict__ cre,
-                                                    const T* __restrict__ cim, int64_t lanes, Geo gf,
-                                                    const T* __restrict__ rf, T* __restrict__ bw) {
-    k_relax_st2d_body<T, KEEP, RST>(single_block<true>(), g, colour, w, wp, econ, b, ein, eout, nrhs, stride, rpb, cre, cim, lanes, gf, rf, bw);
+                                                    int64_t stride, int rpb, const C* __restrict__ cre,
+                                                    const C* __restrict__ cim, int64_t lanes, Geo gf,
+                                                    const T* __restrict__ rf, T* __restrict__ bw, T csc) {
+    k_relax_st2d_body<T, KEEP, RST, C>(single_block<true>(), g, colour, w, wp, econ, b, ein, eout, nrhs, stride, rpb, cre, cim, lanes, gf, rf, bw, csc);
 }
-template <class PK, typename T, bool KEEP, bool RST>
+template <class PK, typename T, bool KEEP, bool RST, typename C = T>
 __global__ __launch_bounds__(256) void k_relax_st2d_batch(Batch<PK> b) {
     VB ehh_vb;
     int ehh_s;
     if (!batch_block<true>(b, ehh_vb, ehh_s)) return;
-    call_pack([&](auto&&... a) { k_relax_st2d_body<T, KEEP, RST>(ehh_vb, a...); }, b.arg[ehh_s]);
+    call_pack([&](auto&&... a) { k_relax_st2d_body<T, KEEP, RST, C>(ehh_vb, a...); }, b.arg[ehh_s]);
 }
 
 // FP64 half-sweep over stored rows with each row split over two wavefronts: the
@@ -951,8 +956,9 @@ __global__ __launch_bounds__(256) void k_relax_st2d_split_batch(Batch<PK> b) {
 }
 
 // y = A x or r = b - A x over stored rows (term j of row t at [j * N + t]).
-template <typename T>
-EHH_DEV void k_apply_st2d_body(VB ehh_vb, const Geo& g, const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ y, int nrhs, int64_t stride, int rpb, const T* __restrict__ cre, const T* __restrict__ cim) {
+// (C, csc: storage of the rows and their scale, as in k_relax_st2d.)
+template <typename T, typename C = T>
+EHH_DEV void k_apply_st2d_body(VB ehh_vb, const Geo& g, const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ y, int nrhs, int64_t stride, int rpb, const C* __restrict__ cre, const C* __restrict__ cim, T csc) {
     constexpr int NF = St<2>::NF, NUP = St<2>::NUP, NT = NF + NUP;
     {
         const int rb0 = blockIdx.y * rpb;
@@ -972,16 +978,20 @@ EHH_DEV void k_apply_st2d_body(VB ehh_vb, const Geo& g, const T* __restrict__ x,
     if (k == 0) p[0] += 1;
     if (k == 1) p[1] += 1;
     const Cols2 cc = cols2(g, k, p);
-    const Buf<T> cR(cre, (uint32_t)(NT * N * sizeof(T))), cI(cim, (uint32_t)(NF * N * sizeof(T)));
-    const uint32_t lo = (uint32_t)t * (uint32_t)sizeof(T), ls = (uint32_t)N * (uint32_t)sizeof(T);
+    const Buf<C> cR(cre, (uint32_t)(NT * N * sizeof(C))), cI(cim, (uint32_t)(NF * N * sizeof(C)));
+    const uint32_t lo = (uint32_t)t * (uint32_t)sizeof(C), cs = (uint32_t)N * (uint32_t)sizeof(C);
+    const auto cv = [csc](C v) -> T {
+        if constexpr (std::is_same<C, T>::value) return v;
+        else return csc * (T)v;
+    };
     // unused terms of the pressure rows are stored as zeros, and not read
     const uint32_t lq = k == 3 ? OOB_OFF : lo;
     T are[NT], aim[NF];
 #pragma unroll
-    for (int j = 0; j < NT; ++j) are[j] = cR.ld(j > 2 * NUP ? lq : lo, j * ls);
+    for (int j = 0; j < NT; ++j) are[j] = cv(cR.ld(j > 2 * NUP ? lq : lo, j * cs));
 #pragma unroll
-    for (int j = 0; j < NF; ++j) aim[j] = cI.ld(lq, j * ls);
-    const uint32_t vb = 2 * ls;
+    for (int j = 0; j < NF; ++j) aim[j] = cv(cI.ld(lq, j * cs));
+    const uint32_t ls = (uint32_t)N * (uint32_t)sizeof(T), vb = 2 * ls;
     for (int r = 0; r < nrhs; ++r) {
         const Buf<T> xv(x + r * stride, vb);
         T vr[NT], vi[NT];
@@ -1007,18 +1017,18 @@ EHH_DEV void k_apply_st2d_body(VB ehh_vb, const Geo& g, const T* __restrict__ x,
         Vec<T>{y + r * stride, g.N}.st(t, o);
     }
 }
-template <typename T>
+template <typename T, typename C = T>
 __global__ __launch_bounds__(256) void k_apply_st2d(Geo g, const T* __restrict__ x, const T* __restrict__ b,
                                                     T* __restrict__ y, int nrhs, int64_t stride, int rpb,
-                                                    const T* __restrict__ cre, const T* __restrict__ cim) {
-    k_apply_st2d_body<T>(single_block<true>(), g, x, b, y, nrhs, stride, rpb, cre, cim);
+                                                    const C* __restrict__ cre, const C* __restrict__ cim, T csc) {
+    k_apply_st2d_body<T, C>(single_block<true>(), g, x, b, y, nrhs, stride, rpb, cre, cim, csc);
 }
-template <class PK, typename T>
+template <class PK, typename T, typename C = T>
 __global__ __launch_bounds__(256) void k_apply_st2d_batch(Batch<PK> b) {
     VB ehh_vb;
     int ehh_s;
     if (!batch_block<true>(b, ehh_vb, ehh_s)) return;
-    call_pack([&](auto&&... a) { k_apply_st2d_body<T>(ehh_vb, a...); }, b.arg[ehh_s]);
+    call_pack([&](auto&&... a) { k_apply_st2d_body<T, C>(ehh_vb, a...); }, b.arg[ehh_s]);
 }
 
 // rc = P^T (b - A e) from a 2D level with stored rows in one launch: sixteen
@@ -3102,8 +3112,15 @@ hipError_t launch_apply(const LevelDesc<T>& L, const T* x, const T* b, T* y, int
     } else if (L.g.dim == 2) {
         if (L.fine)
             EHH_RB_DISPATCH(rb, EHH_LAUNCHK(lb, k_apply_plan, (2, T, FineOp<2, T>, RB), gb, 256, 0, s, FineOp<2, T>{L.g, L.f}, x, b, y, nrhs, stride, rpb));
-        else if (L.sp.rre)
-            EHH_LAUNCHK(lb, k_apply_st2d, (T), gb, 256, 0, s, L.g, x, b, y, nrhs, stride, rpb, L.sp.rre, L.sp.rim);
+        else if (L.sp.rre) {
+            if constexpr (sizeof(T) == 4)
+                if (L.sp.half) {
+                    EHH_LAUNCHK(lb, k_apply_st2d, (T, _Float16), gb, 256, 0, s, L.g, x, b, y, nrhs, stride, rpb,
+                                (const _Float16*)L.sp.rre, (const _Float16*)L.sp.rim, (T)L.sp.scale);
+                    return hipGetLastError();
+                }
+            EHH_LAUNCHK(lb, k_apply_st2d, (T, T), gb, 256, 0, s, L.g, x, b, y, nrhs, stride, rpb, L.sp.rre, L.sp.rim, T(1));
+        }
         else
             EHH_RB_DISPATCH(rb, EHH_LAUNCHK(lb, k_apply_plan, (2, T, StOp<2, T>, RB), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, x, b, y, nrhs, stride, rpb));
     } else if (L.g.dim == 3 && L.fine && 2 * L.g.N * (int64_t)sizeof(T) < (int64_t(1) << 32)) {
@@ -3177,8 +3194,16 @@ hipError_t launch_relax(const LevelDesc<T>& L, int colour, Damp w, int econ, con
             const int64_t groups = L.sp.lanes / 64;
             if (sizeof(T) == 8 && ein && groups <= 256)
                 EHH_LAUNCHK(lb, k_relax_st2d_split, (T), dim3((unsigned)((groups + 1) / 2), gb.y), 256, 0, s, L.g, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpb, L.sp.re[colour], L.sp.im[colour], L.sp.lanes);
-            else
-                EHH_LAUNCHK(lb, k_relax_st2d, (T, sizeof(T) == 4, false), gb, 256, 0, s, L.g, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpb, L.sp.re[colour], L.sp.im[colour], L.sp.lanes, L.g, (const T*)nullptr, (T*)nullptr);
+            else {
+                bool half = false;
+                if constexpr (sizeof(T) == 4)
+                    if (L.sp.half) {
+                        EHH_LAUNCHK(lb, k_relax_st2d, (T, true, false, _Float16), gb, 256, 0, s, L.g, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpb, (const _Float16*)L.sp.re[colour], (const _Float16*)L.sp.im[colour], L.sp.lanes, L.g, (const T*)nullptr, (T*)nullptr, (T)L.sp.scale);
+                        half = true;
+                    }
+                if (!half)
+                    EHH_LAUNCHK(lb, k_relax_st2d, (T, sizeof(T) == 4, false, T), gb, 256, 0, s, L.g, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpb, L.sp.re[colour], L.sp.im[colour], L.sp.lanes, L.g, (const T*)nullptr, (T*)nullptr, T(1));
+            }
         }
         else
             EHH_RB_DISPATCH(rb, EHH_LAUNCHK(lb, k_relax_plan, (2, T, StOp<2, T>, RB), gb, 256, 0, s, StOp<2, T>{L.g, L.s}, colour, tw, twp, econ, b, ein, eout, nrhs, stride, rpb));
@@ -3251,11 +3276,19 @@ hipError_t launch_relax_restrict(const LevelDesc<T>& L, Damp w, int econ, const 
     const int64_t npair = (int64_t)(L.g.n[0] / 2) * L.g.n[1] * L.g.n[2];
     const int rpb = tuned(L.tune_relax, nrhs, 1, rhs_per_block((npair * 8 + 63) / 64, nrhs, 1));
     const dim3 gb(nblk(npair * 8), (nrhs + rpb - 1) / rpb);
-    LaunchBytes lb = bytes_relax(L.g, false, nrhs, false, (int)sizeof(T), (int)sizeof(T), (double)sizeof(T));
+    LaunchBytes lb = bytes_relax(L.g, false, nrhs, false, (int)sizeof(T), (int)sizeof(T), L.sp.half ? 2.0 : (double)sizeof(T));
     lb.mine += nrhs * 2.0 * sizeof(T) * (double)(gf.N + L.g.N);              // rf read, b written
     lb.model += nrhs * 2.0 * sizeof(T) * (gf.dim + 1) * (double)(gf.ncell + L.g.ncell);
-    EHH_LAUNCHK(lb, k_relax_st2d, (T, sizeof(T) == 4, true), gb, 256, 0, s, L.g, 0, (T)w.u, (T)w.p, econ, (const T*)b,
-                       (const T*)nullptr, eout, nrhs, stride, rpb, L.sp.re[0], L.sp.im[0], L.sp.lanes, gf, rf, b);
+    if constexpr (sizeof(T) == 4)
+        if (L.sp.half) {
+            EHH_LAUNCHK(lb, k_relax_st2d, (T, true, true, _Float16), gb, 256, 0, s, L.g, 0, (T)w.u, (T)w.p, econ,
+                        (const T*)b, (const T*)nullptr, eout, nrhs, stride, rpb, (const _Float16*)L.sp.re[0],
+                        (const _Float16*)L.sp.im[0], L.sp.lanes, gf, rf, b, (T)L.sp.scale);
+            return hipGetLastError();
+        }
+    EHH_LAUNCHK(lb, k_relax_st2d, (T, sizeof(T) == 4, true, T), gb, 256, 0, s, L.g, 0, (T)w.u, (T)w.p, econ,
+                (const T*)b, (const T*)nullptr, eout, nrhs, stride, rpb, L.sp.re[0], L.sp.im[0], L.sp.lanes, gf, rf,
+                b, T(1));
     return hipGetLastError();
 }
 template bool relax_restrict_supported<float>(const LevelDesc<float>&, const Geo&, int);
