@@ -1280,17 +1280,27 @@ EHH_DEV void rows3_rb(const Buf<C>& cR, const Buf<C>& cI, uint32_t lo, uint32_t 
     }
 }
 
-// Half-sweep over stored rows on a 3D Galerkin level: eight lanes per cell as in
-// k_relax (lane 8 j + cell holds row j: low/high face of u_0, u_1, u_2, then the
-// pressure; lane 7 carries the other cell's pressure), blocks renumbered per XCD.
+// Half-sweep over stored rows on a 3D Galerkin level.  A workgroup of 256 lanes
+// relaxes 32 cells of the colour; lanes 32 j .. 32 j + 31 hold block row j of
+// those cells (the low and high face of u_0, u_1, u_2, then the pressure; row 7
+// carries the other cell's pressure), so one wavefront holds the two faces of
+// one component for 32 neighbouring cells and a term's loads hit interleaved
+// faces of the same cache lines (with one cell's eight rows in a wavefront,
+// they spread over eight index families).  The Vanka blocks go through LDS:
+// every lane factorises its cell's block from the rows' entries, then for each
+// group of RB sources the rows' residuals are exchanged, lane (j, c) solves
+// source j of the group for cell c, and each row lane applies its correction.
 //
 // C: storage type of the rows (T, or FP16 holding the coefficients divided by
 // the level's power-of-two scale csc, which the sums and the block entries are
 // multiplied by again; csc = 1 otherwise).
 template <typename T, int RB, int CH, typename C = T>
 EHH_DEV void k_relax_st3d_body(VB ehh_vb, const Geo& g, int colour, T w, T wp, int econ, const T* __restrict__ b, const T* __restrict__ ein, T* __restrict__ eout, int nrhs, int64_t stride, int rpb, const C* __restrict__ cre, const C* __restrict__ cim, int64_t lanes, T csc) {
-    constexpr int D = 3, R = 2 * D + 1, NF = St<3>::NF, NT = NF + St<3>::NUP;
+    constexpr int D = 3, R = 2 * D + 1, NF = St<3>::NF, NT = NF + St<3>::NUP, CW = 32;
     constexpr int T_SELF = St<3>::CF, T_NHI = St<3>::CF + 1, T_PLO = NF + 8, T_PHI = NF + 9;
+    static_assert(RB <= 8, "one source of a group per block row");
+    __shared__ T ent[5][R][CW];          // block entries of the rows: dre, dim, ore, oim, gg
+    __shared__ T rs[RB][R][CW][2];       // the rows' residuals, then the corrections
     {
         const int rb0 = blockIdx.y * rpb;
         b += rb0 * stride;
@@ -1300,12 +1310,10 @@ EHH_DEV void k_relax_st3d_body(VB ehh_vb, const Geo& g, int colour, T w, T wp, i
     }
     const int hp = g.n[0] >> 1;
     const int npair = hp * g.n[1] * g.n[2];
-    const int lane = threadIdx.x & 63;
-    const int row = lane >> 3;
-    const int cig = lane & 7;
-    const int64_t gl = (int64_t)ehh_vb.x * blockDim.x + threadIdx.x;
-    const int t = (int)(gl >> 6) * 8 + cig;
-    const int base = cig;
+    const int row = (int)(threadIdx.x >> 5) & 7;
+    const int c = (int)threadIdx.x & (CW - 1);
+    const int64_t gl = (int64_t)ehh_vb.x * 256 + threadIdx.x;
+    const int t = (int)ehh_vb.x * CW + c;
     const bool live = t < npair;
     const int tt = live ? t : 0;
     const int px = tt % hp;
@@ -1327,23 +1335,55 @@ EHH_DEV void k_relax_st3d_body(VB ehh_vb, const Geo& g, int colour, T w, T wp, i
     const uint32_t lo = (uint32_t)gl * (uint32_t)sizeof(C), ls = (uint32_t)lanes * (uint32_t)sizeof(C);
     const uint32_t vb = 2 * (uint32_t)g.N * (uint32_t)sizeof(T), nb = (uint32_t)g.N * (uint32_t)sizeof(T);
     // this row's block entries (the diagonal sits at T_SELF in a u row, at term 0
-    // in the pressure row), then the block factorisation, once for the batch
-    const bool lowrow = row < 2 * D && (row & 1) == 0;
-    T dre = T(1), dim = T(0), ore = T(0), oim = T(0), gg = T(0);
-    if (ok) {
-        const uint32_t js = (uint32_t)(k == 3 ? 0 : T_SELF) * ls;
-        dre = csc * (T)cR.ld(lo + js);
-        if (k < 3) {
-            dim = csc * (T)cI.ld(lo + js);
-            gg = csc * (T)cR.ld(lo + (uint32_t)(lowrow ? T_PHI : T_PLO) * ls);
-            if (lowrow && !econ) {
-                ore = csc * (T)cR.ld(lo + (uint32_t)T_NHI * ls);
-                oim = csc * (T)cI.ld(lo + (uint32_t)T_NHI * ls);
+    // in the pressure row); rows outside the grid keep an identity entry
+    {
+        const bool lowrow = row < 2 * D && (row & 1) == 0;
+        T dre = T(1), dim = T(0), ore = T(0), oim = T(0), gg = T(0);
+        if (ok) {
+            const uint32_t js = (uint32_t)(k == 3 ? 0 : T_SELF) * ls;
+            dre = csc * (T)cR.ld(lo + js);
+            if (k < 3) {
+                dim = csc * (T)cI.ld(lo + js);
+                gg = csc * (T)cR.ld(lo + (uint32_t)(lowrow ? T_PHI : T_PLO) * ls);
+                if (lowrow && !econ) {
+                    ore = csc * (T)cR.ld(lo + (uint32_t)T_NHI * ls);
+                    oim = csc * (T)cI.ld(lo + (uint32_t)T_NHI * ls);
+                }
             }
         }
+        if (row < R) {
+            ent[0][row][c] = dre;
+            ent[1][row][c] = dim;
+            ent[2][row][c] = ore;
+            ent[3][row][c] = oim;
+            ent[4][row][c] = gg;
+        }
     }
-    VankaBlock<D, T> V;
-    V.factor(dre, dim, ore, oim, gg, base, row);
+    __syncthreads();
+    // cell c's block, factorised in every lane: a 2 x 2 inverse per component and
+    // the Schur complement of the pressure
+    cx<T> i00[D], i01[D], i11[D], zlo[D], zhi[D];
+    T glo[D], ghi[D];
+    cx<T> iS;
+    {
+        cx<T> S = mk<T>(ent[0][2 * D][c], T(0));
+#pragma unroll
+        for (int kk = 0; kk < D; ++kk) {
+            const cx<T> all = mk<T>(ent[0][2 * kk][c], ent[1][2 * kk][c]);
+            const cx<T> ahh = mk<T>(ent[0][2 * kk + 1][c], ent[1][2 * kk + 1][c]);
+            const cx<T> alh = mk<T>(ent[2][2 * kk][c], ent[3][2 * kk][c]);
+            glo[kk] = ent[4][2 * kk][c];
+            ghi[kk] = ent[4][2 * kk + 1][c];
+            const cx<T> idet = cinv(all * ahh - alh * alh);
+            i00[kk] = ahh * idet;
+            i11[kk] = all * idet;
+            i01[kk] = mk<T>(T(0), T(0)) - alh * idet;
+            zlo[kk] = glo[kk] * i00[kk] + ghi[kk] * i01[kk];
+            zhi[kk] = glo[kk] * i01[kk] + ghi[kk] * i11[kk];
+            S = S - (glo[kk] * zlo[kk] + ghi[kk] * zhi[kk]);
+        }
+        iS = cinv(S);
+    }
 
     for (int r0 = 0; r0 < nrhs; r0 += RB) {
         T ar[RB], ai[RB];
@@ -1362,30 +1402,76 @@ EHH_DEV void k_relax_st3d_body(VB ehh_vb, const Geo& g, int colour, T w, T wp, i
         }
         // the row's own unknown and the carried pressure as 32-bit byte offsets
         // into buffer descriptors (wave-uniform bases), formed here so that no
-        // per-source address is kept across the row loop
+        // per-source address is kept across the row walk
         uint32_t oi = (uint32_t)idx * (uint32_t)sizeof(T), ob = (uint32_t)ipb * (uint32_t)sizeof(T);
         asm volatile("" : "+v"(oi), "+v"(ob));
+        __syncthreads();   // the previous group's corrections have been read
+        if (row < R) {
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                const int r = r0 + q;
+                if (r >= nrhs) break;
+                T xr = T(0), xi = T(0);
+                if (ok) {
+                    const Buf<T> bq(b + r * stride, vb);
+                    xr = bq.ld(oi, 0) - ar[q];
+                    xi = bq.ld(oi, nb) - ai[q];
+                }
+                rs[q][row][c][0] = xr;
+                rs[q][row][c][1] = xi;
+            }
+        }
+        __syncthreads();
+        // lane (row, c) solves source `row` of the group for cell c
+        if (row < RB && r0 + row < nrhs) {
+            cx<T> rr[R];
+#pragma unroll
+            for (int j = 0; j < R; ++j) rr[j] = mk<T>(rs[row][j][c][0], rs[row][j][c][1]);
+            cx<T> acc = rr[2 * D];
+            cx<T> ylo[D], yhi[D];
+#pragma unroll
+            for (int kk = 0; kk < D; ++kk) {
+                ylo[kk] = i00[kk] * rr[2 * kk] + i01[kk] * rr[2 * kk + 1];
+                yhi[kk] = i01[kk] * rr[2 * kk] + i11[kk] * rr[2 * kk + 1];
+                acc = acc - (glo[kk] * ylo[kk] + ghi[kk] * yhi[kk]);
+            }
+            const cx<T> dp = acc * iS;
+#pragma unroll
+            for (int kk = 0; kk < D; ++kk) {
+                const cx<T> dl = ylo[kk] - zlo[kk] * dp, dh = yhi[kk] - zhi[kk] * dp;
+                rs[row][2 * kk][c][0] = dl.re;
+                rs[row][2 * kk][c][1] = dl.im;
+                rs[row][2 * kk + 1][c][0] = dh.re;
+                rs[row][2 * kk + 1][c][1] = dh.im;
+            }
+            rs[row][2 * D][c][0] = dp.re;
+            rs[row][2 * D][c][1] = dp.im;
+        }
+        __syncthreads();
 #pragma unroll
         for (int q = 0; q < RB; ++q) {
             const int r = r0 + q;
             if (r >= nrhs) break;
-            const Buf<T> bq(b + r * stride, vb), oq(eout + r * stride, vb);
-            const Buf<T> eq(ein ? ein + r * stride : b, vb);
-            cx<T> res = mk<T>(T(0), T(0)), eown = mk<T>(T(0), T(0));
+            const Buf<T> oq(eout + r * stride, vb);
             if (ok) {
-                res = mk<T>(bq.ld(oi, 0), bq.ld(oi, nb)) - mk<T>(ar[q], ai[q]);
-                if (ein) eown = mk<T>(eq.ld(oi, 0), eq.ld(oi, nb));
-            }
-            const cx<T> mine = V.solve(res, base, row);
-            if (ok) {
-                const cx<T> v = eown + (row == 2 * D ? wp : w) * mine;
-                oq.st(oi, v.re);
-                oq.st(oi + nb, v.im);
+                cx<T> eown = mk<T>(T(0), T(0));
+                if (ein) {
+                    const Buf<T> eq(ein + r * stride, vb);
+                    eown = mk<T>(eq.ld(oi, 0), eq.ld(oi, nb));
+                }
+                const T ww = row == 2 * D ? wp : w;
+                oq.st(oi, eown.re + ww * rs[q][row][c][0]);
+                oq.st(oi + nb, eown.im + ww * rs[q][row][c][1]);
             }
             if (carry) {
-                const cx<T> v = ein ? mk<T>(eq.ld(ob, 0), eq.ld(ob, nb)) : mk<T>(T(0), T(0));
-                oq.st(ob, v.re);
-                oq.st(ob + nb, v.im);
+                T vr = T(0), vi = T(0);
+                if (ein) {
+                    const Buf<T> eq(ein + r * stride, vb);
+                    vr = eq.ld(ob, 0);
+                    vi = eq.ld(ob, nb);
+                }
+                oq.st(ob, vr);
+                oq.st(ob + nb, vi);
             }
         }
     }
@@ -1539,8 +1625,9 @@ __global__ __launch_bounds__(256) void k_build_rows3d(StOp<3, T> op, int colour,
     const int64_t gl = e % lanes;
     const int hp = g.n[0] >> 1;
     const int64_t npair = (int64_t)hp * g.n[1] * g.n[2];
-    const int lane = (int)(gl & 63), row = lane >> 3, cig = lane & 7;
-    const int64_t t = (gl >> 6) * 8 + cig;
+    // the lane order of k_relax_st3d: 32 cells per 256 lanes, row j in lanes 32 j ..
+    const int row = (int)((gl & 255) >> 5);
+    const int64_t t = (gl >> 8) * 32 + (gl & 31);
     const bool live = t < npair;
     const int64_t tt = live ? t : 0;
     const int px = (int)(tt % hp);
