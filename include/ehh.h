@@ -292,7 +292,11 @@ int32_t ehh_set_tuning(ehh_handle_t h, const int32_t* table, int32_t len);
  * eviction buffer (device, evict_bytes, a multiple of 4; NULL and 0 for none)
  * so that it finds the caches as cold as inside a solve; the eviction writes
  * alone are timed the same way and subtracted (HIP events, best of three);
- * the launches are also replayed back to back without the writes.
+ * the launches are also replayed back to back without the writes; and the
+ * whole application's launches are replayed in their order without graphs,
+ * each launch timed by start and stop events that its dispatch records itself
+ * (hipExtLaunchKernel), so that no launch gap is counted and every launch
+ * finds the caches as the preceding launches of the application left them.
  * out[cap] receives one entry per kernel in order of first launch, *count how
  * many were written.  v: (device) as for ehh_precondition; z and the handle's
  * workspaces are overwritten by the replays (z's content afterwards is
@@ -312,6 +316,8 @@ typedef struct {
                                cell of w bytes per source (3 V w for a half-sweep from
                                e_in, 2 V w from zero) plus the level's coefficients per
                                cell (fine 4 reals; Galerkin 29 complex in 2D, 169 in 3D) */
+    double  avg_us_seq;     /* average duration of one launch in the in-order replay of
+                               the application (the dispatch's own start to end) */
 } ehh_kernel_time_t;
 int32_t ehh_profile_precondition(ehh_handle_t h, const double* v, double* z, int32_t nrhs, int32_t reps,
                                  void* evict, int64_t evict_bytes, ehh_kernel_time_t* out, int32_t cap,

@@ -37,7 +37,7 @@ namespace {
 struct LogRec {
     const void* kernel;
     LaunchBytes bytes;
-    std::function<void(hipStream_t)> again;
+    LaunchAgain again;
 };
 thread_local bool t_log_on = false;
 thread_local std::vector<LogRec> t_log;
@@ -47,7 +47,7 @@ thread_local std::vector<BatchRec> t_batch;
 bool launch_log_on() { return t_log_on; }
 bool batch_recording() { return t_batch_on; }
 void batch_record(BatchRec&& r) { t_batch.push_back(std::move(r)); }
-void launch_log_add(const void* kernel, LaunchBytes bytes, std::function<void(hipStream_t)> again) {
+void launch_log_add(const void* kernel, LaunchBytes bytes, LaunchAgain again) {
     t_log.push_back(LogRec{kernel, bytes, std::move(again)});
 }
 }  // namespace ehh
@@ -1380,7 +1380,7 @@ int32_t time_replay(ehh_ctx* c, const std::vector<const LogRec*>& recs, int reps
     for (int r = 0; r < reps; ++r)
         for (const LogRec* rec : recs) {
             if (evict) (void)launch_zero(evict, (size_t)evict_bytes, c->cap_stream);
-            if (with_kernel) rec->again(c->cap_stream);
+            if (with_kernel) rec->again(c->cap_stream, nullptr, nullptr);
         }
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(c->cap_stream, &g);
@@ -1408,6 +1408,33 @@ int32_t time_replay(ehh_ctx* c, const std::vector<const LogRec*>& recs, int reps
     (void)hipGraphExecDestroy(ex);
     if (e != hipSuccess) return fail(EHH_ERR_HIP, std::string("timed replay: ") + hipGetErrorString(e));
     *ms = best;
+    return EHH_OK;
+}
+
+// The whole log replayed in order on stream s, each launch between its own start
+// and stop events (recorded by the dispatch itself), once untimed and then reps
+// times: every launch finds the caches as the launches before it in the
+// application left them, as inside a solve.  sum_ms[i]: the durations of
+// launch i summed over the reps.
+int32_t time_in_order(const std::vector<LogRec>& log, int reps, hipStream_t s, std::vector<double>& sum_ms) {
+    const size_t n = log.size();
+    sum_ms.assign(n, 0.0);
+    std::vector<hipEvent_t> ev(2 * n, nullptr);
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < 2 * n && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+    for (int r = 0; r <= reps && e == hipSuccess; ++r) {
+        for (size_t i = 0; i < n; ++i) log[i].again(s, ev[2 * i], ev[2 * i + 1]);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        for (size_t i = 0; i < n && e == hipSuccess && r > 0; ++i) {
+            float f = 0.0f;
+            e = hipEventElapsedTime(&f, ev[2 * i], ev[2 * i + 1]);
+            sum_ms[i] += f;
+        }
+    }
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (e != hipSuccess) return fail(EHH_ERR_HIP, std::string("in-order replay: ") + hipGetErrorString(e));
     return EHH_OK;
 }
 
@@ -1944,6 +1971,10 @@ int32_t ehh_profile_precondition(ehh_handle_t h, const double* v, double* z, int
         if (gv.empty()) order.push_back(r.kernel);
         gv.push_back(&r);
     }
+    std::vector<double> seq_ms;
+    CHK(time_in_order(log, reps, s, seq_ms));
+    std::map<const void*, double> seq_sum;
+    for (size_t i = 0; i < log.size(); ++i) seq_sum[log[i].kernel] += seq_ms[i];
     int32_t k = 0;
     for (const void* kern : order) {
         if (k >= cap) break;
@@ -1959,6 +1990,7 @@ int32_t ehh_profile_precondition(ehh_handle_t h, const double* v, double* z, int
         o.launches = (int32_t)recs.size();
         o.avg_us = std::max(t_all - t_evict, 0.0) * 1e3 / ((double)reps * recs.size());
         o.avg_us_warm = t_warm * 1e3 / ((double)reps * recs.size());
+        o.avg_us_seq = seq_sum[kern] * 1e3 / ((double)reps * recs.size());
         for (const LogRec* r : recs) {
             o.bytes += r->bytes.mine / recs.size();
             o.bytes_model += r->bytes.model / recs.size();

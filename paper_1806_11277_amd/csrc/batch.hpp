@@ -136,10 +136,13 @@ hipError_t launch_batch_pack(const BatchRec* const* recs, int n, hipStream_t s) 
     void* args[] = {&b};
     hipError_t e = hipLaunchKernel(k, grid, block, args, sh, s);
     if (e == hipSuccess && launch_log_on())
-        launch_log_add(k, lb, [b, k, grid, block, sh](hipStream_t s2) {
+        launch_log_add(k, lb, [b, k, grid, block, sh](hipStream_t s2, hipEvent_t e0, hipEvent_t e1) {
             Batch<PK> bb = b;
             void* a2[] = {&bb};
-            (void)hipLaunchKernel(k, grid, block, a2, sh, s2);
+            if (e0)
+                (void)hipExtLaunchKernel(k, grid, block, a2, sh, s2, e0, e1, 0);
+            else
+                (void)hipLaunchKernel(k, grid, block, a2, sh, s2);
         });
     return e;
 }

@@ -7,6 +7,7 @@
 // relaxed atomic load more.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <functional>
@@ -26,7 +27,10 @@ struct LaunchBytes {
 };
 
 bool launch_log_on();
-void launch_log_add(const void* kernel, LaunchBytes bytes, std::function<void(hipStream_t)> again);
+// again(stream, start, stop): the launch repeated on stream; with start / stop
+// events, they record the dispatch's own begin and end (hipExtLaunchKernel)
+using LaunchAgain = std::function<void(hipStream_t, hipEvent_t, hipEvent_t)>;
+void launch_log_add(const void* kernel, LaunchBytes bytes, LaunchAgain again);
 
 // Byte counts of the cycle's kernels on a level of geometry g with R sources in
 // a precision of es bytes per real.  coef_reals: the level's coefficient reals
@@ -80,8 +84,12 @@ inline LaunchBytes bytes_plain(double v) { return LaunchBytes{v, v}; }
         hipLaunchKernelGGL(K, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);                                   \
         if (::ehh::launch_log_on())                                                                       \
             ::ehh::launch_log_add(reinterpret_cast<const void*>(&K), (BYTES),                              \
-                                  [=](hipStream_t ehh_s_) {                                               \
-                                      hipLaunchKernelGGL(K, GRID, BLOCK, SHMEM, ehh_s_, __VA_ARGS__);     \
+                                  [=](hipStream_t ehh_s_, hipEvent_t ehh_e0_, hipEvent_t ehh_e1_) {       \
+                                      if (ehh_e0_)                                                        \
+                                          hipExtLaunchKernelGGL(K, GRID, BLOCK, SHMEM, ehh_s_, ehh_e0_,   \
+                                                                ehh_e1_, 0, __VA_ARGS__);                 \
+                                      else                                                                \
+                                          hipLaunchKernelGGL(K, GRID, BLOCK, SHMEM, ehh_s_, __VA_ARGS__); \
                                   });                                                                     \
     } while (0)
 #define EHH_LAUNCH(K, GRID, BLOCK, SHMEM, STREAM, ...) \

@@ -49,7 +49,8 @@ class ehh_stats_t(ctypes.Structure):
 
 class ehh_kernel_time_t(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_char * 128), ("launches", ctypes.c_int32), ("avg_us", ctypes.c_double),
-                ("avg_us_warm", ctypes.c_double), ("bytes", ctypes.c_double), ("bytes_model", ctypes.c_double)]
+                ("avg_us_warm", ctypes.c_double), ("bytes", ctypes.c_double), ("bytes_model", ctypes.c_double),
+                ("avg_us_seq", ctypes.c_double)]
 
 
 _P = ctypes.c_void_p
@@ -357,7 +358,7 @@ class Solver:
 
     def profile_precondition(self, v, z, reps=5, evict=None, stream=None, cap=256):
         """Per-kernel timing of one preconditioner application (ehh_profile_precondition):
-        a list of dicts (kernel, launches, avg_us, avg_us_warm, bytes, bytes_model) in order of
+        a list of dicts (kernel, launches, avg_us, avg_us_warm, avg_us_seq, bytes, bytes_model) in order of
         first launch.  evict: a device tensor written before every replayed launch."""
         nrhs = self._global(outputs=("z",), v=v, z=z)
         if evict is not None and (not evict.is_cuda or not evict.is_contiguous()):
@@ -369,6 +370,7 @@ class Solver:
                                               _ptr(evict) if evict is not None else None, nbytes, out, cap,
                                               ctypes.byref(cnt), _stream(stream)))
         return [dict(kernel=o.kernel.decode(), launches=o.launches, avg_us=o.avg_us, avg_us_warm=o.avg_us_warm,
+                     avg_us_seq=o.avg_us_seq,
                      bytes=o.bytes, bytes_model=o.bytes_model) for o in out[:cnt.value]]
 
     def media_gradient(self, y, x, grad_lambda, grad_mu, grad_rho, accumulate=False, stream=None):

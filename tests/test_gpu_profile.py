@@ -1,0 +1,50 @@
+"""ehh_profile_precondition: every kernel of one preconditioner application is
+replayed and timed three ways.  The in-order replay times each launch by the
+start and stop events of its own dispatch, so the launches of one application
+add up to no more than the wall time of a precondition call (on one stream the
+dispatches do not overlap) and to most of it; every row names a kernel with
+positive launches, times and algorithmic bytes; the profiler leaves the
+handle usable (a precondition afterwards gives the same bits as before)."""
+import numpy as np
+import pytest
+
+from _helpers import say, workload, rand_cvec, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("name", ["c2s_hetero128_fp64", "c3s_hetero128_batch8_fp32"])
+def test_in_order_kernel_times_add_up_to_the_application(name):
+    import torch
+    from paper_1806_11277_amd import ehh
+    w = workload(name)
+    S = ehh.solver_for_workload(w)
+    nrhs = len(w.sources())
+    v = to_dev(rand_cvec(S.stride // 2, nrhs, 12))
+    z = torch.zeros_like(v)
+    S.precondition(v, z)
+    torch.cuda.synchronize()
+    z0 = z.clone()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        S.precondition(v, z)
+    e1.record()
+    e1.synchronize()
+    t_call = 1e3 * e0.elapsed_time(e1) / reps      # us per application
+    rows = S.profile_precondition(v, torch.zeros_like(v), reps=3)
+    torch.cuda.synchronize()
+    assert rows
+    for r in rows:
+        assert r["launches"] > 0 and r["avg_us_seq"] > 0 and r["avg_us_warm"] > 0 and r["avg_us"] >= 0
+        assert r["bytes"] > 0 and r["bytes_model"] > 0
+    t_seq = sum(r["launches"] * r["avg_us_seq"] for r in rows)
+    say(f"[profile {name}] precondition {t_call:.1f} us; in-order kernels {t_seq:.1f} us "
+        f"({len(rows)} kernels, {sum(r['launches'] for r in rows)} launches)")
+    assert 0.3 * t_call <= t_seq <= 1.05 * t_call
+    z1 = torch.zeros_like(v)
+    S.precondition(v, z1)
+    torch.cuda.synchronize()
+    assert torch.equal(z1, z0)
+    S.close()
