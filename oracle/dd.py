@@ -145,7 +145,8 @@ class DDPreconditioner:
     """DD-MG: one multigrid cycle of the local shifted operator per subdomain."""
 
     def __init__(self, problem: disc.Problem, parts, overlap, pad, levels, damping,
-                 economic=False, cycle=1, colours=1, abl_max=1.0, coarse_dd=None, cycle_level=0, damping_p=None):
+                 economic=False, cycle=1, colours=1, abl_max=1.0, coarse_dd=None, cycle_level=0, damping_p=None,
+                 nu1=1, nu2=1):
         n = problem.n
         self.n = n
         self.problem = problem
@@ -156,7 +157,7 @@ class DDPreconditioner:
         cnt = np.zeros(problem.size)
         for sub in self.subs:
             A_loc = local_operator(problem, sub, abl_max)
-            self.hier.append(mg.Hierarchy(A_loc, sub.nloc, levels, damping, economic, cycle,
+            self.hier.append(mg.Hierarchy(A_loc, sub.nloc, levels, damping, economic, cycle, nu1=nu1, nu2=nu2,
                                           cycle_level=cycle_level, coarse_dd=coarse_dd, damping_p=damping_p))
             m = local_to_global(n, sub)
             self.maps.append(m)

@@ -63,7 +63,8 @@ def oracle_dd(w, pb=None):
                                 list(w.damping), economic=(w.vanka == 0), cycle=w.cycle,
                                 colours=(1 if w.dd_colors == 1 else 2 ** w.dim), abl_max=w.abl_max,
                                 coarse_dd=coarse_dd_of(w), cycle_level=w.cycle_level,
-                                damping_p=(list(w.damping_p) if w.damping_p is not None else None))
+                                damping_p=(list(w.damping_p) if w.damping_p is not None else None),
+                                nu1=w.nu1, nu2=w.nu2)
 
 
 def rand_cvec(N, nrhs, seed):

@@ -68,11 +68,14 @@ def test_batched_fp32_solve_per_source():
     S.close()
 
 
-@pytest.mark.parametrize("bits,colors", [(64, 1), (32, 1), (64, 0)])
-def test_dd_precondition_matches_oracle(bits, colors):
+@pytest.mark.parametrize("bits,colors,nu", [(64, 1, 1), (32, 1, 1), (64, 0, 1), (64, 0, 2), (32, 1, 2)])
+def test_dd_precondition_matches_oracle(bits, colors, nu):
+    """DD around the cycles (3D 2 x 2 x 2 subdomains, both schedules) against the
+    oracle, including two pre- and post-smoothing steps per level inside every
+    subdomain's cycle."""
     import torch
-    w = workload("c4s_layered32_dd8_batch4_fp32", precond_bits=bits, dd_colors=colors)
-    say(f"[dd precondition bits={bits} colors={colors}]")
+    w = workload("c4s_layered32_dd8_batch4_fp32", precond_bits=bits, dd_colors=colors, nu1=nu, nu2=nu)
+    say(f"[dd precondition bits={bits} colors={colors} nu={nu}]")
     pb = oracle_problem(w)
     P = oracle_dd(w, pb)
     S = _solver(w)

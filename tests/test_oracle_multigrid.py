@@ -282,14 +282,22 @@ def _dd_problem(n, seed=14):
     return pb
 
 
-def test_single_subdomain_dd_equals_multigrid():
+@pytest.mark.parametrize("nu", [1, 2])
+def test_single_subdomain_dd_equals_multigrid(nu):
+    """One subdomain without padding: the DD preconditioner is the multigrid cycle
+    itself, with the same number of smoothing steps (Algorithm 1 inside the
+    subdomain solve); two steps give a different cycle than one."""
     n = (16, 16)
     pb = _dd_problem(n)
-    P = ddm.DDPreconditioner(pb, (1, 1), 0, 0, 3, [0.75, 0.5])
-    H = mg.Hierarchy(pb.matrix(shifted=True), n, 3, [0.75, 0.5])
+    P = ddm.DDPreconditioner(pb, (1, 1), 0, 0, 3, [0.75, 0.5], nu1=nu, nu2=nu)
+    H = mg.Hierarchy(pb.matrix(shifted=True), n, 3, [0.75, 0.5], nu1=nu, nu2=nu)
     rng = np.random.default_rng(1)
     v = rng.standard_normal(pb.size) + 1j * rng.standard_normal(pb.size)
-    assert np.linalg.norm(P.apply(v) - H.cycle(v)) < 1e-13 * np.linalg.norm(H.cycle(v))
+    ref = H.cycle(v)
+    assert np.linalg.norm(P.apply(v) - ref) < 1e-13 * np.linalg.norm(ref)
+    if nu > 1:
+        H1 = mg.Hierarchy(pb.matrix(shifted=True), n, 3, [0.75, 0.5])
+        assert np.linalg.norm(H1.cycle(v) - ref) > 1e-3 * np.linalg.norm(ref)
 
 
 @pytest.mark.parametrize("n,parts", [((32, 16), (2, 2)), ((16, 16, 16), (2, 2, 2))])
