@@ -133,8 +133,8 @@ def test_c3_solve_matches_direct_solution(c2_oracle, c2_direct):
 
 @pytest.mark.timeout(900)
 def test_c4_subdomain_cycle_matches_oracle():
-    """c4 at full size: the cycle of one padded 72^3 subdomain (4 levels, 36^3 and
-    18^3 Galerkin levels, 9^3 coarsest) on all 16 sources at once, the launch
+    """c4 at full size: the V(2,1) cycle of one padded 72^3 subdomain (4 levels, 36^3
+    and 18^3 Galerkin levels, 9^3 coarsest) on all 16 sources at once, the launch
     shapes the bench runs, compared source by source with the oracle's cycle of
     the same subdomain operator."""
     import torch
@@ -146,7 +146,7 @@ def test_c4_subdomain_cycle_matches_oracle():
     sub = subs[0]
     assert sub.nloc == (72, 72, 72)
     H = mg.Hierarchy(ddm.local_operator(pb, sub, w.abl_max), sub.nloc, w.levels, list(w.damping),
-                     economic=(w.vanka == 0), cycle=w.cycle)
+                     economic=(w.vanka == 0), cycle=w.cycle, nu1=w.nu1, nu2=w.nu2)
     say("[c4 subdomain 0 cycle, 16 sources]")
     S = _solver(w)
     assert S.subdomain_info(0)["n"] == [72, 72, 72]

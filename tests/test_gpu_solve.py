@@ -109,7 +109,7 @@ def test_c4_configuration_precondition_matches_oracle(c4m_oracle):
     """The bench's c4 solver configuration at 32^3: complex64 cycle on 24^3 padded
     subdomains (padding 6, 4 levels: the 12^3 and 6^3 Galerkin levels run the
     stored-row half-sweep in two full groups of 8 sources), Algorithm 2 with its
-    local residual gather, shift 0.6, all 16 sources compared with the FP64
+    local residual gather, V(2,1), shift 0.6, all 16 sources compared with the FP64
     oracle, norm-wise and per component."""
     import torch
     w, pb, P = c4m_oracle
@@ -135,14 +135,14 @@ def test_c4_configuration_precondition_matches_oracle(c4m_oracle):
 
 def test_c4_configuration_solve_matches_direct_solution():
     """c4's solver settings (2 x 2 x 2 subdomains, padding 6, 4 levels, Algorithm 2,
-    shift 0.6, complex64 cycle) on a 16^3 grid, whose direct factorisation takes
+    V(2,1), shift 0.6, complex64 cycle) on a 16^3 grid, whose direct factorisation takes
     seconds: 16 random right-hand sides solved to 1e-10, every solution within
     1e-6 of the oracle's direct solution."""
     import torch
     from oracle import direct
     c4 = workload("c4m_layered32_dd8_batch16_fp32")
-    w = small_hetero((16, 16, 16), "c4cfg16", levels=4, damping=c4.damping, shift=c4.shift,
-                     precond_bits=32, dd_parts=(2, 2, 2), dd_overlap=4, dd_pad=6, dd_colors=0,
+    w = small_hetero((16, 16, 16), "c4cfg16", levels=4, damping=c4.damping, shift=c4.shift, nu1=c4.nu1,
+                     nu2=c4.nu2, precond_bits=32, dd_parts=(2, 2, 2), dd_overlap=4, dd_pad=6, dd_colors=0,
                      abl_cells=(4, 4, 4))
     say("[c4 configuration at 16^3: solve vs direct, 16 sources]")
     pb = oracle_problem(w)

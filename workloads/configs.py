@@ -160,9 +160,9 @@ _add(Workload(
     description="3D 128^3 layered (8 layers, Vp 1500-4500, 5% perturbation, Poisson 0.30-0.45), "
                 "h=10 m, 8 cells per minimum shear wavelength, 12-cell layer, 2x2x2 overlapping "
                 "subdomains (overlap 4, padding 6, multicolour schedule), 16 sources, shift 0.6, "
-                "complex64 DD-MG V(1,1) preconditioner",
+                "complex64 DD-MG V(2,1) preconditioner (two pre-, one post-smoothing step)",
     dim=3, n=(128, 128, 128), h=10.0, media_fn=lambda: M.layered_3d_media((128, 128, 128)),
-    ppw=8.0, abl_cells=(12, 12, 12), shift=0.6, levels=4, damping=(0.5, 0.5, 0.2),
+    ppw=8.0, abl_cells=(12, 12, 12), shift=0.6, levels=4, nu1=2, nu2=1, damping=(0.5, 0.5, 0.2),
     precond_bits=32, dd_parts=(2, 2, 2), dd_overlap=4, dd_pad=6, dd_colors=0, maxit=500,
     sources_fn=_src_lattice(4, 32, 16, 5, seed=7)))
 
@@ -192,10 +192,10 @@ _add(Workload(
 _add(Workload(
     name="c4m_layered32_dd8_batch16_fp32",
     description="c4 at 32^3 in c4's solver configuration: 2x2x2 subdomains (overlap 4, padding 6, "
-                "multicolour schedule), 4 levels per 24^3 subdomain, shift 0.6, 16 sources, complex64 cycle "
-                "(parity size of the bench configuration)",
+                "multicolour schedule), 4 levels per 24^3 subdomain, V(2,1), shift 0.6, 16 sources, complex64 "
+                "cycle (parity size of the bench configuration)",
     dim=3, n=(32, 32, 32), h=10.0, media_fn=lambda: M.layered_3d_media((32, 32, 32)),
-    ppw=8.0, abl_cells=(6, 6, 6), shift=0.6, levels=4, damping=(0.5, 0.5, 0.2),
+    ppw=8.0, abl_cells=(6, 6, 6), shift=0.6, levels=4, nu1=2, nu2=1, damping=(0.5, 0.5, 0.2),
     precond_bits=32, dd_parts=(2, 2, 2), dd_overlap=4, dd_pad=6, dd_colors=0,
     sources_fn=_src_lattice(4, 8, 4, 5, seed=7)))
 
