@@ -461,9 +461,12 @@ __global__ __launch_bounds__(256) void k_swap_rows(double* __restrict__ A, int64
 }
 
 // A[K,K] <- (Pi_K A[K,K])^{-1} by Gauss-Jordan with partial pivoting inside the
-// block; piv[k0 + k] = row swapped with k0 + k.  One workgroup of 1024 threads
-// holds the block in registers: thread (i0, j) owns the entries of column j in
-// rows i0 + 16 q.  A step publishes in LDS only what other threads need (the
+// block; piv[k0 + k] = row swapped with k0 + k.  One workgroup of GJ_THREADS
+// threads holds the block in registers: thread (i0, j) owns the entries of
+// column j in rows i0 + (GJ_THREADS / 64) q.  (Sixteen wavefronts of 4 entries:
+// four of 16 took 263 against 144 us per block on MI355X, one wavefront per
+// SIMD leaving the latencies of the LDS reads and dependent FP64 operations of
+// a step exposed.)  A step publishes in LDS only what other threads need (the
 // pivot row, row k and column k, before the interchange of rows k and p) and
 // every thread updates its own entries from them, the interchange being folded
 // into the reads.  The pivot of the next step is chosen while its column is
@@ -475,13 +478,15 @@ __device__ inline unsigned long long gj_key(double m, int row) {
     return (__double_as_longlong(m) & ~0x3FULL) | (unsigned long long)(63 - row);
 }
 
-__global__ __launch_bounds__(1024) void k_diag_inverse(double* __restrict__ A, int64_t n, int64_t k0, int kb,
-                                                       int* __restrict__ piv, int* __restrict__ flag) {
+constexpr int GJ_THREADS = 1024;
+__global__ __launch_bounds__(GJ_THREADS) void k_diag_inverse(double* __restrict__ A, int64_t n, int64_t k0, int kb,
+                                                             int* __restrict__ piv, int* __restrict__ flag) {
     __shared__ double rowp[GJ_NB][2], rowk[GJ_NB][2], colk[GJ_NB][2];
     __shared__ unsigned long long key[GJ_NB + 1];
     const int t = threadIdx.x;
+    constexpr int RS = GJ_THREADS / GJ_NB;   // row stride of a thread's entries
     const int j = t & (GJ_NB - 1), i0 = t / GJ_NB;
-    constexpr int Q = GJ_NB * GJ_NB / 1024;
+    constexpr int Q = GJ_NB * GJ_NB / GJ_THREADS;
     const bool jok = j < kb;
     if (t <= GJ_NB) key[t] = 0ULL;
     __syncthreads();
@@ -493,7 +498,7 @@ __global__ __launch_bounds__(1024) void k_diag_inverse(double* __restrict__ A, i
     unsigned long long kmax = 0ULL;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const int i = i0 + 16 * q;
+        const int i = i0 + RS * q;
         ar[q] = ai[q] = 0.0;
         if (i < kb && jok) {
             ar[q] = A[2 * ((k0 + i) * n + k0 + j)];
@@ -510,7 +515,7 @@ __global__ __launch_bounds__(1024) void k_diag_inverse(double* __restrict__ A, i
         const int p = 63 - (int)(key[k] & 0x3FULL);
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            const int i = i0 + 16 * q;
+            const int i = i0 + RS * q;
             if (i < kb && jok) {
                 if (i == p) {
                     rowp[j][0] = ar[q];
@@ -531,7 +536,8 @@ __global__ __launch_bounds__(1024) void k_diag_inverse(double* __restrict__ A, i
         const double pr = rowp[k][0], pi = rowp[k][1];
         const double dd = pr * pr + pi * pi;
         singular = singular || !(dd > 0.0);
-        const double ir = pr / dd, ii = -pi / dd;
+        const double rdd = 1.0 / dd;
+        const double ir = pr * rdd, ii = -pi * rdd;
         // row k of the result: V(k, j) / pivot, and 1 / pivot at j = k
         double rkr = ir, rki = ii;
         if (j != k && jok) {
@@ -542,7 +548,7 @@ __global__ __launch_bounds__(1024) void k_diag_inverse(double* __restrict__ A, i
         unsigned long long km = 0ULL;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            const int i = i0 + 16 * q;
+            const int i = i0 + RS * q;
             if (i < kb && jok) {
                 if (i == k) {
                     ar[q] = rkr;
@@ -572,7 +578,7 @@ __global__ __launch_bounds__(1024) void k_diag_inverse(double* __restrict__ A, i
     if (t == 0 && singular) *flag = 1;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const int i = i0 + 16 * q;
+        const int i = i0 + RS * q;
         if (i < kb && jok) {
             A[2 * ((k0 + i) * n + k0 + j)] = ar[q];
             A[2 * ((k0 + i) * n + k0 + j) + 1] = ai[q];
@@ -601,20 +607,22 @@ __global__ __launch_bounds__(256) void k_zgemm_tile(double* C, int64_t ldc, cons
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) cr[i][j] = ci[i][j] = 0.0;
-    for (int k0 = 0; k0 < kdim; k0 += 16) {
+    // the operands of a 16-wide chunk of k: four entries of A and of B per thread,
+    // loaded into registers one chunk ahead of the arithmetic, so that the loads
+    // of chunk c + 1 are in flight while chunk c is summed
+    double par[4], pai[4], pbr[4], pbi[4];
+    auto load_chunk = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int e = threadIdx.x + 256 * q;
             const int r = e >> 4, kk = e & 15;
             const int64_t gr = row0 + r;
             const int gk = k0 + kk;
-            double vr = 0.0, vi = 0.0;
+            par[q] = pai[q] = 0.0;
             if (gr < m && gk < kdim) {
-                vr = A[2 * (gr * lda + gk)];
-                vi = A[2 * (gr * lda + gk) + 1];
+                par[q] = A[2 * (gr * lda + gk)];
+                pai[q] = A[2 * (gr * lda + gk) + 1];
             }
-            As[kk][2 * r] = vr;
-            As[kk][2 * r + 1] = vi;
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -622,15 +630,25 @@ __global__ __launch_bounds__(256) void k_zgemm_tile(double* C, int64_t ldc, cons
             const int kk = e >> 6, cc = e & 63;
             const int gk = k0 + kk;
             const int64_t gc = col0 + cc;
-            double vr = 0.0, vi = 0.0;
+            pbr[q] = pbi[q] = 0.0;
             if (gk < kdim && gc < ncol) {
-                vr = B[2 * ((int64_t)gk * ldb + gc)];
-                vi = B[2 * ((int64_t)gk * ldb + gc) + 1];
+                pbr[q] = B[2 * ((int64_t)gk * ldb + gc)];
+                pbi[q] = B[2 * ((int64_t)gk * ldb + gc) + 1];
             }
-            Bs[kk][2 * cc] = vr;
-            Bs[kk][2 * cc + 1] = vi;
+        }
+    };
+    load_chunk(0);
+    for (int k0 = 0; k0 < kdim; k0 += 16) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            As[e & 15][2 * (e >> 4)] = par[q];
+            As[e & 15][2 * (e >> 4) + 1] = pai[q];
+            Bs[e >> 6][2 * (e & 63)] = pbr[q];
+            Bs[e >> 6][2 * (e & 63) + 1] = pbi[q];
         }
         __syncthreads();
+        if (k0 + 16 < kdim) load_chunk(k0 + 16);
 #pragma unroll 4
         for (int kk = 0; kk < 16; ++kk) {
             double ar[4], ai[4], br[4], bi[4];
@@ -704,7 +722,7 @@ hipError_t launch_dense_invert(double* A, int64_t n, int* piv, int* flag, hipStr
         const int kb = (int)std::min<int64_t>(GJ_NB, n - k0);
         const int64_t k1 = k0 + kb;   // first index of the next panel
         if (k0 == 0)
-            EHH_LAUNCH(k_diag_inverse, 1, 1024, 0, s, A, n, k0, kb, piv, flag);
+            EHH_LAUNCH(k_diag_inverse, 1, GJ_THREADS, 0, s, A, n, k0, kb, piv, flag);
         else if ((e = hipStreamWaitEvent(s, ev_diag, 0)) != hipSuccess)
             break;
         EHH_LAUNCH(k_swap_rows, nblk(n), 256, 0, s, A, n, k0, kb, piv);
@@ -725,7 +743,7 @@ hipError_t launch_dense_invert(double* A, int64_t n, int* piv, int* flag, hipStr
                                n, A + 2 * (k0 * n + k1), n, (int64_t)kb1, (int64_t)kb1, kb, -1.0, 1, (int64_t)0,
                                (int64_t)0, (int64_t)0, (int64_t)0, (int64_t)-1, (int64_t)-1);
             if ((e = hipEventRecord(ev_tile, s2)) != hipSuccess) break;
-            EHH_LAUNCH(k_diag_inverse, 1, 1024, 0, s2, A, n, k1, kb1, piv, flag);
+            EHH_LAUNCH(k_diag_inverse, 1, GJ_THREADS, 0, s2, A, n, k1, kb1, piv, flag);
             if ((e = hipEventRecord(ev_diag, s2)) != hipSuccess) break;
             skip = k1;
         }
