@@ -1229,10 +1229,12 @@ EHH_DEV inline int col3(const Cols3& c, int j) {
 // once (lane offset lo, term stride ls, both in bytes) and applied to every
 // vector; terms in chunks of CH, each chunk's loads issued before its sums and
 // the next chunk's addresses tied to them (empty asm), so that the registers
-// hold one chunk at a time.
+// hold one chunk at a time.  nt (wave-uniform) ends the walk after the chunk
+// holding term nt - 1: a wavefront of pressure rows only passes 1 + 3 NUP, its
+// row's last nonzero term plus one (the pressure row is stored as zeros beyond).
 template <typename T, int RB, int CH, typename C = T>
 EHH_DEV void rows3_rb(const Buf<C>& cR, const Buf<C>& cI, uint32_t lo, uint32_t ls, const Cols3& cc,
-                      const T* const* ev, uint32_t vb, uint32_t nb, T* ar, T* ai) {
+                      const T* const* ev, uint32_t vb, uint32_t nb, T* ar, T* ai, int nt) {
     constexpr int NF = St<3>::NF, NT = NF + St<3>::NUP;
 #pragma unroll
     for (int q = 0; q < RB; ++q) ar[q] = ai[q] = T(0);
@@ -1243,6 +1245,7 @@ EHH_DEV void rows3_rb(const Buf<C>& cR, const Buf<C>& cI, uint32_t lo, uint32_t 
     for (int q = 0; q < RB; ++q) eb[q] = Buf<T>(ev[q], vb);
 #pragma unroll
     for (int h = 0; h < NT; h += CH) {
+        const bool walk = h < nt;
 #pragma unroll
         for (int q = 0; q < RB; ++q) asm volatile("" ::"v"(ar[q]), "v"(ai[q]));
         asm volatile("" : "+v"(cl.self), "+v"(cl.pc), "+v"(cl.f[0]), "+v"(cl.f[1]), "+v"(cl.f[2]), "+v"(lh));
@@ -1254,7 +1257,7 @@ EHH_DEV void rows3_rb(const Buf<C>& cR, const Buf<C>& cI, uint32_t lo, uint32_t 
 #pragma unroll
         for (int jj = 0; jj < CH; ++jj) {
             const int j = h + jj;
-            if (j < NT) {
+            if (j < NT && walk) {
                 cr[jj] = (T)cR.ld(lh, j * ls);
                 ci[jj] = j < NF ? (T)cI.ld(lh, j * ls) : T(0);
                 const uint32_t o = (uint32_t)col3(cl, j) * (uint32_t)sizeof(T);
@@ -1267,7 +1270,7 @@ EHH_DEV void rows3_rb(const Buf<C>& cR, const Buf<C>& cI, uint32_t lo, uint32_t 
         }
 #pragma unroll
         for (int jj = 0; jj < CH; ++jj) {
-            if (h + jj < NT) {
+            if (h + jj < NT && walk) {
 #pragma unroll
                 for (int q = 0; q < RB; ++q) {
                     ar[q] = fma(cr[jj], vr[jj][q], ar[q]);
@@ -1385,6 +1388,8 @@ EHH_DEV void k_relax_st3d_body(VB ehh_vb, const Geo& g, int colour, T w, T wp, i
         iS = cinv(S);
     }
 
+    // wavefront 3 holds the pressure row (and the carry lanes)
+    const int nt_wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) == D ? 1 + D * St<3>::NUP : NT;
     for (int r0 = 0; r0 < nrhs; r0 += RB) {
         T ar[RB], ai[RB];
 #pragma unroll
@@ -1393,7 +1398,7 @@ EHH_DEV void k_relax_st3d_body(VB ehh_vb, const Geo& g, int colour, T w, T wp, i
             const T* ev[RB];
 #pragma unroll
             for (int q = 0; q < RB; ++q) ev[q] = ein + (r0 + q < nrhs ? r0 + q : r0) * stride;
-            rows3_rb<T, RB, CH, C>(cR, cI, lo, ls, cc, ev, vb, nb, ar, ai);
+            rows3_rb<T, RB, CH, C>(cR, cI, lo, ls, cc, ev, vb, nb, ar, ai, nt_wave);
 #pragma unroll
             for (int q = 0; q < RB; ++q) {
                 ar[q] *= csc;
@@ -1518,12 +1523,15 @@ EHH_DEV void k_apply_st3d_body(VB ehh_vb, const Geo& g, const T* __restrict__ x,
     const uint32_t lc = (uint32_t)t * (uint32_t)sizeof(C), lsc = (uint32_t)N * (uint32_t)sizeof(C);
     const uint32_t lo = (uint32_t)t * (uint32_t)sizeof(T), ls = (uint32_t)N * (uint32_t)sizeof(T);
     const uint32_t vb = 2 * ls;
+    // every row walks all NT terms: ending pressure-row wavefronts early (as the
+    // half-sweep does) costs this kernel a wavefront per SIMD of occupancy, and
+    // measured slower (101 -> 109 us on a 72^3 level with 16 sources)
     for (int r0 = 0; r0 < nrhs; r0 += RB) {
         const T* xv[RB];
 #pragma unroll
         for (int q = 0; q < RB; ++q) xv[q] = x + (r0 + q < nrhs ? r0 + q : r0) * stride;
         T ar[RB], ai[RB];
-        rows3_rb<T, RB, CH, C>(cR, cI, lc, lsc, cc, xv, vb, ls, ar, ai);
+        rows3_rb<T, RB, CH, C>(cR, cI, lc, lsc, cc, xv, vb, ls, ar, ai, NT);
 #pragma unroll
         for (int q = 0; q < RB; ++q) {
             ar[q] *= csc;
