@@ -127,6 +127,10 @@ template hipError_t launch_dd_scatter<double>(const Geo&, const Geo&, const SubM
 // Algorithm 2, step 1: the local residual r_i = q_i - (A u)_{Omega_i} of the
 // global (unshifted) operator, evaluated only at the unknowns of the
 // subdomain's extent and written straight into its padded local vector.
+// Blocks are renumbered per XCD: a row's stencil reads the global rows of its
+// neighbouring blocks, which then sit in the same L2 (on 72^3 subdomains with 16
+// sources 427 -> 407 us; the plain gather, the scatter and the 3D transfers
+// measured slower with the renumbering and keep the hardware order).
 template <int D, typename T>
 EHH_DEV void k_dd_gather_res_body(VB ehh_vb, const Geo& gg, const Geo& gl, const SubMap& m, const FineCoef<double>& A, const double* __restrict__ v, const double* __restrict__ z, T* __restrict__ out, int nrhs) {
     const int64_t t = (int64_t)ehh_vb.x * blockDim.x + threadIdx.x;
@@ -192,13 +196,13 @@ template <int D, typename T>
 __global__ __launch_bounds__(256) void k_dd_gather_res(Geo gg, Geo gl, SubMap m, FineCoef<double> A,
                                                        const double* __restrict__ v, const double* __restrict__ z,
                                                        T* __restrict__ out, int nrhs) {
-    k_dd_gather_res_body<D, T>(single_block<false>(), gg, gl, m, A, v, z, out, nrhs);
+    k_dd_gather_res_body<D, T>(single_block<true>(), gg, gl, m, A, v, z, out, nrhs);
 }
 template <class PK, int D, typename T>
 __global__ __launch_bounds__(256) void k_dd_gather_res_batch(Batch<PK> b) {
     VB ehh_vb;
     int ehh_s;
-    if (!batch_block<false>(b, ehh_vb, ehh_s)) return;
+    if (!batch_block<true>(b, ehh_vb, ehh_s)) return;
     call_pack([&](auto&&... a) { k_dd_gather_res_body<D, T>(ehh_vb, a...); }, b.arg[ehh_s]);
 }
 
