@@ -1292,12 +1292,12 @@ int32_t enqueue_iter(ehh_ctx* c, const LevelDesc<double>& A, int j, int nrhs, hi
     float* v32 = krylov_copy32(c);
     CHK(precondition_any(c, Vj, Zj, nrhs, s, v32 != nullptr));
     HIPCHK(launch_apply<double>(A, Zj, nullptr, c->w, nrhs, s));
-    // CGS2: h1 = V^H w; w -= V h1 and h2 = V^H w (one sweep); w -= V h2 with |w|^2
-    HIPCHK(launch_dots(c->V, j + 1, c->w, N, nrhs, c->partial, c->hcol, m + 1, s));
-    HIPCHK(launch_axpy_dots(c->V, j + 1, c->w, N, nrhs, c->hcol, m + 1, c->partial, c->hcol2, m + 1, s));
-    HIPCHK(launch_axpy_multi(c->V, j + 1, c->w, N, nrhs, c->hcol2, m + 1, c->partial, c->nrm2, s, false));
-    HIPCHK(launch_givens(c->H, c->cs, c->g, c->hcol, c->hcol2, c->partial, N, c->nrm2, j, m, nrhs, c->active,
-                         c->est, c->bnorm, s));
+    // classical Gram-Schmidt, reorthogonalised where one pass is not enough:
+    // h1 = V^H w with |w|^2; w -= V h1 and h2 = V^H w (one sweep); w -= V h2
+    // with |w|^2 (skipped, h2 = 0, where one pass sufficed)
+    HIPCHK(launch_orthogonalise(c->V, j + 1, c->w, N, nrhs, c->partial, c->hcol, c->hcol2, m, s));
+    HIPCHK(launch_givens(c->H, c->cs, c->g, c->hcol, c->hcol2, gs_norm_partials(c->partial, N, nrhs, m), N,
+                         c->nrm2, j, m, nrhs, c->active, c->est, c->bnorm, s));
     HIPCHK(launch_scale(c->w, c->V + (size_t)(j + 1) * nrhs * 2 * N, N, nrhs, c->nrm2, 1, s, v32));
     return EHH_OK;
 }

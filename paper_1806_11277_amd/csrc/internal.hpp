@@ -179,26 +179,24 @@ hipError_t launch_box_scatter(const BoxMap& m, int64_t j0, int64_t j1, const dou
 
 // ---- krylov.hip (FP64, vectors of 2N reals per right-hand side)
 int krylov_blocks(int64_t n2);
-// h[r*ldh + i] = <V_i(r), w(r)> (Hermitian, conj on V) for i < nv; V_i(r) at
-// V + (i*nrhs + r) * 2N; partial: krylov_blocks * nrhs * nv * 2 doubles.
-hipError_t launch_dots(const double* V, int nv, const double* w, int64_t N, int nrhs, double* partial,
-                       double* h, int ldh, hipStream_t s);
-// w(r) -= sum_i h[r*ldh+i] V_i(r); optionally nrm2[r] = |w(r)|^2 (partial used).
-// nrm2 != null: the block partials of |w|^2 go to partial, and (norm_final)
-// their sum to nrm2; without norm_final the sum is left to launch_givens.
-hipError_t launch_axpy_multi(const double* V, int nv, double* w, int64_t N, int nrhs, const double* h,
-                             int ldh, double* partial, double* nrm2, hipStream_t s, bool norm_final = true);
 // nrm2[r] = |x(r)|^2
 hipError_t launch_norm2(const double* x, int64_t N, int nrhs, double* partial, double* nrm2, hipStream_t s);
 // out(r) = x(r) * scale[r] (scale real; mode 1: 1/sqrt(scale[r])); out32, if
 // not null, receives an FP32 copy.
 hipError_t launch_scale(const double* x, double* out, int64_t N, int nrhs, const double* scale, int mode,
                         hipStream_t s, float* out32 = nullptr);
-// w -= sum_i h_i V_i, then hout = <V_i, w> for the updated w (one sweep).
-hipError_t launch_axpy_dots(const double* V, int nv, double* w, int64_t N, int nrhs, const double* h, int ldh,
-                            double* partial, double* hout, int ldo, hipStream_t s);
+// Orthogonalise w(r) against V_0(r) .. V_{nv-1}(r) for every right-hand side
+// (nv <= m): classical Gram-Schmidt, h1 = V^H w and w -= V h1, repeated once
+// (h2 = V^H w, w -= V h2) for the sources where the first pass removed more
+// than half of |w|^2; h2 = 0 elsewhere.  h1, h2: (m + 1) complex entries per
+// source (slot m is scratch: |w|^2 before the pass in h1, the one-pass flag in
+// h2); partial: krylov_blocks * nrhs * (m + 1) * 2 doubles, leaving the block
+// partials of the final |w|^2 at gs_norm_partials(partial, N, nrhs, m).
+hipError_t launch_orthogonalise(const double* V, int nv, double* w, int64_t N, int nrhs, double* partial,
+                                double* h1, double* h2, int m, hipStream_t s);
+double* gs_norm_partials(double* partial, int64_t N, int nrhs, int m);
 // Givens update of column j of every right-hand side's Hessenberg matrix.
-// also forms nrm2 = |w|^2 from the partials launch_axpy_multi left (N: vector length)
+// also forms nrm2 = |w|^2 from the block partials of the final |w|^2 (N: vector length)
 hipError_t launch_givens(double* H, double* cs, double* g, const double* hcol, const double* hcol2,
                          const double* partial, int64_t N, double* nrm2, int j, int m, int nrhs, const int* active,
                          double* est, const double* bnorm, hipStream_t s);

@@ -34,18 +34,21 @@ EHH_DEV double block_sum(double v, double* sm) {
     return s;   // valid in thread 0
 }
 
-// partial[((r * nv + i) * 2 + c) * nb + blk]
+// partial[((r * nv + i) * 2 + c) * nb + blk]; wpart (if given) receives the
+// block partials of |w|^2, wpart[r * nb + blk]
 __global__ __launch_bounds__(KB) void k_dots_partial(const double* __restrict__ V, int nv, const double* __restrict__ w,
-                                                     int64_t N, int nrhs, double* __restrict__ partial) {
+                                                     int64_t N, int nrhs, double* __restrict__ partial,
+                                                     double* __restrict__ wpart) {
     __shared__ double sm[KB / 64];
     const int r = blockIdx.y;
     const int nb = gridDim.x;
     const double* wr = w + (int64_t)r * 2 * N;
-    double are[MAXV], aim[MAXV];
+    double are[MAXV], aim[MAXV], ww = 0.0;
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) are[i] = aim[i] = 0.0;
     for (int64_t e = (int64_t)blockIdx.x * KB + threadIdx.x; e < N; e += (int64_t)nb * KB) {
         const double xr = wr[e], xi = wr[N + e];
+        ww += xr * xr + xi * xi;
 #pragma unroll
         for (int i = 0; i < MAXV; ++i) {
             if (i < nv) {
@@ -65,6 +68,10 @@ __global__ __launch_bounds__(KB) void k_dots_partial(const double* __restrict__ 
             if (threadIdx.x == 0) partial[(((int64_t)r * nv + i) * 2 + 1) * nb + blockIdx.x] = si;
         }
     }
+    if (wpart) {
+        const double sw = block_sum(ww, sm);
+        if (threadIdx.x == 0) wpart[(int64_t)r * nb + blockIdx.x] = sw;
+    }
 }
 
 // One 64-wide wavefront per output: lanes stride over the block partials, then a
@@ -77,30 +84,34 @@ EHH_DEV double wave_sum(const double* p, int nb) {
     return s;
 }
 
+// out[r][i] (complex, i < nv) from the block partials; with wpart, the real
+// part of out[r][wslot] also receives the sum of wpart's partials of source r.
 __global__ __launch_bounds__(256) void k_partial_final(const double* __restrict__ partial, int nv, int nb, int nrhs,
-                                                       double* __restrict__ out, int ldo) {
+                                                       double* __restrict__ out, int ldo,
+                                                       const double* __restrict__ wpart, int wslot) {
     const int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (t >= nrhs * nv * 2) return;
-    const int c = t & 1, i = (t >> 1) % nv, r = (t >> 1) / nv;
-    const double s = wave_sum(partial + (((int64_t)r * nv + i) * 2 + c) * nb, nb);
-    if ((threadIdx.x & 63) == 0) out[2 * ((int64_t)r * ldo + i) + c] = s;
+    if (t < nrhs * nv * 2) {
+        const int c = t & 1, i = (t >> 1) % nv, r = (t >> 1) / nv;
+        const double s = wave_sum(partial + (((int64_t)r * nv + i) * 2 + c) * nb, nb);
+        if ((threadIdx.x & 63) == 0) out[2 * ((int64_t)r * ldo + i) + c] = s;
+    } else if (wpart && t < nrhs * nv * 2 + nrhs) {
+        const int r = t - nrhs * nv * 2;
+        const double s = wave_sum(wpart + (int64_t)r * nb, nb);
+        if ((threadIdx.x & 63) == 0) out[2 * ((int64_t)r * ldo + wslot)] = s;
+    }
 }
 
-hipError_t launch_dots(const double* V, int nv, const double* w, int64_t N, int nrhs, double* partial, double* h,
-                       int ldh, hipStream_t s) {
-    const int nb = krylov_blocks(N);
-    hipLaunchKernelGGL(k_dots_partial, dim3(nb, nrhs), KB, 0, s, V, nv, w, N, nrhs, partial);
-    hipLaunchKernelGGL(k_partial_final, nblk((int64_t)nrhs * nv * 2 * 64), 256, 0, s, partial, nv, nb, nrhs, h, ldh);
-    return hipGetLastError();
-}
-
-// w -= sum_i h_i V_i, optionally with the partial sums of |w|^2.
+// w -= sum_i h_i V_i, optionally with the partial sums of |w|^2.  With
+// fslot >= 0, a source whose h[r][fslot] is nonzero (one Gram-Schmidt pass was
+// enough, so its h is zero and its |w|^2 partials are already in place) is
+// skipped.
 __global__ __launch_bounds__(KB) void k_axpy_multi(const double* __restrict__ V, int nv, double* __restrict__ w,
                                                    int64_t N, int nrhs, const double* __restrict__ h, int ldh,
-                                                   double* __restrict__ partial) {
+                                                   double* __restrict__ partial, int fslot) {
     __shared__ double sm[KB / 64];
     const int r = blockIdx.y;
     const int nb = gridDim.x;
+    if (fslot >= 0 && h[2 * ((int64_t)r * ldh + fslot)] != 0.0) return;
     double* wr = w + (int64_t)r * 2 * N;
     double hr[MAXV], hi[MAXV];
 #pragma unroll
@@ -130,17 +141,38 @@ __global__ __launch_bounds__(KB) void k_axpy_multi(const double* __restrict__ V,
     }
 }
 
+// Whether one classical Gram-Schmidt pass leaves w orthogonal enough to V
+// (the criterion of Daniel, Gragg, Kaufman and Stewart, 1976, with the bound
+// 1/sqrt(2)): the projection removed at most half of |w|^2, i.e.
+// |w|^2 - sum_i |h_i|^2 > |w|^2 / 2 (V orthonormal), so that the updated w
+// keeps at least 1/sqrt(2) of its length and its rounding error relative to V
+// stays of the order of the unit roundoff.  A zero w fails it.
+EHH_DEV bool gs_one_pass(const double* h, int ldh, int r, int nv, int wslot) {
+    const double* hr = h + 2 * (int64_t)r * ldh;
+    double p = 0.0;
+    for (int i = 0; i < nv; ++i) p += hr[2 * i] * hr[2 * i] + hr[2 * i + 1] * hr[2 * i + 1];
+    const double w2 = hr[2 * wslot];
+    return w2 - p > 0.5 * w2;
+}
+
 // Classical Gram-Schmidt, first pass and second projection in one sweep:
 // w <- w - sum_i h_i V_i, then the partial sums of <V_i, w> for the updated w,
-// with each V_i element loaded once for both.
+// with each V_i element loaded once for both.  With wslot >= 0 (h[r][wslot] =
+// |w|^2 before the pass) a source for which one pass is enough (gs_one_pass)
+// writes zero projections, the block partials of the updated |w|^2 to npart
+// (npart[r * nb + blk]) and the flag 1 to hout[r][fslot] (0 otherwise), which
+// the second update reads to skip the source.
 __global__ __launch_bounds__(KB) void k_axpy_dots(const double* __restrict__ V, int nv, double* __restrict__ w,
                                                   int64_t N, int nrhs, const double* __restrict__ h, int ldh,
-                                                  double* __restrict__ partial) {
+                                                  double* __restrict__ partial, int wslot, double* __restrict__ npart,
+                                                  double* __restrict__ hout, int ldo, int fslot) {
     __shared__ double sm[KB / 64];
     const int r = blockIdx.y;
     const int nb = gridDim.x;
     double* wr = w + (int64_t)r * 2 * N;
-    double hr[MAXV], hi[MAXV], are[MAXV], aim[MAXV];
+    const bool one = wslot >= 0 && gs_one_pass(h, ldh, r, nv, wslot);
+    if (wslot >= 0 && blockIdx.x == 0 && threadIdx.x == 0) hout[2 * ((int64_t)r * ldo + fslot)] = one ? 1.0 : 0.0;
+    double hr[MAXV], hi[MAXV], are[MAXV], aim[MAXV], ww = 0.0;
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
         hr[i] = i < nv ? h[2 * ((int64_t)r * ldh + i)] : 0.0;
@@ -162,11 +194,15 @@ __global__ __launch_bounds__(KB) void k_axpy_dots(const double* __restrict__ V, 
         }
         wr[e] = xr;
         wr[N + e] = xi;
+        if (one) {
+            ww += xr * xr + xi * xi;
+        } else {
 #pragma unroll
-        for (int i = 0; i < MAXV; ++i) {
-            if (i < nv) {
-                are[i] += vr[i] * xr + vi[i] * xi;
-                aim[i] += vr[i] * xi - vi[i] * xr;
+            for (int i = 0; i < MAXV; ++i) {
+                if (i < nv) {
+                    are[i] += vr[i] * xr + vi[i] * xi;
+                    aim[i] += vr[i] * xi - vi[i] * xr;
+                }
             }
         }
     }
@@ -179,13 +215,34 @@ __global__ __launch_bounds__(KB) void k_axpy_dots(const double* __restrict__ V, 
             if (threadIdx.x == 0) partial[(((int64_t)r * nv + i) * 2 + 1) * nb + blockIdx.x] = si;
         }
     }
+    if (one) {
+        const double sw = block_sum(ww, sm);
+        if (threadIdx.x == 0) npart[(int64_t)r * nb + blockIdx.x] = sw;
+    }
 }
 
-hipError_t launch_axpy_dots(const double* V, int nv, double* w, int64_t N, int nrhs, const double* h, int ldh,
-                            double* partial, double* hout, int ldo, hipStream_t s) {
+// The block partials of the final |w|^2 that launch_orthogonalise leaves.
+double* gs_norm_partials(double* partial, int64_t N, int nrhs, int m) {
     const int nb = krylov_blocks(N);
-    hipLaunchKernelGGL(k_axpy_dots, dim3(nb, nrhs), KB, 0, s, V, nv, w, N, nrhs, h, ldh, partial);
-    hipLaunchKernelGGL(k_partial_final, nblk((int64_t)nrhs * nv * 2 * 64), 256, 0, s, partial, nv, nb, nrhs, hout, ldo);
+    return partial + (size_t)2 * m * nrhs * nb + (size_t)nrhs * nb;
+}
+
+hipError_t launch_orthogonalise(const double* V, int nv, double* w, int64_t N, int nrhs, double* partial,
+                                double* h1, double* h2, int m, hipStream_t s) {
+    const int nb = krylov_blocks(N), ldh = m + 1;
+    // partial: the projections' block partials (below 2 m nrhs nb), then the
+    // partials of |w|^2 before the pass and of the final |w|^2
+    double* wpart = partial + (size_t)2 * m * nrhs * nb;
+    double* npart = gs_norm_partials(partial, N, nrhs, m);
+    const unsigned nf = nblk((int64_t)(nrhs * nv * 2 + nrhs) * 64);
+    hipLaunchKernelGGL(k_dots_partial, dim3(nb, nrhs), KB, 0, s, V, nv, (const double*)w, N, nrhs, partial, wpart);
+    hipLaunchKernelGGL(k_partial_final, nf, 256, 0, s, (const double*)partial, nv, nb, nrhs, h1, ldh,
+                       (const double*)wpart, m);
+    hipLaunchKernelGGL(k_axpy_dots, dim3(nb, nrhs), KB, 0, s, V, nv, w, N, nrhs, (const double*)h1, ldh, partial, m,
+                       npart, h2, ldh, m);
+    hipLaunchKernelGGL(k_partial_final, nblk((int64_t)nrhs * nv * 2 * 64), 256, 0, s, (const double*)partial, nv, nb,
+                       nrhs, h2, ldh, (const double*)nullptr, 0);
+    hipLaunchKernelGGL(k_axpy_multi, dim3(nb, nrhs), KB, 0, s, V, nv, w, N, nrhs, (const double*)h2, ldh, npart, m);
     return hipGetLastError();
 }
 
@@ -195,15 +252,6 @@ __global__ __launch_bounds__(256) void k_norm_final(const double* __restrict__ p
     if (r >= nrhs) return;
     const double s = wave_sum(partial + (int64_t)r * nb, nb);
     if ((threadIdx.x & 63) == 0) out[r] = s;
-}
-
-hipError_t launch_axpy_multi(const double* V, int nv, double* w, int64_t N, int nrhs, const double* h, int ldh,
-                             double* partial, double* nrm2, hipStream_t s, bool norm_final) {
-    const int nb = krylov_blocks(N);
-    hipLaunchKernelGGL(k_axpy_multi, dim3(nb, nrhs), KB, 0, s, V, nv, w, N, nrhs, h, ldh, nrm2 ? partial : nullptr);
-    if (nrm2 && norm_final)
-        hipLaunchKernelGGL(k_norm_final, nblk((int64_t)nrhs * 64), 256, 0, s, partial, nb, nrhs, nrm2);
-    return hipGetLastError();
 }
 
 __global__ __launch_bounds__(KB) void k_norm_partial(const double* __restrict__ x, int64_t N, double* __restrict__ partial) {
@@ -261,8 +309,8 @@ hipError_t launch_axpby(const double* x, const double* y, double* out, int64_t n
 // hcol[r][i] + hcol2[r][i] for i <= j: <v_i, w> (complex, the two CGS passes),
 // hnext2[r] = |w|^2.
 // One wavefront per right-hand side: |w|^2 = the fixed-order sum of the block
-// partials of k_axpy_multi (the sum k_norm_final forms, written to nrm2 for the
-// scaling of w), then lane 0 applies the rotations.
+// partials of the orthogonalisation's last update (the sum k_norm_final forms,
+// written to nrm2 for the scaling of w), then lane 0 applies the rotations.
 __global__ __launch_bounds__(64) void k_givens(double* __restrict__ H, double* __restrict__ cs,
                                                double* __restrict__ g, const double* __restrict__ hcol,
                                                const double* __restrict__ hcol2, const double* __restrict__ partial,
