@@ -188,7 +188,7 @@ hipError_t launch_scale(const double* x, double* out, int64_t N, int nrhs, const
 // Orthogonalise w(r) against V_0(r) .. V_{nv-1}(r) for every right-hand side
 // (nv <= m): classical Gram-Schmidt, h1 = V^H w and w -= V h1, repeated once
 // (h2 = V^H w, w -= V h2) for the sources where the first pass removed more
-// than half of |w|^2; h2 = 0 elsewhere.  h1, h2: (m + 1) complex entries per
+// than 99 % of |w|^2; h2 = 0 elsewhere.  h1, h2: (m + 1) complex entries per
 // source (slot m is scratch: |w|^2 before the pass in h1, the one-pass flag in
 // h2); partial: krylov_blocks * nrhs * (m + 1) * 2 doubles, leaving the block
 // partials of the final |w|^2 at gs_norm_partials(partial, N, nrhs, m).

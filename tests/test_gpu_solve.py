@@ -46,6 +46,32 @@ def test_solve_matches_direct_solution(name, bits):
     S.close()
 
 
+def test_exact_preconditioner_takes_the_second_gram_schmidt_pass():
+    """With one level and no shift the preconditioner is the exact inverse of A,
+    so A M^-1 v_0 = v_0 lies in the Krylov basis: the first Gram-Schmidt pass
+    removes all of w and the step must reorthogonalise.  FGMRES then stops after
+    one step per source with the direct solution (three sources at once)."""
+    import torch
+    w = workload("c1_homog64", levels=1, precond_bits=64, shift=0.0)
+    say("[exact preconditioner, shift 0]")
+    pb = oracle_problem(w)
+    lu = spla.splu(pb.matrix().tocsc())
+    B = rand_cvec(pb.size, 3, 47)
+    S = _solver(w)
+    x = torch.zeros_like(to_dev(B))
+    st, stats = S.solve(to_dev(B), x, tol=1e-10, maxit=20)
+    torch.cuda.synchronize()
+    assert st == 0, stats
+    got = from_dev(x)
+    for r in range(B.shape[0]):
+        xd = lu.solve(B[r])
+        say(f"  source {r}: iters {stats[r]['iters']} rel_res {stats[r]['rel_res_true']:.2e}")
+        assert stats[r]["iters"] <= 2
+        assert stats[r]["rel_res_true"] <= 1e-10
+        assert np.linalg.norm(got[r] - xd) <= 1e-9 * np.linalg.norm(xd)
+    S.close()
+
+
 def test_batched_fp32_solve_per_source():
     """c3 layout at parity size: 8 sources, complex64 cycle, FP64 Krylov; each
     source reaches its tolerance and matches the direct solution."""
