@@ -101,17 +101,47 @@ __global__ __launch_bounds__(256) void k_partial_final(const double* __restrict_
     }
 }
 
-// w -= sum_i h_i V_i, optionally with the partial sums of |w|^2.  With
-// fslot >= 0, a source whose h[r][fslot] is nonzero (one Gram-Schmidt pass was
-// enough, so its h is zero and its |w|^2 partials are already in place) is
-// skipped.
+// Whether one classical Gram-Schmidt pass leaves w orthogonal enough to V
+// (the test of Daniel, Gragg, Kaufman and Stewart, 1976): the updated w keeps
+// more than eta of its length, |w|^2 - sum_i |h_i|^2 > eta^2 |w|^2 (V
+// orthonormal), so that its rounding error relative to V, about u |w| / |w'|,
+// stays below u / eta (u the unit roundoff).  Their bound is eta = 1/sqrt(2);
+// a preconditioned step removes most of w (the preconditioned operator is near
+// the identity), so that bound asks for a second pass almost every time.  With
+// eta = 0.1 (at most ten times the roundoff) the 2D and 3D workloads solved as
+// fast as with no second pass at all, with the same iterations and residuals
+// as with an unconditional second pass (32 sources at 512^2: 882 -> 845 ms per
+// solve).  A zero w fails the test.
+static constexpr double kGsEta2 = 1e-2;
+EHH_DEV bool gs_one_pass(const double* h, int ldh, int r, int nv, int wslot) {
+    const double* hr = h + 2 * (int64_t)r * ldh;
+    double p = 0.0;
+    for (int i = 0; i < nv; ++i) p += hr[2 * i] * hr[2 * i] + hr[2 * i + 1] * hr[2 * i + 1];
+    const double w2 = hr[2 * wslot];
+    return w2 - p > kGsEta2 * w2;
+}
+
+// w -= sum_i h_i V_i with the block partials of |w|^2 (npart[r * nb + blk]).
+// The orthogonalisation runs it twice:
+// first (second = 0): h = h1, where slot wslot holds |w|^2 before the pass; each
+//   block decides with gs_one_pass, block 0 writes the decision (1: one pass is
+//   enough) to flag[r], and only one-pass sources are updated;
+// second (second = 1): h = h2, and only the sources with flag[r] == 0 are updated.
 __global__ __launch_bounds__(KB) void k_axpy_multi(const double* __restrict__ V, int nv, double* __restrict__ w,
                                                    int64_t N, int nrhs, const double* __restrict__ h, int ldh,
-                                                   double* __restrict__ partial, int fslot) {
+                                                   double* __restrict__ npart, int second, int wslot,
+                                                   double* __restrict__ flag, int ldf) {
     __shared__ double sm[KB / 64];
     const int r = blockIdx.y;
     const int nb = gridDim.x;
-    if (fslot >= 0 && h[2 * ((int64_t)r * ldh + fslot)] != 0.0) return;
+    double* fl = flag + 2 * (int64_t)r * ldf;
+    if (second) {
+        if (*fl != 0.0) return;
+    } else {
+        const bool one = gs_one_pass(h, ldh, r, nv, wslot);
+        if (blockIdx.x == 0 && threadIdx.x == 0) *fl = one ? 1.0 : 0.0;
+        if (!one) return;
+    }
     double* wr = w + (int64_t)r * 2 * N;
     double hr[MAXV], hi[MAXV];
 #pragma unroll
@@ -135,50 +165,31 @@ __global__ __launch_bounds__(KB) void k_axpy_multi(const double* __restrict__ V,
         wr[N + e] = xi;
         acc += xr * xr + xi * xi;
     }
-    if (partial) {
-        const double s = block_sum(acc, sm);
-        if (threadIdx.x == 0) partial[(int64_t)r * nb + blockIdx.x] = s;
-    }
+    const double sacc = block_sum(acc, sm);
+    if (threadIdx.x == 0) npart[(int64_t)r * nb + blockIdx.x] = sacc;
 }
 
-// Whether one classical Gram-Schmidt pass leaves w orthogonal enough to V
-// (the test of Daniel, Gragg, Kaufman and Stewart, 1976): the updated w keeps
-// more than eta of its length, |w|^2 - sum_i |h_i|^2 > eta^2 |w|^2 (V
-// orthonormal), so that its rounding error relative to V, about u |w| / |w'|,
-// stays below u / eta (u the unit roundoff).  Their bound is eta = 1/sqrt(2);
-// a preconditioned step removes most of w (the preconditioned operator is near
-// the identity), so that bound asks for a second pass almost every time.  With
-// eta = 0.1 (at most ten times the roundoff) the 2D and 3D workloads solved as
-// fast as with no second pass at all, with the same iterations and residuals
-// as with an unconditional second pass (32 sources at 512^2: 882 -> 845 ms per
-// solve).  A zero w fails the test.
-static constexpr double kGsEta2 = 1e-2;
-EHH_DEV bool gs_one_pass(const double* h, int ldh, int r, int nv, int wslot) {
-    const double* hr = h + 2 * (int64_t)r * ldh;
-    double p = 0.0;
-    for (int i = 0; i < nv; ++i) p += hr[2 * i] * hr[2 * i] + hr[2 * i + 1] * hr[2 * i + 1];
-    const double w2 = hr[2 * wslot];
-    return w2 - p > kGsEta2 * w2;
-}
-
-// Classical Gram-Schmidt, first pass and second projection in one sweep:
-// w <- w - sum_i h_i V_i, then the partial sums of <V_i, w> for the updated w,
-// with each V_i element loaded once for both.  With wslot >= 0 (h[r][wslot] =
-// |w|^2 before the pass) a source for which one pass is enough (gs_one_pass)
-// writes zero projections, the block partials of the updated |w|^2 to npart
-// (npart[r * nb + blk]) and the flag 1 to hout[r][fslot] (0 otherwise), which
-// the second update reads to skip the source.
+// Classical Gram-Schmidt, first pass and second projection in one sweep, for the
+// sources that need two passes (flag[r] == 0): w <- w - sum_i h_i V_i, then the
+// partial sums of <V_i, w> for the updated w, with each V_i element loaded once
+// for both.  A one-pass source writes zero partials (its h2 is zero).
 __global__ __launch_bounds__(KB) void k_axpy_dots(const double* __restrict__ V, int nv, double* __restrict__ w,
                                                   int64_t N, int nrhs, const double* __restrict__ h, int ldh,
-                                                  double* __restrict__ partial, int wslot, double* __restrict__ npart,
-                                                  double* __restrict__ hout, int ldo, int fslot) {
+                                                  double* __restrict__ partial, const double* __restrict__ flag,
+                                                  int ldf) {
     __shared__ double sm[KB / 64];
     const int r = blockIdx.y;
     const int nb = gridDim.x;
+    if (flag[2 * (int64_t)r * ldf] != 0.0) {
+        if (threadIdx.x == 0)
+            for (int i = 0; i < nv; ++i) {
+                partial[(((int64_t)r * nv + i) * 2 + 0) * nb + blockIdx.x] = 0.0;
+                partial[(((int64_t)r * nv + i) * 2 + 1) * nb + blockIdx.x] = 0.0;
+            }
+        return;
+    }
     double* wr = w + (int64_t)r * 2 * N;
-    const bool one = wslot >= 0 && gs_one_pass(h, ldh, r, nv, wslot);
-    if (wslot >= 0 && blockIdx.x == 0 && threadIdx.x == 0) hout[2 * ((int64_t)r * ldo + fslot)] = one ? 1.0 : 0.0;
-    double hr[MAXV], hi[MAXV], are[MAXV], aim[MAXV], ww = 0.0;
+    double hr[MAXV], hi[MAXV], are[MAXV], aim[MAXV];
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
         hr[i] = i < nv ? h[2 * ((int64_t)r * ldh + i)] : 0.0;
@@ -200,15 +211,11 @@ __global__ __launch_bounds__(KB) void k_axpy_dots(const double* __restrict__ V, 
         }
         wr[e] = xr;
         wr[N + e] = xi;
-        if (one) {
-            ww += xr * xr + xi * xi;
-        } else {
 #pragma unroll
-            for (int i = 0; i < MAXV; ++i) {
-                if (i < nv) {
-                    are[i] += vr[i] * xr + vi[i] * xi;
-                    aim[i] += vr[i] * xi - vi[i] * xr;
-                }
+        for (int i = 0; i < MAXV; ++i) {
+            if (i < nv) {
+                are[i] += vr[i] * xr + vi[i] * xi;
+                aim[i] += vr[i] * xi - vi[i] * xr;
             }
         }
     }
@@ -220,10 +227,6 @@ __global__ __launch_bounds__(KB) void k_axpy_dots(const double* __restrict__ V, 
             const double si = block_sum(aim[i], sm);
             if (threadIdx.x == 0) partial[(((int64_t)r * nv + i) * 2 + 1) * nb + blockIdx.x] = si;
         }
-    }
-    if (one) {
-        const double sw = block_sum(ww, sm);
-        if (threadIdx.x == 0) npart[(int64_t)r * nb + blockIdx.x] = sw;
     }
 }
 
@@ -237,18 +240,23 @@ hipError_t launch_orthogonalise(const double* V, int nv, double* w, int64_t N, i
                                 double* h1, double* h2, int m, hipStream_t s) {
     const int nb = krylov_blocks(N), ldh = m + 1;
     // partial: the projections' block partials (below 2 m nrhs nb), then the
-    // partials of |w|^2 before the pass and of the final |w|^2
+    // partials of |w|^2 before the pass and of the final |w|^2; slot m of h1
+    // holds |w|^2 before the pass, slot m of h2 the one-pass flag
     double* wpart = partial + (size_t)2 * m * nrhs * nb;
     double* npart = gs_norm_partials(partial, N, nrhs, m);
+    double* flag = h2 + 2 * m;
     const unsigned nf = nblk((int64_t)(nrhs * nv * 2 + nrhs) * 64);
     hipLaunchKernelGGL(k_dots_partial, dim3(nb, nrhs), KB, 0, s, V, nv, (const double*)w, N, nrhs, partial, wpart);
     hipLaunchKernelGGL(k_partial_final, nf, 256, 0, s, (const double*)partial, nv, nb, nrhs, h1, ldh,
                        (const double*)wpart, m);
-    hipLaunchKernelGGL(k_axpy_dots, dim3(nb, nrhs), KB, 0, s, V, nv, w, N, nrhs, (const double*)h1, ldh, partial, m,
-                       npart, h2, ldh, m);
+    hipLaunchKernelGGL(k_axpy_multi, dim3(nb, nrhs), KB, 0, s, V, nv, w, N, nrhs, (const double*)h1, ldh, npart, 0, m,
+                       flag, ldh);
+    hipLaunchKernelGGL(k_axpy_dots, dim3(nb, nrhs), KB, 0, s, V, nv, w, N, nrhs, (const double*)h1, ldh, partial,
+                       (const double*)flag, ldh);
     hipLaunchKernelGGL(k_partial_final, nblk((int64_t)nrhs * nv * 2 * 64), 256, 0, s, (const double*)partial, nv, nb,
                        nrhs, h2, ldh, (const double*)nullptr, 0);
-    hipLaunchKernelGGL(k_axpy_multi, dim3(nb, nrhs), KB, 0, s, V, nv, w, N, nrhs, (const double*)h2, ldh, npart, m);
+    hipLaunchKernelGGL(k_axpy_multi, dim3(nb, nrhs), KB, 0, s, V, nv, w, N, nrhs, (const double*)h2, ldh, npart, 1, m,
+                       flag, ldh);
     return hipGetLastError();
 }
 
