@@ -1293,12 +1293,14 @@ int32_t enqueue_iter(ehh_ctx* c, const LevelDesc<double>& A, int j, int nrhs, hi
     CHK(precondition_any(c, Vj, Zj, nrhs, s, v32 != nullptr));
     HIPCHK(launch_apply<double>(A, Zj, nullptr, c->w, nrhs, s));
     // classical Gram-Schmidt, reorthogonalised where one pass is not enough:
-    // h1 = V^H w with |w|^2; w -= V h1 and h2 = V^H w (one sweep); w -= V h2
-    // with |w|^2 (skipped, h2 = 0, where one pass sufficed)
-    HIPCHK(launch_orthogonalise(c->V, j + 1, c->w, N, nrhs, c->partial, c->hcol, c->hcol2, m, s));
+    // h1 = V^H w with |w|^2; where one pass suffices V_{j+1} = (w - V h1) /
+    // |w - V h1| at once; elsewhere w -= V h1 and h2 = V^H w (one sweep),
+    // w -= V h2 with |w|^2, and V_{j+1} = w / |w| after the Givens step
+    double* Vn = c->V + (size_t)(j + 1) * nrhs * 2 * N;
+    HIPCHK(launch_orthogonalise(c->V, j + 1, c->w, N, nrhs, c->partial, c->hcol, c->hcol2, m, c->nrm2, Vn, v32, s));
     HIPCHK(launch_givens(c->H, c->cs, c->g, c->hcol, c->hcol2, gs_norm_partials(c->partial, N, nrhs, m), N,
-                         c->nrm2, j, m, nrhs, c->active, c->est, c->bnorm, s));
-    HIPCHK(launch_scale(c->w, c->V + (size_t)(j + 1) * nrhs * 2 * N, N, nrhs, c->nrm2, 1, s, v32));
+                         c->nrm2, j, m, nrhs, c->active, c->est, c->bnorm, s, gs_flag(c->hcol2, m), m + 1));
+    HIPCHK(launch_scale(c->w, Vn, N, nrhs, c->nrm2, 1, s, v32, gs_flag(c->hcol2, m), m + 1));
     return EHH_OK;
 }
 

@@ -113,34 +113,42 @@ __global__ __launch_bounds__(256) void k_partial_final(const double* __restrict_
 // as with an unconditional second pass (32 sources at 512^2: 882 -> 845 ms per
 // solve).  A zero w fails the test.
 static constexpr double kGsEta2 = 1e-2;
-EHH_DEV bool gs_one_pass(const double* h, int ldh, int r, int nv, int wslot) {
-    const double* hr = h + 2 * (int64_t)r * ldh;
-    double p = 0.0;
-    for (int i = 0; i < nv; ++i) p += hr[2 * i] * hr[2 * i] + hr[2 * i + 1] * hr[2 * i + 1];
-    const double w2 = hr[2 * wslot];
-    return w2 - p > kGsEta2 * w2;
-}
+EHH_DEV bool gs_one_pass(double w2, double p) { return w2 - p > kGsEta2 * w2; }
 
-// w -= sum_i h_i V_i with the block partials of |w|^2 (npart[r * nb + blk]).
-// The orthogonalisation runs it twice:
+// w -= sum_i h_i V_i.  The orthogonalisation runs it twice:
 // first (second = 0): h = h1, where slot wslot holds |w|^2 before the pass; each
 //   block decides with gs_one_pass, block 0 writes the decision (1: one pass is
-//   enough) to flag[r], and only one-pass sources are updated;
-// second (second = 1): h = h2, and only the sources with flag[r] == 0 are updated.
+//   enough) to flag[r], and only one-pass sources are updated.  Their new basis
+//   vector is written at once, normalised: |w - V h|^2 = |w|^2 - sum_i |h_i|^2
+//   (V orthonormal; the test bounds the cancellation to two digits), which block
+//   0 stores in nrm2[r] for the Hessenberg column; out = (w - V h) / |w - V h|
+//   (and out32, if given, in FP32), w is left as it was;
+// second (second = 1): h = h2, and only the sources with flag[r] == 0 are
+//   updated in place, with the block partials of |w|^2 (npart[r * nb + blk]).
 __global__ __launch_bounds__(KB) void k_axpy_multi(const double* __restrict__ V, int nv, double* __restrict__ w,
                                                    int64_t N, int nrhs, const double* __restrict__ h, int ldh,
                                                    double* __restrict__ npart, int second, int wslot,
-                                                   double* __restrict__ flag, int ldf) {
+                                                   double* __restrict__ flag, int ldf, double* __restrict__ nrm2,
+                                                   double* __restrict__ out, float* __restrict__ out32) {
     __shared__ double sm[KB / 64];
     const int r = blockIdx.y;
     const int nb = gridDim.x;
     double* fl = flag + 2 * (int64_t)r * ldf;
+    double f = 1.0;
     if (second) {
         if (*fl != 0.0) return;
     } else {
-        const bool one = gs_one_pass(h, ldh, r, nv, wslot);
-        if (blockIdx.x == 0 && threadIdx.x == 0) *fl = one ? 1.0 : 0.0;
+        const double* hr = h + 2 * (int64_t)r * ldh;
+        double p = 0.0;
+        for (int i = 0; i < nv; ++i) p += hr[2 * i] * hr[2 * i] + hr[2 * i + 1] * hr[2 * i + 1];
+        const double w2 = hr[2 * wslot];
+        const bool one = gs_one_pass(w2, p);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            *fl = one ? 1.0 : 0.0;
+            if (one) nrm2[r] = w2 - p;
+        }
         if (!one) return;
+        f = 1.0 / sqrt(w2 - p);
     }
     double* wr = w + (int64_t)r * 2 * N;
     double hr[MAXV], hi[MAXV];
@@ -161,12 +169,26 @@ __global__ __launch_bounds__(KB) void k_axpy_multi(const double* __restrict__ V,
                 xi -= hr[i] * vi + hi[i] * vr;
             }
         }
-        wr[e] = xr;
-        wr[N + e] = xi;
-        acc += xr * xr + xi * xi;
+        if (second) {
+            wr[e] = xr;
+            wr[N + e] = xi;
+            acc += xr * xr + xi * xi;
+        } else {
+            const double yr = xr * f, yi = xi * f;
+            double* o = out + (int64_t)r * 2 * N;
+            o[e] = yr;
+            o[N + e] = yi;
+            if (out32) {
+                float* o32 = out32 + (int64_t)r * 2 * N;
+                o32[e] = (float)yr;
+                o32[N + e] = (float)yi;
+            }
+        }
     }
-    const double sacc = block_sum(acc, sm);
-    if (threadIdx.x == 0) npart[(int64_t)r * nb + blockIdx.x] = sacc;
+    if (second) {
+        const double sacc = block_sum(acc, sm);
+        if (threadIdx.x == 0) npart[(int64_t)r * nb + blockIdx.x] = sacc;
+    }
 }
 
 // Classical Gram-Schmidt, first pass and second projection in one sweep, for the
@@ -237,7 +259,8 @@ double* gs_norm_partials(double* partial, int64_t N, int nrhs, int m) {
 }
 
 hipError_t launch_orthogonalise(const double* V, int nv, double* w, int64_t N, int nrhs, double* partial,
-                                double* h1, double* h2, int m, hipStream_t s) {
+                                double* h1, double* h2, int m, double* nrm2, double* vnext, float* v32,
+                                hipStream_t s) {
     const int nb = krylov_blocks(N), ldh = m + 1;
     // partial: the projections' block partials (below 2 m nrhs nb), then the
     // partials of |w|^2 before the pass and of the final |w|^2; slot m of h1
@@ -250,13 +273,13 @@ hipError_t launch_orthogonalise(const double* V, int nv, double* w, int64_t N, i
     hipLaunchKernelGGL(k_partial_final, nf, 256, 0, s, (const double*)partial, nv, nb, nrhs, h1, ldh,
                        (const double*)wpart, m);
     hipLaunchKernelGGL(k_axpy_multi, dim3(nb, nrhs), KB, 0, s, V, nv, w, N, nrhs, (const double*)h1, ldh, npart, 0, m,
-                       flag, ldh);
+                       flag, ldh, nrm2, vnext, v32);
     hipLaunchKernelGGL(k_axpy_dots, dim3(nb, nrhs), KB, 0, s, V, nv, w, N, nrhs, (const double*)h1, ldh, partial,
                        (const double*)flag, ldh);
     hipLaunchKernelGGL(k_partial_final, nblk((int64_t)nrhs * nv * 2 * 64), 256, 0, s, (const double*)partial, nv, nb,
                        nrhs, h2, ldh, (const double*)nullptr, 0);
     hipLaunchKernelGGL(k_axpy_multi, dim3(nb, nrhs), KB, 0, s, V, nv, w, N, nrhs, (const double*)h2, ldh, npart, 1, m,
-                       flag, ldh);
+                       flag, ldh, nrm2, vnext, v32);
     return hipGetLastError();
 }
 
@@ -288,12 +311,15 @@ hipError_t launch_norm2(const double* x, int64_t N, int nrhs, double* partial, d
 
 // mode 0: out = x * sc[r]; mode 1: out = x / sqrt(sc[r]) (0 if sc[r] == 0)
 // (out32, when given, receives the same values in FP32: the input of a
-// complex64 preconditioner cycle, written in the same pass.)
+// complex64 preconditioner cycle, written in the same pass.)  Sources whose
+// skip[2 r ldskip] is nonzero are left alone.
 __global__ void k_scale(const double* __restrict__ x, double* __restrict__ out, int64_t N, int nrhs,
-                        const double* __restrict__ sc, int mode, float* __restrict__ out32) {
+                        const double* __restrict__ sc, int mode, float* __restrict__ out32,
+                        const double* __restrict__ skip, int ldskip) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 2 * N * nrhs) return;
     const int r = (int)(t / (2 * N));
+    if (skip && skip[2 * (int64_t)r * ldskip] != 0.0) return;
     double f = sc[r];
     if (mode == 1) f = f > 0.0 ? 1.0 / sqrt(f) : 0.0;
     const double v = x[t] * f;
@@ -302,8 +328,8 @@ __global__ void k_scale(const double* __restrict__ x, double* __restrict__ out, 
 }
 
 hipError_t launch_scale(const double* x, double* out, int64_t N, int nrhs, const double* scale, int mode,
-                        hipStream_t s, float* out32) {
-    hipLaunchKernelGGL(k_scale, nblk(2 * N * nrhs), 256, 0, s, x, out, N, nrhs, scale, mode, out32);
+                        hipStream_t s, float* out32, const double* skip, int ldskip) {
+    hipLaunchKernelGGL(k_scale, nblk(2 * N * nrhs), 256, 0, s, x, out, N, nrhs, scale, mode, out32, skip, ldskip);
     return hipGetLastError();
 }
 
@@ -324,18 +350,22 @@ hipError_t launch_axpby(const double* x, const double* y, double* out, int64_t n
 // hnext2[r] = |w|^2.
 // One wavefront per right-hand side: |w|^2 = the fixed-order sum of the block
 // partials of the orthogonalisation's last update (the sum k_norm_final forms,
-// written to nrm2 for the scaling of w), then lane 0 applies the rotations.
+// written to nrm2 for the scaling of w), or, for a source that one pass served
+// (flag[2 r ldf] nonzero), the nrm2[r] that pass left; then lane 0 applies the
+// rotations.
 __global__ __launch_bounds__(64) void k_givens(double* __restrict__ H, double* __restrict__ cs,
                                                double* __restrict__ g, const double* __restrict__ hcol,
                                                const double* __restrict__ hcol2, const double* __restrict__ partial,
                                                int nblk_w, double* __restrict__ nrm2, int j, int m, int nrhs,
                                                const int* __restrict__ active, double* __restrict__ est,
-                                               const double* __restrict__ bnorm) {
+                                               const double* __restrict__ bnorm, const double* __restrict__ flag,
+                                               int ldf) {
     const int r = blockIdx.x;
     if (r >= nrhs) return;
-    const double w2 = wave_sum(partial + (int64_t)r * nblk_w, nblk_w);
+    const bool one = flag && flag[2 * (int64_t)r * ldf] != 0.0;
+    const double w2 = one ? nrm2[r] : wave_sum(partial + (int64_t)r * nblk_w, nblk_w);
     if (threadIdx.x != 0) return;
-    nrm2[r] = w2;
+    if (!one) nrm2[r] = w2;
     if (!active[r]) return;
     double* col = H + 2 * (((int64_t)r * m + j) * (m + 1));
     double* c = cs + 3 * (int64_t)r * m;
@@ -396,9 +426,9 @@ __global__ __launch_bounds__(64) void k_givens(double* __restrict__ H, double* _
 
 hipError_t launch_givens(double* H, double* cs, double* g, const double* hcol, const double* hcol2,
                          const double* partial, int64_t N, double* nrm2, int j, int m, int nrhs, const int* active,
-                         double* est, const double* bnorm, hipStream_t s) {
+                         double* est, const double* bnorm, hipStream_t s, const double* flag, int ldf) {
     hipLaunchKernelGGL(k_givens, nrhs, 64, 0, s, H, cs, g, hcol, hcol2, partial, krylov_blocks(N), nrm2, j, m, nrhs,
-                       active, est, bnorm);
+                       active, est, bnorm, flag, ldf);
     return hipGetLastError();
 }
 
