@@ -128,6 +128,11 @@ typedef struct {
                                block per level (component-dependent damping (w_u, w_p),
                                section 5.2; damping[] then damps the displacement rows);
                                0 (default) = damping[l] */
+    int32_t reorth;         /* Gram-Schmidt in the FGMRES Arnoldi step: 0 (default) =
+                               classical Gram-Schmidt, repeated once for a right-hand
+                               side whose first pass kept less than 0.1 of |w| (the test
+                               of Daniel, Gragg, Kaufman and Stewart with bound 0.1);
+                               1 = always two passes (CGS2) */
 } ehh_options_t;
 
 typedef struct {

@@ -799,6 +799,7 @@ int32_t check_problem(const ehh_problem_t* p, const ehh_options_t* o) {
     if (o->coarse_dd_overlap < 0) return fail(EHH_ERR_INVALID, "coarse_dd_overlap >= 0");
     if (o->coarse_dd_colors != 0 && o->coarse_dd_colors != 1) return fail(EHH_ERR_INVALID, "coarse_dd_colors must be 0 or 1");
     if (o->dd_batch != 0 && o->dd_batch != 1) return fail(EHH_ERR_INVALID, "dd_batch must be 0 or 1");
+    if (o->reorth != 0 && o->reorth != 1) return fail(EHH_ERR_INVALID, "reorth must be 0 or 1");
     for (int a = 0; a < p->dim; ++a)
         if (o->dd_parts[a] < 1 || o->dd_parts[a] > p->n[a]) return fail(EHH_ERR_INVALID, "dd_parts out of range");
     if (o->dd_overlap < 0 || o->dd_pad < 0) return fail(EHH_ERR_INVALID, "dd_overlap, dd_pad >= 0");
@@ -1292,15 +1293,12 @@ int32_t enqueue_iter(ehh_ctx* c, const LevelDesc<double>& A, int j, int nrhs, hi
     float* v32 = krylov_copy32(c);
     CHK(precondition_any(c, Vj, Zj, nrhs, s, v32 != nullptr));
     HIPCHK(launch_apply<double>(A, Zj, nullptr, c->w, nrhs, s));
-    // classical Gram-Schmidt, reorthogonalised where one pass is not enough:
-    // h1 = V^H w with |w|^2; where one pass suffices V_{j+1} = (w - V h1) /
-    // |w - V h1| at once; elsewhere w -= V h1 and h2 = V^H w (one sweep),
-    // w -= V h2 with |w|^2, and V_{j+1} = w / |w| after the Givens step
+    // classical Gram-Schmidt, reorthogonalised where one pass is not enough,
+    // V_{j+1} = the normalised result; then the Givens step
     double* Vn = c->V + (size_t)(j + 1) * nrhs * 2 * N;
-    HIPCHK(launch_orthogonalise(c->V, j + 1, c->w, N, nrhs, c->partial, c->hcol, c->hcol2, m, c->nrm2, Vn, v32, s));
-    HIPCHK(launch_givens(c->H, c->cs, c->g, c->hcol, c->hcol2, gs_norm_partials(c->partial, N, nrhs, m), N,
-                         c->nrm2, j, m, nrhs, c->active, c->est, c->bnorm, s, gs_flag(c->hcol2, m), m + 1));
-    HIPCHK(launch_scale(c->w, Vn, N, nrhs, c->nrm2, 1, s, v32, gs_flag(c->hcol2, m), m + 1));
+    HIPCHK(launch_orthogonalise(c->V, j + 1, c->w, N, nrhs, c->partial, c->hcol, c->hcol2, m, c->nrm2, Vn, v32,
+                                c->opt.reorth == 1, s));
+    HIPCHK(launch_givens(c->H, c->cs, c->g, c->hcol, c->hcol2, c->nrm2, j, m, nrhs, c->active, c->est, c->bnorm, s));
     return EHH_OK;
 }
 

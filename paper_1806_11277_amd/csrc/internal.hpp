@@ -182,33 +182,25 @@ int krylov_blocks(int64_t n2);
 // nrm2[r] = |x(r)|^2
 hipError_t launch_norm2(const double* x, int64_t N, int nrhs, double* partial, double* nrm2, hipStream_t s);
 // out(r) = x(r) * scale[r] (scale real; mode 1: 1/sqrt(scale[r])); out32, if
-// not null, receives an FP32 copy; sources with skip[2 r ldskip] != 0 are left
-// alone.
+// not null, receives an FP32 copy.
 hipError_t launch_scale(const double* x, double* out, int64_t N, int nrhs, const double* scale, int mode,
-                        hipStream_t s, float* out32 = nullptr, const double* skip = nullptr, int ldskip = 0);
-// Orthogonalise w(r) against V_0(r) .. V_{nv-1}(r) for every right-hand side
-// (nv <= m): classical Gram-Schmidt, h1 = V^H w and w -= V h1, repeated once
-// (h2 = V^H w, w -= V h2) for the sources where the first pass removed more
-// than 99 % of |w|^2; h2 = 0 elsewhere.  h1, h2: (m + 1) complex entries per
-// source (slot m is scratch: |w|^2 before the pass in h1, the one-pass flag in
-// h2, read by launch_givens and launch_scale as gs_flag(h2, m)); partial:
-// krylov_blocks * nrhs * (m + 1) * 2 doubles.  A one-pass source gets its next
-// basis vector vnext(r) (and v32(r), if given) normalised at once and
-// nrm2[r] = |w - V h1|^2; the others keep w and leave the block partials of
-// |w|^2 at gs_norm_partials(partial, N, nrhs, m) for launch_givens.
+                        hipStream_t s, float* out32 = nullptr);
+// One Arnoldi orthogonalisation for every right-hand side (nv <= m): w(r)
+// against V_0(r) .. V_{nv-1}(r) by classical Gram-Schmidt, h1 = V^H w; where
+// the pass kept less than 0.1 of |w| (or always, force_two) a second pass
+// h2 = V^H w' follows, h2 = 0 elsewhere.  The normalised result goes to
+// vnext(r) (and v32(r), if given) and its squared norm to nrm2[r]; w is
+// scratch.  h1, h2: (m + 1) complex entries per source (slot m is scratch:
+// |w|^2 in h1, the one-pass flag in h2); partial: krylov_blocks * nrhs *
+// (m + 1) * 2 doubles.
 hipError_t launch_orthogonalise(const double* V, int nv, double* w, int64_t N, int nrhs, double* partial,
                                 double* h1, double* h2, int m, double* nrm2, double* vnext, float* v32,
-                                hipStream_t s);
-inline const double* gs_flag(const double* h2, int m) { return h2 + 2 * m; }
-double* gs_norm_partials(double* partial, int64_t N, int nrhs, int m);
-// Givens update of column j of every right-hand side's Hessenberg matrix.
-// also forms nrm2 = |w|^2 from the block partials of the final |w|^2 (N: vector length)
-// With flag (gs_flag, stride ldf = m + 1), a flagged source takes |w|^2 from
-// nrm2 instead of the partials.
+                                bool force_two, hipStream_t s);
+// Givens update of column j of every right-hand side's Hessenberg matrix:
+// entries hcol + hcol2 (i <= j) and sqrt(nrm2[r]) below the diagonal.
 hipError_t launch_givens(double* H, double* cs, double* g, const double* hcol, const double* hcol2,
-                         const double* partial, int64_t N, double* nrm2, int j, int m, int nrhs, const int* active,
-                         double* est, const double* bnorm, hipStream_t s, const double* flag = nullptr,
-                         int ldf = 0);
+                         const double* nrm2, int j, int m, int nrhs, const int* active, double* est,
+                         const double* bnorm, hipStream_t s);
 // y = R^{-1} g (columns ncols[r]); x(r) += sum_i y_i Z_i(r)
 hipError_t launch_update_x(const double* H, const double* g, const double* Z, double* x, int64_t N, int nrhs,
                            int m, const int* ncols, double* y, hipStream_t s);

@@ -115,49 +115,44 @@ __global__ __launch_bounds__(256) void k_partial_final(const double* __restrict_
 static constexpr double kGsEta2 = 1e-2;
 EHH_DEV bool gs_one_pass(double w2, double p) { return w2 - p > kGsEta2 * w2; }
 
-// w -= sum_i h_i V_i.  The orthogonalisation runs it twice:
-// first (second = 0): h = h1, where slot wslot holds |w|^2 before the pass; each
-//   block decides with gs_one_pass, block 0 writes the decision (1: one pass is
-//   enough) to flag[r], and only one-pass sources are updated.  Their new basis
-//   vector is written at once, normalised: |w - V h|^2 = |w|^2 - sum_i |h_i|^2
-//   (V orthonormal; the test bounds the cancellation to two digits), which block
-//   0 stores in nrm2[r] for the Hessenberg column; out = (w - V h) / |w - V h|
-//   (and out32, if given, in FP32), w is left as it was;
-// second (second = 1): h = h2, and only the sources with flag[r] == 0 are
-//   updated in place, with the block partials of |w|^2 (npart[r * nb + blk]).
-__global__ __launch_bounds__(KB) void k_axpy_multi(const double* __restrict__ V, int nv, double* __restrict__ w,
-                                                   int64_t N, int nrhs, const double* __restrict__ h, int ldh,
-                                                   double* __restrict__ npart, int second, int wslot,
-                                                   double* __restrict__ flag, int ldf, double* __restrict__ nrm2,
-                                                   double* __restrict__ out, float* __restrict__ out32) {
-    __shared__ double sm[KB / 64];
+// The first Gram-Schmidt update, with h = h1 (slot wslot of h1 holds |w|^2
+// before the pass).  Every block takes the decision of gs_one_pass (none with
+// force_two) and block 0 records it in flag[r] (1: one pass).  A one-pass
+// source gets its next basis vector at once, normalised:
+// |w - V h|^2 = |w|^2 - sum_i |h_i|^2 (V orthonormal; the test bounds the
+// cancellation to two digits), so out = (w - V h) / |w - V h| (and out32, if
+// given, in FP32), nrm2[r] = |w - V h|^2 and h2[r] = 0 for the Hessenberg
+// column; w is left as it was.  The other sources are left to the second pass.
+__global__ __launch_bounds__(KB) void k_gs_first(const double* __restrict__ V, int nv, const double* __restrict__ w,
+                                                 int64_t N, int nrhs, const double* __restrict__ h, int ldh,
+                                                 int wslot, int force_two, double* __restrict__ flag,
+                                                 double* __restrict__ h2, double* __restrict__ nrm2,
+                                                 double* __restrict__ out, float* __restrict__ out32) {
     const int r = blockIdx.y;
     const int nb = gridDim.x;
-    double* fl = flag + 2 * (int64_t)r * ldf;
-    double f = 1.0;
-    if (second) {
-        if (*fl != 0.0) return;
-    } else {
-        const double* hr = h + 2 * (int64_t)r * ldh;
-        double p = 0.0;
-        for (int i = 0; i < nv; ++i) p += hr[2 * i] * hr[2 * i] + hr[2 * i + 1] * hr[2 * i + 1];
-        const double w2 = hr[2 * wslot];
-        const bool one = gs_one_pass(w2, p);
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            *fl = one ? 1.0 : 0.0;
-            if (one) nrm2[r] = w2 - p;
+    const double* hr0 = h + 2 * (int64_t)r * ldh;
+    double p = 0.0;
+    for (int i = 0; i < nv; ++i) p += hr0[2 * i] * hr0[2 * i] + hr0[2 * i + 1] * hr0[2 * i + 1];
+    const double w2 = hr0[2 * wslot];
+    const bool one = !force_two && gs_one_pass(w2, p);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        flag[2 * (int64_t)r * ldh] = one ? 1.0 : 0.0;
+        if (one) {
+            nrm2[r] = w2 - p;
+            for (int i = 0; i < nv; ++i) h2[2 * ((int64_t)r * ldh + i)] = h2[2 * ((int64_t)r * ldh + i) + 1] = 0.0;
         }
-        if (!one) return;
-        f = 1.0 / sqrt(w2 - p);
     }
-    double* wr = w + (int64_t)r * 2 * N;
+    if (!one) return;
+    const double f = 1.0 / sqrt(w2 - p);
+    const double* wr = w + (int64_t)r * 2 * N;
+    double* o = out + (int64_t)r * 2 * N;
+    float* o32 = out32 ? out32 + (int64_t)r * 2 * N : nullptr;
     double hr[MAXV], hi[MAXV];
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
-        hr[i] = i < nv ? h[2 * ((int64_t)r * ldh + i)] : 0.0;
-        hi[i] = i < nv ? h[2 * ((int64_t)r * ldh + i) + 1] : 0.0;
+        hr[i] = i < nv ? hr0[2 * i] : 0.0;
+        hi[i] = i < nv ? hr0[2 * i + 1] : 0.0;
     }
-    double acc = 0.0;
     for (int64_t e = (int64_t)blockIdx.x * KB + threadIdx.x; e < N; e += (int64_t)nb * KB) {
         double xr = wr[e], xi = wr[N + e];
 #pragma unroll
@@ -169,49 +164,31 @@ __global__ __launch_bounds__(KB) void k_axpy_multi(const double* __restrict__ V,
                 xi -= hr[i] * vi + hi[i] * vr;
             }
         }
-        if (second) {
-            wr[e] = xr;
-            wr[N + e] = xi;
-            acc += xr * xr + xi * xi;
-        } else {
-            const double yr = xr * f, yi = xi * f;
-            double* o = out + (int64_t)r * 2 * N;
-            o[e] = yr;
-            o[N + e] = yi;
-            if (out32) {
-                float* o32 = out32 + (int64_t)r * 2 * N;
-                o32[e] = (float)yr;
-                o32[N + e] = (float)yi;
-            }
+        const double yr = xr * f, yi = xi * f;
+        o[e] = yr;
+        o[N + e] = yi;
+        if (o32) {
+            o32[e] = (float)yr;
+            o32[N + e] = (float)yi;
         }
-    }
-    if (second) {
-        const double sacc = block_sum(acc, sm);
-        if (threadIdx.x == 0) npart[(int64_t)r * nb + blockIdx.x] = sacc;
     }
 }
 
 // Classical Gram-Schmidt, first pass and second projection in one sweep, for the
 // sources that need two passes (flag[r] == 0): w <- w - sum_i h_i V_i, then the
-// partial sums of <V_i, w> for the updated w, with each V_i element loaded once
-// for both.  A one-pass source writes zero partials (its h2 is zero).
+// block partials of <V_i, w> and of |w|^2 for the updated w, with each V_i
+// element loaded once for both (partial[((r * nv + i) * 2 + c) * nb + blk],
+// npart[r * nb + blk]).
 __global__ __launch_bounds__(KB) void k_axpy_dots(const double* __restrict__ V, int nv, double* __restrict__ w,
                                                   int64_t N, int nrhs, const double* __restrict__ h, int ldh,
-                                                  double* __restrict__ partial, const double* __restrict__ flag,
-                                                  int ldf) {
+                                                  double* __restrict__ partial, double* __restrict__ npart,
+                                                  const double* __restrict__ flag) {
     __shared__ double sm[KB / 64];
     const int r = blockIdx.y;
     const int nb = gridDim.x;
-    if (flag[2 * (int64_t)r * ldf] != 0.0) {
-        if (threadIdx.x == 0)
-            for (int i = 0; i < nv; ++i) {
-                partial[(((int64_t)r * nv + i) * 2 + 0) * nb + blockIdx.x] = 0.0;
-                partial[(((int64_t)r * nv + i) * 2 + 1) * nb + blockIdx.x] = 0.0;
-            }
-        return;
-    }
+    if (flag[2 * (int64_t)r * ldh] != 0.0) return;
     double* wr = w + (int64_t)r * 2 * N;
-    double hr[MAXV], hi[MAXV], are[MAXV], aim[MAXV];
+    double hr[MAXV], hi[MAXV], are[MAXV], aim[MAXV], ww = 0.0;
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
         hr[i] = i < nv ? h[2 * ((int64_t)r * ldh + i)] : 0.0;
@@ -233,6 +210,7 @@ __global__ __launch_bounds__(KB) void k_axpy_dots(const double* __restrict__ V, 
         }
         wr[e] = xr;
         wr[N + e] = xi;
+        ww += xr * xr + xi * xi;
 #pragma unroll
         for (int i = 0; i < MAXV; ++i) {
             if (i < nv) {
@@ -250,36 +228,95 @@ __global__ __launch_bounds__(KB) void k_axpy_dots(const double* __restrict__ V, 
             if (threadIdx.x == 0) partial[(((int64_t)r * nv + i) * 2 + 1) * nb + blockIdx.x] = si;
         }
     }
+    const double sw = block_sum(ww, sm);
+    if (threadIdx.x == 0) npart[(int64_t)r * nb + blockIdx.x] = sw;
 }
 
-// The block partials of the final |w|^2 that launch_orthogonalise leaves.
-double* gs_norm_partials(double* partial, int64_t N, int nrhs, int m) {
-    const int nb = krylov_blocks(N);
-    return partial + (size_t)2 * m * nrhs * nb + (size_t)nrhs * nb;
+// The second update of a two-pass source (flag[r] == 0).  Every block sums the
+// block partials k_axpy_dots left (one wavefront per sum, the fixed order of
+// wave_sum, so that all blocks agree): h2 = V^H w and |w|^2 of the once-updated
+// w.  Then w - V h2 has |w - V h2|^2 = |w|^2 - sum_i |h2_i|^2 (h2 is tiny, no
+// cancellation), out = (w - V h2) / |w - V h2| (out32 in FP32), and block 0
+// stores h2 and nrm2[r] for the Hessenberg column.  A zero vector stays zero.
+__global__ __launch_bounds__(KB) void k_gs_second(const double* __restrict__ V, int nv, const double* __restrict__ w,
+                                                  int64_t N, int nrhs, const double* __restrict__ partial,
+                                                  const double* __restrict__ npart, int nbp,
+                                                  double* __restrict__ h2, int ldh, const double* __restrict__ flag,
+                                                  double* __restrict__ nrm2, double* __restrict__ out,
+                                                  float* __restrict__ out32) {
+    __shared__ double hs[2 * MAXV + 1];
+    const int r = blockIdx.y;
+    const int nb = gridDim.x;
+    if (flag[2 * (int64_t)r * ldh] != 0.0) return;
+    const int nsum = 2 * nv + 1;
+    for (int q = threadIdx.x >> 6; q < nsum; q += KB / 64) {
+        const double* src = q < 2 * nv ? partial + ((int64_t)r * nv * 2 + q) * nbp : npart + (int64_t)r * nbp;
+        const double sq = wave_sum(src, nbp);
+        if ((threadIdx.x & 63) == 0) hs[q] = sq;
+    }
+    __syncthreads();
+    double hr[MAXV], hi[MAXV];
+    double p = 0.0;
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+        hr[i] = i < nv ? hs[2 * i] : 0.0;
+        hi[i] = i < nv ? hs[2 * i + 1] : 0.0;
+        p += hr[i] * hr[i] + hi[i] * hi[i];
+    }
+    const double n2 = fmax(hs[2 * nv] - p, 0.0);
+    const double f = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int i = 0; i < nv; ++i) {
+            h2[2 * ((int64_t)r * ldh + i)] = hs[2 * i];
+            h2[2 * ((int64_t)r * ldh + i) + 1] = hs[2 * i + 1];
+        }
+        nrm2[r] = n2;
+    }
+    const double* wr = w + (int64_t)r * 2 * N;
+    double* o = out + (int64_t)r * 2 * N;
+    float* o32 = out32 ? out32 + (int64_t)r * 2 * N : nullptr;
+    for (int64_t e = (int64_t)blockIdx.x * KB + threadIdx.x; e < N; e += (int64_t)nb * KB) {
+        double xr = wr[e], xi = wr[N + e];
+#pragma unroll
+        for (int i = 0; i < MAXV; ++i) {
+            if (i < nv) {
+                const double* v = V + ((int64_t)i * nrhs + r) * 2 * N;
+                const double vr = v[e], vi = v[N + e];
+                xr -= hr[i] * vr - hi[i] * vi;
+                xi -= hr[i] * vi + hi[i] * vr;
+            }
+        }
+        const double yr = xr * f, yi = xi * f;
+        o[e] = yr;
+        o[N + e] = yi;
+        if (o32) {
+            o32[e] = (float)yr;
+            o32[N + e] = (float)yi;
+        }
+    }
 }
 
 hipError_t launch_orthogonalise(const double* V, int nv, double* w, int64_t N, int nrhs, double* partial,
                                 double* h1, double* h2, int m, double* nrm2, double* vnext, float* v32,
-                                hipStream_t s) {
+                                bool force_two, hipStream_t s) {
     const int nb = krylov_blocks(N), ldh = m + 1;
     // partial: the projections' block partials (below 2 m nrhs nb), then the
-    // partials of |w|^2 before the pass and of the final |w|^2; slot m of h1
-    // holds |w|^2 before the pass, slot m of h2 the one-pass flag
+    // partials of |w|^2 before the first pass and after it; slot m of h1 holds
+    // |w|^2 before the pass, slot m of h2 the one-pass flag
     double* wpart = partial + (size_t)2 * m * nrhs * nb;
-    double* npart = gs_norm_partials(partial, N, nrhs, m);
+    double* npart = wpart + (size_t)nrhs * nb;
     double* flag = h2 + 2 * m;
     const unsigned nf = nblk((int64_t)(nrhs * nv * 2 + nrhs) * 64);
     hipLaunchKernelGGL(k_dots_partial, dim3(nb, nrhs), KB, 0, s, V, nv, (const double*)w, N, nrhs, partial, wpart);
     hipLaunchKernelGGL(k_partial_final, nf, 256, 0, s, (const double*)partial, nv, nb, nrhs, h1, ldh,
                        (const double*)wpart, m);
-    hipLaunchKernelGGL(k_axpy_multi, dim3(nb, nrhs), KB, 0, s, V, nv, w, N, nrhs, (const double*)h1, ldh, npart, 0, m,
-                       flag, ldh, nrm2, vnext, v32);
+    hipLaunchKernelGGL(k_gs_first, dim3(nb, nrhs), KB, 0, s, V, nv, (const double*)w, N, nrhs, (const double*)h1, ldh,
+                       m, force_two ? 1 : 0, flag, h2, nrm2, vnext, v32);
     hipLaunchKernelGGL(k_axpy_dots, dim3(nb, nrhs), KB, 0, s, V, nv, w, N, nrhs, (const double*)h1, ldh, partial,
-                       (const double*)flag, ldh);
-    hipLaunchKernelGGL(k_partial_final, nblk((int64_t)nrhs * nv * 2 * 64), 256, 0, s, (const double*)partial, nv, nb,
-                       nrhs, h2, ldh, (const double*)nullptr, 0);
-    hipLaunchKernelGGL(k_axpy_multi, dim3(nb, nrhs), KB, 0, s, V, nv, w, N, nrhs, (const double*)h2, ldh, npart, 1, m,
-                       flag, ldh, nrm2, vnext, v32);
+                       npart, (const double*)flag);
+    hipLaunchKernelGGL(k_gs_second, dim3(nb, nrhs), KB, 0, s, V, nv, (const double*)w, N, nrhs,
+                       (const double*)partial, (const double*)npart, nb, h2, ldh, (const double*)flag, nrm2, vnext,
+                       v32);
     return hipGetLastError();
 }
 
@@ -311,15 +348,12 @@ hipError_t launch_norm2(const double* x, int64_t N, int nrhs, double* partial, d
 
 // mode 0: out = x * sc[r]; mode 1: out = x / sqrt(sc[r]) (0 if sc[r] == 0)
 // (out32, when given, receives the same values in FP32: the input of a
-// complex64 preconditioner cycle, written in the same pass.)  Sources whose
-// skip[2 r ldskip] is nonzero are left alone.
+// complex64 preconditioner cycle, written in the same pass.)
 __global__ void k_scale(const double* __restrict__ x, double* __restrict__ out, int64_t N, int nrhs,
-                        const double* __restrict__ sc, int mode, float* __restrict__ out32,
-                        const double* __restrict__ skip, int ldskip) {
+                        const double* __restrict__ sc, int mode, float* __restrict__ out32) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 2 * N * nrhs) return;
     const int r = (int)(t / (2 * N));
-    if (skip && skip[2 * (int64_t)r * ldskip] != 0.0) return;
     double f = sc[r];
     if (mode == 1) f = f > 0.0 ? 1.0 / sqrt(f) : 0.0;
     const double v = x[t] * f;
@@ -328,8 +362,8 @@ __global__ void k_scale(const double* __restrict__ x, double* __restrict__ out, 
 }
 
 hipError_t launch_scale(const double* x, double* out, int64_t N, int nrhs, const double* scale, int mode,
-                        hipStream_t s, float* out32, const double* skip, int ldskip) {
-    hipLaunchKernelGGL(k_scale, nblk(2 * N * nrhs), 256, 0, s, x, out, N, nrhs, scale, mode, out32, skip, ldskip);
+                        hipStream_t s, float* out32) {
+    hipLaunchKernelGGL(k_scale, nblk(2 * N * nrhs), 256, 0, s, x, out, N, nrhs, scale, mode, out32);
     return hipGetLastError();
 }
 
@@ -348,24 +382,18 @@ hipError_t launch_axpby(const double* x, const double* y, double* out, int64_t n
 // H[r][j][i] (column j, i <= m) complex; cs[r][i] = (c, s_re, s_im); g[r][i] complex.
 // hcol[r][i] + hcol2[r][i] for i <= j: <v_i, w> (complex, the two CGS passes),
 // hnext2[r] = |w|^2.
-// One wavefront per right-hand side: |w|^2 = the fixed-order sum of the block
-// partials of the orthogonalisation's last update (the sum k_norm_final forms,
-// written to nrm2 for the scaling of w), or, for a source that one pass served
-// (flag[2 r ldf] nonzero), the nrm2[r] that pass left; then lane 0 applies the
+// One thread per right-hand side (lane 0 of a wavefront): h_{j+1,j} =
+// sqrt(nrm2[r]), the squared norm the orthogonalisation left, then the
 // rotations.
 __global__ __launch_bounds__(64) void k_givens(double* __restrict__ H, double* __restrict__ cs,
                                                double* __restrict__ g, const double* __restrict__ hcol,
-                                               const double* __restrict__ hcol2, const double* __restrict__ partial,
-                                               int nblk_w, double* __restrict__ nrm2, int j, int m, int nrhs,
-                                               const int* __restrict__ active, double* __restrict__ est,
-                                               const double* __restrict__ bnorm, const double* __restrict__ flag,
-                                               int ldf) {
+                                               const double* __restrict__ hcol2, const double* __restrict__ nrm2,
+                                               int j, int m, int nrhs, const int* __restrict__ active,
+                                               double* __restrict__ est, const double* __restrict__ bnorm) {
     const int r = blockIdx.x;
     if (r >= nrhs) return;
-    const bool one = flag && flag[2 * (int64_t)r * ldf] != 0.0;
-    const double w2 = one ? nrm2[r] : wave_sum(partial + (int64_t)r * nblk_w, nblk_w);
     if (threadIdx.x != 0) return;
-    if (!one) nrm2[r] = w2;
+    const double w2 = nrm2[r];
     if (!active[r]) return;
     double* col = H + 2 * (((int64_t)r * m + j) * (m + 1));
     double* c = cs + 3 * (int64_t)r * m;
@@ -425,10 +453,9 @@ __global__ __launch_bounds__(64) void k_givens(double* __restrict__ H, double* _
 }
 
 hipError_t launch_givens(double* H, double* cs, double* g, const double* hcol, const double* hcol2,
-                         const double* partial, int64_t N, double* nrm2, int j, int m, int nrhs, const int* active,
-                         double* est, const double* bnorm, hipStream_t s, const double* flag, int ldf) {
-    hipLaunchKernelGGL(k_givens, nrhs, 64, 0, s, H, cs, g, hcol, hcol2, partial, krylov_blocks(N), nrm2, j, m, nrhs,
-                       active, est, bnorm, flag, ldf);
+                         const double* nrm2, int j, int m, int nrhs, const int* active, double* est,
+                         const double* bnorm, hipStream_t s) {
+    hipLaunchKernelGGL(k_givens, nrhs, 64, 0, s, H, cs, g, hcol, hcol2, nrm2, j, m, nrhs, active, est, bnorm);
     return hipGetLastError();
 }
 

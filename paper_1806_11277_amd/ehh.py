@@ -39,7 +39,8 @@ class ehh_options_t(ctypes.Structure):
                 ("dd_colors", ctypes.c_int32), ("damping", ctypes.c_double * EHH_MAX_LEVELS),
                 ("coarse_bits", ctypes.c_int32), ("coarse_dd_parts", ctypes.c_int32 * 3),
                 ("coarse_dd_overlap", ctypes.c_int32), ("coarse_dd_colors", ctypes.c_int32),
-                ("dd_batch", ctypes.c_int32), ("damping_p", ctypes.c_double * EHH_MAX_LEVELS)]
+                ("dd_batch", ctypes.c_int32), ("damping_p", ctypes.c_double * EHH_MAX_LEVELS),
+                ("reorth", ctypes.c_int32)]
 
 
 class ehh_stats_t(ctypes.Structure):
@@ -208,7 +209,7 @@ class Solver:
                  dd_colors: int = 1, damping: Optional[Sequence[float]] = None,
                  mu_bar: float = 0.0, rho_bar: float = 0.0, coarse_bits: int = 32,
                  coarse_dd_parts: Sequence[int] = (1, 1, 1), coarse_dd_overlap: int = 2, coarse_dd_colors: int = 0,
-                 damping_p: Optional[Sequence[float]] = None, dd_batch: int = 1, stream=None):
+                 damping_p: Optional[Sequence[float]] = None, dd_batch: int = 1, reorth: int = 0, stream=None):
         import torch
         p = ehh_problem_t()
         p.dim = dim
@@ -227,6 +228,7 @@ class Solver:
             o.coarse_dd_parts[a] = int(cp[a])
         o.coarse_dd_overlap, o.coarse_dd_colors = int(coarse_dd_overlap), int(coarse_dd_colors)
         o.dd_batch = int(dd_batch)
+        o.reorth = int(reorth)
         dp = list(dd_parts) + [1] * (3 - len(dd_parts))
         for a in range(3):
             o.dd_parts[a] = int(dp[a])

@@ -72,6 +72,42 @@ def test_exact_preconditioner_takes_the_second_gram_schmidt_pass():
     S.close()
 
 
+@pytest.mark.parametrize("name", ["c2s_hetero128_fp64", "c3s_hetero128_batch8_fp32"])
+def test_two_gram_schmidt_passes_give_the_same_solve(name):
+    """With reorth = 1 every Arnoldi step takes the second Gram-Schmidt pass
+    (its fused projection, the second update and the normalisation from the
+    partial sums); with the default the steps of these workloads take one.  Both
+    reach 1e-10 with the direct solution for every source, in the same number of
+    iterations within 1, and (FP64 cycle) within 2 of the oracle's FGMRES."""
+    import torch
+    w = workload(name)
+    say(f"[two Gram-Schmidt passes {name}]")
+    pb = oracle_problem(w)
+    A = pb.matrix()
+    lu = spla.splu(A.tocsc())
+    B = rhs_matrix(w)
+    its = {}
+    for reorth in (0, 1):
+        S = _solver(w, reorth=reorth)
+        x = torch.zeros_like(to_dev(B))
+        st, stats = S.solve(to_dev(B), x, tol=1e-10, maxit=800)
+        torch.cuda.synchronize()
+        assert st == 0, stats
+        got = from_dev(x)
+        for r in range(B.shape[0]):
+            xd = lu.solve(B[r])
+            assert stats[r]["rel_res_true"] <= 1e-10
+            assert np.linalg.norm(got[r] - xd) <= 1e-6 * np.linalg.norm(xd)
+        its[reorth] = [st_["iters"] for st_ in stats]
+        S.close()
+    say(f"  iterations one pass {its[0]}, two passes {its[1]}")
+    assert all(abs(a - b) <= 1 for a, b in zip(its[0], its[1]))
+    if w.precond_bits == 64:
+        H = oracle_hierarchy(w, pb)
+        _, ost = krylov.fgmres(lambda v: A @ v, H.cycle, B[0], tol=1e-10, restart=w.restart, maxit=800)
+        assert abs(its[1][0] - ost["iters"]) <= 2
+
+
 def test_batched_fp32_solve_per_source():
     """c3 layout at parity size: 8 sources, complex64 cycle, FP64 Krylov; each
     source reaches its tolerance and matches the direct solution."""
@@ -222,6 +258,9 @@ def test_invalid_arguments_are_rejected():
     assert ei.value.status == ehh.EHH_ERR_INVALID
     with pytest.raises(ehh.EHHError) as ei:
         ehh.solver_for_workload(w, levels=7)          # 64 not divisible into 7 levels
+    assert ei.value.status == ehh.EHH_ERR_INVALID
+    with pytest.raises(ehh.EHHError) as ei:
+        ehh.solver_for_workload(w, reorth=2)
     assert ei.value.status == ehh.EHH_ERR_INVALID
     m = w.media()
     bad = np.array(m["rho"], copy=True)
