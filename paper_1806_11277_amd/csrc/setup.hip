@@ -462,124 +462,123 @@ __global__ __launch_bounds__(256) void k_swap_rows(double* __restrict__ A, int64
 
 // A[K,K] <- (Pi_K A[K,K])^{-1} by Gauss-Jordan with partial pivoting inside the
 // block; piv[k0 + k] = row swapped with k0 + k.  One workgroup of GJ_THREADS
-// threads holds the block in registers: thread (i0, j) owns the entries of
-// column j in rows i0 + (GJ_THREADS / 64) q.  (Sixteen wavefronts of 4 entries:
-// four of 16 took 263 against 144 us per block on MI355X, one wavefront per
-// SIMD leaving the latencies of the LDS reads and dependent FP64 operations of
-// a step exposed.)  A step publishes in LDS only what other threads need (the
-// pivot row, row k and column k, before the interchange of rows k and p) and
-// every thread updates its own entries from them, the interchange being folded
-// into the reads.  The pivot of the next step is chosen while its column is
-// updated: the owners of that column fold |a|^2 and the row into a 64-bit key
-// (the modulus's bits above the lowest six, then 63 - row) and take the maximum
-// with an LDS atomic, i.e. the largest modulus (ties within 2^-46 relative going
-// to the lowest row).
+// threads holds the block in registers: lane i of a wavefront owns row i, and
+// wavefront w the columns w + 16 q (sixteen wavefronts of 4 entries).  Rows are
+// then exchanged inside a wavefront (the pivot row and row k of every column
+// are broadcast from their lanes, wave-uniform indices), and a column lives in
+// one wavefront, which picks the next pivot itself (a butterfly maximum over a
+// 64-bit key: the modulus's bits above the lowest six, then 63 - row, i.e. the
+// largest modulus, ties within 2^-46 relative going to the lowest row) and
+// publishes that column and the pivot in LDS (double-buffered): one barrier per
+// step.  (The transposed layout with the rows exchanged through LDS and the
+// pivot taken by an LDS atomic needed two barriers per step: 137 against 128 us
+// per 64 x 64 block under rocprofv3.  Four wavefronts of 16 entries took 263 us,
+// one wavefront per SIMD leaving the latencies of a step exposed.)
 __device__ inline unsigned long long gj_key(double m, int row) {
     return (__double_as_longlong(m) & ~0x3FULL) | (unsigned long long)(63 - row);
+}
+__device__ inline double gj_lane(double x, int lane) {   // x of a lane (wave-uniform index)
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+    return __hiloint2double(hi, lo);
 }
 
 constexpr int GJ_THREADS = 1024;
 __global__ __launch_bounds__(GJ_THREADS) void k_diag_inverse(double* __restrict__ A, int64_t n, int64_t k0, int kb,
                                                              int* __restrict__ piv, int* __restrict__ flag) {
-    __shared__ double rowp[GJ_NB][2], rowk[GJ_NB][2], colk[GJ_NB][2];
-    __shared__ unsigned long long key[GJ_NB + 1];
-    const int t = threadIdx.x;
-    constexpr int RS = GJ_THREADS / GJ_NB;   // row stride of a thread's entries
-    const int j = t & (GJ_NB - 1), i0 = t / GJ_NB;
-    constexpr int Q = GJ_NB * GJ_NB / GJ_THREADS;
-    const bool jok = j < kb;
-    if (t <= GJ_NB) key[t] = 0ULL;
-    __syncthreads();
-    // No global store inside the step loop: a barrier waits for the workgroup's
-    // outstanding stores, so the pivots and the singularity flag are written
-    // after the loop.
-    bool singular = false;
+    constexpr int NW = GJ_THREADS / 64;   // wavefronts
+    constexpr int Q = GJ_NB / NW;         // columns per wavefront
+    static_assert(GJ_NB == 64 && Q * NW == GJ_NB, "one row per lane, whole columns per wavefront");
+    __shared__ double colk[2][GJ_NB][2];  // the step's column k before the interchange
+    __shared__ int pk[2];                 // the step's pivot row
+    __shared__ int pivs[GJ_NB];
+    const int t = threadIdx.x, i = t & 63, wv = t >> 6;
+    const bool iok = i < kb;
     double ar[Q], ai[Q];
-    unsigned long long kmax = 0ULL;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const int i = i0 + RS * q;
+        const int j = wv + NW * q;
         ar[q] = ai[q] = 0.0;
-        if (i < kb && jok) {
+        if (iok && j < kb) {
             ar[q] = A[2 * ((k0 + i) * n + k0 + j)];
             ai[q] = A[2 * ((k0 + i) * n + k0 + j) + 1];
-            if (j == 0) {
-                const unsigned long long kk = gj_key(ar[q] * ar[q] + ai[q] * ai[q], i);
-                kmax = kk > kmax ? kk : kmax;
-            }
         }
     }
-    if (j == 0 && kmax) atomicMax(&key[0], kmax);
-    __syncthreads();
-    for (int k = 0; k < kb; ++k) {
-        const int p = 63 - (int)(key[k] & 0x3FULL);
+    // column c's owner: the pivot among rows c .. kb-1, then column c and the
+    // pivot row in LDS buffer c & 1 (no global store inside the step loop: a
+    // barrier waits for the workgroup's outstanding stores)
+    auto publish = [&](int c) {
+        const int qc = c / NW;
+        double vr = 0.0, vi = 0.0;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int i = i0 + RS * q;
-            if (i < kb && jok) {
-                if (i == p) {
-                    rowp[j][0] = ar[q];
-                    rowp[j][1] = ai[q];
-                }
-                if (i == k) {
-                    rowk[j][0] = ar[q];
-                    rowk[j][1] = ai[q];
-                }
-                if (j == k) {
-                    colk[i][0] = ar[q];
-                    colk[i][1] = ai[q];
-                }
+        for (int q = 0; q < Q; ++q)
+            if (q == qc) {
+                vr = ar[q];
+                vi = ai[q];
             }
+        unsigned long long key = (i >= c && iok) ? gj_key(vr * vr + vi * vi, i) : 0ULL;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const unsigned lo = (unsigned)__shfl_xor((int)(unsigned)key, o, 64);
+            const unsigned hi = (unsigned)__shfl_xor((int)(unsigned)(key >> 32), o, 64);
+            const unsigned long long other = ((unsigned long long)hi << 32) | lo;
+            key = other > key ? other : key;
         }
-        __syncthreads();
+        colk[c & 1][i][0] = vr;
+        colk[c & 1][i][1] = vi;
+        if (i == 0) pk[c & 1] = 63 - (int)(key & 0x3FULL);
+    };
+    if (wv == 0) publish(0);
+    __syncthreads();
+    bool singular = false;
+    for (int k = 0; k < kb; ++k) {
+        const int b = k & 1;
+        const int p = __builtin_amdgcn_readfirstlane(pk[b]);
         // V = the block with rows k and p interchanged; pivot V(k, k) = A(p, k)
-        const double pr = rowp[k][0], pi = rowp[k][1];
+        const double pr = colk[b][p][0], pi = colk[b][p][1];
         const double dd = pr * pr + pi * pi;
         singular = singular || !(dd > 0.0);
         const double rdd = 1.0 / dd;
         const double ir = pr * rdd, ii = -pi * rdd;
-        // row k of the result: V(k, j) / pivot, and 1 / pivot at j = k
-        double rkr = ir, rki = ii;
-        if (j != k && jok) {
-            const double vr = rowp[j][0], vi = rowp[j][1];
-            rkr = vr * ir - vi * ii;
-            rki = vr * ii + vi * ir;
-        }
-        unsigned long long km = 0ULL;
+        // this row's multiplier V(i, k)
+        const int si = i == p ? k : i;
+        const double fr = colk[b][si][0], fi = colk[b][si][1];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            const int i = i0 + RS * q;
-            if (i < kb && jok) {
+            const int j = wv + NW * q;
+            // V(k, j) = A(p, j), and V(p, j) = A(k, j), from their lanes
+            const double apr = gj_lane(ar[q], p), api = gj_lane(ai[q], p);
+            const double akr = gj_lane(ar[q], k), aki = gj_lane(ai[q], k);
+            if (iok && j < kb) {
+                // row k of the result: V(k, j) / pivot, and 1 / pivot at j = k
+                double rkr = ir, rki = ii;
+                if (j != k) {
+                    rkr = apr * ir - api * ii;
+                    rki = apr * ii + api * ir;
+                }
                 if (i == k) {
                     ar[q] = rkr;
                     ai[q] = rki;
+                } else if (j == k) {
+                    ar[q] = -(fr * ir - fi * ii);
+                    ai[q] = -(fr * ii + fi * ir);
                 } else {
-                    const int si = i == p ? k : i;
-                    const double fr = colk[si][0], fi = colk[si][1];
-                    if (j == k) {
-                        ar[q] = -(fr * ir - fi * ii);
-                        ai[q] = -(fr * ii + fi * ir);
-                    } else {
-                        const double vr = i == p ? rowk[j][0] : ar[q], vi = i == p ? rowk[j][1] : ai[q];
-                        ar[q] = vr - (fr * rkr - fi * rki);
-                        ai[q] = vi - (fr * rki + fi * rkr);
-                    }
-                }
-                if (j == k + 1 && i > k) {
-                    const unsigned long long kq = gj_key(ar[q] * ar[q] + ai[q] * ai[q], i);
-                    km = kq > km ? kq : km;
+                    const double vr = i == p ? akr : ar[q], vi = i == p ? aki : ai[q];
+                    ar[q] = vr - (fr * rkr - fi * rki);
+                    ai[q] = vi - (fr * rki + fi * rkr);
                 }
             }
         }
-        if (km) atomicMax(&key[k + 1], km);
+        if (t == 0) pivs[k] = p;
+        if (k + 1 < kb && wv == (k + 1) % NW) publish(k + 1);
         __syncthreads();
     }
-    if (t < kb) piv[k0 + t] = (int)(k0 + 63 - (int)(key[t] & 0x3FULL));
+    if (t < kb) piv[k0 + t] = (int)(k0 + pivs[t]);
     if (t == 0 && singular) *flag = 1;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const int i = i0 + RS * q;
-        if (i < kb && jok) {
+        const int j = wv + NW * q;
+        if (iok && j < kb) {
             A[2 * ((k0 + i) * n + k0 + j)] = ar[q];
             A[2 * ((k0 + i) * n + k0 + j) + 1] = ai[q];
         }
