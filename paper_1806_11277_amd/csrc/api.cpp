@@ -1281,18 +1281,41 @@ int32_t level_of(ehh_ctx* c, int sub, int level, Sub** S, Level** L) {
     return EHH_OK;
 }
 
+// The preconditioned vectors Z are kept in FP32 where the complex64 cycle runs
+// on the whole grid (no domain decomposition, whose averaging sums in FP64):
+// they are then exactly the cycle's output, and the FGMRES product and the
+// solution update read them at half the bytes.
+bool z_in_fp32(const ehh_ctx* c, const LevelDesc<double>& A) {
+    return c->bits() == 32 && !c->dd && apply_x32_supported(A);
+}
+
+// z32 = M^{-1} v by the complex64 cycle on the whole grid, written in FP32
+// (v_in_r0: the cycle's input copy of v is already in place).
+int32_t precondition_f32(ehh_ctx* c, const double* v, float* z32, int nrhs, hipStream_t s, bool v_in_r0) {
+    CHK(ensure_ws(c, nrhs));
+    Sub& S = c->subs[0];
+    if (!v_in_r0) HIPCHK(launch_cast_d2f(v, (float*)S.r0, 2 * c->gg.N * nrhs, s));
+    return cycle<float>(c, S, 0, (const float*)S.r0, z32, true, nrhs, s);
+}
+
 // One Arnoldi step j of flexible GMRES for every right-hand side, enqueued
 // without any host synchronisation (so that it can be captured in a graph):
-// Z_j = M^{-1} V_j, w = A Z_j, two classical Gram-Schmidt passes, |w|, the
-// Givens rotation and the residual estimate, V_{j+1} = w / |w|.
+// Z_j = M^{-1} V_j, w = A Z_j, classical Gram-Schmidt (reorthogonalised where
+// needed), |w|, the Givens rotation and the residual estimate, V_{j+1} = w / |w|.
 int32_t enqueue_iter(ehh_ctx* c, const LevelDesc<double>& A, int j, int nrhs, hipStream_t s) {
     const int m = c->opt.restart;
     const int64_t N = c->gg.N;
     double* Vj = c->V + (size_t)j * nrhs * 2 * N;
-    double* Zj = c->Z + (size_t)j * nrhs * 2 * N;
     float* v32 = krylov_copy32(c);
-    CHK(precondition_any(c, Vj, Zj, nrhs, s, v32 != nullptr));
-    HIPCHK(launch_apply<double>(A, Zj, nullptr, c->w, nrhs, s));
+    if (z_in_fp32(c, A)) {
+        float* Zj = (float*)c->Z + (size_t)j * nrhs * 2 * N;
+        CHK(precondition_f32(c, Vj, Zj, nrhs, s, v32 != nullptr));
+        HIPCHK(launch_apply_x32(A, Zj, c->w, nrhs, s));
+    } else {
+        double* Zj = c->Z + (size_t)j * nrhs * 2 * N;
+        CHK(precondition_any(c, Vj, Zj, nrhs, s, v32 != nullptr));
+        HIPCHK(launch_apply<double>(A, Zj, nullptr, c->w, nrhs, s));
+    }
     // classical Gram-Schmidt, reorthogonalised where one pass is not enough,
     // V_{j+1} = the normalised result; then the Givens step
     double* Vn = c->V + (size_t)(j + 1) * nrhs * 2 * N;
@@ -1754,7 +1777,10 @@ int32_t ehh_solve(ehh_handle_t h, const double* b, double* x, int32_t nrhs, doub
             if (active[r]) ncols[r] = done_cols;
         std::memcpy(hn, ncols.data(), sizeof(int) * nrhs);
         HIPCHK(hipMemcpyAsync(c->ncols, hn, sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
-        HIPCHK(launch_update_x(c->H, c->g, c->Z, x, N, nrhs, m, c->ncols, c->y, s));
+        if (z_in_fp32(c, A))
+            HIPCHK(launch_update_x(c->H, c->g, (const float*)c->Z, x, N, nrhs, m, c->ncols, c->y, s));
+        else
+            HIPCHK(launch_update_x(c->H, c->g, c->Z, x, N, nrhs, m, c->ncols, c->y, s));
         if (breakdown) break;
     }
     // final true residuals

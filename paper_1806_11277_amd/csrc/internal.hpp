@@ -48,6 +48,10 @@ struct Damp {
 // ---- levels.hip
 template <typename T>
 hipError_t launch_apply(const LevelDesc<T>& L, const T* x, const T* b, T* y, int nrhs, hipStream_t s);
+// y = A x on a finest level (2D or 3D, one-thread-per-cell kernels) with x in
+// FP32; apply_x32_supported tells whether the level qualifies.
+bool apply_x32_supported(const LevelDesc<double>& L);
+hipError_t launch_apply_x32(const LevelDesc<double>& L, const float* x, double* y, int nrhs, hipStream_t s);
 template <typename T>
 hipError_t launch_relax(const LevelDesc<T>& L, int colour, Damp w, int econ, const T* b, const T* ein,
                         T* eout, int nrhs, hipStream_t s);
@@ -204,6 +208,8 @@ hipError_t launch_givens(double* H, double* cs, double* g, const double* hcol, c
 // y = R^{-1} g (columns ncols[r]); x(r) += sum_i y_i Z_i(r)
 hipError_t launch_update_x(const double* H, const double* g, const double* Z, double* x, int64_t N, int nrhs,
                            int m, const int* ncols, double* y, hipStream_t s);
+hipError_t launch_update_x(const double* H, const double* g, const float* Z, double* x, int64_t N, int nrhs,
+                           int m, const int* ncols, double* y, hipStream_t s);   // Z in FP32
 
 hipError_t launch_axpby(const double* x, const double* y, double* out, int64_t n, double a, double b,
                         hipStream_t s);

@@ -481,7 +481,8 @@ __global__ void k_backsub(const double* __restrict__ H, const double* __restrict
     }
 }
 
-__global__ __launch_bounds__(256) void k_update_x(const double* __restrict__ Z, double* __restrict__ x, int64_t N,
+template <typename TZ>
+__global__ __launch_bounds__(256) void k_update_x(const TZ* __restrict__ Z, double* __restrict__ x, int64_t N,
                                                   int nrhs, int m, const int* __restrict__ ncols,
                                                   const double* __restrict__ y) {
     const int r = blockIdx.y;
@@ -492,9 +493,9 @@ __global__ __launch_bounds__(256) void k_update_x(const double* __restrict__ Z, 
     double* xr = x + (int64_t)r * 2 * N;
     double ar = xr[e], ai = xr[N + e];
     for (int i = 0; i < nc; ++i) {
-        const double* z = Z + ((int64_t)i * nrhs + r) * 2 * N;
+        const TZ* z = Z + ((int64_t)i * nrhs + r) * 2 * N;
         const double yr = y[2 * ((int64_t)r * m + i)], yi = y[2 * ((int64_t)r * m + i) + 1];
-        const double zr = z[e], zi = z[N + e];
+        const double zr = (double)z[e], zi = (double)z[N + e];
         ar += yr * zr - yi * zi;
         ai += yr * zi + yi * zr;
     }
@@ -505,7 +506,13 @@ __global__ __launch_bounds__(256) void k_update_x(const double* __restrict__ Z, 
 hipError_t launch_update_x(const double* H, const double* g, const double* Z, double* x, int64_t N, int nrhs, int m,
                            const int* ncols, double* y, hipStream_t s) {
     hipLaunchKernelGGL(k_backsub, nblk(nrhs, 64), 64, 0, s, H, g, m, nrhs, ncols, y);
-    hipLaunchKernelGGL(k_update_x, dim3(nblk(N), nrhs), 256, 0, s, Z, x, N, nrhs, m, ncols, y);
+    hipLaunchKernelGGL(k_update_x<double>, dim3(nblk(N), nrhs), 256, 0, s, Z, x, N, nrhs, m, ncols, y);
+    return hipGetLastError();
+}
+hipError_t launch_update_x(const double* H, const double* g, const float* Z, double* x, int64_t N, int nrhs, int m,
+                           const int* ncols, double* y, hipStream_t s) {
+    hipLaunchKernelGGL(k_backsub, nblk(nrhs, 64), 64, 0, s, H, g, m, nrhs, ncols, y);
+    hipLaunchKernelGGL(k_update_x<float>, dim3(nblk(N), nrhs), 256, 0, s, Z, x, N, nrhs, m, ncols, y);
     return hipGetLastError();
 }
 

@@ -1847,8 +1847,8 @@ __global__ __launch_bounds__(256) void k_relax_cell2d_batch(Batch<PK> b) {
 // owns its left u_0 face, its bottom u_1 face and its pressure (the faces on the
 // walls are not unknowns), so every unknown is written once; the three rows
 // need thirteen values of x.
-template <typename T>
-EHH_DEV void k_apply_cell2d_body(VB ehh_vb, const FineOp<2, T>& op, const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ y, int nrhs, int64_t stride, int rpb) {
+template <typename T, typename TX = T>
+EHH_DEV void k_apply_cell2d_body(VB ehh_vb, const FineOp<2, T>& op, const TX* __restrict__ x, const T* __restrict__ b, T* __restrict__ y, int nrhs, int64_t stride, int rpb) {
     const Geo& g = op.g;
     const int n0 = g.n[0], n1 = g.n[1];
     const int64_t t = (int64_t)ehh_vb.x * blockDim.x + threadIdx.x;
@@ -1905,9 +1905,12 @@ EHH_DEV void k_apply_cell2d_body(VB ehh_vb, const FineOp<2, T>& op, const T* __r
                   (fr && vu ? 16384u : 0u) | (ft && vv ? 32768u : 0u);
     const U NB = E * (U)g.N, VB = 2 * NB;
     for (int r = r_begin; r < r_end; ++r) {
-        const Buf<T> xb(x + (int64_t)r * stride, VB);
+        // x may be FP32 (the complex64 cycle's output read by the FP64 matrix-vector
+        // product): its byte offsets are the FP64 ones halved
+        constexpr U XS = sizeof(T) == 2 * sizeof(TX) ? 1u : 0u;
+        const Buf<TX> xb(x + (int64_t)r * stride, VB >> XS);
         const Buf<T> yb(y + (int64_t)r * stride, VB);
-        auto ld = [&](U i) { return mk<T>(xb.ld(i), xb.ld(NB + i)); };
+        auto ld = [&](U i) { return mk<T>((T)xb.ld(i >> XS), (T)xb.ld((NB + i) >> XS)); };
         U nz = nzm;
         asm volatile("" : "+v"(nz));
         auto bit = [&](int b_) { return ((nz >> b_) & 1u) != 0u; };
@@ -1952,11 +1955,11 @@ EHH_DEV void k_apply_cell2d_body(VB ehh_vb, const FineOp<2, T>& op, const T* __r
         yb.st(NB + kp, ap.im);
     }
 }
-template <typename T>
-__global__ __launch_bounds__(256) void k_apply_cell2d(FineOp<2, T> op, const T* __restrict__ x,
+template <typename T, typename TX = T>
+__global__ __launch_bounds__(256) void k_apply_cell2d(FineOp<2, T> op, const TX* __restrict__ x,
                                                       const T* __restrict__ b, T* __restrict__ y, int nrhs,
                                                       int64_t stride, int rpb) {
-    k_apply_cell2d_body<T>(single_block<true>(), op, x, b, y, nrhs, stride, rpb);
+    k_apply_cell2d_body<T, TX>(single_block<true>(), op, x, b, y, nrhs, stride, rpb);
 }
 template <class PK, typename T>
 __global__ __launch_bounds__(256) void k_apply_cell2d_batch(Batch<PK> b) {
@@ -2176,8 +2179,8 @@ __global__ __launch_bounds__(256) void k_relax_cell3d_batch(Batch<PK> b) {
 
 // y = A x (or b - A x) on the finest 3D level, one thread per cell owning its
 // three lower faces (those on the walls are not unknowns) and its pressure.
-template <typename T>
-EHH_DEV void k_apply_cell3d_body(VB ehh_vb, const FineOp<3, T>& op, const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ y, int nrhs, int64_t stride, int rpb) {
+template <typename T, typename TX = T>
+EHH_DEV void k_apply_cell3d_body(VB ehh_vb, const FineOp<3, T>& op, const TX* __restrict__ x, const T* __restrict__ b, T* __restrict__ y, int nrhs, int64_t stride, int rpb) {
     const Geo& g = op.g;
     const int n[3] = {g.n[0], g.n[1], g.n[2]};
     const int64_t t = (int64_t)ehh_vb.x * blockDim.x + threadIdx.x;
@@ -2240,9 +2243,12 @@ EHH_DEV void k_apply_cell3d_body(VB ehh_vb, const FineOp<3, T>& op, const T* __r
     const U pstr[3] = {E, E * (U)n[0], E * (U)n[0] * (U)n[1]};
     const U NB = E * (U)g.N, VB = 2 * NB;
     for (int r = r_begin; r < r_end; ++r) {
-        const Buf<T> xb(x + (int64_t)r * stride, VB);
+        // x may be FP32 (the complex64 cycle's output read by the FP64 matrix-vector
+        // product): its byte offsets are the FP64 ones halved
+        constexpr U XS = sizeof(T) == 2 * sizeof(TX) ? 1u : 0u;
+        const Buf<TX> xb(x + (int64_t)r * stride, VB >> XS);
         const Buf<T> yb(y + (int64_t)r * stride, VB);
-        auto ld = [&](U i) { return mk<T>(xb.ld(i), xb.ld(NB + i)); };
+        auto ld = [&](U i) { return mk<T>((T)xb.ld(i >> XS), (T)xb.ld((NB + i) >> XS)); };
         U nz[3] = {nzm[0], nzm[1], nzm[2]};
         asm volatile("" : "+v"(nz[0]), "+v"(nz[1]), "+v"(nz[2]));
         auto on = [&](int k, int b_, U s_) { return (0u - ((nz[k] >> b_) & 1u)) & s_; };
@@ -2292,11 +2298,11 @@ EHH_DEV void k_apply_cell3d_body(VB ehh_vb, const FineOp<3, T>& op, const T* __r
         yb.st(NB + kp, ap.im);
     }
 }
-template <typename T>
-__global__ __launch_bounds__(256) void k_apply_cell3d(FineOp<3, T> op, const T* __restrict__ x,
+template <typename T, typename TX = T>
+__global__ __launch_bounds__(256) void k_apply_cell3d(FineOp<3, T> op, const TX* __restrict__ x,
                                                       const T* __restrict__ b, T* __restrict__ y, int nrhs,
                                                       int64_t stride, int rpb) {
-    k_apply_cell3d_body<T>(single_block<true>(), op, x, b, y, nrhs, stride, rpb);
+    k_apply_cell3d_body<T, TX>(single_block<true>(), op, x, b, y, nrhs, stride, rpb);
 }
 template <class PK, typename T>
 __global__ __launch_bounds__(256) void k_apply_cell3d_batch(Batch<PK> b) {
@@ -3511,6 +3517,29 @@ hipError_t launch_absmax_bits(const float* x, int64_t n, unsigned* out, hipStrea
 }
 hipError_t launch_to_half(const float* x, void* y, int64_t n, float inv_scale, hipStream_t s) {
     EHH_LAUNCH(k_to_half, nblk(n), 256, 0, s, x, (_Float16*)y, n, inv_scale);
+    return hipGetLastError();
+}
+
+// y = A x on a finest level with x in FP32 and A, y in FP64 (the FGMRES product
+// of the complex64 cycle's output, kept in FP32; each x entry is exact in FP64).
+bool apply_x32_supported(const LevelDesc<double>& L) {
+    return L.fine && (L.g.dim == 2 || L.g.dim == 3) && 2 * L.g.N * (int64_t)sizeof(double) < (int64_t(1) << 32);
+}
+hipError_t launch_apply_x32(const LevelDesc<double>& L, const float* x, double* y, int nrhs, hipStream_t s) {
+    if (!apply_x32_supported(L)) return hipErrorInvalidValue;
+    const int64_t stride = 2 * L.g.N;
+    const int64_t cells = L.g.ncell;
+    const int rpc = tuned(L.tune_apply, nrhs, 1, rhs_per_cells(cells, nrhs, kCellWaves));
+    const dim3 gc(nblk(cells), (nrhs + rpc - 1) / rpc);
+    LaunchBytes lb = bytes_apply(L.g, true, nrhs, false, (int)sizeof(double), (double)sizeof(double));
+    lb.mine -= nrhs * L.g.N * 2.0 * (sizeof(double) - sizeof(float));   // x in FP32
+    lb.model -= nrhs * (double)L.g.ncell * (L.g.dim + 1) * 2.0 * (sizeof(double) - sizeof(float));
+    if (L.g.dim == 2)
+        EHH_LAUNCH_B(lb, (k_apply_cell2d<double, float>), gc, 256, 0, s, FineOp<2, double>{L.g, L.f}, x,
+                     (const double*)nullptr, y, nrhs, stride, rpc);
+    else
+        EHH_LAUNCH_B(lb, (k_apply_cell3d<double, float>), gc, 256, 0, s, FineOp<3, double>{L.g, L.f}, x,
+                     (const double*)nullptr, y, nrhs, stride, rpc);
     return hipGetLastError();
 }
 
