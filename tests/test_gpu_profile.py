@@ -1,8 +1,9 @@
 """ehh_profile_precondition: every kernel of one preconditioner application is
 replayed and timed three ways.  The in-order replay times each launch by the
 start and stop events of its own dispatch, so the launches of one application
-add up to no more than the wall time of a precondition call (on one stream the
-dispatches do not overlap) and to most of it; every row names a kernel with
+add up to about the wall time of a precondition call (on one stream the
+dispatches do not overlap; each timed dispatch also carries its own set-up)
+and to most of it; every row names a kernel with
 positive launches, times and algorithmic bytes; the profiler leaves the
 handle usable (a precondition afterwards gives the same bits as before)."""
 import numpy as np
@@ -42,7 +43,10 @@ def test_in_order_kernel_times_add_up_to_the_application(name):
     t_seq = sum(r["launches"] * r["avg_us_seq"] for r in rows)
     say(f"[profile {name}] precondition {t_call:.1f} us; in-order kernels {t_seq:.1f} us "
         f"({len(rows)} kernels, {sum(r['launches'] for r in rows)} launches)")
-    assert 0.3 * t_call <= t_seq <= 1.05 * t_call
+    # a dispatch timed by its own events also carries its set-up, which back-to-back
+    # dispatches overlap with the previous kernel's drain: with 60 small launches
+    # the sum has read 106 % of the call on one box, so the bound leaves 15 %
+    assert 0.3 * t_call <= t_seq <= 1.15 * t_call
     z1 = torch.zeros_like(v)
     S.precondition(v, z1)
     torch.cuda.synchronize()
