@@ -199,7 +199,7 @@ EHH_DEV cx<double> st_entry(const StOp<D, double>& op, int k, const int* f, int6
 // One thread per (coarse face X of component k, stored offset s).
 template <int D>
 __global__ __launch_bounds__(256) void k_galerkin_uu(Geo gf, StCoef<double> cf, Geo gc, double* __restrict__ stc) {
-    constexpr int NUU = St<D>::NUU, CF = St<D>::CF, NF = St<D>::NF;
+    constexpr int NUU = St<D>::NUU, CF = St<D>::CF;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nu = gc.off[3];
     if (t >= nu * NUU) return;
@@ -237,23 +237,29 @@ __global__ __launch_bounds__(256) void k_galerkin_uu(Geo gf, StCoef<double> cf, 
                     if (!face_ok<D>(gf, k, f)) continue;
                     const double wX = wn_(a) * wt_(b1) * (D == 3 ? wt_(b2) : 1.0);
                     const int64_t fi = face_idx<D>(gf, k, f);
-                    for (int F = 0; F < NF; ++F) {
-                        int gp[3];
-                        int fdn, fd1, fd2;
-                        full_offset<D>(F, fdn, fd1, fd2);
-                        gp[k] = f[k] + fdn;
-                        gp[t1] = f[t1] + fd1;
-                        gp[t2] = D == 3 ? f[t2] + fd2 : 0;
-                        const double wY = wn_(gp[k] - 2 * Y[k]) * wt_(gp[t1] - 2 * Y[t1]) *
-                                          (D == 3 ? wt_(gp[t2] - 2 * Y[t2]) : 1.0);
-                        if (wY == 0.0) continue;
-                        bool ok;
-                        int gq[3];
-                        const cx<double> a_ = st_entry<D>(op, k, f, fi, F, gq, ok);
-                        if (!ok) continue;
-                        sre += wX * wY * a_.re;
-                        sim += wX * wY * a_.im;
-                    }
+                    // only the stencil offsets whose target lies in the support of
+                    // the prolongation at Y (|normal| <= 1 and tangential in -1..2
+                    // around 2 Y), walked in increasing term index F, so that the
+                    // sum takes the same terms in the same order as a walk over all
+                    // NF terms that skips the zero weights
+                    const int nlo = max(-1, 2 * Y[k] - 1 - f[k]), nhi = min(1, 2 * Y[k] + 1 - f[k]);
+                    const int alo = max(-2, 2 * Y[t1] - 1 - f[t1]), ahi = min(2, 2 * Y[t1] + 2 - f[t1]);
+                    const int blo = D == 3 ? max(-2, 2 * Y[t2] - 1 - f[t2]) : 0;
+                    const int bhi = D == 3 ? min(2, 2 * Y[t2] + 2 - f[t2]) : 0;
+                    for (int e2 = blo; e2 <= bhi; ++e2)
+                        for (int e1 = alo; e1 <= ahi; ++e1)
+                            for (int en = nlo; en <= nhi; ++en) {
+                                const int F = (en + 1) + 3 * (e1 + 2) + (D == 3 ? 15 * (e2 + 2) : 0);
+                                const double wY = wn_(f[k] + en - 2 * Y[k]) * wt_(f[t1] + e1 - 2 * Y[t1]) *
+                                                  (D == 3 ? wt_(f[t2] + e2 - 2 * Y[t2]) : 1.0);
+                                if (wY == 0.0) continue;
+                                bool ok;
+                                int gq[3];
+                                const cx<double> a_ = st_entry<D>(op, k, f, fi, F, gq, ok);
+                                if (!ok) continue;
+                                sre += wX * wY * a_.re;
+                                sim += wX * wY * a_.im;
+                            }
                 }
     }
     outp[(int64_t)(2 * s) * gc.cnt[k] + Xi] = sre;
